@@ -1,0 +1,265 @@
+/*
+ * msrs.h -- C ABI of the multiscale random-sampling library for MI355X (gfx950).
+ *
+ * The library computes the offline stage of the domain-decomposition method
+ * of Chen, Li, Lu and Wright, "Random sampling and efficient algorithms for
+ * multiscale PDEs" (Section 3, Algorithm alg:summary): for every buffered
+ * patch, local fine-scale solves with i.i.d. N(0,1) boundary data
+ * (RanLocalSolu), restriction to the patch, and a range finder that keeps an
+ * orthonormal rank-k basis.  The online stage (least-squares gluing and
+ * reconstruction, eqs. elliptic_cond_reduced and rte_cond_reduced) reuses the
+ * resident bases.  Two problems are supported:
+ *
+ *   MSRS_KIND_ELLIPTIC_Q1  -div(a grad u) = 0 on [0,1]^2, Dirichlet data
+ *                          (Section 5), bilinear finite elements on an N x N
+ *                          cell grid, M x M coarse patches;
+ *   MSRS_KIND_KINETIC_DO   v d_x f = (sigma/eps)(<f> - f) on [0,1] x [-1,1],
+ *                          inflow data (Section 4, isotropic scattering),
+ *                          upwind discrete ordinates on N_x cells, M patches.
+ *
+ * Conventions shared by every call
+ *  - Every function returns msrs_status; no C++ exception crosses the ABI.
+ *  - "device" pointers are HIP device allocations of the caller (e.g. torch
+ *    tensors); "host" pointers are ordinary host memory.  The caller owns
+ *    every pointer it passes; device pointers must stay valid until the work
+ *    enqueued on the handle's stream has completed.  The library owns its
+ *    workspace, factors, bases and coarse factor, allocated in msrs_create /
+ *    msrs_assemble_coarse and released by msrs_destroy.
+ *  - All device work is enqueued on the stream given to msrs_create (or to
+ *    msrs_solve_global); calls return without synchronising unless stated.
+ *  - Errors the kernels detect (non-positive pivot, non-finite values,
+ *    refinement that does not converge) are latched on the device and
+ *    reported by msrs_get_stats (which synchronises) and by the next call
+ *    that synchronises; msrs_last_error gives a message.
+ *  - Floating-point data are IEEE binary64, integers are int32/int64 as typed.
+ *  - One handle per host thread.
+ *
+ * Layouts
+ *  - Elliptic coefficient a: N*N values, element (i,j) = cell
+ *    [i h,(i+1)h] x [j h,(j+1)h] at index j*N + i (h = 1/N).
+ *  - Kinetic cross section sigma: N_x values at the cell centres.
+ *  - Patch p = m2*M + m1 (elliptic) or p = m (kinetic).
+ *  - Omega (boundary samples) of patch p: n_bdry(p) x s, column-major, at
+ *    offset omega_off(p) of the concatenated array.  Elliptic boundary nodes
+ *    of the buffered patch are ordered counter-clockwise from its lower-left
+ *    node; kinetic inflow values are [left inflow at the v>0 ordinates
+ *    (ascending v), right inflow at the v<0 ordinates (ascending v)].
+ *  - Y (snapshots) of patch p: n_rows(p) x s, column-major, offset Y_off(p).
+ *    Elliptic rows are the (nH+1)^2 nodes of the closed patch K_m, row-major
+ *    (index jj*(nH+1)+ii, nH = N/M); kinetic rows are (cell c, ordinate j) ->
+ *    c*n_vel + j for the nH+2 cells [first cell of K_m - 1, last cell + 1].
+ *  - Q (bases) of patch p: n_rows(p) x n_cols(p), column-major, offset Q_off(p).
+ *  - Global boundary data f of one request: elliptic 4N values
+ *    counter-clockwise from node (0,0) (bottom i=0..N-1, right j=0..N-1, top
+ *    i=N..1, left j=N..1); kinetic n_vel values laid out as Omega.
+ *  - Global solution u of one request: elliptic (N+1)^2 nodal values, index
+ *    j*(N+1)+i; kinetic N_x*n_vel values, index i*n_vel + j.
+ */
+#ifndef MSRS_H
+#define MSRS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t msrs_status;
+
+#define MSRS_OK             0
+#define MSRS_ERR_ARG        1   /* invalid argument (null, out of range, inconsistent sizes) */
+#define MSRS_ERR_STATE      2   /* call out of order (e.g. range_finder before sampling) */
+#define MSRS_ERR_OOM        3   /* device memory exhausted or footprint above the budget */
+#define MSRS_ERR_HIP        4   /* a HIP runtime call failed */
+#define MSRS_ERR_NO_DEVICE  5   /* no HIP device is visible */
+#define MSRS_ERR_NOT_SPD    6   /* non-positive coefficient or pivot (matrix not SPD / singular) */
+#define MSRS_ERR_NOCONV     7   /* iterative refinement above tolerance after ir_max_iters */
+#define MSRS_ERR_RANK       8   /* sketch rank below the requested rank k */
+#define MSRS_ERR_BUSY       9   /* no free online slot */
+
+#define MSRS_KIND_ELLIPTIC_Q1 0
+#define MSRS_KIND_KINETIC_DO  1
+
+#define MSRS_PREC_FP64     0   /* plain FP64 factor and sweeps */
+#define MSRS_PREC_FP32_IR  1   /* FP32 factor and sweeps, FP64 residuals and refinement */
+
+/* flags */
+#define MSRS_FLAG_FULL_BASIS_ENDS   1u  /* kinetic: full (delta) basis on the two end patches (default on) */
+#define MSRS_FLAG_PER_PATCH_LAUNCH  2u  /* launch every stage once per patch (unbatched reference mode) */
+#define MSRS_FLAG_TIMING            4u  /* record HIP events around every kernel class (msrs_get_stats) */
+
+typedef struct msrs_ctx* msrs_handle;
+
+/* Problem description (msrs_create).  Sizes are validated; see msrs_create. */
+typedef struct msrs_problem_desc {
+    int32_t kind;            /* MSRS_KIND_* */
+    int32_t n_cells;         /* N (cells per side, elliptic) or N_x (kinetic) */
+    int32_t M;               /* coarse patches per side (elliptic) or along x (kinetic); divides n_cells */
+    int32_t n_samples;       /* s, random boundary samples per patch, 1..64 */
+    int32_t rank;            /* k, basis columns kept per sampled patch, 1..s */
+    int32_t precision;       /* MSRS_PREC_* */
+    int32_t ir_max_iters;    /* FP32_IR: refinement iterations at most (0 -> 30) */
+    int32_t n_vel;           /* kinetic: Gauss-Legendre ordinates (even, 2..32) */
+    uint64_t seed;           /* Philox key of the device-drawn boundary samples */
+    double ir_tol;           /* FP32_IR: stop when every ||r_j||/||rhs_j|| <= ir_tol (0 -> 1e-10) */
+    double eps;              /* kinetic: eps of the collision term */
+    const int32_t* overlap;  /* host: buffer width in cells per patch (M*M elliptic, M kinetic) */
+    uint32_t flags;          /* MSRS_FLAG_* */
+    int32_t reserved;
+} msrs_problem_desc;
+
+typedef struct msrs_layout {
+    int32_t n_patches;
+    int32_t n_samples;       /* s */
+    int32_t rank;            /* k */
+    int32_t n_bdry;          /* length of one request's global boundary data */
+    int64_t n_nodes;         /* length of one request's global solution */
+    int64_t omega_total;     /* elements of the concatenated Omega array */
+    int64_t Y_total;         /* elements of the concatenated Y array */
+    int64_t Q_total;         /* elements of the concatenated Q array */
+    int64_t sv_total;        /* elements of the singular-value array (s per patch) */
+    int64_t coarse_dim;      /* unknowns of the least-squares system */
+    int64_t device_bytes;    /* device memory held by the handle */
+} msrs_layout;
+
+typedef struct msrs_patch_info {
+    int32_t x0, y0, cx, cy;  /* buffered patch in cells (kinetic: x0, cx; y0 = cy = 0) */
+    int32_t kx0, ky0, nH;    /* patch K_m origin and width in cells */
+    int32_t n_bdry;          /* boundary samples per column of Omega */
+    int32_t n_rows;          /* rows of Y and Q */
+    int32_t n_cols;          /* columns of Q (k, or n_bdry for a full-basis patch) */
+    int32_t full_basis;      /* 1 if the patch keeps its full delta basis */
+    int32_t line_len;        /* unknowns per block row of the local factorization */
+    int32_t n_lines;         /* block rows of the local factorization */
+    int32_t n_samples;       /* columns of Omega and Y (s, or n_bdry for a full-basis patch) */
+    int64_t omega_off, Y_off, Q_off, sv_off;
+} msrs_patch_info;
+
+typedef struct msrs_stats {
+    int32_t ir_iters;            /* refinement iterations run by the last sampling call */
+    int32_t error_latched;       /* first device-detected error (MSRS_ERR_*) or 0 */
+    double max_rel_residual;     /* max over patches, samples of ||rhs - A x|| / ||rhs|| (FP64) */
+    double min_rel_gap;          /* min over sampled patches of (sigma_k - sigma_{k+1}) / sigma_1 */
+    double kernel_ms[12];        /* accumulated event time per kernel class (MSRS_FLAG_TIMING) */
+    int64_t kernel_launches[12]; /* launches per kernel class */
+} msrs_stats;
+
+/* kernel classes of msrs_stats */
+#define MSRS_K_ASSEMBLE 0
+#define MSRS_K_OMEGA    1
+#define MSRS_K_LIFT     2
+#define MSRS_K_FACTOR   3
+#define MSRS_K_SWEEP    4
+#define MSRS_K_RESIDUAL 5
+#define MSRS_K_RESTRICT 6
+#define MSRS_K_RANGE    7
+#define MSRS_K_COARSE   8
+#define MSRS_K_CSOLVE   9
+#define MSRS_K_RECON    10
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t msrs_version(void);
+
+/* Number of visible HIP devices (0 if none); never fails. */
+int32_t msrs_device_count(void);
+
+/*
+ * Create a handle on the current HIP device for one problem (Section 3:
+ * domain decomposition into patches K_m and buffered patches K~_m, which
+ * grow K_m by overlap[p] cells per side and are clipped to the domain).
+ * stream: hipStream_t (as void*) on which all offline work is enqueued; NULL
+ * is the default stream.  hbm_budget_bytes: upper bound on the device memory
+ * of the handle (0: no bound); MSRS_ERR_OOM if the footprint exceeds it.
+ * Allocates all device buffers.  Errors: ARG, OOM, HIP, NO_DEVICE.
+ */
+msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* stream,
+                        size_t hbm_budget_bytes);
+
+/*
+ * Stage a2: fine-scale operator of every buffered patch (LocalPDESolver's
+ * discretization: bilinear elements, eq. Elliptic; or the upwind ordinates
+ * scheme of eq. RTE with isotropic scattering) and its block-row
+ * factorization.  coef_dev: device, N*N (elliptic a) or N_x (kinetic
+ * sigma) FP64 values, read during the call's kernels only.
+ * Non-positive values or pivots latch MSRS_ERR_NOT_SPD.  Errors: ARG, STATE.
+ */
+msrs_status msrs_assemble_patch(msrs_handle h, const double* coef_dev);
+
+/*
+ * Stages a3-a7 (RanLocalSolu, eqs. elliptic_random / rte_random): for every
+ * patch, s local solves with i.i.d. N(0,1) boundary data, then restriction
+ * to K_m (the reduced Green's matrix G^{eps,r}_m = G~_m Omega_m).
+ * omega_dev: device, concatenated Omega (layout above), or NULL to draw it on
+ * the device with Philox4x32-10 (key = seed, counter = (node, sample,
+ * patch, 0), Box-Muller on two 53-bit uniforms).  Y_out_dev: device,
+ * optional copy of the concatenated Y (NULL: kept resident only).
+ * FP32_IR refines each column until ||r||/||rhs|| <= ir_tol.
+ * Errors: ARG, STATE; latched NOT_SPD / NOCONV.
+ */
+msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, double* Y_out_dev);
+
+/*
+ * Stage a8: range finder of each patch's snapshots (QR at the end of
+ * RanLocalSolu; randomized SVD of Section 2.3): orthonormal basis of the k
+ * leading left singular vectors of Y_m, each column's largest-magnitude
+ * entry made positive.  Full-basis patches keep all columns.
+ * Q_out_dev: device, optional copy of the concatenated Q.  sv_out_dev:
+ * device, optional s singular values of each Y_m (descending).
+ * Errors: STATE; latched RANK if sigma_k(Y_m) <= 1e-13 sigma_1(Y_m).
+ */
+msrs_status msrs_range_finder(msrs_handle h, double* Q_out_dev, double* sv_out_dev);
+
+/*
+ * Online set-up (eqs. elliptic_cond_tilde / gb3): boundary traces and
+ * conormal fluxes of the bases, the normal-equations matrix of the
+ * least-squares system and its FP64 Cholesky factor, kept resident.
+ * Synchronises the stream.  Errors: STATE, OOM; NOT_SPD if P~ is rank
+ * deficient.
+ */
+msrs_status msrs_assemble_coarse(msrs_handle h);
+
+/*
+ * Online solve (eqs. elliptic_cond_reduced / rte_cond_reduced and the ansatz
+ * u = sum_m G_m c_m): for n_req requests, least-squares coefficients from the
+ * global boundary data and the reconstructed global solution.
+ * f_dev: device, n_req x n_bdry (request-major).  u_dev: device,
+ * n_req x n_nodes.  stream: hipStream_t (as void*) for this call, NULL for
+ * the handle's stream.  Elliptic nodes shared by several patches take the
+ * partition-of-unity average.  n_req must not exceed the slot capacity
+ * fixed at msrs_assemble_coarse (msrs_set_max_batch).  Errors: ARG, STATE.
+ */
+msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev,
+                              void* stream);
+
+/*
+ * Copy the resident boundary samples Omega (all patches, layout above) of
+ * the last sampling call to omega_out_dev (device, omega_total doubles).
+ * Full-basis patches hold the identity.  Errors: ARG, STATE.
+ */
+msrs_status msrs_copy_omega(msrs_handle h, double* omega_out_dev);
+
+/* Requests per msrs_solve_global call at most (default 64); call before msrs_assemble_coarse. */
+msrs_status msrs_set_max_batch(msrs_handle h, int32_t max_batch);
+
+/* Sizes and offsets of the concatenated arrays.  Errors: ARG. */
+msrs_status msrs_query_layout(msrs_handle h, msrs_layout* out);
+msrs_status msrs_query_patch(msrs_handle h, int32_t patch, msrs_patch_info* out);
+
+/* Synchronise the handle's stream and report refinement, residual, gap and timing figures. */
+msrs_status msrs_get_stats(msrs_handle h, msrs_stats* out);
+
+/* Zero the accumulated kernel times and launch counts. */
+msrs_status msrs_reset_stats(msrs_handle h);
+
+/* Message of the last error on h (or of the last failed create if h is NULL). */
+const char* msrs_last_error(msrs_handle h);
+
+/* Release every device buffer of the handle (synchronises its stream). */
+void msrs_destroy(msrs_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSRS_H */

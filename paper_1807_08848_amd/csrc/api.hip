@@ -1,0 +1,610 @@
+// Host implementation of the msrs C ABI (include/msrs.h): problem set-up
+// (domain decomposition into patches and buffered patches, Section 3),
+// device buffers, orchestration of the offline and online stages, error
+// latching and timing.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "msrs_internal.h"
+
+using namespace msrs;
+
+// the opaque handle of the ABI is the library context
+struct msrs_ctx : public msrs::Ctx {};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int round16(int v) { return ((v + 15) / 16) * 16; }
+
+// Gauss-Legendre nodes (ascending) and weights on [-1, 1], Newton iteration
+// on the three-term recurrence of the Legendre polynomials.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double pp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                const double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1.0);
+            const double dz = p1 / pp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+template <typename T>
+T* dalloc(Ctx& c, int64_t n) {
+    if (n <= 0) n = 1;
+    void* p = nullptr;
+    MSRS_HIP_CHECK(hipMalloc(&p, (size_t)n * sizeof(T)));
+    c.allocs.push_back(p);
+    c.bytes += n * (int64_t)sizeof(T);
+    return (T*)p;
+}
+
+msrs_status fail(Ctx* c, msrs_status st, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_create_err = msg;
+    return st;
+}
+
+msrs_status hip_fail(Ctx* c, const HipError& e) {
+    char buf[512];
+    std::snprintf(buf, sizeof buf, "HIP error %d (%s) in %s at %s:%d", (int)e.e, hipGetErrorString(e.e), e.what, e.file, e.line);
+    return fail(c, e.e == hipErrorOutOfMemory ? MSRS_ERR_OOM : MSRS_ERR_HIP, buf);
+}
+
+// number of patches launched together: all (batched) or one (reference mode)
+template <typename F>
+void for_patches(Ctx& c, F&& f) {
+    if (c.flags & MSRS_FLAG_PER_PATCH_LAUNCH) {
+        for (int p = 0; p < c.n_patches; ++p) f(p, p + 1);
+    } else {
+        f(0, c.n_patches);
+    }
+}
+
+void build_elliptic(Ctx& c) {
+    const int N = c.N, M = c.M, nH = N / M;
+    int64_t a_off = 0, om_off = 0, x_off = 0, E_off = 0, Y_off = 0, Q_off = 0, sv_off = 0, rn_off = 0;
+    for (int m2 = 0; m2 < M; ++m2)
+        for (int m1 = 0; m1 < M; ++m1) {
+            const int p = m2 * M + m1;
+            const int d = c.overlap[p];
+            PatchDesc P{};
+            const int x0 = std::max(0, m1 * nH - d), x1 = std::min(N, (m1 + 1) * nH + d);
+            const int y0 = std::max(0, m2 * nH - d), y1 = std::min(N, (m2 + 1) * nH + d);
+            P.x0 = x0; P.y0 = y0; P.cx = x1 - x0; P.cy = y1 - y0;
+            P.trans = P.cx > P.cy ? 1 : 0;
+            P.L = std::min(P.cx, P.cy);
+            P.Qn = std::max(P.cx, P.cy);
+            P.b = P.L - 1;
+            P.nl = P.Qn - 1;
+            P.bp = std::max(16, round16(P.b));
+            P.nb = 2 * (P.cx + P.cy);
+            P.s = c.s;
+            P.sp = round16(c.s);
+            P.kx0 = m1 * nH; P.ky0 = m2 * nH; P.nH = nH;
+            P.nrows = (nH + 1) * (nH + 1);
+            P.ncols = c.k;
+            P.full = 0;
+            P.sampled = 1;
+            P.a_off = a_off; a_off += (int64_t)P.L * P.Qn;
+            P.om_off = om_off; om_off += (int64_t)P.nb * P.s;
+            P.x_off = x_off; x_off += (int64_t)P.nl * P.bp * P.sp;
+            P.E_off = E_off; E_off += (int64_t)P.nl * P.bp * P.bp;
+            P.Y_off = Y_off; Y_off += (int64_t)P.nrows * P.s;
+            P.Q_off = Q_off; Q_off += (int64_t)P.nrows * P.ncols;
+            P.sv_off = sv_off; sv_off += P.s;
+            P.rn_off = rn_off; rn_off += 2 * P.sp;
+            c.hp.push_back(P);
+        }
+    c.aL_total = a_off; c.omega_total = om_off; c.x_total = x_off; c.E_total = E_off;
+    c.Y_total = Y_off; c.Q_total = Q_off; c.sv_total = sv_off;
+    c.n_bdry = 4 * N;
+    c.n_nodes = (int64_t)(N + 1) * (N + 1);
+}
+
+void build_kinetic(Ctx& c) {
+    const int Nx = c.N, M = c.M, nH = Nx / M, nv = c.nv;
+    const bool ends = (c.flags & MSRS_FLAG_FULL_BASIS_ENDS) != 0;
+    int64_t a_off = 0, om_off = 0, x_off = 0, E_off = 0, Y_off = 0, Q_off = 0, sv_off = 0, rn_off = 0;
+    for (int m = 0; m < M; ++m) {
+        const bool full = ends && (m == 0 || m == M - 1);
+        const int d = full ? 0 : c.overlap[m];
+        PatchDesc P{};
+        const int x0 = std::max(0, m * nH - d), x1 = std::min(Nx, (m + 1) * nH + d);
+        P.x0 = x0; P.cx = x1 - x0; P.y0 = 0; P.cy = 0;
+        P.trans = 0;
+        P.L = nv; P.Qn = P.cx;
+        P.b = nv; P.nl = P.cx; P.bp = std::max(16, round16(nv));
+        P.nb = nv;
+        P.s = full ? nv : c.s;
+        P.sp = round16(P.s);
+        P.kx0 = m * nH; P.ky0 = 0; P.nH = nH;
+        P.nrows = (nH + 2) * nv;
+        P.ncols = full ? nv : c.k;
+        P.full = full ? 1 : 0;
+        P.sampled = full ? 0 : 1;
+        P.a_off = a_off; a_off += P.cx;
+        P.om_off = om_off; om_off += (int64_t)P.nb * P.s;
+        P.x_off = x_off; x_off += (int64_t)P.nl * P.bp * P.sp;
+        P.E_off = E_off; E_off += (int64_t)P.nl * P.bp * P.bp;
+        P.Y_off = Y_off; Y_off += (int64_t)P.nrows * P.s;
+        P.Q_off = Q_off; Q_off += (int64_t)P.nrows * P.ncols;
+        P.sv_off = sv_off; sv_off += P.s;
+        P.rn_off = rn_off; rn_off += 2 * P.sp;
+        c.hp.push_back(P);
+    }
+    c.aL_total = a_off; c.omega_total = om_off; c.x_total = x_off; c.E_total = E_off;
+    c.Y_total = Y_off; c.Q_total = Q_off; c.sv_total = sv_off;
+    c.n_bdry = nv;
+    c.n_nodes = (int64_t)Nx * nv;
+}
+
+msrs_status validate(const msrs_problem_desc* d, std::string& msg) {
+    if (!d) { msg = "desc is NULL"; return MSRS_ERR_ARG; }
+    if (d->kind != MSRS_KIND_ELLIPTIC_Q1 && d->kind != MSRS_KIND_KINETIC_DO) { msg = "unknown kind"; return MSRS_ERR_ARG; }
+    if (d->n_cells <= 0 || d->M <= 0 || d->n_cells % d->M) { msg = "M must divide n_cells"; return MSRS_ERR_ARG; }
+    if (d->n_samples < 1 || d->n_samples > kMaxSamples) { msg = "n_samples must be in [1, 64]"; return MSRS_ERR_ARG; }
+    if (d->rank < 1 || d->rank > d->n_samples) { msg = "rank must be in [1, n_samples]"; return MSRS_ERR_ARG; }
+    if (d->precision != MSRS_PREC_FP64 && d->precision != MSRS_PREC_FP32_IR) { msg = "unknown precision"; return MSRS_ERR_ARG; }
+    if (!d->overlap) { msg = "overlap is NULL"; return MSRS_ERR_ARG; }
+    const int np = d->kind == MSRS_KIND_ELLIPTIC_Q1 ? d->M * d->M : d->M;
+    for (int p = 0; p < np; ++p)
+        if (d->overlap[p] < 0) { msg = "negative overlap"; return MSRS_ERR_ARG; }
+    if (d->kind == MSRS_KIND_ELLIPTIC_Q1) {
+        const int nH = d->n_cells / d->M;
+        if (nH < 2) { msg = "patches need at least 2 cells per side"; return MSRS_ERR_ARG; }
+        for (int m2 = 0; m2 < d->M; ++m2)
+            for (int m1 = 0; m1 < d->M; ++m1) {
+                const int dd = d->overlap[m2 * d->M + m1];
+                const int cx = std::min(d->n_cells, (m1 + 1) * nH + dd) - std::max(0, m1 * nH - dd);
+                const int cy = std::min(d->n_cells, (m2 + 1) * nH + dd) - std::max(0, m2 * nH - dd);
+                if (std::min(cx, cy) - 1 > kMaxLine) { msg = "buffered patch too large: min side must be <= 129 cells"; return MSRS_ERR_ARG; }
+            }
+        if (d->M < 2) { msg = "elliptic needs M >= 2"; return MSRS_ERR_ARG; }
+    } else {
+        if (d->n_vel < 2 || d->n_vel > 32 || (d->n_vel & 1)) { msg = "n_vel must be even, 2..32"; return MSRS_ERR_ARG; }
+        if (!(d->eps > 0)) { msg = "eps must be positive"; return MSRS_ERR_ARG; }
+        if (d->M < 2) { msg = "kinetic needs M >= 2"; return MSRS_ERR_ARG; }
+        if (d->n_cells / d->M < 1) { msg = "patch too small"; return MSRS_ERR_ARG; }
+    }
+    return MSRS_OK;
+}
+
+void latch_from_host(Ctx& c, msrs_status& st) {
+    // flags copied to pinned memory by the last synchronising call
+    if (c.hflags[0]) { st = MSRS_ERR_NOT_SPD; c.err = "non-positive coefficient or pivot"; }
+    else if (c.hflags[1]) { st = MSRS_ERR_NOCONV; c.err = "iterative refinement did not reach ir_tol"; }
+    else if (c.hflags[2]) { st = MSRS_ERR_RANK; c.err = "sketch rank below the requested rank"; }
+    else if (c.hflags[3]) { st = MSRS_ERR_ARG; c.err = "unsupported patch shape on the device"; }
+}
+
+void sync_flags(Ctx& c) {
+    MSRS_HIP_CHECK(hipMemcpyAsync(c.hflags, c.dflags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+    MSRS_HIP_CHECK(hipStreamSynchronize(c.stream));
+}
+
+void resolve_timing(Ctx& c) {
+    for (auto& pe : c.pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) c.tms[pe.cls] += ms;
+        c.event_pool.push_back(pe.a);
+        c.event_pool.push_back(pe.b);
+    }
+    c.pending.clear();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- StageTimer
+namespace msrs {
+static hipEvent_t take_event(Ctx& c) {
+    if (!c.event_pool.empty()) {
+        hipEvent_t e = c.event_pool.back();
+        c.event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    MSRS_HIP_CHECK(hipEventCreate(&e));
+    return e;
+}
+StageTimer::StageTimer(Ctx& cc, int k) : c(cc), cls(k) {
+    c.tlaunch[cls] += 1;
+    if (!c.timing) return;
+    a = take_event(c);
+    b = take_event(c);
+    MSRS_HIP_CHECK(hipEventRecord(a, c.stream));
+}
+StageTimer::~StageTimer() {
+    if (!c.timing || !a) return;
+    if (hipEventRecord(b, c.stream) == hipSuccess) c.pending.push_back({cls, a, b});
+}
+}  // namespace msrs
+
+// ---------------------------------------------------------------- ABI
+extern "C" {
+
+int32_t msrs_version(void) { return 100; }
+
+int32_t msrs_device_count(void) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+    return n;
+}
+
+msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* stream, size_t hbm_budget_bytes) {
+    if (!out) return fail(nullptr, MSRS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    std::string msg;
+    msrs_status st = validate(desc, msg);
+    if (st != MSRS_OK) return fail(nullptr, st, msg);
+    if (msrs_device_count() <= 0) return fail(nullptr, MSRS_ERR_NO_DEVICE, "no HIP device visible");
+    msrs_ctx* c = new (std::nothrow) msrs_ctx();
+    if (!c) return fail(nullptr, MSRS_ERR_OOM, "host allocation failed");
+    try {
+        MSRS_HIP_CHECK(hipGetDevice(&c->device));
+        c->kind = desc->kind == MSRS_KIND_ELLIPTIC_Q1 ? kElliptic : kKinetic;
+        c->stream = (hipStream_t)stream;
+        c->N = desc->n_cells; c->M = desc->M; c->s = desc->n_samples; c->k = desc->rank;
+        c->prec = desc->precision;
+        c->ir_max = desc->ir_max_iters > 0 ? desc->ir_max_iters : 30;
+        c->ir_tol = desc->ir_tol > 0 ? desc->ir_tol : 1e-10;
+        c->eps = desc->kind == MSRS_KIND_KINETIC_DO ? desc->eps : 1.0;
+        c->nv = desc->kind == MSRS_KIND_KINETIC_DO ? desc->n_vel : 0;
+        c->seed = desc->seed;
+        c->flags = desc->flags;
+        c->timing = (desc->flags & MSRS_FLAG_TIMING) != 0;
+        c->budget = hbm_budget_bytes;
+        const int np = c->kind == kElliptic ? c->M * c->M : c->M;
+        c->overlap.assign(desc->overlap, desc->overlap + np);
+        if (c->kind == kElliptic) build_elliptic(*c); else build_kinetic(*c);
+        c->n_patches = (int)c->hp.size();
+        // footprint
+        const bool ir = c->prec == MSRS_PREC_FP32_IR;
+        int64_t need = c->aL_total * 8 + c->omega_total * 8 + c->x_total * 8 + (ir ? c->x_total * 4 : 0) +
+                       c->E_total * (ir ? 4 : 8) + c->Y_total * 8 + c->Q_total * 8 + c->sv_total * 8;
+        need += (c->kind == kElliptic ? (int64_t)c->N * c->N : c->N) * 8;
+        if (c->budget && (size_t)need > c->budget) {
+            delete c;
+            return fail(nullptr, MSRS_ERR_OOM, "footprint exceeds the HBM budget");
+        }
+        c->dp = dalloc<PatchDesc>(*c, c->n_patches);
+        MSRS_HIP_CHECK(hipMemcpy(c->dp, c->hp.data(), sizeof(PatchDesc) * c->n_patches, hipMemcpyHostToDevice));
+        c->aL = dalloc<double>(*c, c->aL_total);
+        c->om = dalloc<double>(*c, c->omega_total);
+        c->x64 = dalloc<double>(*c, c->x_total);
+        if (ir) c->x32 = dalloc<float>(*c, c->x_total);
+        c->E = ir ? (void*)dalloc<float>(*c, c->E_total) : (void*)dalloc<double>(*c, c->E_total);
+        c->Y = dalloc<double>(*c, c->Y_total);
+        c->Q = dalloc<double>(*c, c->Q_total);
+        c->sv = dalloc<double>(*c, c->sv_total);
+        int64_t rn_total = 0;
+        for (auto& P : c->hp) rn_total += 2 * P.sp;
+        c->rn = dalloc<double>(*c, rn_total);
+        c->gap = dalloc<double>(*c, 2 * c->n_patches);
+        c->conv = dalloc<int32_t>(*c, c->n_patches);
+        c->iters = dalloc<int32_t>(*c, c->n_patches);
+        c->dflags = dalloc<int32_t>(*c, 4);
+        c->coef_copy = dalloc<double>(*c, c->kind == kElliptic ? (int64_t)c->N * c->N : c->N);
+        MSRS_HIP_CHECK(hipMemset(c->dflags, 0, 4 * sizeof(int32_t)));
+        MSRS_HIP_CHECK(hipMemset(c->gap, 0, 2 * c->n_patches * sizeof(double)));
+        MSRS_HIP_CHECK(hipMemset(c->iters, 0, c->n_patches * sizeof(int32_t)));
+        MSRS_HIP_CHECK(hipMemset(c->x64, 0, c->x_total * sizeof(double)));
+        MSRS_HIP_CHECK(hipHostMalloc((void**)&c->hflags, 4 * sizeof(int32_t), hipHostMallocDefault));
+        std::memset(c->hflags, 0, 4 * sizeof(int32_t));
+        std::vector<double> vw(2 * std::max(c->nv, 1), 0.0);
+        if (c->kind == kKinetic) {
+            std::vector<double> x, w;
+            gauss_legendre(c->nv, x, w);
+            for (int i = 0; i < c->nv; ++i) { vw[i] = x[i]; vw[c->nv + i] = w[i]; }
+        }
+        c->vw = dalloc<double>(*c, (int64_t)vw.size());
+        MSRS_HIP_CHECK(hipMemcpy(c->vw, vw.data(), vw.size() * sizeof(double), hipMemcpyHostToDevice));
+        if (c->budget && (size_t)c->bytes > c->budget) {
+            msrs_destroy(c);
+            return fail(nullptr, MSRS_ERR_OOM, "footprint exceeds the HBM budget");
+        }
+    } catch (const HipError& e) {
+        msrs_status s2 = hip_fail(nullptr, e);
+        msrs_destroy(c);
+        return s2;
+    }
+    *out = c;
+    return MSRS_OK;
+}
+
+msrs_status msrs_assemble_patch(msrs_handle h, const double* coef_dev) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (!coef_dev) return fail(c, MSRS_ERR_ARG, "coef_dev is NULL");
+    try {
+        const int64_t n = c->kind == kElliptic ? (int64_t)c->N * c->N : c->N;
+        MSRS_HIP_CHECK(hipMemcpyAsync(c->coef_copy, coef_dev, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        for_patches(*c, [&](int p0, int p1) {
+            if (c->kind == kElliptic) launch_gather_elliptic(*c, c->coef_copy, p0, p1);
+            else launch_gather_kinetic(*c, c->coef_copy, p0, p1);
+        });
+        for_patches(*c, [&](int p0, int p1) { launch_factor(*c, p0, p1); });
+        MSRS_HIP_CHECK(hipGetLastError());
+    } catch (const HipError& e) {
+        return hip_fail(c, e);
+    }
+    c->assembled = true;
+    c->sampled = c->ranged = c->coarse_ready = false;
+    return MSRS_OK;
+}
+
+msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, double* Y_out_dev) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (!c->assembled) return fail(c, MSRS_ERR_STATE, "msrs_assemble_patch must come first");
+    try {
+        for_patches(*c, [&](int p0, int p1) { launch_omega(*c, omega_dev, p0, p1); });
+        for_patches(*c, [&](int p0, int p1) { launch_lift(*c, p0, p1); });
+        if (c->prec == MSRS_PREC_FP64) {
+            for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, false); });
+            for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, true, 0); });
+            c->last_ir_iters = 0;
+        } else {
+            launch_clear_conv(*c);
+            int it = 0;
+            const int first = std::min(c->ir_max, c->ir_hint);
+            for (; it < first; ++it) {
+                for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true); });
+                for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, true, false, it); });
+            }
+            // continue until every patch has converged (one host check per extra iteration)
+            std::vector<int32_t> conv(c->n_patches);
+            while (true) {
+                MSRS_HIP_CHECK(hipMemcpyAsync(conv.data(), c->conv, c->n_patches * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+                MSRS_HIP_CHECK(hipStreamSynchronize(c->stream));
+                const bool all = std::all_of(conv.begin(), conv.end(), [](int32_t v) { return v != 0; });
+                if (all || it >= c->ir_max) {
+                    if (!all) {
+                        const int32_t one = 1;
+                        MSRS_HIP_CHECK(hipMemcpyAsync(c->dflags + 1, &one, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+                        MSRS_HIP_CHECK(hipStreamSynchronize(c->stream));
+                    }
+                    break;
+                }
+                for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true); });
+                for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, true, false, it); });
+                ++it;
+            }
+            std::vector<int32_t> iters(c->n_patches);
+            MSRS_HIP_CHECK(hipMemcpy(iters.data(), c->iters, c->n_patches * sizeof(int32_t), hipMemcpyDeviceToHost));
+            int mx = 0;
+            for (int v : iters) mx = std::max(mx, v);
+            c->last_ir_iters = it;
+            c->ir_hint = std::max(1, mx);
+        }
+        for_patches(*c, [&](int p0, int p1) { launch_restrict(*c, p0, p1); });
+        if (Y_out_dev)
+            MSRS_HIP_CHECK(hipMemcpyAsync(Y_out_dev, c->Y, c->Y_total * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        MSRS_HIP_CHECK(hipGetLastError());
+    } catch (const HipError& e) {
+        return hip_fail(c, e);
+    }
+    c->sampled = true;
+    c->ranged = c->coarse_ready = false;
+    return MSRS_OK;
+}
+
+msrs_status msrs_range_finder(msrs_handle h, double* Q_out_dev, double* sv_out_dev) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (!c->sampled) return fail(c, MSRS_ERR_STATE, "msrs_sample_local_solutions must come first");
+    try {
+        for_patches(*c, [&](int p0, int p1) { launch_range(*c, p0, p1); });
+        if (Q_out_dev)
+            MSRS_HIP_CHECK(hipMemcpyAsync(Q_out_dev, c->Q, c->Q_total * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        if (sv_out_dev)
+            MSRS_HIP_CHECK(hipMemcpyAsync(sv_out_dev, c->sv, c->sv_total * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        MSRS_HIP_CHECK(hipGetLastError());
+    } catch (const HipError& e) {
+        return hip_fail(c, e);
+    }
+    c->ranged = true;
+    c->coarse_ready = false;
+    return MSRS_OK;
+}
+
+msrs_status msrs_copy_omega(msrs_handle h, double* omega_out_dev) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (!omega_out_dev) return fail(c, MSRS_ERR_ARG, "omega_out_dev is NULL");
+    if (!c->sampled) return fail(c, MSRS_ERR_STATE, "msrs_sample_local_solutions must come first");
+    try {
+        MSRS_HIP_CHECK(hipMemcpyAsync(omega_out_dev, c->om, c->omega_total * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    } catch (const HipError& e) {
+        return hip_fail(c, e);
+    }
+    return MSRS_OK;
+}
+
+msrs_status msrs_set_max_batch(msrs_handle h, int32_t max_batch) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (max_batch < 1 || max_batch > 64) return fail(c, MSRS_ERR_ARG, "max_batch must be in [1, 64]");
+    if (c->coarse_ready) return fail(c, MSRS_ERR_STATE, "call before msrs_assemble_coarse");
+    c->max_batch = max_batch;
+    return MSRS_OK;
+}
+
+msrs_status msrs_assemble_coarse(msrs_handle h) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (!c->ranged) return fail(c, MSRS_ERR_STATE, "msrs_range_finder must come first");
+    try {
+        if (!c->dc) {
+            c->hc.assign(c->n_patches, CoarseDesc{});
+            int off = 0;
+            for (int p = 0; p < c->n_patches; ++p) {
+                c->hc[p].col_off = off;
+                c->hc[p].ncols = c->hp[p].ncols;
+                off += c->hp[p].ncols;
+            }
+            c->Np = off;
+            // half bandwidth: last unknown of the farthest coupled patch
+            int bw = 0;
+            for (int p = 0; p < c->n_patches; ++p) {
+                int far = p;
+                if (c->kind == kElliptic) {
+                    const int m1 = p % c->M, m2 = p / c->M;
+                    if (m2 < c->M - 1) far = p + c->M + (m1 < c->M - 1 ? 1 : 0);
+                    else if (m1 < c->M - 1) far = p + 1;
+                } else {
+                    far = std::min(p + 1, c->n_patches - 1);
+                }
+                bw = std::max(bw, c->hc[far].col_off + c->hc[far].ncols - 1 - c->hc[p].col_off);
+            }
+            c->bw = std::min(bw, c->Np - 1);
+            if (c->bw + 1 > 1024) return fail(c, MSRS_ERR_ARG, "coarse band wider than 1023");
+            int kmax = 0;
+            for (auto& d : c->hc) kmax = std::max(kmax, d.ncols);
+            c->dc = dalloc<CoarseDesc>(*c, c->n_patches);
+            MSRS_HIP_CHECK(hipMemcpy(c->dc, c->hc.data(), sizeof(CoarseDesc) * c->n_patches, hipMemcpyHostToDevice));
+            if (c->kind == kElliptic) c->tr = dalloc<double>(*c, (int64_t)c->n_patches * 2 * 4 * (c->N / c->M) * kmax);
+            c->band = dalloc<double>(*c, (int64_t)c->Np * (c->bw + 1));
+            c->crhs = dalloc<double>(*c, (int64_t)c->Np * c->max_batch);
+            if (c->budget && (size_t)c->bytes > c->budget) return fail(c, MSRS_ERR_OOM, "coarse factor exceeds the HBM budget");
+        }
+        coarse_setup(*c);
+        MSRS_HIP_CHECK(hipGetLastError());
+        sync_flags(*c);
+    } catch (const HipError& e) {
+        return hip_fail(c, e);
+    }
+    msrs_status st = MSRS_OK;
+    if (c->hflags[0]) { st = MSRS_ERR_NOT_SPD; c->err = "normal equations not positive definite (P~ rank deficient)"; }
+    if (st == MSRS_OK) c->coarse_ready = true;
+    return st;
+}
+
+msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev, void* stream) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (!c->coarse_ready) return fail(c, MSRS_ERR_STATE, "msrs_assemble_coarse must come first");
+    if (n_req < 1 || n_req > c->max_batch) return fail(c, MSRS_ERR_ARG, "n_req must be in [1, max_batch]");
+    if (!f_dev || !u_dev) return fail(c, MSRS_ERR_ARG, "f_dev / u_dev is NULL");
+    try {
+        hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+        coarse_solve(*c, n_req, f_dev, u_dev, st);
+        MSRS_HIP_CHECK(hipGetLastError());
+    } catch (const HipError& e) {
+        return hip_fail(c, e);
+    }
+    return MSRS_OK;
+}
+
+msrs_status msrs_query_layout(msrs_handle h, msrs_layout* out) {
+    Ctx* c = h;
+    if (!c || !out) return fail(c, MSRS_ERR_ARG, "NULL argument");
+    out->n_patches = c->n_patches;
+    out->n_samples = c->s;
+    out->rank = c->k;
+    out->n_bdry = c->n_bdry;
+    out->n_nodes = c->n_nodes;
+    out->omega_total = c->omega_total;
+    out->Y_total = c->Y_total;
+    out->Q_total = c->Q_total;
+    out->sv_total = c->sv_total;
+    int64_t np = 0;
+    for (auto& P : c->hp) np += P.ncols;
+    out->coarse_dim = np;
+    out->device_bytes = c->bytes;
+    return MSRS_OK;
+}
+
+msrs_status msrs_query_patch(msrs_handle h, int32_t patch, msrs_patch_info* out) {
+    Ctx* c = h;
+    if (!c || !out) return fail(c, MSRS_ERR_ARG, "NULL argument");
+    if (patch < 0 || patch >= c->n_patches) return fail(c, MSRS_ERR_ARG, "patch out of range");
+    const PatchDesc& P = c->hp[patch];
+    out->x0 = P.x0; out->y0 = P.y0; out->cx = P.cx; out->cy = P.cy;
+    out->kx0 = P.kx0; out->ky0 = P.ky0; out->nH = P.nH;
+    out->n_bdry = P.nb;
+    out->n_rows = P.nrows;
+    out->n_cols = P.ncols;
+    out->full_basis = P.full;
+    out->line_len = P.b;
+    out->n_lines = P.nl;
+    out->n_samples = P.s;
+    out->omega_off = P.om_off; out->Y_off = P.Y_off; out->Q_off = P.Q_off; out->sv_off = P.sv_off;
+    return MSRS_OK;
+}
+
+msrs_status msrs_get_stats(msrs_handle h, msrs_stats* out) {
+    Ctx* c = h;
+    if (!c || !out) return fail(c, MSRS_ERR_ARG, "NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    msrs_status st = MSRS_OK;
+    try {
+        sync_flags(*c);
+        std::vector<double> g(2 * c->n_patches);
+        MSRS_HIP_CHECK(hipMemcpy(g.data(), c->gap, g.size() * sizeof(double), hipMemcpyDeviceToHost));
+        double mg = 1e300, mr = 0.0;
+        for (int p = 0; p < c->n_patches; ++p) {
+            if (c->hp[p].sampled) mg = std::min(mg, g[p]);
+            mr = std::max(mr, g[c->n_patches + p]);
+        }
+        out->min_rel_gap = mg == 1e300 ? 0.0 : mg;
+        out->max_rel_residual = mr;
+        out->ir_iters = c->last_ir_iters;
+        resolve_timing(*c);
+        for (int i = 0; i < 12; ++i) { out->kernel_ms[i] = c->tms[i]; out->kernel_launches[i] = c->tlaunch[i]; }
+    } catch (const HipError& e) {
+        return hip_fail(c, e);
+    }
+    latch_from_host(*c, st);
+    out->error_latched = st;
+    return st;
+}
+
+msrs_status msrs_reset_stats(msrs_handle h) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    try {
+        MSRS_HIP_CHECK(hipStreamSynchronize(c->stream));
+        resolve_timing(*c);
+    } catch (const HipError& e) {
+        return hip_fail(c, e);
+    }
+    for (int i = 0; i < 12; ++i) { c->tms[i] = 0; c->tlaunch[i] = 0; }
+    return MSRS_OK;
+}
+
+const char* msrs_last_error(msrs_handle h) {
+    if (!h) return g_create_err.c_str();
+    return h->err.c_str();
+}
+
+void msrs_destroy(msrs_handle h) {
+    msrs_ctx* c = h;
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& pe : c->pending) { (void)hipEventDestroy(pe.a); (void)hipEventDestroy(pe.b); }
+    for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    for (void* p : c->allocs) (void)hipFree(p);
+    if (c->hflags) (void)hipHostFree(c->hflags);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,410 @@
+// Online stage (beside the hot path): least-squares gluing of the local bases.
+//
+// Elliptic (eqs. elliptic_cond_tilde, elliptic_cond_reduced): rows of P~ are
+// value continuity at every node of each interior coarse edge, conormal-flux
+// continuity at the edge's inner nodes, a four-patch flux balance at each
+// interior coarse vertex, and Dirichlet rows on dOmega.  The discrete
+// conormal flux of a basis function q at a node of dK_m is
+// (A^{K_m} q)(x) / h with A^{K_m} the stiffness of K_m's own elements.
+// Kinetic (eqs. gb3, rte_cond_reduced): per interface, v>0 values of the last
+// cell of K_m equal the left ghost of K_{m+1}, v<0 values of K_m's right
+// ghost equal the first cell of K_{m+1}; inflow rows at x = 0 and x = 1.
+//
+// The normal equations P~^T P~ c = P~^T d are block banded (patch order);
+// they are formed in lower band storage band[j*(bw+1) + d] = A[j+d][j],
+// factored once by a band Cholesky, and every request is two band
+// triangular solves plus the reconstruction u = sum_m w_m Q_m c_m (nodal
+// partition of unity w_m = 1/#patches at shared elliptic nodes).
+#include "device_common.h"
+
+namespace msrs {
+
+// element matrix of the bilinear element (times 6), local order SW SE NE NW
+__device__ __constant__ double kKref6[16] = {4, -1, -2, -1, -1, 4, -1, -2, -2, -1, 4, -1, -1, -2, -1, 4};
+
+__device__ __forceinline__ void kbnode(int t, int nH, int& ii, int& jj) {
+    if (t < nH) { ii = t; jj = 0; }
+    else if (t < 2 * nH) { ii = nH; jj = t - nH; }
+    else if (t < 3 * nH) { ii = 3 * nH - t; jj = nH; }
+    else { ii = 0; jj = 4 * nH - t; }
+}
+
+__device__ __forceinline__ int kb_index(int ii, int jj, int nH) {
+    if (jj == 0 && ii < nH) return ii;
+    if (ii == nH && jj < nH) return nH + jj;
+    if (jj == nH && ii > 0) return 2 * nH + (nH - ii);
+    return 3 * nH + (nH - jj);
+}
+
+// global boundary index (counter-clockwise from (0,0)) of node (gx, gy) on dOmega
+__device__ __forceinline__ int gb_index(int gx, int gy, int N) { return kb_index(gx, gy, N); }
+
+// ------------------------------------------------------------ elliptic traces
+// tr layout per patch: [values 4nH x ncols][fluxes 4nH x ncols], row-major (t, col).
+__global__ __launch_bounds__(kThreads) void traces_elliptic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ a,
+                                                                   int N, const double* __restrict__ Q_all, double* __restrict__ tr,
+                                                                   int64_t tr_stride) {
+    const int p = blockIdx.x;
+    const PatchDesc P = pd[p];
+    const int nH = P.nH, W = nH + 1, nc = cd[p].ncols;
+    const double* Q = Q_all + P.Q_off;
+    double* T = tr + (int64_t)p * tr_stride;
+    const double invh = (double)N;
+    for (int o = threadIdx.x; o < 4 * nH * nc; o += kThreads) {
+        const int t = o % (4 * nH), col = o / (4 * nH);
+        int ii, jj;
+        kbnode(t, nH, ii, jj);
+        const double* q = Q + (int64_t)col * P.nrows;
+        double flux = 0.0;
+        // elements around the node: NE (node is SW corner), NW (SE), SW (NE), SE (NW)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int ei = (e == 0 || e == 3) ? ii : ii - 1;
+            const int ej = (e == 0 || e == 1) ? jj : jj - 1;
+            if (ei < 0 || ej < 0 || ei >= nH || ej >= nH) continue;
+            const int alpha = (e == 0) ? 0 : (e == 1) ? 1 : (e == 2) ? 2 : 3;
+            const double ae = a[(size_t)(P.ky0 + ej) * N + P.kx0 + ei];
+            const double cq[4] = {q[ej * W + ei], q[ej * W + ei + 1], q[(ej + 1) * W + ei + 1], q[(ej + 1) * W + ei]};
+            double s = 0.0;
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) s += kKref6[alpha * 4 + bb] * cq[bb];
+            flux += ae * s / 6.0;
+        }
+        T[t * nc + col] = q[jj * W + ii];
+        T[4 * nH * nc + t * nc + col] = flux * invh;
+    }
+}
+
+// ------------------------------------------------------------ normal matrix
+__global__ void fill_kernel(double* a, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] = v;
+}
+
+struct ElTr {
+    const double* T;
+    int nH, nc;
+    __device__ double val(int ii, int jj, int c) const { return T[kb_index(ii, jj, nH) * nc + c]; }
+    __device__ double flx(int ii, int jj, int c) const { return T[4 * nH * nc + kb_index(ii, jj, nH) * nc + c]; }
+};
+
+__device__ __forceinline__ void band_add(double* band, int bw, int row, int col, double v) {
+    // lower storage; caller guarantees row >= col
+    band[(int64_t)col * (bw + 1) + (row - col)] += v;
+}
+
+// One workgroup per patch m: B_mm and the blocks with the neighbours n > m.
+__global__ __launch_bounds__(kThreads) void normal_elliptic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ tr,
+                                                                   int64_t tr_stride, int M, int N, double* __restrict__ band, int bw) {
+    const int m = blockIdx.x;
+    const int m1 = m % M, m2 = m / M;
+    const int nH = pd[m].nH;
+    auto TR = [&](int p) { return ElTr{tr + (int64_t)p * tr_stride, nH, cd[p].ncols}; };
+    const ElTr Tm = TR(m);
+    const int km = cd[m].ncols, om = cd[m].col_off;
+    // ---- B_mm
+    for (int o = threadIdx.x; o < km * km; o += kThreads) {
+        const int a = o / km, b = o % km;
+        if (b < a) continue;      // lower storage: row (b) >= col (a)
+        double s = 0.0;
+        // edges: right, left, top, bottom
+        if (m1 < M - 1) { for (int t = 0; t <= nH; ++t) s += Tm.val(nH, t, a) * Tm.val(nH, t, b);
+                          for (int t = 1; t < nH; ++t) s += Tm.flx(nH, t, a) * Tm.flx(nH, t, b); }
+        if (m1 > 0)     { for (int t = 0; t <= nH; ++t) s += Tm.val(0, t, a) * Tm.val(0, t, b);
+                          for (int t = 1; t < nH; ++t) s += Tm.flx(0, t, a) * Tm.flx(0, t, b); }
+        if (m2 < M - 1) { for (int t = 0; t <= nH; ++t) s += Tm.val(t, nH, a) * Tm.val(t, nH, b);
+                          for (int t = 1; t < nH; ++t) s += Tm.flx(t, nH, a) * Tm.flx(t, nH, b); }
+        if (m2 > 0)     { for (int t = 0; t <= nH; ++t) s += Tm.val(t, 0, a) * Tm.val(t, 0, b);
+                          for (int t = 1; t < nH; ++t) s += Tm.flx(t, 0, a) * Tm.flx(t, 0, b); }
+        // interior vertices at the four corners
+        const int cx[4] = {0, nH, nH, 0}, cy[4] = {0, 0, nH, nH};
+        const int vx[4] = {m1, m1 + 1, m1 + 1, m1}, vy[4] = {m2, m2, m2 + 1, m2 + 1};
+        for (int cn = 0; cn < 4; ++cn)
+            if (vx[cn] > 0 && vx[cn] < M && vy[cn] > 0 && vy[cn] < M) s += Tm.flx(cx[cn], cy[cn], a) * Tm.flx(cx[cn], cy[cn], b);
+        // Dirichlet rows
+        for (int t = 0; t < 4 * nH; ++t) {
+            int ii, jj;
+            kbnode(t, nH, ii, jj);
+            const int gx = m1 * nH + ii, gy = m2 * nH + jj;
+            if (gx == 0 || gx == N || gy == 0 || gy == N) s += Tm.val(ii, jj, a) * Tm.val(ii, jj, b);
+        }
+        band_add(band, bw, om + b, om + a, s);
+    }
+    // ---- off-diagonal blocks B_{m,n}, n > m
+    const int nbrs[4] = {(m1 < M - 1) ? m + 1 : -1, (m1 > 0 && m2 < M - 1) ? m + M - 1 : -1,
+                         (m2 < M - 1) ? m + M : -1, (m1 < M - 1 && m2 < M - 1) ? m + M + 1 : -1};
+    for (int which = 0; which < 4; ++which) {
+        const int n = nbrs[which];
+        if (n < 0) continue;
+        const ElTr Tn = TR(n);
+        const int kn = cd[n].ncols, on = cd[n].col_off;
+        for (int o = threadIdx.x; o < km * kn; o += kThreads) {
+            const int a = o / kn, b = o % kn;
+            double s = 0.0;
+            if (which == 0) {   // right neighbour
+                for (int t = 0; t <= nH; ++t) s -= Tm.val(nH, t, a) * Tn.val(0, t, b);
+                for (int t = 1; t < nH; ++t) s += Tm.flx(nH, t, a) * Tn.flx(0, t, b);
+                if (m2 > 0) s += Tm.flx(nH, 0, a) * Tn.flx(0, 0, b);          // bottom-right vertex
+                if (m2 < M - 1) s += Tm.flx(nH, nH, a) * Tn.flx(0, nH, b);    // top-right vertex
+            } else if (which == 1) {   // top-left diagonal neighbour: vertex at m's top-left
+                s += Tm.flx(0, nH, a) * Tn.flx(nH, 0, b);
+            } else if (which == 2) {   // top neighbour
+                for (int t = 0; t <= nH; ++t) s -= Tm.val(t, nH, a) * Tn.val(t, 0, b);
+                for (int t = 1; t < nH; ++t) s += Tm.flx(t, nH, a) * Tn.flx(t, 0, b);
+                if (m1 > 0) s += Tm.flx(0, nH, a) * Tn.flx(0, 0, b);          // top-left vertex
+                if (m1 < M - 1) s += Tm.flx(nH, nH, a) * Tn.flx(nH, 0, b);    // top-right vertex
+            } else {                   // top-right diagonal neighbour
+                s += Tm.flx(nH, nH, a) * Tn.flx(0, 0, b);
+            }
+            band_add(band, bw, on + b, om + a, s);
+        }
+    }
+}
+
+// kinetic rows read Q directly (restricted layout: cell c in [0, nH+2), ordinate j)
+__global__ __launch_bounds__(kThreads) void normal_kinetic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ Q_all,
+                                                                  const double* __restrict__ vw, int M, int nv,
+                                                                  double* __restrict__ band, int bw) {
+    const int m = blockIdx.x;
+    const PatchDesc P = pd[m];
+    const int nH = P.nH, km = cd[m].ncols, om = cd[m].col_off;
+    const double* Qm = Q_all + P.Q_off;
+    const int nr = P.nrows;
+    auto q = [&](const double* Qb, int nrw, int cell, int j, int col) { return Qb[(int64_t)col * nrw + cell * nv + j]; };
+    for (int o = threadIdx.x; o < km * km; o += kThreads) {
+        const int a = o / km, b = o % km;
+        if (b < a) continue;
+        double s = 0.0;
+        for (int j = 0; j < nv; ++j) {
+            const bool pos = vw[j] > 0;
+            if (m == 0 && pos) s += q(Qm, nr, 0, j, a) * q(Qm, nr, 0, j, b);
+            if (m == M - 1 && !pos) s += q(Qm, nr, nH + 1, j, a) * q(Qm, nr, nH + 1, j, b);
+            if (m < M - 1) { const int cc = pos ? nH : nH + 1; s += q(Qm, nr, cc, j, a) * q(Qm, nr, cc, j, b); }
+            if (m > 0) { const int cc = pos ? 0 : 1; s += q(Qm, nr, cc, j, a) * q(Qm, nr, cc, j, b); }
+        }
+        band_add(band, bw, om + b, om + a, s);
+    }
+    if (m < M - 1) {
+        const PatchDesc Pn = pd[m + 1];
+        const double* Qn = Q_all + Pn.Q_off;
+        const int kn = cd[m + 1].ncols, on = cd[m + 1].col_off;
+        for (int o = threadIdx.x; o < km * kn; o += kThreads) {
+            const int a = o / kn, b = o % kn;
+            double s = 0.0;
+            for (int j = 0; j < nv; ++j) {
+                const bool pos = vw[j] > 0;
+                s -= pos ? q(Qm, nr, nH, j, a) * q(Qn, Pn.nrows, 0, j, b) : q(Qm, nr, nH + 1, j, a) * q(Qn, Pn.nrows, 1, j, b);
+            }
+            band_add(band, bw, on + b, om + a, s);
+        }
+    }
+}
+
+// ------------------------------------------------------------ band Cholesky
+__global__ __launch_bounds__(1024) void band_cholesky_kernel(double* __restrict__ band, int n, int bw, int32_t* flags) {
+    __shared__ double col[1024];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int ld = bw + 1;
+    for (int j = 0; j < n; ++j) {
+        double* Lj = band + (int64_t)j * ld;
+        const int m = min(bw, n - 1 - j);
+        const double d = Lj[0];
+        if (!(d > 0.0) || !isfinite(d)) {
+            if (tid == 0) raise_flag(flags, 0);
+        }
+        const double sd = d > 0.0 ? sqrt(d) : 1.0;
+        __syncthreads();
+        for (int i = tid; i <= m; i += nt) {
+            const double v = (i == 0) ? sd : Lj[i] / sd;
+            col[i] = v;
+        }
+        __syncthreads();
+        for (int i = tid; i <= m; i += nt) Lj[i] = col[i];
+        // trailing update A[j+b][j+a] -= L[j+b][j] L[j+a][j], 1 <= a <= b <= m
+        const int64_t tot = (int64_t)m * m;
+        for (int64_t o = tid; o < tot; o += nt) {
+            const int a = (int)(o / m) + 1, b = (int)(o % m) + 1;
+            if (b < a) continue;
+            band[(int64_t)(j + a) * ld + (b - a)] -= col[b] * col[a];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ per-request rhs
+__global__ __launch_bounds__(kThreads) void rhs_elliptic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ tr,
+                                                                int64_t tr_stride, int M, int N, int Np, const double* __restrict__ f,
+                                                                int n_req, double* __restrict__ rhs) {
+    const int m = blockIdx.x;
+    const int m1 = m % M, m2 = m / M;
+    const int nH = pd[m].nH;
+    const ElTr Tm{tr + (int64_t)m * tr_stride, nH, cd[m].ncols};
+    const int km = cd[m].ncols, om = cd[m].col_off;
+    for (int o = threadIdx.x; o < km * n_req; o += kThreads) {
+        const int a = o % km, r = o / km;
+        double s = 0.0;
+        if (m1 == 0 || m1 == M - 1 || m2 == 0 || m2 == M - 1)
+            for (int t = 0; t < 4 * nH; ++t) {
+                int ii, jj;
+                kbnode(t, nH, ii, jj);
+                const int gx = m1 * nH + ii, gy = m2 * nH + jj;
+                if (gx == 0 || gx == N || gy == 0 || gy == N) s += Tm.val(ii, jj, a) * f[(int64_t)r * 4 * N + gb_index(gx, gy, N)];
+            }
+        rhs[(int64_t)r * Np + om + a] = s;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void rhs_kinetic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ Q_all,
+                                                               const double* __restrict__ vw, int M, int nv, int Np,
+                                                               const double* __restrict__ f, int n_req, double* __restrict__ rhs) {
+    const int m = blockIdx.x;
+    const PatchDesc P = pd[m];
+    const int km = cd[m].ncols, om = cd[m].col_off, h = nv / 2;
+    const double* Q = Q_all + P.Q_off;
+    for (int o = threadIdx.x; o < km * n_req; o += kThreads) {
+        const int a = o % km, r = o / km;
+        double s = 0.0;
+        for (int j = 0; j < nv; ++j) {
+            if (m == 0 && vw[j] > 0) s += Q[(int64_t)a * P.nrows + 0 * nv + j] * f[(int64_t)r * nv + (j - h)];
+            if (m == M - 1 && vw[j] < 0) s += Q[(int64_t)a * P.nrows + (P.nH + 1) * nv + j] * f[(int64_t)r * nv + h + j];
+        }
+        rhs[(int64_t)r * Np + om + a] = s;
+    }
+}
+
+// ------------------------------------------------------------ band solves
+// One workgroup solves L L^T c = rhs for all n_req columns (in place).
+__global__ __launch_bounds__(1024) void band_solve_kernel(const double* __restrict__ band, int n, int bw, double* __restrict__ x, int n_req) {
+    __shared__ double piv[64];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int ld = bw + 1;
+    // forward: L y = b (column oriented)
+    for (int j = 0; j < n; ++j) {
+        const double* Lj = band + (int64_t)j * ld;
+        const int m = min(bw, n - 1 - j);
+        if (tid < n_req) {
+            const double y = x[(int64_t)tid * n + j] / Lj[0];
+            x[(int64_t)tid * n + j] = y;
+            piv[tid] = y;
+        }
+        __syncthreads();
+        for (int o = tid; o < m * n_req; o += nt) {
+            const int d = o % m + 1, r = o / m;
+            x[(int64_t)r * n + j + d] -= Lj[d] * piv[r];
+        }
+        __syncthreads();
+    }
+    // back: L^T c = y (column oriented on L^T)
+    for (int j = n - 1; j >= 0; --j) {
+        const double* Lj = band + (int64_t)j * ld;
+        if (tid < n_req) {
+            const double c = x[(int64_t)tid * n + j] / Lj[0];
+            x[(int64_t)tid * n + j] = c;
+            piv[tid] = c;
+        }
+        __syncthreads();
+        const int m = min(bw, j);
+        for (int o = tid; o < m * n_req; o += nt) {
+            const int d = o % m + 1, r = o / m;
+            const int i = j - d;
+            x[(int64_t)r * n + i] -= band[(int64_t)i * ld + d] * piv[r];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ reconstruction
+__global__ __launch_bounds__(kThreads) void recon_elliptic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ Q_all,
+                                                                  int M, int N, int Np, const double* __restrict__ c, int n_req,
+                                                                  double* __restrict__ u) {
+    const int64_t nn = (int64_t)(N + 1) * (N + 1);
+    const int nH = N / M, W = nH + 1;
+    for (int64_t node = blockIdx.x * (int64_t)kThreads + threadIdx.x; node < nn; node += (int64_t)gridDim.x * kThreads) {
+        const int gx = (int)(node % (N + 1)), gy = (int)(node / (N + 1));
+        int xs[2], ys[2], nx = 0, ny = 0;
+        if (gx % nH == 0 && gx > 0) xs[nx++] = gx / nH - 1;
+        if (gx / nH < M) xs[nx++] = gx / nH;
+        if (gy % nH == 0 && gy > 0) ys[ny++] = gy / nH - 1;
+        if (gy / nH < M) ys[ny++] = gy / nH;
+        const double w = 1.0 / (nx * ny);
+        for (int r = 0; r < n_req; ++r) u[(int64_t)r * nn + node] = 0.0;
+        for (int a = 0; a < nx; ++a)
+            for (int b = 0; b < ny; ++b) {
+                const int m = ys[b] * M + xs[a];
+                const PatchDesc& P = pd[m];
+                const int row = (gy - ys[b] * nH) * W + (gx - xs[a] * nH);
+                const int km = cd[m].ncols, om = cd[m].col_off;
+                const double* Q = Q_all + P.Q_off + row;
+                for (int r = 0; r < n_req; ++r) {
+                    double s = 0.0;
+                    for (int cc = 0; cc < km; ++cc) s += Q[(int64_t)cc * P.nrows] * c[(int64_t)r * Np + om + cc];
+                    u[(int64_t)r * nn + node] += w * s;
+                }
+            }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void recon_kinetic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ Q_all,
+                                                                 int M, int Nx, int nv, int Np, const double* __restrict__ c, int n_req,
+                                                                 double* __restrict__ u) {
+    const int64_t nn = (int64_t)Nx * nv;
+    const int nH = Nx / M;
+    for (int64_t idx = blockIdx.x * (int64_t)kThreads + threadIdx.x; idx < nn; idx += (int64_t)gridDim.x * kThreads) {
+        const int cell = (int)(idx / nv), j = (int)(idx % nv);
+        const int m = cell / nH;
+        const PatchDesc& P = pd[m];
+        const int row = (cell - m * nH + 1) * nv + j;
+        const int km = cd[m].ncols, om = cd[m].col_off;
+        const double* Q = Q_all + P.Q_off + row;
+        for (int r = 0; r < n_req; ++r) {
+            double s = 0.0;
+            for (int cc = 0; cc < km; ++cc) s += Q[(int64_t)cc * P.nrows] * c[(int64_t)r * Np + om + cc];
+            u[(int64_t)r * nn + idx] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------ host side
+void coarse_setup(Ctx& c) {
+    StageTimer t(c, MSRS_K_COARSE);
+    const int64_t nband = (int64_t)c.Np * (c.bw + 1);
+    hipLaunchKernelGGL(fill_kernel, dim3(256), dim3(256), 0, c.stream, c.band, nband, 0.0);
+    if (c.kind == kElliptic) {
+        const int64_t trs = 2LL * 4 * (c.N / c.M) * c.hc[0].ncols;
+        int kmax = 0;
+        for (auto& d : c.hc) kmax = std::max(kmax, d.ncols);
+        const int64_t tr_stride = 2LL * 4 * (c.N / c.M) * kmax;
+        (void)trs;
+        hipLaunchKernelGGL(traces_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.coef_copy, c.N, c.Q, c.tr, tr_stride);
+        hipLaunchKernelGGL(normal_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.tr, tr_stride, c.M, c.N, c.band, c.bw);
+    } else {
+        hipLaunchKernelGGL(normal_kinetic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.Q, c.vw, c.M, c.nv, c.band, c.bw);
+    }
+    hipLaunchKernelGGL(band_cholesky_kernel, dim3(1), dim3(1024), 0, c.stream, c.band, c.Np, c.bw, c.dflags);
+}
+
+void coarse_solve(Ctx& c, int n_req, const double* f, double* u, hipStream_t st) {
+    {
+        StageTimer t(c, MSRS_K_CSOLVE);
+        if (c.kind == kElliptic) {
+            int kmax = 0;
+            for (auto& d : c.hc) kmax = std::max(kmax, d.ncols);
+            const int64_t tr_stride = 2LL * 4 * (c.N / c.M) * kmax;
+            hipLaunchKernelGGL(rhs_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, st, c.dp, c.dc, c.tr, tr_stride, c.M, c.N, c.Np, f, n_req, c.crhs);
+        } else {
+            hipLaunchKernelGGL(rhs_kinetic_kernel, dim3(c.n_patches), dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.vw, c.M, c.nv, c.Np, f, n_req, c.crhs);
+        }
+        hipLaunchKernelGGL(band_solve_kernel, dim3(1), dim3(1024), 0, st, c.band, c.Np, c.bw, c.crhs, n_req);
+    }
+    StageTimer t2(c, MSRS_K_RECON);
+    if (c.kind == kElliptic) {
+        const int64_t nn = (int64_t)(c.N + 1) * (c.N + 1);
+        const int blocks = (int)std::min<int64_t>((nn + kThreads - 1) / kThreads, 4096);
+        hipLaunchKernelGGL(recon_elliptic_kernel, dim3(blocks), dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.M, c.N, c.Np, c.crhs, n_req, u);
+    } else {
+        const int64_t nn = (int64_t)c.N * c.nv;
+        const int blocks = (int)std::min<int64_t>((nn + kThreads - 1) / kThreads, 4096);
+        hipLaunchKernelGGL(recon_kinetic_kernel, dim3(blocks), dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.M, c.N, c.nv, c.Np, c.crhs, n_req, u);
+    }
+}
+
+}  // namespace msrs

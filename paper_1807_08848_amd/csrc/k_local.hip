@@ -1,0 +1,704 @@
+// Local fine-scale solves of the offline stage (LocalPDESolver inside
+// RanLocalSolu, Section 3): coefficient gather, boundary samples, lifting of
+// the boundary data, block-row factorization, multi-RHS sweeps on MFMA, FP64
+// residuals for iterative refinement, and restriction to K_m.
+//
+// Both operators are block tridiagonal in the line ordering of PatchDesc:
+//   A = tridiag(Low_l, Dg_l, Up_l), lines l = 0..nl-1, blocks b x b.
+// Elliptic (bilinear elements, eq. Elliptic): Dg_l = T_l tridiagonal,
+//   Up_l = Low_{l+1} = U_l symmetric tridiagonal (coupling of node lines
+//   l+1 and l+2 through cell row l+1).
+// Kinetic (upwind ordinates, eq. RTE with isotropic scattering):
+//   Dg_l = diag(|v|/dx + sigma_l/eps) - (sigma_l/eps) 1 (w/2)^T,
+//   Low_l = -diag(v+/dx), Up_l = -diag(v-/dx).
+// Block elimination: D_0 = Dg_0, D_{l+1} = Dg_{l+1} - Low_{l+1} D_l^{-1} Up_l;
+// the inverses E_l = D_l^{-1} are formed explicitly (Gauss-Jordan, no
+// pivoting: D_l is SPD (elliptic) or a row-diagonally-dominant M-matrix
+// (kinetic)), so that both sweeps are dense products on MFMA:
+//   forward  y_0 = r_0,  w_l = E_l y_l,  y_{l+1} = r_{l+1} - Low_{l+1} w_l
+//   back     x_{nl-1} = w_{nl-1},  x_l = E_l (y_l - Up_l x_{l+1}).
+#include "device_common.h"
+
+namespace msrs {
+
+// ------------------------------------------------------------ small helpers
+// Counter-clockwise boundary index of local physical node (i, j) of a cx x cy
+// cell block (caller guarantees the node is on the boundary).
+__device__ __forceinline__ int bidx_ccw(int i, int j, int cx, int cy) {
+    if (j == 0 && i < cx) return i;
+    if (i == cx && j < cy) return cx + j;
+    if (j == cy && i > 0) return cx + cy + (cx - i);
+    return 2 * cx + cy + (cy - j);
+}
+
+// physical local node of line coordinates (p, q)
+__device__ __forceinline__ void line_to_phys(const PatchDesc& P, int p, int q, int& i, int& j) {
+    if (P.trans) { i = q; j = p; } else { i = p; j = q; }
+}
+
+__device__ __forceinline__ double a_cell(const double* aL, int L, int cr, int cp) { return aL[cr * L + cp]; }
+
+// Q1 stencil coefficient between node (p,q) and (p+dp, q+dq) of a buffered
+// patch, from the four elements around (p,q): NE=(p,q) NW=(p-1,q)
+// SW=(p-1,q-1) SE=(p,q-1) (cell column, cell row).
+__device__ __forceinline__ double q1_coef(const double* aL, int L, int p, int q, int dp, int dq) {
+    const double NE = a_cell(aL, L, q, p), NW = a_cell(aL, L, q, p - 1);
+    const double SW = a_cell(aL, L, q - 1, p - 1), SE = a_cell(aL, L, q - 1, p);
+    if (dp == 0 && dq == 0) return (2.0 / 3.0) * (NE + NW + SW + SE);
+    if (dq == 0) return dp > 0 ? -(NE + SE) / 6.0 : -(NW + SW) / 6.0;
+    if (dp == 0) return dq > 0 ? -(NE + NW) / 6.0 : -(SE + SW) / 6.0;
+    if (dp > 0) return dq > 0 ? -NE / 3.0 : -SE / 3.0;
+    return dq > 0 ? -NW / 3.0 : -SW / 3.0;
+}
+
+// ------------------------------------------------------------ gather (a2)
+__global__ __launch_bounds__(kThreads) void gather_elliptic_kernel(const PatchDesc* pd, int p0, const double* __restrict__ a,
+                                                                   int N, double* __restrict__ aL_all, int32_t* flags) {
+    const PatchDesc P = pd[p0 + blockIdx.x];
+    double* aL = aL_all + P.a_off;
+    const int n = P.L * P.Qn;
+    for (int idx = threadIdx.x; idx < n; idx += kThreads) {
+        const int cr = idx / P.L, cp = idx - cr * P.L;
+        const int ci = P.trans ? P.x0 + cr : P.x0 + cp;
+        const int cj = P.trans ? P.y0 + cp : P.y0 + cr;
+        const double v = a[(size_t)cj * N + ci];
+        if (!(v > 0.0) || !isfinite(v)) raise_flag(flags, 0);
+        aL[idx] = v;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void gather_kinetic_kernel(const PatchDesc* pd, int p0, const double* __restrict__ sigma,
+                                                                  double* __restrict__ aL_all, int32_t* flags) {
+    const PatchDesc P = pd[p0 + blockIdx.x];
+    for (int i = threadIdx.x; i < P.cx; i += kThreads) {
+        const double v = sigma[P.x0 + i];
+        if (!(v >= 0.0) || !isfinite(v)) raise_flag(flags, 0);
+        aL_all[P.a_off + i] = v;
+    }
+}
+
+// ------------------------------------------------------------ Omega (a3)
+// grid (patch, 16-column group); Omega is nb x s column-major.
+__global__ __launch_bounds__(kThreads) void omega_kernel(const PatchDesc* pd, int p0, const double* __restrict__ user,
+                                                         double* __restrict__ om, uint64_t seed) {
+    const int p = p0 + blockIdx.x;
+    const PatchDesc P = pd[p];
+    const int cs0 = blockIdx.y * 16;
+    if (cs0 >= P.s) return;
+    const int ncol = min(16, P.s - cs0);
+    const int n = P.nb * ncol;
+    for (int idx = threadIdx.x; idx < n; idx += kThreads) {
+        const int c = cs0 + idx / P.nb, t = idx - (idx / P.nb) * P.nb;
+        const int64_t o = P.om_off + (int64_t)c * P.nb + t;
+        double v;
+        if (P.full) v = (t == c) ? 1.0 : 0.0;
+        else if (user) v = user[o];
+        else v = philox_normal(seed, (uint32_t)t, (uint32_t)c, (uint32_t)p);
+        om[o] = v;
+    }
+}
+
+// ------------------------------------------------------------ lifting (a3)
+// rhs = -A_IB omega written into the line vectors (FP64 or FP32), padding
+// zeroed; per-sample ||rhs||^2 to rn[0..sp).  x64 (if given) is zeroed.
+template <int KIND, typename TX>
+__global__ __launch_bounds__(kThreads) void lift_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
+                                                        const double* __restrict__ om, const double* __restrict__ vw, double dx,
+                                                        TX* __restrict__ X, double* __restrict__ x64zero,
+                                                        double* __restrict__ rn_all) {
+    __shared__ double red[kThreads];
+    const PatchDesc P = pd[p0 + blockIdx.x];
+    const double* aL = aL_all + P.a_off;
+    const double* O = om + P.om_off;
+    const int sp = P.sp, bp = P.bp, b = P.b, nl = P.nl;
+    const int per_line = bp * sp;
+    // thread -> (row group, sample column); sp in {16, 32, 48, 64}
+    const int tcol = threadIdx.x % sp;
+    const int trow0 = threadIdx.x / sp, trows = kThreads / sp;
+    const bool active = trow0 < trows;
+    double ssum = 0.0;
+    for (int l = 0; l < nl; ++l) {
+        for (int i = trow0; active && i < bp; i += trows) {
+            const int c = tcol;
+            double v = 0.0;
+            if (i < b && c < P.s) {
+                if (KIND == kElliptic) {
+                    const int p = i + 1, q = l + 1;
+#pragma unroll
+                    for (int dq = -1; dq <= 1; ++dq)
+#pragma unroll
+                        for (int dp = -1; dp <= 1; ++dp) {
+                            const int pp = p + dp, qq = q + dq;
+                            if (pp == 0 || pp == P.L || qq == 0 || qq == P.Qn) {
+                                int ii, jj;
+                                line_to_phys(P, pp, qq, ii, jj);
+                                v -= q1_coef(aL, P.L, p, q, dp, dq) * O[(int64_t)c * P.nb + bidx_ccw(ii, jj, P.cx, P.cy)];
+                            }
+                        }
+                } else {
+                    const int nv = P.b, h = nv / 2;
+                    const double vi = vw[i];
+                    if (l == 0 && vi > 0) v += vi / dx * O[(int64_t)c * P.nb + (i - h)];
+                    if (l == nl - 1 && vi < 0) v += -vi / dx * O[(int64_t)c * P.nb + h + i];
+                }
+            }
+            const int64_t o = P.x_off + (int64_t)l * per_line + (int64_t)i * sp + c;
+            X[o] = (TX)v;
+            if (x64zero) x64zero[o] = 0.0;
+            ssum += v * v;
+        }
+    }
+    // reduce per column: threads with equal tcol
+    __syncthreads();
+    red[threadIdx.x] = active ? ssum : 0.0;
+    __syncthreads();
+    if (threadIdx.x < sp) {
+        double s = 0.0;
+        for (int r = 0; r < trows; ++r) s += red[r * sp + threadIdx.x];
+        rn_all[P.rn_off + threadIdx.x] = s;
+    }
+}
+
+// ------------------------------------------------------------ factorization (a4)
+// Diagonal block entry of line l (i, j < b).
+template <int KIND>
+__device__ __forceinline__ double diag_entry(const PatchDesc& P, const double* aL, const double* vw, double dx, double inv_eps,
+                                             int l, int i, int j) {
+    if (KIND == kElliptic) {
+        const int q = l + 1, L = P.L;
+        if (i == j) {
+            const int p = i + 1;
+            return (2.0 / 3.0) * (a_cell(aL, L, q, p) + a_cell(aL, L, q, p - 1) + a_cell(aL, L, q - 1, p - 1) + a_cell(aL, L, q - 1, p));
+        }
+        if (j == i + 1) return -(a_cell(aL, L, q, i + 1) + a_cell(aL, L, q - 1, i + 1)) / 6.0;
+        if (i == j + 1) return -(a_cell(aL, L, q, j + 1) + a_cell(aL, L, q - 1, j + 1)) / 6.0;
+        return 0.0;
+    } else {
+        const int nv = P.b;
+        const double s = aL[l] * inv_eps;
+        double v = -s * 0.5 * vw[nv + j];
+        if (i == j) v += fabs(vw[i]) / dx + s;
+        return v;
+    }
+}
+
+template <typename T, int KIND, int R>
+__device__ void factor_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw, double dx,
+                            double inv_eps, T* __restrict__ E, T* Es, T* prow, T* pcol, double* cf, int32_t* flags) {
+    constexpr int BP = 16 * R;
+    constexpr int LDE = BP + 1;
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    const int b = P.b, nl = P.nl;
+    T A[R][R];
+    bool bad = false;
+    for (int l = 0; l < nl; ++l) {
+        // coupling coefficients of the previous line (elliptic U_{l-1}: cell row l)
+        if (KIND == kElliptic) {
+            if (l > 0)
+                for (int a = tid; a < b; a += kThreads) {
+                    cf[a] = -(a_cell(aL, P.L, l, a) + a_cell(aL, P.L, l, a + 1)) / 6.0;   // U diagonal
+                    cf[BP + a] = -a_cell(aL, P.L, l, a + 1) / 3.0;                          // U(a, a+1)
+                }
+        } else {
+            for (int a = tid; a < b; a += kThreads) {
+                const double v = vw[a];
+                cf[a] = v > 0 ? v / dx : 0.0;         // v+/dx
+                cf[BP + a] = v < 0 ? -v / dx : 0.0;   // v-/dx
+            }
+        }
+        __syncthreads();
+        // D_l = Dg_l - Low_l E_{l-1} Up_{l-1}
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < R; ++c) {
+                const int i = ty + 16 * r, j = tx + 16 * c;
+                double d;
+                if (i >= b || j >= b) {
+                    d = (i == j) ? 1.0 : 0.0;
+                } else {
+                    d = diag_entry<KIND>(P, aL, vw, dx, inv_eps, l, i, j);
+                    if (l > 0) {
+                        if (KIND == kElliptic) {
+                            double s = 0.0;
+#pragma unroll
+                            for (int da = -1; da <= 1; ++da) {
+                                const int a = i + da;
+                                if (a < 0 || a >= b) continue;
+                                const double uai = (da == 0) ? cf[i] : cf[BP + min(a, i)];
+                                double t = 0.0;
+#pragma unroll
+                                for (int dc = -1; dc <= 1; ++dc) {
+                                    const int cc = j + dc;
+                                    if (cc < 0 || cc >= b) continue;
+                                    const double ucj = (dc == 0) ? cf[j] : cf[BP + min(cc, j)];
+                                    t += (double)Es[a * LDE + cc] * ucj;
+                                }
+                                s += uai * t;
+                            }
+                            d -= s;
+                        } else {
+                            d -= cf[i] * (double)Es[i * LDE + j] * cf[BP + j];
+                        }
+                    }
+                }
+                A[r][c] = (T)d;
+            }
+        // Gauss-Jordan inversion in registers; pivot k = 16*kr + kt
+#pragma unroll
+        for (int kr = 0; kr < R; ++kr) {
+            for (int kt = 0; kt < 16; ++kt) {
+                const int k = 16 * kr + kt;
+                if (k >= b) break;
+                T* pr_s = prow + (k & 1) * BP;
+                T* pc_s = pcol + (k & 1) * BP;
+                if (ty == kt) {
+#pragma unroll
+                    for (int c = 0; c < R; ++c) pr_s[tx + 16 * c] = A[kr][c];
+                }
+                if (tx == kt) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) pc_s[ty + 16 * r] = A[r][kr];
+                }
+                __syncthreads();
+                const T piv = pr_s[k];
+                if (!(piv > T(0)) || !isfinite((double)piv)) bad = true;
+                const T ip = T(1) / piv;
+                T pr[R], pc[R];
+#pragma unroll
+                for (int c = 0; c < R; ++c) pr[c] = pr_s[tx + 16 * c];
+#pragma unroll
+                for (int r = 0; r < R; ++r) pc[r] = pc_s[ty + 16 * r] * ip;
+                const bool isRow = (ty == kt), isCol = (tx == kt);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int c = 0; c < R; ++c) {
+                        T g = A[r][c] - pc[r] * pr[c];
+                        if (c == kr) g = isCol ? ((isRow && r == kr) ? ip : -pc[r]) : g;
+                        if (r == kr) g = isRow ? ((isCol && c == kr) ? ip : pr[c] * ip) : g;
+                        A[r][c] = g;
+                    }
+            }
+        }
+        __syncthreads();   // all reads of Es (previous line) are done
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < R; ++c) Es[(ty + 16 * r) * LDE + tx + 16 * c] = A[r][c];
+        __syncthreads();
+        // store E_l column-major: E[l][j][i]
+        T* El = E + (int64_t)l * BP * BP;
+        for (int o = tid; o < BP * BP; o += kThreads) {
+            const int j = o / BP, i = o - j * BP;
+            El[o] = Es[i * LDE + j];
+        }
+    }
+    if (bad) raise_flag(flags, 0);
+}
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(kThreads) void factor_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
+                                                          const double* __restrict__ vw, double dx, double inv_eps,
+                                                          T* __restrict__ E_all, int32_t* flags) {
+    __shared__ T Es[kMaxLine * (kMaxLine + 1)];
+    __shared__ T prow[2 * kMaxLine], pcol[2 * kMaxLine];
+    __shared__ double cf[2 * kMaxLine];
+    const PatchDesc P = pd[p0 + blockIdx.x];
+    const double* aL = aL_all + P.a_off;
+    T* E = E_all + P.E_off;
+    switch (P.bp / 16) {
+        case 1: factor_body<T, KIND, 1>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
+        case 2: factor_body<T, KIND, 2>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
+        case 3: factor_body<T, KIND, 3>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
+        case 4: factor_body<T, KIND, 4>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
+        case 5: factor_body<T, KIND, 5>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
+        case 6: factor_body<T, KIND, 6>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
+        case 7: factor_body<T, KIND, 7>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
+        case 8: factor_body<T, KIND, 8>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
+        default: raise_flag(flags, 3); break;
+    }
+}
+
+// ------------------------------------------------------------ sweeps (a5)
+// grid (patch, column chunk of sc samples).  Both sweeps of one chunk run in
+// one workgroup; E_l y products on MFMA 16x16x4 (4 waves, wave w owns row
+// tiles w and w+4, all column tiles of the chunk).
+template <typename T>
+__device__ __forceinline__ void mfma_line(const T* __restrict__ El, const T* ybuf, int ld, int bp, int nct,
+                                          typename Mfma<T>::acc acc[2][4]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nrt = bp >> 4;
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = Mfma<T>::zero();
+    const bool has0 = w < nrt, has1 = (w + 4) < nrt;
+    if (!has0) return;
+    const T* A0 = El + (16 * w + li);
+    const T* A1 = El + (16 * (w + 4) + li);
+    for (int k0 = 0; k0 < bp; k0 += 4) {
+        const int k = k0 + lk;
+        const T a0 = A0[(int64_t)k * bp];
+        const T a1 = has1 ? A1[(int64_t)k * bp] : T(0);
+        const T* yb = ybuf + k * ld + li;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c < nct) {
+                const T bv = yb[16 * c];
+                acc[0][c] = Mfma<T>::step(a0, bv, acc[0][c]);
+                if (has1) acc[1][c] = Mfma<T>::step(a1, bv, acc[1][c]);
+            }
+        }
+    }
+}
+
+// store accumulators to an LDS tile (row-major, ld) and optionally to global
+template <typename T>
+__device__ __forceinline__ void store_acc(typename Mfma<T>::acc acc[2][4], T* lds, int ld, int bp, int nct, T* gdst, int gld) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nrt = bp >> 4;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int rt = w + 4 * r;
+        if (rt >= nrt) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c >= nct) continue;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = 16 * rt + Mfma<T>::row(lane, t), j = 16 * c + (lane & 15);
+                const T v = acc[r][c][t];
+                lds[i * ld + j] = v;
+                if (gdst) gdst[(int64_t)i * gld + j] = v;
+            }
+        }
+    }
+}
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(kThreads) void sweep_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
+                                                         const double* __restrict__ vw, double dx, const T* __restrict__ E_all,
+                                                         T* __restrict__ X_all, const int32_t* __restrict__ conv, int sc) {
+    __shared__ T ybuf[kMaxLine * kMaxSamples];
+    __shared__ T wbuf[kMaxLine * kMaxSamples];
+    __shared__ double cu[2 * kMaxLine];
+    const int p = p0 + blockIdx.x;
+    if (conv && conv[p]) return;
+    const PatchDesc P = pd[p];
+    const int s0 = blockIdx.y * sc;
+    if (s0 >= P.sp) return;
+    const int nsc = min(sc, P.sp - s0), nct = nsc >> 4;
+    const int bp = P.bp, b = P.b, nl = P.nl, sp = P.sp;
+    const double* aL = aL_all + P.a_off;
+    const T* E = E_all + P.E_off;
+    T* X = X_all + P.x_off + s0;
+    const int64_t lstride = (int64_t)bp * sp;
+    const int tid = threadIdx.x;
+    typename Mfma<T>::acc acc[2][4];
+
+    // coupling coefficients of line l (elliptic U_l from cell row l+1; kinetic v+/dx, v-/dx)
+    auto load_coupling = [&](int l) {
+        for (int a = tid; a < b; a += kThreads) {
+            if (KIND == kElliptic) {
+                cu[a] = -(a_cell(aL, P.L, l + 1, a) + a_cell(aL, P.L, l + 1, a + 1)) / 6.0;
+                cu[kMaxLine + a] = -a_cell(aL, P.L, l + 1, a + 1) / 3.0;
+            } else {
+                const double v = vw[a];
+                cu[a] = v > 0 ? v / dx : 0.0;
+                cu[kMaxLine + a] = v < 0 ? -v / dx : 0.0;
+            }
+        }
+    };
+    // Low_{l+1} applied to column j of src (elliptic U_l; kinetic -diag(v+/dx))
+    auto apply_low = [&](const T* src, int i, int j) -> double {
+        if (KIND == kElliptic) {
+            double v = cu[i] * (double)src[i * nsc + j];
+            if (i > 0) v += cu[kMaxLine + i - 1] * (double)src[(i - 1) * nsc + j];
+            if (i < b - 1) v += cu[kMaxLine + i] * (double)src[(i + 1) * nsc + j];
+            return v;
+        } else {
+            return -cu[i] * (double)src[i * nsc + j];
+        }
+    };
+    auto apply_up = [&](const T* src, int i, int j) -> double {
+        if (KIND == kElliptic) return apply_low(src, i, j);
+        return -cu[kMaxLine + i] * (double)src[i * nsc + j];
+    };
+
+    // y_0 = r_0
+    for (int o = tid; o < bp * nsc; o += kThreads) {
+        const int i = o / nsc, j = o - i * nsc;
+        ybuf[o] = X[(int64_t)i * sp + j];
+    }
+    __syncthreads();
+    // forward sweep
+    for (int l = 0; l < nl; ++l) {
+        if (l + 1 < nl) load_coupling(l);
+        mfma_line<T>(E + (int64_t)l * bp * bp, ybuf, nsc, bp, nct, acc);
+        if (l + 1 == nl) {
+            store_acc<T>(acc, wbuf, nsc, bp, nct, X + (int64_t)l * lstride, sp);   // x_{nl-1}
+            __syncthreads();
+            break;
+        }
+        store_acc<T>(acc, wbuf, nsc, bp, nct, nullptr, 0);
+        __syncthreads();
+        T* Xn = X + (int64_t)(l + 1) * lstride;
+        for (int o = tid; o < bp * nsc; o += kThreads) {
+            const int i = o / nsc, j = o - i * nsc;
+            T y = T(0);
+            if (i < b) y = (T)((double)Xn[(int64_t)i * sp + j] - apply_low(wbuf, i, j));
+            Xn[(int64_t)i * sp + j] = y;
+            ybuf[o] = y;
+        }
+        __syncthreads();
+    }
+    // back sweep: wbuf holds x_{l+1}
+    for (int l = nl - 2; l >= 0; --l) {
+        load_coupling(l);
+        __syncthreads();
+        T* Xl = X + (int64_t)l * lstride;
+        for (int o = tid; o < bp * nsc; o += kThreads) {
+            const int i = o / nsc, j = o - i * nsc;
+            T z = T(0);
+            if (i < b) z = (T)((double)Xl[(int64_t)i * sp + j] - apply_up(wbuf, i, j));
+            ybuf[o] = z;
+        }
+        __syncthreads();
+        mfma_line<T>(E + (int64_t)l * bp * bp, ybuf, nsc, bp, nct, acc);
+        store_acc<T>(acc, wbuf, nsc, bp, nct, Xl, sp);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ FP64 residual (a6)
+// One workgroup per patch.  accumulate: x64 += x32 first.  Then
+// r = rhs - A x64 per interior unknown; r is written to x32 (next correction
+// right-hand side) unless stats_only; rn[sp..2sp) = ||r_j||^2; conv[p] = 1
+// when every ||r_j|| <= tol ||rhs_j||; relres[p] = max_j ||r_j||/||rhs_j||.
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void residual_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
+                                                            const double* __restrict__ om, const double* __restrict__ vw,
+                                                            double dx, double inv_eps, double* __restrict__ x64_all,
+                                                            float* __restrict__ x32_all, double* __restrict__ rn_all,
+                                                            int32_t* __restrict__ conv, double* __restrict__ relres,
+                                                            int32_t* __restrict__ iters, int it, double tol, int accumulate,
+                                                            int stats_only) {
+    __shared__ double red[kThreads];
+    const int p = p0 + blockIdx.x;
+    if (conv && conv[p]) return;
+    const PatchDesc P = pd[p];
+    const double* aL = aL_all + P.a_off;
+    const double* O = om + P.om_off;
+    const int sp = P.sp, bp = P.bp, b = P.b, nl = P.nl;
+    double* X = x64_all + P.x_off;
+    float* X32 = x32_all ? x32_all + P.x_off : nullptr;
+    const int64_t lstride = (int64_t)bp * sp;
+    const int tcol = threadIdx.x % sp, trows = kThreads / sp, trow0 = threadIdx.x / sp;
+    const bool active = trow0 < trows;
+    if (accumulate) {
+        const int64_t n = (int64_t)nl * lstride;
+        for (int64_t o = threadIdx.x; o < n; o += kThreads) X[o] += (double)X32[o];
+        __syncthreads();
+    }
+    double ssum = 0.0;
+    const int c = tcol;
+    auto xv = [&](int l, int i) -> double { return X[(int64_t)l * lstride + (int64_t)i * sp + c]; };
+    for (int l = 0; l < nl; ++l) {
+        if (KIND == kElliptic) {
+            for (int i = trow0; active && i < bp; i += trows) {
+                double r = 0.0;
+                if (i < b && c < P.s) {
+                    const int pp = i + 1, q = l + 1;
+#pragma unroll
+                    for (int dq = -1; dq <= 1; ++dq)
+#pragma unroll
+                        for (int dp = -1; dp <= 1; ++dp) {
+                            const int p2 = pp + dp, q2 = q + dq;
+                            double u;
+                            if (p2 == 0 || p2 == P.L || q2 == 0 || q2 == P.Qn) {
+                                int ii, jj;
+                                line_to_phys(P, p2, q2, ii, jj);
+                                u = O[(int64_t)c * P.nb + bidx_ccw(ii, jj, P.cx, P.cy)];
+                            } else {
+                                u = xv(q2 - 1, p2 - 1);
+                            }
+                            r -= q1_coef(aL, P.L, pp, q, dp, dq) * u;
+                        }
+                }
+                if (!stats_only) X32[(int64_t)l * lstride + (int64_t)i * sp + c] = (float)r;
+                ssum += r * r;
+            }
+        } else {
+            // each active thread with trow0 == 0 handles a whole cell column (all ordinates)
+            if (active && trow0 == 0) {
+                const int nv = b, h = nv / 2;
+                double rho = 0.0;
+                if (c < P.s)
+                    for (int j = 0; j < nv; ++j) rho += 0.5 * vw[nv + j] * xv(l, j);
+                const double s = aL[l] * inv_eps;
+                for (int i = 0; i < bp; ++i) {
+                    double r = 0.0;
+                    if (i < b && c < P.s) {
+                        const double vi = vw[i];
+                        double acc = (fabs(vi) / dx + s) * xv(l, i) - s * rho;
+                        if (vi > 0) acc -= vi / dx * (l > 0 ? xv(l - 1, i) : O[(int64_t)c * P.nb + (i - h)]);
+                        if (vi < 0) acc -= -vi / dx * (l < nl - 1 ? xv(l + 1, i) : O[(int64_t)c * P.nb + h + i]);
+                        r = -acc;
+                    }
+                    if (!stats_only) X32[(int64_t)l * lstride + (int64_t)i * sp + c] = (float)r;
+                    ssum += r * r;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    red[threadIdx.x] = active ? ssum : 0.0;
+    __syncthreads();
+    double* rn = rn_all + P.rn_off;
+    if (threadIdx.x < 64) {
+        // per column sums, then the max ratio over columns (wave 0)
+        double ratio = 0.0;
+        if (threadIdx.x < sp) {
+            double s2 = 0.0;
+            for (int r = 0; r < trows; ++r) s2 += red[r * sp + threadIdx.x];
+            rn[sp + threadIdx.x] = s2;
+            const double rh = rn[threadIdx.x];
+            if (threadIdx.x < P.s) ratio = rh > 0 ? sqrt(s2 / rh) : (s2 > 0 ? INFINITY : 0.0);
+        }
+        for (int off = 32; off > 0; off >>= 1) ratio = fmax(ratio, __shfl_xor(ratio, off, 64));
+        if (threadIdx.x == 0) {
+            relres[p] = ratio;
+            if (conv && ratio <= tol) { conv[p] = 1; iters[p] = it + 1; }
+        }
+    }
+}
+
+// ------------------------------------------------------------ restriction (a7)
+// grid-stride over (patch in [p0,p1), row, sample); Y column-major.
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void restrict_kernel(const PatchDesc* pd, int p0, const double* __restrict__ x64_all,
+                                                            const double* __restrict__ om, const double* __restrict__ vw,
+                                                            double* __restrict__ Y_all) {
+    const PatchDesc P = pd[p0 + blockIdx.x];
+    const int n = P.nrows * P.s;
+    const double* X = x64_all + P.x_off;
+    const double* O = om + P.om_off;
+    double* Y = Y_all + P.Y_off;
+    const int64_t lstride = (int64_t)P.bp * P.sp;
+    for (int o = threadIdx.x; o < n; o += kThreads) {
+        const int c = o / P.nrows, row = o - c * P.nrows;
+        double v;
+        if (KIND == kElliptic) {
+            const int W = P.nH + 1;
+            const int jj = row / W, ii = row - jj * W;
+            const int ip = P.kx0 - P.x0 + ii, jp = P.ky0 - P.y0 + jj;
+            const int pl = P.trans ? jp : ip, ql = P.trans ? ip : jp;
+            if (pl >= 1 && pl <= P.L - 1 && ql >= 1 && ql <= P.Qn - 1)
+                v = X[(int64_t)(ql - 1) * lstride + (int64_t)(pl - 1) * P.sp + c];
+            else
+                v = O[(int64_t)c * P.nb + bidx_ccw(ip, jp, P.cx, P.cy)];
+        } else {
+            const int nv = P.b, h = nv / 2;
+            const int cell = row / nv, j = row - cell * nv;
+            const int lc = P.kx0 - 1 + cell - P.x0;
+            if (lc >= 0 && lc < P.cx) v = X[(int64_t)lc * lstride + (int64_t)j * P.sp + c];
+            else if (lc < 0) v = vw[j] > 0 ? O[(int64_t)c * P.nb + (j - h)] : 0.0;
+            else v = vw[j] < 0 ? O[(int64_t)c * P.nb + h + j] : 0.0;
+        }
+        Y[o] = v;
+    }
+}
+
+__global__ void clear_kernel(int32_t* a, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = 0;
+}
+
+// ------------------------------------------------------------ launchers
+static inline double dx_of(const Ctx& c) { return 1.0 / c.N; }
+
+void launch_gather_elliptic(Ctx& c, const double* a, int p0, int p1) {
+    StageTimer t(c, MSRS_K_ASSEMBLE);
+    hipLaunchKernelGGL(gather_elliptic_kernel, dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, a, c.N, c.aL, c.dflags);
+}
+
+void launch_gather_kinetic(Ctx& c, const double* sigma, int p0, int p1) {
+    StageTimer t(c, MSRS_K_ASSEMBLE);
+    hipLaunchKernelGGL(gather_kinetic_kernel, dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, sigma, c.aL, c.dflags);
+}
+
+void launch_omega(Ctx& c, const double* user, int p0, int p1) {
+    StageTimer t(c, MSRS_K_OMEGA);
+    int maxs = 0;
+    for (int p = p0; p < p1; ++p) maxs = std::max(maxs, c.hp[p].s);
+    hipLaunchKernelGGL(omega_kernel, dim3(p1 - p0, (maxs + 15) / 16), dim3(kThreads), 0, c.stream, c.dp, p0, user, c.om, c.seed);
+}
+
+void launch_lift(Ctx& c, int p0, int p1) {
+    StageTimer t(c, MSRS_K_LIFT);
+    const bool ir = c.prec == MSRS_PREC_FP32_IR;
+    if (c.kind == kElliptic) {
+        if (ir) hipLaunchKernelGGL((lift_kernel<kElliptic, float>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x32, c.x64, c.rn);
+        else hipLaunchKernelGGL((lift_kernel<kElliptic, double>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, (double*)nullptr, c.rn);
+    } else {
+        if (ir) hipLaunchKernelGGL((lift_kernel<kKinetic, float>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x32, c.x64, c.rn);
+        else hipLaunchKernelGGL((lift_kernel<kKinetic, double>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, (double*)nullptr, c.rn);
+    }
+}
+
+void launch_factor(Ctx& c, int p0, int p1) {
+    StageTimer t(c, MSRS_K_FACTOR);
+    const double inv_eps = 1.0 / c.eps;
+    const bool ir = c.prec == MSRS_PREC_FP32_IR;
+    if (c.kind == kElliptic) {
+        if (ir) hipLaunchKernelGGL((factor_kernel<float, kElliptic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (float*)c.E, c.dflags);
+        else hipLaunchKernelGGL((factor_kernel<double, kElliptic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (double*)c.E, c.dflags);
+    } else {
+        if (ir) hipLaunchKernelGGL((factor_kernel<float, kKinetic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (float*)c.E, c.dflags);
+        else hipLaunchKernelGGL((factor_kernel<double, kKinetic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (double*)c.E, c.dflags);
+    }
+}
+
+void launch_sweep(Ctx& c, int p0, int p1, bool fp32) {
+    StageTimer t(c, MSRS_K_SWEEP);
+    int maxsp = 0;
+    for (int p = p0; p < p1; ++p) maxsp = std::max(maxsp, c.hp[p].sp);
+    const int sc = kMaxSamples;
+    const dim3 grid(p1 - p0, (maxsp + sc - 1) / sc);
+    const int32_t* conv = fp32 ? c.conv : nullptr;
+    if (c.kind == kElliptic) {
+        if (fp32) hipLaunchKernelGGL((sweep_kernel<float, kElliptic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), (const float*)c.E, c.x32, conv, sc);
+        else hipLaunchKernelGGL((sweep_kernel<double, kElliptic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), (const double*)c.E, c.x64, conv, sc);
+    } else {
+        if (fp32) hipLaunchKernelGGL((sweep_kernel<float, kKinetic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), (const float*)c.E, c.x32, conv, sc);
+        else hipLaunchKernelGGL((sweep_kernel<double, kKinetic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), (const double*)c.E, c.x64, conv, sc);
+    }
+}
+
+void launch_residual(Ctx& c, int p0, int p1, bool accumulate, bool stats_only, int it) {
+    StageTimer t(c, MSRS_K_RESIDUAL);
+    const double inv_eps = 1.0 / c.eps;
+    int32_t* conv = stats_only ? nullptr : c.conv;
+    float* x32 = stats_only ? nullptr : c.x32;
+    if (c.kind == kElliptic)
+        hipLaunchKernelGGL((residual_kernel<kElliptic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), inv_eps,
+                           c.x64, x32, c.rn, conv, c.gap + c.n_patches, c.iters, it, c.ir_tol, accumulate ? 1 : 0, stats_only ? 1 : 0);
+    else
+        hipLaunchKernelGGL((residual_kernel<kKinetic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), inv_eps,
+                           c.x64, x32, c.rn, conv, c.gap + c.n_patches, c.iters, it, c.ir_tol, accumulate ? 1 : 0, stats_only ? 1 : 0);
+}
+
+void launch_restrict(Ctx& c, int p0, int p1) {
+    StageTimer t(c, MSRS_K_RESTRICT);
+    if (c.kind == kElliptic)
+        hipLaunchKernelGGL((restrict_kernel<kElliptic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.x64, c.om, c.vw, c.Y);
+    else
+        hipLaunchKernelGGL((restrict_kernel<kKinetic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.x64, c.om, c.vw, c.Y);
+}
+
+void launch_clear_conv(Ctx& c) {
+    hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(kThreads), 0, c.stream, c.conv, c.n_patches);
+}
+
+}  // namespace msrs

@@ -1,0 +1,170 @@
+// Internal declarations of the msrs library: per-patch descriptors, the
+// handle, and the host-side launchers of the kernels in k_*.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/msrs.h"
+
+namespace msrs {
+
+constexpr int kMaxLine = 128;      // padded unknowns per block row (elliptic); 16 | bp
+constexpr int kMaxSamples = 64;    // padded samples per patch
+constexpr int kThreads = 256;      // threads of every per-patch workgroup
+
+// One buffered patch, in the block-row ("line") view of the local problem.
+//
+// Elliptic: the interior unknowns of the buffered patch K~_m are grouped in
+// lines of constant node index q along the shorter side (trans = 1 when the
+// lines run along physical y).  In line coordinates a node is (p, q), p in
+// [0, L] along the line and q in [0, Qn] across; interior unknowns are p in
+// [1, L-1] (b = L-1 per line) and q in [1, Qn-1] (nl = Qn-1 lines).  The
+// element coefficients of K~_m are gathered to aL[cr * L + cp] (cell row cr,
+// cell column cp) in the same orientation.
+//
+// Kinetic: a line is one cell of K~_m with its nv ordinates (b = nv), nl = cx.
+struct PatchDesc {
+    int32_t x0, y0, cx, cy;   // buffered patch (cells)
+    int32_t trans;            // elliptic: lines along physical y
+    int32_t L, Qn;            // cells along / across lines
+    int32_t b, nl, bp;        // unknowns per line, lines, padded line length
+    int32_t nb;               // boundary values per sample column
+    int32_t s, sp;            // sample columns and their padding to 16
+    int32_t kx0, ky0, nH;     // patch K_m (cells)
+    int32_t nrows, ncols;     // rows of Y / Q, columns of Q
+    int32_t full;             // full (delta) basis: Omega = identity
+    int32_t sampled;          // Omega drawn at random (0 for full-basis patches)
+    int64_t a_off;            // aL (doubles)
+    int64_t om_off;           // Omega, nb x s column-major
+    int64_t x_off;            // line vectors, nl x bp x sp (samples fastest)
+    int64_t E_off;            // inverse diagonal blocks, nl x bp x bp (column-major blocks)
+    int64_t Y_off;            // nrows x s column-major
+    int64_t Q_off;            // nrows x ncols column-major
+    int64_t sv_off;           // s singular values
+    int64_t rn_off;           // per-sample norms: [0,sp) ||rhs||^2, [sp,2sp) ||r||^2
+};
+
+// Online (coarse) geometry of one patch.
+struct CoarseDesc {
+    int32_t col_off;          // first unknown of the patch in the least-squares system
+    int32_t ncols;            // its unknowns
+    int32_t nbr[8];           // elliptic: patches that share an edge or vertex (-1 if none)
+    int32_t pad_[6];
+};
+
+enum Kind { kElliptic = 0, kKinetic = 1 };
+
+
+struct Ctx {
+    int kind = kElliptic;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int N = 0, M = 0, s = 0, k = 0, prec = 0, nv = 0;
+    int ir_max = 30;
+    double ir_tol = 1e-10;
+    double eps = 1.0;
+    uint64_t seed = 0;
+    uint32_t flags = 0;
+    size_t budget = 0;
+    int n_patches = 0;
+    int ir_hint = 3;
+    int last_ir_iters = 0;
+    std::string err;
+
+    std::vector<PatchDesc> hp;    // host copy of descriptors
+    std::vector<int32_t> overlap;
+
+    // device buffers
+    PatchDesc* dp = nullptr;
+    double* aL = nullptr;         // gathered coefficients (per patch)
+    double* om = nullptr;         // Omega
+    double* x64 = nullptr;        // FP64 line vectors (solution)
+    float* x32 = nullptr;         // FP32 line vectors (FP32_IR: residual / correction)
+    void* E = nullptr;            // inverse blocks (float or double)
+    double* Y = nullptr;
+    double* Q = nullptr;
+    double* sv = nullptr;
+    double* rn = nullptr;         // norms
+    double* gap = nullptr;        // per patch relative gap
+    int32_t* conv = nullptr;      // per patch converged flag
+    int32_t* dflags = nullptr;    // device error flags [0]=NOT_SPD [1]=NOCONV [2]=RANK [3]=nonfinite
+    int32_t* hflags = nullptr;    // pinned host mirror
+    double* vw = nullptr;         // kinetic ordinates and weights (2 nv)
+    double* rf_ws = nullptr;      // range finder workspace
+    double* coef_copy = nullptr;  // device copy of the coefficient field (traces)
+    int32_t* iters = nullptr;     // per patch refinement iterations at convergence
+
+    int64_t omega_total = 0, Y_total = 0, Q_total = 0, sv_total = 0;
+    int64_t x_total = 0, E_total = 0, aL_total = 0;
+    int64_t bytes = 0;
+
+    bool assembled = false, sampled = false, ranged = false, coarse_ready = false;
+
+    // online
+    int max_batch = 64;
+    int Np = 0, bw = 0;
+    std::vector<CoarseDesc> hc;
+    CoarseDesc* dc = nullptr;
+    double* tr = nullptr;         // traces (values, fluxes)
+    double* band = nullptr;       // normal matrix, then its Cholesky factor (lower band)
+    double* crhs = nullptr;       // per request right-hand sides / coefficients, Np x max_batch
+    int32_t n_bdry = 0;
+    int64_t n_nodes = 0;
+    std::vector<void*> allocs;
+
+    // timing (MSRS_FLAG_TIMING): events around every launcher, resolved in msrs_get_stats
+    bool timing = false;
+    double tms[12] = {0};
+    int64_t tlaunch[12] = {0};
+    struct Pending { int cls; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+};
+
+// ---- launchers (k_*.hip) ---------------------------------------------------
+// Every launcher enqueues on c.stream and takes the patch range [p0, p1).
+void launch_gather_elliptic(Ctx& c, const double* a, int p0, int p1);
+void launch_gather_kinetic(Ctx& c, const double* sigma, int p0, int p1);
+void launch_omega(Ctx& c, const double* user, int p0, int p1);
+void launch_lift(Ctx& c, int p0, int p1);
+void launch_factor(Ctx& c, int p0, int p1);
+void launch_sweep(Ctx& c, int p0, int p1, bool fp32);
+void launch_residual(Ctx& c, int p0, int p1, bool accumulate, bool stats_only, int it);
+void launch_restrict(Ctx& c, int p0, int p1);
+void launch_range(Ctx& c, int p0, int p1);
+void launch_clear_conv(Ctx& c);
+
+// coarse (k_coarse.hip)
+void coarse_setup(Ctx& c);     // traces, normal matrix, Cholesky (enqueued)
+void coarse_solve(Ctx& c, int n_req, const double* f, double* u, hipStream_t st);
+
+// timing helpers (api.hip)
+struct StageTimer {
+    Ctx& c;
+    int cls;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(Ctx& cc, int k);
+    ~StageTimer();
+};
+
+}  // namespace msrs
+
+#define MSRS_HIP_CHECK(expr)                                                          \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess) throw msrs::HipError(e_, #expr, __FILE__, __LINE__);    \
+    } while (0)
+
+namespace msrs {
+struct HipError {
+    hipError_t e;
+    const char* what;
+    const char* file;
+    int line;
+    HipError(hipError_t ee, const char* w, const char* f, int l) : e(ee), what(w), file(f), line(l) {}
+};
+}  // namespace msrs

@@ -1,0 +1,207 @@
+"""Thin Python binding of the msrs C ABI (include/msrs.h).
+
+Argument marshalling only: every computation runs in libmsrs.so's HIP
+kernels.  Device arrays are torch CUDA tensors (float64, contiguous); the
+stream is torch's current stream unless one is given.  Importing this module
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsrs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1807_08848_amd.build`")
+
+# torch first: its HIP runtime then satisfies libmsrs.so's runtime dependency,
+# so that one runtime instance serves both (torch streams are valid handles
+# and stream order spans torch's work and the library's kernels).
+import torch  # noqa: E402,F401
+
+_lib = C.CDLL(LIB_PATH)
+
+OK, ERR_ARG, ERR_STATE, ERR_OOM, ERR_HIP, ERR_NO_DEVICE, ERR_NOT_SPD, ERR_NOCONV, ERR_RANK, ERR_BUSY = range(10)
+STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_STATE", 3: "ERR_OOM", 4: "ERR_HIP", 5: "ERR_NO_DEVICE",
+                6: "ERR_NOT_SPD", 7: "ERR_NOCONV", 8: "ERR_RANK", 9: "ERR_BUSY"}
+KIND_ELLIPTIC_Q1, KIND_KINETIC_DO = 0, 1
+PREC_FP64, PREC_FP32_IR = 0, 1
+FLAG_FULL_BASIS_ENDS, FLAG_PER_PATCH_LAUNCH, FLAG_TIMING = 1, 2, 4
+K_CLASSES = ["assemble", "omega", "lift", "factor", "sweep", "residual", "restrict", "range",
+             "coarse", "csolve", "recon"]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_cells", C.c_int32), ("M", C.c_int32), ("n_samples", C.c_int32),
+                ("rank", C.c_int32), ("precision", C.c_int32), ("ir_max_iters", C.c_int32), ("n_vel", C.c_int32),
+                ("seed", C.c_uint64), ("ir_tol", C.c_double), ("eps", C.c_double),
+                ("overlap", C.POINTER(C.c_int32)), ("flags", C.c_uint32), ("reserved", C.c_int32)]
+
+
+class Layout(C.Structure):
+    _fields_ = [("n_patches", C.c_int32), ("n_samples", C.c_int32), ("rank", C.c_int32), ("n_bdry", C.c_int32),
+                ("n_nodes", C.c_int64), ("omega_total", C.c_int64), ("Y_total", C.c_int64), ("Q_total", C.c_int64),
+                ("sv_total", C.c_int64), ("coarse_dim", C.c_int64), ("device_bytes", C.c_int64)]
+
+
+class PatchInfo(C.Structure):
+    _fields_ = [("x0", C.c_int32), ("y0", C.c_int32), ("cx", C.c_int32), ("cy", C.c_int32),
+                ("kx0", C.c_int32), ("ky0", C.c_int32), ("nH", C.c_int32), ("n_bdry", C.c_int32),
+                ("n_rows", C.c_int32), ("n_cols", C.c_int32), ("full_basis", C.c_int32), ("line_len", C.c_int32),
+                ("n_lines", C.c_int32), ("n_samples", C.c_int32),
+                ("omega_off", C.c_int64), ("Y_off", C.c_int64), ("Q_off", C.c_int64), ("sv_off", C.c_int64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("ir_iters", C.c_int32), ("error_latched", C.c_int32), ("max_rel_residual", C.c_double),
+                ("min_rel_gap", C.c_double), ("kernel_ms", C.c_double * 12), ("kernel_launches", C.c_int64 * 12)]
+
+
+_H = C.c_void_p
+_P = C.c_void_p
+_sig = {
+    "msrs_version": (C.c_int32, []),
+    "msrs_device_count": (C.c_int32, []),
+    "msrs_create": (C.c_int32, [C.POINTER(_H), C.POINTER(ProblemDesc), _P, C.c_size_t]),
+    "msrs_assemble_patch": (C.c_int32, [_H, _P]),
+    "msrs_sample_local_solutions": (C.c_int32, [_H, _P, _P]),
+    "msrs_range_finder": (C.c_int32, [_H, _P, _P]),
+    "msrs_assemble_coarse": (C.c_int32, [_H]),
+    "msrs_solve_global": (C.c_int32, [_H, C.c_int32, _P, _P, _P]),
+    "msrs_set_max_batch": (C.c_int32, [_H, C.c_int32]),
+    "msrs_copy_omega": (C.c_int32, [_H, _P]),
+    "msrs_query_layout": (C.c_int32, [_H, C.POINTER(Layout)]),
+    "msrs_query_patch": (C.c_int32, [_H, C.c_int32, C.POINTER(PatchInfo)]),
+    "msrs_get_stats": (C.c_int32, [_H, C.POINTER(Stats)]),
+    "msrs_reset_stats": (C.c_int32, [_H]),
+    "msrs_last_error": (C.c_char_p, [_H]),
+    "msrs_destroy": (None, [_H]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+lib = _lib
+
+
+class MsrsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def version() -> int:
+    return _lib.msrs_version()
+
+
+def device_count() -> int:
+    return _lib.msrs_device_count()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        if not torch.cuda.is_available():
+            return None
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def make_desc(kind, n_cells, M, overlap, n_samples, rank, precision=PREC_FP64, seed=2, ir_tol=1e-10,
+              ir_max_iters=30, n_vel=0, eps=1.0, flags=0):
+    ov = (C.c_int32 * len(overlap))(*[int(x) for x in overlap])
+    d = ProblemDesc(kind=kind, n_cells=n_cells, M=M, n_samples=n_samples, rank=rank, precision=precision,
+                    ir_max_iters=ir_max_iters, n_vel=n_vel, seed=seed, ir_tol=ir_tol, eps=eps,
+                    overlap=C.cast(ov, C.POINTER(C.c_int32)), flags=flags, reserved=0)
+    d._keep = ov
+    return d
+
+
+class Problem:
+    """One handle of the library (msrs_create ... msrs_destroy)."""
+
+    def __init__(self, desc: ProblemDesc, stream=None, hbm_budget_bytes: int = 0):
+        h = _H()
+        st = _lib.msrs_create(C.byref(h), C.byref(desc), _stream(stream), C.c_size_t(hbm_budget_bytes))
+        if st != OK:
+            raise MsrsError(st, _lib.msrs_last_error(None).decode())
+        self.h = h
+        self.desc = desc
+
+    def _check(self, st):
+        if st != OK:
+            raise MsrsError(st, _lib.msrs_last_error(self.h).decode())
+
+    def assemble_patch(self, coef):
+        self._check(_lib.msrs_assemble_patch(self.h, _ptr(coef)))
+
+    def sample_local_solutions(self, omega=None, Y_out=None):
+        self._check(_lib.msrs_sample_local_solutions(self.h, _ptr(omega), _ptr(Y_out)))
+
+    def range_finder(self, Q_out=None, sv_out=None):
+        self._check(_lib.msrs_range_finder(self.h, _ptr(Q_out), _ptr(sv_out)))
+
+    def copy_omega(self, out):
+        self._check(_lib.msrs_copy_omega(self.h, _ptr(out)))
+
+    def assemble_coarse(self):
+        self._check(_lib.msrs_assemble_coarse(self.h))
+
+    def set_max_batch(self, n):
+        self._check(_lib.msrs_set_max_batch(self.h, int(n)))
+
+    def solve_global(self, f, u, stream=None):
+        n_req = f.shape[0] if f.dim() == 2 else 1
+        s = None if stream is None else _stream(stream)
+        self._check(_lib.msrs_solve_global(self.h, int(n_req), _ptr(f), _ptr(u), s))
+
+    def layout(self) -> Layout:
+        out = Layout()
+        self._check(_lib.msrs_query_layout(self.h, C.byref(out)))
+        return out
+
+    def patch(self, p: int) -> PatchInfo:
+        out = PatchInfo()
+        self._check(_lib.msrs_query_patch(self.h, int(p), C.byref(out)))
+        return out
+
+    def stats(self, check: bool = True) -> Stats:
+        out = Stats()
+        st = _lib.msrs_get_stats(self.h, C.byref(out))
+        if check:
+            self._check(st)
+        return out
+
+    def reset_stats(self):
+        self._check(_lib.msrs_reset_stats(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.msrs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

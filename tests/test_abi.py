@@ -1,0 +1,66 @@
+"""C ABI: the library loads, exports every function include/msrs.h declares,
+and validates arguments on the host (no device work)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msrs.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(msrs_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    from paper_1807_08848_amd import msrs
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(msrs.lib, n), n
+
+
+def test_version_and_device_count():
+    from paper_1807_08848_amd import msrs
+    assert msrs.version() >= 100
+    assert msrs.device_count() >= 0
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((0, 128, 3, [8] * 9, 10, 6), "M must divide"),
+    ((0, 128, 4, [8] * 16, 10, 11), "rank"),
+    ((0, 128, 4, [8] * 16, 65, 6), "n_samples"),
+    ((0, 1024, 4, [128] * 16, 10, 6), "too large"),
+    ((0, 128, 4, [-1] * 16, 10, 6), "negative overlap"),
+    ((1, 4096, 32, [64] * 32, 48, 10), "n_vel"),
+    ((7, 128, 4, [8] * 16, 10, 6), "unknown kind"),
+])
+def test_create_validates_arguments(args, msg):
+    from paper_1807_08848_amd import msrs
+    with pytest.raises(msrs.MsrsError) as e:
+        msrs.Problem(msrs.make_desc(*args))
+    assert e.value.status == msrs.ERR_ARG and msg in str(e.value)
+
+
+def test_null_handle_calls_fail_cleanly():
+    from paper_1807_08848_amd import msrs
+    L = msrs.lib
+    assert L.msrs_assemble_patch(None, None) == msrs.ERR_ARG
+    assert L.msrs_sample_local_solutions(None, None, None) == msrs.ERR_ARG
+    assert L.msrs_range_finder(None, None, None) == msrs.ERR_ARG
+    assert L.msrs_assemble_coarse(None) == msrs.ERR_ARG
+    assert L.msrs_solve_global(None, 1, None, None, None) == msrs.ERR_ARG
+    L.msrs_destroy(None)
+
+
+def test_no_device_is_reported_without_a_gpu():
+    from paper_1807_08848_amd import msrs
+    if msrs.device_count() > 0:
+        pytest.skip("a device is visible")
+    with pytest.raises(msrs.MsrsError) as e:
+        msrs.Problem(msrs.make_desc(0, 128, 4, [8] * 16, 10, 6))
+    assert e.value.status == msrs.ERR_NO_DEVICE
