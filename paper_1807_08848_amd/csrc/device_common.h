@@ -91,6 +91,15 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return r;
 }
 
+// Workgroup barrier that orders LDS only: outstanding global loads (software
+// prefetches) stay in flight across it.  Valid where no thread reads global
+// memory that another thread of the workgroup wrote in the same kernel.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ void raise_flag(int32_t* flags, int which) {
     // sticky flag: every writer stores the same value, so a plain store suffices
     ((volatile int32_t*)flags)[which] = 1;

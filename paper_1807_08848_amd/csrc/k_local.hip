@@ -287,11 +287,15 @@ __device__ void factor_body(const PatchDesc& P, const double* __restrict__ aL, c
 #pragma unroll
             for (int c = 0; c < R; ++c) Es[(ty + 16 * r) * LDE + tx + 16 * c] = A[r][c];
         __syncthreads();
-        // store E_l column-major: E[l][j][i]
+        // store E_l in the MFMA operand order of the sweeps: for row tile rt,
+        // lane (li, lk) and k-step kk, E_l(16 rt + li, 4 kk + lk) sits at
+        // ((rt * 64 + lane) * BP/4 + kk), so each lane reads one contiguous run
         T* El = E + (int64_t)l * BP * BP;
+        constexpr int NKS = BP / 4;
         for (int o = tid; o < BP * BP; o += kThreads) {
-            const int j = o / BP, i = o - j * BP;
-            El[o] = Es[i * LDE + j];
+            const int kk = o % NKS, t = o / NKS;
+            const int lane = t & 63, rt = t >> 6;
+            El[o] = Es[(16 * rt + (lane & 15)) * LDE + 4 * kk + (lane >> 4)];
         }
     }
     if (bad) raise_flag(flags, 0);
@@ -322,153 +326,215 @@ __global__ __launch_bounds__(kThreads) void factor_kernel(const PatchDesc* pd, i
 
 // ------------------------------------------------------------ sweeps (a5)
 // grid (patch, column chunk of sc samples).  Both sweeps of one chunk run in
-// one workgroup; E_l y products on MFMA 16x16x4 (4 waves, wave w owns row
-// tiles w and w+4, all column tiles of the chunk).
-template <typename T>
-__device__ __forceinline__ void mfma_line(const T* __restrict__ El, const T* ybuf, int ld, int bp, int nct,
-                                          typename Mfma<T>::acc acc[2][4]) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nrt = bp >> 4;
+// one workgroup; the products E_l y run on MFMA 16x16x4 (4 waves: wave w owns
+// row tiles w and w+4 and all column tiles of the chunk).
+//
+// Software pipeline: the A operands of E_{l+1} are loaded into registers
+// while line l is processed, and the right-hand side and coupling loads of a
+// line are issued before them, so that the in-order load counter never makes
+// the stencil wait for the prefetch.
+constexpr int kSweepThreads = 512;   // 8 waves: wave w owns row tile w of E_l
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+
+// One patch x column chunk, with compile-time line tiles R (bp = 16 R) and
+// column tiles NCT (16 NCT samples), so the MFMA loop is straight-line code.
+template <typename T, int KIND, int R, int NCT>
+__device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw, double dx,
+                           const T* __restrict__ E, T* __restrict__ X, T* ybuf, T* wbuf, double* craw, double* cvp,
+                           double* cvm) {
+    typedef typename Vec16<T>::type V;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int BP = 16 * R, NKS = 4 * R, NSC = 16 * NCT;
+    constexpr int DI = kSweepThreads / NSC;          // rows between a thread's elements
+    constexpr int RPT = (BP + DI - 1) / DI;          // elements per thread
+    const int tid = threadIdx.x, lane = tid & 63, rt = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = Mfma<T>::zero();
-    const bool has0 = w < nrt, has1 = (w + 4) < nrt;
-    if (!has0) return;
-    const T* A0 = El + (16 * w + li);
-    const T* A1 = El + (16 * (w + 4) + li);
-    for (int k0 = 0; k0 < bp; k0 += 4) {
-        const int k = k0 + lk;
-        const T a0 = A0[(int64_t)k * bp];
-        const T a1 = has1 ? A1[(int64_t)k * bp] : T(0);
-        const T* yb = ybuf + k * ld + li;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (c < nct) {
-                const T bv = yb[16 * c];
-                acc[0][c] = Mfma<T>::step(a0, bv, acc[0][c]);
-                if (has1) acc[1][c] = Mfma<T>::step(a1, bv, acc[1][c]);
-            }
+    const bool mf = rt < R;                          // this wave owns a row tile
+    const int b = P.b, nl = P.nl, sp = P.sp, L = P.L;
+    const int lstride = BP * sp;
+    typename Mfma<T>::acc acc[NCT];
+    T aC[NKS];
+    T rv[RPT];
+    double crow = 0.0;
+    const int i0 = tid / NSC, jj = tid % NSC;
+
+    if (KIND == kKinetic) {
+        for (int a = tid; a < b; a += kSweepThreads) {
+            const double v = vw[a];
+            cvp[a] = v > 0 ? v / dx : 0.0;
+            cvm[a] = v < 0 ? -v / dx : 0.0;
         }
     }
-}
-
-// store accumulators to an LDS tile (row-major, ld) and optionally to global
-template <typename T>
-__device__ __forceinline__ void store_acc(typename Mfma<T>::acc acc[2][4], T* lds, int ld, int bp, int nct, T* gdst, int gld) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nrt = bp >> 4;
+    // Per-line copies of the thread's base indices: the empty asm hides their
+    // loop invariance so that per-element offsets are recomputed each line
+    // instead of being hoisted and kept live.
+    int li0 = i0, ljj = jj, llane = lane;
+    auto launder = [&]() {
+        li0 = i0; ljj = jj; llane = lane;
+        asm volatile("" : "+v"(li0), "+v"(ljj), "+v"(llane));
+    };
+    auto load_line = [&](const T* Xl) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int rt = w + 4 * r;
-        if (rt >= nrt) continue;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (c >= nct) continue;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int i = 16 * rt + Mfma<T>::row(lane, t), j = 16 * c + (lane & 15);
-                const T v = acc[r][c][t];
-                lds[i * ld + j] = v;
-                if (gdst) gdst[(int64_t)i * gld + j] = v;
-            }
+        for (int e = 0; e < RPT; ++e) {
+            const int i = li0 + e * DI;
+            if (BP % DI == 0 || i < BP) rv[e] = Xl[(uint32_t)(i * sp + ljj)];
         }
-    }
-}
-
-template <typename T, int KIND>
-__global__ __launch_bounds__(kThreads) void sweep_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
-                                                         const double* __restrict__ vw, double dx, const T* __restrict__ E_all,
-                                                         T* __restrict__ X_all, const int32_t* __restrict__ conv, int sc) {
-    __shared__ T ybuf[kMaxLine * kMaxSamples];
-    __shared__ T wbuf[kMaxLine * kMaxSamples];
-    __shared__ double cu[2 * kMaxLine];
-    const int p = p0 + blockIdx.x;
-    if (conv && conv[p]) return;
-    const PatchDesc P = pd[p];
-    const int s0 = blockIdx.y * sc;
-    if (s0 >= P.sp) return;
-    const int nsc = min(sc, P.sp - s0), nct = nsc >> 4;
-    const int bp = P.bp, b = P.b, nl = P.nl, sp = P.sp;
-    const double* aL = aL_all + P.a_off;
-    const T* E = E_all + P.E_off;
-    T* X = X_all + P.x_off + s0;
-    const int64_t lstride = (int64_t)bp * sp;
-    const int tid = threadIdx.x;
-    typename Mfma<T>::acc acc[2][4];
-
-    // coupling coefficients of line l (elliptic U_l from cell row l+1; kinetic v+/dx, v-/dx)
-    auto load_coupling = [&](int l) {
-        for (int a = tid; a < b; a += kThreads) {
-            if (KIND == kElliptic) {
-                cu[a] = -(a_cell(aL, P.L, l + 1, a) + a_cell(aL, P.L, l + 1, a + 1)) / 6.0;
-                cu[kMaxLine + a] = -a_cell(aL, P.L, l + 1, a + 1) / 3.0;
-            } else {
-                const double v = vw[a];
-                cu[a] = v > 0 ? v / dx : 0.0;
-                cu[kMaxLine + a] = v < 0 ? -v / dx : 0.0;
+    };
+    auto load_A = [&](const T* El) {
+        if (mf) {
+            const V* A = reinterpret_cast<const V*>(El + (uint32_t)((rt * 64 + llane) * NKS));
+#pragma unroll
+            for (int q = 0; q < NKS / VN; ++q) {
+                const V v = A[q];
+#pragma unroll
+                for (int u = 0; u < VN; ++u) aC[q * VN + u] = v[u];
             }
         }
     };
-    // Low_{l+1} applied to column j of src (elliptic U_l; kinetic -diag(v+/dx))
-    auto apply_low = [&](const T* src, int i, int j) -> double {
+    auto mfma = [&]() {
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) acc[c] = Mfma<T>::zero();
+        if (mf) {
+#pragma unroll
+            for (int kk = 0; kk < NKS; ++kk) {
+                const T* yb = ybuf + (4 * kk + lk) * NSC + li;
+#pragma unroll
+                for (int c = 0; c < NCT; ++c) acc[c] = Mfma<T>::step(aC[kk], yb[16 * c], acc[c]);
+            }
+        }
+    };
+    auto store_acc = [&](T* gdst) {
+        if (mf) {
+#pragma unroll
+            for (int c = 0; c < NCT; ++c)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int i = 16 * rt + Mfma<T>::row(lane, t), j = 16 * c + li;
+                    const T v = acc[c][t];
+                    wbuf[i * NSC + j] = v;
+                    if (gdst) gdst[(uint32_t)(i * sp + j)] = v;
+                }
+        }
+    };
+    // coupling of row i (Low_{l+1} if low, else Up_l) applied to column j of src
+    auto couple = [&](const T* src, int i, int j, bool low) -> double {
         if (KIND == kElliptic) {
-            double v = cu[i] * (double)src[i * nsc + j];
-            if (i > 0) v += cu[kMaxLine + i - 1] * (double)src[(i - 1) * nsc + j];
-            if (i < b - 1) v += cu[kMaxLine + i] * (double)src[(i + 1) * nsc + j];
-            return v;
+            // U_l symmetric tridiagonal from cell row l+1 (craw): diagonal
+            // -(c_i + c_{i+1})/6, off-diagonal (i, i+1) -c_{i+1}/3
+            const int im = i > 0 ? i - 1 : 0, ip = i + 1 < BP ? i + 1 : BP - 1;
+            const double cm = i > 0 ? -craw[i] / 3.0 : 0.0;
+            const double cp = i < b - 1 ? -craw[i + 1] / 3.0 : 0.0;
+            return -(craw[i] + craw[i + 1]) / 6.0 * (double)src[i * NSC + j] + cm * (double)src[im * NSC + j] +
+                   cp * (double)src[ip * NSC + j];
         } else {
-            return -cu[i] * (double)src[i * nsc + j];
+            return -(low ? cvp[i] : cvm[i]) * (double)src[i * NSC + j];
         }
-    };
-    auto apply_up = [&](const T* src, int i, int j) -> double {
-        if (KIND == kElliptic) return apply_low(src, i, j);
-        return -cu[kMaxLine + i] * (double)src[i * nsc + j];
     };
 
     // y_0 = r_0
-    for (int o = tid; o < bp * nsc; o += kThreads) {
-        const int i = o / nsc, j = o - i * nsc;
-        ybuf[o] = X[(int64_t)i * sp + j];
+    launder();
+    load_line(X);
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+        const int i = li0 + e * DI;
+        if (BP % DI == 0 || i < BP) ybuf[i * NSC + ljj] = rv[e];
     }
-    __syncthreads();
-    // forward sweep
+    load_A(E);
+    lds_barrier();
+    // ---- forward sweep
     for (int l = 0; l < nl; ++l) {
-        if (l + 1 < nl) load_coupling(l);
-        mfma_line<T>(E + (int64_t)l * bp * bp, ybuf, nsc, bp, nct, acc);
-        if (l + 1 == nl) {
-            store_acc<T>(acc, wbuf, nsc, bp, nct, X + (int64_t)l * lstride, sp);   // x_{nl-1}
-            __syncthreads();
+        launder();
+        const bool more = l + 1 < nl;
+        if (more) {
+            load_line(X + (l + 1) * lstride);                                      // r_{l+1}
+            if (KIND == kElliptic && tid <= b) crow = aL[(l + 1) * L + tid];     // U_l: cell row l+1
+        }
+        mfma();
+        if (!more) {
+            store_acc(X + l * lstride);   // x_{nl-1}
+            lds_barrier();
             break;
         }
-        store_acc<T>(acc, wbuf, nsc, bp, nct, nullptr, 0);
-        __syncthreads();
-        T* Xn = X + (int64_t)(l + 1) * lstride;
-        for (int o = tid; o < bp * nsc; o += kThreads) {
-            const int i = o / nsc, j = o - i * nsc;
-            T y = T(0);
-            if (i < b) y = (T)((double)Xn[(int64_t)i * sp + j] - apply_low(wbuf, i, j));
-            Xn[(int64_t)i * sp + j] = y;
-            ybuf[o] = y;
+        load_A(E + (int64_t)(l + 1) * BP * BP);                                   // E_{l+1}
+        store_acc(nullptr);
+        if (KIND == kElliptic && tid <= b) craw[tid] = crow;
+        lds_barrier();
+        T* Xn = X + (l + 1) * lstride;
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) {
+            const int i = li0 + e * DI;
+            if (BP % DI == 0 || i < BP) {
+                const double v = (double)rv[e] - couple(wbuf, i, ljj, true);
+                const T y = i < b ? (T)v : T(0);
+                Xn[(uint32_t)(i * sp + ljj)] = y;
+                ybuf[i * NSC + ljj] = y;
+            }
         }
-        __syncthreads();
+        lds_barrier();
     }
-    // back sweep: wbuf holds x_{l+1}
+    // ---- back sweep: wbuf holds x_{l+1}
     for (int l = nl - 2; l >= 0; --l) {
-        load_coupling(l);
-        __syncthreads();
-        T* Xl = X + (int64_t)l * lstride;
-        for (int o = tid; o < bp * nsc; o += kThreads) {
-            const int i = o / nsc, j = o - i * nsc;
-            T z = T(0);
-            if (i < b) z = (T)((double)Xl[(int64_t)i * sp + j] - apply_up(wbuf, i, j));
-            ybuf[o] = z;
+        launder();
+        load_line(X + l * lstride);                                                // y_l
+        if (KIND == kElliptic && tid <= b) crow = aL[(l + 1) * L + tid];         // U_l: cell row l+1
+        load_A(E + (int64_t)l * BP * BP);                                          // E_l
+        if (KIND == kElliptic && tid <= b) craw[tid] = crow;
+        lds_barrier();
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) {
+            const int i = li0 + e * DI;
+            if (BP % DI == 0 || i < BP) {
+                const double v = (double)rv[e] - couple(wbuf, i, ljj, false);
+                ybuf[i * NSC + ljj] = i < b ? (T)v : T(0);
+            }
         }
-        __syncthreads();
-        mfma_line<T>(E + (int64_t)l * bp * bp, ybuf, nsc, bp, nct, acc);
-        store_acc<T>(acc, wbuf, nsc, bp, nct, Xl, sp);
-        __syncthreads();
+        lds_barrier();
+        mfma();
+        store_acc(X + l * lstride);
+        lds_barrier();
+    }
+}
+
+// grid (patch, column chunk of 16*NCT samples); sp of every patch is a
+// multiple of the chunk.  Both sweeps of one chunk run in one workgroup.
+template <typename T, int KIND, int NCT>
+__global__ __launch_bounds__(kSweepThreads) void sweep_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
+                                                              const double* __restrict__ vw, double dx, const T* __restrict__ E_all,
+                                                              T* __restrict__ X_all, const int32_t* __restrict__ conv,
+                                                              int32_t* flags) {
+    __shared__ T ybuf[kMaxLine * 16 * NCT];
+    __shared__ T wbuf[kMaxLine * 16 * NCT];
+    __shared__ double craw[kMaxLine + 1];
+    __shared__ double cvp[kMaxLine], cvm[kMaxLine];
+    const int p = p0 + blockIdx.x;
+    if (conv && conv[p]) return;
+    const PatchDesc P = pd[p];
+    const int s0 = blockIdx.y * 16 * NCT;
+    if (s0 >= P.sp) return;
+    const double* aL = aL_all + P.a_off;
+    const T* E = E_all + P.E_off;
+    T* X = X_all + P.x_off + s0;
+    if (KIND == kKinetic) {
+        switch (P.bp >> 4) {
+            case 1: sweep_body<T, KIND, 1, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
+            case 2: sweep_body<T, KIND, 2, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
+            default: if (threadIdx.x == 0) raise_flag(flags, 3); break;
+        }
+        return;
+    }
+    switch (P.bp >> 4) {
+        case 1: sweep_body<T, KIND, 1, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
+        case 2: sweep_body<T, KIND, 2, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
+        case 3: sweep_body<T, KIND, 3, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
+        case 4: sweep_body<T, KIND, 4, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
+        case 5: sweep_body<T, KIND, 5, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
+        case 6: sweep_body<T, KIND, 6, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
+        case 7: sweep_body<T, KIND, 7, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
+        case 8: sweep_body<T, KIND, 8, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
+        default: if (threadIdx.x == 0) raise_flag(flags, 3); break;
     }
 }
 
@@ -660,20 +726,48 @@ void launch_factor(Ctx& c, int p0, int p1) {
     }
 }
 
+// samples per sweep workgroup: the largest of {64, 32, 16} (FP64 at most 32,
+// a register budget) not above the requested width that divides every sp
+static int sweep_chunk(const Ctx& c, int p0, int p1, bool fp32) {
+    int want = fp32 ? c.sweep_cols32 : std::min(c.sweep_cols64, 32);
+    for (int sc : {64, 32, 16}) {
+        if (sc > want) continue;
+        bool ok = true;
+        for (int p = p0; p < p1; ++p) ok = ok && (c.hp[p].sp % sc == 0);
+        if (ok) return sc;
+    }
+    return 16;
+}
+
 void launch_sweep(Ctx& c, int p0, int p1, bool fp32) {
     StageTimer t(c, MSRS_K_SWEEP);
     int maxsp = 0;
     for (int p = p0; p < p1; ++p) maxsp = std::max(maxsp, c.hp[p].sp);
-    const int sc = kMaxSamples;
-    const dim3 grid(p1 - p0, (maxsp + sc - 1) / sc);
+    const int sc = sweep_chunk(c, p0, p1, fp32);
+    const dim3 grid(p1 - p0, maxsp / sc), blk(kSweepThreads);
     const int32_t* conv = fp32 ? c.conv : nullptr;
+    const double dx = dx_of(c);
+#define MSRS_SWEEP(TT, KK, NN, XX) hipLaunchKernelGGL((sweep_kernel<TT, KK, NN>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, conv, c.dflags)
     if (c.kind == kElliptic) {
-        if (fp32) hipLaunchKernelGGL((sweep_kernel<float, kElliptic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), (const float*)c.E, c.x32, conv, sc);
-        else hipLaunchKernelGGL((sweep_kernel<double, kElliptic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), (const double*)c.E, c.x64, conv, sc);
+        if (fp32) {
+            if (sc == 64) MSRS_SWEEP(float, kElliptic, 4, c.x32);
+            else if (sc == 32) MSRS_SWEEP(float, kElliptic, 2, c.x32);
+            else MSRS_SWEEP(float, kElliptic, 1, c.x32);
+        } else {
+            if (sc == 32) MSRS_SWEEP(double, kElliptic, 2, c.x64);
+            else MSRS_SWEEP(double, kElliptic, 1, c.x64);
+        }
     } else {
-        if (fp32) hipLaunchKernelGGL((sweep_kernel<float, kKinetic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), (const float*)c.E, c.x32, conv, sc);
-        else hipLaunchKernelGGL((sweep_kernel<double, kKinetic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), (const double*)c.E, c.x64, conv, sc);
+        if (fp32) {
+            if (sc == 64) MSRS_SWEEP(float, kKinetic, 4, c.x32);
+            else if (sc == 32) MSRS_SWEEP(float, kKinetic, 2, c.x32);
+            else MSRS_SWEEP(float, kKinetic, 1, c.x32);
+        } else {
+            if (sc == 32) MSRS_SWEEP(double, kKinetic, 2, c.x64);
+            else MSRS_SWEEP(double, kKinetic, 1, c.x64);
+        }
     }
+#undef MSRS_SWEEP
 }
 
 void launch_residual(Ctx& c, int p0, int p1, bool accumulate, bool stats_only, int it) {

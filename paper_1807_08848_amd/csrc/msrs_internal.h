@@ -106,6 +106,8 @@ struct Ctx {
 
     // online
     int max_batch = 64;
+    int sweep_cols32 = 64;       // samples per sweep workgroup (FP32), 16 | value
+    int sweep_cols64 = 32;       // samples per sweep workgroup (FP64)
     int Np = 0, bw = 0;
     std::vector<CoarseDesc> hc;
     CoarseDesc* dc = nullptr;
