@@ -294,6 +294,7 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->E = ir ? (void*)dalloc<float>(*c, c->E_total) : (void*)dalloc<double>(*c, c->E_total);
         c->Y = dalloc<double>(*c, c->Y_total);
         c->Q = dalloc<double>(*c, c->Q_total);
+        c->rf_ws = dalloc<double>(*c, c->Q_total);
         c->sv = dalloc<double>(*c, c->sv_total);
         int64_t rn_total = 0;
         for (auto& P : c->hp) rn_total += 2 * P.sp;
@@ -301,6 +302,8 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->gap = dalloc<double>(*c, 2 * c->n_patches);
         c->conv = dalloc<int32_t>(*c, c->n_patches);
         c->iters = dalloc<int32_t>(*c, c->n_patches);
+        for (auto& P : c->hp) c->maxch = std::max(c->maxch, (P.nl + kChunkLines - 1) / kChunkLines);
+        c->part = dalloc<double>(*c, (int64_t)c->n_patches * c->maxch * kMaxSamples);
         c->dflags = dalloc<int32_t>(*c, 4);
         c->coef_copy = dalloc<double>(*c, c->kind == kElliptic ? (int64_t)c->N * c->N : c->N);
         MSRS_HIP_CHECK(hipMemset(c->dflags, 0, 4 * sizeof(int32_t)));
@@ -360,7 +363,7 @@ msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, 
         for_patches(*c, [&](int p0, int p1) { launch_lift(*c, p0, p1); });
         if (c->prec == MSRS_PREC_FP64) {
             for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, false); });
-            for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, true, 0); });
+            for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, true, 0); });
             c->last_ir_iters = 0;
         } else {
             launch_clear_conv(*c);
@@ -368,7 +371,7 @@ msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, 
             const int first = std::min(c->ir_max, c->ir_hint);
             for (; it < first; ++it) {
                 for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true); });
-                for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, true, false, it); });
+                for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it); });
             }
             // continue until every patch has converged (one host check per extra iteration)
             std::vector<int32_t> conv(c->n_patches);
@@ -385,7 +388,7 @@ msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, 
                     break;
                 }
                 for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true); });
-                for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, true, false, it); });
+                for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it); });
                 ++it;
             }
             std::vector<int32_t> iters(c->n_patches);

@@ -99,64 +99,80 @@ __global__ __launch_bounds__(kThreads) void omega_kernel(const PatchDesc* pd, in
 }
 
 // ------------------------------------------------------------ lifting (a3)
-// rhs = -A_IB omega written into the line vectors (FP64 or FP32), padding
-// zeroed; per-sample ||rhs||^2 to rn[0..sp).  x64 (if given) is zeroed.
+// Lines are processed in chunks of kChunkLines per workgroup: grid (patch,
+// chunk).  Per-sample sums of squares go to part[(p * maxch + chunk) * 64 + col]
+// and are reduced per patch by norms_kernel (fixed order, no atomics).
+
+// thread -> (row group, sample column) over a line of bp x sp values
+struct LineMap {
+    int col, row0, rows;
+    bool active;
+    __device__ LineMap(int sp) : col(threadIdx.x % sp), row0(threadIdx.x / sp), rows(kThreads / sp) {
+        active = row0 < rows;
+    }
+};
+
+__device__ __forceinline__ void partial_column_sums(double ssum, const LineMap& m, int sp, double* red, double* out) {
+    __syncthreads();
+    red[threadIdx.x] = m.active ? ssum : 0.0;
+    __syncthreads();
+    if (threadIdx.x < sp) {
+        double s = 0.0;
+        for (int r = 0; r < m.rows; ++r) s += red[r * sp + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// rhs = -A_IB omega into the line vectors X (FP64 or FP32), padding zeroed;
+// x64zero (if given) is zeroed.
 template <int KIND, typename TX>
 __global__ __launch_bounds__(kThreads) void lift_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
                                                         const double* __restrict__ om, const double* __restrict__ vw, double dx,
                                                         TX* __restrict__ X, double* __restrict__ x64zero,
-                                                        double* __restrict__ rn_all) {
+                                                        double* __restrict__ part, int maxch) {
     __shared__ double red[kThreads];
-    const PatchDesc P = pd[p0 + blockIdx.x];
+    const int p = p0 + blockIdx.x;
+    const PatchDesc P = pd[p];
+    const int l0 = blockIdx.y * kChunkLines;
+    if (l0 >= P.nl) return;
+    const int l1 = min(P.nl, l0 + kChunkLines);
     const double* aL = aL_all + P.a_off;
     const double* O = om + P.om_off;
     const int sp = P.sp, bp = P.bp, b = P.b, nl = P.nl;
-    const int per_line = bp * sp;
-    // thread -> (row group, sample column); sp in {16, 32, 48, 64}
-    const int tcol = threadIdx.x % sp;
-    const int trow0 = threadIdx.x / sp, trows = kThreads / sp;
-    const bool active = trow0 < trows;
+    const LineMap m(sp);
+    const int c = m.col;
     double ssum = 0.0;
-    for (int l = 0; l < nl; ++l) {
-        for (int i = trow0; active && i < bp; i += trows) {
-            const int c = tcol;
+    for (int l = l0; l < l1; ++l) {
+        for (int i = m.row0; m.active && i < bp; i += m.rows) {
             double v = 0.0;
             if (i < b && c < P.s) {
                 if (KIND == kElliptic) {
-                    const int p = i + 1, q = l + 1;
+                    const int pp = i + 1, q = l + 1;
 #pragma unroll
                     for (int dq = -1; dq <= 1; ++dq)
 #pragma unroll
                         for (int dp = -1; dp <= 1; ++dp) {
-                            const int pp = p + dp, qq = q + dq;
-                            if (pp == 0 || pp == P.L || qq == 0 || qq == P.Qn) {
+                            const int p2 = pp + dp, q2 = q + dq;
+                            if (p2 == 0 || p2 == P.L || q2 == 0 || q2 == P.Qn) {
                                 int ii, jj;
-                                line_to_phys(P, pp, qq, ii, jj);
-                                v -= q1_coef(aL, P.L, p, q, dp, dq) * O[(int64_t)c * P.nb + bidx_ccw(ii, jj, P.cx, P.cy)];
+                                line_to_phys(P, p2, q2, ii, jj);
+                                v -= q1_coef(aL, P.L, pp, q, dp, dq) * O[(int64_t)c * P.nb + bidx_ccw(ii, jj, P.cx, P.cy)];
                             }
                         }
                 } else {
-                    const int nv = P.b, h = nv / 2;
+                    const int h = b / 2;
                     const double vi = vw[i];
                     if (l == 0 && vi > 0) v += vi / dx * O[(int64_t)c * P.nb + (i - h)];
                     if (l == nl - 1 && vi < 0) v += -vi / dx * O[(int64_t)c * P.nb + h + i];
                 }
             }
-            const int64_t o = P.x_off + (int64_t)l * per_line + (int64_t)i * sp + c;
+            const int64_t o = P.x_off + (int64_t)l * bp * sp + (int64_t)i * sp + c;
             X[o] = (TX)v;
             if (x64zero) x64zero[o] = 0.0;
             ssum += v * v;
         }
     }
-    // reduce per column: threads with equal tcol
-    __syncthreads();
-    red[threadIdx.x] = active ? ssum : 0.0;
-    __syncthreads();
-    if (threadIdx.x < sp) {
-        double s = 0.0;
-        for (int r = 0; r < trows; ++r) s += red[r * sp + threadIdx.x];
-        rn_all[P.rn_off + threadIdx.x] = s;
-    }
+    partial_column_sums(ssum, m, sp, red, part + ((int64_t)p * maxch + blockIdx.y) * kMaxSamples);
 }
 
 // ------------------------------------------------------------ factorization (a4)
@@ -301,26 +317,301 @@ __device__ void factor_body(const PatchDesc& P, const double* __restrict__ aL, c
     if (bad) raise_flag(flags, 0);
 }
 
+// ---- blocked Gauss-Jordan on MFMA
+// The block D_l (BP = 16 R) is held as R x R tiles of 16 x 16 in MFMA
+// accumulator layout, tile (ti, tj) on wave (ti R + tj) % 8.  Pivots are taken
+// in panels of 16: the panel's diagonal block is inverted by one wave with
+// cross-lane shuffles, then X = Dinv A_{p,*} (new row panel), -A_{*,p} Dinv
+// (new column panel) and the rank-16 update A_{i,j} -= A_{i,p} X_j run on MFMA.
+constexpr int kFactorThreads = 512;
+
+// Inverse of a 16 x 16 block (row-major in LDS, ld 16) by one wave: lane l
+// holds row l%16, columns 4(l/16)..4(l/16)+3; Gauss-Jordan without pivoting.
+template <typename T>
+__device__ __forceinline__ void inv16_wave(const T* A, T* Dinv, bool& bad) {
+    const int l = threadIdx.x & 63, r = l & 15, cg = l >> 4;
+    T a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = A[r * 16 + 4 * cg + u];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int kg = k >> 2, ku = k & 3;
+        T prow[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) prow[u] = __shfl(a[u], k + 16 * cg, 64);
+        const T pcol = __shfl(a[ku], r + 16 * kg, 64);
+        const T piv = __shfl(a[ku], k + 16 * kg, 64);
+        if (!(piv > T(0)) || !isfinite((double)piv)) bad = true;
+        const T ip = T(1) / piv;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool ck = (4 * cg + u) == k;
+            const T gen = ck ? -pcol * ip : a[u] - pcol * ip * prow[u];
+            a[u] = (r == k) ? (ck ? ip : prow[u] * ip) : gen;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) Dinv[r * 16 + 4 * cg + u] = a[u];
+}
+
+template <typename T, int KIND, int R>
+__device__ __noinline__ void factor_mfma_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw,
+                                              double dx, double inv_eps, T* __restrict__ E, T* lds, double* cf,
+                                              double* crow, int32_t* flags) {
+    constexpr int BP = 16 * R, LDE = BP + 1, NT = R * R, NSLOT = (NT + 7) / 8;
+    constexpr int NKS = BP / 4;
+    typedef typename Mfma<T>::acc Acc;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int b = P.b, nl = P.nl, L = P.L;
+    T* Es = lds;                         // E_{l-1}, BP x LDE (row-major)
+    // panel buffers alias Es (free once D_l is formed)
+    T* Pc = lds;                         // [2][BP x 16]  column panel (row i, panel column k)
+    T* Pr = lds + 2 * BP * 16;           // [2][16 x BP]  row panel
+    T* Xs = lds + 4 * BP * 16;           // [2][16 x BP]  new row panel
+    T* Dv = lds + 6 * BP * 16;           // [2][16 x 16]  inverse of the diagonal block
+    Acc tile[NSLOT];
+    bool bad = false;
+    const int npan = (b + 15) / 16;
+    // elliptic: cell rows r and r+1 of the coefficient block live in crow[r & 1],
+    // crow[(r + 1) & 1] (ld kMaxLine + 1); row l + 2 is prefetched into a register
+    double rnext = 0.0;
+    if (KIND == kElliptic) {
+        if (tid < L) {
+            crow[tid] = aL[tid];
+            crow[(kMaxLine + 1) + tid] = aL[L + tid];
+            if (nl >= 2) rnext = aL[2 * L + tid];
+        }
+    } else {
+        for (int a = tid; a < b; a += kFactorThreads) {
+            const double v = vw[a];
+            cf[a] = v > 0 ? v / dx : 0.0;
+            cf[BP + a] = v < 0 ? -v / dx : 0.0;
+        }
+    }
+
+    for (int l = 0; l < nl; ++l) {
+        const double* rA = crow + (l & 1) * (kMaxLine + 1);          // cell row l
+        const double* rB = crow + ((l + 1) & 1) * (kMaxLine + 1);    // cell row l + 1
+        __syncthreads();
+        // coupling of the previous line (elliptic U_{l-1}: cell row l)
+        if (KIND == kElliptic && l > 0)
+            for (int a = tid; a < b; a += kFactorThreads) {
+                cf[a] = -(rA[a] + rA[a + 1]) / 6.0;
+                cf[BP + a] = -rA[a + 1] / 3.0;
+            }
+        __syncthreads();
+        // diagonal block entry (i, j < b) of line l
+        auto dg = [&](int i, int j) -> double {
+            if (KIND == kElliptic) {
+                if (i == j) return (2.0 / 3.0) * (rB[i + 1] + rB[i] + rA[i] + rA[i + 1]);
+                if (j == i + 1) return -(rB[i + 1] + rA[i + 1]) / 6.0;
+                if (i == j + 1) return -(rB[j + 1] + rA[j + 1]) / 6.0;
+                return 0.0;
+            } else {
+                return diag_entry<KIND>(P, aL, vw, dx, inv_eps, l, i, j);
+            }
+        };
+        // D_l = Dg_l - Low_l E_{l-1} Up_{l-1}, formed in place in LDS in two
+        // passes (Z = E_{l-1} Up_{l-1}, then D = Dg_l - Low_l Z), then loaded
+        // into the owned tiles.  Thread element e: o = tid + e * 512.
+        constexpr int EPT = (BP * BP + kFactorThreads - 1) / kFactorThreads;
+        if (l > 0) {
+            T z[EPT];
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int o = tid + e * kFactorThreads;
+                const int i = o / BP, j = o - (o / BP) * BP;
+                double v = 0.0;
+                if (o < BP * BP && i < b && j < b) {
+                    if (KIND == kElliptic) {
+                        // (E U)(i,j) = E(i,j-1) U(j-1,j) + E(i,j) U(j,j) + E(i,j+1) U(j+1,j)
+                        v = (double)Es[i * LDE + j] * cf[j];
+                        if (j > 0) v += (double)Es[i * LDE + j - 1] * cf[BP + j - 1];
+                        if (j < b - 1) v += (double)Es[i * LDE + j + 1] * cf[BP + j];
+                    } else {
+                        v = (double)Es[i * LDE + j] * cf[BP + j];
+                    }
+                }
+                z[e] = (T)v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int o = tid + e * kFactorThreads;
+                if (o < BP * BP) Es[(o / BP) * LDE + o % BP] = z[e];
+            }
+            __syncthreads();
+        }
+        {
+            T d[EPT];
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int o = tid + e * kFactorThreads;
+                const int i = o / BP, j = o - (o / BP) * BP;
+                double v = (i == j) ? 1.0 : 0.0;
+                if (o < BP * BP && i < b && j < b) {
+                    v = dg(i, j);
+                    if (l > 0) {
+                        if (KIND == kElliptic) {
+                            // (U^T Z)(i,j) = U(i-1,i) Z(i-1,j) + U(i,i) Z(i,j) + U(i+1,i) Z(i+1,j)
+                            double sv = cf[i] * (double)Es[i * LDE + j];
+                            if (i > 0) sv += cf[BP + i - 1] * (double)Es[(i - 1) * LDE + j];
+                            if (i < b - 1) sv += cf[BP + i] * (double)Es[(i + 1) * LDE + j];
+                            v -= sv;
+                        } else {
+                            v -= cf[i] * (double)Es[i * LDE + j];
+                        }
+                    }
+                }
+                d[e] = (T)v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int o = tid + e * kFactorThreads;
+                if (o < BP * BP) Es[(o / BP) * LDE + o % BP] = d[e];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < NSLOT; ++q) {
+            const int idx = q * 8 + w;
+            if (idx >= NT) continue;
+            const int ti = idx / R, tj = idx - ti * R;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) tile[q][t] = Es[(16 * ti + Mfma<T>::row(lane, t)) * LDE + 16 * tj + li];
+        }
+        __syncthreads();   // Es (E_{l-1}) no longer needed: panel buffers may overwrite it
+        // blocked Gauss-Jordan over the panels
+        for (int pn = 0; pn < npan; ++pn) {
+            const int buf = pn & 1;
+            T* pc = Pc + buf * BP * 16;
+            T* pr = Pr + buf * 16 * BP;
+            T* xs = Xs + buf * 16 * BP;
+            T* dv = Dv + buf * 256;
+            // B1: publish the panel column and row
+#pragma unroll
+            for (int q = 0; q < NSLOT; ++q) {
+                const int idx = q * 8 + w;
+                if (idx >= NT) continue;
+                const int ti = idx / R, tj = idx - ti * R;
+                if (tj != pn && ti != pn) continue;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int ii = Mfma<T>::row(lane, t);
+                    if (tj == pn) pc[(16 * ti + ii) * 16 + li] = tile[q][t];
+                    if (ti == pn) pr[ii * BP + 16 * tj + li] = tile[q][t];
+                }
+            }
+            __syncthreads();
+            // B2: inverse of the diagonal block (wave 0)
+            if (w == 0) inv16_wave<T>(pc + 16 * pn * 16, dv, bad);
+            __syncthreads();
+            // B3a: new row panel X_j = Dinv A_{p,j} (owners of row-panel tiles)
+#pragma unroll
+            for (int q = 0; q < NSLOT; ++q) {
+                const int idx = q * 8 + w;
+                if (idx >= NT) continue;
+                const int ti = idx / R, tj = idx - ti * R;
+                if (ti != pn || tj == pn) continue;
+                Acc x = Mfma<T>::zero();
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const int k = 4 * st + lk;
+                    x = Mfma<T>::step(dv[li * 16 + k], pr[k * BP + 16 * tj + li], x);
+                }
+                tile[q] = x;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) xs[Mfma<T>::row(lane, t) * BP + 16 * tj + li] = x[t];
+            }
+            __syncthreads();
+            // B3b: column panel and rank-16 update of the rest; diagonal tile = Dinv
+#pragma unroll
+            for (int q = 0; q < NSLOT; ++q) {
+                const int idx = q * 8 + w;
+                if (idx >= NT) continue;
+                const int ti = idx / R, tj = idx - ti * R;
+                if (ti == pn) {
+                    if (tj == pn) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) tile[q][t] = dv[Mfma<T>::row(lane, t) * 16 + li];
+                    }
+                    continue;
+                }
+                if (tj == pn) {
+                    Acc x = Mfma<T>::zero();
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) {
+                        const int k = 4 * st + lk;
+                        x = Mfma<T>::step(-pc[(16 * ti + li) * 16 + k], dv[k * 16 + li], x);
+                    }
+                    tile[q] = x;
+                } else {
+                    Acc x = tile[q];
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) {
+                        const int k = 4 * st + lk;
+                        x = Mfma<T>::step(-pc[(16 * ti + li) * 16 + k], xs[k * BP + 16 * tj + li], x);
+                    }
+                    tile[q] = x;
+                }
+            }
+        }
+        __syncthreads();   // panel buffers done: Es may be rewritten
+        // E_l -> Es (row-major), then to global in the sweep's MFMA operand order
+#pragma unroll
+        for (int q = 0; q < NSLOT; ++q) {
+            const int idx = q * 8 + w;
+            if (idx >= NT) continue;
+            const int ti = idx / R, tj = idx - ti * R;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) Es[(16 * ti + Mfma<T>::row(lane, t)) * LDE + 16 * tj + li] = tile[q][t];
+        }
+        __syncthreads();
+        T* El = E + (int64_t)l * BP * BP;
+        for (int o = tid; o < BP * BP; o += kFactorThreads) {
+            const int kk = o % NKS, t = o / NKS;
+            const int ln = t & 63, rt = t >> 6;
+            El[o] = Es[(16 * rt + (ln & 15)) * LDE + 4 * kk + (ln >> 4)];
+        }
+        // cell row l + 2 replaces row l; prefetch row l + 3
+        if (KIND == kElliptic && tid < L && l + 2 <= nl) {
+            crow[(l & 1) * (kMaxLine + 1) + tid] = rnext;
+            if (l + 3 <= nl) rnext = aL[(l + 3) * L + tid];
+        }
+    }
+    if (bad) raise_flag(flags, 0);
+}
+
 template <typename T, int KIND>
-__global__ __launch_bounds__(kThreads) void factor_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
-                                                          const double* __restrict__ vw, double dx, double inv_eps,
-                                                          T* __restrict__ E_all, int32_t* flags) {
-    __shared__ T Es[kMaxLine * (kMaxLine + 1)];
-    __shared__ T prow[2 * kMaxLine], pcol[2 * kMaxLine];
+__global__ __launch_bounds__(kFactorThreads) void factor_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
+                                                                const double* __restrict__ vw, double dx, double inv_eps,
+                                                                T* __restrict__ E_all, int32_t* flags) {
+    __shared__ T lds[kMaxLine * (kMaxLine + 1)];
     __shared__ double cf[2 * kMaxLine];
+    __shared__ double crow[2 * (kMaxLine + 1)];
     const PatchDesc P = pd[p0 + blockIdx.x];
     const double* aL = aL_all + P.a_off;
     T* E = E_all + P.E_off;
+    if (KIND == kKinetic) {
+        switch (P.bp / 16) {
+            case 1: factor_mfma_body<T, KIND, 1>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
+            case 2: factor_mfma_body<T, KIND, 2>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
+            default: if (threadIdx.x == 0) raise_flag(flags, 3); break;
+        }
+        return;
+    }
     switch (P.bp / 16) {
-        case 1: factor_body<T, KIND, 1>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
-        case 2: factor_body<T, KIND, 2>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
-        case 3: factor_body<T, KIND, 3>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
-        case 4: factor_body<T, KIND, 4>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
-        case 5: factor_body<T, KIND, 5>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
-        case 6: factor_body<T, KIND, 6>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
-        case 7: factor_body<T, KIND, 7>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
-        case 8: factor_body<T, KIND, 8>(P, aL, vw, dx, inv_eps, E, Es, prow, pcol, cf, flags); break;
-        default: raise_flag(flags, 3); break;
+        case 1: factor_mfma_body<T, KIND, 1>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
+        case 2: factor_mfma_body<T, KIND, 2>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
+        case 3: factor_mfma_body<T, KIND, 3>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
+        case 4: factor_mfma_body<T, KIND, 4>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
+        case 5: factor_mfma_body<T, KIND, 5>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
+        case 6: factor_mfma_body<T, KIND, 6>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
+        case 7: factor_mfma_body<T, KIND, 7>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
+        case 8: factor_mfma_body<T, KIND, 8>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
+        default: if (threadIdx.x == 0) raise_flag(flags, 3); break;
     }
 }
 
@@ -343,8 +634,8 @@ template <> struct Vec16<double> { typedef double2 type; static constexpr int n 
 // column tiles NCT (16 NCT samples), so the MFMA loop is straight-line code.
 template <typename T, int KIND, int R, int NCT>
 __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw, double dx,
-                           const T* __restrict__ E, T* __restrict__ X, T* ybuf, T* wbuf, double* craw, double* cvp,
-                           double* cvm) {
+                           const T* __restrict__ E, T* __restrict__ X, double* __restrict__ X64, T* ybuf, T* wbuf,
+                           double* craw, double* cvp, double* cvm) {
     typedef typename Vec16<T>::type V;
     constexpr int VN = Vec16<T>::n;
     constexpr int BP = 16 * R, NKS = 4 * R, NSC = 16 * NCT;
@@ -406,7 +697,9 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
             }
         }
     };
-    auto store_acc = [&](T* gdst) {
+    // accumulators -> wbuf, and for a solution line (gdst) to global; with X64
+    // the correction is also added to the FP64 iterate (refinement)
+    auto store_acc = [&](T* gdst, double* g64) {
         if (mf) {
 #pragma unroll
             for (int c = 0; c < NCT; ++c)
@@ -416,6 +709,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
                     const T v = acc[c][t];
                     wbuf[i * NSC + j] = v;
                     if (gdst) gdst[(uint32_t)(i * sp + j)] = v;
+                    if (g64) g64[(uint32_t)(i * sp + j)] += (double)v;
                 }
         }
     };
@@ -454,12 +748,12 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         }
         mfma();
         if (!more) {
-            store_acc(X + l * lstride);   // x_{nl-1}
+            store_acc(X + l * lstride, X64 ? X64 + l * lstride : nullptr);   // x_{nl-1}
             lds_barrier();
             break;
         }
         load_A(E + (int64_t)(l + 1) * BP * BP);                                   // E_{l+1}
-        store_acc(nullptr);
+        store_acc(nullptr, nullptr);
         if (KIND == kElliptic && tid <= b) craw[tid] = crow;
         lds_barrier();
         T* Xn = X + (l + 1) * lstride;
@@ -493,7 +787,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         }
         lds_barrier();
         mfma();
-        store_acc(X + l * lstride);
+        store_acc(X + l * lstride, X64 ? X64 + l * lstride : nullptr);
         lds_barrier();
     }
 }
@@ -503,8 +797,8 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
 template <typename T, int KIND, int NCT>
 __global__ __launch_bounds__(kSweepThreads) void sweep_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
                                                               const double* __restrict__ vw, double dx, const T* __restrict__ E_all,
-                                                              T* __restrict__ X_all, const int32_t* __restrict__ conv,
-                                                              int32_t* flags) {
+                                                              T* __restrict__ X_all, double* __restrict__ X64_all,
+                                                              const int32_t* __restrict__ conv, int32_t* flags) {
     __shared__ T ybuf[kMaxLine * 16 * NCT];
     __shared__ T wbuf[kMaxLine * 16 * NCT];
     __shared__ double craw[kMaxLine + 1];
@@ -517,63 +811,57 @@ __global__ __launch_bounds__(kSweepThreads) void sweep_kernel(const PatchDesc* p
     const double* aL = aL_all + P.a_off;
     const T* E = E_all + P.E_off;
     T* X = X_all + P.x_off + s0;
+    double* X64 = X64_all ? X64_all + P.x_off + s0 : nullptr;
     if (KIND == kKinetic) {
         switch (P.bp >> 4) {
-            case 1: sweep_body<T, KIND, 1, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
-            case 2: sweep_body<T, KIND, 2, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
+            case 1: sweep_body<T, KIND, 1, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
+            case 2: sweep_body<T, KIND, 2, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
             default: if (threadIdx.x == 0) raise_flag(flags, 3); break;
         }
         return;
     }
     switch (P.bp >> 4) {
-        case 1: sweep_body<T, KIND, 1, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
-        case 2: sweep_body<T, KIND, 2, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
-        case 3: sweep_body<T, KIND, 3, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
-        case 4: sweep_body<T, KIND, 4, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
-        case 5: sweep_body<T, KIND, 5, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
-        case 6: sweep_body<T, KIND, 6, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
-        case 7: sweep_body<T, KIND, 7, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
-        case 8: sweep_body<T, KIND, 8, NCT>(P, aL, vw, dx, E, X, ybuf, wbuf, craw, cvp, cvm); break;
+        case 1: sweep_body<T, KIND, 1, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
+        case 2: sweep_body<T, KIND, 2, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
+        case 3: sweep_body<T, KIND, 3, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
+        case 4: sweep_body<T, KIND, 4, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
+        case 5: sweep_body<T, KIND, 5, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
+        case 6: sweep_body<T, KIND, 6, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
+        case 7: sweep_body<T, KIND, 7, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
+        case 8: sweep_body<T, KIND, 8, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
         default: if (threadIdx.x == 0) raise_flag(flags, 3); break;
     }
 }
 
 // ------------------------------------------------------------ FP64 residual (a6)
-// One workgroup per patch.  accumulate: x64 += x32 first.  Then
-// r = rhs - A x64 per interior unknown; r is written to x32 (next correction
-// right-hand side) unless stats_only; rn[sp..2sp) = ||r_j||^2; conv[p] = 1
-// when every ||r_j|| <= tol ||rhs_j||; relres[p] = max_j ||r_j||/||rhs_j||.
+// r = rhs - A x64 per interior unknown, grid (patch, chunk of lines); r is
+// written to x32 (the next correction's right-hand side) unless x32 is null.
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void residual_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
                                                             const double* __restrict__ om, const double* __restrict__ vw,
-                                                            double dx, double inv_eps, double* __restrict__ x64_all,
-                                                            float* __restrict__ x32_all, double* __restrict__ rn_all,
-                                                            int32_t* __restrict__ conv, double* __restrict__ relres,
-                                                            int32_t* __restrict__ iters, int it, double tol, int accumulate,
-                                                            int stats_only) {
+                                                            double dx, double inv_eps, const double* __restrict__ x64_all,
+                                                            float* __restrict__ x32_all, const int32_t* __restrict__ conv,
+                                                            double* __restrict__ part, int maxch) {
     __shared__ double red[kThreads];
     const int p = p0 + blockIdx.x;
     if (conv && conv[p]) return;
     const PatchDesc P = pd[p];
+    const int l0 = blockIdx.y * kChunkLines;
+    if (l0 >= P.nl) return;
+    const int l1 = min(P.nl, l0 + kChunkLines);
     const double* aL = aL_all + P.a_off;
     const double* O = om + P.om_off;
     const int sp = P.sp, bp = P.bp, b = P.b, nl = P.nl;
-    double* X = x64_all + P.x_off;
+    const double* X = x64_all + P.x_off;
     float* X32 = x32_all ? x32_all + P.x_off : nullptr;
     const int64_t lstride = (int64_t)bp * sp;
-    const int tcol = threadIdx.x % sp, trows = kThreads / sp, trow0 = threadIdx.x / sp;
-    const bool active = trow0 < trows;
-    if (accumulate) {
-        const int64_t n = (int64_t)nl * lstride;
-        for (int64_t o = threadIdx.x; o < n; o += kThreads) X[o] += (double)X32[o];
-        __syncthreads();
-    }
+    const LineMap m(sp);
+    const int c = m.col;
     double ssum = 0.0;
-    const int c = tcol;
     auto xv = [&](int l, int i) -> double { return X[(int64_t)l * lstride + (int64_t)i * sp + c]; };
-    for (int l = 0; l < nl; ++l) {
-        if (KIND == kElliptic) {
-            for (int i = trow0; active && i < bp; i += trows) {
+    if (KIND == kElliptic) {
+        for (int l = l0; l < l1; ++l) {
+            for (int i = m.row0; m.active && i < bp; i += m.rows) {
                 double r = 0.0;
                 if (i < b && c < P.s) {
                     const int pp = i + 1, q = l + 1;
@@ -593,51 +881,77 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const PatchDesc* pd,
                             r -= q1_coef(aL, P.L, pp, q, dp, dq) * u;
                         }
                 }
-                if (!stats_only) X32[(int64_t)l * lstride + (int64_t)i * sp + c] = (float)r;
+                if (X32) X32[(int64_t)l * lstride + (int64_t)i * sp + c] = (float)r;
                 ssum += r * r;
             }
-        } else {
-            // each active thread with trow0 == 0 handles a whole cell column (all ordinates)
-            if (active && trow0 == 0) {
-                const int nv = b, h = nv / 2;
-                double rho = 0.0;
-                if (c < P.s)
-                    for (int j = 0; j < nv; ++j) rho += 0.5 * vw[nv + j] * xv(l, j);
-                const double s = aL[l] * inv_eps;
-                for (int i = 0; i < bp; ++i) {
-                    double r = 0.0;
-                    if (i < b && c < P.s) {
-                        const double vi = vw[i];
-                        double acc = (fabs(vi) / dx + s) * xv(l, i) - s * rho;
-                        if (vi > 0) acc -= vi / dx * (l > 0 ? xv(l - 1, i) : O[(int64_t)c * P.nb + (i - h)]);
-                        if (vi < 0) acc -= -vi / dx * (l < nl - 1 ? xv(l + 1, i) : O[(int64_t)c * P.nb + h + i]);
-                        r = -acc;
-                    }
-                    if (!stats_only) X32[(int64_t)l * lstride + (int64_t)i * sp + c] = (float)r;
-                    ssum += r * r;
+        }
+    } else {
+        // thread (row group g, column c): cells l0 + g, l0 + g + rows, ...; all ordinates of a cell
+        const int h = b / 2;
+        for (int l = l0 + m.row0; m.active && l < l1; l += m.rows) {
+            double rho = 0.0;
+            if (c < P.s)
+                for (int j = 0; j < b; ++j) rho += 0.5 * vw[b + j] * xv(l, j);
+            const double sg = aL[l] * inv_eps;
+            for (int i = 0; i < bp; ++i) {
+                double r = 0.0;
+                if (i < b && c < P.s) {
+                    const double vi = vw[i];
+                    double acc = (fabs(vi) / dx + sg) * xv(l, i) - sg * rho;
+                    if (vi > 0) acc -= vi / dx * (l > 0 ? xv(l - 1, i) : O[(int64_t)c * P.nb + (i - h)]);
+                    if (vi < 0) acc -= -vi / dx * (l < nl - 1 ? xv(l + 1, i) : O[(int64_t)c * P.nb + h + i]);
+                    r = -acc;
                 }
+                if (X32) X32[(int64_t)l * lstride + (int64_t)i * sp + c] = (float)r;
+                ssum += r * r;
             }
         }
     }
-    __syncthreads();
-    red[threadIdx.x] = active ? ssum : 0.0;
-    __syncthreads();
+    partial_column_sums(ssum, m, sp, red, part + ((int64_t)p * maxch + blockIdx.y) * kMaxSamples);
+}
+
+// x64 += x32 (the FP32 correction) over one chunk of lines of unconverged patches.
+__global__ __launch_bounds__(kThreads) void accum_kernel(const PatchDesc* pd, int p0, double* __restrict__ x64_all,
+                                                         const float* __restrict__ x32_all, const int32_t* __restrict__ conv) {
+    const int p = p0 + blockIdx.x;
+    if (conv[p]) return;
+    const PatchDesc P = pd[p];
+    const int l0 = blockIdx.y * kChunkLines;
+    if (l0 >= P.nl) return;
+    const int l1 = min(P.nl, l0 + kChunkLines);
+    const int64_t a = P.x_off + (int64_t)l0 * P.bp * P.sp, e = P.x_off + (int64_t)l1 * P.bp * P.sp;
+    for (int64_t o = a + threadIdx.x; o < e; o += kThreads) x64_all[o] += (double)x32_all[o];
+}
+
+// Per patch: sum the chunk partials.  which = 0: ||rhs_j||^2 -> rn[0..sp).
+// which = 1: ||r_j||^2 -> rn[sp..2sp), relres[p] = max_j ||r_j||/||rhs_j||,
+// and (if conv) conv[p] = 1, iters[p] = it + 1 once relres[p] <= tol.
+__global__ __launch_bounds__(64) void norms_kernel(const PatchDesc* pd, int p0, const double* __restrict__ part, int maxch,
+                                                   double* __restrict__ rn_all, int which, int32_t* __restrict__ conv,
+                                                   double* __restrict__ relres, int32_t* __restrict__ iters, int it, double tol) {
+    const int p = p0 + blockIdx.x;
+    if (which == 1 && conv && conv[p]) return;
+    const PatchDesc P = pd[p];
+    const int nch = (P.nl + kChunkLines - 1) / kChunkLines;
+    const int t = threadIdx.x;
     double* rn = rn_all + P.rn_off;
-    if (threadIdx.x < 64) {
-        // per column sums, then the max ratio over columns (wave 0)
-        double ratio = 0.0;
-        if (threadIdx.x < sp) {
-            double s2 = 0.0;
-            for (int r = 0; r < trows; ++r) s2 += red[r * sp + threadIdx.x];
-            rn[sp + threadIdx.x] = s2;
-            const double rh = rn[threadIdx.x];
-            if (threadIdx.x < P.s) ratio = rh > 0 ? sqrt(s2 / rh) : (s2 > 0 ? INFINITY : 0.0);
-        }
-        for (int off = 32; off > 0; off >>= 1) ratio = fmax(ratio, __shfl_xor(ratio, off, 64));
-        if (threadIdx.x == 0) {
-            relres[p] = ratio;
-            if (conv && ratio <= tol) { conv[p] = 1; iters[p] = it + 1; }
-        }
+    double s2 = 0.0;
+    if (t < P.sp)
+        for (int ch = 0; ch < nch; ++ch) s2 += part[((int64_t)p * maxch + ch) * kMaxSamples + t];
+    if (which == 0) {
+        if (t < P.sp) rn[t] = s2;
+        return;
+    }
+    double ratio = 0.0;
+    if (t < P.sp) {
+        rn[P.sp + t] = s2;
+        const double rh = rn[t];
+        if (t < P.s) ratio = rh > 0 ? sqrt(s2 / rh) : (s2 > 0 ? INFINITY : 0.0);
+    }
+    for (int off = 32; off > 0; off >>= 1) ratio = fmax(ratio, __shfl_xor(ratio, off, 64));
+    if (t == 0) {
+        relres[p] = ratio;
+        if (conv && ratio <= tol) { conv[p] = 1; iters[p] = it + 1; }
     }
 }
 
@@ -701,16 +1015,25 @@ void launch_omega(Ctx& c, const double* user, int p0, int p1) {
     hipLaunchKernelGGL(omega_kernel, dim3(p1 - p0, (maxs + 15) / 16), dim3(kThreads), 0, c.stream, c.dp, p0, user, c.om, c.seed);
 }
 
+static int max_chunks(const Ctx& c, int p0, int p1) {
+    int m = 1;
+    for (int p = p0; p < p1; ++p) m = std::max(m, (c.hp[p].nl + kChunkLines - 1) / kChunkLines);
+    return m;
+}
+
 void launch_lift(Ctx& c, int p0, int p1) {
     StageTimer t(c, MSRS_K_LIFT);
     const bool ir = c.prec == MSRS_PREC_FP32_IR;
+    const dim3 grid(p1 - p0, max_chunks(c, p0, p1));
     if (c.kind == kElliptic) {
-        if (ir) hipLaunchKernelGGL((lift_kernel<kElliptic, float>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x32, c.x64, c.rn);
-        else hipLaunchKernelGGL((lift_kernel<kElliptic, double>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, (double*)nullptr, c.rn);
+        if (ir) hipLaunchKernelGGL((lift_kernel<kElliptic, float>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x32, c.x64, c.part, c.maxch);
+        else hipLaunchKernelGGL((lift_kernel<kElliptic, double>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, (double*)nullptr, c.part, c.maxch);
     } else {
-        if (ir) hipLaunchKernelGGL((lift_kernel<kKinetic, float>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x32, c.x64, c.rn);
-        else hipLaunchKernelGGL((lift_kernel<kKinetic, double>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, (double*)nullptr, c.rn);
+        if (ir) hipLaunchKernelGGL((lift_kernel<kKinetic, float>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x32, c.x64, c.part, c.maxch);
+        else hipLaunchKernelGGL((lift_kernel<kKinetic, double>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, (double*)nullptr, c.part, c.maxch);
     }
+    hipLaunchKernelGGL(norms_kernel, dim3(p1 - p0), dim3(64), 0, c.stream, c.dp, p0, c.part, c.maxch, c.rn, 0, (int32_t*)nullptr,
+                       (double*)nullptr, (int32_t*)nullptr, 0, 0.0);
 }
 
 void launch_factor(Ctx& c, int p0, int p1) {
@@ -718,11 +1041,11 @@ void launch_factor(Ctx& c, int p0, int p1) {
     const double inv_eps = 1.0 / c.eps;
     const bool ir = c.prec == MSRS_PREC_FP32_IR;
     if (c.kind == kElliptic) {
-        if (ir) hipLaunchKernelGGL((factor_kernel<float, kElliptic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (float*)c.E, c.dflags);
-        else hipLaunchKernelGGL((factor_kernel<double, kElliptic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (double*)c.E, c.dflags);
+        if (ir) hipLaunchKernelGGL((factor_kernel<float, kElliptic>), dim3(p1 - p0), dim3(kFactorThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (float*)c.E, c.dflags);
+        else hipLaunchKernelGGL((factor_kernel<double, kElliptic>), dim3(p1 - p0), dim3(kFactorThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (double*)c.E, c.dflags);
     } else {
-        if (ir) hipLaunchKernelGGL((factor_kernel<float, kKinetic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (float*)c.E, c.dflags);
-        else hipLaunchKernelGGL((factor_kernel<double, kKinetic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (double*)c.E, c.dflags);
+        if (ir) hipLaunchKernelGGL((factor_kernel<float, kKinetic>), dim3(p1 - p0), dim3(kFactorThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (float*)c.E, c.dflags);
+        else hipLaunchKernelGGL((factor_kernel<double, kKinetic>), dim3(p1 - p0), dim3(kFactorThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (double*)c.E, c.dflags);
     }
 }
 
@@ -747,7 +1070,8 @@ void launch_sweep(Ctx& c, int p0, int p1, bool fp32) {
     const dim3 grid(p1 - p0, maxsp / sc), blk(kSweepThreads);
     const int32_t* conv = fp32 ? c.conv : nullptr;
     const double dx = dx_of(c);
-#define MSRS_SWEEP(TT, KK, NN, XX) hipLaunchKernelGGL((sweep_kernel<TT, KK, NN>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, conv, c.dflags)
+    double* x64acc = nullptr;   // the refinement update runs in accum_kernel
+#define MSRS_SWEEP(TT, KK, NN, XX) hipLaunchKernelGGL((sweep_kernel<TT, KK, NN>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, x64acc, conv, c.dflags)
     if (c.kind == kElliptic) {
         if (fp32) {
             if (sc == 64) MSRS_SWEEP(float, kElliptic, 4, c.x32);
@@ -770,17 +1094,21 @@ void launch_sweep(Ctx& c, int p0, int p1, bool fp32) {
 #undef MSRS_SWEEP
 }
 
-void launch_residual(Ctx& c, int p0, int p1, bool accumulate, bool stats_only, int it) {
+void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it) {
     StageTimer t(c, MSRS_K_RESIDUAL);
     const double inv_eps = 1.0 / c.eps;
     int32_t* conv = stats_only ? nullptr : c.conv;
     float* x32 = stats_only ? nullptr : c.x32;
+    const dim3 grid(p1 - p0, max_chunks(c, p0, p1));
+    if (!stats_only) hipLaunchKernelGGL(accum_kernel, grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.x64, c.x32, c.conv);
     if (c.kind == kElliptic)
-        hipLaunchKernelGGL((residual_kernel<kElliptic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), inv_eps,
-                           c.x64, x32, c.rn, conv, c.gap + c.n_patches, c.iters, it, c.ir_tol, accumulate ? 1 : 0, stats_only ? 1 : 0);
+        hipLaunchKernelGGL((residual_kernel<kElliptic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), inv_eps,
+                           c.x64, x32, conv, c.part, c.maxch);
     else
-        hipLaunchKernelGGL((residual_kernel<kKinetic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), inv_eps,
-                           c.x64, x32, c.rn, conv, c.gap + c.n_patches, c.iters, it, c.ir_tol, accumulate ? 1 : 0, stats_only ? 1 : 0);
+        hipLaunchKernelGGL((residual_kernel<kKinetic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), inv_eps,
+                           c.x64, x32, conv, c.part, c.maxch);
+    hipLaunchKernelGGL(norms_kernel, dim3(p1 - p0), dim3(64), 0, c.stream, c.dp, p0, c.part, c.maxch, c.rn, 1, conv,
+                       c.gap + c.n_patches, c.iters, it, c.ir_tol);
 }
 
 void launch_restrict(Ctx& c, int p0, int p1) {

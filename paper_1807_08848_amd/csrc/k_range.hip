@@ -15,43 +15,67 @@ namespace msrs {
 constexpr int kRfMax = 64;     // max columns
 constexpr int kRfChunk = 32;   // rows staged per Gram step
 
-// G (ld kRfMax, LDS) = A^T A for A column-major (lda rows), ncols <= 64.
-__device__ void gram_lds(const double* __restrict__ A, int nrows, int lda, int ncols, double* G, double* stage) {
+// G (ld kRfMax, LDS) = A^T A for A column-major (lda rows), ncols <= 16 TS.
+// Thread (ty, tx) accumulates the TS x TS block of entries (ty + 16 r, tx + 16 c).
+template <int TS>
+__device__ void gram_tile(const double* __restrict__ A, int nrows, int lda, int ncols, double* G, double* stage) {
+    // chunk elements per thread: kRfChunk * ncols <= 32 * 64 = 8 * kThreads
+    constexpr int EPT = kRfChunk * kRfMax / kThreads;
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-    double acc[4][4];
+    double acc[TS][TS];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < TS; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
-    for (int r0 = 0; r0 < nrows; r0 += kRfChunk) {
-        const int nr = min(kRfChunk, nrows - r0);
-        __syncthreads();
-        for (int o = tid; o < kRfChunk * ncols; o += kThreads) {
+        for (int c = 0; c < TS; ++c) acc[r][c] = 0.0;
+    const int n = kRfChunk * ncols;
+    double pre[EPT];
+    auto fetch = [&](int r0) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int o = tid + e * kThreads;
             const int col = o / kRfChunk, row = o - col * kRfChunk;
-            stage[row * kRfMax + col] = row < nr ? A[(int64_t)col * lda + r0 + row] : 0.0;
+            pre[e] = (o < n && r0 + row < nrows) ? A[(int64_t)col * lda + r0 + row] : 0.0;
+        }
+    };
+    fetch(0);
+    for (int r0 = 0; r0 < nrows; r0 += kRfChunk) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int o = tid + e * kThreads;
+            if (o < n) stage[(o % kRfChunk) * kRfMax + o / kRfChunk] = pre[e];
         }
         __syncthreads();
+        if (r0 + kRfChunk < nrows) fetch(r0 + kRfChunk);   // next chunk in flight during this one
+        const int nr = min(kRfChunk, nrows - r0);
         for (int row = 0; row < nr; ++row) {
-            double a[4], b[4];
+            double a[TS], b[TS];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = stage[row * kRfMax + ty + 16 * r];
+            for (int r = 0; r < TS; ++r) a[r] = stage[row * kRfMax + ty + 16 * r];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = stage[row * kRfMax + tx + 16 * c];
+            for (int c = 0; c < TS; ++c) b[c] = stage[row * kRfMax + tx + 16 * c];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < TS; ++r)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+                for (int c = 0; c < TS; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < TS; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < TS; ++c) {
             const int i = ty + 16 * r, j = tx + 16 * c;
             if (i < ncols && j < ncols) G[i * kRfMax + j] = acc[r][c];
         }
     __syncthreads();
+}
+
+__device__ void gram_lds(const double* __restrict__ A, int nrows, int lda, int ncols, double* G, double* stage) {
+    if (ncols <= 16) gram_tile<1>(A, nrows, lda, ncols, G, stage);
+    else if (ncols <= 32) gram_tile<2>(A, nrows, lda, ncols, G, stage);
+    else if (ncols <= 48) gram_tile<3>(A, nrows, lda, ncols, G, stage);
+    else gram_tile<4>(A, nrows, lda, ncols, G, stage);
 }
 
 // Cholesky of the n x n SPD matrix G (LDS, ld kRfMax) in place (lower).
@@ -82,25 +106,48 @@ __device__ bool chol_lds(double* G, int n, int* okflag) {
     return ok;
 }
 
-// Q (column-major, ldq rows, n columns) <- Q L^{-T}, L lower in LDS: each row
-// q solves x L^T = q, i.e. x_j = (q_j - sum_{c<j} x_c L[j][c]) / L[j][j].
-__device__ void trsm_rows(double* __restrict__ Q, int nrows, int ldq, int n, const double* L) {
-    for (int row = threadIdx.x; row < nrows; row += kThreads) {
-        double x[kRfMax];
-#pragma unroll 4
-        for (int j = 0; j < n; ++j) {
-            double v = Q[(int64_t)j * ldq + row];
-            for (int c = 0; c < j; ++c) v -= x[c] * L[j * kRfMax + c];
-            x[j] = v / L[j * kRfMax + j];
+// T (ld kRfMax) = L^{-T} for the lower Cholesky factor L (n x n, LDS): thread
+// j forms column j of L^{-1} by forward substitution; T[i][j] = L^{-1}[j][i].
+__device__ void inv_transpose_lds(const double* L, int n, double* T) {
+    const int j = threadIdx.x;
+    if (j < n) {
+        for (int i = 0; i < n; ++i) {
+            double v = (i == j) ? 1.0 : 0.0;
+            for (int c = j; c < i; ++c) v -= L[i * kRfMax + c] * T[j * kRfMax + c];
+            T[j * kRfMax + i] = (i < j) ? 0.0 : v / L[i * kRfMax + i];
         }
-        for (int j = 0; j < n; ++j) Q[(int64_t)j * ldq + row] = x[j];
+    }
+    __syncthreads();
+}
+
+// out (nrows x k, column-major) = A (nrows x m, column-major) * B (m x k, LDS ld kRfMax).
+// A thread owns one row and a block of 8 columns, so each A element is read
+// once per 8 outputs (coalesced across threads); B is broadcast from LDS.
+__device__ void gemm_rows(const double* __restrict__ A, int nrows, int m, const double* B, int k, double* __restrict__ out) {
+    constexpr int CB = 8;
+    const int nblk = (k + CB - 1) / CB;
+    for (int o = threadIdx.x; o < nrows * nblk; o += kThreads) {
+        const int jb = o / nrows, r = o - jb * nrows;
+        const int j0 = jb * CB;
+        double acc[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[c] = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < m; ++i) {
+            const double a = A[(int64_t)i * nrows + r];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) acc[c] = fma(a, B[i * kRfMax + min(j0 + c, kRfMax - 1)], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            if (j0 + c < k) out[(int64_t)(j0 + c) * nrows + r] = acc[c];
     }
     __syncthreads();
 }
 
 __global__ __launch_bounds__(kThreads) void range_kernel(const PatchDesc* pd, int p0, const double* __restrict__ Y_all,
-                                                         double* __restrict__ Q_all, double* __restrict__ sv_all,
-                                                         double* __restrict__ gap, int32_t* flags) {
+                                                         double* __restrict__ Q_all, double* __restrict__ ws_all,
+                                                         double* __restrict__ sv_all, double* __restrict__ gap, int32_t* flags) {
     __shared__ double G[kRfMax * kRfMax];
     __shared__ double V[kRfMax * kRfMax];
     __shared__ double stage[kRfChunk * kRfMax];
@@ -120,6 +167,7 @@ __global__ __launch_bounds__(kThreads) void range_kernel(const PatchDesc* pd, in
     const int k = P.ncols;
     const double* Y = Y_all + P.Y_off;
     double* Q = Q_all + P.Q_off;
+    double* W = ws_all + P.Q_off;   // workspace of the same shape as Q
 
     // 1. Gram matrix
     gram_lds(Y, nrows, nrows, s, G, stage);
@@ -132,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void range_kernel(const PatchDesc* pd, in
     }
     __syncthreads();
     double fro = 0.0;
-    for (int o = 0; o < s; ++o) fro += G[o * kRfMax + o] * G[o * kRfMax + o];   // only for scale
+    for (int o = 0; o < s; ++o) fro += G[o * kRfMax + o] * G[o * kRfMax + o];
     for (int sweep = 0; sweep < 30; ++sweep) {
         for (int st = 0; st < n - 1; ++st) {
             if (tid < n / 2) {
@@ -153,24 +201,28 @@ __global__ __launch_bounds__(kThreads) void range_kernel(const PatchDesc* pd, in
                 sn[i] = t * c;
             }
             __syncthreads();
-            // rows: A <- J^T A
-            for (int o = tid; o < (n / 2) * n; o += kThreads) {
-                const int i = o / n, j = o % n;
-                const int a = pu[i], b = pv[i];
-                const double c = cs[i], sv = sn[i];
-                const double ga = G[a * kRfMax + j], gb = G[b * kRfMax + j];
-                G[a * kRfMax + j] = c * ga - sv * gb;
-                G[b * kRfMax + j] = sv * ga + c * gb;
+            // G <- J^T G J on 2x2 blocks (pairs i, i2): rows rotate by pair i,
+            // columns by pair i2; V <- V J on (row j, pair i)
+            const int np2 = n / 2;
+            for (int o = tid; o < np2 * np2; o += kThreads) {
+                const int i = o / np2, i2 = o % np2;
+                const int a = pu[i], b = pv[i], a2 = pu[i2], b2 = pv[i2];
+                const double c = cs[i], sv = sn[i], c2 = cs[i2], s2 = sn[i2];
+                const double g00 = G[a * kRfMax + a2], g01 = G[a * kRfMax + b2];
+                const double g10 = G[b * kRfMax + a2], g11 = G[b * kRfMax + b2];
+                // rows
+                const double r00 = c * g00 - sv * g10, r01 = c * g01 - sv * g11;
+                const double r10 = sv * g00 + c * g10, r11 = sv * g01 + c * g11;
+                // columns
+                G[a * kRfMax + a2] = c2 * r00 - s2 * r01;
+                G[a * kRfMax + b2] = s2 * r00 + c2 * r01;
+                G[b * kRfMax + a2] = c2 * r10 - s2 * r11;
+                G[b * kRfMax + b2] = s2 * r10 + c2 * r11;
             }
-            __syncthreads();
-            // columns: A <- A J, V <- V J
-            for (int o = tid; o < (n / 2) * n; o += kThreads) {
+            for (int o = tid; o < np2 * n; o += kThreads) {
                 const int i = o / n, j = o % n;
                 const int a = pu[i], b = pv[i];
                 const double c = cs[i], sv = sn[i];
-                const double ga = G[j * kRfMax + a], gb = G[j * kRfMax + b];
-                G[j * kRfMax + a] = c * ga - sv * gb;
-                G[j * kRfMax + b] = sv * ga + c * gb;
                 const double va = V[j * kRfMax + a], vb = V[j * kRfMax + b];
                 V[j * kRfMax + a] = c * va - sv * vb;
                 V[j * kRfMax + b] = sv * va + c * vb;
@@ -185,11 +237,11 @@ __global__ __launch_bounds__(kThreads) void range_kernel(const PatchDesc* pd, in
         }
         red_v[tid] = loc;
         __syncthreads();
-        if (tid == 0) {
-            double t = 0.0;
-            for (int i = 0; i < kThreads; ++i) t += red_v[i];
-            offn = t;
+        for (int w = kThreads / 2; w > 0; w >>= 1) {
+            if (tid < w) red_v[tid] += red_v[tid + w];
+            __syncthreads();
         }
+        if (tid == 0) offn = red_v[0];
         __syncthreads();
         if (offn <= 1e-32 * fro) break;
     }
@@ -210,39 +262,32 @@ __global__ __launch_bounds__(kThreads) void range_kernel(const PatchDesc* pd, in
         gap[p] = (k < s) ? (sk - svp[k]) / s1 : 1.0;
     }
     __syncthreads();
-    // 4. B = V[:, perm[:k]] / sigma, s x k (ld kRfMax), stored in G (free after the sort)
+    // 4. B = V[:, perm[:k]] / sigma (s x k, in G, free after the sort); W = Y B
     for (int o = tid; o < s * k; o += kThreads) {
         const int i = o / k, j = o % k;
         const double sg = sqrt(fmax(lam[perm[j]], 0.0));
         G[i * kRfMax + j] = sg > 0 ? V[i * kRfMax + perm[j]] / sg : 0.0;
     }
     __syncthreads();
-    // 5. Q = Y B
-    for (int row = tid; row < nrows; row += kThreads) {
-        double q[kRfMax];
-        for (int j = 0; j < k; ++j) q[j] = 0.0;
-        for (int i = 0; i < s; ++i) {
-            const double y = Y[(int64_t)i * nrows + row];
-            for (int j = 0; j < k; ++j) q[j] = fma(y, G[i * kRfMax + j], q[j]);
-        }
-        for (int j = 0; j < k; ++j) Q[(int64_t)j * nrows + row] = q[j];
-    }
-    __syncthreads();
-    // 6. two Cholesky-QR passes on the k columns
+    gemm_rows(Y, nrows, s, G, k, W);
+    // 5. two Cholesky-QR passes on the k columns: W -> Q -> W
     for (int pass = 0; pass < 2; ++pass) {
-        gram_lds(Q, nrows, nrows, k, G, stage);
+        const double* src = pass == 0 ? W : Q;
+        double* dst = pass == 0 ? Q : W;
+        gram_lds(src, nrows, nrows, k, G, stage);
         if (!chol_lds(G, k, &okflag)) {
             if (tid == 0) raise_flag(flags, 2);
             return;
         }
-        trsm_rows(Q, nrows, nrows, k, G);
+        inv_transpose_lds(G, k, V);
+        gemm_rows(src, nrows, k, V, k, dst);
     }
-    // 7. sign fix: largest |entry| of each column positive, lowest index on ties
+    // 6. sign fix (largest |entry| of each column positive, lowest index on ties), W -> Q
     for (int j = 0; j < k; ++j) {
         double bv = -1.0;
         int bi = 0;
         for (int row = tid; row < nrows; row += kThreads) {
-            const double a = fabs(Q[(int64_t)j * nrows + row]);
+            const double a = fabs(W[(int64_t)j * nrows + row]);
             if (a > bv || (a == bv && row < bi)) { bv = a; bi = row; }
         }
         red_v[tid] = bv;
@@ -257,16 +302,15 @@ __global__ __launch_bounds__(kThreads) void range_kernel(const PatchDesc* pd, in
             __syncthreads();
         }
         const int at = min(max(red_i[0], 0), nrows - 1);
-        const bool flip = Q[(int64_t)j * nrows + at] < 0.0;
+        const double sg = W[(int64_t)j * nrows + at] < 0.0 ? -1.0 : 1.0;
         __syncthreads();
-        if (flip)
-            for (int row = tid; row < nrows; row += kThreads) Q[(int64_t)j * nrows + row] = -Q[(int64_t)j * nrows + row];
+        for (int row = tid; row < nrows; row += kThreads) Q[(int64_t)j * nrows + row] = sg * W[(int64_t)j * nrows + row];
     }
 }
 
 void launch_range(Ctx& c, int p0, int p1) {
     StageTimer t(c, MSRS_K_RANGE);
-    hipLaunchKernelGGL(range_kernel, dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.Y, c.Q, c.sv, c.gap, c.dflags);
+    hipLaunchKernelGGL(range_kernel, dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.Y, c.Q, c.rf_ws, c.sv, c.gap, c.dflags);
 }
 
 }  // namespace msrs

@@ -15,6 +15,7 @@ namespace msrs {
 constexpr int kMaxLine = 128;      // padded unknowns per block row (elliptic); 16 | bp
 constexpr int kMaxSamples = 64;    // padded samples per patch
 constexpr int kThreads = 256;      // threads of every per-patch workgroup
+constexpr int kChunkLines = 8;     // block rows per workgroup of the lifting and residual kernels
 
 // One buffered patch, in the block-row ("line") view of the local problem.
 //
@@ -97,6 +98,8 @@ struct Ctx {
     double* rf_ws = nullptr;      // range finder workspace
     double* coef_copy = nullptr;  // device copy of the coefficient field (traces)
     int32_t* iters = nullptr;     // per patch refinement iterations at convergence
+    double* part = nullptr;       // per (patch, line chunk) partial column sums, 64 each
+    int maxch = 1;                // line chunks per patch at most
 
     int64_t omega_total = 0, Y_total = 0, Q_total = 0, sv_total = 0;
     int64_t x_total = 0, E_total = 0, aL_total = 0;
@@ -135,7 +138,7 @@ void launch_omega(Ctx& c, const double* user, int p0, int p1);
 void launch_lift(Ctx& c, int p0, int p1);
 void launch_factor(Ctx& c, int p0, int p1);
 void launch_sweep(Ctx& c, int p0, int p1, bool fp32);
-void launch_residual(Ctx& c, int p0, int p1, bool accumulate, bool stats_only, int it);
+void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it);
 void launch_restrict(Ctx& c, int p0, int p1);
 void launch_range(Ctx& c, int p0, int p1);
 void launch_clear_conv(Ctx& c);
