@@ -304,6 +304,29 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->iters = dalloc<int32_t>(*c, c->n_patches);
         for (auto& P : c->hp) c->maxch = std::max(c->maxch, (P.nl + kChunkLines - 1) / kChunkLines);
         c->part = dalloc<double>(*c, (int64_t)c->n_patches * c->maxch * kMaxSamples);
+        {
+            std::vector<int32_t> ids(c->n_patches);
+            for (int p = 0; p < c->n_patches; ++p) ids[p] = p;
+            c->pid = dalloc<int32_t>(*c, c->n_patches);
+            MSRS_HIP_CHECK(hipMemcpy(c->pid, ids.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+            std::vector<std::vector<int32_t>> grp(9);
+            for (int p = 0; p < c->n_patches; ++p) grp[std::min(8, c->hp[p].bp / 16)].push_back(p);
+            int ngroups = 0;
+            for (int g = 0; g < 9; ++g) {
+                c->rgroup_n[g] = (int)grp[g].size();
+                if (grp[g].empty()) continue;
+                c->rgroup[g] = dalloc<int32_t>(*c, (int64_t)grp[g].size());
+                MSRS_HIP_CHECK(hipMemcpy(c->rgroup[g], grp[g].data(), grp[g].size() * sizeof(int32_t), hipMemcpyHostToDevice));
+                ++ngroups;
+            }
+            if (ngroups > 1) {
+                MSRS_HIP_CHECK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+                for (int k = 0; k < ngroups; ++k) {
+                    MSRS_HIP_CHECK(hipStreamCreateWithFlags(&c->aux[k], hipStreamNonBlocking));
+                    MSRS_HIP_CHECK(hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming));
+                }
+            }
+        }
         c->dflags = dalloc<int32_t>(*c, 4);
         c->coef_copy = dalloc<double>(*c, c->kind == kElliptic ? (int64_t)c->N * c->N : c->N);
         MSRS_HIP_CHECK(hipMemset(c->dflags, 0, 4 * sizeof(int32_t)));
@@ -605,6 +628,11 @@ void msrs_destroy(msrs_handle h) {
     (void)hipStreamSynchronize(c->stream);
     for (auto& pe : c->pending) { (void)hipEventDestroy(pe.a); (void)hipEventDestroy(pe.b); }
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    for (int k = 0; k < 8; ++k) {
+        if (c->aux[k]) (void)hipStreamDestroy(c->aux[k]);
+        if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->hflags) (void)hipHostFree(c->hflags);
     delete c;

@@ -355,14 +355,25 @@ __device__ __forceinline__ void inv16_wave(const T* A, T* Dinv, bool& bad) {
 }
 
 template <typename T, int KIND, int R>
-__device__ __noinline__ void factor_mfma_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw,
+__device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw,
                                               double dx, double inv_eps, T* __restrict__ E, T* lds, double* cf,
                                               double* crow, int32_t* flags) {
     constexpr int BP = 16 * R, LDE = BP + 1, NT = R * R, NSLOT = (NT + 7) / 8;
     constexpr int NKS = BP / 4;
     typedef typename Mfma<T>::acc Acc;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int li = lane & 15, lk = lane >> 4;
+    const int tid0 = threadIdx.x, w = tid0 >> 6;
+    // Lane-dependent indices are re-derived per block row and per panel from a
+    // laundered thread id, so their address arithmetic is not hoisted and kept
+    // live across the loops (register pressure).
+    int tid = tid0, lane = tid0 & 63, li = lane & 15, lk = lane >> 4;
+    auto launder = [&]() {
+        int t = tid0;
+        asm volatile("" : "+v"(t));
+        tid = t;
+        lane = t & 63;
+        li = lane & 15;
+        lk = lane >> 4;
+    };
     const int b = P.b, nl = P.nl, L = P.L;
     T* Es = lds;                         // E_{l-1}, BP x LDE (row-major)
     // panel buffers alias Es (free once D_l is formed)
@@ -391,6 +402,7 @@ __device__ __noinline__ void factor_mfma_body(const PatchDesc& P, const double* 
     }
 
     for (int l = 0; l < nl; ++l) {
+        launder();
         const double* rA = crow + (l & 1) * (kMaxLine + 1);          // cell row l
         const double* rB = crow + ((l + 1) & 1) * (kMaxLine + 1);    // cell row l + 1
         __syncthreads();
@@ -485,6 +497,7 @@ __device__ __noinline__ void factor_mfma_body(const PatchDesc& P, const double* 
         __syncthreads();   // Es (E_{l-1}) no longer needed: panel buffers may overwrite it
         // blocked Gauss-Jordan over the panels
         for (int pn = 0; pn < npan; ++pn) {
+            launder();
             const int buf = pn & 1;
             T* pc = Pc + buf * BP * 16;
             T* pr = Pr + buf * 16 * BP;
@@ -559,6 +572,7 @@ __device__ __noinline__ void factor_mfma_body(const PatchDesc& P, const double* 
             }
         }
         __syncthreads();   // panel buffers done: Es may be rewritten
+        launder();
         // E_l -> Es (row-major), then to global in the sweep's MFMA operand order
 #pragma unroll
         for (int q = 0; q < NSLOT; ++q) {
@@ -584,35 +598,24 @@ __device__ __noinline__ void factor_mfma_body(const PatchDesc& P, const double* 
     if (bad) raise_flag(flags, 0);
 }
 
-template <typename T, int KIND>
-__global__ __launch_bounds__(kFactorThreads) void factor_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
-                                                                const double* __restrict__ vw, double dx, double inv_eps,
-                                                                T* __restrict__ E_all, int32_t* flags) {
-    __shared__ T lds[kMaxLine * (kMaxLine + 1)];
+// One kernel per line-tile count R (each with its own register allocation);
+// plist lists the patches of this R (workgroup x -> patch plist[x]).
+template <typename T, int KIND, int R>
+__global__ __launch_bounds__(kFactorThreads) void factor_kernel(const PatchDesc* pd, const int32_t* __restrict__ plist,
+                                                                const double* __restrict__ aL_all, const double* __restrict__ vw,
+                                                                double dx, double inv_eps, T* __restrict__ E_all, int32_t* flags) {
+    // E_{l-1} (BP x (BP+1)) and, aliased, the panel buffers (6 x 16 BP + 512)
+    constexpr int BPR = 16 * R;
+    constexpr int LDS_ELEMS = BPR * (BPR + 1) > 96 * BPR + 512 ? BPR * (BPR + 1) : 96 * BPR + 512;
+    __shared__ T lds[LDS_ELEMS];
     __shared__ double cf[2 * kMaxLine];
     __shared__ double crow[2 * (kMaxLine + 1)];
-    const PatchDesc P = pd[p0 + blockIdx.x];
-    const double* aL = aL_all + P.a_off;
-    T* E = E_all + P.E_off;
-    if (KIND == kKinetic) {
-        switch (P.bp / 16) {
-            case 1: factor_mfma_body<T, KIND, 1>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
-            case 2: factor_mfma_body<T, KIND, 2>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
-            default: if (threadIdx.x == 0) raise_flag(flags, 3); break;
-        }
+    const PatchDesc P = pd[plist[blockIdx.x]];
+    if (P.bp != 16 * R) {
+        if (threadIdx.x == 0) raise_flag(flags, 3);
         return;
     }
-    switch (P.bp / 16) {
-        case 1: factor_mfma_body<T, KIND, 1>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
-        case 2: factor_mfma_body<T, KIND, 2>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
-        case 3: factor_mfma_body<T, KIND, 3>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
-        case 4: factor_mfma_body<T, KIND, 4>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
-        case 5: factor_mfma_body<T, KIND, 5>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
-        case 6: factor_mfma_body<T, KIND, 6>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
-        case 7: factor_mfma_body<T, KIND, 7>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
-        case 8: factor_mfma_body<T, KIND, 8>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, flags); break;
-        default: if (threadIdx.x == 0) raise_flag(flags, 3); break;
-    }
+    factor_mfma_body<T, KIND, R>(P, aL_all + P.a_off, vw, dx, inv_eps, E_all + P.E_off, lds, cf, crow, flags);
 }
 
 // ------------------------------------------------------------ sweeps (a5)
@@ -1036,16 +1039,63 @@ void launch_lift(Ctx& c, int p0, int p1) {
                        (double*)nullptr, (int32_t*)nullptr, 0, 0.0);
 }
 
-void launch_factor(Ctx& c, int p0, int p1) {
-    StageTimer t(c, MSRS_K_FACTOR);
+template <typename T, int KIND>
+static void launch_factor_r(Ctx& c, int R, hipStream_t st, const int32_t* plist, int n) {
     const double inv_eps = 1.0 / c.eps;
+    const dim3 grid(n), blk(kFactorThreads);
+    T* E = (T*)c.E;
+#define MSRS_FACTOR(RR) hipLaunchKernelGGL((factor_kernel<T, KIND, RR>), grid, blk, 0, st, c.dp, plist, c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags)
+    switch (R) {
+        case 1: MSRS_FACTOR(1); break;
+        case 2: MSRS_FACTOR(2); break;
+        case 3: if constexpr (KIND == kElliptic) MSRS_FACTOR(3); break;
+        case 4: if constexpr (KIND == kElliptic) MSRS_FACTOR(4); break;
+        case 5: if constexpr (KIND == kElliptic) MSRS_FACTOR(5); break;
+        case 6: if constexpr (KIND == kElliptic) MSRS_FACTOR(6); break;
+        case 7: if constexpr (KIND == kElliptic) MSRS_FACTOR(7); break;
+        case 8: if constexpr (KIND == kElliptic) MSRS_FACTOR(8); break;
+        default: break;
+    }
+#undef MSRS_FACTOR
+}
+
+static void launch_factor_group(Ctx& c, int R, hipStream_t st, const int32_t* plist, int n) {
     const bool ir = c.prec == MSRS_PREC_FP32_IR;
     if (c.kind == kElliptic) {
-        if (ir) hipLaunchKernelGGL((factor_kernel<float, kElliptic>), dim3(p1 - p0), dim3(kFactorThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (float*)c.E, c.dflags);
-        else hipLaunchKernelGGL((factor_kernel<double, kElliptic>), dim3(p1 - p0), dim3(kFactorThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (double*)c.E, c.dflags);
+        if (ir) launch_factor_r<float, kElliptic>(c, R, st, plist, n);
+        else launch_factor_r<double, kElliptic>(c, R, st, plist, n);
     } else {
-        if (ir) hipLaunchKernelGGL((factor_kernel<float, kKinetic>), dim3(p1 - p0), dim3(kFactorThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (float*)c.E, c.dflags);
-        else hipLaunchKernelGGL((factor_kernel<double, kKinetic>), dim3(p1 - p0), dim3(kFactorThreads), 0, c.stream, c.dp, p0, c.aL, c.vw, dx_of(c), inv_eps, (double*)c.E, c.dflags);
+        if (ir) launch_factor_r<float, kKinetic>(c, R, st, plist, n);
+        else launch_factor_r<double, kKinetic>(c, R, st, plist, n);
+    }
+}
+
+// Patches are grouped by line-tile count R; each group runs its own kernel.
+// A single patch (reference mode) launches on the handle's stream; a batch
+// forks one stream per group from the handle's stream and joins back.
+void launch_factor(Ctx& c, int p0, int p1) {
+    StageTimer t(c, MSRS_K_FACTOR);
+    if (p1 - p0 == 1) {
+        launch_factor_group(c, c.hp[p0].bp / 16, c.stream, c.pid + p0, 1);
+        return;
+    }
+    int ng = 0;
+    for (int g = 0; g < 9; ++g) ng += c.rgroup_n[g] > 0;
+    if (ng <= 1) {
+        for (int g = 0; g < 9; ++g)
+            if (c.rgroup_n[g]) launch_factor_group(c, g, c.stream, c.rgroup[g], c.rgroup_n[g]);
+        return;
+    }
+    MSRS_HIP_CHECK(hipEventRecord(c.ev_fork, c.stream));
+    int k = 0;
+    for (int g = 0; g < 9; ++g) {
+        if (!c.rgroup_n[g]) continue;
+        hipStream_t st = c.aux[k];
+        MSRS_HIP_CHECK(hipStreamWaitEvent(st, c.ev_fork, 0));
+        launch_factor_group(c, g, st, c.rgroup[g], c.rgroup_n[g]);
+        MSRS_HIP_CHECK(hipEventRecord(c.ev_join[k], st));
+        MSRS_HIP_CHECK(hipStreamWaitEvent(c.stream, c.ev_join[k], 0));
+        ++k;
     }
 }
 

@@ -99,6 +99,11 @@ struct Ctx {
     double* coef_copy = nullptr;  // device copy of the coefficient field (traces)
     int32_t* iters = nullptr;     // per patch refinement iterations at convergence
     double* part = nullptr;       // per (patch, line chunk) partial column sums, 64 each
+    int32_t* pid = nullptr;       // 0..n_patches-1 (single-patch launches)
+    int32_t* rgroup[9] = {};      // patches with line-tile count R (device lists)
+    int rgroup_n[9] = {};
+    hipStream_t aux[8] = {};      // fork streams of the per-R factor kernels
+    hipEvent_t ev_fork = nullptr, ev_join[8] = {};
     int maxch = 1;                // line chunks per patch at most
 
     int64_t omega_total = 0, Y_total = 0, Q_total = 0, sv_total = 0;
