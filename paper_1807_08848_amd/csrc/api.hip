@@ -295,6 +295,11 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->Y = dalloc<double>(*c, c->Y_total);
         c->Q = dalloc<double>(*c, c->Q_total);
         c->rf_ws = dalloc<double>(*c, c->Q_total);
+        for (auto& P : c->hp) c->rf_maxrc = std::max(c->rf_maxrc, (P.nrows + 511) / 512);
+        c->rf_part = dalloc<double>(*c, (int64_t)c->n_patches * c->rf_maxrc * 4096);
+        c->rf_small = dalloc<double>(*c, (int64_t)c->n_patches * 4096);
+        c->rf_pval = dalloc<double>(*c, (int64_t)c->n_patches * c->rf_maxrc * 64);
+        c->rf_pidx = dalloc<int32_t>(*c, (int64_t)c->n_patches * c->rf_maxrc * 64);
         c->sv = dalloc<double>(*c, c->sv_total);
         int64_t rn_total = 0;
         for (auto& P : c->hp) rn_total += 2 * P.sp;

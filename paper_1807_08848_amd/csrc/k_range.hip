@@ -1,53 +1,56 @@
 // Range finder of the snapshots (stage a8): the QR at the end of
 // RanLocalSolu and the randomized range finder of Section 2.3, in FP64.
 //
-// Per patch (one workgroup): G = Y^T Y; cyclic Jacobi eigendecomposition
-// G = V diag(lambda) V^T (so sigma_j(Y) = sqrt(lambda_j), left singular
-// vectors Y V_j / sigma_j); the k leading ones are formed and then
-// re-orthonormalised by two Cholesky-QR passes (G' = Q^T Q = R^T R,
-// Q <- Q R^{-1}, twice).  This handles rank-deficient sketches (more
-// samples than boundary degrees of freedom) with the same code path.  Each
-// column's largest-magnitude entry is made positive (first index on ties).
+// Per patch: G = Y^T Y; cyclic Jacobi eigendecomposition G = V diag(lambda)
+// V^T, so sigma_j(Y) = sqrt(lambda_j) and Y V_j / sigma_j are the left
+// singular vectors; the k leading ones are formed and re-orthonormalised by
+// two Cholesky-QR passes (G' = W^T W = L L^T, Q = W L^{-T}, twice).  This
+// handles rank-deficient sketches (more samples than boundary degrees of
+// freedom) with the same code path.  Each column's largest-magnitude entry is
+// made positive (first index on ties).
+//
+// Tall work (Gram matrices, products with the small s x k / k x k factors,
+// the column argmax) runs over (patch, chunk of kRowChunk rows) workgroups with
+// per-chunk partials reduced per patch in a fixed order; the small dense
+// work (Jacobi, Cholesky) runs one workgroup per patch.
 #include "device_common.h"
 
 namespace msrs {
 
-constexpr int kRfMax = 64;     // max columns
-constexpr int kRfChunk = 32;   // rows staged per Gram step
+constexpr int kRfMax = 64;          // max columns
+constexpr int kRfStage = 32;        // rows staged in LDS per Gram step
+constexpr int kRowChunk = 512;      // rows per workgroup of the tall kernels
+constexpr int kSmall = kRfMax * kRfMax;
 
-// G (ld kRfMax, LDS) = A^T A for A column-major (lda rows), ncols <= 16 TS.
-// Thread (ty, tx) accumulates the TS x TS block of entries (ty + 16 r, tx + 16 c).
+// columns and base of the tall matrix a kernel works on
+struct Tall {
+    const double* base;
+    int ncols;
+};
+enum Which { kY = 0, kQ = 1, kW = 2 };
+
+__device__ __forceinline__ Tall tall_of(const PatchDesc& P, int which, const double* Y, const double* Q, const double* W) {
+    if (which == kY) return Tall{Y + P.Y_off, P.s};
+    return Tall{(which == kQ ? Q : W) + P.Q_off, P.ncols};
+}
+
+// ---------------------------------------------------------------- Gram partials
 template <int TS>
-__device__ void gram_tile(const double* __restrict__ A, int nrows, int lda, int ncols, double* G, double* stage) {
-    // chunk elements per thread: kRfChunk * ncols <= 32 * 64 = 8 * kThreads
-    constexpr int EPT = kRfChunk * kRfMax / kThreads;
+__device__ void gram_rows(const double* __restrict__ A, int nrows, int r0, int r1, int ncols, double* stage, double* out) {
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
     double acc[TS][TS];
 #pragma unroll
     for (int r = 0; r < TS; ++r)
 #pragma unroll
         for (int c = 0; c < TS; ++c) acc[r][c] = 0.0;
-    const int n = kRfChunk * ncols;
-    double pre[EPT];
-    auto fetch = [&](int r0) {
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int o = tid + e * kThreads;
-            const int col = o / kRfChunk, row = o - col * kRfChunk;
-            pre[e] = (o < n && r0 + row < nrows) ? A[(int64_t)col * lda + r0 + row] : 0.0;
-        }
-    };
-    fetch(0);
-    for (int r0 = 0; r0 < nrows; r0 += kRfChunk) {
+    for (int q0 = r0; q0 < r1; q0 += kRfStage) {
+        const int nr = min(kRfStage, r1 - q0);
         __syncthreads();
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int o = tid + e * kThreads;
-            if (o < n) stage[(o % kRfChunk) * kRfMax + o / kRfChunk] = pre[e];
+        for (int o = tid; o < kRfStage * ncols; o += kThreads) {
+            const int col = o / kRfStage, row = o - col * kRfStage;
+            stage[row * kRfMax + col] = row < nr ? A[(int64_t)col * nrows + q0 + row] : 0.0;
         }
         __syncthreads();
-        if (r0 + kRfChunk < nrows) fetch(r0 + kRfChunk);   // next chunk in flight during this one
-        const int nr = min(kRfChunk, nrows - r0);
         for (int row = 0; row < nr; ++row) {
             double a[TS], b[TS];
 #pragma unroll
@@ -60,130 +63,77 @@ __device__ void gram_tile(const double* __restrict__ A, int nrows, int lda, int 
                 for (int c = 0; c < TS; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
         }
     }
-    __syncthreads();
 #pragma unroll
     for (int r = 0; r < TS; ++r)
 #pragma unroll
         for (int c = 0; c < TS; ++c) {
             const int i = ty + 16 * r, j = tx + 16 * c;
-            if (i < ncols && j < ncols) G[i * kRfMax + j] = acc[r][c];
+            if (i < ncols && j < ncols) out[i * kRfMax + j] = acc[r][c];
         }
-    __syncthreads();
 }
 
-__device__ void gram_lds(const double* __restrict__ A, int nrows, int lda, int ncols, double* G, double* stage) {
-    if (ncols <= 16) gram_tile<1>(A, nrows, lda, ncols, G, stage);
-    else if (ncols <= 32) gram_tile<2>(A, nrows, lda, ncols, G, stage);
-    else if (ncols <= 48) gram_tile<3>(A, nrows, lda, ncols, G, stage);
-    else gram_tile<4>(A, nrows, lda, ncols, G, stage);
+// grid (patch, row chunk): partial Gram of the chunk's rows -> part[(p * maxrc + chunk) * 4096]
+__global__ __launch_bounds__(kThreads) void gram_partial_kernel(const PatchDesc* pd, int p0, int which, const double* __restrict__ Y,
+                                                                const double* __restrict__ Q, const double* __restrict__ W,
+                                                                double* __restrict__ part, int maxrc) {
+    __shared__ double stage[kRfStage * kRfMax];
+    const int p = p0 + blockIdx.x;
+    const PatchDesc P = pd[p];
+    const int r0 = blockIdx.y * kRowChunk;
+    if (r0 >= P.nrows) return;
+    const int r1 = min(P.nrows, r0 + kRowChunk);
+    const Tall T = tall_of(P, which, Y, Q, W);
+    double* out = part + ((int64_t)p * maxrc + blockIdx.y) * kSmall;
+    if (T.ncols <= 16) gram_rows<1>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
+    else if (T.ncols <= 32) gram_rows<2>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
+    else if (T.ncols <= 48) gram_rows<3>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
+    else gram_rows<4>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
 }
 
-// Cholesky of the n x n SPD matrix G (LDS, ld kRfMax) in place (lower).
-// Returns false (uniformly) on a non-positive pivot.
-__device__ bool chol_lds(double* G, int n, int* okflag) {
-    const int tid = threadIdx.x;
-    if (tid == 0) *okflag = 1;
-    __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        if (tid == 0) {
-            const double d = G[j * kRfMax + j];
-            if (!(d > 0.0) || !isfinite(d)) *okflag = 0;
-            G[j * kRfMax + j] = d > 0.0 ? sqrt(d) : 1.0;
-        }
-        __syncthreads();
-        const double ljj = G[j * kRfMax + j];
-        for (int i = j + 1 + tid; i < n; i += kThreads) G[i * kRfMax + j] /= ljj;
-        __syncthreads();
-        const int m = n - j - 1;
-        for (int o = tid; o < m * m; o += kThreads) {
-            const int a = j + 1 + o / m, b = j + 1 + o % m;
-            if (b <= a) G[a * kRfMax + b] -= G[a * kRfMax + j] * G[b * kRfMax + j];
-        }
-        __syncthreads();
-    }
-    const bool ok = *okflag != 0;
-    __syncthreads();
-    return ok;
-}
-
-// T (ld kRfMax) = L^{-T} for the lower Cholesky factor L (n x n, LDS): thread
-// j forms column j of L^{-1} by forward substitution; T[i][j] = L^{-1}[j][i].
-__device__ void inv_transpose_lds(const double* L, int n, double* T) {
-    const int j = threadIdx.x;
-    if (j < n) {
-        for (int i = 0; i < n; ++i) {
-            double v = (i == j) ? 1.0 : 0.0;
-            for (int c = j; c < i; ++c) v -= L[i * kRfMax + c] * T[j * kRfMax + c];
-            T[j * kRfMax + i] = (i < j) ? 0.0 : v / L[i * kRfMax + i];
-        }
+// sum of the chunk partials of patch p into G (LDS, ld kRfMax), fixed order
+__device__ void sum_partials(const double* __restrict__ part, int p, int maxrc, int nch, int n, double* G) {
+    for (int o = threadIdx.x; o < n * n; o += kThreads) {
+        const int i = o / n, j = o % n;
+        double s = 0.0;
+        for (int ch = 0; ch < nch; ++ch) s += part[((int64_t)p * maxrc + ch) * kSmall + i * kRfMax + j];
+        G[i * kRfMax + j] = s;
     }
     __syncthreads();
 }
 
-// out (nrows x k, column-major) = A (nrows x m, column-major) * B (m x k, LDS ld kRfMax).
-// A thread owns one row and a block of 8 columns, so each A element is read
-// once per 8 outputs (coalesced across threads); B is broadcast from LDS.
-__device__ void gemm_rows(const double* __restrict__ A, int nrows, int m, const double* B, int k, double* __restrict__ out) {
-    constexpr int CB = 8;
-    const int nblk = (k + CB - 1) / CB;
-    for (int o = threadIdx.x; o < nrows * nblk; o += kThreads) {
-        const int jb = o / nrows, r = o - jb * nrows;
-        const int j0 = jb * CB;
-        double acc[CB];
-#pragma unroll
-        for (int c = 0; c < CB; ++c) acc[c] = 0.0;
-#pragma unroll 8
-        for (int i = 0; i < m; ++i) {
-            const double a = A[(int64_t)i * nrows + r];
-#pragma unroll
-            for (int c = 0; c < CB; ++c) acc[c] = fma(a, B[i * kRfMax + min(j0 + c, kRfMax - 1)], acc[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < CB; ++c)
-            if (j0 + c < k) out[(int64_t)(j0 + c) * nrows + r] = acc[c];
-    }
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(kThreads) void range_kernel(const PatchDesc* pd, int p0, const double* __restrict__ Y_all,
-                                                         double* __restrict__ Q_all, double* __restrict__ ws_all,
-                                                         double* __restrict__ sv_all, double* __restrict__ gap, int32_t* flags) {
-    __shared__ double G[kRfMax * kRfMax];
-    __shared__ double V[kRfMax * kRfMax];
-    __shared__ double stage[kRfChunk * kRfMax];
+// ---------------------------------------------------------------- eigendecomposition
+// One workgroup per patch: G = sum of partials, cyclic Jacobi (round-robin
+// pairs, two-sided updates on 2x2 blocks), eigenvalues sorted descending,
+// singular values, relative gap, and B = V[:, :k] / sigma -> small[p] (s x k).
+__global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int p0, const double* __restrict__ part, int maxrc,
+                                                       double* __restrict__ small, double* __restrict__ sv_all,
+                                                       double* __restrict__ gap, int32_t* flags) {
+    __shared__ double G[kSmall];
+    __shared__ double V[kSmall];
     __shared__ double cs[kRfMax / 2], sn[kRfMax / 2];
     __shared__ int pu[kRfMax / 2], pv[kRfMax / 2];
     __shared__ int perm[kRfMax];
     __shared__ double lam[kRfMax];
-    __shared__ int okflag;
-    __shared__ double red_v[kThreads];
-    __shared__ int red_i[kThreads];
+    __shared__ double red[kThreads];
     __shared__ double offn;
-
     const int p = p0 + blockIdx.x;
     const PatchDesc P = pd[p];
     const int tid = threadIdx.x;
-    const int s = P.s, nrows = P.nrows;
-    const int k = P.ncols;
-    const double* Y = Y_all + P.Y_off;
-    double* Q = Q_all + P.Q_off;
-    double* W = ws_all + P.Q_off;   // workspace of the same shape as Q
-
-    // 1. Gram matrix
-    gram_lds(Y, nrows, nrows, s, G, stage);
-    // 2. cyclic Jacobi with round-robin pairs, n even
-    const int n = s + (s & 1);
-    for (int o = tid; o < kRfMax * kRfMax; o += kThreads) {
-        const int i = o / kRfMax, j = o % kRfMax;
-        V[o] = (i == j) ? 1.0 : 0.0;
-        if (i >= s || j >= s) G[o] = 0.0;
+    const int s = P.s, k = P.ncols;
+    const int nch = (P.nrows + kRowChunk - 1) / kRowChunk;
+    for (int o = tid; o < kSmall; o += kThreads) {
+        G[o] = 0.0;
+        V[o] = (o / kRfMax == o % kRfMax) ? 1.0 : 0.0;
     }
     __syncthreads();
+    sum_partials(part, p, maxrc, nch, s, G);
+    const int n = s + (s & 1);
     double fro = 0.0;
     for (int o = 0; o < s; ++o) fro += G[o * kRfMax + o] * G[o * kRfMax + o];
+    const int np2 = n / 2;
     for (int sweep = 0; sweep < 30; ++sweep) {
         for (int st = 0; st < n - 1; ++st) {
-            if (tid < n / 2) {
+            if (tid < np2) {
                 const int i = tid;
                 const int u = (i == 0) ? 0 : ((i - 1 + st) % (n - 1)) + 1;
                 const int v = ((n - 2 - i + st) % (n - 1)) + 1;
@@ -201,19 +151,15 @@ __global__ __launch_bounds__(kThreads) void range_kernel(const PatchDesc* pd, in
                 sn[i] = t * c;
             }
             __syncthreads();
-            // G <- J^T G J on 2x2 blocks (pairs i, i2): rows rotate by pair i,
-            // columns by pair i2; V <- V J on (row j, pair i)
-            const int np2 = n / 2;
+            // G <- J^T G J on 2x2 blocks (rows by pair i, columns by pair i2); V <- V J
             for (int o = tid; o < np2 * np2; o += kThreads) {
                 const int i = o / np2, i2 = o % np2;
                 const int a = pu[i], b = pv[i], a2 = pu[i2], b2 = pv[i2];
                 const double c = cs[i], sv = sn[i], c2 = cs[i2], s2 = sn[i2];
                 const double g00 = G[a * kRfMax + a2], g01 = G[a * kRfMax + b2];
                 const double g10 = G[b * kRfMax + a2], g11 = G[b * kRfMax + b2];
-                // rows
                 const double r00 = c * g00 - sv * g10, r01 = c * g01 - sv * g11;
                 const double r10 = sv * g00 + c * g10, r11 = sv * g01 + c * g11;
-                // columns
                 G[a * kRfMax + a2] = c2 * r00 - s2 * r01;
                 G[a * kRfMax + b2] = s2 * r00 + c2 * r01;
                 G[b * kRfMax + a2] = c2 * r10 - s2 * r11;
@@ -229,23 +175,21 @@ __global__ __launch_bounds__(kThreads) void range_kernel(const PatchDesc* pd, in
             }
             __syncthreads();
         }
-        // off-diagonal norm
         double loc = 0.0;
         for (int o = tid; o < s * s; o += kThreads) {
             const int i = o / s, j = o % s;
             if (i != j) loc += G[i * kRfMax + j] * G[i * kRfMax + j];
         }
-        red_v[tid] = loc;
+        red[tid] = loc;
         __syncthreads();
         for (int w = kThreads / 2; w > 0; w >>= 1) {
-            if (tid < w) red_v[tid] += red_v[tid + w];
+            if (tid < w) red[tid] += red[tid + w];
             __syncthreads();
         }
-        if (tid == 0) offn = red_v[0];
+        if (tid == 0) offn = red[0];
         __syncthreads();
         if (offn <= 1e-32 * fro) break;
     }
-    // 3. sort eigenvalues descending (stable selection on thread 0)
     if (tid == 0) {
         for (int i = 0; i < s; ++i) { perm[i] = i; lam[i] = G[i * kRfMax + i]; }
         for (int i = 0; i < s; ++i) {
@@ -256,61 +200,205 @@ __global__ __launch_bounds__(kThreads) void range_kernel(const PatchDesc* pd, in
         }
         double* svp = sv_all + P.sv_off;
         for (int i = 0; i < s; ++i) svp[i] = sqrt(fmax(lam[perm[i]], 0.0));
-        const double s1 = svp[0];
-        const double sk = svp[k - 1];
+        const double s1 = svp[0], sk = svp[k - 1];
         if (!(sk > 1e-13 * s1)) raise_flag(flags, 2);
         gap[p] = (k < s) ? (sk - svp[k]) / s1 : 1.0;
     }
     __syncthreads();
-    // 4. B = V[:, perm[:k]] / sigma (s x k, in G, free after the sort); W = Y B
-    for (int o = tid; o < s * k; o += kThreads) {
-        const int i = o / k, j = o % k;
-        const double sg = sqrt(fmax(lam[perm[j]], 0.0));
-        G[i * kRfMax + j] = sg > 0 ? V[i * kRfMax + perm[j]] / sg : 0.0;
+    double* B = small + (int64_t)p * kSmall;
+    for (int o = tid; o < kSmall; o += kThreads) {
+        const int i = o / kRfMax, j = o % kRfMax;
+        double v = 0.0;
+        if (i < s && j < k) {
+            const double sg = sqrt(fmax(lam[perm[j]], 0.0));
+            v = sg > 0 ? V[i * kRfMax + perm[j]] / sg : 0.0;
+        }
+        B[o] = v;
     }
+}
+
+// ---------------------------------------------------------------- Cholesky factor
+// One workgroup per patch: G' = sum of partials (k x k), G' = L L^T,
+// T = L^{-T} -> small[p].  A non-positive pivot latches ERR_RANK.
+__global__ __launch_bounds__(kThreads) void chol_kernel(const PatchDesc* pd, int p0, const double* __restrict__ part, int maxrc,
+                                                        double* __restrict__ small, int32_t* flags) {
+    __shared__ double G[kSmall];
+    __shared__ int bad;
+    const int p = p0 + blockIdx.x;
+    const PatchDesc P = pd[p];
+    const int tid = threadIdx.x, n = P.ncols;
+    const int nch = (P.nrows + kRowChunk - 1) / kRowChunk;
+    if (tid == 0) bad = 0;
+    sum_partials(part, p, maxrc, nch, n, G);
+    for (int j = 0; j < n; ++j) {
+        if (tid == 0) {
+            const double d = G[j * kRfMax + j];
+            if (!(d > 0.0) || !isfinite(d)) bad = 1;
+            G[j * kRfMax + j] = d > 0.0 ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        const double ljj = G[j * kRfMax + j];
+        for (int i = j + 1 + tid; i < n; i += kThreads) G[i * kRfMax + j] /= ljj;
+        __syncthreads();
+        const int m = n - j - 1;
+        for (int o = tid; o < m * m; o += kThreads) {
+            const int a = j + 1 + o / m, b = j + 1 + o % m;
+            if (b <= a) G[a * kRfMax + b] -= G[a * kRfMax + j] * G[b * kRfMax + j];
+        }
+        __syncthreads();
+    }
+    // column c of L^{-1} by forward substitution (thread c); T[i][c] ... stored as T[c][i] = L^{-1}[i][c]
+    double* T = small + (int64_t)p * kSmall;
+    if (tid < kRfMax) {
+        const int c = tid;
+        for (int i = 0; i < kRfMax; ++i) {
+            double v = 0.0;
+            if (c < n && i < n && i >= c) {
+                v = (i == c) ? 1.0 : 0.0;
+                for (int q = c; q < i; ++q) v -= G[i * kRfMax + q] * T[c * kRfMax + q];
+                v /= G[i * kRfMax + i];
+            }
+            T[c * kRfMax + i] = v;
+        }
+    }
+    if (tid == 0 && bad) raise_flag(flags, 2);
+}
+
+// ---------------------------------------------------------------- tall products
+// grid (patch, row chunk): dst = src * small[p] (m x k), src / dst tall
+// matrices of the patch; a thread owns one row and 8 columns.
+__global__ __launch_bounds__(kThreads) void tall_gemm_kernel(const PatchDesc* pd, int p0, int src_which, int dst_which,
+                                                             const double* __restrict__ Y, double* __restrict__ Q,
+                                                             double* __restrict__ W, const double* __restrict__ small) {
+    __shared__ double B[kSmall];
+    const int p = p0 + blockIdx.x;
+    const PatchDesc P = pd[p];
+    const int r0 = blockIdx.y * kRowChunk;
+    if (r0 >= P.nrows) return;
+    const int r1 = min(P.nrows, r0 + kRowChunk);
+    const Tall S = tall_of(P, src_which, Y, Q, W);
+    double* D = (dst_which == kQ ? Q : W) + P.Q_off;
+    const int m = S.ncols, k = P.ncols, nrows = P.nrows;
+    for (int o = threadIdx.x; o < kSmall; o += kThreads) B[o] = small[(int64_t)p * kSmall + o];
     __syncthreads();
-    gemm_rows(Y, nrows, s, G, k, W);
-    // 5. two Cholesky-QR passes on the k columns: W -> Q -> W
-    for (int pass = 0; pass < 2; ++pass) {
-        const double* src = pass == 0 ? W : Q;
-        double* dst = pass == 0 ? Q : W;
-        gram_lds(src, nrows, nrows, k, G, stage);
-        if (!chol_lds(G, k, &okflag)) {
-            if (tid == 0) raise_flag(flags, 2);
-            return;
+    constexpr int CB = 8;
+    const int nblk = (k + CB - 1) / CB, nr = r1 - r0;
+    for (int o = threadIdx.x; o < nr * nblk; o += kThreads) {
+        const int jb = o / nr, r = r0 + (o - jb * nr);
+        const int j0 = jb * CB;
+        double acc[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[c] = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < m; ++i) {
+            const double a = S.base[(int64_t)i * nrows + r];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) acc[c] = fma(a, B[i * kRfMax + min(j0 + c, kRfMax - 1)], acc[c]);
         }
-        inv_transpose_lds(G, k, V);
-        gemm_rows(src, nrows, k, V, k, dst);
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            if (j0 + c < k) D[(int64_t)(j0 + c) * nrows + r] = acc[c];
     }
-    // 6. sign fix (largest |entry| of each column positive, lowest index on ties), W -> Q
-    for (int j = 0; j < k; ++j) {
+}
+
+// ---------------------------------------------------------------- sign fix
+// grid (patch, row chunk): per column, the largest |W| of the chunk and its
+// first row -> parts (value, index).
+__global__ __launch_bounds__(kThreads) void sign_partial_kernel(const PatchDesc* pd, int p0, const double* __restrict__ W,
+                                                                double* __restrict__ pval, int32_t* __restrict__ pidx, int maxrc) {
+    __shared__ double rv[kThreads];
+    __shared__ int ri[kThreads];
+    const int p = p0 + blockIdx.x;
+    const PatchDesc P = pd[p];
+    const int r0 = blockIdx.y * kRowChunk;
+    if (r0 >= P.nrows) return;
+    const int r1 = min(P.nrows, r0 + kRowChunk);
+    const double* A = W + P.Q_off;
+    const int tid = threadIdx.x;
+    for (int j = 0; j < P.ncols; ++j) {
         double bv = -1.0;
-        int bi = 0;
-        for (int row = tid; row < nrows; row += kThreads) {
-            const double a = fabs(W[(int64_t)j * nrows + row]);
-            if (a > bv || (a == bv && row < bi)) { bv = a; bi = row; }
+        int bi = r0;
+        for (int r = r0 + tid; r < r1; r += kThreads) {
+            const double a = fabs(A[(int64_t)j * P.nrows + r]);
+            if (a > bv) { bv = a; bi = r; }
         }
-        red_v[tid] = bv;
-        red_i[tid] = bi;
+        rv[tid] = bv;
+        ri[tid] = bi;
         __syncthreads();
         for (int w = kThreads / 2; w > 0; w >>= 1) {
             if (tid < w) {
-                const double ov = red_v[tid + w];
-                const int oi = red_i[tid + w];
-                if (ov > red_v[tid] || (ov == red_v[tid] && oi < red_i[tid])) { red_v[tid] = ov; red_i[tid] = oi; }
+                const double ov = rv[tid + w];
+                const int oi = ri[tid + w];
+                if (ov > rv[tid] || (ov == rv[tid] && oi < ri[tid])) { rv[tid] = ov; ri[tid] = oi; }
             }
             __syncthreads();
         }
-        const int at = min(max(red_i[0], 0), nrows - 1);
-        const double sg = W[(int64_t)j * nrows + at] < 0.0 ? -1.0 : 1.0;
+        if (tid == 0) {
+            pval[((int64_t)p * maxrc + blockIdx.y) * kRfMax + j] = rv[0];
+            pidx[((int64_t)p * maxrc + blockIdx.y) * kRfMax + j] = ri[0];
+        }
         __syncthreads();
-        for (int row = tid; row < nrows; row += kThreads) Q[(int64_t)j * nrows + row] = sg * W[(int64_t)j * nrows + row];
+    }
+}
+
+// one workgroup per patch: combine the chunk maxima (first index on ties) -> sign per column in small[p][0..k)
+__global__ __launch_bounds__(kRfMax) void sign_final_kernel(const PatchDesc* pd, int p0, const double* __restrict__ W,
+                                                           const double* __restrict__ pval, const int32_t* __restrict__ pidx,
+                                                           int maxrc, double* __restrict__ small) {
+    const int p = p0 + blockIdx.x;
+    const PatchDesc P = pd[p];
+    const int j = threadIdx.x;
+    if (j >= P.ncols) return;
+    const int nch = (P.nrows + kRowChunk - 1) / kRowChunk;
+    double bv = -1.0;
+    int bi = 0;
+    for (int ch = 0; ch < nch; ++ch) {
+        const double v = pval[((int64_t)p * maxrc + ch) * kRfMax + j];
+        const int i = pidx[((int64_t)p * maxrc + ch) * kRfMax + j];
+        if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
+    }
+    bi = min(max(bi, 0), P.nrows - 1);
+    small[(int64_t)p * kSmall + j] = W[P.Q_off + (int64_t)j * P.nrows + bi] < 0.0 ? -1.0 : 1.0;
+}
+
+// grid (patch, row chunk): Q = W * sign(column)
+__global__ __launch_bounds__(kThreads) void sign_apply_kernel(const PatchDesc* pd, int p0, const double* __restrict__ W,
+                                                              double* __restrict__ Q, const double* __restrict__ small) {
+    const int p = p0 + blockIdx.x;
+    const PatchDesc P = pd[p];
+    const int r0 = blockIdx.y * kRowChunk;
+    if (r0 >= P.nrows) return;
+    const int r1 = min(P.nrows, r0 + kRowChunk), nr = r1 - r0;
+    for (int o = threadIdx.x; o < nr * P.ncols; o += kThreads) {
+        const int j = o / nr, r = r0 + (o - j * nr);
+        const int64_t idx = P.Q_off + (int64_t)j * P.nrows + r;
+        Q[idx] = small[(int64_t)p * kSmall + j] * W[idx];
     }
 }
 
 void launch_range(Ctx& c, int p0, int p1) {
     StageTimer t(c, MSRS_K_RANGE);
-    hipLaunchKernelGGL(range_kernel, dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.Y, c.Q, c.rf_ws, c.sv, c.gap, c.dflags);
+    int maxrows = 0;
+    for (int p = p0; p < p1; ++p) maxrows = std::max(maxrows, c.hp[p].nrows);
+    const int np = p1 - p0;
+    const dim3 tall(np, (maxrows + kRowChunk - 1) / kRowChunk), one(np);
+    const int mrc = c.rf_maxrc;
+    hipStream_t st = c.stream;
+    // snapshots: Gram, eigendecomposition, W = Y B
+    hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kY, c.Y, c.Q, c.rf_ws, c.rf_part, mrc);
+    hipLaunchKernelGGL(eig_kernel, one, dim3(kThreads), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap, c.dflags);
+    hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kY, (int)kW, c.Y, c.Q, c.rf_ws, c.rf_small);
+    // two Cholesky-QR passes: W -> Q -> W
+    for (int pass = 0; pass < 2; ++pass) {
+        const int src = pass == 0 ? kW : kQ, dst = pass == 0 ? kQ : kW;
+        hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, src, c.Y, c.Q, c.rf_ws, c.rf_part, mrc);
+        hipLaunchKernelGGL(chol_kernel, one, dim3(kThreads), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.dflags);
+        hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, src, dst, c.Y, c.Q, c.rf_ws, c.rf_small);
+    }
+    // sign fix: W -> Q
+    hipLaunchKernelGGL(sign_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, c.rf_ws, c.rf_pval, c.rf_pidx, mrc);
+    hipLaunchKernelGGL(sign_final_kernel, one, dim3(kRfMax), 0, st, c.dp, p0, c.rf_ws, c.rf_pval, c.rf_pidx, mrc, c.rf_small);
+    hipLaunchKernelGGL(sign_apply_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, c.rf_ws, c.Q, c.rf_small);
 }
 
 }  // namespace msrs

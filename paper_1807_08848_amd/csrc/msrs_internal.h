@@ -95,7 +95,12 @@ struct Ctx {
     int32_t* dflags = nullptr;    // device error flags [0]=NOT_SPD [1]=NOCONV [2]=RANK [3]=nonfinite
     int32_t* hflags = nullptr;    // pinned host mirror
     double* vw = nullptr;         // kinetic ordinates and weights (2 nv)
-    double* rf_ws = nullptr;      // range finder workspace
+    double* rf_ws = nullptr;      // range finder workspace (shape of Q)
+    double* rf_part = nullptr;    // per (patch, row chunk) partial Gram matrices, 64 x 64 each
+    double* rf_small = nullptr;   // per patch 64 x 64 factor (B, L^{-T}, signs)
+    double* rf_pval = nullptr;    // per (patch, row chunk) column maxima
+    int32_t* rf_pidx = nullptr;
+    int rf_maxrc = 1;             // row chunks per patch at most
     double* coef_copy = nullptr;  // device copy of the coefficient field (traces)
     int32_t* iters = nullptr;     // per patch refinement iterations at convergence
     double* part = nullptr;       // per (patch, line chunk) partial column sums, 64 each
