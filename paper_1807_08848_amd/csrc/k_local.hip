@@ -959,18 +959,22 @@ __global__ __launch_bounds__(64) void norms_kernel(const PatchDesc* pd, int p0, 
 }
 
 // ------------------------------------------------------------ restriction (a7)
-// grid-stride over (patch in [p0,p1), row, sample); Y column-major.
+// grid (patch, chunk of kRestrictChunk outputs); Y column-major.
+constexpr int kRestrictChunk = 4096;
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void restrict_kernel(const PatchDesc* pd, int p0, const double* __restrict__ x64_all,
                                                             const double* __restrict__ om, const double* __restrict__ vw,
                                                             double* __restrict__ Y_all) {
     const PatchDesc P = pd[p0 + blockIdx.x];
     const int n = P.nrows * P.s;
+    const int o0 = blockIdx.y * kRestrictChunk;
+    if (o0 >= n) return;
+    const int o1 = min(n, o0 + kRestrictChunk);
     const double* X = x64_all + P.x_off;
     const double* O = om + P.om_off;
     double* Y = Y_all + P.Y_off;
     const int64_t lstride = (int64_t)P.bp * P.sp;
-    for (int o = threadIdx.x; o < n; o += kThreads) {
+    for (int o = o0 + threadIdx.x; o < o1; o += kThreads) {
         const int c = o / P.nrows, row = o - c * P.nrows;
         double v;
         if (KIND == kElliptic) {
@@ -1163,10 +1167,13 @@ void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it) {
 
 void launch_restrict(Ctx& c, int p0, int p1) {
     StageTimer t(c, MSRS_K_RESTRICT);
+    int64_t maxn = 0;
+    for (int p = p0; p < p1; ++p) maxn = std::max<int64_t>(maxn, (int64_t)c.hp[p].nrows * c.hp[p].s);
+    const dim3 grid(p1 - p0, (int)((maxn + kRestrictChunk - 1) / kRestrictChunk));
     if (c.kind == kElliptic)
-        hipLaunchKernelGGL((restrict_kernel<kElliptic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.x64, c.om, c.vw, c.Y);
+        hipLaunchKernelGGL((restrict_kernel<kElliptic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.x64, c.om, c.vw, c.Y);
     else
-        hipLaunchKernelGGL((restrict_kernel<kKinetic>), dim3(p1 - p0), dim3(kThreads), 0, c.stream, c.dp, p0, c.x64, c.om, c.vw, c.Y);
+        hipLaunchKernelGGL((restrict_kernel<kKinetic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.x64, c.om, c.vw, c.Y);
 }
 
 void launch_clear_conv(Ctx& c) {

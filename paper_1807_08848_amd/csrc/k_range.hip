@@ -114,8 +114,7 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
     __shared__ int pu[kRfMax / 2], pv[kRfMax / 2];
     __shared__ int perm[kRfMax];
     __shared__ double lam[kRfMax];
-    __shared__ double red[kThreads];
-    __shared__ double offn;
+    __shared__ int rot;
     const int p = p0 + blockIdx.x;
     const PatchDesc P = pd[p];
     const int tid = threadIdx.x;
@@ -127,23 +126,27 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
     }
     __syncthreads();
     sum_partials(part, p, maxrc, nch, s, G);
-    const int n = s + (s & 1);
-    double fro = 0.0;
-    for (int o = 0; o < s; ++o) fro += G[o * kRfMax + o] * G[o * kRfMax + o];
-    const int np2 = n / 2;
+    const int n = s + (s & 1), np2 = n / 2, nm1 = n - 1;
+    // Sweeps until every rotation of a sweep finds |g_pq| <= 1e-15 sqrt(g_pp g_qq)
+    // (relative off-diagonal criterion), at most 30.
+    if (tid == 0) rot = 0;
+    __syncthreads();
     for (int sweep = 0; sweep < 30; ++sweep) {
-        for (int st = 0; st < n - 1; ++st) {
+        for (int st = 0; st < nm1; ++st) {
             if (tid < np2) {
                 const int i = tid;
-                const int u = (i == 0) ? 0 : ((i - 1 + st) % (n - 1)) + 1;
-                const int v = ((n - 2 - i + st) % (n - 1)) + 1;
+                int u = 0;
+                if (i > 0) { u = i - 1 + st; if (u >= nm1) u -= nm1; u += 1; }
+                int v = nm1 - 1 - i + st; if (v >= nm1) v -= nm1; v += 1;
                 const int a = min(u, v), b = max(u, v);
                 pu[i] = a;
                 pv[i] = b;
                 double c = 1.0, t = 0.0;
                 const double apq = G[a * kRfMax + b];
                 if (b < s && apq != 0.0) {
-                    const double tau = (G[b * kRfMax + b] - G[a * kRfMax + a]) / (2.0 * apq);
+                    const double app = G[a * kRfMax + a], aqq = G[b * kRfMax + b];
+                    if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) rot = 1;
+                    const double tau = (aqq - app) / (2.0 * apq);
                     t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                     c = 1.0 / sqrt(1.0 + t * t);
                 }
@@ -151,9 +154,11 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
                 sn[i] = t * c;
             }
             __syncthreads();
-            // G <- J^T G J on 2x2 blocks (rows by pair i, columns by pair i2); V <- V J
-            for (int o = tid; o < np2 * np2; o += kThreads) {
-                const int i = o / np2, i2 = o % np2;
+            // G <- J^T G J on 2x2 blocks (rows by pair i, columns by pair i2): thread
+            // (i = tid / 32 + 8 r, i2 = tid % 32)
+            for (int i = tid >> 5; i < np2; i += kThreads / 32) {
+                const int i2 = tid & 31;
+                if (i2 >= np2) continue;
                 const int a = pu[i], b = pv[i], a2 = pu[i2], b2 = pv[i2];
                 const double c = cs[i], sv = sn[i], c2 = cs[i2], s2 = sn[i2];
                 const double g00 = G[a * kRfMax + a2], g01 = G[a * kRfMax + b2];
@@ -165,8 +170,10 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
                 G[b * kRfMax + a2] = c2 * r10 - s2 * r11;
                 G[b * kRfMax + b2] = s2 * r10 + c2 * r11;
             }
-            for (int o = tid; o < np2 * n; o += kThreads) {
-                const int i = o / n, j = o % n;
+            // V <- V J: thread (row j = tid % 64, pairs i = tid / 64 + 4 r)
+            for (int i = tid >> 6; i < np2; i += kThreads / 64) {
+                const int j = tid & 63;
+                if (j >= n) continue;
                 const int a = pu[i], b = pv[i];
                 const double c = cs[i], sv = sn[i];
                 const double va = V[j * kRfMax + a], vb = V[j * kRfMax + b];
@@ -175,20 +182,12 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
             }
             __syncthreads();
         }
-        double loc = 0.0;
-        for (int o = tid; o < s * s; o += kThreads) {
-            const int i = o / s, j = o % s;
-            if (i != j) loc += G[i * kRfMax + j] * G[i * kRfMax + j];
-        }
-        red[tid] = loc;
+        // uniform decision: every thread reads the flag before it is reset
+        const int r = rot;
         __syncthreads();
-        for (int w = kThreads / 2; w > 0; w >>= 1) {
-            if (tid < w) red[tid] += red[tid + w];
-            __syncthreads();
-        }
-        if (tid == 0) offn = red[0];
+        if (tid == 0) rot = 0;
         __syncthreads();
-        if (offn <= 1e-32 * fro) break;
+        if (!r) break;
     }
     if (tid == 0) {
         for (int i = 0; i < s; ++i) { perm[i] = i; lam[i] = G[i * kRfMax + i]; }
