@@ -123,6 +123,132 @@ def run_gpu(cfg, precision, steps, warmup, flags=0):
     return res
 
 
+def build_model(cfg, precision=1):
+    """A handle of the workload with its bases and coarse factor resident."""
+    import torch
+    from paper_1807_08848_amd import msrs
+    d = msrs.make_desc(msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"], list(cfg["overlap"]), cfg["s"], cfg["k"],
+                       precision=precision, seed=cfg["seed"])
+    pr = msrs.Problem(d)
+    pr.assemble_patch(torch.tensor(cfg["coef"], device="cuda:0"))
+    pr.sample_local_solutions()
+    pr.range_finder()
+    pr.set_max_batch(4096)
+    t0 = time.perf_counter()
+    pr.assemble_coarse()
+    torch.cuda.synchronize()
+    return pr, time.perf_counter() - t0
+
+
+def run_serving(lams=(200, 500, 1000, 2000), seconds=2.0, seed_arrival=5):
+    """Online stage over two resident models (h = 1/512 and h = 1/1024 domains).
+
+    Open-loop Poisson arrivals at each rate (50/50 model mix, pre-drawn arrival
+    times, boundary data of 16 Fourier modes): latency = solution resident in
+    HBM minus scheduled arrival.  Also the saturation throughput of the server
+    (all requests queued at once) and of the plain FP64 path (one request at
+    a time: P~^T d and two band triangular solves, then the reconstruction).
+    """
+    import threading
+    import numpy as np
+    import torch
+    import synth
+    from synth import configs
+    from paper_1807_08848_amd import msrs
+    sys.setswitchinterval(1e-4)
+    cfgs = [configs.elliptic_lognormal_512(), configs.elliptic_lognormal_1024()]
+    models, setup = [], []
+    for c in cfgs:
+        pr, ts = build_model(c)
+        models.append(pr)
+        setup.append(ts)
+    nn = [m.layout().n_nodes for m in models]
+    pool = [synth.fourier_boundary(c["N"], range(64)) for c in cfgs]   # request bodies, reused cyclically
+    # accuracy of the batched solve against the banded direct solve on the same bases
+    acc = []
+    for pr, P in zip(models, pool):
+        f = torch.tensor(P[:8], device="cuda:0")
+        ub = torch.empty((8, pr.layout().n_nodes), device="cuda:0", dtype=torch.float64)
+        ud = torch.empty_like(ub)
+        pr.solve_global(f, ub)
+        pr.solve_global_banded(f, ud)
+        torch.cuda.synchronize()
+        acc.append(float((ub - ud).abs().max() / ud.abs().max()))
+    # plain FP64 path, one request at a time
+    plain = {}
+    for c, pr, P in zip(cfgs, models, pool):
+        f = torch.tensor(P[:1], device="cuda:0")
+        u = torch.empty((1, pr.layout().n_nodes), device="cuda:0", dtype=torch.float64)
+        pr.solve_global_banded(f, u)
+        torch.cuda.synchronize()
+        n = 10
+        t0 = time.perf_counter()
+        for i in range(n):
+            pr.solve_global_banded(f, u)
+            torch.cuda.synchronize()
+        plain[c["name"]] = (time.perf_counter() - t0) / n * 1e3
+    plain_rate = 2.0 / sum(plain.values()) * 1e3      # 50/50 mix, requests/s
+
+    def drive(srv, arrivals, mdl):
+        infos = [None] * len(arrivals)
+        tickets = [None] * len(arrivals)
+        ready = threading.Semaphore(0)
+
+        def fetcher():
+            for i in range(len(arrivals)):
+                ready.acquire()
+                infos[i] = srv.fetch(tickets[i], None)
+        th = threading.Thread(target=fetcher)
+        th.start()
+        for i, ta in enumerate(arrivals):
+            if ta > 0:
+                while msrs.server_clock() < ta:
+                    pass
+            while True:
+                t = srv.try_submit(int(mdl[i]), pool[mdl[i]][i % 64], float(ta))
+                if t is not None:
+                    break
+            tickets[i] = t
+            ready.release()
+        th.join()
+        return infos
+
+    rng = np.random.default_rng(seed_arrival)
+    res = {}
+    with msrs.Server(models, n_streams=4, max_batch=32, slot_bytes=2 << 30) as srv:
+        drive(srv, [0.0] * 200, rng.integers(0, 2, 200))                       # warm-up
+        for lam in lams:
+            n = int(max(400, lam * seconds))
+            mdl = rng.integers(0, 2, n)
+            arr = msrs.server_clock() + 0.02 + np.cumsum(rng.exponential(1.0 / lam, n))
+            infos = drive(srv, list(arr), mdl)
+            lat = np.array([i.t_done - i.t_arrival for i in infos]) * 1e3
+            span = max(i.t_done for i in infos) - arr[0]
+            res[str(lam)] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                             "requests": n, "solves_per_s": n / span,
+                             "mean_batch": float(np.mean([i.batch_size for i in infos]))}
+            print(f"[bench] serving lambda={lam}: p50 {res[str(lam)]['p50_ms']:.3f} ms, "
+                  f"p99 {res[str(lam)]['p99_ms']:.3f} ms", file=sys.stderr, flush=True)
+        n = 4000
+        mdl = rng.integers(0, 2, n)
+        t0 = msrs.server_clock()
+        infos = drive(srv, [0.0] * n, mdl)
+        sat = n / (max(i.t_done for i in infos) - t0)
+        st = srv.stats()
+    out = {
+        "workload": "serving over elliptic_lognormal_512 + elliptic_lognormal_1024 (50/50, Poisson arrivals)",
+        "n_nodes": nn, "coarse_dim": [int(m.layout().coarse_dim) for m in models], "setup_s": setup,
+        "rel_err_batched_vs_banded": acc, "open_loop": res,
+        "saturation_solves_per_s": sat, "plain_fp64_ms_per_request": plain,
+        "plain_fp64_solves_per_s": plain_rate, "speedup_vs_plain": sat / plain_rate,
+        "server": {"streams": 4, "max_batch": 32, "mean_batch": st.mean_batch, "max_in_flight": st.max_in_flight,
+                   "admission_waits": st.admission_waits, "peak_slot_bytes": st.peak_slot_bytes},
+    }
+    for m in models:
+        m.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +257,7 @@ def main():
     ap.add_argument("--workload", default="elliptic_lognormal_512")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -172,6 +299,9 @@ def main():
         rp = run_gpu(cfg, msrs.PREC_FP64, max(1, min(3, args.steps)), 1, flags=msrs.FLAG_PER_PATCH_LAUNCH)
         vp = rp["n_solves"] * max(1, min(3, args.steps)) / rp["T"]
         out["plain_fp64"] = {"value": vp, "speedup": value / vp}
+    if not args.no_serve:
+        print("[bench] online serving (two resident models)", file=sys.stderr, flush=True)
+        out["online"] = run_serving()
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -222,15 +222,30 @@ msrs_status msrs_assemble_coarse(msrs_handle h);
 /*
  * Online solve (eqs. elliptic_cond_reduced / rte_cond_reduced and the ansatz
  * u = sum_m G_m c_m): for n_req requests, least-squares coefficients from the
- * global boundary data and the reconstructed global solution.
+ * global boundary data and the reconstructed global solution.  The
+ * coefficients are c = K f with the solution operator
+ * K = (P~^T P~)^{-1} P~_D^T formed at msrs_assemble_coarse (the right-hand
+ * side of the least-squares system is zero outside the Dirichlet / inflow
+ * rows), so a batch costs one pass over K and the bases.
  * f_dev: device, n_req x n_bdry (request-major).  u_dev: device,
  * n_req x n_nodes.  stream: hipStream_t (as void*) for this call, NULL for
  * the handle's stream.  Elliptic nodes shared by several patches take the
- * partition-of-unity average.  n_req must not exceed the slot capacity
- * fixed at msrs_assemble_coarse (msrs_set_max_batch).  Errors: ARG, STATE.
+ * partition-of-unity average.  Calls on different streams may overlap: each
+ * takes one of four internal workspaces that is no longer in use on the
+ * device, or fails with MSRS_ERR_BUSY.  Errors: ARG (n_req outside
+ * [1, max_batch]), STATE, BUSY.
  */
 msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev,
                               void* stream);
+
+/*
+ * The same solve by the plain direct method, one request after another:
+ * d~ = P~^T d and two band triangular solves with the Cholesky factor of
+ * P~^T P~ per request, then the reconstruction.  Same arguments, layouts
+ * and errors as msrs_solve_global; results agree to rounding.
+ */
+msrs_status msrs_solve_global_banded(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev,
+                                     void* stream);
 
 /*
  * Copy the resident boundary samples Omega (all patches, layout above) of
@@ -239,7 +254,7 @@ msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev,
  */
 msrs_status msrs_copy_omega(msrs_handle h, double* omega_out_dev);
 
-/* Requests per msrs_solve_global call at most (default 64); call before msrs_assemble_coarse. */
+/* Requests per msrs_solve_global call at most (1..4096, default 64). */
 msrs_status msrs_set_max_batch(msrs_handle h, int32_t max_batch);
 
 /* Sizes and offsets of the concatenated arrays.  Errors: ARG. */
@@ -257,6 +272,105 @@ const char* msrs_last_error(msrs_handle h);
 
 /* Release every device buffer of the handle (synchronises its stream). */
 void msrs_destroy(msrs_handle h);
+
+/* ------------------------------------------------------------------------
+ * Request server (the online stage as a service over resident models)
+ *
+ * A server holds one or more handles whose coarse problem is assembled
+ * (e.g. two grids of different size).  Requests -- a model index and that
+ * model's global boundary data f in host memory -- are queued in arrival
+ * order and admitted when an HBM slot for their solution fits in the slot
+ * budget (admission by footprint; strict arrival order, so a large request
+ * is never overtaken).  Admitted requests of one model are solved in batches
+ * of at most max_batch by msrs_solve_global's method on n_streams streams at
+ * once; requests arriving while batches run are admitted and launched as
+ * slots and streams free up.  A request's solution stays in its slot until
+ * msrs_server_fetch copies it out and releases the slot.  A result does not
+ * depend on the batch it ran in: every request's arithmetic is the same,
+ * alone or in a mix.
+ *
+ * Threads: submit, wait, fetch and get_stats may be called from any host
+ * threads at once; destroy must not overlap any other call on the server.
+ * While a server exists its handles refuse the offline and set-up calls
+ * (MSRS_ERR_STATE); msrs_solve_global stays usable.
+ * ---------------------------------------------------------------------- */
+typedef struct msrs_server_s* msrs_server;
+
+typedef struct msrs_server_config {
+    int32_t n_streams;       /* batches in flight at once, 1..8 (0 -> 4) */
+    int32_t max_batch;       /* requests per batch, 1..256 (0 -> 32) */
+    int32_t max_pending;     /* submitted and not yet fetched requests at most (0 -> 4096) */
+    int32_t reserved;
+    size_t slot_bytes;       /* device bytes for request solutions (0 -> 1 GiB) */
+    size_t staging_bytes;    /* pinned host bytes for queued boundary data (0 -> 64 MiB) */
+} msrs_server_config;
+
+typedef struct msrs_request_info {
+    int32_t model;
+    int32_t status;          /* MSRS_OK, or the error that failed the request */
+    int32_t batch_size;      /* requests of the batch that solved it */
+    int32_t stream;          /* index of the server stream that solved it */
+    double t_arrival;        /* seconds on msrs_server_clock */
+    double t_admit;          /* slot granted */
+    double t_launch;         /* batch enqueued */
+    double t_done;           /* batch observed complete (solution resident) */
+} msrs_request_info;
+
+typedef struct msrs_server_stats {
+    int64_t submitted, completed, batches;
+    int64_t max_in_flight;     /* requests on the device at once, at most */
+    int64_t peak_slot_bytes;   /* slot memory in use, at most */
+    int64_t slot_capacity;
+    int64_t admission_waits;   /* requests that had to wait for slot memory */
+    double mean_batch;         /* requests per batch */
+} msrs_server_stats;
+
+/* Monotonic clock of the server's timestamps, in seconds. */
+double msrs_server_clock(void);
+
+/* Message of the last failed server call of the calling thread. */
+const char* msrs_server_last_error(void);
+
+/*
+ * Create a server over n_models handles (host array; every handle must have
+ * passed msrs_assemble_coarse, all on one device).  cfg: host, NULL for the
+ * defaults.  Allocates the slot memory, pinned staging and per-stream
+ * workspaces and starts the worker thread.  Errors: ARG, STATE, OOM (a
+ * model's solution or boundary data exceeds the budgets), HIP.
+ */
+msrs_status msrs_server_create(msrs_server* out, const msrs_handle* models, int32_t n_models,
+                               const msrs_server_config* cfg);
+
+/*
+ * Queue one request: f_host (host, n_bdry of the model) is copied before the
+ * call returns.  t_arrival: arrival time on msrs_server_clock (<= 0: now),
+ * the origin of the request's latency.  *ticket identifies it in wait and
+ * fetch.  Errors: ARG, STATE (shutting down), BUSY (max_pending unfetched
+ * requests or staging full; retry later), the server's latched error.
+ */
+msrs_status msrs_server_submit(msrs_server s, int32_t model, const double* f_host, double t_arrival,
+                               int64_t* ticket);
+
+/* Wait until the request is solved (timeout_s < 0: no limit).  BUSY on time-out. */
+msrs_status msrs_server_wait(msrs_server s, int64_t ticket, double timeout_s);
+
+/*
+ * Wait for the request, copy its solution (n_nodes doubles) to u_out (host
+ * or device; NULL: discard), fill *info (nullable) and release the request
+ * and its slot; the ticket is invalid afterwards.  Errors: ARG (unknown
+ * ticket), HIP, or the error that failed the request.
+ */
+msrs_status msrs_server_fetch(msrs_server s, int64_t ticket, double* u_out, msrs_request_info* info);
+
+/* Counters of the server; returns its latched error, if any. */
+msrs_status msrs_server_get_stats(msrs_server s, msrs_server_stats* out);
+
+/*
+ * Stop the server: queued requests that were not launched fail with
+ * MSRS_ERR_STATE, launched batches are waited for, memory and streams are
+ * released and the handles accept offline calls again.
+ */
+void msrs_server_destroy(msrs_server s);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "k_local.hip", "k_range.hip", "k_coarse.hip"]
+SOURCES = ["api.hip", "k_local.hip", "k_range.hip", "k_coarse.hip", "serve.hip"]
 LIB = os.path.join(HERE, "libmsrs.so")
 ARCH = os.environ.get("MSRS_OFFLOAD_ARCH", "gfx950")
 

@@ -12,9 +12,6 @@
 
 using namespace msrs;
 
-// the opaque handle of the ABI is the library context
-struct msrs_ctx : public msrs::Ctx {};
-
 namespace {
 
 thread_local std::string g_create_err;
@@ -204,7 +201,8 @@ void sync_flags(Ctx& c) {
 void resolve_timing(Ctx& c) {
     for (auto& pe : c.pending) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) c.tms[pe.cls] += ms;
+        // events of online calls may sit on other streams than the handle's
+        if (hipEventSynchronize(pe.b) == hipSuccess && hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) c.tms[pe.cls] += ms;
         c.event_pool.push_back(pe.a);
         c.event_pool.push_back(pe.b);
     }
@@ -225,16 +223,16 @@ static hipEvent_t take_event(Ctx& c) {
     MSRS_HIP_CHECK(hipEventCreate(&e));
     return e;
 }
-StageTimer::StageTimer(Ctx& cc, int k) : c(cc), cls(k) {
+StageTimer::StageTimer(Ctx& cc, int k, hipStream_t s) : c(cc), cls(k), st(s ? s : cc.stream) {
     c.tlaunch[cls] += 1;
     if (!c.timing) return;
     a = take_event(c);
     b = take_event(c);
-    MSRS_HIP_CHECK(hipEventRecord(a, c.stream));
+    MSRS_HIP_CHECK(hipEventRecord(a, st));
 }
 StageTimer::~StageTimer() {
     if (!c.timing || !a) return;
-    if (hipEventRecord(b, c.stream) == hipSuccess) c.pending.push_back({cls, a, b});
+    if (hipEventRecord(b, st) == hipSuccess) c.pending.push_back({cls, a, b});
 }
 }  // namespace msrs
 
@@ -364,6 +362,7 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
 msrs_status msrs_assemble_patch(msrs_handle h, const double* coef_dev) {
     Ctx* c = h;
     if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
     if (!coef_dev) return fail(c, MSRS_ERR_ARG, "coef_dev is NULL");
     try {
         const int64_t n = c->kind == kElliptic ? (int64_t)c->N * c->N : c->N;
@@ -385,6 +384,7 @@ msrs_status msrs_assemble_patch(msrs_handle h, const double* coef_dev) {
 msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, double* Y_out_dev) {
     Ctx* c = h;
     if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
     if (!c->assembled) return fail(c, MSRS_ERR_STATE, "msrs_assemble_patch must come first");
     try {
         for_patches(*c, [&](int p0, int p1) { launch_omega(*c, omega_dev, p0, p1); });
@@ -441,6 +441,7 @@ msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, 
 msrs_status msrs_range_finder(msrs_handle h, double* Q_out_dev, double* sv_out_dev) {
     Ctx* c = h;
     if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
     if (!c->sampled) return fail(c, MSRS_ERR_STATE, "msrs_sample_local_solutions must come first");
     try {
         for_patches(*c, [&](int p0, int p1) { launch_range(*c, p0, p1); });
@@ -473,8 +474,8 @@ msrs_status msrs_copy_omega(msrs_handle h, double* omega_out_dev) {
 msrs_status msrs_set_max_batch(msrs_handle h, int32_t max_batch) {
     Ctx* c = h;
     if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
-    if (max_batch < 1 || max_batch > 64) return fail(c, MSRS_ERR_ARG, "max_batch must be in [1, 64]");
-    if (c->coarse_ready) return fail(c, MSRS_ERR_STATE, "call before msrs_assemble_coarse");
+    if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
+    if (max_batch < 1 || max_batch > 4096) return fail(c, MSRS_ERR_ARG, "max_batch must be in [1, 4096]");
     c->max_batch = max_batch;
     return MSRS_OK;
 }
@@ -482,6 +483,7 @@ msrs_status msrs_set_max_batch(msrs_handle h, int32_t max_batch) {
 msrs_status msrs_assemble_coarse(msrs_handle h) {
     Ctx* c = h;
     if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
     if (!c->ranged) return fail(c, MSRS_ERR_STATE, "msrs_range_finder must come first");
     try {
         if (!c->dc) {
@@ -512,9 +514,16 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
             for (auto& d : c->hc) kmax = std::max(kmax, d.ncols);
             c->dc = dalloc<CoarseDesc>(*c, c->n_patches);
             MSRS_HIP_CHECK(hipMemcpy(c->dc, c->hc.data(), sizeof(CoarseDesc) * c->n_patches, hipMemcpyHostToDevice));
-            if (c->kind == kElliptic) c->tr = dalloc<double>(*c, (int64_t)c->n_patches * 2 * 4 * (c->N / c->M) * kmax);
+            if (c->kind == kElliptic) {
+                c->tr_stride = 2LL * 4 * (c->N / c->M) * kmax;
+                c->tr = dalloc<double>(*c, (int64_t)c->n_patches * c->tr_stride);
+            }
             c->band = dalloc<double>(*c, (int64_t)c->Np * (c->bw + 1));
-            c->crhs = dalloc<double>(*c, (int64_t)c->Np * c->max_batch);
+            c->Kop = dalloc<double>(*c, (int64_t)c->Np * c->n_bdry);
+            for (auto& w : c->ws) {
+                w.cbuf = dalloc<double>(*c, (int64_t)c->Np * kOutPerLaunch);
+                MSRS_HIP_CHECK(hipEventCreateWithFlags(&w.done, hipEventDisableTiming));
+            }
             if (c->budget && (size_t)c->bytes > c->budget) return fail(c, MSRS_ERR_OOM, "coarse factor exceeds the HBM budget");
         }
         coarse_setup(*c);
@@ -529,20 +538,50 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
     return st;
 }
 
-msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev, void* stream) {
-    Ctx* c = h;
+// A free online workspace (its last use on the device has completed), or null.
+static Ctx::OnlineWs* take_ws(Ctx* c) {
+    for (auto& w : c->ws) {
+        if (!w.used) return &w;
+        const hipError_t q = hipEventQuery(w.done);
+        if (q == hipSuccess) return &w;
+        if (q != hipErrorNotReady) MSRS_HIP_CHECK(q);
+    }
+    return nullptr;
+}
+
+static msrs_status solve_common(Ctx* c, int32_t n_req, const double* f_dev, double* u_dev, void* stream, bool banded) {
     if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
     if (!c->coarse_ready) return fail(c, MSRS_ERR_STATE, "msrs_assemble_coarse must come first");
     if (n_req < 1 || n_req > c->max_batch) return fail(c, MSRS_ERR_ARG, "n_req must be in [1, max_batch]");
     if (!f_dev || !u_dev) return fail(c, MSRS_ERR_ARG, "f_dev / u_dev is NULL");
     try {
         hipStream_t st = stream ? (hipStream_t)stream : c->stream;
-        coarse_solve(*c, n_req, f_dev, u_dev, st);
+        Ctx::OnlineWs* w = take_ws(c);
+        if (!w) return fail(c, MSRS_ERR_BUSY, "every online workspace is in use by unfinished calls");
+        if (banded) {
+            StageTimer t(*c, MSRS_K_CSOLVE, st);
+            for (int r = 0; r < n_req; ++r) coarse_banded(*c, f_dev + (int64_t)r * c->n_bdry, u_dev + r * c->n_nodes, w->cbuf, st);
+        } else {
+            std::vector<double*> u(n_req);
+            for (int r = 0; r < n_req; ++r) u[r] = u_dev + r * c->n_nodes;
+            StageTimer t(*c, MSRS_K_CSOLVE, st);
+            coarse_apply(*c, n_req, f_dev, c->n_bdry, u.data(), w->cbuf, st);
+        }
         MSRS_HIP_CHECK(hipGetLastError());
+        MSRS_HIP_CHECK(hipEventRecord(w->done, st));
+        w->used = true;
     } catch (const HipError& e) {
         return hip_fail(c, e);
     }
     return MSRS_OK;
+}
+
+msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev, void* stream) {
+    return solve_common(h, n_req, f_dev, u_dev, stream, false);
+}
+
+msrs_status msrs_solve_global_banded(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev, void* stream) {
+    return solve_common(h, n_req, f_dev, u_dev, stream, true);
 }
 
 msrs_status msrs_query_layout(msrs_handle h, msrs_layout* out) {
@@ -631,6 +670,8 @@ void msrs_destroy(msrs_handle h) {
     msrs_ctx* c = h;
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    for (auto& w : c->ws)
+        if (w.used) (void)hipEventSynchronize(w.done);
     for (auto& pe : c->pending) { (void)hipEventDestroy(pe.a); (void)hipEventDestroy(pe.b); }
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
     for (int k = 0; k < 8; ++k) {
@@ -638,6 +679,8 @@ void msrs_destroy(msrs_handle h) {
         if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
     }
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    for (auto& w : c->ws)
+        if (w.done) (void)hipEventDestroy(w.done);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->hflags) (void)hipHostFree(c->hflags);
     delete c;

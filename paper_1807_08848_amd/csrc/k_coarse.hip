@@ -11,10 +11,12 @@
 // ghost equal the first cell of K_{m+1}; inflow rows at x = 0 and x = 1.
 //
 // The normal equations P~^T P~ c = P~^T d are block banded (patch order);
-// they are formed in lower band storage band[j*(bw+1) + d] = A[j+d][j],
-// factored once by a band Cholesky, and every request is two band
-// triangular solves plus the reconstruction u = sum_m w_m Q_m c_m (nodal
-// partition of unity w_m = 1/#patches at shared elliptic nodes).
+// they are formed in lower band storage band[j*(bw+1) + d] = A[j+d][j] and
+// factored once by a band Cholesky.  A request's coefficients are either two
+// band triangular solves (banded path) or one product with the precomputed
+// solution operator (batched path), then the reconstruction
+// u = sum_m w_m Q_m c_m (nodal partition of unity w_m = 1/#patches at shared
+// elliptic nodes).
 #include "device_common.h"
 
 namespace msrs {
@@ -230,53 +232,17 @@ __global__ __launch_bounds__(1024) void band_cholesky_kernel(double* __restrict_
     }
 }
 
-// ------------------------------------------------------------ per-request rhs
-__global__ __launch_bounds__(kThreads) void rhs_elliptic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ tr,
-                                                                int64_t tr_stride, int M, int N, int Np, const double* __restrict__ f,
-                                                                int n_req, double* __restrict__ rhs) {
-    const int m = blockIdx.x;
-    const int m1 = m % M, m2 = m / M;
-    const int nH = pd[m].nH;
-    const ElTr Tm{tr + (int64_t)m * tr_stride, nH, cd[m].ncols};
-    const int km = cd[m].ncols, om = cd[m].col_off;
-    for (int o = threadIdx.x; o < km * n_req; o += kThreads) {
-        const int a = o % km, r = o / km;
-        double s = 0.0;
-        if (m1 == 0 || m1 == M - 1 || m2 == 0 || m2 == M - 1)
-            for (int t = 0; t < 4 * nH; ++t) {
-                int ii, jj;
-                kbnode(t, nH, ii, jj);
-                const int gx = m1 * nH + ii, gy = m2 * nH + jj;
-                if (gx == 0 || gx == N || gy == 0 || gy == N) s += Tm.val(ii, jj, a) * f[(int64_t)r * 4 * N + gb_index(gx, gy, N)];
-            }
-        rhs[(int64_t)r * Np + om + a] = s;
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void rhs_kinetic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ Q_all,
-                                                               const double* __restrict__ vw, int M, int nv, int Np,
-                                                               const double* __restrict__ f, int n_req, double* __restrict__ rhs) {
-    const int m = blockIdx.x;
-    const PatchDesc P = pd[m];
-    const int km = cd[m].ncols, om = cd[m].col_off, h = nv / 2;
-    const double* Q = Q_all + P.Q_off;
-    for (int o = threadIdx.x; o < km * n_req; o += kThreads) {
-        const int a = o % km, r = o / km;
-        double s = 0.0;
-        for (int j = 0; j < nv; ++j) {
-            if (m == 0 && vw[j] > 0) s += Q[(int64_t)a * P.nrows + 0 * nv + j] * f[(int64_t)r * nv + (j - h)];
-            if (m == M - 1 && vw[j] < 0) s += Q[(int64_t)a * P.nrows + (P.nH + 1) * nv + j] * f[(int64_t)r * nv + h + j];
-        }
-        rhs[(int64_t)r * Np + om + a] = s;
-    }
-}
-
 // ------------------------------------------------------------ band solves
-// One workgroup solves L L^T c = rhs for all n_req columns (in place).
-__global__ __launch_bounds__(1024) void band_solve_kernel(const double* __restrict__ band, int n, int bw, double* __restrict__ x, int n_req) {
+// L L^T X = B for the columns of B (column-major, n rows, ncols columns), in
+// place; workgroup x solves columns [64 x, 64 x + 64).
+__global__ __launch_bounds__(1024) void band_solve_kernel(const double* __restrict__ band, int n, int bw, double* __restrict__ xall,
+                                                          int ncols) {
     __shared__ double piv[64];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int ld = bw + 1;
+    const int c0 = blockIdx.x * 64;
+    const int n_req = min(64, ncols - c0);
+    double* x = xall + (int64_t)c0 * n;
     // forward: L y = b (column oriented)
     for (int j = 0; j < n; ++j) {
         const double* Lj = band + (int64_t)j * ld;
@@ -312,10 +278,121 @@ __global__ __launch_bounds__(1024) void band_solve_kernel(const double* __restri
     }
 }
 
+// ------------------------------------------------------------ Dirichlet columns
+// Column t of P~_D^T (global boundary datum t): in the unknowns of every patch
+// with a Dirichlet row at datum t, the basis values there.  Written into K
+// (Np x n_bdry, column-major) before the band solves turn it into the
+// solution operator.
+__global__ __launch_bounds__(kThreads) void dirichlet_cols_elliptic_kernel(const PatchDesc* pd, const CoarseDesc* cd,
+                                                                           const double* __restrict__ tr, int64_t tr_stride,
+                                                                           int M, int N, int Np, double* __restrict__ K) {
+    const int m = blockIdx.x;
+    const int m1 = m % M, m2 = m / M;
+    if (!(m1 == 0 || m1 == M - 1 || m2 == 0 || m2 == M - 1)) return;
+    const int nH = pd[m].nH;
+    const ElTr Tm{tr + (int64_t)m * tr_stride, nH, cd[m].ncols};
+    const int km = cd[m].ncols, om = cd[m].col_off;
+    for (int o = threadIdx.x; o < 4 * nH * km; o += kThreads) {
+        const int t = o / km, a = o % km;
+        int ii, jj;
+        kbnode(t, nH, ii, jj);
+        const int gx = m1 * nH + ii, gy = m2 * nH + jj;
+        if (gx == 0 || gx == N || gy == 0 || gy == N) K[(int64_t)gb_index(gx, gy, N) * Np + om + a] = Tm.val(ii, jj, a);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void dirichlet_cols_kinetic_kernel(const PatchDesc* pd, const CoarseDesc* cd,
+                                                                          const double* __restrict__ Q_all, const double* __restrict__ vw,
+                                                                          int M, int nv, int Np, double* __restrict__ K) {
+    const int m = blockIdx.x;
+    if (m != 0 && m != M - 1) return;
+    const PatchDesc P = pd[m];
+    const int km = cd[m].ncols, om = cd[m].col_off, h = nv / 2;
+    const double* Q = Q_all + P.Q_off;
+    for (int o = threadIdx.x; o < nv * km; o += kThreads) {
+        const int j = o / km, a = o % km;
+        if (m == 0 && vw[j] > 0) K[(int64_t)(j - h) * Np + om + a] = Q[(int64_t)a * P.nrows + 0 * nv + j];
+        if (m == M - 1 && vw[j] < 0) K[(int64_t)(h + j) * Np + om + a] = Q[(int64_t)a * P.nrows + (P.nH + 1) * nv + j];
+    }
+}
+
+// ------------------------------------------------------------ per-request rhs (banded path)
+// d~ = P~^T d for one request: only the Dirichlet rows of d are non-zero.
+__global__ __launch_bounds__(kThreads) void rhs_elliptic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ tr,
+                                                                int64_t tr_stride, int M, int N, const double* __restrict__ f,
+                                                                double* __restrict__ rhs) {
+    const int m = blockIdx.x;
+    const int m1 = m % M, m2 = m / M;
+    const int nH = pd[m].nH;
+    const ElTr Tm{tr + (int64_t)m * tr_stride, nH, cd[m].ncols};
+    const int km = cd[m].ncols, om = cd[m].col_off;
+    const bool edge = (m1 == 0 || m1 == M - 1 || m2 == 0 || m2 == M - 1);
+    for (int a = threadIdx.x; a < km; a += kThreads) {
+        double s = 0.0;
+        if (edge)
+            for (int t = 0; t < 4 * nH; ++t) {
+                int ii, jj;
+                kbnode(t, nH, ii, jj);
+                const int gx = m1 * nH + ii, gy = m2 * nH + jj;
+                if (gx == 0 || gx == N || gy == 0 || gy == N) s += Tm.val(ii, jj, a) * f[gb_index(gx, gy, N)];
+            }
+        rhs[om + a] = s;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void rhs_kinetic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ Q_all,
+                                                               const double* __restrict__ vw, int M, int nv,
+                                                               const double* __restrict__ f, double* __restrict__ rhs) {
+    const int m = blockIdx.x;
+    const PatchDesc P = pd[m];
+    const int km = cd[m].ncols, om = cd[m].col_off, h = nv / 2;
+    const double* Q = Q_all + P.Q_off;
+    for (int a = threadIdx.x; a < km; a += kThreads) {
+        double s = 0.0;
+        for (int j = 0; j < nv; ++j) {
+            if (m == 0 && vw[j] > 0) s += Q[(int64_t)a * P.nrows + 0 * nv + j] * f[j - h];
+            if (m == M - 1 && vw[j] < 0) s += Q[(int64_t)a * P.nrows + (P.nH + 1) * nv + j] * f[h + j];
+        }
+        rhs[om + a] = s;
+    }
+}
+
+// ------------------------------------------------------------ batched path: c = K f
+// c[r*Np + j] = sum_t K[t*Np + j] f[r*f_ld + t] for n_req requests.  A thread
+// owns unknown j and RB requests; K streams once per RB requests, f is
+// wave-uniform (scalar loads).
+template <int RB>
+__global__ __launch_bounds__(kThreads) void apply_K_kernel(const double* __restrict__ K, int Np, int nb,
+                                                           const double* __restrict__ f, int64_t f_ld, int n_req,
+                                                           double* __restrict__ c) {
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    const int r0 = blockIdx.y * RB;
+    if (j >= Np) return;
+    const int nr = min(RB, n_req - r0);
+    const double* fr[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) fr[r] = f + (int64_t)(r0 + min(r, nr - 1)) * f_ld;
+    double acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = 0.0;
+#pragma unroll 4
+    for (int t = 0; t < nb; ++t) {
+        const double kv = K[(int64_t)t * Np + j];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) acc[r] = fma(kv, fr[r][t], acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+        if (r < nr) c[(int64_t)(r0 + r) * Np + j] = acc[r];
+}
+
 // ------------------------------------------------------------ reconstruction
+// u_r(x) = sum_m w_m(x) (Q_m c_{r,m})(x) for the requests of one launch; the
+// output of request r is out.u[r] (requests need not be contiguous).
 __global__ __launch_bounds__(kThreads) void recon_elliptic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ Q_all,
                                                                   int M, int N, int Np, const double* __restrict__ c, int n_req,
-                                                                  double* __restrict__ u) {
+                                                                  OutPtrs out) {
+    constexpr int RB = 8;
     const int64_t nn = (int64_t)(N + 1) * (N + 1);
     const int nH = N / M, W = nH + 1;
     for (int64_t node = blockIdx.x * (int64_t)kThreads + threadIdx.x; node < nn; node += (int64_t)gridDim.x * kThreads) {
@@ -326,26 +403,36 @@ __global__ __launch_bounds__(kThreads) void recon_elliptic_kernel(const PatchDes
         if (gy % nH == 0 && gy > 0) ys[ny++] = gy / nH - 1;
         if (gy / nH < M) ys[ny++] = gy / nH;
         const double w = 1.0 / (nx * ny);
-        for (int r = 0; r < n_req; ++r) u[(int64_t)r * nn + node] = 0.0;
-        for (int a = 0; a < nx; ++a)
-            for (int b = 0; b < ny; ++b) {
-                const int m = ys[b] * M + xs[a];
-                const PatchDesc& P = pd[m];
-                const int row = (gy - ys[b] * nH) * W + (gx - xs[a] * nH);
-                const int km = cd[m].ncols, om = cd[m].col_off;
-                const double* Q = Q_all + P.Q_off + row;
-                for (int r = 0; r < n_req; ++r) {
-                    double s = 0.0;
-                    for (int cc = 0; cc < km; ++cc) s += Q[(int64_t)cc * P.nrows] * c[(int64_t)r * Np + om + cc];
-                    u[(int64_t)r * nn + node] += w * s;
+        for (int r0 = 0; r0 < n_req; r0 += RB) {
+            const int nr = min(RB, n_req - r0);
+            double acc[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) acc[r] = 0.0;
+            for (int a = 0; a < nx; ++a)
+                for (int b = 0; b < ny; ++b) {
+                    const int m = ys[b] * M + xs[a];
+                    const PatchDesc& P = pd[m];
+                    const int row = (gy - ys[b] * nH) * W + (gx - xs[a] * nH);
+                    const int km = cd[m].ncols, om = cd[m].col_off;
+                    const double* Q = Q_all + P.Q_off + row;
+                    const double* cm = c + (int64_t)r0 * Np + om;
+                    for (int cc = 0; cc < km; ++cc) {
+                        const double q = Q[(int64_t)cc * P.nrows];
+#pragma unroll
+                        for (int r = 0; r < RB; ++r)
+                            if (r < nr) acc[r] = fma(q, cm[(int64_t)r * Np + cc], acc[r]);
+                    }
                 }
-            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                if (r < nr) out.u[r0 + r][node] = w * acc[r];
+        }
     }
 }
 
 __global__ __launch_bounds__(kThreads) void recon_kinetic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ Q_all,
                                                                  int M, int Nx, int nv, int Np, const double* __restrict__ c, int n_req,
-                                                                 double* __restrict__ u) {
+                                                                 OutPtrs out) {
     const int64_t nn = (int64_t)Nx * nv;
     const int nH = Nx / M;
     for (int64_t idx = blockIdx.x * (int64_t)kThreads + threadIdx.x; idx < nn; idx += (int64_t)gridDim.x * kThreads) {
@@ -358,53 +445,66 @@ __global__ __launch_bounds__(kThreads) void recon_kinetic_kernel(const PatchDesc
         for (int r = 0; r < n_req; ++r) {
             double s = 0.0;
             for (int cc = 0; cc < km; ++cc) s += Q[(int64_t)cc * P.nrows] * c[(int64_t)r * Np + om + cc];
-            u[(int64_t)r * nn + idx] = s;
+            out.u[r][idx] = s;
         }
     }
 }
 
 // ------------------------------------------------------------ host side
+// Set-up: traces, normal matrix, band Cholesky, then the solution operator
+// K = (P~^T P~)^{-1} P~_D^T (Np x n_bdry, column-major).  The right-hand side
+// d of the least-squares system vanishes outside the Dirichlet (inflow) rows,
+// so every request's coefficients are c = K f: one dense product instead of
+// two sequential band solves per request.
 void coarse_setup(Ctx& c) {
     StageTimer t(c, MSRS_K_COARSE);
     const int64_t nband = (int64_t)c.Np * (c.bw + 1);
     hipLaunchKernelGGL(fill_kernel, dim3(256), dim3(256), 0, c.stream, c.band, nband, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, c.stream, c.Kop, (int64_t)c.Np * c.n_bdry, 0.0);
     if (c.kind == kElliptic) {
-        const int64_t trs = 2LL * 4 * (c.N / c.M) * c.hc[0].ncols;
-        int kmax = 0;
-        for (auto& d : c.hc) kmax = std::max(kmax, d.ncols);
-        const int64_t tr_stride = 2LL * 4 * (c.N / c.M) * kmax;
-        (void)trs;
-        hipLaunchKernelGGL(traces_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.coef_copy, c.N, c.Q, c.tr, tr_stride);
-        hipLaunchKernelGGL(normal_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.tr, tr_stride, c.M, c.N, c.band, c.bw);
+        hipLaunchKernelGGL(traces_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.coef_copy, c.N, c.Q, c.tr, c.tr_stride);
+        hipLaunchKernelGGL(normal_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.tr, c.tr_stride, c.M, c.N, c.band, c.bw);
+        hipLaunchKernelGGL(dirichlet_cols_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.tr, c.tr_stride, c.M, c.N, c.Np, c.Kop);
     } else {
         hipLaunchKernelGGL(normal_kinetic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.Q, c.vw, c.M, c.nv, c.band, c.bw);
+        hipLaunchKernelGGL(dirichlet_cols_kinetic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.Q, c.vw, c.M, c.nv, c.Np, c.Kop);
     }
     hipLaunchKernelGGL(band_cholesky_kernel, dim3(1), dim3(1024), 0, c.stream, c.band, c.Np, c.bw, c.dflags);
+    hipLaunchKernelGGL(band_solve_kernel, dim3((c.n_bdry + 63) / 64), dim3(1024), 0, c.stream, c.band, c.Np, c.bw, c.Kop, c.n_bdry);
 }
 
-void coarse_solve(Ctx& c, int n_req, const double* f, double* u, hipStream_t st) {
-    {
-        StageTimer t(c, MSRS_K_CSOLVE);
-        if (c.kind == kElliptic) {
-            int kmax = 0;
-            for (auto& d : c.hc) kmax = std::max(kmax, d.ncols);
-            const int64_t tr_stride = 2LL * 4 * (c.N / c.M) * kmax;
-            hipLaunchKernelGGL(rhs_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, st, c.dp, c.dc, c.tr, tr_stride, c.M, c.N, c.Np, f, n_req, c.crhs);
-        } else {
-            hipLaunchKernelGGL(rhs_kinetic_kernel, dim3(c.n_patches), dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.vw, c.M, c.nv, c.Np, f, n_req, c.crhs);
-        }
-        hipLaunchKernelGGL(band_solve_kernel, dim3(1), dim3(1024), 0, st, c.band, c.Np, c.bw, c.crhs, n_req);
-    }
-    StageTimer t2(c, MSRS_K_RECON);
+static void launch_recon(const Ctx& c, const double* cbuf, int n_req, const OutPtrs& out, hipStream_t st) {
     if (c.kind == kElliptic) {
         const int64_t nn = (int64_t)(c.N + 1) * (c.N + 1);
-        const int blocks = (int)std::min<int64_t>((nn + kThreads - 1) / kThreads, 4096);
-        hipLaunchKernelGGL(recon_elliptic_kernel, dim3(blocks), dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.M, c.N, c.Np, c.crhs, n_req, u);
+        const int blocks = (int)std::min<int64_t>((nn + kThreads - 1) / kThreads, 8192);
+        hipLaunchKernelGGL(recon_elliptic_kernel, dim3(blocks), dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.M, c.N, c.Np, cbuf, n_req, out);
     } else {
         const int64_t nn = (int64_t)c.N * c.nv;
-        const int blocks = (int)std::min<int64_t>((nn + kThreads - 1) / kThreads, 4096);
-        hipLaunchKernelGGL(recon_kinetic_kernel, dim3(blocks), dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.M, c.N, c.nv, c.Np, c.crhs, n_req, u);
+        const int blocks = (int)std::min<int64_t>((nn + kThreads - 1) / kThreads, 8192);
+        hipLaunchKernelGGL(recon_kinetic_kernel, dim3(blocks), dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.M, c.N, c.nv, c.Np, cbuf, n_req, out);
     }
+}
+
+void coarse_apply(const Ctx& c, int n_req, const double* f, int64_t f_ld, double* const* u, double* cbuf, hipStream_t st) {
+    for (int r0 = 0; r0 < n_req; r0 += kOutPerLaunch) {
+        const int nr = std::min(kOutPerLaunch, n_req - r0);
+        const dim3 g((c.Np + kThreads - 1) / kThreads, (nr + 7) / 8);
+        hipLaunchKernelGGL(apply_K_kernel<8>, g, dim3(kThreads), 0, st, c.Kop, c.Np, c.n_bdry, f + r0 * f_ld, f_ld, nr, cbuf);
+        OutPtrs out{};
+        for (int r = 0; r < nr; ++r) out.u[r] = u[r0 + r];
+        launch_recon(c, cbuf, nr, out, st);
+    }
+}
+
+void coarse_banded(const Ctx& c, const double* f, double* u, double* cbuf, hipStream_t st) {
+    if (c.kind == kElliptic)
+        hipLaunchKernelGGL(rhs_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, st, c.dp, c.dc, c.tr, c.tr_stride, c.M, c.N, f, cbuf);
+    else
+        hipLaunchKernelGGL(rhs_kinetic_kernel, dim3(c.n_patches), dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.vw, c.M, c.nv, f, cbuf);
+    hipLaunchKernelGGL(band_solve_kernel, dim3(1), dim3(1024), 0, st, c.band, c.Np, c.bw, cbuf, 1);
+    OutPtrs out{};
+    out.u[0] = u;
+    launch_recon(c, cbuf, 1, out, st);
 }
 
 }  // namespace msrs

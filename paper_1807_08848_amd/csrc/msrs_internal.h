@@ -16,6 +16,12 @@ constexpr int kMaxLine = 128;      // padded unknowns per block row (elliptic); 
 constexpr int kMaxSamples = 64;    // padded samples per patch
 constexpr int kThreads = 256;      // threads of every per-patch workgroup
 constexpr int kChunkLines = 8;     // block rows per workgroup of the lifting and residual kernels
+constexpr int kOutPerLaunch = 32;  // requests per reconstruction launch
+constexpr int kOnlineWs = 4;       // concurrent msrs_solve_global calls per handle
+
+// Output pointers of the requests of one reconstruction launch, passed by
+// value in the kernel arguments (no device pointer array to stage).
+struct OutPtrs { double* u[kOutPerLaunch]; };
 
 // One buffered patch, in the block-row ("line") view of the local problem.
 //
@@ -126,7 +132,13 @@ struct Ctx {
     CoarseDesc* dc = nullptr;
     double* tr = nullptr;         // traces (values, fluxes)
     double* band = nullptr;       // normal matrix, then its Cholesky factor (lower band)
-    double* crhs = nullptr;       // per request right-hand sides / coefficients, Np x max_batch
+    double* Kop = nullptr;        // solution operator (P~^T P~)^{-1} P~_D^T, Np x n_bdry column-major
+    int64_t tr_stride = 0;        // doubles per patch of tr
+    // online workspaces: msrs_solve_global calls on different streams take
+    // distinct ones; a workspace is free once its event has completed
+    struct OnlineWs { double* cbuf = nullptr; hipEvent_t done = nullptr; bool used = false; };
+    OnlineWs ws[kOnlineWs];
+    int served = 0;               // servers holding this handle (offline and set-up calls refused)
     int32_t n_bdry = 0;
     int64_t n_nodes = 0;
     std::vector<void*> allocs;
@@ -155,18 +167,27 @@ void launch_clear_conv(Ctx& c);
 
 // coarse (k_coarse.hip)
 void coarse_setup(Ctx& c);     // traces, normal matrix, Cholesky (enqueued)
-void coarse_solve(Ctx& c, int n_req, const double* f, double* u, hipStream_t st);
+// Batched path: n_req requests, boundary data f (request r at f + r*f_ld,
+// device), outputs u[r] (device), coefficient workspace cbuf (Np x
+// kOutPerLaunch).  Reads the handle only, so several streams may run it.
+void coarse_apply(const Ctx& c, int n_req, const double* f, int64_t f_ld, double* const* u, double* cbuf, hipStream_t st);
+// Banded path: one request by P~^T d and two band triangular solves; cbuf Np.
+void coarse_banded(const Ctx& c, const double* f, double* u, double* cbuf, hipStream_t st);
 
 // timing helpers (api.hip)
 struct StageTimer {
     Ctx& c;
     int cls;
     hipEvent_t a = nullptr, b = nullptr;
-    StageTimer(Ctx& cc, int k);
+    hipStream_t st;
+    StageTimer(Ctx& cc, int k, hipStream_t s = nullptr);
     ~StageTimer();
 };
 
 }  // namespace msrs
+
+// the opaque handle of the ABI is the library context
+struct msrs_ctx : public msrs::Ctx {};
 
 #define MSRS_HIP_CHECK(expr)                                                          \
     do {                                                                              \

@@ -59,6 +59,22 @@ class Stats(C.Structure):
                 ("min_rel_gap", C.c_double), ("kernel_ms", C.c_double * 12), ("kernel_launches", C.c_int64 * 12)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("n_streams", C.c_int32), ("max_batch", C.c_int32), ("max_pending", C.c_int32),
+                ("reserved", C.c_int32), ("slot_bytes", C.c_size_t), ("staging_bytes", C.c_size_t)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("model", C.c_int32), ("status", C.c_int32), ("batch_size", C.c_int32), ("stream", C.c_int32),
+                ("t_arrival", C.c_double), ("t_admit", C.c_double), ("t_launch", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
+                ("max_in_flight", C.c_int64), ("peak_slot_bytes", C.c_int64), ("slot_capacity", C.c_int64),
+                ("admission_waits", C.c_int64), ("mean_batch", C.c_double)]
+
+
 _H = C.c_void_p
 _P = C.c_void_p
 _sig = {
@@ -70,6 +86,15 @@ _sig = {
     "msrs_range_finder": (C.c_int32, [_H, _P, _P]),
     "msrs_assemble_coarse": (C.c_int32, [_H]),
     "msrs_solve_global": (C.c_int32, [_H, C.c_int32, _P, _P, _P]),
+    "msrs_solve_global_banded": (C.c_int32, [_H, C.c_int32, _P, _P, _P]),
+    "msrs_server_clock": (C.c_double, []),
+    "msrs_server_last_error": (C.c_char_p, []),
+    "msrs_server_create": (C.c_int32, [C.POINTER(_H), C.POINTER(_H), C.c_int32, C.POINTER(ServerConfig)]),
+    "msrs_server_submit": (C.c_int32, [_H, C.c_int32, _P, C.c_double, C.POINTER(C.c_int64)]),
+    "msrs_server_wait": (C.c_int32, [_H, C.c_int64, C.c_double]),
+    "msrs_server_fetch": (C.c_int32, [_H, C.c_int64, _P, C.POINTER(RequestInfo)]),
+    "msrs_server_get_stats": (C.c_int32, [_H, C.POINTER(ServerStats)]),
+    "msrs_server_destroy": (None, [_H]),
     "msrs_set_max_batch": (C.c_int32, [_H, C.c_int32]),
     "msrs_copy_omega": (C.c_int32, [_H, _P]),
     "msrs_query_layout": (C.c_int32, [_H, C.POINTER(Layout)]),
@@ -169,6 +194,11 @@ class Problem:
         s = None if stream is None else _stream(stream)
         self._check(_lib.msrs_solve_global(self.h, int(n_req), _ptr(f), _ptr(u), s))
 
+    def solve_global_banded(self, f, u, stream=None):
+        n_req = f.shape[0] if f.dim() == 2 else 1
+        s = None if stream is None else _stream(stream)
+        self._check(_lib.msrs_solve_global_banded(self.h, int(n_req), _ptr(f), _ptr(u), s))
+
     def layout(self) -> Layout:
         out = Layout()
         self._check(_lib.msrs_query_layout(self.h, C.byref(out)))
@@ -192,6 +222,93 @@ class Problem:
     def close(self):
         if getattr(self, "h", None):
             _lib.msrs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def server_clock() -> float:
+    return _lib.msrs_server_clock()
+
+
+class Server:
+    """A request server over resident problems (msrs_server_create ... destroy).
+
+    submit() takes boundary data in host memory (a float64 numpy array);
+    fetch() copies the solution into a host numpy array or a CUDA tensor and
+    returns the request's RequestInfo.
+    """
+
+    def __init__(self, problems, n_streams=0, max_batch=0, max_pending=0, slot_bytes=0, staging_bytes=0):
+        hs = (_H * len(problems))(*[p.h for p in problems])
+        cfg = ServerConfig(n_streams=n_streams, max_batch=max_batch, max_pending=max_pending, reserved=0,
+                           slot_bytes=slot_bytes, staging_bytes=staging_bytes)
+        h = _H()
+        st = _lib.msrs_server_create(C.byref(h), hs, len(problems), C.byref(cfg))
+        if st != OK:
+            raise MsrsError(st, _lib.msrs_server_last_error().decode())
+        self.h = h
+        self.problems = list(problems)
+
+    def _check(self, st):
+        if st != OK:
+            raise MsrsError(st, _lib.msrs_server_last_error().decode())
+
+    def submit(self, model: int, f, t_arrival: float = 0.0) -> int:
+        import numpy as np
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        t = C.c_int64()
+        self._check(_lib.msrs_server_submit(self.h, int(model), f.ctypes.data_as(C.c_void_p), float(t_arrival), C.byref(t)))
+        return t.value
+
+    def try_submit(self, model: int, f, t_arrival: float = 0.0):
+        """submit() that returns None instead of raising on ERR_BUSY (back-pressure)."""
+        try:
+            return self.submit(model, f, t_arrival)
+        except MsrsError as e:
+            if e.status == ERR_BUSY:
+                return None
+            raise
+
+    def wait(self, ticket: int, timeout: float = -1.0) -> bool:
+        st = _lib.msrs_server_wait(self.h, int(ticket), float(timeout))
+        if st == ERR_BUSY:
+            return False
+        self._check(st)
+        return True
+
+    def fetch(self, ticket: int, out=None) -> RequestInfo:
+        info = RequestInfo()
+        if out is None:
+            p = None
+        elif hasattr(out, "data_ptr"):
+            p = _ptr(out)
+        else:
+            import numpy as np
+            if not (out.dtype == np.float64 and out.flags["C_CONTIGUOUS"]):
+                raise ValueError("expected a contiguous float64 array")
+            p = out.ctypes.data_as(C.c_void_p)
+        self._check(_lib.msrs_server_fetch(self.h, int(ticket), p, C.byref(info)))
+        return info
+
+    def stats(self) -> ServerStats:
+        out = ServerStats()
+        self._check(_lib.msrs_server_get_stats(self.h, C.byref(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.msrs_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

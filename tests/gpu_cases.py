@@ -69,3 +69,40 @@ def run(cfg, precision, omegas=None, flags=0, phi=None, n_req=None, max_batch=No
 
 def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def resident(cfg, precision, max_batch=None):
+    """A handle with bases and coarse factor resident (caller closes it)."""
+    import torch
+    from paper_1807_08848_amd import msrs
+
+    kin = cfg["kind"] == "kinetic"
+    d = msrs.make_desc(msrs.KIND_KINETIC_DO if kin else msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"],
+                       list(cfg["overlap"]), cfg["s"], cfg["k"], precision=precision, seed=cfg["seed"],
+                       n_vel=cfg.get("n_vel", 0), eps=cfg.get("eps", 1.0),
+                       flags=msrs.FLAG_FULL_BASIS_ENDS if kin else 0)
+    pr = msrs.Problem(d)
+    try:
+        a = torch.tensor(np.asarray(cfg["coef"]), device="cuda:0", dtype=torch.float64)
+        pr.assemble_patch(a)
+        pr.sample_local_solutions()
+        pr.range_finder()
+        if max_batch:
+            pr.set_max_batch(max_batch)
+        pr.assemble_coarse()
+        torch.cuda.synchronize()
+        return pr
+    except Exception:
+        pr.close()
+        raise
+
+
+def bases(pr):
+    """Per-patch Q of a resident handle (host), in the oracle's patch dicts' shape."""
+    import torch
+    L = pr.layout()
+    infos = [pr.patch(p) for p in range(L.n_patches)]
+    Q = torch.empty(L.Q_total, device="cuda:0", dtype=torch.float64)
+    pr.range_finder(Q)
+    Qh = Q.cpu().numpy()
+    return [_unpack(Qh, i.Q_off, i.n_rows, i.n_cols) for i in infos]

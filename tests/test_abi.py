@@ -64,3 +64,23 @@ def test_no_device_is_reported_without_a_gpu():
     with pytest.raises(msrs.MsrsError) as e:
         msrs.Problem(msrs.make_desc(0, 128, 4, [8] * 16, 10, 6))
     assert e.value.status == msrs.ERR_NO_DEVICE
+
+
+def test_null_server_calls_fail_cleanly():
+    import ctypes as C
+    from paper_1807_08848_amd import msrs
+    L = msrs.lib
+    t = C.c_int64()
+    f = (C.c_double * 4)()
+    assert L.msrs_server_create(None, None, 0, None) == msrs.ERR_ARG
+    out = C.c_void_p()
+    assert L.msrs_server_create(C.byref(out), None, 0, None) == msrs.ERR_ARG
+    hs = (C.c_void_p * 1)(None)
+    assert L.msrs_server_create(C.byref(out), hs, 1, None) == msrs.ERR_ARG
+    assert "NULL" in L.msrs_server_last_error().decode()
+    assert L.msrs_server_submit(None, 0, f, 0.0, C.byref(t)) == msrs.ERR_ARG
+    assert L.msrs_server_wait(None, 1, 0.0) == msrs.ERR_ARG
+    assert L.msrs_server_fetch(None, 1, None, None) == msrs.ERR_ARG
+    assert L.msrs_solve_global_banded(None, 1, None, None, None) == msrs.ERR_ARG
+    L.msrs_server_destroy(None)
+    assert L.msrs_server_clock() > 0
