@@ -149,13 +149,11 @@ def run_serving(lams=(200, 500, 1000, 2000), seconds=2.0, seed_arrival=5):
     (all requests queued at once) and of the plain FP64 path (one request at
     a time: P~^T d and two band triangular solves, then the reconstruction).
     """
-    import threading
     import numpy as np
     import torch
     import synth
     from synth import configs
     from paper_1807_08848_amd import msrs
-    sys.setswitchinterval(1e-4)
     cfgs = [configs.elliptic_lognormal_512(), configs.elliptic_lognormal_1024()]
     models, setup = [], []
     for c in cfgs:
@@ -189,57 +187,51 @@ def run_serving(lams=(200, 500, 1000, 2000), seconds=2.0, seed_arrival=5):
         plain[c["name"]] = (time.perf_counter() - t0) / n * 1e3
     plain_rate = 2.0 / sum(plain.values()) * 1e3      # 50/50 mix, requests/s
 
-    def drive(srv, arrivals, mdl):
-        infos = [None] * len(arrivals)
-        tickets = [None] * len(arrivals)
-        ready = threading.Semaphore(0)
-
-        def fetcher():
-            for i in range(len(arrivals)):
-                ready.acquire()
-                infos[i] = srv.fetch(tickets[i], None)
-        th = threading.Thread(target=fetcher)
-        th.start()
-        for i, ta in enumerate(arrivals):
-            if ta > 0:
-                while msrs.server_clock() < ta:
-                    pass
-            while True:
-                t = srv.try_submit(int(mdl[i]), pool[mdl[i]][i % 64], float(ta))
-                if t is not None:
-                    break
-            tickets[i] = t
-            ready.release()
-        th.join()
-        return infos
+    def summary(infos, t_first):
+        lat = np.array([i.t_done - i.t_arrival for i in infos]) * 1e3
+        mdl = np.array([i.model for i in infos])
+        span = max(i.t_done for i in infos) - t_first
+        out = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "requests": len(infos), "solves_per_s": len(infos) / span,
+               "mean_batch": float(np.mean([i.batch_size for i in infos])),
+               "mean_ms": {"wait_admit": float(np.mean([i.t_admit - i.t_arrival for i in infos]) * 1e3),
+                           "wait_launch": float(np.mean([i.t_launch - i.t_admit for i in infos]) * 1e3),
+                           "device": float(np.mean([i.t_done - i.t_launch for i in infos]) * 1e3)}}
+        for m, c in enumerate(cfgs):
+            if np.any(mdl == m):
+                out["p50_ms_" + c["name"]] = float(np.percentile(lat[mdl == m], 50))
+                out["p99_ms_" + c["name"]] = float(np.percentile(lat[mdl == m], 99))
+        return out
 
     rng = np.random.default_rng(seed_arrival)
     res = {}
     with msrs.Server(models, n_streams=4, max_batch=32, slot_bytes=2 << 30) as srv:
-        drive(srv, [0.0] * 200, rng.integers(0, 2, 200))                       # warm-up
+        mdl = rng.integers(0, 2, 200)
+        srv.replay(mdl, [pool[m][i % 64] for i, m in enumerate(mdl)])          # warm-up
         for lam in lams:
             n = int(max(400, lam * seconds))
             mdl = rng.integers(0, 2, n)
             arr = msrs.server_clock() + 0.02 + np.cumsum(rng.exponential(1.0 / lam, n))
-            infos = drive(srv, list(arr), mdl)
-            lat = np.array([i.t_done - i.t_arrival for i in infos]) * 1e3
-            span = max(i.t_done for i in infos) - arr[0]
-            res[str(lam)] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                             "requests": n, "solves_per_s": n / span,
-                             "mean_batch": float(np.mean([i.batch_size for i in infos]))}
+            infos = srv.replay(mdl, [pool[m][i % 64] for i, m in enumerate(mdl)], arr)
+            res[str(lam)] = summary(infos, arr[0])
             print(f"[bench] serving lambda={lam}: p50 {res[str(lam)]['p50_ms']:.3f} ms, "
                   f"p99 {res[str(lam)]['p99_ms']:.3f} ms", file=sys.stderr, flush=True)
-        n = 4000
+        # saturation: the whole trace queued at once (back-pressure from the
+        # slot and staging budgets), completion rate of the device
+        n = 8000
         mdl = rng.integers(0, 2, n)
         t0 = msrs.server_clock()
-        infos = drive(srv, [0.0] * n, mdl)
-        sat = n / (max(i.t_done for i in infos) - t0)
+        infos = srv.replay(mdl, [pool[m][i % 64] for i, m in enumerate(mdl)])
+        sat_s = summary(infos, t0)
+        sat = sat_s["solves_per_s"]
+        sat_batch = sat_s["mean_batch"]
         st = srv.stats()
     out = {
         "workload": "serving over elliptic_lognormal_512 + elliptic_lognormal_1024 (50/50, Poisson arrivals)",
         "n_nodes": nn, "coarse_dim": [int(m.layout().coarse_dim) for m in models], "setup_s": setup,
         "rel_err_batched_vs_banded": acc, "open_loop": res,
-        "saturation_solves_per_s": sat, "plain_fp64_ms_per_request": plain,
+        "saturation_solves_per_s": sat, "saturation_mean_batch": sat_batch, "saturation": sat_s,
+        "plain_fp64_ms_per_request": plain,
         "plain_fp64_solves_per_s": plain_rate, "speedup_vs_plain": sat / plain_rate,
         "server": {"streams": 4, "max_batch": 32, "mean_batch": st.mean_batch, "max_in_flight": st.max_in_flight,
                    "admission_waits": st.admission_waits, "peak_slot_bytes": st.peak_slot_bytes},

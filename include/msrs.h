@@ -230,10 +230,11 @@ msrs_status msrs_assemble_coarse(msrs_handle h);
  * f_dev: device, n_req x n_bdry (request-major).  u_dev: device,
  * n_req x n_nodes.  stream: hipStream_t (as void*) for this call, NULL for
  * the handle's stream.  Elliptic nodes shared by several patches take the
- * partition-of-unity average.  Calls on different streams may overlap: each
- * takes one of four internal workspaces that is no longer in use on the
- * device, or fails with MSRS_ERR_BUSY.  Errors: ARG (n_req outside
- * [1, max_batch]), STATE, BUSY.
+ * partition-of-unity average.  Calls on one stream reuse one internal
+ * workspace in stream order; calls on up to four different streams may
+ * overlap, each taking a workspace that is no longer in use on the device,
+ * and a call that finds none fails with MSRS_ERR_BUSY.  Errors: ARG (n_req
+ * outside [1, max_batch]), STATE, BUSY.
  */
 msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev,
                               void* stream);
@@ -300,7 +301,8 @@ typedef struct msrs_server_config {
     int32_t n_streams;       /* batches in flight at once, 1..8 (0 -> 4) */
     int32_t max_batch;       /* requests per batch, 1..256 (0 -> 32) */
     int32_t max_pending;     /* submitted and not yet fetched requests at most (0 -> 4096) */
-    int32_t reserved;
+    int32_t idle_spin_us;    /* the worker polls for this long after its last activity before
+                                it sleeps (0 -> 10000; trades a host core for arrival latency) */
     size_t slot_bytes;       /* device bytes for request solutions (0 -> 1 GiB) */
     size_t staging_bytes;    /* pinned host bytes for queued boundary data (0 -> 64 MiB) */
 } msrs_server_config;
@@ -350,6 +352,27 @@ msrs_status msrs_server_create(msrs_server* out, const msrs_handle* models, int3
  */
 msrs_status msrs_server_submit(msrs_server s, int32_t model, const double* f_host, double t_arrival,
                                int64_t* ticket);
+
+/*
+ * Queue n requests in order under one lock (models[i], f_host[i] as in
+ * msrs_server_submit; t_arrival nullable).  Stops at the first request that
+ * cannot be queued and returns that request's error; *n_done requests were
+ * queued, with their tickets in tickets[0 .. *n_done).
+ */
+msrs_status msrs_server_submit_many(msrs_server s, int32_t n, const int32_t* models, const double* const* f_host,
+                                    const double* t_arrival, int64_t* tickets, int32_t* n_done);
+
+/*
+ * Replay an arrival trace (load generation and capacity measurement): queue
+ * request i (models[i], f_host[i]) once msrs_server_clock reaches
+ * t_arrival[i] (ascending; NULL: all at once), waiting out back-pressure, and
+ * return when every queued request has finished.  Solutions are discarded:
+ * a slot is released as soon as its request completes, and infos[i] (host,
+ * n records) receives the request's timestamps.  The calling thread spins
+ * between arrivals.  Errors: ARG, the first submission or request error.
+ */
+msrs_status msrs_server_replay(msrs_server s, int32_t n, const int32_t* models, const double* const* f_host,
+                               const double* t_arrival, msrs_request_info* infos);
 
 /* Wait until the request is solved (timeout_s < 0: no limit).  BUSY on time-out. */
 msrs_status msrs_server_wait(msrs_server s, int64_t ticket, double timeout_s);

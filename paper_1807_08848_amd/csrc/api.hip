@@ -492,6 +492,7 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
             for (int p = 0; p < c->n_patches; ++p) {
                 c->hc[p].col_off = off;
                 c->hc[p].ncols = c->hp[p].ncols;
+                c->hc[p].b_off = -1;
                 off += c->hp[p].ncols;
             }
             c->Np = off;
@@ -513,15 +514,37 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
             int kmax = 0;
             for (auto& d : c->hc) kmax = std::max(kmax, d.ncols);
             c->dc = dalloc<CoarseDesc>(*c, c->n_patches);
-            MSRS_HIP_CHECK(hipMemcpy(c->dc, c->hc.data(), sizeof(CoarseDesc) * c->n_patches, hipMemcpyHostToDevice));
             if (c->kind == kElliptic) {
                 c->tr_stride = 2LL * 4 * (c->N / c->M) * kmax;
                 c->tr = dalloc<double>(*c, (int64_t)c->n_patches * c->tr_stride);
             }
             c->band = dalloc<double>(*c, (int64_t)c->Np * (c->bw + 1));
-            c->Kop = dalloc<double>(*c, (int64_t)c->Np * c->n_bdry);
+            // patches with Dirichlet (inflow) rows and their columns of G_B
+            c->bpatch.clear();
+            std::vector<int32_t> bmap;
+            for (int p = 0; p < c->n_patches; ++p) {
+                bool bd;
+                if (c->kind == kElliptic) {
+                    const int m1 = p % c->M, m2 = p / c->M;
+                    bd = m1 == 0 || m2 == 0 || m1 == c->M - 1 || m2 == c->M - 1;
+                } else {
+                    bd = p == 0 || p == c->n_patches - 1;
+                }
+                if (!bd) continue;
+                c->hc[p].b_off = (int32_t)bmap.size();
+                c->bpatch.push_back(p);
+                for (int a = 0; a < c->hc[p].ncols; ++a) bmap.push_back(c->hc[p].col_off + a);
+            }
+            c->nB = (int)bmap.size();
+            MSRS_HIP_CHECK(hipMemcpy(c->dc, c->hc.data(), sizeof(CoarseDesc) * c->n_patches, hipMemcpyHostToDevice));
+            c->dbpatch = dalloc<int32_t>(*c, (int64_t)c->bpatch.size());
+            MSRS_HIP_CHECK(hipMemcpy(c->dbpatch, c->bpatch.data(), sizeof(int32_t) * c->bpatch.size(), hipMemcpyHostToDevice));
+            c->bmap = dalloc<int32_t>(*c, c->nB);
+            MSRS_HIP_CHECK(hipMemcpy(c->bmap, bmap.data(), sizeof(int32_t) * bmap.size(), hipMemcpyHostToDevice));
+            c->GB = dalloc<double>(*c, (int64_t)c->Np * c->nB);
             for (auto& w : c->ws) {
                 w.cbuf = dalloc<double>(*c, (int64_t)c->Np * kOutPerLaunch);
+                w.gbuf = dalloc<double>(*c, (int64_t)c->nB * kOutPerLaunch);
                 MSRS_HIP_CHECK(hipEventCreateWithFlags(&w.done, hipEventDisableTiming));
             }
             if (c->budget && (size_t)c->bytes > c->budget) return fail(c, MSRS_ERR_OOM, "coarse factor exceeds the HBM budget");
@@ -538,8 +561,12 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
     return st;
 }
 
-// A free online workspace (its last use on the device has completed), or null.
-static Ctx::OnlineWs* take_ws(Ctx* c) {
+// An online workspace that the call on stream st may use: one last used on
+// st (stream order puts this call after that use), else one whose last use
+// has completed on the device, else null.
+static Ctx::OnlineWs* take_ws(Ctx* c, hipStream_t st) {
+    for (auto& w : c->ws)
+        if (w.used && w.last == st) return &w;
     for (auto& w : c->ws) {
         if (!w.used) return &w;
         const hipError_t q = hipEventQuery(w.done);
@@ -556,20 +583,25 @@ static msrs_status solve_common(Ctx* c, int32_t n_req, const double* f_dev, doub
     if (!f_dev || !u_dev) return fail(c, MSRS_ERR_ARG, "f_dev / u_dev is NULL");
     try {
         hipStream_t st = stream ? (hipStream_t)stream : c->stream;
-        Ctx::OnlineWs* w = take_ws(c);
+        Ctx::OnlineWs* w = take_ws(c, st);
         if (!w) return fail(c, MSRS_ERR_BUSY, "every online workspace is in use by unfinished calls");
         if (banded) {
             StageTimer t(*c, MSRS_K_CSOLVE, st);
             for (int r = 0; r < n_req; ++r) coarse_banded(*c, f_dev + (int64_t)r * c->n_bdry, u_dev + r * c->n_nodes, w->cbuf, st);
         } else {
             std::vector<double*> u(n_req);
-            for (int r = 0; r < n_req; ++r) u[r] = u_dev + r * c->n_nodes;
+            std::vector<const double*> f(n_req);
+            for (int r = 0; r < n_req; ++r) {
+                u[r] = u_dev + r * c->n_nodes;
+                f[r] = f_dev + (int64_t)r * c->n_bdry;
+            }
             StageTimer t(*c, MSRS_K_CSOLVE, st);
-            coarse_apply(*c, n_req, f_dev, c->n_bdry, u.data(), w->cbuf, st);
+            coarse_apply(*c, n_req, f.data(), u.data(), w->gbuf, w->cbuf, st);
         }
         MSRS_HIP_CHECK(hipGetLastError());
         MSRS_HIP_CHECK(hipEventRecord(w->done, st));
         w->used = true;
+        w->last = st;
     } catch (const HipError& e) {
         return hip_fail(c, e);
     }

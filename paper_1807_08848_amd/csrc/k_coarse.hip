@@ -278,42 +278,12 @@ __global__ __launch_bounds__(1024) void band_solve_kernel(const double* __restri
     }
 }
 
-// ------------------------------------------------------------ Dirichlet columns
-// Column t of P~_D^T (global boundary datum t): in the unknowns of every patch
-// with a Dirichlet row at datum t, the basis values there.  Written into K
-// (Np x n_bdry, column-major) before the band solves turn it into the
-// solution operator.
-__global__ __launch_bounds__(kThreads) void dirichlet_cols_elliptic_kernel(const PatchDesc* pd, const CoarseDesc* cd,
-                                                                           const double* __restrict__ tr, int64_t tr_stride,
-                                                                           int M, int N, int Np, double* __restrict__ K) {
-    const int m = blockIdx.x;
-    const int m1 = m % M, m2 = m / M;
-    if (!(m1 == 0 || m1 == M - 1 || m2 == 0 || m2 == M - 1)) return;
-    const int nH = pd[m].nH;
-    const ElTr Tm{tr + (int64_t)m * tr_stride, nH, cd[m].ncols};
-    const int km = cd[m].ncols, om = cd[m].col_off;
-    for (int o = threadIdx.x; o < 4 * nH * km; o += kThreads) {
-        const int t = o / km, a = o % km;
-        int ii, jj;
-        kbnode(t, nH, ii, jj);
-        const int gx = m1 * nH + ii, gy = m2 * nH + jj;
-        if (gx == 0 || gx == N || gy == 0 || gy == N) K[(int64_t)gb_index(gx, gy, N) * Np + om + a] = Tm.val(ii, jj, a);
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void dirichlet_cols_kinetic_kernel(const PatchDesc* pd, const CoarseDesc* cd,
-                                                                          const double* __restrict__ Q_all, const double* __restrict__ vw,
-                                                                          int M, int nv, int Np, double* __restrict__ K) {
-    const int m = blockIdx.x;
-    if (m != 0 && m != M - 1) return;
-    const PatchDesc P = pd[m];
-    const int km = cd[m].ncols, om = cd[m].col_off, h = nv / 2;
-    const double* Q = Q_all + P.Q_off;
-    for (int o = threadIdx.x; o < nv * km; o += kThreads) {
-        const int j = o / km, a = o % km;
-        if (m == 0 && vw[j] > 0) K[(int64_t)(j - h) * Np + om + a] = Q[(int64_t)a * P.nrows + 0 * nv + j];
-        if (m == M - 1 && vw[j] < 0) K[(int64_t)(h + j) * Np + om + a] = Q[(int64_t)a * P.nrows + (P.nH + 1) * nv + j];
-    }
+// ------------------------------------------------------------ G_B set-up
+// GB (Np x nB, column-major) = unit columns e_{bmap[i]}; the band solves then
+// turn it into (P~^T P~)^{-1} restricted to the boundary-patch unknowns.
+__global__ void unit_cols_kernel(double* __restrict__ GB, int Np, int nB, const int32_t* __restrict__ bmap) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nB) GB[(int64_t)i * Np + bmap[i]] = 1.0;
 }
 
 // ------------------------------------------------------------ per-request rhs (banded path)
@@ -357,33 +327,87 @@ __global__ __launch_bounds__(kThreads) void rhs_kinetic_kernel(const PatchDesc* 
     }
 }
 
-// ------------------------------------------------------------ batched path: c = K f
-// c[r*Np + j] = sum_t K[t*Np + j] f[r*f_ld + t] for n_req requests.  A thread
-// owns unknown j and RB requests; K streams once per RB requests, f is
-// wave-uniform (scalar loads).
+// ------------------------------------------------------------ batched path
+// g = P~_D^T d for the requests of one launch: only the unknowns of patches
+// with Dirichlet rows are non-zero; g[r*nB + b_off(m) + a].  Grid (boundary
+// patch, request).  The boundary data are read where the caller holds them
+// (device memory, or the server's mapped pinned staging: each value crosses
+// the bus once per patch that touches it).
+__global__ __launch_bounds__(kThreads) void bdry_rhs_elliptic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ tr,
+                                                                     int64_t tr_stride, const int32_t* __restrict__ bpatch, int M, int N,
+                                                                     InPtrs in, int nB, double* __restrict__ g) {
+    const int m = bpatch[blockIdx.x], r = blockIdx.y;
+    const int m1 = m % M, m2 = m / M;
+    const int nH = pd[m].nH;
+    const ElTr Tm{tr + (int64_t)m * tr_stride, nH, cd[m].ncols};
+    const int km = cd[m].ncols, bo = cd[m].b_off;
+    const double* fr = in.f[r];
+    for (int a = threadIdx.x; a < km; a += kThreads) {
+        double s = 0.0;
+        for (int t = 0; t < 4 * nH; ++t) {
+            int ii, jj;
+            kbnode(t, nH, ii, jj);
+            const int gx = m1 * nH + ii, gy = m2 * nH + jj;
+            if (gx == 0 || gx == N || gy == 0 || gy == N) s += Tm.val(ii, jj, a) * fr[gb_index(gx, gy, N)];
+        }
+        g[(int64_t)r * nB + bo + a] = s;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void bdry_rhs_kinetic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ Q_all,
+                                                                    const double* __restrict__ vw, const int32_t* __restrict__ bpatch, int M,
+                                                                    int nv, InPtrs in, int nB, double* __restrict__ g) {
+    const int m = bpatch[blockIdx.x], r = blockIdx.y;
+    const PatchDesc P = pd[m];
+    const int km = cd[m].ncols, bo = cd[m].b_off, h = nv / 2;
+    const double* Q = Q_all + P.Q_off;
+    const double* fr = in.f[r];
+    for (int a = threadIdx.x; a < km; a += kThreads) {
+        double s = 0.0;
+        for (int j = 0; j < nv; ++j) {
+            if (m == 0 && vw[j] > 0) s += Q[(int64_t)a * P.nrows + 0 * nv + j] * fr[j - h];
+            if (m == M - 1 && vw[j] < 0) s += Q[(int64_t)a * P.nrows + (P.nH + 1) * nv + j] * fr[h + j];
+        }
+        g[(int64_t)r * nB + bo + a] = s;
+    }
+}
+
+// c[r*Np + j] = sum_i GB[i*Np + j] g[r*nB + i] for the requests of one launch.
+// A workgroup owns 64 rows (one per lane) and RB requests; its four waves
+// take every fourth column, so G_B streams once per RB requests with
+// coalesced 512-byte rows, g is wave-uniform (scalar loads), and the four
+// partial sums meet in LDS in a fixed order.
 template <int RB>
-__global__ __launch_bounds__(kThreads) void apply_K_kernel(const double* __restrict__ K, int Np, int nb,
-                                                           const double* __restrict__ f, int64_t f_ld, int n_req,
-                                                           double* __restrict__ c) {
-    const int j = blockIdx.x * kThreads + threadIdx.x;
+__global__ __launch_bounds__(kThreads) void apply_G_kernel(const double* __restrict__ GB, int Np, int nB,
+                                                           const double* __restrict__ g, int n_req, double* __restrict__ c) {
+    __shared__ double red[3][RB][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
     const int r0 = blockIdx.y * RB;
-    if (j >= Np) return;
     const int nr = min(RB, n_req - r0);
-    const double* fr[RB];
+    const int jj = min(j, Np - 1);
+    const double* gr[RB];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) fr[r] = f + (int64_t)(r0 + min(r, nr - 1)) * f_ld;
+    for (int r = 0; r < RB; ++r) gr[r] = g + (int64_t)(r0 + min(r, nr - 1)) * nB;
     double acc[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) acc[r] = 0.0;
-#pragma unroll 4
-    for (int t = 0; t < nb; ++t) {
-        const double kv = K[(int64_t)t * Np + j];
+#pragma unroll 2
+    for (int i = w; i < nB; i += 4) {
+        const double gv = GB[(int64_t)i * Np + jj];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) acc[r] = fma(kv, fr[r][t], acc[r]);
+        for (int r = 0; r < RB; ++r) acc[r] = fma(gv, gr[r][i], acc[r]);
     }
+    if (w > 0) {
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
-        if (r < nr) c[(int64_t)(r0 + r) * Np + j] = acc[r];
+        for (int r = 0; r < RB; ++r) red[w - 1][r][lane] = acc[r];
+    }
+    __syncthreads();
+    if (w == 0 && j < Np) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            if (r < nr) c[(int64_t)(r0 + r) * Np + j] = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+    }
 }
 
 // ------------------------------------------------------------ reconstruction
@@ -451,26 +475,26 @@ __global__ __launch_bounds__(kThreads) void recon_kinetic_kernel(const PatchDesc
 }
 
 // ------------------------------------------------------------ host side
-// Set-up: traces, normal matrix, band Cholesky, then the solution operator
-// K = (P~^T P~)^{-1} P~_D^T (Np x n_bdry, column-major).  The right-hand side
-// d of the least-squares system vanishes outside the Dirichlet (inflow) rows,
-// so every request's coefficients are c = K f: one dense product instead of
-// two sequential band solves per request.
+// Set-up: traces, normal matrix, band Cholesky, then G_B: the columns of
+// (P~^T P~)^{-1} at the unknowns of patches with Dirichlet (inflow) rows
+// (Np x nB, column-major).  The right-hand side d of the least-squares system
+// vanishes outside those rows, so P~^T d lives on the same unknowns and every
+// request's coefficients are c = G_B (P~_D^T f): a short sparse product and
+// one dense pass instead of two sequential band solves per request.
 void coarse_setup(Ctx& c) {
     StageTimer t(c, MSRS_K_COARSE);
     const int64_t nband = (int64_t)c.Np * (c.bw + 1);
     hipLaunchKernelGGL(fill_kernel, dim3(256), dim3(256), 0, c.stream, c.band, nband, 0.0);
-    hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, c.stream, c.Kop, (int64_t)c.Np * c.n_bdry, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, c.stream, c.GB, (int64_t)c.Np * c.nB, 0.0);
+    hipLaunchKernelGGL(unit_cols_kernel, dim3((c.nB + 255) / 256), dim3(256), 0, c.stream, c.GB, c.Np, c.nB, c.bmap);
     if (c.kind == kElliptic) {
         hipLaunchKernelGGL(traces_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.coef_copy, c.N, c.Q, c.tr, c.tr_stride);
         hipLaunchKernelGGL(normal_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.tr, c.tr_stride, c.M, c.N, c.band, c.bw);
-        hipLaunchKernelGGL(dirichlet_cols_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.tr, c.tr_stride, c.M, c.N, c.Np, c.Kop);
     } else {
         hipLaunchKernelGGL(normal_kinetic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.Q, c.vw, c.M, c.nv, c.band, c.bw);
-        hipLaunchKernelGGL(dirichlet_cols_kinetic_kernel, dim3(c.n_patches), dim3(kThreads), 0, c.stream, c.dp, c.dc, c.Q, c.vw, c.M, c.nv, c.Np, c.Kop);
     }
     hipLaunchKernelGGL(band_cholesky_kernel, dim3(1), dim3(1024), 0, c.stream, c.band, c.Np, c.bw, c.dflags);
-    hipLaunchKernelGGL(band_solve_kernel, dim3((c.n_bdry + 63) / 64), dim3(1024), 0, c.stream, c.band, c.Np, c.bw, c.Kop, c.n_bdry);
+    hipLaunchKernelGGL(band_solve_kernel, dim3((c.nB + 63) / 64), dim3(1024), 0, c.stream, c.band, c.Np, c.bw, c.GB, c.nB);
 }
 
 static void launch_recon(const Ctx& c, const double* cbuf, int n_req, const OutPtrs& out, hipStream_t st) {
@@ -485,13 +509,25 @@ static void launch_recon(const Ctx& c, const double* cbuf, int n_req, const OutP
     }
 }
 
-void coarse_apply(const Ctx& c, int n_req, const double* f, int64_t f_ld, double* const* u, double* cbuf, hipStream_t st) {
+void coarse_apply(const Ctx& c, int n_req, const double* const* f, double* const* u, double* gbuf, double* cbuf,
+                  hipStream_t st) {
+    constexpr int RB = 16;
     for (int r0 = 0; r0 < n_req; r0 += kOutPerLaunch) {
         const int nr = std::min(kOutPerLaunch, n_req - r0);
-        const dim3 g((c.Np + kThreads - 1) / kThreads, (nr + 7) / 8);
-        hipLaunchKernelGGL(apply_K_kernel<8>, g, dim3(kThreads), 0, st, c.Kop, c.Np, c.n_bdry, f + r0 * f_ld, f_ld, nr, cbuf);
+        InPtrs in{};
         OutPtrs out{};
-        for (int r = 0; r < nr; ++r) out.u[r] = u[r0 + r];
+        for (int r = 0; r < nr; ++r) {
+            in.f[r] = f[r0 + r];
+            out.u[r] = u[r0 + r];
+        }
+        const dim3 gb((unsigned)c.bpatch.size(), nr);
+        if (c.kind == kElliptic)
+            hipLaunchKernelGGL(bdry_rhs_elliptic_kernel, gb, dim3(kThreads), 0, st, c.dp, c.dc, c.tr, c.tr_stride, c.dbpatch, c.M, c.N, in,
+                               c.nB, gbuf);
+        else
+            hipLaunchKernelGGL(bdry_rhs_kinetic_kernel, gb, dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.vw, c.dbpatch, c.M, c.nv, in, c.nB, gbuf);
+        const dim3 ga((c.Np + 63) / 64, (nr + RB - 1) / RB);
+        hipLaunchKernelGGL(apply_G_kernel<RB>, ga, dim3(kThreads), 0, st, c.GB, c.Np, c.nB, gbuf, nr, cbuf);
         launch_recon(c, cbuf, nr, out, st);
     }
 }

@@ -19,8 +19,10 @@ constexpr int kChunkLines = 8;     // block rows per workgroup of the lifting an
 constexpr int kOutPerLaunch = 32;  // requests per reconstruction launch
 constexpr int kOnlineWs = 4;       // concurrent msrs_solve_global calls per handle
 
-// Output pointers of the requests of one reconstruction launch, passed by
-// value in the kernel arguments (no device pointer array to stage).
+// Input and output pointers of the requests of one launch, passed by value in
+// the kernel arguments (no device pointer array to stage).  Inputs may be
+// device memory or mapped pinned host memory.
+struct InPtrs { const double* f[kOutPerLaunch]; };
 struct OutPtrs { double* u[kOutPerLaunch]; };
 
 // One buffered patch, in the block-row ("line") view of the local problem.
@@ -60,7 +62,8 @@ struct CoarseDesc {
     int32_t col_off;          // first unknown of the patch in the least-squares system
     int32_t ncols;            // its unknowns
     int32_t nbr[8];           // elliptic: patches that share an edge or vertex (-1 if none)
-    int32_t pad_[6];
+    int32_t b_off;            // first column of the patch in G_B (boundary patches), else -1
+    int32_t pad_[5];
 };
 
 enum Kind { kElliptic = 0, kKinetic = 1 };
@@ -132,11 +135,21 @@ struct Ctx {
     CoarseDesc* dc = nullptr;
     double* tr = nullptr;         // traces (values, fluxes)
     double* band = nullptr;       // normal matrix, then its Cholesky factor (lower band)
-    double* Kop = nullptr;        // solution operator (P~^T P~)^{-1} P~_D^T, Np x n_bdry column-major
+    double* GB = nullptr;         // (P~^T P~)^{-1} restricted to the columns of boundary-patch unknowns, Np x nB
+    int nB = 0;                   // unknowns of the patches with Dirichlet / inflow rows
+    std::vector<int32_t> bpatch;  // those patches (host), and on the device:
+    int32_t* dbpatch = nullptr;
+    int32_t* bmap = nullptr;      // column i of G_B -> its unknown in the least-squares system
     int64_t tr_stride = 0;        // doubles per patch of tr
     // online workspaces: msrs_solve_global calls on different streams take
     // distinct ones; a workspace is free once its event has completed
-    struct OnlineWs { double* cbuf = nullptr; hipEvent_t done = nullptr; bool used = false; };
+    struct OnlineWs {
+        double* cbuf = nullptr;
+        double* gbuf = nullptr;
+        hipEvent_t done = nullptr;   // recorded after the last use
+        hipStream_t last = nullptr;  // stream of the last use (stream order makes reuse there safe)
+        bool used = false;
+    };
     OnlineWs ws[kOnlineWs];
     int served = 0;               // servers holding this handle (offline and set-up calls refused)
     int32_t n_bdry = 0;
@@ -167,10 +180,12 @@ void launch_clear_conv(Ctx& c);
 
 // coarse (k_coarse.hip)
 void coarse_setup(Ctx& c);     // traces, normal matrix, Cholesky (enqueued)
-// Batched path: n_req requests, boundary data f (request r at f + r*f_ld,
-// device), outputs u[r] (device), coefficient workspace cbuf (Np x
-// kOutPerLaunch).  Reads the handle only, so several streams may run it.
-void coarse_apply(const Ctx& c, int n_req, const double* f, int64_t f_ld, double* const* u, double* cbuf, hipStream_t st);
+// Batched path: n_req requests, boundary data f[r] (device or mapped pinned
+// host memory), outputs u[r] (device), workspaces gbuf (nB x kOutPerLaunch)
+// and cbuf (Np x kOutPerLaunch).  Reads the handle only, so several streams
+// may run it at once.
+void coarse_apply(const Ctx& c, int n_req, const double* const* f, double* const* u, double* gbuf, double* cbuf,
+                  hipStream_t st);
 // Banded path: one request by P~^T d and two band triangular solves; cbuf Np.
 void coarse_banded(const Ctx& c, const double* f, double* u, double* cbuf, hipStream_t st);
 

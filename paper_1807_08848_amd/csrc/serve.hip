@@ -35,18 +35,6 @@ double now_s() {
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-// Boundary data of the requests of one gather launch (device addresses of
-// pinned host staging), passed by value in the kernel arguments.
-struct InPtrs { const double* f[kOutPerLaunch]; };
-
-// fbuf[r * nb + t] = in.f[r][t]: one coalesced read of each request's
-// boundary data from pinned host memory into the batch's device buffer.
-__global__ __launch_bounds__(kThreads) void gather_requests_kernel(InPtrs in, int nb, double* __restrict__ fbuf) {
-    const int t = blockIdx.x * kThreads + threadIdx.x;
-    const int r = blockIdx.y;
-    if (t < nb) fbuf[(int64_t)r * nb + t] = in.f[r][t];
-}
-
 enum ReqState { kWaiting = 0, kAdmitted = 1, kRunning = 2, kDone = 3, kFailed = 4 };
 
 struct Req {
@@ -57,14 +45,16 @@ struct Req {
     int64_t stage_off = -1, stage_bytes = 0;
     int batch = 0, stream = -1;
     bool stalled = false, fetching = false;
+    msrs_request_info* discard_info = nullptr;   // replayed request: record here and release at completion
+    int64_t* discard_count = nullptr;            // ... and count it for its replay call
     double t_arrival = 0, t_admit = 0, t_launch = 0, t_done = 0;
 };
 
 struct Lane {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
-    double* fbuf = nullptr;   // max_batch x max n_bdry
     double* cbuf = nullptr;   // max Np x kOutPerLaunch
+    double* gbuf = nullptr;   // max nB x kOutPerLaunch
     std::vector<int64_t> ids;
     bool busy = false;
 };
@@ -75,6 +65,7 @@ struct msrs_server_s {
     std::vector<Ctx*> models;
     int device = 0;
     int n_streams = 4, max_batch = 32, max_pending = 4096;
+    double idle_spin_s = 0.01;
     char* dslots = nullptr;
     serve::Arena slots;
     char* hstage = nullptr;      // pinned host
@@ -106,6 +97,17 @@ msrs_status sfail(msrs_status st, const std::string& msg) {
     return st;
 }
 
+void fill_info(const Req& r, msrs_status st, msrs_request_info* info) {
+    info->model = r.model;
+    info->status = st;
+    info->batch_size = r.batch;
+    info->stream = r.stream;
+    info->t_arrival = r.t_arrival;
+    info->t_admit = r.t_admit;
+    info->t_launch = r.t_launch;
+    info->t_done = r.t_done;
+}
+
 // Worker side: mark every request of a failed server and stop launching.
 void fail_all(msrs_server_s* s, msrs_status st, const std::string& msg) {
     if (s->fatal == MSRS_OK) {
@@ -123,24 +125,32 @@ void fail_all(msrs_server_s* s, msrs_status st, const std::string& msg) {
             r.state = kFailed;
             r.status = st;
         }
+    // replayed requests report through their info records
+    for (auto it = s->reqs.begin(); it != s->reqs.end();) {
+        Req& r = it->second;
+        if (r.discard_info && r.state == kFailed) {
+            fill_info(r, r.status, r.discard_info);
+            if (r.slot_off >= 0) s->slots.release(r.slot_off, r.slot_bytes);
+            if (r.stage_off >= 0) s->stage.release(r.stage_off, r.stage_bytes);
+            *r.discard_count += 1;
+            it = s->reqs.erase(it);
+        } else {
+            ++it;
+        }
+    }
 }
 
 void launch_batch(msrs_server_s* s, int k, const std::vector<serve::Scheduler::Item>& b) {
     Lane& L = s->lanes[k];
     const Ctx& c = *s->models[b[0].model];
-    const int n = (int)b.size(), nb = c.n_bdry;
+    const int n = (int)b.size();
     const double t = now_s();
     std::vector<double*> u(n);
-    for (int r0 = 0; r0 < n; r0 += kOutPerLaunch) {
-        const int nr = std::min(kOutPerLaunch, n - r0);
-        InPtrs in{};
-        for (int r = 0; r < nr; ++r) in.f[r] = (const double*)(s->hstage_dev + s->reqs[b[r0 + r].id].stage_off);
-        hipLaunchKernelGGL(gather_requests_kernel, dim3((nb + kThreads - 1) / kThreads, nr), dim3(kThreads), 0, L.st, in, nb,
-                           L.fbuf + (int64_t)r0 * nb);
-    }
+    std::vector<const double*> f(n);
     L.ids.clear();
     for (int r = 0; r < n; ++r) {
         Req& q = s->reqs[b[r].id];
+        f[r] = (const double*)(s->hstage_dev + q.stage_off);   // read by the kernels from pinned memory
         u[r] = (double*)(s->dslots + q.slot_off);
         q.state = kRunning;
         q.t_launch = t;
@@ -148,7 +158,7 @@ void launch_batch(msrs_server_s* s, int k, const std::vector<serve::Scheduler::I
         q.stream = k;
         L.ids.push_back(b[r].id);
     }
-    coarse_apply(c, n, L.fbuf, nb, u.data(), L.cbuf, L.st);
+    coarse_apply(c, n, f.data(), u.data(), L.gbuf, L.cbuf, L.st);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(L.ev, L.st);
     if (e != hipSuccess) throw HipError(e, "batch launch", __FILE__, __LINE__);
@@ -162,6 +172,7 @@ void launch_batch(msrs_server_s* s, int k, const std::vector<serve::Scheduler::I
 void worker_main(msrs_server_s* s) {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
+    double last_active = now_s();
     for (;;) {
         bool done_any = false, busy = false;
         try {
@@ -173,11 +184,18 @@ void worker_main(msrs_server_s* s) {
                 if (q != hipSuccess) throw HipError(q, "hipEventQuery", __FILE__, __LINE__);
                 const double t = now_s();
                 for (int64_t id : L.ids) {
-                    Req& r = s->reqs[id];
+                    auto rit = s->reqs.find(id);
+                    Req& r = rit->second;
                     r.state = kDone;
                     r.t_done = t;
                     s->stage.release(r.stage_off, r.stage_bytes);
                     r.stage_off = -1;
+                    if (r.discard_info) {
+                        fill_info(r, MSRS_OK, r.discard_info);
+                        s->slots.release(r.slot_off, r.slot_bytes);
+                        *r.discard_count += 1;
+                        s->reqs.erase(rit);
+                    }
                 }
                 s->n_completed += (int64_t)L.ids.size();
                 s->in_flight -= (int64_t)L.ids.size();
@@ -223,14 +241,18 @@ void worker_main(msrs_server_s* s) {
             busy = false;
         }
         if (s->stop && !busy) break;
-        if (busy) {
-            // batches in flight: poll their events (a timed wait would add
-            // the kernel's timer slack to every completion)
+        const double tn = now_s();
+        if (busy || done_any) last_active = tn;
+        if (busy || tn - last_active < s->idle_spin_s) {
+            // batches in flight, or recently active: poll (a timed or
+            // notified wait would add the scheduler's wake-up latency to
+            // every completion and arrival)
             lk.unlock();
             std::this_thread::yield();
             lk.lock();
-        } else if (!done_any) {
+        } else {
             s->cv_work.wait(lk);
+            last_active = now_s();
         }
     }
 }
@@ -254,11 +276,13 @@ msrs_status msrs_server_create(msrs_server* out, const msrs_handle* models, int3
     const int n_streams = d.n_streams ? d.n_streams : 4;
     const int max_batch = d.max_batch ? d.max_batch : 32;
     const int max_pending = d.max_pending ? d.max_pending : 4096;
+    const int idle_spin_us = d.idle_spin_us ? d.idle_spin_us : 10000;
     const size_t slot_bytes = d.slot_bytes ? d.slot_bytes : ((size_t)1 << 30);
     const size_t staging_bytes = d.staging_bytes ? d.staging_bytes : ((size_t)64 << 20);
     if (n_streams < 1 || n_streams > kMaxStreams) return sfail(MSRS_ERR_ARG, "n_streams must be in [1, 8]");
     if (max_batch < 1 || max_batch > kMaxBatch) return sfail(MSRS_ERR_ARG, "max_batch must be in [1, 256]");
     if (max_pending < 1) return sfail(MSRS_ERR_ARG, "max_pending must be positive");
+    if (idle_spin_us < 0) return sfail(MSRS_ERR_ARG, "idle_spin_us must not be negative");
     int dev0 = -1;
     for (int i = 0; i < n_models; ++i) {
         Ctx* c = models[i];
@@ -278,6 +302,7 @@ msrs_status msrs_server_create(msrs_server* out, const msrs_handle* models, int3
     s->n_streams = n_streams;
     s->max_batch = max_batch;
     s->max_pending = max_pending;
+    s->idle_spin_s = idle_spin_us * 1e-6;
     s->sched = serve::Scheduler(n_models);
     msrs_status st = MSRS_OK;
     std::string msg;
@@ -289,11 +314,10 @@ msrs_status msrs_server_create(msrs_server* out, const msrs_handle* models, int3
         }
         return r == hipSuccess;
     };
-    int nb_max = 0;
-    int64_t np_max = 0;
+    int64_t np_max = 0, nB_max = 0;
     for (Ctx* c : s->models) {
-        nb_max = std::max(nb_max, (int)c->n_bdry);
         np_max = std::max<int64_t>(np_max, c->Np);
+        nB_max = std::max<int64_t>(nB_max, c->nB);
     }
     if (chk(hipSetDevice(dev0), "hipSetDevice") && chk(hipMalloc((void**)&s->dslots, slot_bytes), "hipMalloc slots")) {
         s->dallocs.push_back(s->dslots);
@@ -308,8 +332,8 @@ msrs_status msrs_server_create(msrs_server* out, const msrs_handle* models, int3
         if (e != hipSuccess) break;
         chk(hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking), "hipStreamCreate");
         chk(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming), "hipEventCreate");
-        if (chk(hipMalloc((void**)&L.fbuf, sizeof(double) * (size_t)max_batch * nb_max), "hipMalloc fbuf")) s->dallocs.push_back(L.fbuf);
         if (chk(hipMalloc((void**)&L.cbuf, sizeof(double) * (size_t)np_max * kOutPerLaunch), "hipMalloc cbuf")) s->dallocs.push_back(L.cbuf);
+        if (chk(hipMalloc((void**)&L.gbuf, sizeof(double) * (size_t)nB_max * kOutPerLaunch), "hipMalloc gbuf")) s->dallocs.push_back(L.gbuf);
     }
     if (e != hipSuccess) {
         st = e == hipErrorOutOfMemory ? MSRS_ERR_OOM : MSRS_ERR_HIP;
@@ -322,15 +346,18 @@ msrs_status msrs_server_create(msrs_server* out, const msrs_handle* models, int3
     return MSRS_OK;
 }
 
-msrs_status msrs_server_submit(msrs_server s, int32_t model, const double* f_host, double t_arrival, int64_t* ticket) {
-    if (!valid(s)) return sfail(MSRS_ERR_ARG, "server is NULL");
-    if (!f_host || !ticket) return sfail(MSRS_ERR_ARG, "f_host / ticket is NULL");
+}  // extern "C"
+
+namespace {
+// Queue one request; the caller holds s->mu.
+msrs_status submit_locked(msrs_server s, int32_t model, const double* f_host, double t_arrival, int64_t* ticket,
+                          msrs_request_info* discard_info = nullptr, int64_t* discard_count = nullptr) {
+    if (!f_host) return sfail(MSRS_ERR_ARG, "f_host is NULL");
     if (model < 0 || model >= (int)s->models.size()) return sfail(MSRS_ERR_ARG, "model index out of range");
-    const Ctx& c = *s->models[model];
-    std::unique_lock<std::mutex> lk(s->mu);
     if (s->fatal != MSRS_OK) return sfail(s->fatal, s->fatal_msg);
     if (s->stop) return sfail(MSRS_ERR_STATE, "server is shutting down");
     if ((int64_t)s->reqs.size() >= s->max_pending) return sfail(MSRS_ERR_BUSY, "max_pending requests are unfetched");
+    const Ctx& c = *s->models[model];
     const int64_t sb = (int64_t)c.n_bdry * 8;
     const int64_t off = s->stage.alloc(sb);
     if (off < 0) return sfail(MSRS_ERR_BUSY, "host staging for boundary data is full");
@@ -342,11 +369,81 @@ msrs_status msrs_server_submit(msrs_server s, int32_t model, const double* f_hos
     r.stage_bytes = sb;
     r.slot_bytes = c.n_nodes * 8;
     r.t_arrival = t_arrival > 0 ? t_arrival : now_s();
+    r.discard_info = discard_info;
+    r.discard_count = discard_count;
     s->sched.push(id, model, r.slot_bytes);
     s->n_submitted += 1;
     *ticket = id;
-    lk.unlock();
-    s->cv_work.notify_one();
+    return MSRS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+msrs_status msrs_server_submit(msrs_server s, int32_t model, const double* f_host, double t_arrival, int64_t* ticket) {
+    if (!valid(s)) return sfail(MSRS_ERR_ARG, "server is NULL");
+    if (!ticket) return sfail(MSRS_ERR_ARG, "ticket is NULL");
+    msrs_status st;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        st = submit_locked(s, model, f_host, t_arrival, ticket);
+    }
+    if (st == MSRS_OK) s->cv_work.notify_one();
+    return st;
+}
+
+msrs_status msrs_server_submit_many(msrs_server s, int32_t n, const int32_t* models, const double* const* f_host,
+                                    const double* t_arrival, int64_t* tickets, int32_t* n_done) {
+    if (!valid(s)) return sfail(MSRS_ERR_ARG, "server is NULL");
+    if (n < 0 || (n > 0 && (!models || !f_host || !tickets)) || !n_done) return sfail(MSRS_ERR_ARG, "NULL argument");
+    msrs_status st = MSRS_OK;
+    int k = 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (; k < n; ++k) {
+            st = submit_locked(s, models[k], f_host[k], t_arrival ? t_arrival[k] : 0.0, &tickets[k]);
+            if (st != MSRS_OK) break;
+        }
+    }
+    *n_done = k;
+    if (k > 0) s->cv_work.notify_one();
+    return st;
+}
+
+msrs_status msrs_server_replay(msrs_server s, int32_t n, const int32_t* models, const double* const* f_host,
+                               const double* t_arrival, msrs_request_info* infos) {
+    if (!valid(s)) return sfail(MSRS_ERR_ARG, "server is NULL");
+    if (n < 0 || (n > 0 && (!models || !f_host || !infos))) return sfail(MSRS_ERR_ARG, "NULL argument");
+    for (int i = 0; i < n; ++i) {
+        if (models[i] < 0 || models[i] >= (int)s->models.size()) return sfail(MSRS_ERR_ARG, "model index out of range");
+        if (!f_host[i]) return sfail(MSRS_ERR_ARG, "f_host has a NULL entry");
+    }
+    int64_t finished = 0;   // guarded by s->mu
+    msrs_status st = MSRS_OK;
+    int k = 0;
+    for (; k < n; ++k) {
+        const double ta = t_arrival ? t_arrival[k] : 0.0;
+        if (ta > 0)
+            while (now_s() < ta) {
+            }
+        for (;;) {
+            int64_t ticket;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                st = submit_locked(s, models[k], f_host[k], ta, &ticket, &infos[k], &finished);
+            }
+            if (st != MSRS_ERR_BUSY) break;
+            std::this_thread::yield();   // back-pressure: wait for staging / pending room
+        }
+        if (st != MSRS_OK) break;
+        s->cv_work.notify_one();
+    }
+    // every queued request of this call reports through its info record
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return finished >= k; });
+    if (st != MSRS_OK) return st;
+    for (int i = 0; i < n; ++i)
+        if (infos[i].status != MSRS_OK) return sfail(infos[i].status, s->fatal_msg.empty() ? "request failed" : s->fatal_msg);
     return MSRS_OK;
 }
 
@@ -354,7 +451,7 @@ msrs_status msrs_server_wait(msrs_server s, int64_t ticket, double timeout_s) {
     if (!valid(s)) return sfail(MSRS_ERR_ARG, "server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return sfail(MSRS_ERR_ARG, "unknown ticket");
+    if (it == s->reqs.end() || it->second.discard_info) return sfail(MSRS_ERR_ARG, "unknown ticket");
     auto ready = [&] { return it->second.state >= kDone; };
     if (timeout_s < 0) s->cv_done.wait(lk, ready);
     else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) return sfail(MSRS_ERR_BUSY, "request not finished");
@@ -366,22 +463,13 @@ msrs_status msrs_server_fetch(msrs_server s, int64_t ticket, double* u_out, msrs
     if (!valid(s)) return sfail(MSRS_ERR_ARG, "server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return sfail(MSRS_ERR_ARG, "unknown ticket");
+    if (it == s->reqs.end() || it->second.discard_info) return sfail(MSRS_ERR_ARG, "unknown ticket");
     if (it->second.fetching) return sfail(MSRS_ERR_ARG, "ticket is being fetched by another call");
     it->second.fetching = true;
     s->cv_done.wait(lk, [&] { return it->second.state >= kDone; });
     Req r = it->second;
     msrs_status st = r.state == kFailed ? r.status : MSRS_OK;
-    if (info) {
-        info->model = r.model;
-        info->status = st;
-        info->batch_size = r.batch;
-        info->stream = r.stream;
-        info->t_arrival = r.t_arrival;
-        info->t_admit = r.t_admit;
-        info->t_launch = r.t_launch;
-        info->t_done = r.t_done;
-    }
+    if (info) fill_info(r, st, info);
     if (st == MSRS_OK && u_out) {
         // the slot stays held (and unlisted for reuse) while the copy runs
         lk.unlock();

@@ -61,7 +61,7 @@ class Stats(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("n_streams", C.c_int32), ("max_batch", C.c_int32), ("max_pending", C.c_int32),
-                ("reserved", C.c_int32), ("slot_bytes", C.c_size_t), ("staging_bytes", C.c_size_t)]
+                ("idle_spin_us", C.c_int32), ("slot_bytes", C.c_size_t), ("staging_bytes", C.c_size_t)]
 
 
 class RequestInfo(C.Structure):
@@ -91,6 +91,8 @@ _sig = {
     "msrs_server_last_error": (C.c_char_p, []),
     "msrs_server_create": (C.c_int32, [C.POINTER(_H), C.POINTER(_H), C.c_int32, C.POINTER(ServerConfig)]),
     "msrs_server_submit": (C.c_int32, [_H, C.c_int32, _P, C.c_double, C.POINTER(C.c_int64)]),
+    "msrs_server_submit_many": (C.c_int32, [_H, C.c_int32, _P, _P, _P, _P, C.POINTER(C.c_int32)]),
+    "msrs_server_replay": (C.c_int32, [_H, C.c_int32, _P, _P, _P, C.POINTER(RequestInfo)]),
     "msrs_server_wait": (C.c_int32, [_H, C.c_int64, C.c_double]),
     "msrs_server_fetch": (C.c_int32, [_H, C.c_int64, _P, C.POINTER(RequestInfo)]),
     "msrs_server_get_stats": (C.c_int32, [_H, C.POINTER(ServerStats)]),
@@ -249,10 +251,11 @@ class Server:
     returns the request's RequestInfo.
     """
 
-    def __init__(self, problems, n_streams=0, max_batch=0, max_pending=0, slot_bytes=0, staging_bytes=0):
+    def __init__(self, problems, n_streams=0, max_batch=0, max_pending=0, slot_bytes=0, staging_bytes=0,
+                 idle_spin_us=0):
         hs = (_H * len(problems))(*[p.h for p in problems])
-        cfg = ServerConfig(n_streams=n_streams, max_batch=max_batch, max_pending=max_pending, reserved=0,
-                           slot_bytes=slot_bytes, staging_bytes=staging_bytes)
+        cfg = ServerConfig(n_streams=n_streams, max_batch=max_batch, max_pending=max_pending,
+                           idle_spin_us=idle_spin_us, slot_bytes=slot_bytes, staging_bytes=staging_bytes)
         h = _H()
         st = _lib.msrs_server_create(C.byref(h), hs, len(problems), C.byref(cfg))
         if st != OK:
@@ -279,6 +282,36 @@ class Server:
             if e.status == ERR_BUSY:
                 return None
             raise
+
+    def submit_many(self, models, fs, t_arrival=None):
+        """Queue requests in order; returns the tickets of those queued (stops at ERR_BUSY)."""
+        import numpy as np
+        n = len(models)
+        fs = [np.ascontiguousarray(f, dtype=np.float64) for f in fs]
+        m = np.ascontiguousarray(models, dtype=np.int32)
+        ptrs = (C.c_void_p * n)(*[f.ctypes.data for f in fs])
+        ta = None if t_arrival is None else np.ascontiguousarray(t_arrival, dtype=np.float64)
+        tk = np.zeros(n, dtype=np.int64)
+        done = C.c_int32()
+        st = _lib.msrs_server_submit_many(self.h, n, m.ctypes.data_as(C.c_void_p), ptrs,
+                                          None if ta is None else ta.ctypes.data_as(C.c_void_p),
+                                          tk.ctypes.data_as(C.c_void_p), C.byref(done))
+        if st not in (OK, ERR_BUSY):
+            self._check(st)
+        return list(tk[:done.value])
+
+    def replay(self, models, fs, t_arrival=None):
+        """Replay an arrival trace natively (msrs_server_replay); returns the RequestInfo records."""
+        import numpy as np
+        n = len(models)
+        fs = [np.ascontiguousarray(f, dtype=np.float64) for f in fs]
+        m = np.ascontiguousarray(models, dtype=np.int32)
+        ptrs = (C.c_void_p * n)(*[f.ctypes.data for f in fs])
+        ta = None if t_arrival is None else np.ascontiguousarray(t_arrival, dtype=np.float64)
+        infos = (RequestInfo * n)()
+        self._check(_lib.msrs_server_replay(self.h, n, m.ctypes.data_as(C.c_void_p), ptrs,
+                                            None if ta is None else ta.ctypes.data_as(C.c_void_p), infos))
+        return list(infos)
 
     def wait(self, ticket: int, timeout: float = -1.0) -> bool:
         st = _lib.msrs_server_wait(self.h, int(ticket), float(timeout))

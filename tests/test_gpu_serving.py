@@ -106,10 +106,12 @@ def test_server_results_equal_alone_and_in_a_mix(models):
     big = max(p.layout().n_nodes for p in prs) * 8
     with msrs.Server(prs, n_streams=3, max_batch=5, slot_bytes=6 * big) as srv:
         tickets = []
-        for i in range(n):
+        for i in range(n // 2):
             tickets.append(srv.submit(int(mdl[i]), reqs[i]))
             if i % 17 == 0:
                 time.sleep(0.002)          # let batches start while requests keep arriving
+        while len(tickets) < n:            # the rest in bulk, as far as staging allows
+            tickets += srv.submit_many(mdl[len(tickets):], reqs[len(tickets):])
         outs, infos = [], []
         for i, t in enumerate(tickets):
             u = np.empty(prs[mdl[i]].layout().n_nodes)
@@ -130,32 +132,27 @@ def test_server_results_equal_alone_and_in_a_mix(models):
 
 
 def test_server_open_loop_poisson(models):
-    """Open-loop Poisson arrivals (mixed models); every request completes, latencies are sane."""
+    """Open-loop Poisson arrivals replayed natively (mixed models): every request
+    completes, latencies are ordered and sane, slots are released at completion."""
     from paper_1807_08848_amd import msrs
-    import torch
     cfgs, prs = models
     rng = np.random.default_rng(7)
     n, lam = 300, 2000.0
-    gaps = rng.exponential(1.0 / lam, n)
     mdl = rng.integers(0, 2, n)
     reqs = [_requests(cfgs[m], [i])[0] for i, m in enumerate(mdl)]
-    sink = torch.empty(max(p.layout().n_nodes for p in prs), device="cuda:0", dtype=torch.float64)
     with msrs.Server(prs[:2]) as srv:
-        t0 = msrs.server_clock() + 0.01
-        arr = t0 + np.cumsum(gaps)
-        tickets = []
-        for i in range(n):
-            while msrs.server_clock() < arr[i]:
-                pass
-            tickets.append(srv.submit(int(mdl[i]), reqs[i], float(arr[i])))
-        lat = []
-        for i, t in enumerate(tickets):
-            inf = srv.fetch(t, sink[:prs[mdl[i]].layout().n_nodes])     # device-to-device copy-out
-            lat.append(inf.t_done - inf.t_arrival)
+        arr = msrs.server_clock() + 0.01 + np.cumsum(rng.exponential(1.0 / lam, n))
+        infos = srv.replay(mdl, reqs, arr)
         st = srv.stats()
-    assert st.completed == n
-    lat = np.array(lat)
-    assert np.all(lat > 0) and np.percentile(lat, 50) < 0.5
+        burst = srv.replay(mdl[:100], reqs[:100])           # all at once: batches form
+    assert st.completed == n and st.peak_slot_bytes <= st.slot_capacity
+    for i, inf in enumerate(infos):
+        assert inf.status == 0 and inf.model == mdl[i]
+        assert abs(inf.t_arrival - arr[i]) < 1e-9
+        assert inf.t_arrival <= inf.t_admit <= inf.t_launch <= inf.t_done
+    lat = np.array([i.t_done - i.t_arrival for i in infos])
+    assert np.percentile(lat, 50) < 0.5
+    assert max(i.batch_size for i in burst) > 1
 
 
 def test_server_argument_and_state_errors(models):
