@@ -93,9 +93,9 @@ def _oracle_patch(args):
     return 0
 
 
-def run_gpu(cfg, precision, steps, warmup, flags=0):
+def run_gpu(cfg, precision, steps, warmup, flags=0, tune=False):
     import torch
-    from paper_1807_08848_amd import msrs
+    from paper_1807_08848_amd import msrs, tuning
     dev = torch.device("cuda:0")
     d = msrs.make_desc(msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"], list(cfg["overlap"]), cfg["s"], cfg["k"],
                        precision=precision, seed=cfg["seed"], flags=flags | msrs.FLAG_TIMING)
@@ -107,6 +107,10 @@ def run_gpu(cfg, precision, steps, warmup, flags=0):
         pr.sample_local_solutions(None, None)
         pr.range_finder(None, None)
 
+    tuned = None
+    if tune:
+        pr.assemble_patch(a)
+        tuned = tuning.tune(pr, msrs.TUNE_STAGE_OFFLINE)
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -118,15 +122,15 @@ def run_gpu(cfg, precision, steps, warmup, flags=0):
     T = time.perf_counter() - t0
     st = pr.stats()
     L = pr.layout()
-    res = dict(T=T, stats=st, n_solves=L.n_patches * cfg["s"])
+    res = dict(T=T, stats=st, n_solves=L.n_patches * cfg["s"], tuned=tuned)
     pr.close()
     return res
 
 
 def build_model(cfg, precision=1):
-    """A handle of the workload with its bases and coarse factor resident."""
+    """A handle of the workload with its bases and coarse factor resident (online shapes tuned)."""
     import torch
-    from paper_1807_08848_amd import msrs
+    from paper_1807_08848_amd import msrs, tuning
     d = msrs.make_desc(msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"], list(cfg["overlap"]), cfg["s"], cfg["k"],
                        precision=precision, seed=cfg["seed"])
     pr = msrs.Problem(d)
@@ -137,7 +141,9 @@ def build_model(cfg, precision=1):
     t0 = time.perf_counter()
     pr.assemble_coarse()
     torch.cuda.synchronize()
-    return pr, time.perf_counter() - t0
+    ts = time.perf_counter() - t0
+    pr.tuned = tuning.tune(pr, msrs.TUNE_STAGE_ONLINE)
+    return pr, ts
 
 
 def run_serving(lams=(200, 500, 1000, 2000), seconds=2.0, seed_arrival=5):
@@ -229,6 +235,7 @@ def run_serving(lams=(200, 500, 1000, 2000), seconds=2.0, seed_arrival=5):
     out = {
         "workload": "serving over elliptic_lognormal_512 + elliptic_lognormal_1024 (50/50, Poisson arrivals)",
         "n_nodes": nn, "coarse_dim": [int(m.layout().coarse_dim) for m in models], "setup_s": setup,
+        "autotune": [m.tuned for m in models],
         "rel_err_batched_vs_banded": acc, "open_loop": res,
         "saturation_solves_per_s": sat, "saturation_mean_batch": sat_batch, "saturation": sat_s,
         "plain_fp64_ms_per_request": plain,
@@ -259,7 +266,7 @@ def main():
     from paper_1807_08848_amd import msrs
     print(f"[bench] workload {cfg['name']}: FP32 factor/sweeps + FP64 refinement, {args.warmup} warmup + "
           f"{args.steps} timed steps", file=sys.stderr, flush=True)
-    r = run_gpu(cfg, msrs.PREC_FP32_IR, args.steps, args.warmup)
+    r = run_gpu(cfg, msrs.PREC_FP32_IR, args.steps, args.warmup, tune=True)
     T, st = r["T"], r["stats"]
     value = r["n_solves"] * args.steps / T
     # dominant kernel and its roofline
@@ -284,7 +291,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                      "avg_launch_ms": avg_ms, "launches": n[dom]},
         "kernel_ms_per_step": {msrs.K_CLASSES[k]: ms[k] / args.steps for k in range(11) if n[k]},
-        "ir_iters": st.ir_iters, "max_rel_residual": st.max_rel_residual,
+        "ir_iters": st.ir_iters, "max_rel_residual": st.max_rel_residual, "autotune": r["tuned"],
     }
     if not args.no_plain:
         print("[bench] plain FP64 reference (one launch per patch per stage)", file=sys.stderr, flush=True)

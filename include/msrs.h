@@ -258,6 +258,39 @@ msrs_status msrs_copy_omega(msrs_handle h, double* omega_out_dev);
 /* Requests per msrs_solve_global call at most (1..4096, default 64). */
 msrs_status msrs_set_max_batch(msrs_handle h, int32_t max_batch);
 
+/*
+ * Launch-shape parameters (results do not depend on them beyond rounding
+ * order; the batched online results of one request are the same for every
+ * value).  Set any time; they apply to later calls.  Errors: ARG (unknown key
+ * or value not listed).
+ */
+#define MSRS_TUNE_SWEEP_COLS   0   /* samples per sweep workgroup: 16, 32, 64 (FP64 path: at most 32) */
+#define MSRS_TUNE_RECON_BATCH  1   /* requests per reconstruction pass: 1, 2, 4, 8, 16 */
+#define MSRS_TUNE_APPLY_BATCH  2   /* requests per workgroup of the G_B product: 4, 8, 16 */
+msrs_status msrs_set_tuning(msrs_handle h, int32_t key, int32_t value);
+msrs_status msrs_get_tuning(msrs_handle h, int32_t key, int32_t* value);
+
+typedef struct msrs_tune_report {
+    int32_t n_trials;
+    int32_t key[32];     /* MSRS_TUNE_SWEEP_COLS, or 100*RECON_BATCH + APPLY_BATCH (= 102) */
+    int32_t value[32];   /* the candidate (online: 100*recon_batch + apply_batch) */
+    double ms[32];       /* device milliseconds per call */
+} msrs_tune_report;
+
+#define MSRS_TUNE_STAGE_OFFLINE 0   /* sweep columns, timed on msrs_sample_local_solutions */
+#define MSRS_TUNE_STAGE_ONLINE  1   /* reconstruction x product batches, timed on a 32-request solve */
+
+/*
+ * Autotuner: time every candidate of a stage on this handle's own problem
+ * (warm-up + reps calls between events on the handle's stream), keep the
+ * fastest and report all trials.  OFFLINE needs msrs_assemble_patch and
+ * leaves the handle sampled (results do not depend on the choice); ONLINE
+ * needs msrs_assemble_coarse and uses zero requests in temporary device
+ * buffers.  Synchronises.  Errors: ARG, STATE, BUSY, HIP, and those of the
+ * timed calls.
+ */
+msrs_status msrs_autotune(msrs_handle h, int32_t stage, int32_t reps, msrs_tune_report* out);
+
 /* Sizes and offsets of the concatenated arrays.  Errors: ARG. */
 msrs_status msrs_query_layout(msrs_handle h, msrs_layout* out);
 msrs_status msrs_query_patch(msrs_handle h, int32_t patch, msrs_patch_info* out);

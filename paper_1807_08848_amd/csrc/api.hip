@@ -236,6 +236,43 @@ StageTimer::~StageTimer() {
 }
 }  // namespace msrs
 
+namespace {
+// An online workspace that the call on stream st may use: one last used on
+// st (stream order puts this call after that use), else one whose last use
+// has completed on the device, else null.
+Ctx::OnlineWs* take_ws(Ctx* c, hipStream_t st) {
+    for (auto& w : c->ws)
+        if (w.used && w.last == st) return &w;
+    for (auto& w : c->ws) {
+        if (!w.used) return &w;
+        const hipError_t q = hipEventQuery(w.done);
+        if (q == hipSuccess) return &w;
+        if (q != hipErrorNotReady) MSRS_HIP_CHECK(q);
+    }
+    return nullptr;
+}
+
+// Time one candidate: warm-up call, then reps calls between events on the
+// handle's stream; average milliseconds per call.
+template <typename F>
+double time_calls(Ctx& c, int reps, F&& f) {
+    hipEvent_t a, b;
+    MSRS_HIP_CHECK(hipEventCreate(&a));
+    MSRS_HIP_CHECK(hipEventCreate(&b));
+    f();
+    MSRS_HIP_CHECK(hipEventRecord(a, c.stream));
+    for (int i = 0; i < reps; ++i) f();
+    MSRS_HIP_CHECK(hipEventRecord(b, c.stream));
+    MSRS_HIP_CHECK(hipEventSynchronize(b));
+    float ms = 0.f;
+    MSRS_HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms / reps;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------- ABI
 extern "C" {
 
@@ -542,6 +579,7 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
             c->bmap = dalloc<int32_t>(*c, c->nB);
             MSRS_HIP_CHECK(hipMemcpy(c->bmap, bmap.data(), sizeof(int32_t) * bmap.size(), hipMemcpyHostToDevice));
             c->GB = dalloc<double>(*c, (int64_t)c->Np * c->nB);
+            c->GT = dalloc<double>(*c, (int64_t)c->Np * c->nB);
             for (auto& w : c->ws) {
                 w.cbuf = dalloc<double>(*c, (int64_t)c->Np * kOutPerLaunch);
                 w.gbuf = dalloc<double>(*c, (int64_t)c->nB * kOutPerLaunch);
@@ -559,21 +597,6 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
     if (c->hflags[0]) { st = MSRS_ERR_NOT_SPD; c->err = "normal equations not positive definite (P~ rank deficient)"; }
     if (st == MSRS_OK) c->coarse_ready = true;
     return st;
-}
-
-// An online workspace that the call on stream st may use: one last used on
-// st (stream order puts this call after that use), else one whose last use
-// has completed on the device, else null.
-static Ctx::OnlineWs* take_ws(Ctx* c, hipStream_t st) {
-    for (auto& w : c->ws)
-        if (w.used && w.last == st) return &w;
-    for (auto& w : c->ws) {
-        if (!w.used) return &w;
-        const hipError_t q = hipEventQuery(w.done);
-        if (q == hipSuccess) return &w;
-        if (q != hipErrorNotReady) MSRS_HIP_CHECK(q);
-    }
-    return nullptr;
 }
 
 static msrs_status solve_common(Ctx* c, int32_t n_req, const double* f_dev, double* u_dev, void* stream, bool banded) {
@@ -614,6 +637,134 @@ msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev,
 
 msrs_status msrs_solve_global_banded(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev, void* stream) {
     return solve_common(h, n_req, f_dev, u_dev, stream, true);
+}
+
+msrs_status msrs_set_tuning(msrs_handle h, int32_t key, int32_t value) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    auto in = [&](std::initializer_list<int> ok) {
+        for (int v : ok)
+            if (v == value) return true;
+        return false;
+    };
+    switch (key) {
+        case MSRS_TUNE_SWEEP_COLS:
+            if (!in({16, 32, 64})) return fail(c, MSRS_ERR_ARG, "sweep columns must be 16, 32 or 64");
+            c->sweep_cols32 = value;
+            c->sweep_cols64 = std::min(value, 32);
+            return MSRS_OK;
+        case MSRS_TUNE_RECON_BATCH:
+            if (!in({1, 2, 4, 8, 16})) return fail(c, MSRS_ERR_ARG, "reconstruction batch must be 1, 2, 4, 8 or 16");
+            c->recon_batch = value;
+            return MSRS_OK;
+        case MSRS_TUNE_APPLY_BATCH:
+            if (!in({4, 8, 16})) return fail(c, MSRS_ERR_ARG, "apply batch must be 4, 8 or 16");
+            c->apply_batch = value;
+            return MSRS_OK;
+        default:
+            return fail(c, MSRS_ERR_ARG, "unknown tuning key");
+    }
+}
+
+msrs_status msrs_autotune(msrs_handle h, int32_t stage, int32_t reps, msrs_tune_report* out) {
+    Ctx* c = h;
+    if (!c || !out) return fail(c, MSRS_ERR_ARG, "NULL argument");
+    if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
+    if (reps < 1 || reps > 1000) return fail(c, MSRS_ERR_ARG, "reps must be in [1, 1000]");
+    *out = msrs_tune_report{};
+    auto record = [&](int key, int value, double ms) {
+        if (out->n_trials < 32) {
+            out->key[out->n_trials] = key;
+            out->value[out->n_trials] = value;
+            out->ms[out->n_trials] = ms;
+            out->n_trials += 1;
+        }
+    };
+    const bool timing = c->timing;
+    c->timing = false;   // candidates are timed as whole calls
+    msrs_status st = MSRS_OK;
+    try {
+        if (stage == MSRS_TUNE_STAGE_OFFLINE) {
+            if (!c->assembled) { c->timing = timing; return fail(c, MSRS_ERR_STATE, "msrs_assemble_patch must come first"); }
+            double best = 1e300;
+            int arg = c->sweep_cols32;
+            for (int sc : {16, 32, 64}) {
+                c->sweep_cols32 = sc;
+                c->sweep_cols64 = std::min(sc, 32);
+                const double ms = time_calls(*c, reps, [&] {
+                    const msrs_status s2 = msrs_sample_local_solutions(h, nullptr, nullptr);
+                    if (s2 != MSRS_OK) throw s2;
+                });
+                record(MSRS_TUNE_SWEEP_COLS, sc, ms);
+                if (ms < best) { best = ms; arg = sc; }
+            }
+            c->sweep_cols32 = arg;
+            c->sweep_cols64 = std::min(arg, 32);
+            // leave the handle sampled with the chosen shape (same results)
+            st = msrs_sample_local_solutions(h, nullptr, nullptr);
+        } else if (stage == MSRS_TUNE_STAGE_ONLINE) {
+            if (!c->coarse_ready) { c->timing = timing; return fail(c, MSRS_ERR_STATE, "msrs_assemble_coarse must come first"); }
+            const int nr = kOutPerLaunch;
+            double* f = nullptr;
+            double* u = nullptr;
+            MSRS_HIP_CHECK(hipMalloc(&f, sizeof(double) * (size_t)nr * c->n_bdry));
+            MSRS_HIP_CHECK(hipMalloc(&u, sizeof(double) * (size_t)nr * c->n_nodes));
+            MSRS_HIP_CHECK(hipMemsetAsync(f, 0, sizeof(double) * (size_t)nr * c->n_bdry, c->stream));
+            std::vector<const double*> fp(nr);
+            std::vector<double*> up(nr);
+            for (int r = 0; r < nr; ++r) {
+                fp[r] = f + (int64_t)r * c->n_bdry;
+                up[r] = u + (int64_t)r * c->n_nodes;
+            }
+            Ctx::OnlineWs* w = take_ws(c, c->stream);
+            if (!w) {
+                (void)hipFree(f);
+                (void)hipFree(u);
+                c->timing = timing;
+                return fail(c, MSRS_ERR_BUSY, "every online workspace is in use by unfinished calls");
+            }
+            double best = 1e300;
+            int ra = c->recon_batch, aa = c->apply_batch;
+            for (int rb : {4, 8, 16})
+                for (int ab : {4, 8, 16}) {
+                    c->recon_batch = rb;
+                    c->apply_batch = ab;
+                    const double ms = time_calls(*c, reps, [&] { coarse_apply(*c, nr, fp.data(), up.data(), w->gbuf, w->cbuf, c->stream); });
+                    record(MSRS_TUNE_RECON_BATCH * 100 + MSRS_TUNE_APPLY_BATCH, rb * 100 + ab, ms);
+                    if (ms < best) { best = ms; ra = rb; aa = ab; }
+                }
+            c->recon_batch = ra;
+            c->apply_batch = aa;
+            MSRS_HIP_CHECK(hipEventRecord(w->done, c->stream));
+            w->used = true;
+            w->last = c->stream;
+            MSRS_HIP_CHECK(hipStreamSynchronize(c->stream));
+            (void)hipFree(f);
+            (void)hipFree(u);
+        } else {
+            c->timing = timing;
+            return fail(c, MSRS_ERR_ARG, "unknown stage");
+        }
+    } catch (const HipError& e) {
+        c->timing = timing;
+        return hip_fail(c, e);
+    } catch (msrs_status s2) {
+        c->timing = timing;
+        return s2;
+    }
+    c->timing = timing;
+    return st;
+}
+
+msrs_status msrs_get_tuning(msrs_handle h, int32_t key, int32_t* value) {
+    Ctx* c = h;
+    if (!c || !value) return fail(c, MSRS_ERR_ARG, "NULL argument");
+    switch (key) {
+        case MSRS_TUNE_SWEEP_COLS: *value = c->sweep_cols32; return MSRS_OK;
+        case MSRS_TUNE_RECON_BATCH: *value = c->recon_batch; return MSRS_OK;
+        case MSRS_TUNE_APPLY_BATCH: *value = c->apply_batch; return MSRS_OK;
+        default: return fail(c, MSRS_ERR_ARG, "unknown tuning key");
+    }
 }
 
 msrs_status msrs_query_layout(msrs_handle h, msrs_layout* out) {

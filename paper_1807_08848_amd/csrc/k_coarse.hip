@@ -333,24 +333,44 @@ __global__ __launch_bounds__(kThreads) void rhs_kinetic_kernel(const PatchDesc* 
 // patch, request).  The boundary data are read where the caller holds them
 // (device memory, or the server's mapped pinned staging: each value crosses
 // the bus once per patch that touches it).
+__device__ __forceinline__ double wave_sum(double v) {
+    // butterfly over the 64 lanes: a fixed order, so a sum does not depend on
+    // which other requests share the launch
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Waves take every fourth basis column (KW at a time), lanes the boundary
+// nodes of K_m; each lane reads its node's datum once for all its columns.
 __global__ __launch_bounds__(kThreads) void bdry_rhs_elliptic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ tr,
                                                                      int64_t tr_stride, const int32_t* __restrict__ bpatch, int M, int N,
                                                                      InPtrs in, int nB, double* __restrict__ g) {
+    constexpr int KW = 4;
     const int m = bpatch[blockIdx.x], r = blockIdx.y;
     const int m1 = m % M, m2 = m / M;
     const int nH = pd[m].nH;
-    const ElTr Tm{tr + (int64_t)m * tr_stride, nH, cd[m].ncols};
-    const int km = cd[m].ncols, bo = cd[m].b_off;
+    const int km = cd[m].ncols, bo = cd[m].b_off, nc = cd[m].ncols;
+    const double* T = tr + (int64_t)m * tr_stride;
     const double* fr = in.f[r];
-    for (int a = threadIdx.x; a < km; a += kThreads) {
-        double s = 0.0;
-        for (int t = 0; t < 4 * nH; ++t) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int a0 = w * KW; a0 < km; a0 += 4 * KW) {
+        double acc[KW] = {};
+        for (int t = lane; t < 4 * nH; t += 64) {
             int ii, jj;
             kbnode(t, nH, ii, jj);
             const int gx = m1 * nH + ii, gy = m2 * nH + jj;
-            if (gx == 0 || gx == N || gy == 0 || gy == N) s += Tm.val(ii, jj, a) * fr[gb_index(gx, gy, N)];
+            if (!(gx == 0 || gx == N || gy == 0 || gy == N)) continue;
+            const double fv = fr[gb_index(gx, gy, N)];
+#pragma unroll
+            for (int q = 0; q < KW; ++q)
+                if (a0 + q < km) acc[q] = fma(T[t * nc + a0 + q], fv, acc[q]);
         }
-        g[(int64_t)r * nB + bo + a] = s;
+#pragma unroll
+        for (int q = 0; q < KW; ++q) {
+            const double v = wave_sum(acc[q]);
+            if (lane == 0 && a0 + q < km) g[(int64_t)r * nB + bo + a0 + q] = v;
+        }
     }
 }
 
@@ -372,47 +392,149 @@ __global__ __launch_bounds__(kThreads) void bdry_rhs_kinetic_kernel(const PatchD
     }
 }
 
-// c[r*Np + j] = sum_i GB[i*Np + j] g[r*nB + i] for the requests of one launch.
-// A workgroup owns 64 rows (one per lane) and RB requests; its four waves
-// take every fourth column, so G_B streams once per RB requests with
-// coalesced 512-byte rows, g is wave-uniform (scalar loads), and the four
-// partial sums meet in LDS in a fixed order.
-template <int RB>
-__global__ __launch_bounds__(kThreads) void apply_G_kernel(const double* __restrict__ GB, int Np, int nB,
-                                                           const double* __restrict__ g, int n_req, double* __restrict__ c) {
-    __shared__ double red[3][RB][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int j = blockIdx.x * 64 + lane;
-    const int r0 = blockIdx.y * RB;
-    const int nr = min(RB, n_req - r0);
-    const int jj = min(j, Np - 1);
-    const double* gr[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) gr[r] = g + (int64_t)(r0 + min(r, nr - 1)) * nB;
-    double acc[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) acc[r] = 0.0;
-#pragma unroll 2
-    for (int i = w; i < nB; i += 4) {
-        const double gv = GB[(int64_t)i * Np + jj];
-#pragma unroll
-        for (int r = 0; r < RB; ++r) acc[r] = fma(gv, gr[r][i], acc[r]);
-    }
-    if (w > 0) {
-#pragma unroll
-        for (int r = 0; r < RB; ++r) red[w - 1][r][lane] = acc[r];
+// GT (Np x nB, row-major) = transpose of GB, through 64 x 64 LDS tiles.
+__global__ __launch_bounds__(kThreads) void transpose_kernel(const double* __restrict__ A, int rows, int cols, double* __restrict__ B) {
+    // A: rows x cols column-major (A[c*rows + r]); B: B[r*cols + c]
+    __shared__ double t[64][65];
+    const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+    for (int o = threadIdx.x; o < 64 * 64; o += kThreads) {
+        const int rr = o & 63, cc = o >> 6;
+        if (r0 + rr < rows && c0 + cc < cols) t[cc][rr] = A[(int64_t)(c0 + cc) * rows + r0 + rr];
     }
     __syncthreads();
-    if (w == 0 && j < Np) {
+    for (int o = threadIdx.x; o < 64 * 64; o += kThreads) {
+        const int cc = o & 63, rr = o >> 6;
+        if (r0 + rr < rows && c0 + cc < cols) B[(int64_t)(r0 + rr) * cols + c0 + cc] = t[cc][rr];
+    }
+}
+
+// c[r*Np + j] = sum_i GT[j*nB + i] g[r*nB + i] for the requests of one launch.
+// A workgroup owns kGRows rows (two per wave) and RB requests.  Lanes stride
+// the columns, so every row streams as independent 512-byte loads (16 in
+// flight per wave); g is staged in LDS in column chunks; each row's lane
+// sums meet in a fixed butterfly.
+constexpr int kGRows = 8, kGChunk = 512;
+template <int RB>
+__global__ __launch_bounds__(kThreads) void apply_G_kernel(const double* __restrict__ GT, int Np, int nB,
+                                                           const double* __restrict__ g, int n_req, double* __restrict__ c) {
+    __shared__ double gs[RB][kGChunk];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = blockIdx.y * RB;
+    const int nr = min(RB, n_req - r0);
+    const int j0 = blockIdx.x * kGRows + 2 * w;
+    const int ja = min(j0, Np - 1), jb = min(j0 + 1, Np - 1);
+    double acc0[RB] = {}, acc1[RB] = {};
+    for (int i0 = 0; i0 < nB; i0 += kGChunk) {
+        const int ni = min(kGChunk, nB - i0);
+        __syncthreads();
+        for (int o = threadIdx.x; o < RB * kGChunk; o += kThreads) {
+            const int r = o / kGChunk, i = o % kGChunk;
+            gs[r][i] = (r < nr && i < ni) ? g[(int64_t)(r0 + r) * nB + i0 + i] : 0.0;
+        }
+        __syncthreads();
+        double ga[kGChunk / 64], gb[kGChunk / 64];
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
-            if (r < nr) c[(int64_t)(r0 + r) * Np + j] = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+        for (int t = 0; t < kGChunk / 64; ++t) {
+            const int i = t * 64 + lane;
+            ga[t] = i < ni ? GT[(int64_t)ja * nB + i0 + i] : 0.0;
+            gb[t] = i < ni ? GT[(int64_t)jb * nB + i0 + i] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < kGChunk / 64; ++t) {
+            const int i = t * 64 + lane;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const double gv = gs[r][i];
+                acc0[r] = fma(ga[t], gv, acc0[r]);
+                acc1[r] = fma(gb[t], gv, acc1[r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const double s0 = wave_sum(acc0[r]), s1 = wave_sum(acc1[r]);
+        if (lane == 0 && r < nr) {
+            if (j0 < Np) c[(int64_t)(r0 + r) * Np + j0] = s0;
+            if (j0 + 1 < Np) c[(int64_t)(r0 + r) * Np + j0 + 1] = s1;
+        }
     }
 }
 
 // ------------------------------------------------------------ reconstruction
 // u_r(x) = sum_m w_m(x) (Q_m c_{r,m})(x) for the requests of one launch; the
 // output of request r is out.u[r] (requests need not be contiguous).
+//
+// Tiled form (nH >= 16): a workgroup owns a 16 x 16 tile of nodes, which
+// touches at most 2 x 2 patches.  The loop over those patches is uniform
+// across the workgroup, so a patch's coefficients c_{r,m} are wave-uniform
+// (scalar loads) while each thread streams its node's basis rows once and
+// accumulates every request of the launch in registers; nodes outside the
+// patch add zeros.  Q is read once per launch and u written once.
+constexpr int kTile = 16;
+template <int NR>
+__global__ __launch_bounds__(kThreads) void recon_tiled_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ Q_all,
+                                                               int M, int N, int Np, const double* __restrict__ c, int n_req,
+                                                               OutPtrs out) {
+    // Requests go in passes of NR (the second pass re-reads the tile's basis
+    // rows from cache); within a pass all NR are computed (rows of c past
+    // n_req are workspace: their sums are discarded), so the request loop
+    // has no branches and each request's coefficients arrive as wide scalar
+    // loads.  Past km, q = 0 and the coefficient index is clamped inside the
+    // patch, so a partial chunk adds exact zeros.
+    constexpr int QC = 16;
+    const int nH = N / M, W = nH + 1;
+    const int X0 = blockIdx.x * kTile, Y0 = blockIdx.y * kTile;
+    const int pxa = X0 > 0 ? (X0 - 1) / nH : 0, pya = Y0 > 0 ? (Y0 - 1) / nH : 0;
+    const int gx = X0 + (threadIdx.x & (kTile - 1)), gy = Y0 + threadIdx.x / kTile;
+    const bool valid = gx <= N && gy <= N;
+    const int nx = ((gx % nH == 0 && gx > 0) ? 1 : 0) + (gx / nH < M ? 1 : 0);
+    const int ny = ((gy % nH == 0 && gy > 0) ? 1 : 0) + (gy / nH < M ? 1 : 0);
+    const double w = 1.0 / (nx * ny);
+    const int64_t node = (int64_t)gy * (N + 1) + gx;
+    for (int rb = 0; rb < n_req; rb += NR) {
+        double acc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+        for (int sl = 0; sl < 4; ++sl) {
+            const int px = pxa + (sl & 1), py = pya + (sl >> 1);
+            if (px >= M || py >= M) continue;
+            if (X0 > (px + 1) * nH || X0 + kTile - 1 < px * nH || Y0 > (py + 1) * nH || Y0 + kTile - 1 < py * nH) continue;
+            const int m = py * M + px;
+            const PatchDesc& P = pd[m];
+            const int km = cd[m].ncols, om = cd[m].col_off;
+            const bool member = valid && gx >= px * nH && gx <= (px + 1) * nH && gy >= py * nH && gy <= (py + 1) * nH;
+            const double* Q = Q_all + P.Q_off + (member ? (gy - py * nH) * W + (gx - px * nH) : 0);
+            for (int c0 = 0; c0 < km; c0 += QC) {
+                double q[QC];
+#pragma unroll
+                for (int t = 0; t < QC; ++t) q[t] = (member && c0 + t < km) ? Q[(int64_t)(c0 + t) * P.nrows] : 0.0;
+                const int kc = min(QC, km - c0);
+                if (kc == QC) {
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const double* cr = c + (int64_t)(rb + r) * Np + om + c0;
+#pragma unroll
+                        for (int t = 0; t < QC; ++t) acc[r] = fma(q[t], cr[t], acc[r]);
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const double* cr = c + (int64_t)(rb + r) * Np + om + c0;
+#pragma unroll
+                        for (int t = 0; t < QC; ++t) acc[r] = fma(q[t], cr[min(t, kc - 1)], acc[r]);
+                    }
+                }
+            }
+        }
+        if (valid) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (rb + r < n_req) out.u[rb + r][node] = w * acc[r];
+        }
+    }
+}
+
+// Generic form (any nH): a thread per node, coefficients from global memory.
 __global__ __launch_bounds__(kThreads) void recon_elliptic_kernel(const PatchDesc* pd, const CoarseDesc* cd, const double* __restrict__ Q_all,
                                                                   int M, int N, int Np, const double* __restrict__ c, int n_req,
                                                                   OutPtrs out) {
@@ -495,10 +617,21 @@ void coarse_setup(Ctx& c) {
     }
     hipLaunchKernelGGL(band_cholesky_kernel, dim3(1), dim3(1024), 0, c.stream, c.band, c.Np, c.bw, c.dflags);
     hipLaunchKernelGGL(band_solve_kernel, dim3((c.nB + 63) / 64), dim3(1024), 0, c.stream, c.band, c.Np, c.bw, c.GB, c.nB);
+    hipLaunchKernelGGL(transpose_kernel, dim3((c.Np + 63) / 64, (c.nB + 63) / 64), dim3(kThreads), 0, c.stream, c.GB, c.Np, c.nB, c.GT);
 }
 
 static void launch_recon(const Ctx& c, const double* cbuf, int n_req, const OutPtrs& out, hipStream_t st) {
-    if (c.kind == kElliptic) {
+    if (c.kind == kElliptic && c.N / c.M >= kTile) {
+        const dim3 g((c.N + kTile) / kTile, (c.N + kTile) / kTile);
+#define MSRS_RECON(NR) hipLaunchKernelGGL(recon_tiled_kernel<NR>, g, dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.M, c.N, c.Np, cbuf, n_req, out)
+        const int nr = std::min(n_req, c.recon_batch);
+        if (nr <= 1) MSRS_RECON(1);
+        else if (nr <= 2) MSRS_RECON(2);
+        else if (nr <= 4) MSRS_RECON(4);
+        else if (nr <= 8) MSRS_RECON(8);
+        else MSRS_RECON(16);
+#undef MSRS_RECON
+    } else if (c.kind == kElliptic) {
         const int64_t nn = (int64_t)(c.N + 1) * (c.N + 1);
         const int blocks = (int)std::min<int64_t>((nn + kThreads - 1) / kThreads, 8192);
         hipLaunchKernelGGL(recon_elliptic_kernel, dim3(blocks), dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.M, c.N, c.Np, cbuf, n_req, out);
@@ -511,7 +644,6 @@ static void launch_recon(const Ctx& c, const double* cbuf, int n_req, const OutP
 
 void coarse_apply(const Ctx& c, int n_req, const double* const* f, double* const* u, double* gbuf, double* cbuf,
                   hipStream_t st) {
-    constexpr int RB = 16;
     for (int r0 = 0; r0 < n_req; r0 += kOutPerLaunch) {
         const int nr = std::min(kOutPerLaunch, n_req - r0);
         InPtrs in{};
@@ -526,8 +658,11 @@ void coarse_apply(const Ctx& c, int n_req, const double* const* f, double* const
                                c.nB, gbuf);
         else
             hipLaunchKernelGGL(bdry_rhs_kinetic_kernel, gb, dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.vw, c.dbpatch, c.M, c.nv, in, c.nB, gbuf);
-        const dim3 ga((c.Np + 63) / 64, (nr + RB - 1) / RB);
-        hipLaunchKernelGGL(apply_G_kernel<RB>, ga, dim3(kThreads), 0, st, c.GB, c.Np, c.nB, gbuf, nr, cbuf);
+        const int rb = c.apply_batch;
+        const dim3 ga((c.Np + kGRows - 1) / kGRows, (nr + rb - 1) / rb);
+        if (rb == 4) hipLaunchKernelGGL(apply_G_kernel<4>, ga, dim3(kThreads), 0, st, c.GT, c.Np, c.nB, gbuf, nr, cbuf);
+        else if (rb == 16) hipLaunchKernelGGL(apply_G_kernel<16>, ga, dim3(kThreads), 0, st, c.GT, c.Np, c.nB, gbuf, nr, cbuf);
+        else hipLaunchKernelGGL(apply_G_kernel<8>, ga, dim3(kThreads), 0, st, c.GT, c.Np, c.nB, gbuf, nr, cbuf);
         launch_recon(c, cbuf, nr, out, st);
     }
 }

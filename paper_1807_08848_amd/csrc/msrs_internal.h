@@ -130,12 +130,15 @@ struct Ctx {
     int max_batch = 64;
     int sweep_cols32 = 64;       // samples per sweep workgroup (FP32), 16 | value
     int sweep_cols64 = 32;       // samples per sweep workgroup (FP64)
+    int recon_batch = 8;         // requests per reconstruction pass (1, 2, 4, 8, 16)
+    int apply_batch = 8;         // requests per G_B workgroup (4, 8, 16)
     int Np = 0, bw = 0;
     std::vector<CoarseDesc> hc;
     CoarseDesc* dc = nullptr;
     double* tr = nullptr;         // traces (values, fluxes)
     double* band = nullptr;       // normal matrix, then its Cholesky factor (lower band)
     double* GB = nullptr;         // (P~^T P~)^{-1} restricted to the columns of boundary-patch unknowns, Np x nB
+    double* GT = nullptr;         // the same, row-major (row j contiguous): the batched solve streams its rows
     int nB = 0;                   // unknowns of the patches with Dirichlet / inflow rows
     std::vector<int32_t> bpatch;  // those patches (host), and on the device:
     int32_t* dbpatch = nullptr;

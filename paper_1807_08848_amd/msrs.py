@@ -29,6 +29,9 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_STATE", 3: "ERR_OOM", 4: "ERR_HIP
 KIND_ELLIPTIC_Q1, KIND_KINETIC_DO = 0, 1
 PREC_FP64, PREC_FP32_IR = 0, 1
 FLAG_FULL_BASIS_ENDS, FLAG_PER_PATCH_LAUNCH, FLAG_TIMING = 1, 2, 4
+TUNE_SWEEP_COLS, TUNE_RECON_BATCH, TUNE_APPLY_BATCH = 0, 1, 2
+TUNE_STAGE_OFFLINE, TUNE_STAGE_ONLINE = 0, 1
+TUNE_NAMES = {TUNE_SWEEP_COLS: "sweep_cols", TUNE_RECON_BATCH: "recon_batch", TUNE_APPLY_BATCH: "apply_batch"}
 K_CLASSES = ["assemble", "omega", "lift", "factor", "sweep", "residual", "restrict", "range",
              "coarse", "csolve", "recon"]
 
@@ -75,6 +78,10 @@ class ServerStats(C.Structure):
                 ("admission_waits", C.c_int64), ("mean_batch", C.c_double)]
 
 
+class TuneReport(C.Structure):
+    _fields_ = [("n_trials", C.c_int32), ("key", C.c_int32 * 32), ("value", C.c_int32 * 32), ("ms", C.c_double * 32)]
+
+
 _H = C.c_void_p
 _P = C.c_void_p
 _sig = {
@@ -100,6 +107,9 @@ _sig = {
     "msrs_set_max_batch": (C.c_int32, [_H, C.c_int32]),
     "msrs_copy_omega": (C.c_int32, [_H, _P]),
     "msrs_query_layout": (C.c_int32, [_H, C.POINTER(Layout)]),
+    "msrs_set_tuning": (C.c_int32, [_H, C.c_int32, C.c_int32]),
+    "msrs_get_tuning": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_int32)]),
+    "msrs_autotune": (C.c_int32, [_H, C.c_int32, C.c_int32, C.POINTER(TuneReport)]),
     "msrs_query_patch": (C.c_int32, [_H, C.c_int32, C.POINTER(PatchInfo)]),
     "msrs_get_stats": (C.c_int32, [_H, C.POINTER(Stats)]),
     "msrs_reset_stats": (C.c_int32, [_H]),
@@ -200,6 +210,20 @@ class Problem:
         n_req = f.shape[0] if f.dim() == 2 else 1
         s = None if stream is None else _stream(stream)
         self._check(_lib.msrs_solve_global_banded(self.h, int(n_req), _ptr(f), _ptr(u), s))
+
+    def set_tuning(self, key: int, value: int):
+        self._check(_lib.msrs_set_tuning(self.h, int(key), int(value)))
+
+    def get_tuning(self, key: int) -> int:
+        v = C.c_int32()
+        self._check(_lib.msrs_get_tuning(self.h, int(key), C.byref(v)))
+        return v.value
+
+    def autotune(self, stage: int, reps: int = 3):
+        """Native autotuner (msrs_autotune): returns [(key, value, ms), ...]; the fastest is kept."""
+        out = TuneReport()
+        self._check(_lib.msrs_autotune(self.h, int(stage), int(reps), C.byref(out)))
+        return [(out.key[i], out.value[i], out.ms[i]) for i in range(out.n_trials)]
 
     def layout(self) -> Layout:
         out = Layout()

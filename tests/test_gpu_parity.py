@@ -200,3 +200,28 @@ def test_single_hip_runtime_shared_with_torch(gpu):
         st.synchronize()
     ref = E.offline(cfg["coef"], cfg["N"], cfg["M"], cfg["overlap"], cfg["s"], cfg["k"], seed=cfg["seed"])
     assert abs(float(ysum) - sum(np.abs(r["Y"]).sum() for r in ref)) < 1e-9 * float(ysum)
+
+
+def test_sweep_width_and_offline_autotune_keep_results(gpu):
+    """Snapshots do not depend on the sweep workgroup width; the offline autotuner
+    times the three widths and keeps one."""
+    import torch
+    from paper_1807_08848_amd import msrs
+    cfg = configs.small_elliptic(N=64, M=2, delta=8, s=40, k=6, coef="lognormal")
+    d = msrs.make_desc(msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"], list(cfg["overlap"]), cfg["s"], cfg["k"],
+                       precision=FP32_IR, seed=cfg["seed"])
+    with msrs.Problem(d) as pr:
+        L = pr.layout()
+        pr.assemble_patch(torch.tensor(cfg["coef"], device="cuda:0"))
+        Ys = []
+        for sc in (16, 32, 64):
+            pr.set_tuning(msrs.TUNE_SWEEP_COLS, sc)
+            Y = torch.empty(L.Y_total, device="cuda:0", dtype=torch.float64)
+            pr.sample_local_solutions(None, Y)
+            Ys.append(Y.cpu().numpy())
+        for Y in Ys[1:]:
+            assert np.abs(Y - Ys[0]).max() <= 1e-13 * np.abs(Ys[0]).max()
+        trials = pr.autotune(msrs.TUNE_STAGE_OFFLINE, reps=1)
+        assert [t[1] for t in trials] == [16, 32, 64]
+        assert pr.get_tuning(msrs.TUNE_SWEEP_COLS) == min(trials, key=lambda t: t[2])[1]
+        pr.range_finder()        # the tuner left the handle sampled

@@ -174,3 +174,29 @@ def test_server_argument_and_state_errors(models):
     # the handle is usable again once the server is gone
     f = _requests(cfgs[0], [3])
     assert np.isfinite(_solve(prs[0], f)).all()
+
+
+def test_tuning_keeps_results_bitwise(models):
+    """Every launch shape of the online product and reconstruction gives the same bits;
+    the autotuner reports all 9 candidates and keeps one of them."""
+    from paper_1807_08848_amd import msrs
+    cfgs, prs = models
+    pr = prs[1]
+    f = _requests(cfgs[1], range(21))
+    ref = None
+    for rb in (1, 2, 4, 8, 16):
+        for ab in (4, 8, 16):
+            pr.set_tuning(msrs.TUNE_RECON_BATCH, rb)
+            pr.set_tuning(msrs.TUNE_APPLY_BATCH, ab)
+            u = _solve(pr, f)
+            if ref is None:
+                ref = u
+            assert np.array_equal(u, ref), (rb, ab)
+    trials = pr.autotune(msrs.TUNE_STAGE_ONLINE, reps=2)
+    assert len(trials) == 9 and all(t[2] > 0 for t in trials)
+    best = min(trials, key=lambda t: t[2])[1]
+    assert pr.get_tuning(msrs.TUNE_RECON_BATCH) * 100 + pr.get_tuning(msrs.TUNE_APPLY_BATCH) == best
+    assert np.array_equal(_solve(pr, f), ref)
+    with pytest.raises(msrs.MsrsError) as e:
+        pr.set_tuning(msrs.TUNE_APPLY_BATCH, 5)
+    assert e.value.status == msrs.ERR_ARG
