@@ -93,37 +93,61 @@ def _oracle_patch(args):
     return 0
 
 
-def run_gpu(cfg, precision, steps, warmup, flags=0, tune=False):
+def run_gpu(cfg, precision, steps, warmup, flags=0, tune=False, graph=False):
+    """Time `steps` offline steps (assemble + sample + range finder) after `warmup`.
+
+    Eager: the three calls per step, with per-kernel-class HIP event timing.
+    graph=True additionally times replays of the captured step (the
+    production form: no host synchronisation between refinement iterations).
+    """
     import torch
     from paper_1807_08848_amd import msrs, tuning
     dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
     d = msrs.make_desc(msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"], list(cfg["overlap"]), cfg["s"], cfg["k"],
                        precision=precision, seed=cfg["seed"], flags=flags | msrs.FLAG_TIMING)
-    pr = msrs.Problem(d)
-    a = torch.tensor(cfg["coef"], device=dev)
+    with torch.cuda.stream(stream):
+        pr = msrs.Problem(d, stream=stream)
+        a = torch.tensor(cfg["coef"], device=dev)
 
-    def step():
-        pr.assemble_patch(a)
-        pr.sample_local_solutions(None, None)
-        pr.range_finder(None, None)
+        def step():
+            pr.assemble_patch(a)
+            pr.sample_local_solutions(None, None)
+            pr.range_finder(None, None)
 
-    tuned = None
-    if tune:
-        pr.assemble_patch(a)
-        tuned = tuning.tune(pr, msrs.TUNE_STAGE_OFFLINE)
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    pr.reset_stats()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    T = time.perf_counter() - t0
-    st = pr.stats()
-    L = pr.layout()
-    res = dict(T=T, stats=st, n_solves=L.n_patches * cfg["s"], tuned=tuned)
-    pr.close()
+        tuned = None
+        if tune:
+            pr.assemble_patch(a)
+            tuned = tuning.tune(pr, msrs.TUNE_STAGE_OFFLINE)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        pr.reset_stats()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        st = pr.stats()
+        L = pr.layout()
+        res = dict(T=T, stats=st, n_solves=L.n_patches * cfg["s"], tuned=tuned)
+        if graph:
+            t0 = time.perf_counter()
+            pr.offline_graph_capture(a)
+            t_cap = time.perf_counter() - t0
+            for _ in range(warmup):
+                pr.offline_graph_launch()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                pr.offline_graph_launch()
+            torch.cuda.synchronize()
+            res["T_graph"] = time.perf_counter() - t0
+            res["graph_capture_s"] = t_cap
+            sg = pr.stats()
+            res["graph_ok"] = sg.error_latched == 0 and sg.max_rel_residual <= 1e-10
+            res["graph_max_rel_residual"] = sg.max_rel_residual
+        pr.close()
     return res
 
 
@@ -266,8 +290,11 @@ def main():
     from paper_1807_08848_amd import msrs
     print(f"[bench] workload {cfg['name']}: FP32 factor/sweeps + FP64 refinement, {args.warmup} warmup + "
           f"{args.steps} timed steps", file=sys.stderr, flush=True)
-    r = run_gpu(cfg, msrs.PREC_FP32_IR, args.steps, args.warmup, tune=True)
-    T, st = r["T"], r["stats"]
+    r = run_gpu(cfg, msrs.PREC_FP32_IR, args.steps, args.warmup, tune=True, graph=True)
+    st = r["stats"]
+    if not r["graph_ok"]:
+        raise RuntimeError("graph replay latched an error or missed the residual tolerance")
+    T = r["T_graph"]
     value = r["n_solves"] * args.steps / T
     # dominant kernel and its roofline
     alg = algorithmic(cfg)
@@ -292,6 +319,9 @@ def main():
                      "avg_launch_ms": avg_ms, "launches": n[dom]},
         "kernel_ms_per_step": {msrs.K_CLASSES[k]: ms[k] / args.steps for k in range(11) if n[k]},
         "ir_iters": st.ir_iters, "max_rel_residual": st.max_rel_residual, "autotune": r["tuned"],
+        "timed_form": "hipGraph replay of the captured step",
+        "graph": {"capture_s": r["graph_capture_s"], "max_rel_residual": r["graph_max_rel_residual"],
+                  "eager_ms_per_step": r["T"] / args.steps * 1e3},
     }
     if not args.no_plain:
         print("[bench] plain FP64 reference (one launch per patch per stage)", file=sys.stderr, flush=True)

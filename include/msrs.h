@@ -157,6 +157,7 @@ typedef struct msrs_stats {
 #define MSRS_K_COARSE   8
 #define MSRS_K_CSOLVE   9
 #define MSRS_K_RECON    10
+#define MSRS_K_GRAPH    11   /* a replay of the captured offline step, as a whole */
 
 /* Library version (major*10000 + minor*100 + patch). */
 int32_t msrs_version(void);
@@ -247,6 +248,32 @@ msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev,
  */
 msrs_status msrs_solve_global_banded(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev,
                                      void* stream);
+
+/*
+ * Capture one offline step -- msrs_assemble_patch(coef_dev),
+ * msrs_sample_local_solutions with device-drawn samples, msrs_range_finder
+ * -- as a HIP graph of the handle's stream (which must not be the default
+ * stream), and instantiate it.  Nothing runs during the capture.  coef_dev
+ * is baked into the graph: it must stay valid, and a replay reads its
+ * current contents.  FP32_IR: the graph runs a fixed number of refinement
+ * iterations, one more than the most any patch needed in the preceding
+ * eager sampling call (required first); converged patches skip their work,
+ * so the results equal the eager ones, and a patch still above ir_tol after
+ * the last iteration latches MSRS_ERR_NOCONV.  A new capture replaces the
+ * previous graph.  Synchronises.  Errors: ARG, STATE, HIP.
+ */
+msrs_status msrs_offline_graph_capture(msrs_handle h, const double* coef_dev);
+
+/* Enqueue one replay of the captured offline step on the handle's stream. */
+msrs_status msrs_offline_graph_launch(msrs_handle h);
+
+/*
+ * Copy the resident snapshots Y, bases Q and singular values (each
+ * nullable; device buffers of Y_total, Q_total, sv_total doubles) on the
+ * handle's stream, without recomputing them.  Errors: ARG, STATE (not
+ * computed yet).
+ */
+msrs_status msrs_copy_results(msrs_handle h, double* Y_out_dev, double* Q_out_dev, double* sv_out_dev);
 
 /*
  * Copy the resident boundary samples Omega (all patches, layout above) of

@@ -273,6 +273,77 @@ double time_calls(Ctx& c, int reps, F&& f) {
 
 }  // namespace
 
+namespace {
+// Enqueue stages a3-a7.  fixed_iters < 0: FP32 refinement until every patch
+// has converged (host checks between iterations); fixed_iters >= 0: exactly
+// that many iterations with no host synchronisation (converged patches skip
+// their work) and a device-side NOCONV check, the form a graph can capture.
+void sample_enqueue(Ctx* c, const double* omega_dev, int fixed_iters) {
+    for_patches(*c, [&](int p0, int p1) { launch_omega(*c, omega_dev, p0, p1); });
+    for_patches(*c, [&](int p0, int p1) { launch_lift(*c, p0, p1); });
+    if (c->prec == MSRS_PREC_FP64) {
+        for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, false); });
+        for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, true, 0); });
+        c->last_ir_iters = 0;
+    } else if (fixed_iters >= 0) {
+        launch_clear_conv(*c);
+        for (int it = 0; it < fixed_iters; ++it) {
+            for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true); });
+            for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it); });
+        }
+        launch_check_conv(*c);
+        c->last_ir_iters = fixed_iters;
+    } else {
+        launch_clear_conv(*c);
+        int it = 0;
+        const int first = std::min(c->ir_max, c->ir_hint);
+        for (; it < first; ++it) {
+            for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true); });
+            for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it); });
+        }
+        // continue until every patch has converged (one host check per extra iteration)
+        std::vector<int32_t> conv(c->n_patches);
+        while (true) {
+            MSRS_HIP_CHECK(hipMemcpyAsync(conv.data(), c->conv, c->n_patches * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+            MSRS_HIP_CHECK(hipStreamSynchronize(c->stream));
+            const bool all = std::all_of(conv.begin(), conv.end(), [](int32_t v) { return v != 0; });
+            if (all || it >= c->ir_max) {
+                if (!all) launch_check_conv(*c);
+                break;
+            }
+            for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true); });
+            for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it); });
+            ++it;
+        }
+        std::vector<int32_t> iters(c->n_patches);
+        MSRS_HIP_CHECK(hipMemcpyAsync(iters.data(), c->iters, c->n_patches * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        MSRS_HIP_CHECK(hipStreamSynchronize(c->stream));
+        int mx = 0;
+        for (int v : iters) mx = std::max(mx, v);
+        c->last_ir_iters = it;
+        c->ir_hint = std::max(1, mx);
+    }
+    for_patches(*c, [&](int p0, int p1) { launch_restrict(*c, p0, p1); });
+}
+
+void assemble_enqueue(Ctx* c, const double* coef_dev) {
+    const int64_t n = c->kind == kElliptic ? (int64_t)c->N * c->N : c->N;
+    MSRS_HIP_CHECK(hipMemcpyAsync(c->coef_copy, coef_dev, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    for_patches(*c, [&](int p0, int p1) {
+        if (c->kind == kElliptic) launch_gather_elliptic(*c, c->coef_copy, p0, p1);
+        else launch_gather_kinetic(*c, c->coef_copy, p0, p1);
+    });
+    for_patches(*c, [&](int p0, int p1) { launch_factor(*c, p0, p1); });
+}
+
+void drop_graph(Ctx* c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+}  // namespace
+
 // ---------------------------------------------------------------- ABI
 extern "C" {
 
@@ -402,13 +473,7 @@ msrs_status msrs_assemble_patch(msrs_handle h, const double* coef_dev) {
     if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
     if (!coef_dev) return fail(c, MSRS_ERR_ARG, "coef_dev is NULL");
     try {
-        const int64_t n = c->kind == kElliptic ? (int64_t)c->N * c->N : c->N;
-        MSRS_HIP_CHECK(hipMemcpyAsync(c->coef_copy, coef_dev, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        for_patches(*c, [&](int p0, int p1) {
-            if (c->kind == kElliptic) launch_gather_elliptic(*c, c->coef_copy, p0, p1);
-            else launch_gather_kinetic(*c, c->coef_copy, p0, p1);
-        });
-        for_patches(*c, [&](int p0, int p1) { launch_factor(*c, p0, p1); });
+        assemble_enqueue(c, coef_dev);
         MSRS_HIP_CHECK(hipGetLastError());
     } catch (const HipError& e) {
         return hip_fail(c, e);
@@ -424,46 +489,7 @@ msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, 
     if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
     if (!c->assembled) return fail(c, MSRS_ERR_STATE, "msrs_assemble_patch must come first");
     try {
-        for_patches(*c, [&](int p0, int p1) { launch_omega(*c, omega_dev, p0, p1); });
-        for_patches(*c, [&](int p0, int p1) { launch_lift(*c, p0, p1); });
-        if (c->prec == MSRS_PREC_FP64) {
-            for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, false); });
-            for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, true, 0); });
-            c->last_ir_iters = 0;
-        } else {
-            launch_clear_conv(*c);
-            int it = 0;
-            const int first = std::min(c->ir_max, c->ir_hint);
-            for (; it < first; ++it) {
-                for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true); });
-                for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it); });
-            }
-            // continue until every patch has converged (one host check per extra iteration)
-            std::vector<int32_t> conv(c->n_patches);
-            while (true) {
-                MSRS_HIP_CHECK(hipMemcpyAsync(conv.data(), c->conv, c->n_patches * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-                MSRS_HIP_CHECK(hipStreamSynchronize(c->stream));
-                const bool all = std::all_of(conv.begin(), conv.end(), [](int32_t v) { return v != 0; });
-                if (all || it >= c->ir_max) {
-                    if (!all) {
-                        const int32_t one = 1;
-                        MSRS_HIP_CHECK(hipMemcpyAsync(c->dflags + 1, &one, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-                        MSRS_HIP_CHECK(hipStreamSynchronize(c->stream));
-                    }
-                    break;
-                }
-                for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true); });
-                for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it); });
-                ++it;
-            }
-            std::vector<int32_t> iters(c->n_patches);
-            MSRS_HIP_CHECK(hipMemcpy(iters.data(), c->iters, c->n_patches * sizeof(int32_t), hipMemcpyDeviceToHost));
-            int mx = 0;
-            for (int v : iters) mx = std::max(mx, v);
-            c->last_ir_iters = it;
-            c->ir_hint = std::max(1, mx);
-        }
-        for_patches(*c, [&](int p0, int p1) { launch_restrict(*c, p0, p1); });
+        sample_enqueue(c, omega_dev, -1);
         if (Y_out_dev)
             MSRS_HIP_CHECK(hipMemcpyAsync(Y_out_dev, c->Y, c->Y_total * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         MSRS_HIP_CHECK(hipGetLastError());
@@ -492,6 +518,74 @@ msrs_status msrs_range_finder(msrs_handle h, double* Q_out_dev, double* sv_out_d
     }
     c->ranged = true;
     c->coarse_ready = false;
+    return MSRS_OK;
+}
+
+msrs_status msrs_offline_graph_capture(msrs_handle h, const double* coef_dev) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
+    if (!coef_dev) return fail(c, MSRS_ERR_ARG, "coef_dev is NULL");
+    if (!c->stream) return fail(c, MSRS_ERR_STATE, "graph capture needs a handle created on a non-default stream");
+    if (c->prec == MSRS_PREC_FP32_IR && !c->sampled) return fail(c, MSRS_ERR_STATE, "an eager msrs_sample_local_solutions must come first");
+    const bool timing = c->timing;
+    try {
+        drop_graph(c);
+        MSRS_HIP_CHECK(hipStreamSynchronize(c->stream));
+        const int iters = c->prec == MSRS_PREC_FP32_IR ? std::min(c->ir_max, c->ir_hint + 1) : 0;
+        c->timing = false;   // no event nodes inside the graph
+        MSRS_HIP_CHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        try {
+            assemble_enqueue(c, coef_dev);
+            sample_enqueue(c, nullptr, iters);
+            for_patches(*c, [&](int p0, int p1) { launch_range(*c, p0, p1); });
+        } catch (const HipError&) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(c->stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        MSRS_HIP_CHECK(hipStreamEndCapture(c->stream, &c->graph));
+        MSRS_HIP_CHECK(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+        c->graph_iters = iters;
+    } catch (const HipError& e) {
+        c->timing = timing;
+        drop_graph(c);
+        return hip_fail(c, e);
+    }
+    c->timing = timing;
+    return MSRS_OK;
+}
+
+msrs_status msrs_offline_graph_launch(msrs_handle h) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
+    if (!c->graph_exec) return fail(c, MSRS_ERR_STATE, "msrs_offline_graph_capture must come first");
+    try {
+        StageTimer t(*c, MSRS_K_GRAPH);
+        MSRS_HIP_CHECK(hipGraphLaunch(c->graph_exec, c->stream));
+    } catch (const HipError& e) {
+        return hip_fail(c, e);
+    }
+    c->assembled = c->sampled = c->ranged = true;
+    c->coarse_ready = false;
+    c->last_ir_iters = c->graph_iters;
+    return MSRS_OK;
+}
+
+msrs_status msrs_copy_results(msrs_handle h, double* Y_out_dev, double* Q_out_dev, double* sv_out_dev) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if ((Y_out_dev && !c->sampled) || ((Q_out_dev || sv_out_dev) && !c->ranged))
+        return fail(c, MSRS_ERR_STATE, "the requested results have not been computed");
+    try {
+        if (Y_out_dev) MSRS_HIP_CHECK(hipMemcpyAsync(Y_out_dev, c->Y, c->Y_total * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        if (Q_out_dev) MSRS_HIP_CHECK(hipMemcpyAsync(Q_out_dev, c->Q, c->Q_total * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        if (sv_out_dev) MSRS_HIP_CHECK(hipMemcpyAsync(sv_out_dev, c->sv, c->sv_total * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    } catch (const HipError& e) {
+        return hip_fail(c, e);
+    }
     return MSRS_OK;
 }
 
@@ -864,6 +958,7 @@ void msrs_destroy(msrs_handle h) {
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     for (auto& w : c->ws)
         if (w.done) (void)hipEventDestroy(w.done);
+    drop_graph(c);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->hflags) (void)hipHostFree(c->hflags);
     delete c;

@@ -1180,4 +1180,15 @@ void launch_clear_conv(Ctx& c) {
     hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(kThreads), 0, c.stream, c.conv, c.n_patches);
 }
 
+// NOCONV if a patch has not converged after a fixed number of refinement
+// iterations (the host-free form of the convergence check).
+__global__ void check_conv_kernel(const int32_t* __restrict__ conv, int n, int32_t* flags) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (!conv[i]) raise_flag(flags, 1);
+}
+
+void launch_check_conv(Ctx& c) {
+    hipLaunchKernelGGL(check_conv_kernel, dim3(1), dim3(kThreads), 0, c.stream, c.conv, c.n_patches, c.dflags);
+}
+
 }  // namespace msrs

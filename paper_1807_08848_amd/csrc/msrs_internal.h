@@ -155,6 +155,11 @@ struct Ctx {
     };
     OnlineWs ws[kOnlineWs];
     int served = 0;               // servers holding this handle (offline and set-up calls refused)
+
+    // captured offline step (msrs_offline_graph_capture)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_iters = 0;
     int32_t n_bdry = 0;
     int64_t n_nodes = 0;
     std::vector<void*> allocs;
@@ -180,6 +185,7 @@ void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it);
 void launch_restrict(Ctx& c, int p0, int p1);
 void launch_range(Ctx& c, int p0, int p1);
 void launch_clear_conv(Ctx& c);
+void launch_check_conv(Ctx& c);
 
 // coarse (k_coarse.hip)
 void coarse_setup(Ctx& c);     // traces, normal matrix, Cholesky (enqueued)

@@ -33,7 +33,7 @@ TUNE_SWEEP_COLS, TUNE_RECON_BATCH, TUNE_APPLY_BATCH = 0, 1, 2
 TUNE_STAGE_OFFLINE, TUNE_STAGE_ONLINE = 0, 1
 TUNE_NAMES = {TUNE_SWEEP_COLS: "sweep_cols", TUNE_RECON_BATCH: "recon_batch", TUNE_APPLY_BATCH: "apply_batch"}
 K_CLASSES = ["assemble", "omega", "lift", "factor", "sweep", "residual", "restrict", "range",
-             "coarse", "csolve", "recon"]
+             "coarse", "csolve", "recon", "graph"]
 
 
 class ProblemDesc(C.Structure):
@@ -106,6 +106,9 @@ _sig = {
     "msrs_server_destroy": (None, [_H]),
     "msrs_set_max_batch": (C.c_int32, [_H, C.c_int32]),
     "msrs_copy_omega": (C.c_int32, [_H, _P]),
+    "msrs_copy_results": (C.c_int32, [_H, _P, _P, _P]),
+    "msrs_offline_graph_capture": (C.c_int32, [_H, _P]),
+    "msrs_offline_graph_launch": (C.c_int32, [_H]),
     "msrs_query_layout": (C.c_int32, [_H, C.POINTER(Layout)]),
     "msrs_set_tuning": (C.c_int32, [_H, C.c_int32, C.c_int32]),
     "msrs_get_tuning": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_int32)]),
@@ -194,6 +197,15 @@ class Problem:
 
     def copy_omega(self, out):
         self._check(_lib.msrs_copy_omega(self.h, _ptr(out)))
+
+    def copy_results(self, Y_out=None, Q_out=None, sv_out=None):
+        self._check(_lib.msrs_copy_results(self.h, _ptr(Y_out), _ptr(Q_out), _ptr(sv_out)))
+
+    def offline_graph_capture(self, coef):
+        self._check(_lib.msrs_offline_graph_capture(self.h, _ptr(coef)))
+
+    def offline_graph_launch(self):
+        self._check(_lib.msrs_offline_graph_launch(self.h))
 
     def assemble_coarse(self):
         self._check(_lib.msrs_assemble_coarse(self.h))

@@ -225,3 +225,50 @@ def test_sweep_width_and_offline_autotune_keep_results(gpu):
         assert [t[1] for t in trials] == [16, 32, 64]
         assert pr.get_tuning(msrs.TUNE_SWEEP_COLS) == min(trials, key=lambda t: t[2])[1]
         pr.range_finder()        # the tuner left the handle sampled
+
+
+def test_offline_graph_replays_match_eager(gpu):
+    """The captured offline step replays to the eager results (every replay, with
+    eager torch work and synchronisations between replays) and reads the current
+    coefficient values."""
+    import torch
+    from paper_1807_08848_amd import msrs
+    cfg = configs.small_elliptic(N=64, M=4, delta=4, s=12, k=8, coef="lognormal")
+    st = torch.cuda.Stream()
+    d = msrs.make_desc(msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"], list(cfg["overlap"]), cfg["s"], cfg["k"],
+                       precision=FP32_IR, seed=cfg["seed"])
+    with torch.cuda.stream(st), msrs.Problem(d, stream=st) as pr:
+        L = pr.layout()
+        a = torch.tensor(cfg["coef"], device="cuda:0")
+
+        def grab():
+            Y = torch.empty(L.Y_total, device="cuda:0", dtype=torch.float64)
+            Q = torch.empty(L.Q_total, device="cuda:0", dtype=torch.float64)
+            sv = torch.empty(L.sv_total, device="cuda:0", dtype=torch.float64)
+            pr.copy_results(Y, Q, sv)
+            st.synchronize()
+            return Y.cpu().numpy(), Q.cpu().numpy(), sv.cpu().numpy()
+
+        pr.assemble_patch(a)
+        pr.sample_local_solutions()
+        pr.range_finder()
+        ref = grab()
+        pr.offline_graph_capture(a)
+        for rep in range(3):
+            x = torch.randn(4096, device="cuda:0")          # eager work between replays
+            float(x.sum())
+            pr.offline_graph_launch()
+            got = grab()
+            for g, r in zip(got, ref):
+                assert np.array_equal(g, r), rep
+        assert pr.stats().error_latched == 0
+        # a replay reads the coefficient buffer's current contents
+        a.mul_(torch.tensor(1.0 + 0.2 * np.sin(np.arange(a.numel())), device="cuda:0"))
+        pr.offline_graph_launch()
+        got = grab()
+        pr.assemble_patch(a)
+        pr.sample_local_solutions()
+        pr.range_finder()
+        ref2 = grab()
+        assert np.abs(got[0] - ref2[0]).max() <= 1e-12 * np.abs(ref2[0]).max()
+        assert not np.allclose(got[0], ref[0])
