@@ -327,27 +327,53 @@ constexpr int kFactorThreads = 512;
 
 // Inverse of a 16 x 16 block (row-major in LDS, ld 16) by one wave: lane l
 // holds row l%16, columns 4(l/16)..4(l/16)+3; Gauss-Jordan without pivoting.
+// FP32 pivot step K: the pivot row reaches every lane of a 16-lane row by a
+// DPP row broadcast, the pivot itself by readlane, and its reciprocal is the
+// hardware approximation (the FP32 factor is refined in FP64 downstream).
+template <int K>
+__device__ __forceinline__ void inv16_pivot_f32(float (&a)[4], int r, int cg, bool& bad) {
+    constexpr int kg = K >> 2, ku = K & 3;
+    float prow[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) prow[u] = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(a[u]), 0x150 + K, 0xF, 0xF, false));
+    const float pcol = __shfl(a[ku], r + 16 * kg, 64);
+    const float piv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[ku]), K + 16 * kg));
+    if (!(piv > 0.f) || !isfinite(piv)) bad = true;
+    const float ip = __builtin_amdgcn_rcpf(piv);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const bool ck = (4 * cg + u) == K;
+        const float gen = ck ? -pcol * ip : a[u] - pcol * ip * prow[u];
+        a[u] = (r == K) ? (ck ? ip : prow[u] * ip) : gen;
+    }
+    if constexpr (K + 1 < 16) inv16_pivot_f32<K + 1>(a, r, cg, bad);
+}
+
 template <typename T>
 __device__ __forceinline__ void inv16_wave(const T* A, T* Dinv, bool& bad) {
     const int l = threadIdx.x & 63, r = l & 15, cg = l >> 4;
     T a[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) a[u] = A[r * 16 + 4 * cg + u];
+    if constexpr (sizeof(T) == 4) {
+        inv16_pivot_f32<0>(a, r, cg, bad);
+    } else {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int kg = k >> 2, ku = k & 3;
-        T prow[4];
+        for (int k = 0; k < 16; ++k) {
+            const int kg = k >> 2, ku = k & 3;
+            T prow[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) prow[u] = __shfl(a[u], k + 16 * cg, 64);
-        const T pcol = __shfl(a[ku], r + 16 * kg, 64);
-        const T piv = __shfl(a[ku], k + 16 * kg, 64);
-        if (!(piv > T(0)) || !isfinite((double)piv)) bad = true;
-        const T ip = T(1) / piv;
+            for (int u = 0; u < 4; ++u) prow[u] = __shfl(a[u], k + 16 * cg, 64);
+            const T pcol = __shfl(a[ku], r + 16 * kg, 64);
+            const T piv = __shfl(a[ku], k + 16 * kg, 64);
+            if (!(piv > T(0)) || !isfinite((double)piv)) bad = true;
+            const T ip = T(1) / piv;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const bool ck = (4 * cg + u) == k;
-            const T gen = ck ? -pcol * ip : a[u] - pcol * ip * prow[u];
-            a[u] = (r == k) ? (ck ? ip : prow[u] * ip) : gen;
+            for (int u = 0; u < 4; ++u) {
+                const bool ck = (4 * cg + u) == k;
+                const T gen = ck ? -pcol * ip : a[u] - pcol * ip * prow[u];
+                a[u] = (r == k) ? (ck ? ip : prow[u] * ip) : gen;
+            }
         }
     }
 #pragma unroll
@@ -424,75 +450,81 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
                 return diag_entry<KIND>(P, aL, vw, dx, inv_eps, l, i, j);
             }
         };
-        // D_l = Dg_l - Low_l E_{l-1} Up_{l-1}, formed in place in LDS in two
-        // passes (Z = E_{l-1} Up_{l-1}, then D = Dg_l - Low_l Z), then loaded
-        // into the owned tiles.  Thread element e: o = tid + e * 512.
-        constexpr int EPT = (BP * BP + kFactorThreads - 1) / kFactorThreads;
-        if (l > 0) {
-            T z[EPT];
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const int o = tid + e * kFactorThreads;
-                const int i = o / BP, j = o - (o / BP) * BP;
-                double v = 0.0;
-                if (o < BP * BP && i < b && j < b) {
-                    if (KIND == kElliptic) {
-                        // (E U)(i,j) = E(i,j-1) U(j-1,j) + E(i,j) U(j,j) + E(i,j+1) U(j+1,j)
-                        v = (double)Es[i * LDE + j] * cf[j];
-                        if (j > 0) v += (double)Es[i * LDE + j - 1] * cf[BP + j - 1];
-                        if (j < b - 1) v += (double)Es[i * LDE + j + 1] * cf[BP + j];
-                    } else {
-                        v = (double)Es[i * LDE + j] * cf[BP + j];
-                    }
-                }
-                z[e] = (T)v;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const int o = tid + e * kFactorThreads;
-                if (o < BP * BP) Es[(o / BP) * LDE + o % BP] = z[e];
-            }
-            __syncthreads();
-        }
-        {
-            T d[EPT];
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const int o = tid + e * kFactorThreads;
-                const int i = o / BP, j = o - (o / BP) * BP;
-                double v = (i == j) ? 1.0 : 0.0;
-                if (o < BP * BP && i < b && j < b) {
-                    v = dg(i, j);
-                    if (l > 0) {
-                        if (KIND == kElliptic) {
-                            // (U^T Z)(i,j) = U(i-1,i) Z(i-1,j) + U(i,i) Z(i,j) + U(i+1,i) Z(i+1,j)
-                            double sv = cf[i] * (double)Es[i * LDE + j];
-                            if (i > 0) sv += cf[BP + i - 1] * (double)Es[(i - 1) * LDE + j];
-                            if (i < b - 1) sv += cf[BP + i] * (double)Es[(i + 1) * LDE + j];
-                            v -= sv;
-                        } else {
-                            v -= cf[i] * (double)Es[i * LDE + j];
-                        }
-                    }
-                }
-                d[e] = (T)v;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const int o = tid + e * kFactorThreads;
-                if (o < BP * BP) Es[(o / BP) * LDE + o % BP] = d[e];
-            }
-            __syncthreads();
-        }
+        // D_l = Dg_l - Up_{l-1}^T E_{l-1} Up_{l-1}, evaluated straight into the
+        // owned MFMA tiles from E_{l-1} (row-major in LDS): no write-back, one
+        // barrier.  Indices past the line (outside [0, b)) carry zero
+        // coefficients; their reads are clamped inside the tile (finite values
+        // times zero).  Past the line, D is the identity (padding).
 #pragma unroll
         for (int q = 0; q < NSLOT; ++q) {
             const int idx = q * 8 + w;
             if (idx >= NT) continue;
             const int ti = idx / R, tj = idx - ti * R;
+            const int j = 16 * tj + li;
+            if constexpr (KIND == kElliptic && sizeof(T) == 4) {
+                // f32 tiles: a lane's rows ib..ib+3 are consecutive and share column j,
+                // so Z(i', j) = (E_{l-1} Up)(i', j) is formed once for rows ib-1..ib+4
+                const int ib = 16 * ti + 4 * lk;
+                double zc[6];
+                if (l > 0) {
+                    const double c0 = (j > 0 && j < b) ? cf[BP + j - 1] : 0.0;
+                    const double c1 = (j < b) ? cf[j] : 0.0;
+                    const double c2 = (j < b - 1) ? cf[BP + j] : 0.0;
+                    const int jm = j > 0 ? j - 1 : 0, jp = j < BP - 1 ? j + 1 : BP - 1;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) tile[q][t] = Es[(16 * ti + Mfma<T>::row(lane, t)) * LDE + 16 * tj + li];
+                    for (int r = 0; r < 6; ++r) {
+                        const int ir = ib - 1 + r;
+                        const int irc = ir < 0 ? 0 : (ir > BP - 1 ? BP - 1 : ir);
+                        const T* er = Es + irc * LDE;
+                        const double z = c0 * (double)er[jm] + c1 * (double)er[j] + c2 * (double)er[jp];
+                        zc[r] = (ir >= 0 && ir < b) ? z : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int i = ib + t;
+                    double v = (i == j) ? 1.0 : 0.0;
+                    if (i < b && j < b) {
+                        v = dg(i, j);
+                        if (l > 0) {
+                            const double r0 = i > 0 ? cf[BP + i - 1] : 0.0;
+                            const double r2 = i < b - 1 ? cf[BP + i] : 0.0;
+                            v -= r0 * zc[t] + cf[i] * zc[t + 1] + r2 * zc[t + 2];
+                        }
+                    }
+                    tile[q][t] = (T)v;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int i = 16 * ti + Mfma<T>::row(lane, t);
+                    double v = (i == j) ? 1.0 : 0.0;
+                    if (i < b && j < b) {
+                        v = dg(i, j);
+                        if (l > 0) {
+                            if (KIND == kElliptic) {
+                                // sum over i' in {i-1, i, i+1}, j' in {j-1, j, j+1} of Up(i', i) E(i', j') Up(j', j)
+                                double sv = 0.0;
+#pragma unroll
+                                for (int di = -1; di <= 1; ++di) {
+                                    const int ir = i + di;
+                                    if (ir < 0 || ir >= b) continue;
+                                    const double ru = di == 0 ? cf[i] : (di < 0 ? cf[BP + i - 1] : cf[BP + i]);
+                                    const T* er = Es + ir * LDE;
+                                    double z = cf[j] * (double)er[j];
+                                    if (j > 0) z += cf[BP + j - 1] * (double)er[j - 1];
+                                    if (j < b - 1) z += cf[BP + j] * (double)er[j + 1];
+                                    sv += ru * z;
+                                }
+                                v -= sv;
+                            } else {
+                                v -= cf[i] * (double)Es[i * LDE + j] * cf[BP + j];
+                            }
+                        }
+                    }
+                    tile[q][t] = (T)v;
+                }
+            }
         }
         __syncthreads();   // Es (E_{l-1}) no longer needed: panel buffers may overwrite it
         // blocked Gauss-Jordan over the panels
