@@ -78,7 +78,7 @@ void for_patches(Ctx& c, F&& f) {
 
 void build_elliptic(Ctx& c) {
     const int N = c.N, M = c.M, nH = N / M;
-    int64_t a_off = 0, om_off = 0, x_off = 0, E_off = 0, Y_off = 0, Q_off = 0, sv_off = 0, rn_off = 0;
+    int64_t a_off = 0, om_off = 0, x_off = 0, E_off = 0, Y_off = 0, Q_off = 0, sv_off = 0, rn_off = 0, tw_off = 0;
     for (int m2 = 0; m2 < M; ++m2)
         for (int m1 = 0; m1 < M; ++m1) {
             const int p = m2 * M + m1;
@@ -109,9 +109,10 @@ void build_elliptic(Ctx& c) {
             P.Q_off = Q_off; Q_off += (int64_t)P.nrows * P.ncols;
             P.sv_off = sv_off; sv_off += P.s;
             P.rn_off = rn_off; rn_off += 2 * P.sp;
+            P.tw_off = tw_off; tw_off += 2LL * P.bp * P.sp;
             c.hp.push_back(P);
         }
-    c.aL_total = a_off; c.omega_total = om_off; c.x_total = x_off; c.E_total = E_off;
+    c.aL_total = a_off; c.omega_total = om_off; c.x_total = x_off; c.E_total = E_off; c.tw_total = tw_off;
     c.Y_total = Y_off; c.Q_total = Q_off; c.sv_total = sv_off;
     c.n_bdry = 4 * N;
     c.n_nodes = (int64_t)(N + 1) * (N + 1);
@@ -120,7 +121,7 @@ void build_elliptic(Ctx& c) {
 void build_kinetic(Ctx& c) {
     const int Nx = c.N, M = c.M, nH = Nx / M, nv = c.nv;
     const bool ends = (c.flags & MSRS_FLAG_FULL_BASIS_ENDS) != 0;
-    int64_t a_off = 0, om_off = 0, x_off = 0, E_off = 0, Y_off = 0, Q_off = 0, sv_off = 0, rn_off = 0;
+    int64_t a_off = 0, om_off = 0, x_off = 0, E_off = 0, Y_off = 0, Q_off = 0, sv_off = 0, rn_off = 0, tw_off = 0;
     for (int m = 0; m < M; ++m) {
         const bool full = ends && (m == 0 || m == M - 1);
         const int d = full ? 0 : c.overlap[m];
@@ -146,9 +147,10 @@ void build_kinetic(Ctx& c) {
         P.Q_off = Q_off; Q_off += (int64_t)P.nrows * P.ncols;
         P.sv_off = sv_off; sv_off += P.s;
         P.rn_off = rn_off; rn_off += 2 * P.sp;
+        P.tw_off = tw_off; tw_off += 2LL * P.bp * P.sp;
         c.hp.push_back(P);
     }
-    c.aL_total = a_off; c.omega_total = om_off; c.x_total = x_off; c.E_total = E_off;
+    c.aL_total = a_off; c.omega_total = om_off; c.x_total = x_off; c.E_total = E_off; c.tw_total = tw_off;
     c.Y_total = Y_off; c.Q_total = Q_off; c.sv_total = sv_off;
     c.n_bdry = nv;
     c.n_nodes = (int64_t)Nx * nv;
@@ -398,6 +400,7 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->x64 = dalloc<double>(*c, c->x_total);
         if (ir) c->x32 = dalloc<float>(*c, c->x_total);
         c->E = ir ? (void*)dalloc<float>(*c, c->E_total) : (void*)dalloc<double>(*c, c->E_total);
+        c->tw = dalloc<double>(*c, c->tw_total);
         c->Y = dalloc<double>(*c, c->Y_total);
         c->Q = dalloc<double>(*c, c->Q_total);
         c->rf_ws = dalloc<double>(*c, c->Q_total);

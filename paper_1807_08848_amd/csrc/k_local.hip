@@ -198,124 +198,6 @@ __device__ __forceinline__ double diag_entry(const PatchDesc& P, const double* a
     }
 }
 
-template <typename T, int KIND, int R>
-__device__ void factor_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw, double dx,
-                            double inv_eps, T* __restrict__ E, T* Es, T* prow, T* pcol, double* cf, int32_t* flags) {
-    constexpr int BP = 16 * R;
-    constexpr int LDE = BP + 1;
-    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-    const int b = P.b, nl = P.nl;
-    T A[R][R];
-    bool bad = false;
-    for (int l = 0; l < nl; ++l) {
-        // coupling coefficients of the previous line (elliptic U_{l-1}: cell row l)
-        if (KIND == kElliptic) {
-            if (l > 0)
-                for (int a = tid; a < b; a += kThreads) {
-                    cf[a] = -(a_cell(aL, P.L, l, a) + a_cell(aL, P.L, l, a + 1)) / 6.0;   // U diagonal
-                    cf[BP + a] = -a_cell(aL, P.L, l, a + 1) / 3.0;                          // U(a, a+1)
-                }
-        } else {
-            for (int a = tid; a < b; a += kThreads) {
-                const double v = vw[a];
-                cf[a] = v > 0 ? v / dx : 0.0;         // v+/dx
-                cf[BP + a] = v < 0 ? -v / dx : 0.0;   // v-/dx
-            }
-        }
-        __syncthreads();
-        // D_l = Dg_l - Low_l E_{l-1} Up_{l-1}
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int c = 0; c < R; ++c) {
-                const int i = ty + 16 * r, j = tx + 16 * c;
-                double d;
-                if (i >= b || j >= b) {
-                    d = (i == j) ? 1.0 : 0.0;
-                } else {
-                    d = diag_entry<KIND>(P, aL, vw, dx, inv_eps, l, i, j);
-                    if (l > 0) {
-                        if (KIND == kElliptic) {
-                            double s = 0.0;
-#pragma unroll
-                            for (int da = -1; da <= 1; ++da) {
-                                const int a = i + da;
-                                if (a < 0 || a >= b) continue;
-                                const double uai = (da == 0) ? cf[i] : cf[BP + min(a, i)];
-                                double t = 0.0;
-#pragma unroll
-                                for (int dc = -1; dc <= 1; ++dc) {
-                                    const int cc = j + dc;
-                                    if (cc < 0 || cc >= b) continue;
-                                    const double ucj = (dc == 0) ? cf[j] : cf[BP + min(cc, j)];
-                                    t += (double)Es[a * LDE + cc] * ucj;
-                                }
-                                s += uai * t;
-                            }
-                            d -= s;
-                        } else {
-                            d -= cf[i] * (double)Es[i * LDE + j] * cf[BP + j];
-                        }
-                    }
-                }
-                A[r][c] = (T)d;
-            }
-        // Gauss-Jordan inversion in registers; pivot k = 16*kr + kt
-#pragma unroll
-        for (int kr = 0; kr < R; ++kr) {
-            for (int kt = 0; kt < 16; ++kt) {
-                const int k = 16 * kr + kt;
-                if (k >= b) break;
-                T* pr_s = prow + (k & 1) * BP;
-                T* pc_s = pcol + (k & 1) * BP;
-                if (ty == kt) {
-#pragma unroll
-                    for (int c = 0; c < R; ++c) pr_s[tx + 16 * c] = A[kr][c];
-                }
-                if (tx == kt) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) pc_s[ty + 16 * r] = A[r][kr];
-                }
-                __syncthreads();
-                const T piv = pr_s[k];
-                if (!(piv > T(0)) || !isfinite((double)piv)) bad = true;
-                const T ip = T(1) / piv;
-                T pr[R], pc[R];
-#pragma unroll
-                for (int c = 0; c < R; ++c) pr[c] = pr_s[tx + 16 * c];
-#pragma unroll
-                for (int r = 0; r < R; ++r) pc[r] = pc_s[ty + 16 * r] * ip;
-                const bool isRow = (ty == kt), isCol = (tx == kt);
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                    for (int c = 0; c < R; ++c) {
-                        T g = A[r][c] - pc[r] * pr[c];
-                        if (c == kr) g = isCol ? ((isRow && r == kr) ? ip : -pc[r]) : g;
-                        if (r == kr) g = isRow ? ((isCol && c == kr) ? ip : pr[c] * ip) : g;
-                        A[r][c] = g;
-                    }
-            }
-        }
-        __syncthreads();   // all reads of Es (previous line) are done
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int c = 0; c < R; ++c) Es[(ty + 16 * r) * LDE + tx + 16 * c] = A[r][c];
-        __syncthreads();
-        // store E_l in the MFMA operand order of the sweeps: for row tile rt,
-        // lane (li, lk) and k-step kk, E_l(16 rt + li, 4 kk + lk) sits at
-        // ((rt * 64 + lane) * BP/4 + kk), so each lane reads one contiguous run
-        T* El = E + (int64_t)l * BP * BP;
-        constexpr int NKS = BP / 4;
-        for (int o = tid; o < BP * BP; o += kThreads) {
-            const int kk = o % NKS, t = o / NKS;
-            const int lane = t & 63, rt = t >> 6;
-            El[o] = Es[(16 * rt + (lane & 15)) * LDE + 4 * kk + (lane >> 4)];
-        }
-    }
-    if (bad) raise_flag(flags, 0);
-}
 
 // ---- blocked Gauss-Jordan on MFMA
 // The block D_l (BP = 16 R) is held as R x R tiles of 16 x 16 in MFMA
@@ -380,10 +262,19 @@ __device__ __forceinline__ void inv16_wave(const T* A, T* Dinv, bool& bad) {
     for (int u = 0; u < 4; ++u) Dinv[r * 16 + 4 * cg + u] = a[u];
 }
 
-template <typename T, int KIND, int R>
+// The block-tridiagonal elimination runs from both ends ("twisted"): the
+// top half eliminates lines 0 .. m-1 downwards (D_l = A_l - Low_l E_{l-1}
+// Up_{l-1}), the bottom half lines nl-1 .. m+1 upwards (D_l = A_l - Up_l
+// E_{l+1} Low_{l+1}), both at once, and the middle line m = nl/2 takes both
+// Schur terms.  E_l = D_l^{-1} is stored at line l in the sweep's MFMA
+// operand order.  This halves the sequential chain per patch.
+//
+// Mode: MID = false runs one half (dir = +1 top, -1 bottom); MID = true the
+// middle line, reading E_{m-1} and E_{m+1} back from HBM.
+template <typename T, int KIND, int R, bool MID>
 __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw,
                                               double dx, double inv_eps, T* __restrict__ E, T* lds, double* cf,
-                                              double* crow, int32_t* flags) {
+                                              double* crow, int dir, int32_t* flags) {
     constexpr int BP = 16 * R, LDE = BP + 1, NT = R * R, NSLOT = (NT + 7) / 8;
     constexpr int NKS = BP / 4;
     typedef typename Mfma<T>::acc Acc;
@@ -401,7 +292,12 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
         lk = lane >> 4;
     };
     const int b = P.b, nl = P.nl, L = P.L;
-    T* Es = lds;                         // E_{l-1}, BP x LDE (row-major)
+    const int m = nl / 2;
+    // lines of this block: line0, line0 + dir, ... (nsteps of them)
+    const int nsteps = MID ? 1 : (dir > 0 ? m : nl - 1 - m);
+    const int line0 = MID ? m : (dir > 0 ? 0 : nl - 1);
+    if (nsteps <= 0) return;   // uniform over the workgroup
+    T* Es = lds;                         // E of the previously eliminated line, BP x LDE (row-major)
     // panel buffers alias Es (free once D_l is formed)
     T* Pc = lds;                         // [2][BP x 16]  column panel (row i, panel column k)
     T* Pr = lds + 2 * BP * 16;           // [2][16 x BP]  row panel
@@ -410,14 +306,16 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
     Acc tile[NSLOT];
     bool bad = false;
     const int npan = (b + 15) / 16;
-    // elliptic: cell rows r and r+1 of the coefficient block live in crow[r & 1],
-    // crow[(r + 1) & 1] (ld kMaxLine + 1); row l + 2 is prefetched into a register
+    // elliptic: cell row r lives in crow[r & 1] (ld kMaxLine + 1); a line
+    // needs its two bounding cell rows, and each step brings one new row,
+    // prefetched into a register one step ahead
     double rnext = 0.0;
+    const int rnew0 = dir > 0 ? line0 + 2 : line0 - 1;   // the row the second step needs
     if (KIND == kElliptic) {
         if (tid < L) {
-            crow[tid] = aL[tid];
-            crow[(kMaxLine + 1) + tid] = aL[L + tid];
-            if (nl >= 2) rnext = aL[2 * L + tid];
+            crow[(line0 & 1) * (kMaxLine + 1) + tid] = aL[line0 * L + tid];
+            crow[((line0 + 1) & 1) * (kMaxLine + 1) + tid] = aL[(line0 + 1) * L + tid];
+            if (!MID && nsteps > 1) rnext = aL[rnew0 * L + tid];
         }
     } else {
         for (int a = tid; a < b; a += kFactorThreads) {
@@ -426,20 +324,39 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
             cf[BP + a] = v < 0 ? -v / dx : 0.0;
         }
     }
+    // global E block (MFMA operand order) -> Es (row-major)
+    auto load_E = [&](const T* Eg) {
+        for (int o = tid; o < BP * BP; o += kFactorThreads) {
+            const int kk = o % NKS, t = o / NKS;
+            const int ln = t & 63, rt = t >> 6;
+            Es[(16 * rt + (ln & 15)) * LDE + 4 * kk + (ln >> 4)] = Eg[o];
+        }
+    };
+    // elliptic coupling block between two adjacent lines from their shared
+    // cell row cr (symmetric tridiagonal): diagonal -(c_a + c_{a+1})/6,
+    // off-diagonal (a, a+1) -c_{a+1}/3
+    auto set_cf = [&](const double* cr) {
+        for (int a = tid; a < b; a += kFactorThreads) {
+            cf[a] = -(cr[a] + cr[a + 1]) / 6.0;
+            cf[BP + a] = -cr[a + 1] / 3.0;
+        }
+    };
 
-    for (int l = 0; l < nl; ++l) {
+    for (int l = 0; l < nsteps; ++l) {
         launder();
-        const double* rA = crow + (l & 1) * (kMaxLine + 1);          // cell row l
-        const double* rB = crow + ((l + 1) & 1) * (kMaxLine + 1);    // cell row l + 1
+        const int ln = line0 + dir * l;
+        const double* rA = crow + (ln & 1) * (kMaxLine + 1);          // cell row ln
+        const double* rB = crow + ((ln + 1) & 1) * (kMaxLine + 1);    // cell row ln + 1
+        // the Schur terms of this line: previously eliminated neighbour(s)
+        const bool term1 = MID ? (m > 0) : (l > 0);
+        const bool term2 = MID && (m < nl - 1);
+        if (MID && term1) load_E(E + (int64_t)(m - 1) * BP * BP);
         __syncthreads();
-        // coupling of the previous line (elliptic U_{l-1}: cell row l)
-        if (KIND == kElliptic && l > 0)
-            for (int a = tid; a < b; a += kFactorThreads) {
-                cf[a] = -(rA[a] + rA[a + 1]) / 6.0;
-                cf[BP + a] = -rA[a + 1] / 3.0;
-            }
+        // coupling to the first neighbour: top / middle -> line ln-1 (cell row ln),
+        // bottom -> line ln+1 (cell row ln+1)
+        if (KIND == kElliptic && term1) set_cf(dir < 0 ? rB : rA);
         __syncthreads();
-        // diagonal block entry (i, j < b) of line l
+        // diagonal block entry (i, j < b) of line ln
         auto dg = [&](int i, int j) -> double {
             if (KIND == kElliptic) {
                 if (i == j) return (2.0 / 3.0) * (rB[i + 1] + rB[i] + rA[i] + rA[i + 1]);
@@ -447,86 +364,99 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
                 if (i == j + 1) return -(rB[j + 1] + rA[j + 1]) / 6.0;
                 return 0.0;
             } else {
-                return diag_entry<KIND>(P, aL, vw, dx, inv_eps, l, i, j);
+                return diag_entry<KIND>(P, aL, vw, dx, inv_eps, ln, i, j);
             }
         };
-        // D_l = Dg_l - Up_{l-1}^T E_{l-1} Up_{l-1}, evaluated straight into the
-        // owned MFMA tiles from E_{l-1} (row-major in LDS): no write-back, one
-        // barrier.  Indices past the line (outside [0, b)) carry zero
-        // coefficients; their reads are clamped inside the tile (finite values
-        // times zero).  Past the line, D is the identity (padding).
+        // D = (init ? Dg : D) - (term ? C^T E C : 0) straight into the owned
+        // MFMA tiles from the neighbour's E (row-major in LDS): no write-back.
+        // Indices past the line (outside [0, b)) carry zero coefficients;
+        // their reads are clamped inside the tile (finite values times zero).
+        // Past the line, D is the identity (padding).  Kinetic: the coupling
+        // is diagonal, Low = v+/dx before Up = v-/dx (top) or after (bottom).
+        auto schur = [&](bool init, bool term, bool kin_rev) {
 #pragma unroll
-        for (int q = 0; q < NSLOT; ++q) {
-            const int idx = q * 8 + w;
-            if (idx >= NT) continue;
-            const int ti = idx / R, tj = idx - ti * R;
-            const int j = 16 * tj + li;
-            if constexpr (KIND == kElliptic && sizeof(T) == 4) {
-                // f32 tiles: a lane's rows ib..ib+3 are consecutive and share column j,
-                // so Z(i', j) = (E_{l-1} Up)(i', j) is formed once for rows ib-1..ib+4
-                const int ib = 16 * ti + 4 * lk;
-                double zc[6];
-                if (l > 0) {
-                    const double c0 = (j > 0 && j < b) ? cf[BP + j - 1] : 0.0;
-                    const double c1 = (j < b) ? cf[j] : 0.0;
-                    const double c2 = (j < b - 1) ? cf[BP + j] : 0.0;
-                    const int jm = j > 0 ? j - 1 : 0, jp = j < BP - 1 ? j + 1 : BP - 1;
+            for (int q = 0; q < NSLOT; ++q) {
+                const int idx = q * 8 + w;
+                if (idx >= NT) continue;
+                const int ti = idx / R, tj = idx - ti * R;
+                const int j = 16 * tj + li;
+                if constexpr (KIND == kElliptic && sizeof(T) == 4) {
+                    // f32 tiles: a lane's rows ib..ib+3 are consecutive and share column j,
+                    // so Z(i', j) = (E C)(i', j) is formed once for rows ib-1..ib+4
+                    const int ib = 16 * ti + 4 * lk;
+                    double zc[6];
+                    if (term) {
+                        const double c0 = (j > 0 && j < b) ? cf[BP + j - 1] : 0.0;
+                        const double c1 = (j < b) ? cf[j] : 0.0;
+                        const double c2 = (j < b - 1) ? cf[BP + j] : 0.0;
+                        const int jm = j > 0 ? j - 1 : 0, jp = j < BP - 1 ? j + 1 : BP - 1;
 #pragma unroll
-                    for (int r = 0; r < 6; ++r) {
-                        const int ir = ib - 1 + r;
-                        const int irc = ir < 0 ? 0 : (ir > BP - 1 ? BP - 1 : ir);
-                        const T* er = Es + irc * LDE;
-                        const double z = c0 * (double)er[jm] + c1 * (double)er[j] + c2 * (double)er[jp];
-                        zc[r] = (ir >= 0 && ir < b) ? z : 0.0;
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int i = ib + t;
-                    double v = (i == j) ? 1.0 : 0.0;
-                    if (i < b && j < b) {
-                        v = dg(i, j);
-                        if (l > 0) {
-                            const double r0 = i > 0 ? cf[BP + i - 1] : 0.0;
-                            const double r2 = i < b - 1 ? cf[BP + i] : 0.0;
-                            v -= r0 * zc[t] + cf[i] * zc[t + 1] + r2 * zc[t + 2];
+                        for (int r = 0; r < 6; ++r) {
+                            const int ir = ib - 1 + r;
+                            const int irc = ir < 0 ? 0 : (ir > BP - 1 ? BP - 1 : ir);
+                            const T* er = Es + irc * LDE;
+                            const double z = c0 * (double)er[jm] + c1 * (double)er[j] + c2 * (double)er[jp];
+                            zc[r] = (ir >= 0 && ir < b) ? z : 0.0;
                         }
                     }
-                    tile[q][t] = (T)v;
-                }
-            } else {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int i = 16 * ti + Mfma<T>::row(lane, t);
-                    double v = (i == j) ? 1.0 : 0.0;
-                    if (i < b && j < b) {
-                        v = dg(i, j);
-                        if (l > 0) {
-                            if (KIND == kElliptic) {
-                                // sum over i' in {i-1, i, i+1}, j' in {j-1, j, j+1} of Up(i', i) E(i', j') Up(j', j)
-                                double sv = 0.0;
-#pragma unroll
-                                for (int di = -1; di <= 1; ++di) {
-                                    const int ir = i + di;
-                                    if (ir < 0 || ir >= b) continue;
-                                    const double ru = di == 0 ? cf[i] : (di < 0 ? cf[BP + i - 1] : cf[BP + i]);
-                                    const T* er = Es + ir * LDE;
-                                    double z = cf[j] * (double)er[j];
-                                    if (j > 0) z += cf[BP + j - 1] * (double)er[j - 1];
-                                    if (j < b - 1) z += cf[BP + j] * (double)er[j + 1];
-                                    sv += ru * z;
-                                }
-                                v -= sv;
-                            } else {
-                                v -= cf[i] * (double)Es[i * LDE + j] * cf[BP + j];
+                    for (int t = 0; t < 4; ++t) {
+                        const int i = ib + t;
+                        double v = init ? ((i == j) ? 1.0 : 0.0) : (double)tile[q][t];
+                        if (i < b && j < b) {
+                            if (init) v = dg(i, j);
+                            if (term) {
+                                const double r0 = i > 0 ? cf[BP + i - 1] : 0.0;
+                                const double r2 = i < b - 1 ? cf[BP + i] : 0.0;
+                                v -= r0 * zc[t] + cf[i] * zc[t + 1] + r2 * zc[t + 2];
                             }
                         }
+                        tile[q][t] = (T)v;
                     }
-                    tile[q][t] = (T)v;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int i = 16 * ti + Mfma<T>::row(lane, t);
+                        double v = init ? ((i == j) ? 1.0 : 0.0) : (double)tile[q][t];
+                        if (i < b && j < b) {
+                            if (init) v = dg(i, j);
+                            if (term) {
+                                if (KIND == kElliptic) {
+                                    // sum over i' in {i-1, i, i+1}, j' in {j-1, j, j+1} of C(i', i) E(i', j') C(j', j)
+                                    double sv = 0.0;
+#pragma unroll
+                                    for (int di = -1; di <= 1; ++di) {
+                                        const int ir = i + di;
+                                        if (ir < 0 || ir >= b) continue;
+                                        const double ru = di == 0 ? cf[i] : (di < 0 ? cf[BP + i - 1] : cf[BP + i]);
+                                        const T* er = Es + ir * LDE;
+                                        double z = cf[j] * (double)er[j];
+                                        if (j > 0) z += cf[BP + j - 1] * (double)er[j - 1];
+                                        if (j < b - 1) z += cf[BP + j] * (double)er[j + 1];
+                                        sv += ru * z;
+                                    }
+                                    v -= sv;
+                                } else {
+                                    v -= kin_rev ? cf[BP + i] * (double)Es[i * LDE + j] * cf[j]
+                                                 : cf[i] * (double)Es[i * LDE + j] * cf[BP + j];
+                                }
+                            }
+                        }
+                        tile[q][t] = (T)v;
+                    }
                 }
             }
+        };
+        schur(true, term1, dir < 0);
+        if (term2) {
+            // middle line: second term from the line below (E_{m+1}, cell row m+1)
+            __syncthreads();
+            load_E(E + (int64_t)(m + 1) * BP * BP);
+            if (KIND == kElliptic) set_cf(rB);
+            __syncthreads();
+            schur(false, true, true);
         }
-        __syncthreads();   // Es (E_{l-1}) no longer needed: panel buffers may overwrite it
+        __syncthreads();   // Es no longer needed: panel buffers may overwrite it
         // blocked Gauss-Jordan over the panels
         for (int pn = 0; pn < npan; ++pn) {
             launder();
@@ -605,7 +535,8 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
         }
         __syncthreads();   // panel buffers done: Es may be rewritten
         launder();
-        // E_l -> Es (row-major), then to global in the sweep's MFMA operand order
+        // E_ln -> Es (row-major, the next step's neighbour), then to global in
+        // the sweep's MFMA operand order
 #pragma unroll
         for (int q = 0; q < NSLOT; ++q) {
             const int idx = q * 8 + w;
@@ -615,28 +546,33 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
             for (int t = 0; t < 4; ++t) Es[(16 * ti + Mfma<T>::row(lane, t)) * LDE + 16 * tj + li] = tile[q][t];
         }
         __syncthreads();
-        T* El = E + (int64_t)l * BP * BP;
+        T* El = E + (int64_t)ln * BP * BP;
         for (int o = tid; o < BP * BP; o += kFactorThreads) {
             const int kk = o % NKS, t = o / NKS;
-            const int ln = t & 63, rt = t >> 6;
-            El[o] = Es[(16 * rt + (ln & 15)) * LDE + 4 * kk + (ln >> 4)];
+            const int lnn = t & 63, rt = t >> 6;
+            El[o] = Es[(16 * rt + (lnn & 15)) * LDE + 4 * kk + (lnn >> 4)];
         }
-        // cell row l + 2 replaces row l; prefetch row l + 3
-        if (KIND == kElliptic && tid < L && l + 2 <= nl) {
-            crow[(l & 1) * (kMaxLine + 1) + tid] = rnext;
-            if (l + 3 <= nl) rnext = aL[(l + 3) * L + tid];
+        // the next line needs one new cell row: ln + 2 (top, replacing row ln)
+        // or ln - 1 (bottom, replacing row ln + 1); prefetch the one after
+        if (KIND == kElliptic && !MID && tid < L && l + 1 < nsteps) {
+            const int rnew = dir > 0 ? ln + 2 : ln - 1;
+            crow[(rnew & 1) * (kMaxLine + 1) + tid] = rnext;
+            const int rfut = dir > 0 ? ln + 3 : ln - 2;
+            if (l + 2 < nsteps) rnext = aL[rfut * L + tid];
         }
     }
     if (bad) raise_flag(flags, 0);
 }
 
 // One kernel per line-tile count R (each with its own register allocation);
-// plist lists the patches of this R (workgroup x -> patch plist[x]).
-template <typename T, int KIND, int R>
+// plist lists the patches of this R (workgroup x -> patch plist[x]).  The
+// halves kernel has grid (patches, 2): y = 0 top, y = 1 bottom; the middle
+// kernel one workgroup per patch, after it.
+template <typename T, int KIND, int R, bool MID>
 __global__ __launch_bounds__(kFactorThreads) void factor_kernel(const PatchDesc* pd, const int32_t* __restrict__ plist,
                                                                 const double* __restrict__ aL_all, const double* __restrict__ vw,
                                                                 double dx, double inv_eps, T* __restrict__ E_all, int32_t* flags) {
-    // E_{l-1} (BP x (BP+1)) and, aliased, the panel buffers (6 x 16 BP + 512)
+    // E (BP x (BP+1)) and, aliased, the panel buffers (6 x 16 BP + 512)
     constexpr int BPR = 16 * R;
     constexpr int LDS_ELEMS = BPR * (BPR + 1) > 96 * BPR + 512 ? BPR * (BPR + 1) : 96 * BPR + 512;
     __shared__ T lds[LDS_ELEMS];
@@ -647,15 +583,30 @@ __global__ __launch_bounds__(kFactorThreads) void factor_kernel(const PatchDesc*
         if (threadIdx.x == 0) raise_flag(flags, 3);
         return;
     }
-    factor_mfma_body<T, KIND, R>(P, aL_all + P.a_off, vw, dx, inv_eps, E_all + P.E_off, lds, cf, crow, flags);
+    const int dir = MID ? 0 : (blockIdx.y == 0 ? 1 : -1);
+    factor_mfma_body<T, KIND, R, MID>(P, aL_all + P.a_off, vw, dx, inv_eps, E_all + P.E_off, lds, cf, crow, dir, flags);
 }
 
 // ------------------------------------------------------------ sweeps (a5)
-// grid (patch, column chunk of sc samples).  Both sweeps of one chunk run in
-// one workgroup; the products E_l y run on MFMA 16x16x4 (4 waves: wave w owns
-// row tiles w and w+4 and all column tiles of the chunk).
+// Twisted block sweeps, matching the twisted elimination (m = nl/2; E_l is
+// the inverse of the top recursion for l < m, of the bottom recursion for
+// l > m, of the two-sided Schur complement at m):
+//   forward halves (one kernel, grid (patch, chunk, half)):
+//     top     y_0 = r_0,        y_{l+1} = r_{l+1} - Low_{l+1} E_l y_l,  l < m-1;
+//             t_top = r_m - Low_m E_{m-1} y_{m-1}
+//     bottom  y_{nl-1} = r_{nl-1}, y_{l-1} = r_{l-1} - Up_{l-1} E_l y_l, l > m+1;
+//             t_bot = Up_m E_{m+1} y_{m+1}
+//   middle and back halves (second kernel, same grid):
+//     x_m = E_m (t_top - t_bot) (both halves form it; the top stores it, and
+//     nothing of the second kernel reads line m of X)
+//     top     x_l = E_l (y_l - Up_l x_{l+1}),   l = m-1 .. 0
+//     bottom  x_l = E_l (y_l - Low_l x_{l-1}),  l = m+1 .. nl-1
+// The y_l overwrite the right-hand sides in place and the x_l the y_l; t_top
+// and t_bot go through a small per-patch buffer, so no workgroup ever waits
+// for another.  The products E_l y run on MFMA 16x16x4 (8 waves: wave w owns
+// row tile w of E_l and all column tiles of the chunk).
 //
-// Software pipeline: the A operands of E_{l+1} are loaded into registers
+// Software pipeline: the A operands of the next E_l are loaded into registers
 // while line l is processed, and the right-hand side and coupling loads of a
 // line are issued before them, so that the in-order load counter never makes
 // the stencil wait for the prefetch.
@@ -665,11 +616,12 @@ template <typename T> struct Vec16;
 template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
 template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
 
-// One patch x column chunk, with compile-time line tiles R (bp = 16 R) and
-// column tiles NCT (16 NCT samples), so the MFMA loop is straight-line code.
-template <typename T, int KIND, int R, int NCT>
+// One patch x column chunk x half, with compile-time line tiles R (bp = 16 R)
+// and column tiles NCT (16 NCT samples), so the MFMA loop is straight-line
+// code.  TW: this chunk's [2][bp x sp] middle-line couplings (row stride sp).
+template <typename T, int KIND, int R, int NCT, int PHASE>
 __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw, double dx,
-                           const T* __restrict__ E, T* __restrict__ X, double* __restrict__ X64, T* ybuf, T* wbuf,
+                           const T* __restrict__ E, T* __restrict__ X, T* __restrict__ TW, int half, T* ybuf, T* wbuf,
                            double* craw, double* cvp, double* cvm) {
     typedef typename Vec16<T>::type V;
     constexpr int VN = Vec16<T>::n;
@@ -677,15 +629,17 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
     constexpr int DI = kSweepThreads / NSC;          // rows between a thread's elements
     constexpr int RPT = (BP + DI - 1) / DI;          // elements per thread
     const int tid = threadIdx.x, lane = tid & 63, rt = tid >> 6;
-    const int li = lane & 15, lk = lane >> 4;
     const bool mf = rt < R;                          // this wave owns a row tile
     const int b = P.b, nl = P.nl, sp = P.sp, L = P.L;
     const int lstride = BP * sp;
+    const int m = nl / 2;
+    const int dir = half == 0 ? 1 : -1;
     typename Mfma<T>::acc acc[NCT];
     T aC[NKS];
     T rv[RPT];
     double crow = 0.0;
     const int i0 = tid / NSC, jj = tid % NSC;
+    T* TWh = TW + (int64_t)half * lstride;
 
     if (KIND == kKinetic) {
         for (int a = tid; a < b; a += kSweepThreads) {
@@ -721,38 +675,39 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         }
     };
     auto mfma = [&]() {
+        const int lli = llane & 15, llk = llane >> 4;
 #pragma unroll
         for (int c = 0; c < NCT; ++c) acc[c] = Mfma<T>::zero();
         if (mf) {
 #pragma unroll
             for (int kk = 0; kk < NKS; ++kk) {
-                const T* yb = ybuf + (4 * kk + lk) * NSC + li;
+                const T* yb = ybuf + (4 * kk + llk) * NSC + lli;
 #pragma unroll
                 for (int c = 0; c < NCT; ++c) acc[c] = Mfma<T>::step(aC[kk], yb[16 * c], acc[c]);
             }
         }
     };
-    // accumulators -> wbuf, and for a solution line (gdst) to global; with X64
-    // the correction is also added to the FP64 iterate (refinement)
-    auto store_acc = [&](T* gdst, double* g64) {
+    // accumulators -> wbuf, and for a solution line (gdst) to global
+    auto store_acc = [&](T* gdst) {
+        const int lli = llane & 15;
         if (mf) {
 #pragma unroll
             for (int c = 0; c < NCT; ++c)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const int i = 16 * rt + Mfma<T>::row(lane, t), j = 16 * c + li;
+                    const int i = 16 * rt + Mfma<T>::row(llane, t), j = 16 * c + lli;
                     const T v = acc[c][t];
                     wbuf[i * NSC + j] = v;
                     if (gdst) gdst[(uint32_t)(i * sp + j)] = v;
-                    if (g64) g64[(uint32_t)(i * sp + j)] += (double)v;
                 }
         }
     };
-    // coupling of row i (Low_{l+1} if low, else Up_l) applied to column j of src
+    // coupling block between two adjacent lines applied to column j of src,
+    // row i: Low (A_{l+1,l}) if low, else Up (A_{l,l+1}).  Elliptic: the
+    // symmetric tridiagonal block of their shared cell row (craw): diagonal
+    // -(c_i + c_{i+1})/6, off-diagonal (i, i+1) -c_{i+1}/3
     auto couple = [&](const T* src, int i, int j, bool low) -> double {
         if (KIND == kElliptic) {
-            // U_l symmetric tridiagonal from cell row l+1 (craw): diagonal
-            // -(c_i + c_{i+1})/6, off-diagonal (i, i+1) -c_{i+1}/3
             const int im = i > 0 ? i - 1 : 0, ip = i + 1 < BP ? i + 1 : BP - 1;
             const double cm = i > 0 ? -craw[i] / 3.0 : 0.0;
             const double cp = i < b - 1 ? -craw[i + 1] / 3.0 : 0.0;
@@ -763,76 +718,104 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         }
     };
 
-    // y_0 = r_0
-    launder();
-    load_line(X);
-#pragma unroll
-    for (int e = 0; e < RPT; ++e) {
-        const int i = li0 + e * DI;
-        if (BP % DI == 0 || i < BP) ybuf[i * NSC + ljj] = rv[e];
-    }
-    load_A(E);
-    lds_barrier();
-    // ---- forward sweep
-    for (int l = 0; l < nl; ++l) {
+    if constexpr (PHASE == 0) {
+        // ---- forward half: lines ln0, ln0 + dir, ...; the last one couples into m
+        const int nst = half == 0 ? m : nl - 1 - m;
+        const int ln0 = half == 0 ? 0 : nl - 1;
+        const bool low = half == 0;   // top: Low_{l+1} (line below from above); bottom: Up_{l-1}
         launder();
-        const bool more = l + 1 < nl;
-        if (more) {
-            load_line(X + (l + 1) * lstride);                                      // r_{l+1}
-            if (KIND == kElliptic && tid <= b) crow = aL[(l + 1) * L + tid];     // U_l: cell row l+1
-        }
-        mfma();
-        if (!more) {
-            store_acc(X + l * lstride, X64 ? X64 + l * lstride : nullptr);   // x_{nl-1}
-            lds_barrier();
-            break;
-        }
-        load_A(E + (int64_t)(l + 1) * BP * BP);                                   // E_{l+1}
-        store_acc(nullptr, nullptr);
-        if (KIND == kElliptic && tid <= b) craw[tid] = crow;
-        lds_barrier();
-        T* Xn = X + (l + 1) * lstride;
+        if (nst <= 0) {
+            // no line in this half: t_top = r_m, t_bot = 0
+            if (half == 0) load_line(X + m * lstride);
 #pragma unroll
-        for (int e = 0; e < RPT; ++e) {
-            const int i = li0 + e * DI;
-            if (BP % DI == 0 || i < BP) {
-                const double v = (double)rv[e] - couple(wbuf, i, ljj, true);
-                const T y = i < b ? (T)v : T(0);
-                Xn[(uint32_t)(i * sp + ljj)] = y;
-                ybuf[i * NSC + ljj] = y;
+            for (int e = 0; e < RPT; ++e) {
+                const int i = li0 + e * DI;
+                if (BP % DI == 0 || i < BP) TWh[(uint32_t)(i * sp + ljj)] = (half == 0 && i < b) ? rv[e] : T(0);
             }
+            return;
         }
+        load_line(X + ln0 * lstride);                 // y_{ln0} = r_{ln0}
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) {
+            const int i = li0 + e * DI;
+            if (BP % DI == 0 || i < BP) ybuf[i * NSC + ljj] = rv[e];
+        }
+        load_A(E + (int64_t)ln0 * BP * BP);
         lds_barrier();
-    }
-    // ---- back sweep: wbuf holds x_{l+1}
-    for (int l = nl - 2; l >= 0; --l) {
+        for (int k = 0; k < nst; ++k) {
+            launder();
+            const int ln = ln0 + dir * k, nx = ln + dir;    // nx: next line (m after the last step)
+            const bool more = k + 1 < nst;
+            const bool sub = more || half == 0;      // the top's last step carries r_m into t_top
+            if (sub) load_line(X + nx * lstride);                                    // r_{nx}
+            if (KIND == kElliptic && tid <= b) crow = aL[(ln > nx ? ln : nx) * L + tid];   // shared cell row
+            mfma();                                                                   // w = E_ln y_ln
+            if (more) load_A(E + (int64_t)nx * BP * BP);
+            store_acc(nullptr);
+            if (KIND == kElliptic && tid <= b) craw[tid] = crow;
+            lds_barrier();
+            T* dst = more ? X + nx * lstride : TWh;
+#pragma unroll
+            for (int e = 0; e < RPT; ++e) {
+                const int i = li0 + e * DI;
+                if (BP % DI == 0 || i < BP) {
+                    const double cw = couple(wbuf, i, ljj, low);
+                    const double v = sub ? (double)rv[e] - cw : cw;
+                    const T y = i < b ? (T)v : T(0);
+                    dst[(uint32_t)(i * sp + ljj)] = y;
+                    if (more) ybuf[i * NSC + ljj] = y;
+                }
+            }
+            lds_barrier();
+        }
+    } else {
+        // ---- middle line, then the back half
         launder();
-        load_line(X + l * lstride);                                                // y_l
-        if (KIND == kElliptic && tid <= b) crow = aL[(l + 1) * L + tid];         // U_l: cell row l+1
-        load_A(E + (int64_t)l * BP * BP);                                          // E_l
-        if (KIND == kElliptic && tid <= b) craw[tid] = crow;
-        lds_barrier();
+        load_A(E + (int64_t)m * BP * BP);
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
             const int i = li0 + e * DI;
             if (BP % DI == 0 || i < BP) {
-                const double v = (double)rv[e] - couple(wbuf, i, ljj, false);
+                const double v = (double)TW[(uint32_t)(i * sp + ljj)] - (double)TW[lstride + (uint32_t)(i * sp + ljj)];
                 ybuf[i * NSC + ljj] = i < b ? (T)v : T(0);
             }
         }
         lds_barrier();
         mfma();
-        store_acc(X + l * lstride, X64 ? X64 + l * lstride : nullptr);
+        store_acc(half == 0 ? X + m * lstride : nullptr);   // x_m (identical in both halves)
         lds_barrier();
+        const int nst = half == 0 ? m : nl - 1 - m;
+        const bool low = half != 0;   // top: Up_l x_{l+1}; bottom: Low_l x_{l-1}
+        for (int k = 0; k < nst; ++k) {
+            launder();
+            const int ln = m - dir * (k + 1), pv = ln + dir;    // pv: the line solved before
+            load_line(X + ln * lstride);                                               // y_ln
+            if (KIND == kElliptic && tid <= b) crow = aL[(ln > pv ? ln : pv) * L + tid];   // shared cell row
+            load_A(E + (int64_t)ln * BP * BP);
+            if (KIND == kElliptic && tid <= b) craw[tid] = crow;
+            lds_barrier();
+#pragma unroll
+            for (int e = 0; e < RPT; ++e) {
+                const int i = li0 + e * DI;
+                if (BP % DI == 0 || i < BP) {
+                    const double v = (double)rv[e] - couple(wbuf, i, ljj, low);
+                    ybuf[i * NSC + ljj] = i < b ? (T)v : T(0);
+                }
+            }
+            lds_barrier();
+            mfma();
+            store_acc(X + ln * lstride);
+            lds_barrier();
+        }
     }
 }
 
-// grid (patch, column chunk of 16*NCT samples); sp of every patch is a
-// multiple of the chunk.  Both sweeps of one chunk run in one workgroup.
-template <typename T, int KIND, int NCT>
+// grid (patch, column chunk of 16*NCT samples, half); sp of every patch is a
+// multiple of the chunk.
+template <typename T, int KIND, int NCT, int PHASE>
 __global__ __launch_bounds__(kSweepThreads) void sweep_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
                                                               const double* __restrict__ vw, double dx, const T* __restrict__ E_all,
-                                                              T* __restrict__ X_all, double* __restrict__ X64_all,
+                                                              T* __restrict__ X_all, T* __restrict__ TW_all,
                                                               const int32_t* __restrict__ conv, int32_t* flags) {
     __shared__ T ybuf[kMaxLine * 16 * NCT];
     __shared__ T wbuf[kMaxLine * 16 * NCT];
@@ -843,29 +826,32 @@ __global__ __launch_bounds__(kSweepThreads) void sweep_kernel(const PatchDesc* p
     const PatchDesc P = pd[p];
     const int s0 = blockIdx.y * 16 * NCT;
     if (s0 >= P.sp) return;
+    const int half = blockIdx.z;
     const double* aL = aL_all + P.a_off;
     const T* E = E_all + P.E_off;
     T* X = X_all + P.x_off + s0;
-    double* X64 = X64_all ? X64_all + P.x_off + s0 : nullptr;
+    T* TW = TW_all + P.tw_off + s0;
+#define MSRS_SWB(RR) sweep_body<T, KIND, RR, NCT, PHASE>(P, aL, vw, dx, E, X, TW, half, ybuf, wbuf, craw, cvp, cvm)
     if (KIND == kKinetic) {
         switch (P.bp >> 4) {
-            case 1: sweep_body<T, KIND, 1, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
-            case 2: sweep_body<T, KIND, 2, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
+            case 1: MSRS_SWB(1); break;
+            case 2: MSRS_SWB(2); break;
             default: if (threadIdx.x == 0) raise_flag(flags, 3); break;
         }
         return;
     }
     switch (P.bp >> 4) {
-        case 1: sweep_body<T, KIND, 1, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
-        case 2: sweep_body<T, KIND, 2, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
-        case 3: sweep_body<T, KIND, 3, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
-        case 4: sweep_body<T, KIND, 4, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
-        case 5: sweep_body<T, KIND, 5, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
-        case 6: sweep_body<T, KIND, 6, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
-        case 7: sweep_body<T, KIND, 7, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
-        case 8: sweep_body<T, KIND, 8, NCT>(P, aL, vw, dx, E, X, X64, ybuf, wbuf, craw, cvp, cvm); break;
+        case 1: MSRS_SWB(1); break;
+        case 2: MSRS_SWB(2); break;
+        case 3: MSRS_SWB(3); break;
+        case 4: MSRS_SWB(4); break;
+        case 5: MSRS_SWB(5); break;
+        case 6: MSRS_SWB(6); break;
+        case 7: MSRS_SWB(7); break;
+        case 8: MSRS_SWB(8); break;
         default: if (threadIdx.x == 0) raise_flag(flags, 3); break;
     }
+#undef MSRS_SWB
 }
 
 // ------------------------------------------------------------ FP64 residual (a6)
@@ -1078,9 +1064,15 @@ void launch_lift(Ctx& c, int p0, int p1) {
 template <typename T, int KIND>
 static void launch_factor_r(Ctx& c, int R, hipStream_t st, const int32_t* plist, int n) {
     const double inv_eps = 1.0 / c.eps;
-    const dim3 grid(n), blk(kFactorThreads);
     T* E = (T*)c.E;
-#define MSRS_FACTOR(RR) hipLaunchKernelGGL((factor_kernel<T, KIND, RR>), grid, blk, 0, st, c.dp, plist, c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags)
+    // both halves at once, then the middle lines
+#define MSRS_FACTOR(RR)                                                                                                          \
+    do {                                                                                                                        \
+        hipLaunchKernelGGL((factor_kernel<T, KIND, RR, false>), dim3(n, 2), dim3(kFactorThreads), 0, st, c.dp, plist, c.aL, c.vw, \
+                           dx_of(c), inv_eps, E, c.dflags);                                                                     \
+        hipLaunchKernelGGL((factor_kernel<T, KIND, RR, true>), dim3(n), dim3(kFactorThreads), 0, st, c.dp, plist, c.aL, c.vw,     \
+                           dx_of(c), inv_eps, E, c.dflags);                                                                     \
+    } while (0)
     switch (R) {
         case 1: MSRS_FACTOR(1); break;
         case 2: MSRS_FACTOR(2); break;
@@ -1153,11 +1145,16 @@ void launch_sweep(Ctx& c, int p0, int p1, bool fp32) {
     int maxsp = 0;
     for (int p = p0; p < p1; ++p) maxsp = std::max(maxsp, c.hp[p].sp);
     const int sc = sweep_chunk(c, p0, p1, fp32);
-    const dim3 grid(p1 - p0, maxsp / sc), blk(kSweepThreads);
+    const dim3 grid(p1 - p0, maxsp / sc, 2), blk(kSweepThreads);
     const int32_t* conv = fp32 ? c.conv : nullptr;
     const double dx = dx_of(c);
-    double* x64acc = nullptr;   // the refinement update runs in accum_kernel
-#define MSRS_SWEEP(TT, KK, NN, XX) hipLaunchKernelGGL((sweep_kernel<TT, KK, NN>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, x64acc, conv, c.dflags)
+#define MSRS_SWEEP(TT, KK, NN, XX)                                                                                             \
+    do {                                                                                                                      \
+        hipLaunchKernelGGL((sweep_kernel<TT, KK, NN, 0>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, \
+                           (TT*)c.tw, conv, c.dflags);                                                                         \
+        hipLaunchKernelGGL((sweep_kernel<TT, KK, NN, 1>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, \
+                           (TT*)c.tw, conv, c.dflags);                                                                         \
+    } while (0)
     if (c.kind == kElliptic) {
         if (fp32) {
             if (sc == 64) MSRS_SWEEP(float, kElliptic, 4, c.x32);

@@ -55,6 +55,7 @@ struct PatchDesc {
     int64_t Q_off;            // nrows x ncols column-major
     int64_t sv_off;           // s singular values
     int64_t rn_off;           // per-sample norms: [0,sp) ||rhs||^2, [sp,2sp) ||r||^2
+    int64_t tw_off;           // sweeps: the two halves' couplings into the middle line, 2 x bp x sp
 };
 
 // Online (coarse) geometry of one patch.
@@ -95,6 +96,8 @@ struct Ctx {
     double* x64 = nullptr;        // FP64 line vectors (solution)
     float* x32 = nullptr;         // FP32 line vectors (FP32_IR: residual / correction)
     void* E = nullptr;            // inverse blocks (float or double)
+    void* tw = nullptr;           // middle-line couplings of the twisted sweeps (float or double)
+    int64_t tw_total = 0;
     double* Y = nullptr;
     double* Q = nullptr;
     double* sv = nullptr;
