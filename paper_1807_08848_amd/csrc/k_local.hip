@@ -207,7 +207,8 @@ __device__ __forceinline__ double diag_entry(const PatchDesc& P, const double* a
 // (new column panel) and the rank-16 update A_{i,j} -= A_{i,p} X_j run on MFMA.
 constexpr int kFactorThreads = 512;
 
-// Inverse of a 16 x 16 block (row-major in LDS, ld 16) by one wave: lane l
+// Inverse of a 16 x 16 block (row-major in LDS, leading dimension LDA; the
+// inverse with LDD) by one wave: lane l
 // holds row l%16, columns 4(l/16)..4(l/16)+3; Gauss-Jordan without pivoting.
 // FP32 pivot step K: the pivot row reaches every lane of a 16-lane row by a
 // DPP row broadcast, the pivot itself by readlane, and its reciprocal is the
@@ -231,12 +232,12 @@ __device__ __forceinline__ void inv16_pivot_f32(float (&a)[4], int r, int cg, bo
     if constexpr (K + 1 < 16) inv16_pivot_f32<K + 1>(a, r, cg, bad);
 }
 
-template <typename T>
+template <typename T, int LDA, int LDD>
 __device__ __forceinline__ void inv16_wave(const T* A, T* Dinv, bool& bad) {
     const int l = threadIdx.x & 63, r = l & 15, cg = l >> 4;
     T a[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = A[r * 16 + 4 * cg + u];
+    for (int u = 0; u < 4; ++u) a[u] = A[r * LDA + 4 * cg + u];
     if constexpr (sizeof(T) == 4) {
         inv16_pivot_f32<0>(a, r, cg, bad);
     } else {
@@ -259,7 +260,7 @@ __device__ __forceinline__ void inv16_wave(const T* A, T* Dinv, bool& bad) {
         }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) Dinv[r * 16 + 4 * cg + u] = a[u];
+    for (int u = 0; u < 4; ++u) Dinv[r * LDD + 4 * cg + u] = a[u];
 }
 
 // The block-tridiagonal elimination runs from both ends ("twisted"): the
@@ -298,11 +299,14 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
     const int line0 = MID ? m : (dir > 0 ? 0 : nl - 1);
     if (nsteps <= 0) return;   // uniform over the workgroup
     T* Es = lds;                         // E of the previously eliminated line, BP x LDE (row-major)
-    // panel buffers alias Es (free once D_l is formed)
-    T* Pc = lds;                         // [2][BP x 16]  column panel (row i, panel column k)
-    T* Pr = lds + 2 * BP * 16;           // [2][16 x BP]  row panel
-    T* Xs = lds + 4 * BP * 16;           // [2][16 x BP]  new row panel
-    T* Dv = lds + 6 * BP * 16;           // [2][16 x 16]  inverse of the diagonal block
+    // panel buffers alias Es (free once D_l is formed); odd leading dimensions
+    // spread the MFMA operand reads (16 rows x 4 k, or 4 rows x 16 columns)
+    // over distinct LDS banks
+    constexpr int PCL = 17, PRL = BP + 1, DVL = 17;
+    T* Pc = lds;                                   // [2][BP x PCL]  column panel (row i, panel column k)
+    T* Pr = lds + 2 * BP * PCL;                    // [2][16 x PRL]  row panel
+    T* Xs = Pr + 2 * 16 * PRL;                     // [2][16 x PRL]  new row panel
+    T* Dv = Xs + 2 * 16 * PRL;                     // [2][16 x DVL]  inverse of the diagonal block
     Acc tile[NSLOT];
     bool bad = false;
     const int npan = (b + 15) / 16;
@@ -461,10 +465,10 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
         for (int pn = 0; pn < npan; ++pn) {
             launder();
             const int buf = pn & 1;
-            T* pc = Pc + buf * BP * 16;
-            T* pr = Pr + buf * 16 * BP;
-            T* xs = Xs + buf * 16 * BP;
-            T* dv = Dv + buf * 256;
+            T* pc = Pc + buf * BP * PCL;
+            T* pr = Pr + buf * 16 * PRL;
+            T* xs = Xs + buf * 16 * PRL;
+            T* dv = Dv + buf * 16 * DVL;
             // B1: publish the panel column and row
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
@@ -475,13 +479,13 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int ii = Mfma<T>::row(lane, t);
-                    if (tj == pn) pc[(16 * ti + ii) * 16 + li] = tile[q][t];
-                    if (ti == pn) pr[ii * BP + 16 * tj + li] = tile[q][t];
+                    if (tj == pn) pc[(16 * ti + ii) * PCL + li] = tile[q][t];
+                    if (ti == pn) pr[ii * PRL + 16 * tj + li] = tile[q][t];
                 }
             }
             __syncthreads();
             // B2: inverse of the diagonal block (wave 0)
-            if (w == 0) inv16_wave<T>(pc + 16 * pn * 16, dv, bad);
+            if (w == 0) inv16_wave<T, PCL, DVL>(pc + 16 * pn * PCL, dv, bad);
             __syncthreads();
             // B3a: new row panel X_j = Dinv A_{p,j} (owners of row-panel tiles)
 #pragma unroll
@@ -494,11 +498,11 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
 #pragma unroll
                 for (int st = 0; st < 4; ++st) {
                     const int k = 4 * st + lk;
-                    x = Mfma<T>::step(dv[li * 16 + k], pr[k * BP + 16 * tj + li], x);
+                    x = Mfma<T>::step(dv[li * DVL + k], pr[k * PRL + 16 * tj + li], x);
                 }
                 tile[q] = x;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) xs[Mfma<T>::row(lane, t) * BP + 16 * tj + li] = x[t];
+                for (int t = 0; t < 4; ++t) xs[Mfma<T>::row(lane, t) * PRL + 16 * tj + li] = x[t];
             }
             __syncthreads();
             // B3b: column panel and rank-16 update of the rest; diagonal tile = Dinv
@@ -510,7 +514,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
                 if (ti == pn) {
                     if (tj == pn) {
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) tile[q][t] = dv[Mfma<T>::row(lane, t) * 16 + li];
+                        for (int t = 0; t < 4; ++t) tile[q][t] = dv[Mfma<T>::row(lane, t) * DVL + li];
                     }
                     continue;
                 }
@@ -519,7 +523,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
 #pragma unroll
                     for (int st = 0; st < 4; ++st) {
                         const int k = 4 * st + lk;
-                        x = Mfma<T>::step(-pc[(16 * ti + li) * 16 + k], dv[k * 16 + li], x);
+                        x = Mfma<T>::step(-pc[(16 * ti + li) * PCL + k], dv[k * DVL + li], x);
                     }
                     tile[q] = x;
                 } else {
@@ -527,7 +531,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
 #pragma unroll
                     for (int st = 0; st < 4; ++st) {
                         const int k = 4 * st + lk;
-                        x = Mfma<T>::step(-pc[(16 * ti + li) * 16 + k], xs[k * BP + 16 * tj + li], x);
+                        x = Mfma<T>::step(-pc[(16 * ti + li) * PCL + k], xs[k * PRL + 16 * tj + li], x);
                     }
                     tile[q] = x;
                 }
@@ -572,9 +576,10 @@ template <typename T, int KIND, int R, bool MID>
 __global__ __launch_bounds__(kFactorThreads) void factor_kernel(const PatchDesc* pd, const int32_t* __restrict__ plist,
                                                                 const double* __restrict__ aL_all, const double* __restrict__ vw,
                                                                 double dx, double inv_eps, T* __restrict__ E_all, int32_t* flags) {
-    // E (BP x (BP+1)) and, aliased, the panel buffers (6 x 16 BP + 512)
+    // E (BP x (BP+1)) and, aliased, the panel buffers (2 BP x 17 + 4 x 16 (BP+1) + 2 x 16 x 17)
     constexpr int BPR = 16 * R;
-    constexpr int LDS_ELEMS = BPR * (BPR + 1) > 96 * BPR + 512 ? BPR * (BPR + 1) : 96 * BPR + 512;
+    constexpr int PANEL = 2 * BPR * 17 + 4 * 16 * (BPR + 1) + 2 * 16 * 17;
+    constexpr int LDS_ELEMS = BPR * (BPR + 1) > PANEL ? BPR * (BPR + 1) : PANEL;
     __shared__ T lds[LDS_ELEMS];
     __shared__ double cf[2 * kMaxLine];
     __shared__ double crow[2 * (kMaxLine + 1)];

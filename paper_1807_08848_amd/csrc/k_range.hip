@@ -90,13 +90,13 @@ __global__ __launch_bounds__(kThreads) void gram_partial_kernel(const PatchDesc*
     else gram_rows<4>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
 }
 
-// sum of the chunk partials of patch p into G (LDS, ld kRfMax), fixed order
-__device__ void sum_partials(const double* __restrict__ part, int p, int maxrc, int nch, int n, double* G) {
+// sum of the chunk partials of patch p into G (LDS, leading dimension ld), fixed order
+__device__ void sum_partials(const double* __restrict__ part, int p, int maxrc, int nch, int n, double* G, int ld = kRfMax) {
     for (int o = threadIdx.x; o < n * n; o += kThreads) {
         const int i = o / n, j = o % n;
         double s = 0.0;
         for (int ch = 0; ch < nch; ++ch) s += part[((int64_t)p * maxrc + ch) * kSmall + i * kRfMax + j];
-        G[i * kRfMax + j] = s;
+        G[i * ld + j] = s;
     }
     __syncthreads();
 }
@@ -108,9 +108,12 @@ __device__ void sum_partials(const double* __restrict__ part, int p, int maxrc, 
 __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int p0, const double* __restrict__ part, int maxrc,
                                                        double* __restrict__ small, double* __restrict__ sv_all,
                                                        double* __restrict__ gap, int32_t* flags) {
-    __shared__ double G[kSmall];
-    __shared__ double V[kSmall];
-    __shared__ double cs[kRfMax / 2], sn[kRfMax / 2];
+    // G and V with an odd leading dimension: a wave's column accesses
+    // (V[j][a] over rows j) fall on distinct LDS banks
+    constexpr int LDG = kRfMax + 1;
+    __shared__ double G[kRfMax * LDG];
+    __shared__ double V[kRfMax * LDG];
+    __shared__ double cs[kRfMax / 2], sn[kRfMax / 2], tn[kRfMax / 2];
     __shared__ int pu[kRfMax / 2], pv[kRfMax / 2];
     __shared__ int perm[kRfMax];
     __shared__ double lam[kRfMax];
@@ -120,15 +123,21 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
     const int tid = threadIdx.x;
     const int s = P.s, k = P.ncols;
     const int nch = (P.nrows + kRowChunk - 1) / kRowChunk;
-    for (int o = tid; o < kSmall; o += kThreads) {
+    for (int o = tid; o < kRfMax * LDG; o += kThreads) {
         G[o] = 0.0;
-        V[o] = (o / kRfMax == o % kRfMax) ? 1.0 : 0.0;
+        V[o] = (o / LDG == o % LDG) ? 1.0 : 0.0;
     }
     __syncthreads();
-    sum_partials(part, p, maxrc, nch, s, G);
+    sum_partials(part, p, maxrc, nch, s, G, LDG);
     const int n = s + (s & 1), np2 = n / 2, nm1 = n - 1;
     // Sweeps until every rotation of a sweep finds |g_pq| <= 1e-15 sqrt(g_pp g_qq)
-    // (relative off-diagonal criterion), at most 30.
+    // (relative off-diagonal criterion) or |g_pq| <= 1e-16 trace(G) (the level of
+    // the rounding in forming G = Y^T Y, below which the relative test cannot be
+    // met between widely separated eigenvalues), at most 30.  The trace is
+    // invariant under the rotations.
+    double gtr = 0.0;
+    for (int i = 0; i < s; ++i) gtr += G[i * LDG + i];
+    const double floor_abs = 1e-16 * gtr;
     if (tid == 0) rot = 0;
     __syncthreads();
     for (int sweep = 0; sweep < 30; ++sweep) {
@@ -142,16 +151,17 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
                 pu[i] = a;
                 pv[i] = b;
                 double c = 1.0, t = 0.0;
-                const double apq = G[a * kRfMax + b];
+                const double apq = G[a * LDG + b];
                 if (b < s && apq != 0.0) {
-                    const double app = G[a * kRfMax + a], aqq = G[b * kRfMax + b];
-                    if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) rot = 1;
+                    const double app = G[a * LDG + a], aqq = G[b * LDG + b];
+                    if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) rot = 1;
                     const double tau = (aqq - app) / (2.0 * apq);
                     t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                     c = 1.0 / sqrt(1.0 + t * t);
                 }
                 cs[i] = c;
                 sn[i] = t * c;
+                tn[i] = t;
             }
             __syncthreads();
             // G <- J^T G J on 2x2 blocks (rows by pair i, columns by pair i2): thread
@@ -161,14 +171,25 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
                 if (i2 >= np2) continue;
                 const int a = pu[i], b = pv[i], a2 = pu[i2], b2 = pv[i2];
                 const double c = cs[i], sv = sn[i], c2 = cs[i2], s2 = sn[i2];
-                const double g00 = G[a * kRfMax + a2], g01 = G[a * kRfMax + b2];
-                const double g10 = G[b * kRfMax + a2], g11 = G[b * kRfMax + b2];
+                const double g00 = G[a * LDG + a2], g01 = G[a * LDG + b2];
+                const double g10 = G[b * LDG + a2], g11 = G[b * LDG + b2];
+                if (i == i2) {
+                    // the rotated pair's own block: diagonal by the tangent update,
+                    // the annihilated entry exactly zero (no rounding residue left
+                    // to stall the relative test on widely separated eigenvalues)
+                    const double t = tn[i];
+                    G[a * LDG + a] = g00 - t * g01;
+                    G[b * LDG + b] = g11 + t * g01;
+                    G[a * LDG + b] = 0.0;
+                    G[b * LDG + a] = 0.0;
+                    continue;
+                }
                 const double r00 = c * g00 - sv * g10, r01 = c * g01 - sv * g11;
                 const double r10 = sv * g00 + c * g10, r11 = sv * g01 + c * g11;
-                G[a * kRfMax + a2] = c2 * r00 - s2 * r01;
-                G[a * kRfMax + b2] = s2 * r00 + c2 * r01;
-                G[b * kRfMax + a2] = c2 * r10 - s2 * r11;
-                G[b * kRfMax + b2] = s2 * r10 + c2 * r11;
+                G[a * LDG + a2] = c2 * r00 - s2 * r01;
+                G[a * LDG + b2] = s2 * r00 + c2 * r01;
+                G[b * LDG + a2] = c2 * r10 - s2 * r11;
+                G[b * LDG + b2] = s2 * r10 + c2 * r11;
             }
             // V <- V J: thread (row j = tid % 64, pairs i = tid / 64 + 4 r)
             for (int i = tid >> 6; i < np2; i += kThreads / 64) {
@@ -176,9 +197,9 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
                 if (j >= n) continue;
                 const int a = pu[i], b = pv[i];
                 const double c = cs[i], sv = sn[i];
-                const double va = V[j * kRfMax + a], vb = V[j * kRfMax + b];
-                V[j * kRfMax + a] = c * va - sv * vb;
-                V[j * kRfMax + b] = sv * va + c * vb;
+                const double va = V[j * LDG + a], vb = V[j * LDG + b];
+                V[j * LDG + a] = c * va - sv * vb;
+                V[j * LDG + b] = sv * va + c * vb;
             }
             __syncthreads();
         }
@@ -190,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
         if (!r) break;
     }
     if (tid == 0) {
-        for (int i = 0; i < s; ++i) { perm[i] = i; lam[i] = G[i * kRfMax + i]; }
+        for (int i = 0; i < s; ++i) { perm[i] = i; lam[i] = G[i * LDG + i]; }
         for (int i = 0; i < s; ++i) {
             int best = i;
             for (int j = i + 1; j < s; ++j)
@@ -210,7 +231,7 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
         double v = 0.0;
         if (i < s && j < k) {
             const double sg = sqrt(fmax(lam[perm[j]], 0.0));
-            v = sg > 0 ? V[i * kRfMax + perm[j]] / sg : 0.0;
+            v = sg > 0 ? V[i * LDG + perm[j]] / sg : 0.0;
         }
         B[o] = v;
     }
