@@ -288,7 +288,8 @@ msrs_status msrs_set_max_batch(msrs_handle h, int32_t max_batch);
 /*
  * Launch-shape parameters (results do not depend on them beyond rounding
  * order; the batched online results of one request are the same for every
- * value).  Set any time; they apply to later calls.  Errors: ARG (unknown key
+ * value).  Set any time; they apply to later calls (a captured offline graph
+ * keeps the shapes it was captured with).  Errors: ARG (unknown key
  * or value not listed).
  */
 #define MSRS_TUNE_SWEEP_COLS   0   /* samples per sweep workgroup: 16, 32, 64 (FP64 path: at most 32) */
@@ -331,7 +332,11 @@ msrs_status msrs_reset_stats(msrs_handle h);
 /* Message of the last error on h (or of the last failed create if h is NULL). */
 const char* msrs_last_error(msrs_handle h);
 
-/* Release every device buffer of the handle (synchronises its stream). */
+/*
+ * Release every device buffer of the handle (synchronises its stream and
+ * waits for its online calls).  Destroy every server that holds the handle
+ * first: a server keeps using the handle's bases and coarse operator.
+ */
 void msrs_destroy(msrs_handle h);
 
 /* ------------------------------------------------------------------------

@@ -787,16 +787,16 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         }
         lds_barrier();
         mfma();
-        store_acc(half == 0 ? X + m * lstride : nullptr);   // x_m (identical in both halves)
-        lds_barrier();
         const int nst = half == 0 ? m : nl - 1 - m;
         const bool low = half != 0;   // top: Up_l x_{l+1}; bottom: Low_l x_{l-1}
+        if (nst > 0) load_A(E + (int64_t)(m - dir) * BP * BP);        // the first back line, one step ahead
+        store_acc(half == 0 ? X + m * lstride : nullptr);   // x_m (identical in both halves)
+        lds_barrier();
         for (int k = 0; k < nst; ++k) {
             launder();
             const int ln = m - dir * (k + 1), pv = ln + dir;    // pv: the line solved before
             load_line(X + ln * lstride);                                               // y_ln
             if (KIND == kElliptic && tid <= b) crow = aL[(ln > pv ? ln : pv) * L + tid];   // shared cell row
-            load_A(E + (int64_t)ln * BP * BP);
             if (KIND == kElliptic && tid <= b) craw[tid] = crow;
             lds_barrier();
 #pragma unroll
@@ -808,7 +808,8 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
                 }
             }
             lds_barrier();
-            mfma();
+            mfma();                                                                    // x_ln = E_ln z
+            if (k + 1 < nst) load_A(E + (int64_t)(ln - dir) * BP * BP);              // E of the next line
             store_acc(X + ln * lstride);
             lds_barrier();
         }
@@ -934,6 +935,96 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const PatchDesc* pd,
         }
     }
     partial_column_sums(ssum, m, sp, red, part + ((int64_t)p * maxch + blockIdx.y) * kMaxSamples);
+}
+
+// Elliptic residual, sliding-window form: thread (line l0 + lo, sample c)
+// walks down its line with the 3 x 3 stencil window of x in registers (three
+// new loads per node instead of nine) and the coefficient cell rows of the
+// chunk staged in LDS (two new cells per node), so the loads scale with the
+// output instead of nine-fold.  Same arithmetic as the generic kernel.
+constexpr int kResThreads = kChunkLines * kMaxSamples;   // 8 lines x up to 64 samples
+__global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
+                                                                   const double* __restrict__ om, const double* __restrict__ x64_all,
+                                                                   float* __restrict__ x32_all, const int32_t* __restrict__ conv,
+                                                                   double* __restrict__ part, int maxch) {
+    __shared__ double cell[(kChunkLines + 1) * (kMaxLine + 1)];
+    __shared__ double red[kResThreads];
+    const int p = p0 + blockIdx.x;
+    if (conv && conv[p]) return;
+    const PatchDesc P = pd[p];
+    const int l0 = blockIdx.y * kChunkLines;
+    if (l0 >= P.nl) return;
+    const int l1 = min(P.nl, l0 + kChunkLines);
+    const double* aL = aL_all + P.a_off;
+    const double* O = om + P.om_off;
+    const int sp = P.sp, bp = P.bp, b = P.b, L = P.L, Qn = P.Qn;
+    const double* X = x64_all + P.x_off;
+    float* X32 = x32_all ? x32_all + P.x_off : nullptr;
+    const int64_t lstride = (int64_t)bp * sp;
+    const int tid = threadIdx.x;
+    // cell rows l0 .. l1 (line l is bounded by cell rows l and l + 1)
+    for (int o = tid; o < (l1 - l0 + 1) * L; o += kResThreads) cell[o] = aL[(int64_t)l0 * L + o];
+    __syncthreads();
+    const int lo = tid / sp, c = tid - lo * sp;
+    const bool active = lo < l1 - l0;
+    double ssum = 0.0;
+    if (active) {
+        const int l = l0 + lo, q = l + 1;
+        float* R32 = X32 ? X32 + (int64_t)l * lstride + c : nullptr;
+        if (c < P.s) {
+            // u(q2, p2): interior nodes from x, nodes on the buffered patch's boundary from Omega
+            auto u = [&](int q2, int p2) -> double {
+                if (p2 == 0 || p2 == L || q2 == 0 || q2 == Qn) {
+                    int ii, jj;
+                    line_to_phys(P, p2, q2, ii, jj);
+                    return O[(int64_t)c * P.nb + bidx_ccw(ii, jj, P.cx, P.cy)];
+                }
+                return X[(int64_t)(q2 - 1) * lstride + (int64_t)(p2 - 1) * sp + c];
+            };
+            const double* cS = cell + (l - l0) * L;        // cell row q - 1
+            const double* cN = cell + (l - l0 + 1) * L;    // cell row q
+            // window columns p-1, p, p+1 of node rows q-1, q, q+1
+            double wm[3], w0[3], wp[3];
+            wm[0] = u(q - 1, 0); w0[0] = u(q, 0); wp[0] = u(q + 1, 0);
+            wm[1] = u(q - 1, 1); w0[1] = u(q, 1); wp[1] = u(q + 1, 1);
+            double SW = cS[0], NW = cN[0];
+            for (int pp = 1; pp <= b; ++pp) {
+                wm[2] = u(q - 1, pp + 1);
+                w0[2] = u(q, pp + 1);
+                wp[2] = u(q + 1, pp + 1);
+                const double SE = cS[pp], NE = cN[pp];
+                // same terms and order as q1_coef over dq, dp = -1, 0, 1
+                double r = 0.0;
+                r -= (-SW / 3.0) * wm[0];
+                r -= (-(SE + SW) / 6.0) * wm[1];
+                r -= (-SE / 3.0) * wm[2];
+                r -= (-(NW + SW) / 6.0) * w0[0];
+                r -= ((2.0 / 3.0) * (NE + NW + SW + SE)) * w0[1];
+                r -= (-(NE + SE) / 6.0) * w0[2];
+                r -= (-NW / 3.0) * wp[0];
+                r -= (-(NE + NW) / 6.0) * wp[1];
+                r -= (-NE / 3.0) * wp[2];
+                if (R32) R32[(int64_t)(pp - 1) * sp] = (float)r;
+                ssum += r * r;
+                wm[0] = wm[1]; wm[1] = wm[2];
+                w0[0] = w0[1]; w0[1] = w0[2];
+                wp[0] = wp[1]; wp[1] = wp[2];
+                SW = SE; NW = NE;
+            }
+            if (R32)
+                for (int i = b; i < bp; ++i) R32[(int64_t)i * sp] = 0.0f;
+        } else if (R32) {
+            for (int i = 0; i < bp; ++i) R32[(int64_t)i * sp] = 0.0f;
+        }
+    }
+    // per-sample sums over the chunk's lines, fixed order
+    red[tid] = ssum;
+    __syncthreads();
+    if (tid < sp) {
+        double s = 0.0;
+        for (int r = 0; r < l1 - l0; ++r) s += red[r * sp + tid];
+        part[((int64_t)p * maxch + blockIdx.y) * kMaxSamples + tid] = s;
+    }
 }
 
 // x64 += x32 (the FP32 correction) over one chunk of lines of unconverged patches.
@@ -1190,8 +1281,8 @@ void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it) {
     const dim3 grid(p1 - p0, max_chunks(c, p0, p1));
     if (!stats_only) hipLaunchKernelGGL(accum_kernel, grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.x64, c.x32, c.conv);
     if (c.kind == kElliptic)
-        hipLaunchKernelGGL((residual_kernel<kElliptic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), inv_eps,
-                           c.x64, x32, conv, c.part, c.maxch);
+        hipLaunchKernelGGL(residual_ell_kernel, grid, dim3(kResThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.x64, x32, conv, c.part,
+                           c.maxch);
     else
         hipLaunchKernelGGL((residual_kernel<kKinetic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), inv_eps,
                            c.x64, x32, conv, c.part, c.maxch);
