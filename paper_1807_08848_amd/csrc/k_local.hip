@@ -608,8 +608,11 @@ __global__ __launch_bounds__(kFactorThreads) void factor_kernel(const PatchDesc*
 //     bottom  x_l = E_l (y_l - Low_l x_{l-1}),  l = m+1 .. nl-1
 // The y_l overwrite the right-hand sides in place and the x_l the y_l; t_top
 // and t_bot go through a small per-patch buffer, so no workgroup ever waits
-// for another.  The products E_l y run on MFMA 16x16x4 (8 waves: wave w owns
-// row tile w of E_l and all column tiles of the chunk).
+// for another.  In FP32 refinement the solution x_l is the correction, and the
+// back halves also add it to the FP64 iterate (X64, prefetched one stage
+// ahead), which saves a separate accumulation pass.  The products E_l y run
+// on MFMA 16x16x4 (8 waves: wave w owns row tile w of E_l and all column
+// tiles of the chunk).
 //
 // Software pipeline: the A operands of the next E_l are loaded into registers
 // while line l is processed, and the right-hand side and coupling loads of a
@@ -626,8 +629,8 @@ template <> struct Vec16<double> { typedef double2 type; static constexpr int n 
 // code.  TW: this chunk's [2][bp x sp] middle-line couplings (row stride sp).
 template <typename T, int KIND, int R, int NCT, int PHASE>
 __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw, double dx,
-                           const T* __restrict__ E, T* __restrict__ X, T* __restrict__ TW, int half, T* ybuf, T* wbuf,
-                           double* craw, double* cvp, double* cvm) {
+                           const T* __restrict__ E, T* __restrict__ X, double* __restrict__ X64, T* __restrict__ TW, int half,
+                           T* ybuf, T* wbuf, double* craw, double* cvp, double* cvm) {
     typedef typename Vec16<T>::type V;
     constexpr int VN = Vec16<T>::n;
     constexpr int BP = 16 * R, NKS = 4 * R, NSC = 16 * NCT;
@@ -692,8 +695,22 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
             }
         }
     };
-    // accumulators -> wbuf, and for a solution line (gdst) to global
-    auto store_acc = [&](T* gdst) {
+    // accumulators -> wbuf, and for a solution line (gdst) to global; with
+    // g64 the FP64 iterate of that line (prefetched into pre64) gets += v
+    double pre64[NCT][4];
+    auto load_64 = [&](const double* g64) {
+        const int lli = llane & 15;
+        if (mf) {
+#pragma unroll
+            for (int c = 0; c < NCT; ++c)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int i = 16 * rt + Mfma<T>::row(llane, t), j = 16 * c + lli;
+                    pre64[c][t] = g64[(uint32_t)(i * sp + j)];
+                }
+        }
+    };
+    auto store_acc = [&](T* gdst, double* g64) {
         const int lli = llane & 15;
         if (mf) {
 #pragma unroll
@@ -704,6 +721,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
                     const T v = acc[c][t];
                     wbuf[i * NSC + j] = v;
                     if (gdst) gdst[(uint32_t)(i * sp + j)] = v;
+                    if (g64) g64[(uint32_t)(i * sp + j)] = pre64[c][t] + (double)v;
                 }
         }
     };
@@ -756,7 +774,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
             if (KIND == kElliptic && tid <= b) crow = aL[(ln > nx ? ln : nx) * L + tid];   // shared cell row
             mfma();                                                                   // w = E_ln y_ln
             if (more) load_A(E + (int64_t)nx * BP * BP);
-            store_acc(nullptr);
+            store_acc(nullptr, nullptr);
             if (KIND == kElliptic && tid <= b) craw[tid] = crow;
             lds_barrier();
             T* dst = more ? X + nx * lstride : TWh;
@@ -777,6 +795,8 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         // ---- middle line, then the back half
         launder();
         load_A(E + (int64_t)m * BP * BP);
+        const bool acc64 = X64 && half == 0;   // line m's iterate is updated once, by the top half
+        if (acc64) load_64(X64 + m * lstride);
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
             const int i = li0 + e * DI;
@@ -790,13 +810,14 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         const int nst = half == 0 ? m : nl - 1 - m;
         const bool low = half != 0;   // top: Up_l x_{l+1}; bottom: Low_l x_{l-1}
         if (nst > 0) load_A(E + (int64_t)(m - dir) * BP * BP);        // the first back line, one step ahead
-        store_acc(half == 0 ? X + m * lstride : nullptr);   // x_m (identical in both halves)
+        store_acc(half == 0 ? X + m * lstride : nullptr, acc64 ? X64 + m * lstride : nullptr);   // x_m (identical in both halves)
         lds_barrier();
         for (int k = 0; k < nst; ++k) {
             launder();
             const int ln = m - dir * (k + 1), pv = ln + dir;    // pv: the line solved before
             load_line(X + ln * lstride);                                               // y_ln
             if (KIND == kElliptic && tid <= b) crow = aL[(ln > pv ? ln : pv) * L + tid];   // shared cell row
+            if (X64) load_64(X64 + ln * lstride);
             if (KIND == kElliptic && tid <= b) craw[tid] = crow;
             lds_barrier();
 #pragma unroll
@@ -810,7 +831,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
             lds_barrier();
             mfma();                                                                    // x_ln = E_ln z
             if (k + 1 < nst) load_A(E + (int64_t)(ln - dir) * BP * BP);              // E of the next line
-            store_acc(X + ln * lstride);
+            store_acc(X + ln * lstride, X64 ? X64 + ln * lstride : nullptr);
             lds_barrier();
         }
     }
@@ -821,7 +842,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
 template <typename T, int KIND, int NCT, int PHASE>
 __global__ __launch_bounds__(kSweepThreads) void sweep_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
                                                               const double* __restrict__ vw, double dx, const T* __restrict__ E_all,
-                                                              T* __restrict__ X_all, T* __restrict__ TW_all,
+                                                              T* __restrict__ X_all, double* __restrict__ X64_all, T* __restrict__ TW_all,
                                                               const int32_t* __restrict__ conv, int32_t* flags) {
     __shared__ T ybuf[kMaxLine * 16 * NCT];
     __shared__ T wbuf[kMaxLine * 16 * NCT];
@@ -837,7 +858,8 @@ __global__ __launch_bounds__(kSweepThreads) void sweep_kernel(const PatchDesc* p
     const T* E = E_all + P.E_off;
     T* X = X_all + P.x_off + s0;
     T* TW = TW_all + P.tw_off + s0;
-#define MSRS_SWB(RR) sweep_body<T, KIND, RR, NCT, PHASE>(P, aL, vw, dx, E, X, TW, half, ybuf, wbuf, craw, cvp, cvm)
+    double* X64 = X64_all ? X64_all + P.x_off + s0 : nullptr;
+#define MSRS_SWB(RR) sweep_body<T, KIND, RR, NCT, PHASE>(P, aL, vw, dx, E, X, X64, TW, half, ybuf, wbuf, craw, cvp, cvm)
     if (KIND == kKinetic) {
         switch (P.bp >> 4) {
             case 1: MSRS_SWB(1); break;
@@ -1027,18 +1049,6 @@ __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDe
     }
 }
 
-// x64 += x32 (the FP32 correction) over one chunk of lines of unconverged patches.
-__global__ __launch_bounds__(kThreads) void accum_kernel(const PatchDesc* pd, int p0, double* __restrict__ x64_all,
-                                                         const float* __restrict__ x32_all, const int32_t* __restrict__ conv) {
-    const int p = p0 + blockIdx.x;
-    if (conv[p]) return;
-    const PatchDesc P = pd[p];
-    const int l0 = blockIdx.y * kChunkLines;
-    if (l0 >= P.nl) return;
-    const int l1 = min(P.nl, l0 + kChunkLines);
-    const int64_t a = P.x_off + (int64_t)l0 * P.bp * P.sp, e = P.x_off + (int64_t)l1 * P.bp * P.sp;
-    for (int64_t o = a + threadIdx.x; o < e; o += kThreads) x64_all[o] += (double)x32_all[o];
-}
 
 // Per patch: sum the chunk partials.  which = 0: ||rhs_j||^2 -> rn[0..sp).
 // which = 1: ||r_j||^2 -> rn[sp..2sp), relres[p] = max_j ||r_j||/||rhs_j||,
@@ -1244,12 +1254,14 @@ void launch_sweep(Ctx& c, int p0, int p1, bool fp32) {
     const dim3 grid(p1 - p0, maxsp / sc, 2), blk(kSweepThreads);
     const int32_t* conv = fp32 ? c.conv : nullptr;
     const double dx = dx_of(c);
+    // FP32 refinement: the back halves add the correction to the FP64 iterate
+    double* x64acc = fp32 ? c.x64 : nullptr;
 #define MSRS_SWEEP(TT, KK, NN, XX)                                                                                             \
     do {                                                                                                                      \
         hipLaunchKernelGGL((sweep_kernel<TT, KK, NN, 0>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, \
-                           (TT*)c.tw, conv, c.dflags);                                                                         \
+                           (double*)nullptr, (TT*)c.tw, conv, c.dflags);                                                      \
         hipLaunchKernelGGL((sweep_kernel<TT, KK, NN, 1>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, \
-                           (TT*)c.tw, conv, c.dflags);                                                                         \
+                           x64acc, (TT*)c.tw, conv, c.dflags);                                                                 \
     } while (0)
     if (c.kind == kElliptic) {
         if (fp32) {
@@ -1279,7 +1291,6 @@ void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it) {
     int32_t* conv = stats_only ? nullptr : c.conv;
     float* x32 = stats_only ? nullptr : c.x32;
     const dim3 grid(p1 - p0, max_chunks(c, p0, p1));
-    if (!stats_only) hipLaunchKernelGGL(accum_kernel, grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.x64, c.x32, c.conv);
     if (c.kind == kElliptic)
         hipLaunchKernelGGL(residual_ell_kernel, grid, dim3(kResThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.x64, x32, conv, c.part,
                            c.maxch);
