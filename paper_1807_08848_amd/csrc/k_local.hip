@@ -201,11 +201,12 @@ __device__ __forceinline__ double diag_entry(const PatchDesc& P, const double* a
 
 // ---- blocked Gauss-Jordan on MFMA
 // The block D_l (BP = 16 R) is held as R x R tiles of 16 x 16 in MFMA
-// accumulator layout, tile (ti, tj) on wave (ti R + tj) % 8.  Pivots are taken
+// accumulator layout, tile (ti, tj) on wave (ti R + tj) % kFactorWaves.  Pivots are taken
 // in panels of 16: the panel's diagonal block is inverted by one wave with
 // cross-lane shuffles, then X = Dinv A_{p,*} (new row panel), -A_{*,p} Dinv
 // (new column panel) and the rank-16 update A_{i,j} -= A_{i,p} X_j run on MFMA.
-constexpr int kFactorThreads = 512;
+constexpr int kFactorWaves = 16;
+constexpr int kFactorThreads = 64 * kFactorWaves;
 
 // Inverse of a 16 x 16 block (row-major in LDS, leading dimension LDA; the
 // inverse with LDD) by one wave: lane l
@@ -276,7 +277,7 @@ template <typename T, int KIND, int R, bool MID>
 __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw,
                                               double dx, double inv_eps, T* __restrict__ E, T* lds, double* cf,
                                               double* crow, int dir, int32_t* flags) {
-    constexpr int BP = 16 * R, LDE = BP + 1, NT = R * R, NSLOT = (NT + 7) / 8;
+    constexpr int BP = 16 * R, LDE = BP + 1, NT = R * R, NSLOT = (NT + kFactorWaves - 1) / kFactorWaves;
     constexpr int NKS = BP / 4;
     typedef typename Mfma<T>::acc Acc;
     const int tid0 = threadIdx.x, w = tid0 >> 6;
@@ -380,7 +381,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
         auto schur = [&](bool init, bool term, bool kin_rev) {
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
-                const int idx = q * 8 + w;
+                const int idx = q * kFactorWaves + w;
                 if (idx >= NT) continue;
                 const int ti = idx / R, tj = idx - ti * R;
                 const int j = 16 * tj + li;
@@ -472,7 +473,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
             // B1: publish the panel column and row
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
-                const int idx = q * 8 + w;
+                const int idx = q * kFactorWaves + w;
                 if (idx >= NT) continue;
                 const int ti = idx / R, tj = idx - ti * R;
                 if (tj != pn && ti != pn) continue;
@@ -490,7 +491,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
             // B3a: new row panel X_j = Dinv A_{p,j} (owners of row-panel tiles)
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
-                const int idx = q * 8 + w;
+                const int idx = q * kFactorWaves + w;
                 if (idx >= NT) continue;
                 const int ti = idx / R, tj = idx - ti * R;
                 if (ti != pn || tj == pn) continue;
@@ -508,7 +509,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
             // B3b: column panel and rank-16 update of the rest; diagonal tile = Dinv
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
-                const int idx = q * 8 + w;
+                const int idx = q * kFactorWaves + w;
                 if (idx >= NT) continue;
                 const int ti = idx / R, tj = idx - ti * R;
                 if (ti == pn) {
@@ -543,7 +544,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
         // the sweep's MFMA operand order
 #pragma unroll
         for (int q = 0; q < NSLOT; ++q) {
-            const int idx = q * 8 + w;
+            const int idx = q * kFactorWaves + w;
             if (idx >= NT) continue;
             const int ti = idx / R, tj = idx - ti * R;
 #pragma unroll
