@@ -130,8 +130,10 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
     __syncthreads();
     sum_partials(part, p, maxrc, nch, s, G, LDG);
     const int n = s + (s & 1), np2 = n / 2, nm1 = n - 1;
-    // Sweeps until every rotation of a sweep finds |g_pq| <= 1e-15 sqrt(g_pp g_qq)
-    // (relative off-diagonal criterion) or |g_pq| <= 1e-16 trace(G) (the level of
+    // Sweeps until every rotation of a sweep finds |g_pq| <= 1e-13 sqrt(g_pp g_qq)
+    // (relative off-diagonal criterion; the rotation it leaves is below 1e-13
+    // over the relative gap, and the convergence is quadratic by then) or
+    // |g_pq| <= 1e-16 trace(G) (the level of
     // the rounding in forming G = Y^T Y, below which the relative test cannot be
     // met between widely separated eigenvalues), at most 30.  The trace is
     // invariant under the rotations.
@@ -154,10 +156,11 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
                 const double apq = G[a * LDG + b];
                 if (b < s && apq != 0.0) {
                     const double app = G[a * LDG + a], aqq = G[b * LDG + b];
-                    if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > floor_abs) rot = 1;
+                    // |g_pq| > 1e-13 sqrt|g_pp g_qq| compared in squares
+                    if (apq * apq > 1e-26 * fabs(app * aqq) && fabs(apq) > floor_abs) rot = 1;
                     const double tau = (aqq - app) / (2.0 * apq);
                     t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
+                    c = rsqrt(1.0 + t * t);
                 }
                 cs[i] = c;
                 sn[i] = t * c;
