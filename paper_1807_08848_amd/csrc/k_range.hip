@@ -102,6 +102,17 @@ __device__ void sum_partials(const double* __restrict__ part, int p, int maxrc, 
 }
 
 // ---------------------------------------------------------------- eigendecomposition
+// Pair i of round st in the round-robin ordering of n = nm1 + 1 indices: index 0
+// stays, the others rotate one place per round, and pair i joins the i-th
+// positions from both ends; after nm1 rounds every pair has met once.
+__device__ __forceinline__ void rr_pair(int i, int st, int nm1, int& a, int& b) {
+    int u = 0;
+    if (i > 0) { u = i - 1 + st; if (u >= nm1) u -= nm1; u += 1; }
+    int v = nm1 - 1 - i + st; if (v >= nm1) v -= nm1; v += 1;
+    a = min(u, v);
+    b = max(u, v);
+}
+
 // One workgroup per patch: G = sum of partials, cyclic Jacobi (round-robin
 // pairs, two-sided updates on 2x2 blocks), eigenvalues sorted descending,
 // singular values, relative gap, and B = V[:, :k] / sigma -> small[p] (s x k).
@@ -114,7 +125,6 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
     __shared__ double G[kRfMax * LDG];
     __shared__ double V[kRfMax * LDG];
     __shared__ double cs[kRfMax / 2], sn[kRfMax / 2], tn[kRfMax / 2];
-    __shared__ int pu[kRfMax / 2], pv[kRfMax / 2];
     __shared__ int perm[kRfMax];
     __shared__ double lam[kRfMax];
     __shared__ int rot;
@@ -130,6 +140,9 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
     __syncthreads();
     sum_partials(part, p, maxrc, nch, s, G, LDG);
     const int n = s + (s & 1), np2 = n / 2, nm1 = n - 1;
+    int shp = 0, shn = 0;
+    while ((1 << shp) < np2) ++shp;
+    while ((1 << shn) < n) ++shn;
     // Sweeps until every rotation of a sweep finds |g_pq| <= 1e-13 sqrt(g_pp g_qq)
     // (relative off-diagonal criterion; the rotation it leaves is below 1e-13
     // over the relative gap, and the convergence is quadratic by then) or
@@ -146,20 +159,17 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
         for (int st = 0; st < nm1; ++st) {
             if (tid < np2) {
                 const int i = tid;
-                int u = 0;
-                if (i > 0) { u = i - 1 + st; if (u >= nm1) u -= nm1; u += 1; }
-                int v = nm1 - 1 - i + st; if (v >= nm1) v -= nm1; v += 1;
-                const int a = min(u, v), b = max(u, v);
-                pu[i] = a;
-                pv[i] = b;
+                int a, b;
+                rr_pair(i, st, nm1, a, b);
                 double c = 1.0, t = 0.0;
-                const double apq = G[a * LDG + b];
+                const double apq = G[a * LDG + b], app = G[a * LDG + a], aqq = G[b * LDG + b];
                 if (b < s && apq != 0.0) {
-                    const double app = G[a * LDG + a], aqq = G[b * LDG + b];
                     // |g_pq| > 1e-13 sqrt|g_pp g_qq| compared in squares
                     if (apq * apq > 1e-26 * fabs(app * aqq) && fabs(apq) > floor_abs) rot = 1;
-                    const double tau = (aqq - app) / (2.0 * apq);
-                    t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    // the smaller root of t^2 + 2 tau t - 1 = 0, tau = d / (2 g_pq),
+                    // d = g_qq - g_pp, with numerator and denominator scaled by 2|g_pq|
+                    const double d = aqq - app;
+                    t = (d < 0 ? -2.0 * apq : 2.0 * apq) / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
                     c = rsqrt(1.0 + t * t);
                 }
                 cs[i] = c;
@@ -167,12 +177,15 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
                 tn[i] = t;
             }
             __syncthreads();
-            // G <- J^T G J on 2x2 blocks (rows by pair i, columns by pair i2): thread
-            // (i = tid / 32 + 8 r, i2 = tid % 32)
-            for (int i = tid >> 5; i < np2; i += kThreads / 32) {
-                const int i2 = tid & 31;
+            // G <- J^T G J on 2x2 blocks (rows by pair i, columns by pair i2) and
+            // V <- V J (rows j < n, pairs i) over flat work indices, the inner
+            // index padded to a power of two only (no lane idle for s = 32)
+            for (int o = tid; o < (np2 << shp); o += kThreads) {
+                const int i = o >> shp, i2 = o & ((1 << shp) - 1);
                 if (i2 >= np2) continue;
-                const int a = pu[i], b = pv[i], a2 = pu[i2], b2 = pv[i2];
+                int a, b, a2, b2;
+                rr_pair(i, st, nm1, a, b);
+                rr_pair(i2, st, nm1, a2, b2);
                 const double c = cs[i], sv = sn[i], c2 = cs[i2], s2 = sn[i2];
                 const double g00 = G[a * LDG + a2], g01 = G[a * LDG + b2];
                 const double g10 = G[b * LDG + a2], g11 = G[b * LDG + b2];
@@ -194,11 +207,11 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
                 G[b * LDG + a2] = c2 * r10 - s2 * r11;
                 G[b * LDG + b2] = s2 * r10 + c2 * r11;
             }
-            // V <- V J: thread (row j = tid % 64, pairs i = tid / 64 + 4 r)
-            for (int i = tid >> 6; i < np2; i += kThreads / 64) {
-                const int j = tid & 63;
+            for (int o = tid; o < (np2 << shn); o += kThreads) {
+                const int i = o >> shn, j = o & ((1 << shn) - 1);
                 if (j >= n) continue;
-                const int a = pu[i], b = pv[i];
+                int a, b;
+                rr_pair(i, st, nm1, a, b);
                 const double c = cs[i], sv = sn[i];
                 const double va = V[j * LDG + a], vb = V[j * LDG + b];
                 V[j * LDG + a] = c * va - sv * vb;
@@ -213,14 +226,23 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
         __syncthreads();
         if (!r) break;
     }
-    if (tid == 0) {
-        for (int i = 0; i < s; ++i) { perm[i] = i; lam[i] = G[i * LDG + i]; }
-        for (int i = 0; i < s; ++i) {
-            int best = i;
-            for (int j = i + 1; j < s; ++j)
-                if (lam[perm[j]] > lam[perm[best]]) best = j;
-            const int t = perm[i]; perm[i] = perm[best]; perm[best] = t;
+    // descending order by rank: eigenvalue i goes to the number of eigenvalues
+    // above it, ties by index (a NaN ranks as -inf, so the ranks stay a
+    // permutation)
+    if (tid < s) {
+        const double gi = G[tid * LDG + tid];
+        const double li = (gi == gi) ? gi : -INFINITY;
+        int r = 0;
+        for (int j = 0; j < s; ++j) {
+            const double gj = G[j * LDG + j];
+            const double lj = (gj == gj) ? gj : -INFINITY;
+            r += (lj > li) || (lj == li && j < tid);
         }
+        perm[r] = tid;
+        lam[tid] = gi;
+    }
+    __syncthreads();
+    if (tid == 0) {
         double* svp = sv_all + P.sv_off;
         for (int i = 0; i < s; ++i) svp[i] = sqrt(fmax(lam[perm[i]], 0.0));
         const double s1 = svp[0], sk = svp[k - 1];
