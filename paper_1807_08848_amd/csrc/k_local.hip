@@ -342,8 +342,8 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
     // off-diagonal (a, a+1) -c_{a+1}/3
     auto set_cf = [&](const double* cr) {
         for (int a = tid; a < b; a += kFactorThreads) {
-            cf[a] = -(cr[a] + cr[a + 1]) / 6.0;
-            cf[BP + a] = -cr[a + 1] / 3.0;
+            cf[a] = (cr[a] + cr[a + 1]) * (-1.0 / 6.0);
+            cf[BP + a] = cr[a + 1] * (-1.0 / 3.0);
         }
     };
 
@@ -365,8 +365,8 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
         auto dg = [&](int i, int j) -> double {
             if (KIND == kElliptic) {
                 if (i == j) return (2.0 / 3.0) * (rB[i + 1] + rB[i] + rA[i] + rA[i + 1]);
-                if (j == i + 1) return -(rB[i + 1] + rA[i + 1]) / 6.0;
-                if (i == j + 1) return -(rB[j + 1] + rA[j + 1]) / 6.0;
+                if (j == i + 1) return (rB[i + 1] + rA[i + 1]) * (-1.0 / 6.0);
+                if (i == j + 1) return (rB[j + 1] + rA[j + 1]) * (-1.0 / 6.0);
                 return 0.0;
             } else {
                 return diag_entry<KIND>(P, aL, vw, dx, inv_eps, ln, i, j);
@@ -665,11 +665,11 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         li0 = i0; ljj = jj; llane = lane;
         asm volatile("" : "+v"(li0), "+v"(ljj), "+v"(llane));
     };
-    auto load_line = [&](const T* Xl) {
+    auto load_line = [&](const T* Xl, T (&dst)[RPT]) {
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
             const int i = li0 + e * DI;
-            if (BP % DI == 0 || i < BP) rv[e] = Xl[(uint32_t)(i * sp + ljj)];
+            if (BP % DI == 0 || i < BP) dst[e] = Xl[(uint32_t)(i * sp + ljj)];
         }
     };
     auto load_A = [&](const T* El) {
@@ -698,8 +698,8 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
     };
     // accumulators -> wbuf, and for a solution line (gdst) to global; with
     // g64 the FP64 iterate of that line (prefetched into pre64) gets += v
-    double pre64[NCT][4];
-    auto load_64 = [&](const double* g64) {
+    double pre64[NCT][4], pre64n[NCT][4];
+    auto load_64 = [&](const double* g64, double (&dst)[NCT][4]) {
         const int lli = llane & 15;
         if (mf) {
 #pragma unroll
@@ -707,7 +707,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int i = 16 * rt + Mfma<T>::row(llane, t), j = 16 * c + lli;
-                    pre64[c][t] = g64[(uint32_t)(i * sp + j)];
+                    dst[c][t] = g64[(uint32_t)(i * sp + j)];
                 }
         }
     };
@@ -728,14 +728,15 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
     };
     // coupling block between two adjacent lines applied to column j of src,
     // row i: Low (A_{l+1,l}) if low, else Up (A_{l,l+1}).  Elliptic: the
-    // symmetric tridiagonal block of their shared cell row (craw): diagonal
-    // -(c_i + c_{i+1})/6, off-diagonal (i, i+1) -c_{i+1}/3
+    // symmetric tridiagonal block of their shared cell row c: diagonal
+    // -(c_i + c_{i+1})/6, off-diagonal (i, i+1) -c_{i+1}/3; craw holds the
+    // row already scaled by -1/3
     auto couple = [&](const T* src, int i, int j, bool low) -> double {
         if (KIND == kElliptic) {
             const int im = i > 0 ? i - 1 : 0, ip = i + 1 < BP ? i + 1 : BP - 1;
-            const double cm = i > 0 ? -craw[i] / 3.0 : 0.0;
-            const double cp = i < b - 1 ? -craw[i + 1] / 3.0 : 0.0;
-            return -(craw[i] + craw[i + 1]) / 6.0 * (double)src[i * NSC + j] + cm * (double)src[im * NSC + j] +
+            const double cm = i > 0 ? craw[i] : 0.0;
+            const double cp = i < b - 1 ? craw[i + 1] : 0.0;
+            return 0.5 * (craw[i] + craw[i + 1]) * (double)src[i * NSC + j] + cm * (double)src[im * NSC + j] +
                    cp * (double)src[ip * NSC + j];
         } else {
             return -(low ? cvp[i] : cvm[i]) * (double)src[i * NSC + j];
@@ -750,7 +751,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         launder();
         if (nst <= 0) {
             // no line in this half: t_top = r_m, t_bot = 0
-            if (half == 0) load_line(X + m * lstride);
+            if (half == 0) load_line(X + m * lstride, rv);
 #pragma unroll
             for (int e = 0; e < RPT; ++e) {
                 const int i = li0 + e * DI;
@@ -758,25 +759,33 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
             }
             return;
         }
-        load_line(X + ln0 * lstride);                 // y_{ln0} = r_{ln0}
+        // step k works on line ln = ln0 + dir k and its successor nx = ln + dir
+        // (m after the last step); the successor's right-hand side r_nx and the
+        // shared cell row are loaded one step ahead, E_nx during the step
+        auto sub_of = [&](int k) { return k + 1 < nst || half == 0; };   // the top's last step carries r_m
+        load_line(X + ln0 * lstride, rv);                 // y_{ln0} = r_{ln0}
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
             const int i = li0 + e * DI;
             if (BP % DI == 0 || i < BP) ybuf[i * NSC + ljj] = rv[e];
         }
         load_A(E + (int64_t)ln0 * BP * BP);
+        if (sub_of(0)) load_line(X + (ln0 + dir) * lstride, rv);
+        if (KIND == kElliptic && tid <= b) crow = aL[(dir > 0 ? ln0 + 1 : ln0) * L + tid];
         lds_barrier();
         for (int k = 0; k < nst; ++k) {
             launder();
-            const int ln = ln0 + dir * k, nx = ln + dir;    // nx: next line (m after the last step)
+            const int ln = ln0 + dir * k, nx = ln + dir;
             const bool more = k + 1 < nst;
-            const bool sub = more || half == 0;      // the top's last step carries r_m into t_top
-            if (sub) load_line(X + nx * lstride);                                    // r_{nx}
-            if (KIND == kElliptic && tid <= b) crow = aL[(ln > nx ? ln : nx) * L + tid];   // shared cell row
+            const bool sub = sub_of(k);
+            T rvn[RPT];
+            double crown = 0.0;
+            if (more && sub_of(k + 1)) load_line(X + (nx + dir) * lstride, rvn);          // r of the next step
+            if (KIND == kElliptic && more && tid <= b) crown = aL[(dir > 0 ? nx + 1 : nx) * L + tid];
             mfma();                                                                   // w = E_ln y_ln
             if (more) load_A(E + (int64_t)nx * BP * BP);
             store_acc(nullptr, nullptr);
-            if (KIND == kElliptic && tid <= b) craw[tid] = crow;
+            if (KIND == kElliptic && tid <= b) craw[tid] = crow * (-1.0 / 3.0);
             lds_barrier();
             T* dst = more ? X + nx * lstride : TWh;
 #pragma unroll
@@ -790,14 +799,20 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
                     if (more) ybuf[i * NSC + ljj] = y;
                 }
             }
+#pragma unroll
+            for (int e = 0; e < RPT; ++e) rv[e] = rvn[e];
+            crow = crown;
             lds_barrier();
         }
     } else {
-        // ---- middle line, then the back half
+        // ---- middle line, then the back half; step k solves line
+        // ln = m - dir (k + 1) from pv = ln + dir.  Its right-hand side y_ln, the
+        // shared cell row and (FP32 refinement) the FP64 iterate of the line are
+        // loaded one step ahead, E_ln during the step before.
         launder();
         load_A(E + (int64_t)m * BP * BP);
         const bool acc64 = X64 && half == 0;   // line m's iterate is updated once, by the top half
-        if (acc64) load_64(X64 + m * lstride);
+        if (acc64) load_64(X64 + m * lstride, pre64);
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
             const int i = li0 + e * DI;
@@ -806,20 +821,36 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
                 ybuf[i * NSC + ljj] = i < b ? (T)v : T(0);
             }
         }
-        lds_barrier();
-        mfma();
         const int nst = half == 0 ? m : nl - 1 - m;
         const bool low = half != 0;   // top: Up_l x_{l+1}; bottom: Low_l x_{l-1}
+        if (nst > 0) {
+            const int l1 = m - dir;
+            load_line(X + l1 * lstride, rv);
+            if (KIND == kElliptic && tid <= b) crow = aL[(dir > 0 ? m : l1) * L + tid];
+            if (X64) load_64(X64 + l1 * lstride, pre64n);
+        }
+        lds_barrier();
+        mfma();
         if (nst > 0) load_A(E + (int64_t)(m - dir) * BP * BP);        // the first back line, one step ahead
         store_acc(half == 0 ? X + m * lstride : nullptr, acc64 ? X64 + m * lstride : nullptr);   // x_m (identical in both halves)
         lds_barrier();
         for (int k = 0; k < nst; ++k) {
             launder();
-            const int ln = m - dir * (k + 1), pv = ln + dir;    // pv: the line solved before
-            load_line(X + ln * lstride);                                               // y_ln
-            if (KIND == kElliptic && tid <= b) crow = aL[(ln > pv ? ln : pv) * L + tid];   // shared cell row
-            if (X64) load_64(X64 + ln * lstride);
-            if (KIND == kElliptic && tid <= b) craw[tid] = crow;
+            const int ln = m - dir * (k + 1);
+            const bool more = k + 1 < nst;
+#pragma unroll
+            for (int c = 0; c < NCT; ++c)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) pre64[c][t] = pre64n[c][t];
+            T rvn[RPT];
+            double crown = 0.0;
+            if (more) {
+                const int l2 = ln - dir;
+                load_line(X + l2 * lstride, rvn);                                     // y of the next step
+                if (KIND == kElliptic && tid <= b) crown = aL[(dir > 0 ? ln : l2) * L + tid];
+                if (X64) load_64(X64 + l2 * lstride, pre64n);
+            }
+            if (KIND == kElliptic && tid <= b) craw[tid] = crow * (-1.0 / 3.0);
             lds_barrier();
 #pragma unroll
             for (int e = 0; e < RPT; ++e) {
@@ -831,8 +862,11 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
             }
             lds_barrier();
             mfma();                                                                    // x_ln = E_ln z
-            if (k + 1 < nst) load_A(E + (int64_t)(ln - dir) * BP * BP);              // E of the next line
+            if (more) load_A(E + (int64_t)(ln - dir) * BP * BP);                     // E of the next line
             store_acc(X + ln * lstride, X64 ? X64 + ln * lstride : nullptr);
+#pragma unroll
+            for (int e = 0; e < RPT; ++e) rv[e] = rvn[e];
+            crow = crown;
             lds_barrier();
         }
     }
@@ -1016,17 +1050,19 @@ __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDe
                 w0[2] = u(q, pp + 1);
                 wp[2] = u(q + 1, pp + 1);
                 const double SE = cS[pp], NE = cN[pp];
-                // same terms and order as q1_coef over dq, dp = -1, 0, 1
+                // the terms of q1_coef over dq, dp = -1, 0, 1, in that order; the
+                // divisions by 3 and 6 as products with the rounded reciprocals
+                constexpr double k3 = 1.0 / 3.0, k6 = 1.0 / 6.0;
                 double r = 0.0;
-                r -= (-SW / 3.0) * wm[0];
-                r -= (-(SE + SW) / 6.0) * wm[1];
-                r -= (-SE / 3.0) * wm[2];
-                r -= (-(NW + SW) / 6.0) * w0[0];
+                r += (SW * k3) * wm[0];
+                r += ((SE + SW) * k6) * wm[1];
+                r += (SE * k3) * wm[2];
+                r += ((NW + SW) * k6) * w0[0];
                 r -= ((2.0 / 3.0) * (NE + NW + SW + SE)) * w0[1];
-                r -= (-(NE + SE) / 6.0) * w0[2];
-                r -= (-NW / 3.0) * wp[0];
-                r -= (-(NE + NW) / 6.0) * wp[1];
-                r -= (-NE / 3.0) * wp[2];
+                r += ((NE + SE) * k6) * w0[2];
+                r += (NW * k3) * wp[0];
+                r += ((NE + NW) * k6) * wp[1];
+                r += (NE * k3) * wp[2];
                 if (R32) R32[(int64_t)(pp - 1) * sp] = (float)r;
                 ssum += r * r;
                 wm[0] = wm[1]; wm[1] = wm[2];
