@@ -283,6 +283,7 @@ namespace {
 void sample_enqueue(Ctx* c, const double* omega_dev, int fixed_iters) {
     for_patches(*c, [&](int p0, int p1) { launch_omega(*c, omega_dev, p0, p1); });
     for_patches(*c, [&](int p0, int p1) { launch_lift(*c, p0, p1); });
+    join_factor(*c);   // the sweeps need the factor
     if (c->prec == MSRS_PREC_FP64) {
         for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, false); });
         for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, true, 0); });
@@ -539,10 +540,17 @@ msrs_status msrs_offline_graph_capture(msrs_handle h, const double* coef_dev) {
         c->timing = false;   // no event nodes inside the graph
         MSRS_HIP_CHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         try {
+            // the factor's streams join the capture stream only before the first
+            // sweep: the boundary draws and the lift run beside the factor
+            c->defer_factor_join = true;
+            c->n_join = 0;
             assemble_enqueue(c, coef_dev);
+            c->defer_factor_join = false;
             sample_enqueue(c, nullptr, iters);
             for_patches(*c, [&](int p0, int p1) { launch_range(*c, p0, p1); });
         } catch (const HipError&) {
+            c->defer_factor_join = false;
+            c->n_join = 0;
             hipGraph_t g = nullptr;
             (void)hipStreamEndCapture(c->stream, &g);
             if (g) (void)hipGraphDestroy(g);

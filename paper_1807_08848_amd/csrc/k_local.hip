@@ -1265,9 +1265,15 @@ void launch_factor(Ctx& c, int p0, int p1) {
         MSRS_HIP_CHECK(hipStreamWaitEvent(st, c.ev_fork, 0));
         launch_factor_group(c, g, st, c.rgroup[g], c.rgroup_n[g]);
         MSRS_HIP_CHECK(hipEventRecord(c.ev_join[k], st));
-        MSRS_HIP_CHECK(hipStreamWaitEvent(c.stream, c.ev_join[k], 0));
+        if (!c.defer_factor_join) MSRS_HIP_CHECK(hipStreamWaitEvent(c.stream, c.ev_join[k], 0));
         ++k;
     }
+    if (c.defer_factor_join) c.n_join = k;
+}
+
+void join_factor(Ctx& c) {
+    for (int k = 0; k < c.n_join; ++k) MSRS_HIP_CHECK(hipStreamWaitEvent(c.stream, c.ev_join[k], 0));
+    c.n_join = 0;
 }
 
 // samples per sweep workgroup: the largest of {64, 32, 16} (FP64 at most 32,
