@@ -201,18 +201,54 @@ __device__ __forceinline__ double diag_entry(const PatchDesc& P, const double* a
 
 // ---- blocked Gauss-Jordan on MFMA
 // The block D_l (BP = 16 R) is held as R x R tiles of 16 x 16 in MFMA
-// accumulator layout, tile (ti, tj) on wave (ti R + tj) % kFactorWaves.  Pivots are taken
+// accumulator layout, spread over the waves by factor_tile.  Pivots are taken
 // in panels of 16: the panel's diagonal block is inverted by one wave with
 // cross-lane shuffles, then X = Dinv A_{p,*} (new row panel), -A_{*,p} Dinv
 // (new column panel) and the rank-16 update A_{i,j} -= A_{i,p} X_j run on MFMA.
 constexpr int kFactorWaves = 16;
 constexpr int kFactorThreads = 64 * kFactorWaves;
 
+// Tile map of the blocked factor: slot q of wave w holds tile ti R + tj, or
+// nothing (-1).  Up to R = 5 tiles per side, diagonal tile d sits alone on
+// wave d (so that in FP32 its owner inverts it while the other waves run the
+// panel update) and the R (R - 1) off-diagonal tiles go row-major and
+// round-robin over waves R .. 15; from R = 6 on (three or more slots per wave
+// there, which slows the Schur build more than the inverse gains), all R^2
+// tiles go round-robin over the 16 waves.
+template <int R>
+constexpr bool factor_diag_alone() { return R <= 5; }
+template <int R>
+__device__ __forceinline__ int factor_tile(int q, int w) {
+    if constexpr (!factor_diag_alone<R>()) {
+        const int idx = q * kFactorWaves + w;
+        return idx < R * R ? idx : -1;
+    } else {
+        constexpr int NW = kFactorWaves - R, NOFF = R * (R - 1), RM = R > 1 ? R - 1 : 1;
+        if (w < R) return q == 0 ? w * (R + 1) : -1;
+        const int o = q * NW + (w - R);
+        if (o >= NOFF) return -1;
+        const int i = o / RM, jj = o - i * RM;
+        return i * R + (jj < i ? jj : jj + 1);
+    }
+}
+template <int R>
+constexpr int factor_slots() {
+    if constexpr (!factor_diag_alone<R>()) {
+        return (R * R + kFactorWaves - 1) / kFactorWaves;
+    } else {
+        constexpr int NW = kFactorWaves - R, NOFF = R * (R - 1);
+        return NOFF == 0 ? 1 : (NOFF + NW - 1) / NW;
+    }
+}
+
 // Inverse of a 16 x 16 block (row-major in LDS, leading dimension LDA; the
 // inverse with LDD) by one wave: lane l
 // holds row l%16, columns 4(l/16)..4(l/16)+3; Gauss-Jordan without pivoting.
 // FP32 pivot step K: the pivot row reaches every lane of a 16-lane row by a
-// DPP row broadcast, the pivot itself by readlane, and its reciprocal is the
+// DPP row broadcast; the pivot column entry of row r sits in lane r of 16-lane
+// row K/4, which two row-swap permutes (16- then 32-lane halves, each taken
+// from the side that holds that row) copy to all four rows without a trip
+// through LDS; the pivot itself comes by readlane, and its reciprocal is the
 // hardware approximation (the FP32 factor is refined in FP64 downstream).
 template <int K>
 __device__ __forceinline__ void inv16_pivot_f32(float (&a)[4], int r, int cg, bool& bad) {
@@ -220,7 +256,11 @@ __device__ __forceinline__ void inv16_pivot_f32(float (&a)[4], int r, int cg, bo
     float prow[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) prow[u] = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(a[u]), 0x150 + K, 0xF, 0xF, false));
-    const float pcol = __shfl(a[ku], r + 16 * kg, 64);
+    const unsigned xc = __float_as_uint(a[ku]);
+    const auto s16 = __builtin_amdgcn_permlane16_swap(xc, xc, false, false);   // rows (0,0,2,2) | (1,1,3,3)
+    const unsigned h = (kg & 1) ? s16[1] : s16[0];
+    const auto s32 = __builtin_amdgcn_permlane32_swap(h, h, false, false);     // rows (0,1,0,1) | (2,3,2,3) of h
+    const float pcol = __uint_as_float((kg & 2) ? s32[1] : s32[0]);
     const float piv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[ku]), K + 16 * kg));
     if (!(piv > 0.f) || !isfinite(piv)) bad = true;
     const float ip = __builtin_amdgcn_rcpf(piv);
@@ -231,6 +271,37 @@ __device__ __forceinline__ void inv16_pivot_f32(float (&a)[4], int r, int cg, bo
         a[u] = (r == K) ? (ck ? ip : prow[u] * ip) : gen;
     }
     if constexpr (K + 1 < 16) inv16_pivot_f32<K + 1>(a, r, cg, bad);
+}
+
+// In-register inverse of a 16 x 16 FP32 block in MFMA accumulator layout
+// (lane l: column c = l % 16, rows 4 q + t in a[t], q = l / 16), Gauss-Jordan
+// without pivoting.  Pivot step K: the pivot column entries of the lane's rows
+// come by a DPP row broadcast from lane K of the same 16-lane row; the pivot
+// row entry of its column sits in 16-lane row K/4, register K%4, copied to all
+// rows by the two row-swap permutes; the pivot by readlane, its reciprocal the
+// hardware approximation.
+template <int K>
+__device__ __forceinline__ void inv16_acc_f32(float (&a)[4], int c, int q, bool& bad) {
+    constexpr int kq = K >> 2, kt = K & 3;
+    float pcol[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) pcol[t] = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(a[t]), 0x150 + K, 0xF, 0xF, false));
+    const unsigned xr = __float_as_uint(a[kt]);
+    const auto s16 = __builtin_amdgcn_permlane16_swap(xr, xr, false, false);
+    const unsigned h = (kq & 1) ? s16[1] : s16[0];
+    const auto s32 = __builtin_amdgcn_permlane32_swap(h, h, false, false);
+    const float prow = __uint_as_float((kq & 2) ? s32[1] : s32[0]);
+    const float piv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[kt]), K + 16 * kq));
+    if (!(piv > 0.f) || !isfinite(piv)) bad = true;
+    const float ip = __builtin_amdgcn_rcpf(piv);
+    const bool ck = c == K;
+    const float prs = ck ? ip : prow * ip;   // the new pivot row (its own entry 1/p)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float gen = ck ? -pcol[t] * ip : a[t] - pcol[t] * prs;
+        a[t] = (t == kt && q == kq) ? prs : gen;
+    }
+    if constexpr (K + 1 < 16) inv16_acc_f32<K + 1>(a, c, q, bad);
 }
 
 template <typename T, int LDA, int LDD>
@@ -277,7 +348,7 @@ template <typename T, int KIND, int R, bool MID>
 __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw,
                                               double dx, double inv_eps, T* __restrict__ E, T* lds, double* cf,
                                               double* crow, int dir, int32_t* flags) {
-    constexpr int BP = 16 * R, LDE = BP + 1, NT = R * R, NSLOT = (NT + kFactorWaves - 1) / kFactorWaves;
+    constexpr int BP = 16 * R, LDE = BP + 1, NSLOT = factor_slots<R>();
     constexpr int NKS = BP / 4;
     typedef typename Mfma<T>::acc Acc;
     const int tid0 = threadIdx.x, w = tid0 >> 6;
@@ -381,8 +452,8 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
         auto schur = [&](bool init, bool term, bool kin_rev) {
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
-                const int idx = q * kFactorWaves + w;
-                if (idx >= NT) continue;
+                const int idx = factor_tile<R>(q, w);
+                if (idx < 0) continue;
                 const int ti = idx / R, tj = idx - ti * R;
                 const int j = 16 * tj + li;
                 if constexpr (KIND == kElliptic && sizeof(T) == 4) {
@@ -462,37 +533,50 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
             schur(false, true, true);
         }
         __syncthreads();   // Es no longer needed: panel buffers may overwrite it
-        // blocked Gauss-Jordan over the panels
-        for (int pn = 0; pn < npan; ++pn) {
-            launder();
-            const int buf = pn & 1;
-            T* pc = Pc + buf * BP * PCL;
-            T* pr = Pr + buf * 16 * PRL;
-            T* xs = Xs + buf * 16 * PRL;
-            T* dv = Dv + buf * 16 * DVL;
-            // B1: publish the panel column and row
+        // blocked Gauss-Jordan over the panels.  Panel pn: B1 publish its column
+        // and row tiles, B2 invert the diagonal block, B3a new row panel
+        // X_j = Dinv A_{p,j}, B3b column panel -A_{i,p} Dinv and rank-16 update
+        // A_{i,j} -= A_{i,p} X_j.  FP32 runs B1 and B2 of panel pn+1 inside B3b of
+        // panel pn (look-ahead): the owner of the next diagonal tile inverts it
+        // in registers while the other waves finish their updates.
+        auto publish = [&](int p, T* pc, T* pr) {
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
-                const int idx = q * kFactorWaves + w;
-                if (idx >= NT) continue;
+                const int idx = factor_tile<R>(q, w);
+                if (idx < 0) continue;
                 const int ti = idx / R, tj = idx - ti * R;
-                if (tj != pn && ti != pn) continue;
+                if (tj != p && ti != p) continue;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int ii = Mfma<T>::row(lane, t);
-                    if (tj == pn) pc[(16 * ti + ii) * PCL + li] = tile[q][t];
-                    if (ti == pn) pr[ii * PRL + 16 * tj + li] = tile[q][t];
+                    if (tj == p) pc[(16 * ti + ii) * PCL + li] = tile[q][t];
+                    if (ti == p) pr[ii * PRL + 16 * tj + li] = tile[q][t];
                 }
             }
-            __syncthreads();
-            // B2: inverse of the diagonal block (wave 0)
-            if (w == 0) inv16_wave<T, PCL, DVL>(pc + 16 * pn * PCL, dv, bad);
-            __syncthreads();
-            // B3a: new row panel X_j = Dinv A_{p,j} (owners of row-panel tiles)
+        };
+        // FP32: the diagonal tile (p, p) -> its inverse, in place and in dv
+        auto invert_diag = [&](int p, T* dv) {
+            if constexpr (sizeof(T) == 4) {
+#pragma unroll
+                for (int q = 0; q < NSLOT; ++q) {
+                    if (factor_tile<R>(q, w) != p * (R + 1)) continue;
+                    float a4[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) a4[t] = tile[q][t];
+                    inv16_acc_f32<0>(a4, li, lk, bad);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        tile[q][t] = a4[t];
+                        dv[(4 * lk + t) * DVL + li] = a4[t];
+                    }
+                }
+            }
+        };
+        auto row_panel = [&](int pn, const T* pr, T* xs, const T* dv) {
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
-                const int idx = q * kFactorWaves + w;
-                if (idx >= NT) continue;
+                const int idx = factor_tile<R>(q, w);
+                if (idx < 0) continue;
                 const int ti = idx / R, tj = idx - ti * R;
                 if (ti != pn || tj == pn) continue;
                 Acc x = Mfma<T>::zero();
@@ -505,15 +589,15 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
 #pragma unroll
                 for (int t = 0; t < 4; ++t) xs[Mfma<T>::row(lane, t) * PRL + 16 * tj + li] = x[t];
             }
-            __syncthreads();
-            // B3b: column panel and rank-16 update of the rest; diagonal tile = Dinv
+        };
+        auto update = [&](int pn, const T* pc, const T* xs, const T* dv, bool set_diag) {
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
-                const int idx = q * kFactorWaves + w;
-                if (idx >= NT) continue;
+                const int idx = factor_tile<R>(q, w);
+                if (idx < 0) continue;
                 const int ti = idx / R, tj = idx - ti * R;
                 if (ti == pn) {
-                    if (tj == pn) {
+                    if (tj == pn && set_diag) {
 #pragma unroll
                         for (int t = 0; t < 4; ++t) tile[q][t] = dv[Mfma<T>::row(lane, t) * DVL + li];
                     }
@@ -537,6 +621,39 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
                     tile[q] = x;
                 }
             }
+        };
+        if constexpr (sizeof(T) == 4) {
+            publish(0, Pc, Pr);
+            invert_diag(0, Dv);
+            __syncthreads();
+            for (int pn = 0; pn < npan; ++pn) {
+                launder();
+                const int buf = pn & 1, nb = buf ^ 1;
+                row_panel(pn, Pr + buf * 16 * PRL, Xs + buf * 16 * PRL, Dv + buf * 16 * DVL);
+                __syncthreads();
+                update(pn, Pc + buf * BP * PCL, Xs + buf * 16 * PRL, Dv + buf * 16 * DVL, false);
+                if (pn + 1 < npan) {
+                    publish(pn + 1, Pc + nb * BP * PCL, Pr + nb * 16 * PRL);
+                    invert_diag(pn + 1, Dv + nb * 16 * DVL);
+                }
+                __syncthreads();
+            }
+        } else {
+            for (int pn = 0; pn < npan; ++pn) {
+                launder();
+                const int buf = pn & 1;
+                T* pc = Pc + buf * BP * PCL;
+                T* pr = Pr + buf * 16 * PRL;
+                T* xs = Xs + buf * 16 * PRL;
+                T* dv = Dv + buf * 16 * DVL;
+                publish(pn, pc, pr);
+                __syncthreads();
+                if (w == 0) inv16_wave<T, PCL, DVL>(pc + 16 * pn * PCL, dv, bad);
+                __syncthreads();
+                row_panel(pn, pr, xs, dv);
+                __syncthreads();
+                update(pn, pc, xs, dv, true);
+            }
         }
         __syncthreads();   // panel buffers done: Es may be rewritten
         launder();
@@ -544,8 +661,8 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
         // the sweep's MFMA operand order
 #pragma unroll
         for (int q = 0; q < NSLOT; ++q) {
-            const int idx = q * kFactorWaves + w;
-            if (idx >= NT) continue;
+            const int idx = factor_tile<R>(q, w);
+            if (idx < 0) continue;
             const int ti = idx / R, tj = idx - ti * R;
 #pragma unroll
             for (int t = 0; t < 4; ++t) Es[(16 * ti + Mfma<T>::row(lane, t)) * LDE + 16 * tj + li] = tile[q][t];
