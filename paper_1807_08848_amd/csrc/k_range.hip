@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kThreads) void gram_partial_kernel(const PatchDesc*
 
 // sum of the chunk partials of patch p into G (LDS, leading dimension ld), fixed order
 __device__ void sum_partials(const double* __restrict__ part, int p, int maxrc, int nch, int n, double* G, int ld = kRfMax) {
-    for (int o = threadIdx.x; o < n * n; o += kThreads) {
+    for (int o = threadIdx.x; o < n * n; o += blockDim.x) {
         const int i = o / n, j = o % n;
         double s = 0.0;
         for (int ch = 0; ch < nch; ++ch) s += part[((int64_t)p * maxrc + ch) * kSmall + i * kRfMax + j];
@@ -116,33 +116,50 @@ __device__ __forceinline__ void rr_pair(int i, int st, int nm1, int& a, int& b) 
 // One workgroup per patch: G = sum of partials, cyclic Jacobi (round-robin
 // pairs, two-sided updates on 2x2 blocks), eigenvalues sorted descending,
 // singular values, relative gap, and B = V[:, :k] / sigma -> small[p] (s x k).
-__global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int p0, const double* __restrict__ part, int maxrc,
-                                                       double* __restrict__ small, double* __restrict__ sv_all,
-                                                       double* __restrict__ gap, int32_t* flags) {
+// In a round, thread (i, i2) (pairs i, i2 < n/2, i2 padded to a power of two
+// P2 <= 32, so that the threads of one i lie in one wave) owns the 2x2 block
+// (pair i, pair i2) of G and rows i2 and i2 + n/2 of V in the two columns of
+// pair i.  It forms the rotation of pair i2 itself and takes that of pair i
+// from the lane of its group with i2 = i.  G is double-buffered (a round reads
+// one copy and writes the other), so one barrier per round suffices.
+constexpr int kEigMaxThreads = (kRfMax / 2) * 32;
+
+int eig_threads(int max_s) {
+    const int np2 = (max_s + (max_s & 1)) / 2;
+    int p2 = 1;
+    while (p2 < np2) p2 *= 2;
+    return std::max(64, (np2 * p2 + 63) / 64 * 64);
+}
+
+__global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(const PatchDesc* pd, int p0, const double* __restrict__ part, int maxrc,
+                                                             double* __restrict__ small, double* __restrict__ sv_all,
+                                                             double* __restrict__ gap, int32_t* flags) {
     // G and V with an odd leading dimension: a wave's column accesses
     // (V[j][a] over rows j) fall on distinct LDS banks
     constexpr int LDG = kRfMax + 1;
-    __shared__ double G[kRfMax * LDG];
+    __shared__ double Gb[2][kRfMax * LDG];
     __shared__ double V[kRfMax * LDG];
-    __shared__ double cs[kRfMax / 2], sn[kRfMax / 2], tn[kRfMax / 2];
     __shared__ int perm[kRfMax];
     __shared__ double lam[kRfMax];
     __shared__ int rot;
     const int p = p0 + blockIdx.x;
     const PatchDesc P = pd[p];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nth = blockDim.x;
     const int s = P.s, k = P.ncols;
     const int nch = (P.nrows + kRowChunk - 1) / kRowChunk;
-    for (int o = tid; o < kRfMax * LDG; o += kThreads) {
-        G[o] = 0.0;
+    for (int o = tid; o < kRfMax * LDG; o += nth) {
+        Gb[0][o] = 0.0;
+        Gb[1][o] = 0.0;
         V[o] = (o / LDG == o % LDG) ? 1.0 : 0.0;
     }
     __syncthreads();
-    sum_partials(part, p, maxrc, nch, s, G, LDG);
+    sum_partials(part, p, maxrc, nch, s, Gb[0], LDG);
     const int n = s + (s & 1), np2 = n / 2, nm1 = n - 1;
-    int shp = 0, shn = 0;
-    while ((1 << shp) < np2) ++shp;
-    while ((1 << shn) < n) ++shn;
+    int sh = 0;
+    while ((1 << sh) < np2) ++sh;
+    const int i = tid >> sh, i2 = tid & ((1 << sh) - 1);
+    const bool act = i < np2 && i2 < np2;
+    const int src = (tid & ~((1 << sh) - 1)) + (i & ((1 << sh) - 1));   // lane (i, i2 = i)
     // Sweeps until every rotation of a sweep finds |g_pq| <= 1e-13 sqrt(g_pp g_qq)
     // (relative off-diagonal criterion; the rotation it leaves is below 1e-13
     // over the relative gap, and the convergence is quadratic by then) or
@@ -151,72 +168,65 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
     // met between widely separated eigenvalues), at most 30.  The trace is
     // invariant under the rotations.
     double gtr = 0.0;
-    for (int i = 0; i < s; ++i) gtr += G[i * LDG + i];
+    for (int x = 0; x < s; ++x) gtr += Gb[0][x * LDG + x];
     const double floor_abs = 1e-16 * gtr;
     if (tid == 0) rot = 0;
     __syncthreads();
+    int cur = 0;
     for (int sweep = 0; sweep < 30; ++sweep) {
         for (int st = 0; st < nm1; ++st) {
-            if (tid < np2) {
-                const int i = tid;
-                int a, b;
+            const double* Gc = Gb[cur];
+            double* Gn = Gb[cur ^ 1];
+            int a = 0, b = 0, a2 = 0, b2 = 0;
+            double c2 = 1.0, s2 = 0.0, t2 = 0.0;   // rotation of pair i2
+            double g00 = 0.0, g01 = 0.0, g10 = 0.0, g11 = 0.0, va0 = 0.0, vb0 = 0.0, va1 = 0.0, vb1 = 0.0;
+            if (act) {
                 rr_pair(i, st, nm1, a, b);
-                double c = 1.0, t = 0.0;
-                const double apq = G[a * LDG + b], app = G[a * LDG + a], aqq = G[b * LDG + b];
-                if (b < s && apq != 0.0) {
+                rr_pair(i2, st, nm1, a2, b2);
+                const double apq = Gc[a2 * LDG + b2], app = Gc[a2 * LDG + a2], aqq = Gc[b2 * LDG + b2];
+                g00 = Gc[a * LDG + a2];
+                g01 = Gc[a * LDG + b2];
+                g10 = Gc[b * LDG + a2];
+                g11 = Gc[b * LDG + b2];
+                va0 = V[i2 * LDG + a];
+                vb0 = V[i2 * LDG + b];
+                va1 = V[(i2 + np2) * LDG + a];
+                vb1 = V[(i2 + np2) * LDG + b];
+                if (b2 < s && apq != 0.0) {
                     // |g_pq| > 1e-13 sqrt|g_pp g_qq| compared in squares
                     if (apq * apq > 1e-26 * fabs(app * aqq) && fabs(apq) > floor_abs) rot = 1;
                     // the smaller root of t^2 + 2 tau t - 1 = 0, tau = d / (2 g_pq),
                     // d = g_qq - g_pp, with numerator and denominator scaled by 2|g_pq|
                     const double d = aqq - app;
-                    t = (d < 0 ? -2.0 * apq : 2.0 * apq) / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
-                    c = rsqrt(1.0 + t * t);
+                    t2 = (d < 0 ? -2.0 * apq : 2.0 * apq) / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
+                    c2 = rsqrt(1.0 + t2 * t2);
+                    s2 = t2 * c2;
                 }
-                cs[i] = c;
-                sn[i] = t * c;
-                tn[i] = t;
             }
-            __syncthreads();
-            // G <- J^T G J on 2x2 blocks (rows by pair i, columns by pair i2) and
-            // V <- V J (rows j < n, pairs i) over flat work indices, the inner
-            // index padded to a power of two only (no lane idle for s = 32)
-            for (int o = tid; o < (np2 << shp); o += kThreads) {
-                const int i = o >> shp, i2 = o & ((1 << shp) - 1);
-                if (i2 >= np2) continue;
-                int a, b, a2, b2;
-                rr_pair(i, st, nm1, a, b);
-                rr_pair(i2, st, nm1, a2, b2);
-                const double c = cs[i], sv = sn[i], c2 = cs[i2], s2 = sn[i2];
-                const double g00 = G[a * LDG + a2], g01 = G[a * LDG + b2];
-                const double g10 = G[b * LDG + a2], g11 = G[b * LDG + b2];
+            const double c = __shfl(c2, src, 64), sv = __shfl(s2, src, 64), t = __shfl(t2, src, 64);
+            if (act) {
                 if (i == i2) {
                     // the rotated pair's own block: diagonal by the tangent update,
                     // the annihilated entry exactly zero (no rounding residue left
                     // to stall the relative test on widely separated eigenvalues)
-                    const double t = tn[i];
-                    G[a * LDG + a] = g00 - t * g01;
-                    G[b * LDG + b] = g11 + t * g01;
-                    G[a * LDG + b] = 0.0;
-                    G[b * LDG + a] = 0.0;
-                    continue;
+                    Gn[a * LDG + a] = g00 - t * g01;
+                    Gn[b * LDG + b] = g11 + t * g01;
+                    Gn[a * LDG + b] = 0.0;
+                    Gn[b * LDG + a] = 0.0;
+                } else {
+                    const double r00 = c * g00 - sv * g10, r01 = c * g01 - sv * g11;
+                    const double r10 = sv * g00 + c * g10, r11 = sv * g01 + c * g11;
+                    Gn[a * LDG + a2] = c2 * r00 - s2 * r01;
+                    Gn[a * LDG + b2] = s2 * r00 + c2 * r01;
+                    Gn[b * LDG + a2] = c2 * r10 - s2 * r11;
+                    Gn[b * LDG + b2] = s2 * r10 + c2 * r11;
                 }
-                const double r00 = c * g00 - sv * g10, r01 = c * g01 - sv * g11;
-                const double r10 = sv * g00 + c * g10, r11 = sv * g01 + c * g11;
-                G[a * LDG + a2] = c2 * r00 - s2 * r01;
-                G[a * LDG + b2] = s2 * r00 + c2 * r01;
-                G[b * LDG + a2] = c2 * r10 - s2 * r11;
-                G[b * LDG + b2] = s2 * r10 + c2 * r11;
+                V[i2 * LDG + a] = c * va0 - sv * vb0;
+                V[i2 * LDG + b] = sv * va0 + c * vb0;
+                V[(i2 + np2) * LDG + a] = c * va1 - sv * vb1;
+                V[(i2 + np2) * LDG + b] = sv * va1 + c * vb1;
             }
-            for (int o = tid; o < (np2 << shn); o += kThreads) {
-                const int i = o >> shn, j = o & ((1 << shn) - 1);
-                if (j >= n) continue;
-                int a, b;
-                rr_pair(i, st, nm1, a, b);
-                const double c = cs[i], sv = sn[i];
-                const double va = V[j * LDG + a], vb = V[j * LDG + b];
-                V[j * LDG + a] = c * va - sv * vb;
-                V[j * LDG + b] = sv * va + c * vb;
-            }
+            cur ^= 1;
             __syncthreads();
         }
         // uniform decision: every thread reads the flag before it is reset
@@ -226,6 +236,7 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
         __syncthreads();
         if (!r) break;
     }
+    const double* G = Gb[cur];
     // descending order by rank: eigenvalue i goes to the number of eigenvalues
     // above it, ties by index (a NaN ranks as -inf, so the ranks stay a
     // permutation)
@@ -251,7 +262,7 @@ __global__ __launch_bounds__(kThreads) void eig_kernel(const PatchDesc* pd, int 
     }
     __syncthreads();
     double* B = small + (int64_t)p * kSmall;
-    for (int o = tid; o < kSmall; o += kThreads) {
+    for (int o = tid; o < kSmall; o += nth) {
         const int i = o / kRfMax, j = o % kRfMax;
         double v = 0.0;
         if (i < s && j < k) {
@@ -431,7 +442,10 @@ void launch_range(Ctx& c, int p0, int p1) {
     hipStream_t st = c.stream;
     // snapshots: Gram, eigendecomposition, W = Y B
     hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kY, c.Y, c.Q, c.rf_ws, c.rf_part, mrc);
-    hipLaunchKernelGGL(eig_kernel, one, dim3(kThreads), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap, c.dflags);
+    int maxs = 0;
+    for (int p = p0; p < p1; ++p) maxs = std::max(maxs, c.hp[p].s);
+    hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
+                       c.dflags);
     hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kY, (int)kW, c.Y, c.Q, c.rf_ws, c.rf_small);
     // two Cholesky-QR passes: W -> Q -> W
     for (int pass = 0; pass < 2; ++pass) {
