@@ -789,15 +789,16 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
             if (BP % DI == 0 || i < BP) dst[e] = Xl[(uint32_t)(i * sp + ljj)];
         }
     };
+    // every wave loads (the ones past the row tiles a copy of the last tile):
+    // loads outside branches keep the compiler's wait counts exact
     auto load_A = [&](const T* El) {
-        if (mf) {
-            const V* A = reinterpret_cast<const V*>(El + (uint32_t)((rt * 64 + llane) * NKS));
+        const int rtc = rt < R ? rt : R - 1;
+        const V* A = reinterpret_cast<const V*>(El + (uint32_t)((rtc * 64 + llane) * NKS));
 #pragma unroll
-            for (int q = 0; q < NKS / VN; ++q) {
-                const V v = A[q];
+        for (int q = 0; q < NKS / VN; ++q) {
+            const V v = A[q];
 #pragma unroll
-                for (int u = 0; u < VN; ++u) aC[q * VN + u] = v[u];
-            }
+            for (int u = 0; u < VN; ++u) aC[q * VN + u] = v[u];
         }
     };
     auto mfma = [&]() {
@@ -815,20 +816,17 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
     };
     // accumulators -> wbuf, and for a solution line (gdst) to global; with
     // g64 the FP64 iterate of that line (prefetched into pre64) gets += v
-    double pre64[NCT][4], pre64n[NCT][4];
     auto load_64 = [&](const double* g64, double (&dst)[NCT][4]) {
-        const int lli = llane & 15;
-        if (mf) {
+        const int lli = llane & 15, rtc = rt < R ? rt : R - 1;
 #pragma unroll
-            for (int c = 0; c < NCT; ++c)
+        for (int c = 0; c < NCT; ++c)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int i = 16 * rt + Mfma<T>::row(llane, t), j = 16 * c + lli;
-                    dst[c][t] = g64[(uint32_t)(i * sp + j)];
-                }
-        }
+            for (int t = 0; t < 4; ++t) {
+                const int i = 16 * rtc + Mfma<T>::row(llane, t), j = 16 * c + lli;
+                dst[c][t] = g64[(uint32_t)(i * sp + j)];
+            }
     };
-    auto store_acc = [&](T* gdst, double* g64) {
+    auto store_acc = [&](T* gdst, double* g64, const double (&pre64)[NCT][4]) {
         const int lli = llane & 15;
         if (mf) {
 #pragma unroll
@@ -860,49 +858,56 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         }
     };
 
+    // Register sets of prefetched loads alternate between consecutive steps
+    // (the step body is instantiated twice per loop trip), so that no copy of
+    // a register with a load in flight makes the wave wait for it early.
+    double nopre[NCT][4] = {};
     if constexpr (PHASE == 0) {
         // ---- forward half: lines ln0, ln0 + dir, ...; the last one couples into m
         const int nst = half == 0 ? m : nl - 1 - m;
         const int ln0 = half == 0 ? 0 : nl - 1;
         const bool low = half == 0;   // top: Low_{l+1} (line below from above); bottom: Up_{l-1}
+        T rvA[RPT], rvB[RPT];
         launder();
         if (nst <= 0) {
             // no line in this half: t_top = r_m, t_bot = 0
-            if (half == 0) load_line(X + m * lstride, rv);
+            if (half == 0) load_line(X + m * lstride, rvA);
 #pragma unroll
             for (int e = 0; e < RPT; ++e) {
                 const int i = li0 + e * DI;
-                if (BP % DI == 0 || i < BP) TWh[(uint32_t)(i * sp + ljj)] = (half == 0 && i < b) ? rv[e] : T(0);
+                if (BP % DI == 0 || i < BP) TWh[(uint32_t)(i * sp + ljj)] = (half == 0 && i < b) ? rvA[e] : T(0);
             }
             return;
         }
         // step k works on line ln = ln0 + dir k and its successor nx = ln + dir
         // (m after the last step); the successor's right-hand side r_nx and the
-        // shared cell row are loaded one step ahead, E_nx during the step
+        // shared cell row are loaded during the step before, after its products
+        // (so that the products' operand waits never cover them), E_nx likewise
         auto sub_of = [&](int k) { return k + 1 < nst || half == 0; };   // the top's last step carries r_m
-        load_line(X + ln0 * lstride, rv);                 // y_{ln0} = r_{ln0}
+        load_line(X + ln0 * lstride, rvA);                 // y_{ln0} = r_{ln0}
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
             const int i = li0 + e * DI;
-            if (BP % DI == 0 || i < BP) ybuf[i * NSC + ljj] = rv[e];
+            if (BP % DI == 0 || i < BP) ybuf[i * NSC + ljj] = rvA[e];
         }
         load_A(E + (int64_t)ln0 * BP * BP);
-        if (sub_of(0)) load_line(X + (ln0 + dir) * lstride, rv);
-        if (KIND == kElliptic && tid <= b) crow = aL[(dir > 0 ? ln0 + 1 : ln0) * L + tid];
+        double crA = 0.0, crB = 0.0;
+        if (sub_of(0)) load_line(X + (ln0 + dir) * lstride, rvA);
+        if (KIND == kElliptic) crA = aL[(dir > 0 ? ln0 + 1 : ln0) * L + min(tid, b)];
         lds_barrier();
-        for (int k = 0; k < nst; ++k) {
+        auto step = [&](int k, T (&rc)[RPT], T (&rn)[RPT], double& cc, double& cn) {
             launder();
             const int ln = ln0 + dir * k, nx = ln + dir;
             const bool more = k + 1 < nst;
             const bool sub = sub_of(k);
-            T rvn[RPT];
-            double crown = 0.0;
-            if (more && sub_of(k + 1)) load_line(X + (nx + dir) * lstride, rvn);          // r of the next step
-            if (KIND == kElliptic && more && tid <= b) crown = aL[(dir > 0 ? nx + 1 : nx) * L + tid];
             mfma();                                                                   // w = E_ln y_ln
-            if (more) load_A(E + (int64_t)nx * BP * BP);
-            store_acc(nullptr, nullptr);
-            if (KIND == kElliptic && tid <= b) craw[tid] = crow * (-1.0 / 3.0);
+            // r of the next step, its cell row and E (unconditional, clamped to
+            // lines that exist when there is no next step)
+            load_line(X + ((more && sub_of(k + 1)) ? nx + dir : nx) * lstride, rn);
+            if (KIND == kElliptic) cn = aL[(more ? (dir > 0 ? nx + 1 : nx) : (dir > 0 ? ln + 1 : ln)) * L + min(tid, b)];
+            load_A(E + (int64_t)(more ? nx : ln) * BP * BP);
+            store_acc(nullptr, nullptr, nopre);
+            if (KIND == kElliptic && tid <= b) craw[tid] = cc * (-1.0 / 3.0);
             lds_barrier();
             T* dst = more ? X + nx * lstride : TWh;
 #pragma unroll
@@ -910,16 +915,17 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
                 const int i = li0 + e * DI;
                 if (BP % DI == 0 || i < BP) {
                     const double cw = couple(wbuf, i, ljj, low);
-                    const double v = sub ? (double)rv[e] - cw : cw;
+                    const double v = sub ? (double)rc[e] - cw : cw;
                     const T y = i < b ? (T)v : T(0);
                     dst[(uint32_t)(i * sp + ljj)] = y;
                     if (more) ybuf[i * NSC + ljj] = y;
                 }
             }
-#pragma unroll
-            for (int e = 0; e < RPT; ++e) rv[e] = rvn[e];
-            crow = crown;
             lds_barrier();
+        };
+        for (int k = 0; k < nst; k += 2) {
+            step(k, rvA, rvB, crA, crB);
+            if (k + 1 < nst) step(k + 1, rvB, rvA, crB, crA);
         }
     } else {
         // ---- middle line, then the back half; step k solves line
@@ -927,6 +933,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         // shared cell row and (FP32 refinement) the FP64 iterate of the line are
         // loaded one step ahead, E_ln during the step before.
         launder();
+        double pre64[NCT][4] = {}, pre64n[NCT][4] = {};
         load_A(E + (int64_t)m * BP * BP);
         const bool acc64 = X64 && half == 0;   // line m's iterate is updated once, by the top half
         if (acc64) load_64(X64 + m * lstride, pre64);
@@ -949,7 +956,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         lds_barrier();
         mfma();
         if (nst > 0) load_A(E + (int64_t)(m - dir) * BP * BP);        // the first back line, one step ahead
-        store_acc(half == 0 ? X + m * lstride : nullptr, acc64 ? X64 + m * lstride : nullptr);   // x_m (identical in both halves)
+        store_acc(half == 0 ? X + m * lstride : nullptr, acc64 ? X64 + m * lstride : nullptr, pre64);   // x_m (identical in both halves)
         lds_barrier();
         for (int k = 0; k < nst; ++k) {
             launder();
@@ -980,7 +987,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
             lds_barrier();
             mfma();                                                                    // x_ln = E_ln z
             if (more) load_A(E + (int64_t)(ln - dir) * BP * BP);                     // E of the next line
-            store_acc(X + ln * lstride, X64 ? X64 + ln * lstride : nullptr);
+            store_acc(X + ln * lstride, X64 ? X64 + ln * lstride : nullptr, pre64);
 #pragma unroll
             for (int e = 0; e < RPT; ++e) rv[e] = rvn[e];
             crow = crown;
