@@ -77,6 +77,7 @@ typedef int32_t msrs_status;
 #define MSRS_ERR_NOCONV     7   /* iterative refinement above tolerance after ir_max_iters */
 #define MSRS_ERR_RANK       8   /* sketch rank below the requested rank k */
 #define MSRS_ERR_BUSY       9   /* no free online slot */
+#define MSRS_ERR_IO        10   /* a basis file could not be written or read, or is not one */
 
 #define MSRS_KIND_ELLIPTIC_Q1 0
 #define MSRS_KIND_KINETIC_DO  1
@@ -281,6 +282,30 @@ msrs_status msrs_copy_results(msrs_handle h, double* Y_out_dev, double* Q_out_de
  * Full-basis patches hold the identity.  Errors: ARG, STATE.
  */
 msrs_status msrs_copy_omega(msrs_handle h, double* omega_out_dev);
+
+/*
+ * Keep the product of the offline stage (the call summary of the method,
+ * Alg. 1: the local bases are computed once and reused by every online
+ * solve) in a file, and make a handle of it again later.
+ *
+ * msrs_save writes the problem description, the coefficient field, the bases
+ * Q, the singular values and the per-patch gaps and residuals of handle h
+ * to path (created or truncated): a little-endian binary file with an
+ * 8-byte magic, a version and a 64-bit FNV-1a checksum over everything after
+ * the magic.  It synchronizes the handle's stream.  Errors: ARG (NULL
+ * argument), STATE (no range finder yet, or the handle is held by a
+ * server), IO (the file cannot be written), HIP.
+ *
+ * msrs_load reads such a file and creates a new handle on stream (as
+ * msrs_create, HBM budget unbounded) that holds the bases and the coefficient
+ * field: msrs_assemble_coarse and msrs_solve_global may follow at once; the
+ * offline calls start over from msrs_assemble_patch.  The caller destroys
+ * the handle.  Errors: ARG (NULL argument), IO (unreadable file, wrong magic
+ * or version, sizes that do not match the description, checksum mismatch),
+ * and those of msrs_create.  *out is NULL on failure.
+ */
+msrs_status msrs_save(msrs_handle h, const char* path);
+msrs_status msrs_load(msrs_handle* out, const char* path, void* stream);
 
 /* Requests per msrs_solve_global call at most (1..4096, default 64). */
 msrs_status msrs_set_max_batch(msrs_handle h, int32_t max_batch);

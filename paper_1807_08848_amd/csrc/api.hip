@@ -347,6 +347,55 @@ void drop_graph(Ctx* c) {
 }
 }  // namespace
 
+// ---- basis files
+namespace {
+constexpr char kBasisMagic[8] = {'M', 'S', 'R', 'S', 'B', 'A', 'S', '1'};
+constexpr uint32_t kBasisVersion = 1;
+
+// FNV-1a (64-bit) over a byte range, continuing from h
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+struct BasisWriter {
+    FILE* f;
+    uint64_t h = 1469598103934665603ull;
+    bool ok = true;
+    void put(const void* p, size_t n) {
+        if (ok && n && fwrite(p, 1, n, f) != n) ok = false;
+        h = fnv1a(h, p, n);
+    }
+    template <class V> void val(const V& v) { put(&v, sizeof(v)); }
+};
+
+struct BasisReader {
+    FILE* f;
+    uint64_t h = 1469598103934665603ull;
+    bool ok = true;
+    void get(void* p, size_t n) {
+        if (ok && n && fread(p, 1, n, f) != n) ok = false;
+        if (ok) h = fnv1a(h, p, n);
+    }
+    template <class V> V val() {
+        V v{};
+        get(&v, sizeof(v));
+        return v;
+    }
+};
+
+struct FileGuard {
+    FILE* f;
+    ~FileGuard() {
+        if (f) fclose(f);
+    }
+};
+}  // namespace
+
 // ---------------------------------------------------------------- ABI
 extern "C" {
 
@@ -597,6 +646,138 @@ msrs_status msrs_copy_results(msrs_handle h, double* Y_out_dev, double* Q_out_de
     } catch (const HipError& e) {
         return hip_fail(c, e);
     }
+    return MSRS_OK;
+}
+
+
+msrs_status msrs_save(msrs_handle h, const char* path) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (!path) return fail(c, MSRS_ERR_ARG, "path is NULL");
+    if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
+    if (!c->ranged) return fail(c, MSRS_ERR_STATE, "msrs_range_finder must come first");
+    try {
+        const int64_t ncoef = c->kind == kElliptic ? (int64_t)c->N * c->N : c->N;
+        std::vector<double> coef(ncoef), Q(c->Q_total), sv(c->sv_total), gp(2 * c->n_patches);
+        MSRS_HIP_CHECK(hipMemcpyAsync(coef.data(), c->coef_copy, ncoef * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        MSRS_HIP_CHECK(hipMemcpyAsync(Q.data(), c->Q, Q.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        MSRS_HIP_CHECK(hipMemcpyAsync(sv.data(), c->sv, sv.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        MSRS_HIP_CHECK(hipMemcpyAsync(gp.data(), c->gap, gp.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        MSRS_HIP_CHECK(hipStreamSynchronize(c->stream));
+        FileGuard g{fopen(path, "wb")};
+        if (!g.f) return fail(c, MSRS_ERR_IO, std::string("cannot open for writing: ") + path);
+        if (fwrite(kBasisMagic, 1, sizeof(kBasisMagic), g.f) != sizeof(kBasisMagic))
+            return fail(c, MSRS_ERR_IO, std::string("write failed: ") + path);
+        BasisWriter w{g.f};
+        w.val(kBasisVersion);
+        w.val<int32_t>(c->kind == kElliptic ? MSRS_KIND_ELLIPTIC_Q1 : MSRS_KIND_KINETIC_DO);
+        w.val<int32_t>(c->N);
+        w.val<int32_t>(c->M);
+        w.val<int32_t>(c->s);
+        w.val<int32_t>(c->k);
+        w.val<int32_t>(c->prec);
+        w.val<int32_t>(c->ir_max);
+        w.val<int32_t>(c->nv);
+        w.val<uint64_t>(c->seed);
+        w.val<double>(c->ir_tol);
+        w.val<double>(c->eps);
+        w.val<uint32_t>(c->flags);
+        w.val<int32_t>(c->last_ir_iters);
+        w.val<int32_t>((int32_t)c->overlap.size());
+        w.put(c->overlap.data(), c->overlap.size() * sizeof(int32_t));
+        w.val<int64_t>(ncoef);
+        w.val<int64_t>(c->Q_total);
+        w.val<int64_t>(c->sv_total);
+        w.val<int64_t>((int64_t)gp.size());
+        w.put(coef.data(), coef.size() * sizeof(double));
+        w.put(Q.data(), Q.size() * sizeof(double));
+        w.put(sv.data(), sv.size() * sizeof(double));
+        w.put(gp.data(), gp.size() * sizeof(double));
+        const uint64_t sum = w.h;
+        if (!w.ok || fwrite(&sum, 1, sizeof(sum), g.f) != sizeof(sum) || fflush(g.f) != 0)
+            return fail(c, MSRS_ERR_IO, std::string("write failed: ") + path);
+    } catch (const HipError& e) {
+        return hip_fail(c, e);
+    } catch (const std::bad_alloc&) {
+        return fail(c, MSRS_ERR_OOM, "host allocation failed");
+    }
+    return MSRS_OK;
+}
+
+msrs_status msrs_load(msrs_handle* out, const char* path, void* stream) {
+    if (!out) return fail(nullptr, MSRS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!path) return fail(nullptr, MSRS_ERR_ARG, "path is NULL");
+    const std::string where = std::string(": ") + path;
+    FileGuard g{fopen(path, "rb")};
+    if (!g.f) return fail(nullptr, MSRS_ERR_IO, "cannot open for reading" + where);
+    char magic[sizeof(kBasisMagic)];
+    if (fread(magic, 1, sizeof(magic), g.f) != sizeof(magic) || std::memcmp(magic, kBasisMagic, sizeof(magic)))
+        return fail(nullptr, MSRS_ERR_IO, "not a basis file" + where);
+    BasisReader r{g.f};
+    if (r.val<uint32_t>() != kBasisVersion || !r.ok) return fail(nullptr, MSRS_ERR_IO, "unsupported basis file version" + where);
+    msrs_problem_desc d{};
+    d.kind = r.val<int32_t>();
+    d.n_cells = r.val<int32_t>();
+    d.M = r.val<int32_t>();
+    d.n_samples = r.val<int32_t>();
+    d.rank = r.val<int32_t>();
+    d.precision = r.val<int32_t>();
+    d.ir_max_iters = r.val<int32_t>();
+    d.n_vel = r.val<int32_t>();
+    d.seed = r.val<uint64_t>();
+    d.ir_tol = r.val<double>();
+    d.eps = r.val<double>();
+    d.flags = r.val<uint32_t>();
+    const int32_t ir_iters = r.val<int32_t>();
+    const int32_t nov = r.val<int32_t>();
+    if (!r.ok || nov < 1 || nov > (1 << 20)) return fail(nullptr, MSRS_ERR_IO, "truncated or corrupt header" + where);
+    std::vector<int32_t> ov(nov);
+    r.get(ov.data(), ov.size() * sizeof(int32_t));
+    d.overlap = ov.data();
+    const int64_t ncoef = r.val<int64_t>(), nQ = r.val<int64_t>(), nsv = r.val<int64_t>(), ngp = r.val<int64_t>();
+    if (!r.ok) return fail(nullptr, MSRS_ERR_IO, "truncated or corrupt header" + where);
+    const int64_t expect_ov = d.kind == MSRS_KIND_ELLIPTIC_Q1 ? (int64_t)d.M * d.M : d.M;
+    const int64_t expect_coef = d.kind == MSRS_KIND_ELLIPTIC_Q1 ? (int64_t)d.n_cells * d.n_cells : d.n_cells;
+    if (nov != expect_ov || ncoef != expect_coef)
+        return fail(nullptr, MSRS_ERR_IO, "sizes do not match the description" + where);
+    msrs_handle h = nullptr;
+    const msrs_status cst = msrs_create(&h, &d, stream, 0);
+    if (cst != MSRS_OK) return cst;
+    Ctx* c = h;
+    if (nQ != c->Q_total || nsv != c->sv_total || ngp != 2LL * c->n_patches) {
+        msrs_destroy(h);
+        return fail(nullptr, MSRS_ERR_IO, "sizes do not match the description" + where);
+    }
+    try {
+        std::vector<double> coef(ncoef), Q(nQ), sv(nsv), gp(ngp);
+        r.get(coef.data(), coef.size() * sizeof(double));
+        r.get(Q.data(), Q.size() * sizeof(double));
+        r.get(sv.data(), sv.size() * sizeof(double));
+        r.get(gp.data(), gp.size() * sizeof(double));
+        const uint64_t sum = r.h;
+        uint64_t stored = 0;
+        if (!r.ok || fread(&stored, 1, sizeof(stored), g.f) != sizeof(stored) || stored != sum) {
+            msrs_destroy(h);
+            return fail(nullptr, MSRS_ERR_IO, "truncated file or checksum mismatch" + where);
+        }
+        MSRS_HIP_CHECK(hipMemcpyAsync(c->coef_copy, coef.data(), ncoef * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        MSRS_HIP_CHECK(hipMemcpyAsync(c->Q, Q.data(), nQ * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        MSRS_HIP_CHECK(hipMemcpyAsync(c->sv, sv.data(), nsv * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        MSRS_HIP_CHECK(hipMemcpyAsync(c->gap, gp.data(), ngp * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        MSRS_HIP_CHECK(hipStreamSynchronize(c->stream));
+    } catch (const HipError& e) {
+        msrs_destroy(h);
+        return fail(nullptr, e.e == hipErrorOutOfMemory ? MSRS_ERR_OOM : MSRS_ERR_HIP, std::string("HIP: ") + e.what);
+    } catch (const std::bad_alloc&) {
+        msrs_destroy(h);
+        return fail(nullptr, MSRS_ERR_OOM, "host allocation failed");
+    }
+    c->last_ir_iters = ir_iters;
+    c->assembled = c->sampled = false;
+    c->ranged = true;
+    c->coarse_ready = false;
+    *out = h;
     return MSRS_OK;
 }
 

@@ -23,9 +23,9 @@ import torch  # noqa: E402,F401
 
 _lib = C.CDLL(LIB_PATH)
 
-OK, ERR_ARG, ERR_STATE, ERR_OOM, ERR_HIP, ERR_NO_DEVICE, ERR_NOT_SPD, ERR_NOCONV, ERR_RANK, ERR_BUSY = range(10)
+OK, ERR_ARG, ERR_STATE, ERR_OOM, ERR_HIP, ERR_NO_DEVICE, ERR_NOT_SPD, ERR_NOCONV, ERR_RANK, ERR_BUSY, ERR_IO = range(11)
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_STATE", 3: "ERR_OOM", 4: "ERR_HIP", 5: "ERR_NO_DEVICE",
-                6: "ERR_NOT_SPD", 7: "ERR_NOCONV", 8: "ERR_RANK", 9: "ERR_BUSY"}
+                6: "ERR_NOT_SPD", 7: "ERR_NOCONV", 8: "ERR_RANK", 9: "ERR_BUSY", 10: "ERR_IO"}
 KIND_ELLIPTIC_Q1, KIND_KINETIC_DO = 0, 1
 PREC_FP64, PREC_FP32_IR = 0, 1
 FLAG_FULL_BASIS_ENDS, FLAG_PER_PATCH_LAUNCH, FLAG_TIMING = 1, 2, 4
@@ -106,6 +106,8 @@ _sig = {
     "msrs_server_destroy": (None, [_H]),
     "msrs_set_max_batch": (C.c_int32, [_H, C.c_int32]),
     "msrs_copy_omega": (C.c_int32, [_H, _P]),
+    "msrs_save": (C.c_int32, [_H, C.c_char_p]),
+    "msrs_load": (C.c_int32, [C.POINTER(_H), C.c_char_p, _P]),
     "msrs_copy_results": (C.c_int32, [_H, _P, _P, _P]),
     "msrs_offline_graph_capture": (C.c_int32, [_H, _P]),
     "msrs_offline_graph_launch": (C.c_int32, [_H]),
@@ -185,6 +187,22 @@ class Problem:
     def _check(self, st):
         if st != OK:
             raise MsrsError(st, _lib.msrs_last_error(self.h).decode())
+
+    def save(self, path):
+        """Write the offline product (bases, singular values, coefficients) to a basis file."""
+        self._check(_lib.msrs_save(self.h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path, stream=None):
+        """A handle made from a basis file, ready for assemble_coarse / solve_global."""
+        h = _H()
+        st = _lib.msrs_load(C.byref(h), os.fsencode(path), _stream(stream))
+        if st != OK:
+            raise MsrsError(st, _lib.msrs_last_error(None).decode())
+        obj = cls.__new__(cls)
+        obj.h = h
+        obj.desc = None
+        return obj
 
     def assemble_patch(self, coef):
         self._check(_lib.msrs_assemble_patch(self.h, _ptr(coef)))

@@ -1,0 +1,111 @@
+"""Basis files (msrs_save / msrs_load): the product of the offline stage kept
+on disk and made into a handle again.
+
+CPU: the loader rejects files it cannot trust (missing, foreign, other
+version, truncated, inconsistent sizes) before any device work.  GPU: a
+loaded handle holds the same bases and statistics, and its online solves
+equal those of the handle that computed the bases, bit for bit; one flipped
+byte in the data fails the checksum.
+"""
+import ctypes as C
+import struct
+
+import numpy as np
+import pytest
+
+MAGIC = b"MSRSBAS1"
+
+
+def _header(version=1, kind=0, n_cells=128, M=4, s=10, k=6, prec=1, ir_max=30, nv=0, seed=2, tol=1e-10, eps=1.0,
+            flags=0, ir_iters=3, overlap=None, counts=(128 * 128, 0, 0, 0)):
+    ov = [8] * (M * M) if overlap is None else overlap
+    b = struct.pack("<I8iQddIii", version, kind, n_cells, M, s, k, prec, ir_max, nv, seed, tol, eps, flags, ir_iters,
+                    len(ov))
+    b += struct.pack(f"<{len(ov)}i", *ov)
+    b += struct.pack("<4q", *counts)
+    return MAGIC + b
+
+
+@pytest.mark.parametrize("content,msg", [
+    (None, "cannot open"),
+    (b"NOTABASI" + bytes(64), "not a basis file"),
+    (MAGIC[:5], "not a basis file"),
+    (lambda: _header(version=2), "unsupported basis file version"),
+    (lambda: _header()[:30], "truncated or corrupt header"),
+    (lambda: _header(overlap=[8] * 9), "sizes do not match"),
+    (lambda: _header(counts=(64 * 64, 0, 0, 0)), "sizes do not match"),
+])
+def test_load_rejects_files_it_cannot_trust(tmp_path, content, msg):
+    from paper_1807_08848_amd import msrs
+    path = tmp_path / "bases.msrs"
+    if content is not None:
+        path.write_bytes(content() if callable(content) else content)
+    with pytest.raises(msrs.MsrsError) as e:
+        msrs.Problem.load(str(path))
+    assert e.value.status == msrs.ERR_IO and msg in str(e.value)
+
+
+def test_save_and_load_reject_null_arguments():
+    from paper_1807_08848_amd import msrs
+    L = msrs.lib
+    assert L.msrs_save(None, b"bases.msrs") == msrs.ERR_ARG
+    assert L.msrs_load(None, b"bases.msrs", None) == msrs.ERR_ARG
+    out = C.c_void_p()
+    assert L.msrs_load(C.byref(out), None, None) == msrs.ERR_ARG
+    assert not out.value
+
+
+@pytest.mark.gpu
+def test_loaded_bases_solve_like_the_original(tmp_path):
+    import torch
+    import synth
+    from synth import configs
+    from paper_1807_08848_amd import msrs
+    from gpu_cases import resident
+
+    cfg = configs.small_elliptic(N=64, M=4, delta=4, s=12, k=8)
+    pr = resident(cfg, msrs.PREC_FP32_IR)
+    dev = torch.device("cuda:0")
+    path = str(tmp_path / "bases.msrs")
+    try:
+        pr.save(path)
+        L = pr.layout()
+        f = torch.tensor(synth.fourier_boundary(cfg["N"], range(5)), device=dev)
+        u0 = torch.empty((5, L.n_nodes), device=dev, dtype=torch.float64)
+        pr.solve_global(f, u0)
+        Q0 = torch.empty(L.Q_total, device=dev, dtype=torch.float64)
+        sv0 = torch.empty(L.sv_total, device=dev, dtype=torch.float64)
+        pr.copy_results(None, Q0, sv0)
+        st0 = pr.stats()
+
+        ld = msrs.Problem.load(path)
+        try:
+            L1 = ld.layout()
+            assert (L1.Q_total, L1.sv_total, L1.n_nodes, L1.n_bdry) == (L.Q_total, L.sv_total, L.n_nodes, L.n_bdry)
+            Q1 = torch.empty_like(Q0)
+            sv1 = torch.empty_like(sv0)
+            ld.copy_results(None, Q1, sv1)
+            torch.cuda.synchronize()
+            assert torch.equal(Q0, Q1) and torch.equal(sv0, sv1)
+            st1 = ld.stats()
+            assert st1.ir_iters == st0.ir_iters and st1.min_rel_gap == st0.min_rel_gap
+            with pytest.raises(msrs.MsrsError) as e:     # the factor is not part of the file
+                ld.sample_local_solutions()
+            assert e.value.status == msrs.ERR_STATE
+            ld.assemble_coarse()
+            u1 = torch.empty_like(u0)
+            ld.solve_global(f, u1)
+            torch.cuda.synchronize()
+            assert torch.equal(u0, u1)
+        finally:
+            ld.close()
+
+        raw = bytearray(open(path, "rb").read())
+        raw[len(raw) // 2] ^= 0x40
+        bad = tmp_path / "flipped.msrs"
+        bad.write_bytes(bytes(raw))
+        with pytest.raises(msrs.MsrsError) as e:
+            msrs.Problem.load(str(bad))
+        assert e.value.status == msrs.ERR_IO and "checksum" in str(e.value)
+    finally:
+        pr.close()
