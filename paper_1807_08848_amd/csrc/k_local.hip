@@ -116,7 +116,7 @@ __device__ __forceinline__ void partial_column_sums(double ssum, const LineMap& 
     __syncthreads();
     red[threadIdx.x] = m.active ? ssum : 0.0;
     __syncthreads();
-    if (threadIdx.x < sp) {
+    if ((int)threadIdx.x < sp) {
         double s = 0.0;
         for (int r = 0; r < m.rows; ++r) s += red[r * sp + threadIdx.x];
         out[threadIdx.x] = s;

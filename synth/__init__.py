@@ -23,6 +23,7 @@ __all__ = [
     "cell_centres", "periodic_coefficient", "lognormal_coefficient",
     "overlap_draw", "global_boundary_nodes", "dirichlet_sin_cos",
     "fourier_boundary", "kinetic_sigma", "gaussian_matrix", "layered_coefficient",
+    "two_scale_coefficient", "high_contrast_coefficient", "dirichlet_sine",
 ]
 
 
@@ -35,6 +36,32 @@ def periodic_coefficient(N: int, eps: float = 1.0 / 16.0) -> np.ndarray:
     """a(x,y) = 1.1 + sin(2 pi x/eps) sin(2 pi y/eps) at the N*N element centroids (flat, j-major)."""
     xc = cell_centres(N)
     a = 1.1 + np.sin(2 * np.pi * xc[None, :] / eps) * np.sin(2 * np.pi * xc[:, None] / eps)
+    return np.ascontiguousarray(a.reshape(-1))
+
+
+def two_scale_coefficient(N: int, eps: float = 2.0 ** -4) -> np.ndarray:
+    """The two-scale medium of the paper's elliptic test (Sec. 5.1, media
+    equation) at the N*N element centroids (flat, j-major): a smooth O(1)
+    part 2 + sin(2 pi x) cos(2 pi y) plus two quotients of eps-periodic
+    trigonometric terms, each bounded away from zero and infinity."""
+    xc = cell_centres(N)
+    x, y = xc[None, :], xc[:, None]
+    k = 2 * np.pi / eps
+    a = (2 + np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+         + (2 + 1.8 * np.sin(k * x)) / (2 + 1.8 * np.cos(k * y))
+         + (2 + np.sin(k * y)) / (2 + 1.8 * np.cos(k * x)))
+    return np.ascontiguousarray(a.reshape(-1))
+
+
+def high_contrast_coefficient(N: int, contrast: float = 1000.0) -> np.ndarray:
+    """The high-contrast medium of the paper's comparison test (Sec. 5.2):
+    1 everywhere plus `contrast` on the set where
+    x cos(100 r) <= y - 1/2, r the distance to (1/2, 1/2), at the N*N element
+    centroids (flat, j-major)."""
+    xc = cell_centres(N)
+    x, y = xc[None, :], xc[:, None]
+    r = np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2)
+    a = 1.0 + contrast * (x * np.cos(100.0 * r) <= y - 0.5)
     return np.ascontiguousarray(a.reshape(-1))
 
 
@@ -87,6 +114,15 @@ def dirichlet_sin_cos(N: int) -> np.ndarray:
     """phi = sin(2 pi x) + cos(2 pi y) on the 4N global boundary nodes."""
     b = global_boundary_nodes(N) / N
     return np.sin(2 * np.pi * b[:, 0]) + np.cos(2 * np.pi * b[:, 1])
+
+
+def dirichlet_sine(N: int) -> np.ndarray:
+    """A sine over the boundary, phi = sin(pi t / 2) in the perimeter
+    arclength t in [0, 4) (counter-clockwise from (0,0)), on the 4N global
+    boundary nodes: one smooth period around the square (the paper's global
+    elliptic test specifies sine boundary data and nothing more)."""
+    t = np.arange(4 * N, dtype=np.float64) / N
+    return np.sin(np.pi * t / 2)
 
 
 def fourier_boundary(N: int, request_ids, seed: int = 4, n_modes: int = 16) -> np.ndarray:

@@ -8,7 +8,8 @@ from __future__ import annotations
 import numpy as np
 
 from . import (lognormal_coefficient, overlap_draw, periodic_coefficient,
-               dirichlet_sin_cos, kinetic_sigma)
+               dirichlet_sin_cos, kinetic_sigma, two_scale_coefficient, high_contrast_coefficient,
+               dirichlet_sine)
 
 COEF_SEED = 1
 OMEGA_SEED = 2
@@ -52,6 +53,26 @@ def kinetic_slab_4096():
                 coef=kinetic_sigma(Nx), seed=OMEGA_SEED)
 
 
+def elliptic_two_scale_100(k=10):
+    """The paper's elliptic test: h=1/100, 5x5 patches of 20x20 cells, buffered
+    patches concentric with all sides twice as long (10 cells, clipped at the
+    domain), k random samples and rank k (the paper's k_m, no oversampling),
+    two-scale medium eps=2^-4, sine boundary data."""
+    N, M = 100, 5
+    return dict(name=f"elliptic_two_scale_N100_M5_k{k}", kind="elliptic", N=N, M=M,
+                overlap=np.full(M * M, 10, dtype=np.int32), s=k, k=k,
+                coef=two_scale_coefficient(N, 2.0 ** -4), phi=dirichlet_sine(N), seed=OMEGA_SEED)
+
+
+def elliptic_high_contrast_100(k=6):
+    """The paper's high-contrast comparison: h=1/100, 5x5 patches (H=1/5), the
+    same buffers as the two-scale test, k random samples and rank k."""
+    N, M = 100, 5
+    return dict(name=f"elliptic_high_contrast_N100_M5_k{k}", kind="elliptic", N=N, M=M,
+                overlap=np.full(M * M, 10, dtype=np.int32), s=k, k=k,
+                coef=high_contrast_coefficient(N), phi=dirichlet_sine(N), seed=OMEGA_SEED)
+
+
 def small_elliptic(N=32, M=2, delta=4, s=8, k=5, coef="periodic"):
     """Small elliptic case for fast parity tests (several tiles, ragged sizes)."""
     if coef == "periodic":
@@ -68,4 +89,6 @@ WORKLOADS = {
     "elliptic_lognormal_512": elliptic_lognormal_512,
     "elliptic_lognormal_1024": elliptic_lognormal_1024,
     "kinetic_slab_4096": kinetic_slab_4096,
+    "elliptic_two_scale_100": elliptic_two_scale_100,
+    "elliptic_high_contrast_100": elliptic_high_contrast_100,
 }
