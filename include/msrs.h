@@ -89,6 +89,10 @@ typedef int32_t msrs_status;
 #define MSRS_FLAG_FULL_BASIS_ENDS   1u  /* kinetic: full (delta) basis on the two end patches (default on) */
 #define MSRS_FLAG_PER_PATCH_LAUNCH  2u  /* launch every stage once per patch (unbatched reference mode) */
 #define MSRS_FLAG_TIMING            4u  /* record HIP events around every kernel class (msrs_get_stats) */
+/* elliptic: every patch that touches the domain boundary uses no buffer and the
+ * full (delta) basis of its 4 N/M boundary nodes instead of random samples
+ * (needs 4 N/M <= 64); interior patches are sampled as usual */
+#define MSRS_FLAG_FULL_BASIS_BOUNDARY 8u
 
 typedef struct msrs_ctx* msrs_handle;
 

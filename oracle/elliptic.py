@@ -177,19 +177,29 @@ def full_basis_patch(a_flat, N, g) -> np.ndarray:
     return sample_patch(a_flat, N, g, np.eye(nb))
 
 
-def offline(a_flat, N, M, overlap, s, k, seed=2, omegas=None, full_basis=False):
+def offline(a_flat, N, M, overlap, s, k, seed=2, omegas=None, full_basis=False, full_basis_boundary=False):
     """Offline stage over all patches: snapshots Y_m, rank-k bases Q_m and singular values.
 
     omegas: optional list of explicit boundary sample matrices (one per patch);
     default draws them with Philox(seed).  full_basis=True runs DetLocalSolu
     on the unbuffered patches instead and keeps the full Green's matrix.
+    full_basis_boundary=True does so only for the patches that touch the
+    domain boundary (no buffer, Kronecker-delta data at all 4 N/M boundary
+    nodes), with the basis orthonormalized by the range finder at full rank;
+    the interior patches are sampled as usual.
     """
     geo = patch_geometry(N, M, 0 if full_basis else overlap)
+    geo0 = patch_geometry(N, M, 0) if full_basis_boundary else None
     out = []
     for g in geo:
+        on_boundary = g["m1"] in (0, M - 1) or g["m2"] in (0, M - 1)
         if full_basis:
             Y = full_basis_patch(a_flat, N, g)
             Q, sv = Y, None
+        elif full_basis_boundary and on_boundary:
+            g = geo0[g["p"]]
+            Y = full_basis_patch(a_flat, N, g)
+            Q, sv = range_finder(Y, Y.shape[1])
         else:
             om = omegas[g["p"]] if omegas is not None else patch_omega(seed, g, s)
             Y = sample_patch(a_flat, N, g, om)

@@ -78,11 +78,13 @@ void for_patches(Ctx& c, F&& f) {
 
 void build_elliptic(Ctx& c) {
     const int N = c.N, M = c.M, nH = N / M;
+    const bool fbb = (c.flags & MSRS_FLAG_FULL_BASIS_BOUNDARY) != 0;
     int64_t a_off = 0, om_off = 0, x_off = 0, E_off = 0, Y_off = 0, Q_off = 0, sv_off = 0, rn_off = 0, tw_off = 0;
     for (int m2 = 0; m2 < M; ++m2)
         for (int m1 = 0; m1 < M; ++m1) {
             const int p = m2 * M + m1;
-            const int d = c.overlap[p];
+            const bool full = fbb && (m1 == 0 || m1 == M - 1 || m2 == 0 || m2 == M - 1);
+            const int d = full ? 0 : c.overlap[p];
             PatchDesc P{};
             const int x0 = std::max(0, m1 * nH - d), x1 = std::min(N, (m1 + 1) * nH + d);
             const int y0 = std::max(0, m2 * nH - d), y1 = std::min(N, (m2 + 1) * nH + d);
@@ -94,13 +96,13 @@ void build_elliptic(Ctx& c) {
             P.nl = P.Qn - 1;
             P.bp = std::max(16, round16(P.b));
             P.nb = 2 * (P.cx + P.cy);
-            P.s = c.s;
-            P.sp = round16(c.s);
+            P.s = full ? P.nb : c.s;
+            P.sp = round16(P.s);
             P.kx0 = m1 * nH; P.ky0 = m2 * nH; P.nH = nH;
             P.nrows = (nH + 1) * (nH + 1);
-            P.ncols = c.k;
-            P.full = 0;
-            P.sampled = 1;
+            P.ncols = full ? P.nb : c.k;
+            P.full = full ? 1 : 0;
+            P.sampled = full ? 0 : 1;
             P.a_off = a_off; a_off += (int64_t)P.L * P.Qn;
             P.om_off = om_off; om_off += (int64_t)P.nb * P.s;
             P.x_off = x_off; x_off += (int64_t)P.nl * P.bp * P.sp;
@@ -178,6 +180,10 @@ msrs_status validate(const msrs_problem_desc* d, std::string& msg) {
                 if (std::min(cx, cy) - 1 > kMaxLine) { msg = "buffered patch too large: min side must be <= 129 cells"; return MSRS_ERR_ARG; }
             }
         if (d->M < 2) { msg = "elliptic needs M >= 2"; return MSRS_ERR_ARG; }
+        if ((d->flags & MSRS_FLAG_FULL_BASIS_BOUNDARY) && 4 * nH > kMaxSamples) {
+            msg = "full basis on boundary patches needs 4 N/M <= 64 boundary nodes";
+            return MSRS_ERR_ARG;
+        }
     } else {
         if (d->n_vel < 2 || d->n_vel > 32 || (d->n_vel & 1)) { msg = "n_vel must be even, 2..32"; return MSRS_ERR_ARG; }
         if (!(d->eps > 0)) { msg = "eps must be positive"; return MSRS_ERR_ARG; }

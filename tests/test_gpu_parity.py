@@ -272,3 +272,24 @@ def test_offline_graph_replays_match_eager(gpu):
         ref2 = grab()
         assert np.abs(got[0] - ref2[0]).max() <= 1e-12 * np.abs(ref2[0]).max()
         assert not np.allclose(got[0], ref[0])
+
+
+@pytest.mark.parametrize("k", [8, 16])
+def test_elliptic_full_basis_on_boundary_patches(gpu, k):
+    """Boundary patches with the full delta basis and no buffer, interior
+    patches sampled (MSRS_FLAG_FULL_BASIS_BOUNDARY): parity with the oracle's
+    option, and the reduced solution close to the fine solve, falling with k
+    (oracle: 0.107 at k=8, 0.0041 at k=16 on this workload)."""
+    N, M = 64, 4
+    cfg = dict(name="full_basis_boundary", kind="elliptic", N=N, M=M, overlap=np.full(M * M, 8, dtype=np.int32),
+               s=k, k=k, coef=synth.periodic_coefficient(N, 1.0 / 8.0), phi=synth.dirichlet_sin_cos(N), seed=2)
+    out = run(cfg, FP32_IR, phi=cfg["phi"], flags=gpu.FLAG_FULL_BASIS_BOUNDARY)
+    ref = E.offline(cfg["coef"], N, M, cfg["overlap"], k, k, seed=2, full_basis_boundary=True)
+    for p, inf in enumerate(out["infos"]):
+        on_bd = (p % M) in (0, M - 1) or (p // M) in (0, M - 1)
+        assert inf.full_basis == int(on_bd) and inf.n_cols == (4 * (N // M) if on_bd else k)
+    _check_bases(out, ref, 1e-8)
+    u_or = E.online(N, M, ref, cfg["coef"], cfg["phi"])
+    assert E.relative_l2(out["u"][0], u_or) <= 1e-6
+    err = E.relative_l2(out["u"][0], E.global_solve(cfg["coef"], N, cfg["phi"]))
+    assert err < (0.15 if k == 8 else 1e-2)

@@ -225,3 +225,16 @@ def test_reduced_global_error_decreases_with_rank():
         errs.append(e)
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 1e-2
+
+
+def test_full_basis_boundary_option_matches_independent_construction():
+    """The oracle's full_basis_boundary option (delta bases on the boundary
+    patches, range finder at full rank) gives the reduced solution of the
+    construction above (numpy QR of the same Green's matrices)."""
+    N, M = 48, 3
+    a = synth.periodic_coefficient(N, 1.0 / 8.0)
+    phi = synth.dirichlet_sin_cos(N)
+    for k in (4, 10):
+        u1 = E.online(N, M, _boundary_full_offline(a, N, M, 8, k, k, seed=3), a, phi)
+        u2 = E.online(N, M, E.offline(a, N, M, 8, k, k, seed=3, full_basis_boundary=True), a, phi)
+        assert E.relative_l2(u2, u1) < 1e-10
