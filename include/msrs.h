@@ -105,13 +105,17 @@ typedef struct msrs_problem_desc {
     int32_t rank;            /* k, basis columns kept per sampled patch, 1..s */
     int32_t precision;       /* MSRS_PREC_* */
     int32_t ir_max_iters;    /* FP32_IR: refinement iterations at most (0 -> 30) */
-    int32_t n_vel;           /* kinetic: Gauss-Legendre ordinates (even, 2..32) */
+    int32_t n_vel;           /* kinetic: Gauss-Legendre ordinates (even, 2..64) */
     uint64_t seed;           /* Philox key of the device-drawn boundary samples */
     double ir_tol;           /* FP32_IR: stop when every ||r_j||/||rhs_j|| <= ir_tol (0 -> 1e-10) */
     double eps;              /* kinetic: eps of the collision term */
     const int32_t* overlap;  /* host: buffer width in cells per patch (M*M elliptic, M kinetic) */
     uint32_t flags;          /* MSRS_FLAG_* */
     int32_t reserved;
+    double hg_g;             /* kinetic: anisotropy g in (-1, 1) of the Henyey-Greenstein scattering kernel
+                                k(v, v') = (1 - g^2) / (2 (1 + g^2 + 2 g v v')) (Sec. 4, eq. HG); 0: isotropic,
+                                k = 1/2 (eq. def.LL.hom).  The collision term is int k(v,v') f(v') dv' -
+                                int k(v',v) dv' f(v), by Gauss-Legendre quadrature on the ordinates. */
 } msrs_problem_desc;
 
 typedef struct msrs_layout {

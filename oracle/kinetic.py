@@ -34,13 +34,26 @@ def ordinates(nv: int = 32):
     return v, w
 
 
-def assemble(sigma: np.ndarray, eps: float, dx: float, v: np.ndarray, w: np.ndarray):
+def hg_kernel(v: np.ndarray, g: float) -> np.ndarray:
+    """The Henyey-Greenstein scattering kernel of eq. HG on the ordinates:
+    k(v_i, v_j) = (1/2) (1 - g^2) / (1 + g^2 + 2 g v_i v_j)."""
+    return 0.5 * (1 - g * g) / (1 + g * g + 2 * g * np.outer(v, v))
+
+
+def assemble(sigma: np.ndarray, eps: float, dx: float, v: np.ndarray, w: np.ndarray, hg: float = 0.0):
     """Upwind discrete-ordinates operator on n cells; unknown (i,j) -> i*nv + j.
 
     Returns (A, L) with A the n*nv square matrix and L the n*nv x nv lifting
     of the inflow vector [left inflow for v>0 (ascending), right inflow for
     v<0 (ascending)], so that A f = L omega.
+
+    hg != 0 replaces the isotropic collision term by the one of eq. RTE with
+    the kernel of eq. HG, by quadrature on the ordinates: gain
+    sum_j k(v_i, v_j) w_j f_j, loss (sum_j k(v_j, v_i) w_j) f_i, both scaled by
+    sigma_i / eps.
     """
+    if hg != 0.0:
+        return _assemble_hg(sigma, eps, dx, v, w, hg)
     n, nv = sigma.size, v.size
     pos = np.where(v > 0)[0]
     neg = np.where(v < 0)[0]
@@ -69,6 +82,34 @@ def assemble(sigma: np.ndarray, eps: float, dx: float, v: np.ndarray, w: np.ndar
     return A, L
 
 
+def _assemble_hg(sigma, eps, dx, v, w, g):
+    n, nv = sigma.size, v.size
+    k = hg_kernel(v, g)
+    gain = k * w[None, :]                    # gain_ij = k(v_i, v_j) w_j
+    loss = (k * w[:, None]).sum(axis=0)      # loss_i = sum_j k(v_j, v_i) w_j
+    s = sigma / eps
+    blocks = []
+    for i in range(n):
+        D = np.diag(np.abs(v) / dx + s[i] * loss) - s[i] * gain
+        blocks.append(D)
+    A = sp.block_diag(blocks, format="lil")
+    for i in range(n):
+        for j in range(nv):
+            if v[j] > 0 and i > 0:
+                A[i * nv + j, (i - 1) * nv + j] = -v[j] / dx
+            if v[j] < 0 and i < n - 1:
+                A[i * nv + j, (i + 1) * nv + j] = v[j] / dx
+    A = A.tocsr()
+    pos = np.where(v > 0)[0]
+    neg = np.where(v < 0)[0]
+    L = np.zeros((n * nv, nv))
+    for t, j in enumerate(pos):
+        L[0 * nv + j, t] = v[j] / dx
+    for t, j in enumerate(neg):
+        L[(n - 1) * nv + j, len(pos) + t] = -v[j] / dx
+    return A, L
+
+
 def banded(A: sp.spmatrix, l: int, u: int) -> np.ndarray:
     C = A.tocoo()
     ab = np.zeros((l + u + 1, A.shape[0]))
@@ -77,7 +118,7 @@ def banded(A: sp.spmatrix, l: int, u: int) -> np.ndarray:
     return ab
 
 
-def local_solve(sigma: np.ndarray, eps: float, dx: float, v, w, omega: np.ndarray) -> np.ndarray:
+def local_solve(sigma: np.ndarray, eps: float, dx: float, v, w, omega: np.ndarray, hg: float = 0.0) -> np.ndarray:
     """LocalPDESolver for the slab: banded LU solve of A f = L omega for all columns.
 
     Returns the extended solution (n+2, nv, s): cells 0..n-1 in the middle,
@@ -88,7 +129,7 @@ def local_solve(sigma: np.ndarray, eps: float, dx: float, v, w, omega: np.ndarra
     if omega.ndim == 1:
         omega = omega[:, None]
     n, nv = sigma.size, v.size
-    A, L = assemble(sigma, eps, dx, v, w)
+    A, L = assemble(sigma, eps, dx, v, w, hg)
     f = sla.solve_banded((nv, nv), banded(A, nv, nv), L @ omega)
     s = omega.shape[1]
     ext = np.zeros((n + 2, nv, s))
@@ -120,10 +161,10 @@ def restrict(ext: np.ndarray, g: dict) -> np.ndarray:
     return blk.reshape(-1, ext.shape[2])
 
 
-def sample_patch(sigma_all, eps, Nx, nv, g, omega) -> np.ndarray:
+def sample_patch(sigma_all, eps, Nx, nv, g, omega, hg: float = 0.0) -> np.ndarray:
     v, w = ordinates(nv)
     sig = sigma_all[g["x0"]:g["x0"] + g["cx"]]
-    return restrict(local_solve(sig, eps, 1.0 / Nx, v, w, omega), g)
+    return restrict(local_solve(sig, eps, 1.0 / Nx, v, w, omega, hg), g)
 
 
 def patch_omega(seed: int, g: dict, nv: int, s: int) -> np.ndarray:
@@ -131,7 +172,7 @@ def patch_omega(seed: int, g: dict, nv: int, s: int) -> np.ndarray:
 
 
 def offline(sigma_all, eps, Nx, M, overlap, nv, s, k, seed=2, omegas=None, full_basis=False,
-            full_basis_ends=True):
+            full_basis_ends=True, hg: float = 0.0):
     """Offline stage: snapshots and bases per patch.
 
     End patches (m = 0 and m = M-1) use the full basis on the unbuffered
@@ -144,11 +185,11 @@ def offline(sigma_all, eps, Nx, M, overlap, nv, s, k, seed=2, omegas=None, full_
     for g, g0 in zip(geo, geo0):
         end = g["p"] in (0, M - 1)
         if full_basis or (full_basis_ends and end):
-            Y = sample_patch(sigma_all, eps, Nx, nv, g0, np.eye(nv))
+            Y = sample_patch(sigma_all, eps, Nx, nv, g0, np.eye(nv), hg)
             out.append(dict(geo=g0, Y=Y, Q=Y, sv=None, full=True))
         else:
             om = omegas[g["p"]] if omegas is not None else patch_omega(seed, g, nv, s)
-            Y = sample_patch(sigma_all, eps, Nx, nv, g, om)
+            Y = sample_patch(sigma_all, eps, Nx, nv, g, om, hg)
             Q, sv = range_finder(Y, k)
             out.append(dict(geo=g, Y=Y, Q=Q, sv=sv, full=False))
     return out
@@ -216,11 +257,11 @@ def online(M, nv, patches, phi):
     return f[:, 0] if one else f
 
 
-def global_solve(sigma_all, eps, nv, phi) -> np.ndarray:
+def global_solve(sigma_all, eps, nv, phi, hg: float = 0.0) -> np.ndarray:
     """Brute-force fine solve on all cells with the global inflow data (Nx*nv,)."""
     v, w = ordinates(nv)
     Nx = sigma_all.size
-    ext = local_solve(sigma_all, eps, 1.0 / Nx, v, w, phi)
+    ext = local_solve(sigma_all, eps, 1.0 / Nx, v, w, phi, hg)
     return ext[1:Nx + 1].reshape(Nx * nv, -1)[:, 0] if np.ndim(phi) == 1 else ext[1:Nx + 1].reshape(Nx * nv, -1)
 
 

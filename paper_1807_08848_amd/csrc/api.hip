@@ -141,6 +141,7 @@ void build_kinetic(Ctx& c) {
         P.ncols = full ? nv : c.k;
         P.full = full ? 1 : 0;
         P.sampled = full ? 0 : 1;
+        P.hg = c.hg != 0.0 ? 1 : 0;
         P.a_off = a_off; a_off += P.cx;
         P.om_off = om_off; om_off += (int64_t)P.nb * P.s;
         P.x_off = x_off; x_off += (int64_t)P.nl * P.bp * P.sp;
@@ -185,7 +186,8 @@ msrs_status validate(const msrs_problem_desc* d, std::string& msg) {
             return MSRS_ERR_ARG;
         }
     } else {
-        if (d->n_vel < 2 || d->n_vel > 32 || (d->n_vel & 1)) { msg = "n_vel must be even, 2..32"; return MSRS_ERR_ARG; }
+        if (d->n_vel < 2 || d->n_vel > 64 || (d->n_vel & 1)) { msg = "n_vel must be even, 2..64"; return MSRS_ERR_ARG; }
+        if (!(d->hg_g > -1.0 && d->hg_g < 1.0)) { msg = "hg_g must be in (-1, 1)"; return MSRS_ERR_ARG; }
         if (!(d->eps > 0)) { msg = "eps must be positive"; return MSRS_ERR_ARG; }
         if (d->M < 2) { msg = "kinetic needs M >= 2"; return MSRS_ERR_ARG; }
         if (d->n_cells / d->M < 1) { msg = "patch too small"; return MSRS_ERR_ARG; }
@@ -431,6 +433,7 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->ir_max = desc->ir_max_iters > 0 ? desc->ir_max_iters : 30;
         c->ir_tol = desc->ir_tol > 0 ? desc->ir_tol : 1e-10;
         c->eps = desc->kind == MSRS_KIND_KINETIC_DO ? desc->eps : 1.0;
+        c->hg = desc->kind == MSRS_KIND_KINETIC_DO ? desc->hg_g : 0.0;
         c->nv = desc->kind == MSRS_KIND_KINETIC_DO ? desc->n_vel : 0;
         c->seed = desc->seed;
         c->flags = desc->flags;
@@ -505,11 +508,26 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         MSRS_HIP_CHECK(hipMemset(c->x64, 0, c->x_total * sizeof(double)));
         MSRS_HIP_CHECK(hipHostMalloc((void**)&c->hflags, 4 * sizeof(int32_t), hipHostMallocDefault));
         std::memset(c->hflags, 0, 4 * sizeof(int32_t));
-        std::vector<double> vw(2 * std::max(c->nv, 1), 0.0);
+        // kinetic ordinate tables: [v (nv) | w (nv) | lambda (nv) | K (nv x nv)], with
+        // K_ij = k(v_i, v_j) w_j the quadrature of the gain and lambda_i =
+        // sum_j k(v_j, v_i) w_j that of the loss (isotropic: K_ij = w_j / 2, lambda = 1)
+        const int nvt = std::max(c->nv, 1);
+        std::vector<double> vw(3 * nvt + (int64_t)nvt * nvt, 0.0);
         if (c->kind == kKinetic) {
+            const int nv = c->nv;
             std::vector<double> x, w;
-            gauss_legendre(c->nv, x, w);
-            for (int i = 0; i < c->nv; ++i) { vw[i] = x[i]; vw[c->nv + i] = w[i]; }
+            gauss_legendre(nv, x, w);
+            for (int i = 0; i < nv; ++i) { vw[i] = x[i]; vw[nv + i] = w[i]; }
+            const double g = c->hg;
+            auto kern = [&](double a, double b) { return g == 0.0 ? 0.5 : 0.5 * (1 - g * g) / (1 + g * g + 2 * g * a * b); };
+            for (int i = 0; i < nv; ++i) {
+                double lam = 0.0;
+                for (int j = 0; j < nv; ++j) {
+                    vw[3 * nv + (int64_t)i * nv + j] = kern(x[i], x[j]) * w[j];
+                    lam += kern(x[j], x[i]) * w[j];
+                }
+                vw[2 * nv + i] = g == 0.0 ? 1.0 : lam;
+            }
         }
         c->vw = dalloc<double>(*c, (int64_t)vw.size());
         MSRS_HIP_CHECK(hipMemcpy(c->vw, vw.data(), vw.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -687,6 +705,7 @@ msrs_status msrs_save(msrs_handle h, const char* path) {
         w.val<uint64_t>(c->seed);
         w.val<double>(c->ir_tol);
         w.val<double>(c->eps);
+        w.val<double>(c->hg);
         w.val<uint32_t>(c->flags);
         w.val<int32_t>(c->last_ir_iters);
         w.val<int32_t>((int32_t)c->overlap.size());
@@ -734,6 +753,7 @@ msrs_status msrs_load(msrs_handle* out, const char* path, void* stream) {
     d.seed = r.val<uint64_t>();
     d.ir_tol = r.val<double>();
     d.eps = r.val<double>();
+    d.hg_g = r.val<double>();
     d.flags = r.val<uint32_t>();
     const int32_t ir_iters = r.val<int32_t>();
     const int32_t nov = r.val<int32_t>();

@@ -192,6 +192,11 @@ __device__ __forceinline__ double diag_entry(const PatchDesc& P, const double* a
     } else {
         const int nv = P.b;
         const double s = aL[l] * inv_eps;
+        if (P.hg) {
+            double v = -s * vw[3 * nv + i * nv + j];
+            if (i == j) v += fabs(vw[i]) / dx + s * vw[2 * nv + i];
+            return v;
+        }
         double v = -s * 0.5 * vw[nv + j];
         if (i == j) v += fabs(vw[i]) / dx + s;
         return v;
@@ -1023,6 +1028,8 @@ __global__ __launch_bounds__(kSweepThreads) void sweep_kernel(const PatchDesc* p
         switch (P.bp >> 4) {
             case 1: MSRS_SWB(1); break;
             case 2: MSRS_SWB(2); break;
+            case 3: MSRS_SWB(3); break;
+            case 4: MSRS_SWB(4); break;
             default: if (threadIdx.x == 0) raise_flag(flags, 3); break;
         }
         return;
@@ -1098,14 +1105,22 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const PatchDesc* pd,
         const int h = b / 2;
         for (int l = l0 + m.row0; m.active && l < l1; l += m.rows) {
             double rho = 0.0;
-            if (c < P.s)
+            if (c < P.s && !P.hg)
                 for (int j = 0; j < b; ++j) rho += 0.5 * vw[b + j] * xv(l, j);
             const double sg = aL[l] * inv_eps;
             for (int i = 0; i < bp; ++i) {
                 double r = 0.0;
                 if (i < b && c < P.s) {
                     const double vi = vw[i];
-                    double acc = (fabs(vi) / dx + sg) * xv(l, i) - sg * rho;
+                    double acc;
+                    if (P.hg) {
+                        // anisotropic: gain sum_j K_ij f_j, loss lambda_i f_i
+                        double gain = 0.0;
+                        for (int j = 0; j < b; ++j) gain += vw[3 * b + i * b + j] * xv(l, j);
+                        acc = (fabs(vi) / dx + sg * vw[2 * b + i]) * xv(l, i) - sg * gain;
+                    } else {
+                        acc = (fabs(vi) / dx + sg) * xv(l, i) - sg * rho;
+                    }
                     if (vi > 0) acc -= vi / dx * (l > 0 ? xv(l - 1, i) : O[(int64_t)c * P.nb + (i - h)]);
                     if (vi < 0) acc -= -vi / dx * (l < nl - 1 ? xv(l + 1, i) : O[(int64_t)c * P.nb + h + i]);
                     r = -acc;
@@ -1343,8 +1358,8 @@ static void launch_factor_r(Ctx& c, int R, hipStream_t st, const int32_t* plist,
     switch (R) {
         case 1: MSRS_FACTOR(1); break;
         case 2: MSRS_FACTOR(2); break;
-        case 3: if constexpr (KIND == kElliptic) MSRS_FACTOR(3); break;
-        case 4: if constexpr (KIND == kElliptic) MSRS_FACTOR(4); break;
+        case 3: MSRS_FACTOR(3); break;
+        case 4: MSRS_FACTOR(4); break;
         case 5: if constexpr (KIND == kElliptic) MSRS_FACTOR(5); break;
         case 6: if constexpr (KIND == kElliptic) MSRS_FACTOR(6); break;
         case 7: if constexpr (KIND == kElliptic) MSRS_FACTOR(7); break;

@@ -47,6 +47,7 @@ struct PatchDesc {
     int32_t nrows, ncols;     // rows of Y / Q, columns of Q
     int32_t full;             // full (delta) basis: Omega = identity
     int32_t sampled;          // Omega drawn at random (0 for full-basis patches)
+    int32_t hg;               // kinetic: anisotropic (Henyey-Greenstein) scattering, tables in vw
     int64_t a_off;            // aL (doubles)
     int64_t om_off;           // Omega, nb x s column-major
     int64_t x_off;            // line vectors, nl x bp x sp (samples fastest)
@@ -78,6 +79,7 @@ struct Ctx {
     int ir_max = 30;
     double ir_tol = 1e-10;
     double eps = 1.0;
+    double hg = 0.0;          // kinetic: Henyey-Greenstein anisotropy g (0: isotropic)
     uint64_t seed = 0;
     uint32_t flags = 0;
     size_t budget = 0;

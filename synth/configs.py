@@ -73,6 +73,18 @@ def elliptic_high_contrast_100(k=6):
                 coef=high_contrast_coefficient(N), phi=dirichlet_sine(N), seed=OMEGA_SEED)
 
 
+def kinetic_hg_100(eps=2.0 ** -6, k=10, n_vel=64):
+    """The paper's transport test (Sec. 4.3): dx=0.01 (100 cells), M=10, buffered
+    patches twice as large (5 cells each side), Henyey-Greenstein scattering
+    with g=1/2 and sigma=1, k random samples and rank k, full bases on the two
+    end patches; 64 Gauss-Legendre ordinates stand in for the paper's 120-point
+    grid (the end patches' full basis has one column per ordinate, at most 64)."""
+    Nx, M = 100, 10
+    return dict(name=f"kinetic_hg_Nx100_M10_k{k}_eps{eps:g}", kind="kinetic", N=Nx, M=M,
+                overlap=np.full(M, 5, dtype=np.int32), s=k, k=k, n_vel=n_vel, eps=eps, hg=0.5,
+                coef=np.ones(Nx), seed=OMEGA_SEED)
+
+
 def small_elliptic(N=32, M=2, delta=4, s=8, k=5, coef="periodic"):
     """Small elliptic case for fast parity tests (several tiles, ragged sizes)."""
     if coef == "periodic":
@@ -91,4 +103,5 @@ WORKLOADS = {
     "kinetic_slab_4096": kinetic_slab_4096,
     "elliptic_two_scale_100": elliptic_two_scale_100,
     "elliptic_high_contrast_100": elliptic_high_contrast_100,
+    "kinetic_hg_100": kinetic_hg_100,
 }

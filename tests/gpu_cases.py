@@ -22,7 +22,7 @@ def run(cfg, precision, omegas=None, flags=0, phi=None, n_req=None, max_batch=No
     kin = cfg["kind"] == "kinetic"
     d = msrs.make_desc(msrs.KIND_KINETIC_DO if kin else msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"],
                        list(cfg["overlap"]), cfg["s"], cfg["k"], precision=precision, seed=cfg["seed"],
-                       n_vel=cfg.get("n_vel", 0), eps=cfg.get("eps", 1.0),
+                       n_vel=cfg.get("n_vel", 0), eps=cfg.get("eps", 1.0), hg=cfg.get("hg", 0.0),
                        flags=flags | (msrs.FLAG_FULL_BASIS_ENDS if kin else 0))
     pr = msrs.Problem(d)
     try:
