@@ -122,8 +122,11 @@ def run_gpu(cfg, precision, steps, warmup, flags=0, tune=False, graph=False):
     from paper_1807_08848_amd import msrs, tuning
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream()
-    d = msrs.make_desc(msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"], list(cfg["overlap"]), cfg["s"], cfg["k"],
-                       precision=precision, seed=cfg["seed"], flags=flags | msrs.FLAG_TIMING)
+    kin = cfg["kind"] == "kinetic"
+    d = msrs.make_desc(msrs.KIND_KINETIC_DO if kin else msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"],
+                       list(cfg["overlap"]), cfg["s"], cfg["k"], precision=precision, seed=cfg["seed"],
+                       n_vel=cfg.get("n_vel", 0), eps=cfg.get("eps", 1.0), hg=cfg.get("hg", 0.0),
+                       flags=flags | msrs.FLAG_TIMING | (msrs.FLAG_FULL_BASIS_ENDS if kin else 0))
     with torch.cuda.stream(stream):
         pr = msrs.Problem(d, stream=stream)
         a = torch.tensor(cfg["coef"], device=dev)
@@ -148,7 +151,9 @@ def run_gpu(cfg, precision, steps, warmup, flags=0, tune=False, graph=False):
         T = time.perf_counter() - t0
         st = pr.stats()
         L = pr.layout()
-        res = dict(T=T, stats=st, n_solves=L.n_patches * cfg["s"], tuned=tuned)
+        # local solves per step: s per sampled patch, one per basis column of a full-basis patch
+        n_solves = sum(pr.patch(p).n_samples for p in range(L.n_patches))
+        res = dict(T=T, stats=st, n_solves=n_solves, tuned=tuned)
         if graph:
             t0 = time.perf_counter()
             pr.offline_graph_capture(a)
@@ -314,8 +319,9 @@ def main():
         raise RuntimeError("graph replay latched an error or missed the residual tolerance")
     T = r["T_graph"]
     value = r["n_solves"] * args.steps / T
-    # dominant kernel and its roofline
-    alg = algorithmic(cfg)
+    # dominant kernel and its roofline (the banded-direct counts are those of the elliptic geometry)
+    kinetic = cfg["kind"] == "kinetic"
+    alg = algorithmic(cfg) if not kinetic else {K_FACTOR: 0, K_SWEEP: 0, K_RANGE: 0}
     ms = {k: st.kernel_ms[k] for k in range(11)}
     n = {k: st.kernel_launches[k] for k in range(11)}
     dom = max((K_FACTOR, K_SWEEP, K_RANGE), key=lambda k: ms[k])
@@ -331,7 +337,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic (seeded lognormal medium, device Philox boundary samples)",
         "config": {"workload": cfg["name"], "N": cfg["N"], "M": cfg["M"], "samples": cfg["s"], "rank": cfg["k"],
-                   "patches": cfg["M"] ** 2, "precision": "fp32 factor+sweeps, fp64 refinement/range finder"},
+                   "patches": cfg["M"] if kinetic else cfg["M"] ** 2,
+                   "precision": "fp32 factor+sweeps, fp64 refinement/range finder"},
         "roofline": {"bound": kind[0], "kernel": kind[2], "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic({K_FACTOR: "factor", K_SWEEP: "sweep", K_RANGE: "range"}[dom]),
@@ -342,6 +349,8 @@ def main():
         "graph": {"capture_s": r["graph_capture_s"], "max_rel_residual": r["graph_max_rel_residual"],
                   "eager_ms_per_step": r["T"] / args.steps * 1e3},
     }
+    if kinetic:
+        out["roofline"] = None     # no banded-direct count is defined for the transport operator here
     if not args.no_plain:
         print("[bench] plain FP64 reference (one launch per patch per stage)", file=sys.stderr, flush=True)
         rp = run_gpu(cfg, msrs.PREC_FP64, max(1, min(3, args.steps)), 1, flags=msrs.FLAG_PER_PATCH_LAUNCH)
