@@ -1074,7 +1074,7 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const PatchDesc* pd,
     const int c = m.col;
     double ssum = 0.0;
     auto xv = [&](int l, int i) -> double { return X[(int64_t)l * lstride + (int64_t)i * sp + c]; };
-    if (KIND == kElliptic) {
+    if constexpr (KIND == kElliptic) {
         for (int l = l0; l < l1; ++l) {
             for (int i = m.row0; m.active && i < bp; i += m.rows) {
                 double r = 0.0;
@@ -1103,30 +1103,50 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const PatchDesc* pd,
     } else {
         // thread (row group g, column c): cells l0 + g, l0 + g + rows, ...; all ordinates of a cell
         const int h = b / 2;
+        // anisotropic scattering: the gain table K (b x b) staged in LDS once, and
+        // the gain of 16 ordinates at a time, so that a cell's values are read
+        // once per 16 ordinates rather than once per ordinate
+        __shared__ double Ks[kMaxHgVel * kMaxHgVel];
+        if (P.hg) {
+            for (int o = threadIdx.x; o < b * b; o += kThreads) Ks[o] = vw[3 * b + o];
+            __syncthreads();
+        }
         for (int l = l0 + m.row0; m.active && l < l1; l += m.rows) {
             double rho = 0.0;
             if (c < P.s && !P.hg)
                 for (int j = 0; j < b; ++j) rho += 0.5 * vw[b + j] * xv(l, j);
             const double sg = aL[l] * inv_eps;
-            for (int i = 0; i < bp; ++i) {
-                double r = 0.0;
-                if (i < b && c < P.s) {
-                    const double vi = vw[i];
-                    double acc;
-                    if (P.hg) {
-                        // anisotropic: gain sum_j K_ij f_j, loss lambda_i f_i
-                        double gain = 0.0;
-                        for (int j = 0; j < b; ++j) gain += vw[3 * b + i * b + j] * xv(l, j);
-                        acc = (fabs(vi) / dx + sg * vw[2 * b + i]) * xv(l, i) - sg * gain;
-                    } else {
-                        acc = (fabs(vi) / dx + sg) * xv(l, i) - sg * rho;
+            for (int i0 = 0; i0 < bp; i0 += 16) {
+                double gain[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) gain[u] = 0.0;
+                if (P.hg && c < P.s) {
+                    for (int j = 0; j < b; ++j) {
+                        const double xj = xv(l, j);
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) gain[u] += Ks[min(i0 + u, b - 1) * b + j] * xj;
                     }
-                    if (vi > 0) acc -= vi / dx * (l > 0 ? xv(l - 1, i) : O[(int64_t)c * P.nb + (i - h)]);
-                    if (vi < 0) acc -= -vi / dx * (l < nl - 1 ? xv(l + 1, i) : O[(int64_t)c * P.nb + h + i]);
-                    r = -acc;
                 }
-                if (X32) X32[(int64_t)l * lstride + (int64_t)i * sp + c] = (float)r;
-                ssum += r * r;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int i = i0 + u;
+                    double r = 0.0;
+                    if (i < b && c < P.s) {
+                        const double vi = vw[i];
+                        double acc;
+                        if (P.hg) {
+                            // gain sum_j K_ij f_j, loss lambda_i f_i
+                            acc = (fabs(vi) / dx + sg * vw[2 * b + i]) * xv(l, i) - sg * gain[u];
+                        } else {
+                            acc = (fabs(vi) / dx + sg) * xv(l, i) - sg * rho;
+                        }
+                        if (vi > 0) acc -= vi / dx * (l > 0 ? xv(l - 1, i) : O[(int64_t)c * P.nb + (i - h)]);
+                        if (vi < 0) acc -= -vi / dx * (l < nl - 1 ? xv(l + 1, i) : O[(int64_t)c * P.nb + h + i]);
+                        r = -acc;
+                    }
+                    if (X32) X32[(int64_t)l * lstride + (int64_t)i * sp + c] = (float)r;
+                    ssum += r * r;
+                }
             }
         }
     }

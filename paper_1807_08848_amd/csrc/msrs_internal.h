@@ -14,6 +14,7 @@ namespace msrs {
 
 constexpr int kMaxLine = 128;      // padded unknowns per block row (elliptic); 16 | bp
 constexpr int kMaxSamples = 64;    // padded samples per patch
+constexpr int kMaxHgVel = 64;      // ordinates of an anisotropic-scattering (kinetic) problem at most
 constexpr int kThreads = 256;      // threads of every per-patch workgroup
 constexpr int kChunkLines = 8;     // block rows per workgroup of the lifting and residual kernels
 constexpr int kOutPerLaunch = 32;  // requests per reconstruction launch
