@@ -48,7 +48,9 @@
  *    Elliptic rows are the (nH+1)^2 nodes of the closed patch K_m, row-major
  *    (index jj*(nH+1)+ii, nH = N/M); kinetic rows are (cell c, ordinate j) ->
  *    c*n_vel + j for the nH+2 cells [first cell of K_m - 1, last cell + 1].
- *  - Q (bases) of patch p: n_rows(p) x n_cols(p), column-major, offset Q_off(p).
+ *  - Q (bases) of patch p: n_rows(p) x n_cols(p), column-major, offset Q_off(p);
+ *    the space reserved is n_rows(p) x k (x n_bdry for a full-basis patch),
+ *    whose columns past n_cols(p) are zero.
  *  - Global boundary data f of one request: elliptic 4N values
  *    counter-clockwise from node (0,0) (bottom i=0..N-1, right j=0..N-1, top
  *    i=N..1, left j=N..1); kinetic n_vel values laid out as Omega.
@@ -116,6 +118,10 @@ typedef struct msrs_problem_desc {
                                 k(v, v') = (1 - g^2) / (2 (1 + g^2 + 2 g v v')) (Sec. 4, eq. HG); 0: isotropic,
                                 k = 1/2 (eq. def.LL.hom).  The collision term is int k(v,v') f(v') dv' -
                                 int k(v',v) dv' f(v), by Gauss-Legendre quadrature on the ordinates. */
+    double rank_tol;         /* 0: every sampled patch keeps rank k.  In (0, 1): each keeps its numerical rank at
+                                this relative tolerance (Def. num_rank with tau = rank_tol sigma_1(Y_m): the number of
+                                singular values of Y_m above it), at least 1 and at most k; msrs_query_patch reports
+                                it as n_cols once the range finder has run, and the columns of Q past it are zero. */
 } msrs_problem_desc;
 
 typedef struct msrs_layout {
@@ -128,7 +134,7 @@ typedef struct msrs_layout {
     int64_t Y_total;         /* elements of the concatenated Y array */
     int64_t Q_total;         /* elements of the concatenated Q array */
     int64_t sv_total;        /* elements of the singular-value array (s per patch) */
-    int64_t coarse_dim;      /* unknowns of the least-squares system */
+    int64_t coarse_dim;      /* unknowns of the least-squares system (the sum of n_cols) */
     int64_t device_bytes;    /* device memory held by the handle */
 } msrs_layout;
 
@@ -137,7 +143,7 @@ typedef struct msrs_patch_info {
     int32_t kx0, ky0, nH;    /* patch K_m origin and width in cells */
     int32_t n_bdry;          /* boundary samples per column of Omega */
     int32_t n_rows;          /* rows of Y and Q */
-    int32_t n_cols;          /* columns of Q (k, or n_bdry for a full-basis patch) */
+    int32_t n_cols;          /* columns of Q (k, or n_bdry for a full-basis patch, or the rank chosen at rank_tol) */
     int32_t full_basis;      /* 1 if the patch keeps its full delta basis */
     int32_t line_len;        /* unknowns per block row of the local factorization */
     int32_t n_lines;         /* block rows of the local factorization */
@@ -297,7 +303,7 @@ msrs_status msrs_copy_omega(msrs_handle h, double* omega_out_dev);
  * solve) in a file, and make a handle of it again later.
  *
  * msrs_save writes the problem description, the coefficient field, the bases
- * Q, the singular values and the per-patch gaps and residuals of handle h
+ * Q, the singular values, the per-patch gaps and residuals and the ranks of handle h
  * to path (created or truncated): a little-endian binary file with an
  * 8-byte magic, a version and a 64-bit FNV-1a checksum over everything after
  * the magic.  It synchronizes the handle's stream.  Errors: ARG (NULL
@@ -309,7 +315,7 @@ msrs_status msrs_copy_omega(msrs_handle h, double* omega_out_dev);
  * field: msrs_assemble_coarse and msrs_solve_global may follow at once; the
  * offline calls start over from msrs_assemble_patch.  The caller destroys
  * the handle.  Errors: ARG (NULL argument), IO (unreadable file, wrong magic
- * or version, sizes that do not match the description, checksum mismatch),
+ * or version, sizes or ranks that do not match the description, checksum mismatch),
  * and those of msrs_create.  *out is NULL on failure.
  */
 msrs_status msrs_save(msrs_handle h, const char* path);
@@ -352,7 +358,9 @@ typedef struct msrs_tune_report {
  */
 msrs_status msrs_autotune(msrs_handle h, int32_t stage, int32_t reps, msrs_tune_report* out);
 
-/* Sizes and offsets of the concatenated arrays.  Errors: ARG. */
+/* Sizes and offsets of the concatenated arrays.  After a range finder with
+ * rank_tol > 0 the first query synchronizes the handle's stream to read the
+ * ranks it chose.  Errors: ARG, HIP. */
 msrs_status msrs_query_layout(msrs_handle h, msrs_layout* out);
 msrs_status msrs_query_patch(msrs_handle h, int32_t patch, msrs_patch_info* out);
 

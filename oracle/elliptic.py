@@ -31,7 +31,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from . import philox
-from .rangefinder import range_finder
+from .rangefinder import adaptive_rank, range_finder
 
 # Bilinear element stiffness of the unit square for -div(grad u), local node
 # order SW, SE, NE, NW (counter-clockwise).  Scale-free in 2D: the element
@@ -177,7 +177,8 @@ def full_basis_patch(a_flat, N, g) -> np.ndarray:
     return sample_patch(a_flat, N, g, np.eye(nb))
 
 
-def offline(a_flat, N, M, overlap, s, k, seed=2, omegas=None, full_basis=False, full_basis_boundary=False):
+def offline(a_flat, N, M, overlap, s, k, seed=2, omegas=None, full_basis=False, full_basis_boundary=False,
+            rank_tol=0.0):
     """Offline stage over all patches: snapshots Y_m, rank-k bases Q_m and singular values.
 
     omegas: optional list of explicit boundary sample matrices (one per patch);
@@ -186,7 +187,9 @@ def offline(a_flat, N, M, overlap, s, k, seed=2, omegas=None, full_basis=False, 
     full_basis_boundary=True does so only for the patches that touch the
     domain boundary (no buffer, Kronecker-delta data at all 4 N/M boundary
     nodes), with the basis orthonormalized by the range finder at full rank;
-    the interior patches are sampled as usual.
+    the interior patches are sampled as usual.  rank_tol > 0 keeps, per
+    sampled patch, the numerical rank of Y_m at tau = rank_tol sigma_1(Y_m)
+    (Def. num_rank), at most k, instead of k.
     """
     geo = patch_geometry(N, M, 0 if full_basis else overlap)
     geo0 = patch_geometry(N, M, 0) if full_basis_boundary else None
@@ -204,6 +207,9 @@ def offline(a_flat, N, M, overlap, s, k, seed=2, omegas=None, full_basis=False, 
             om = omegas[g["p"]] if omegas is not None else patch_omega(seed, g, s)
             Y = sample_patch(a_flat, N, g, om)
             Q, sv = range_finder(Y, k)
+            kt = adaptive_rank(sv, k, rank_tol)
+            if kt < k:
+                Q, sv = range_finder(Y, kt)
         out.append(dict(geo=g, Y=Y, Q=Q, sv=sv))
     return out
 

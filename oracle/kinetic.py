@@ -25,7 +25,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from . import philox
-from .rangefinder import range_finder
+from .rangefinder import adaptive_rank, range_finder
 
 
 def ordinates(nv: int = 32):
@@ -172,12 +172,14 @@ def patch_omega(seed: int, g: dict, nv: int, s: int) -> np.ndarray:
 
 
 def offline(sigma_all, eps, Nx, M, overlap, nv, s, k, seed=2, omegas=None, full_basis=False,
-            full_basis_ends=True, hg: float = 0.0):
+            full_basis_ends=True, hg: float = 0.0, rank_tol: float = 0.0):
     """Offline stage: snapshots and bases per patch.
 
     End patches (m = 0 and m = M-1) use the full basis on the unbuffered
     patch (inflow deltas), as the paper does to capture the global inflow
-    data; full_basis=True does so for every patch.
+    data; full_basis=True does so for every patch.  rank_tol > 0 keeps, per
+    sampled patch, the numerical rank of Y_m at tau = rank_tol sigma_1(Y_m)
+    (Def. num_rank), at most k, instead of k.
     """
     geo = patch_geometry(Nx, M, overlap)
     geo0 = patch_geometry(Nx, M, 0)
@@ -191,6 +193,9 @@ def offline(sigma_all, eps, Nx, M, overlap, nv, s, k, seed=2, omegas=None, full_
             om = omegas[g["p"]] if omegas is not None else patch_omega(seed, g, nv, s)
             Y = sample_patch(sigma_all, eps, Nx, nv, g, om, hg)
             Q, sv = range_finder(Y, k)
+            kt = adaptive_rank(sv, k, rank_tol)
+            if kt < k:
+                Q, sv = range_finder(Y, kt)
             out.append(dict(geo=g, Y=Y, Q=Q, sv=sv, full=False))
     return out
 

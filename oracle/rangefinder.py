@@ -29,6 +29,22 @@ def range_finder(Y: np.ndarray, k: int):
     return sign_fix(Qk), S
 
 
+def numerical_rank(sv: np.ndarray, tau: float) -> int:
+    """Numerical tau-rank (Def. num_rank): the smallest rank of a matrix within
+    spectral-norm distance tau.  By Eckart-Young the best rank-r approximation
+    is at distance sigma_{r+1}, so this is the number of singular values above
+    tau."""
+    return int(np.count_nonzero(np.asarray(sv) > tau))
+
+
+def adaptive_rank(sv: np.ndarray, k: int, rank_tol: float) -> int:
+    """Rank kept for a sampled patch: k when rank_tol is 0, else the numerical
+    rank of the snapshots at tau = rank_tol sigma_1, clamped to [1, k]."""
+    if rank_tol <= 0.0:
+        return k
+    return max(1, min(k, numerical_rank(sv, rank_tol * sv[0])))
+
+
 def projection_error(G: np.ndarray, Q: np.ndarray) -> float:
     """||G - Q Q^T G||_2 / ||G||_2, the local error of the elliptic and kinetic local tests."""
     E = G - Q @ (Q.T @ G)

@@ -101,6 +101,7 @@ void build_elliptic(Ctx& c) {
             P.kx0 = m1 * nH; P.ky0 = m2 * nH; P.nH = nH;
             P.nrows = (nH + 1) * (nH + 1);
             P.ncols = full ? P.nb : c.k;
+            P.kreq = P.ncols;
             P.full = full ? 1 : 0;
             P.sampled = full ? 0 : 1;
             P.a_off = a_off; a_off += (int64_t)P.L * P.Qn;
@@ -139,6 +140,7 @@ void build_kinetic(Ctx& c) {
         P.kx0 = m * nH; P.ky0 = 0; P.nH = nH;
         P.nrows = (nH + 2) * nv;
         P.ncols = full ? nv : c.k;
+        P.kreq = P.ncols;
         P.full = full ? 1 : 0;
         P.sampled = full ? 0 : 1;
         P.hg = c.hg != 0.0 ? 1 : 0;
@@ -167,6 +169,7 @@ msrs_status validate(const msrs_problem_desc* d, std::string& msg) {
     if (d->rank < 1 || d->rank > d->n_samples) { msg = "rank must be in [1, n_samples]"; return MSRS_ERR_ARG; }
     if (d->precision != MSRS_PREC_FP64 && d->precision != MSRS_PREC_FP32_IR) { msg = "unknown precision"; return MSRS_ERR_ARG; }
     if (!d->overlap) { msg = "overlap is NULL"; return MSRS_ERR_ARG; }
+    if (!(d->rank_tol >= 0.0 && d->rank_tol < 1.0)) { msg = "rank_tol must be in [0, 1)"; return MSRS_ERR_ARG; }
     const int np = d->kind == MSRS_KIND_ELLIPTIC_Q1 ? d->M * d->M : d->M;
     for (int p = 0; p < np; ++p)
         if (d->overlap[p] < 0) { msg = "negative overlap"; return MSRS_ERR_ARG; }
@@ -434,6 +437,7 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->ir_tol = desc->ir_tol > 0 ? desc->ir_tol : 1e-10;
         c->eps = desc->kind == MSRS_KIND_KINETIC_DO ? desc->eps : 1.0;
         c->hg = desc->kind == MSRS_KIND_KINETIC_DO ? desc->hg_g : 0.0;
+        c->rank_tol = desc->rank_tol;
         c->nv = desc->kind == MSRS_KIND_KINETIC_DO ? desc->n_vel : 0;
         c->seed = desc->seed;
         c->flags = desc->flags;
@@ -578,6 +582,17 @@ msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, 
     return MSRS_OK;
 }
 
+// Host copy of the ranks the range finder chose at a tolerance (the device
+// descriptors hold them once the range finder has run).
+static void sync_ranks(Ctx* c) {
+    if (!c->ranks_stale) return;
+    std::vector<PatchDesc> d(c->n_patches);
+    MSRS_HIP_CHECK(hipMemcpyAsync(d.data(), c->dp, sizeof(PatchDesc) * c->n_patches, hipMemcpyDeviceToHost, c->stream));
+    MSRS_HIP_CHECK(hipStreamSynchronize(c->stream));
+    for (int p = 0; p < c->n_patches; ++p) c->hp[p].ncols = d[p].ncols;
+    c->ranks_stale = false;
+}
+
 msrs_status msrs_range_finder(msrs_handle h, double* Q_out_dev, double* sv_out_dev) {
     Ctx* c = h;
     if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
@@ -595,6 +610,7 @@ msrs_status msrs_range_finder(msrs_handle h, double* Q_out_dev, double* sv_out_d
     }
     c->ranged = true;
     c->coarse_ready = false;
+    c->ranks_stale = c->rank_tol > 0.0;
     return MSRS_OK;
 }
 
@@ -654,6 +670,7 @@ msrs_status msrs_offline_graph_launch(msrs_handle h) {
     }
     c->assembled = c->sampled = c->ranged = true;
     c->coarse_ready = false;
+    c->ranks_stale = c->rank_tol > 0.0;
     c->last_ir_iters = c->graph_iters;
     return MSRS_OK;
 }
@@ -681,8 +698,11 @@ msrs_status msrs_save(msrs_handle h, const char* path) {
     if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
     if (!c->ranged) return fail(c, MSRS_ERR_STATE, "msrs_range_finder must come first");
     try {
+        sync_ranks(c);
         const int64_t ncoef = c->kind == kElliptic ? (int64_t)c->N * c->N : c->N;
         std::vector<double> coef(ncoef), Q(c->Q_total), sv(c->sv_total), gp(2 * c->n_patches);
+        std::vector<int32_t> ranks(c->n_patches);
+        for (int p = 0; p < c->n_patches; ++p) ranks[p] = c->hp[p].ncols;
         MSRS_HIP_CHECK(hipMemcpyAsync(coef.data(), c->coef_copy, ncoef * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         MSRS_HIP_CHECK(hipMemcpyAsync(Q.data(), c->Q, Q.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         MSRS_HIP_CHECK(hipMemcpyAsync(sv.data(), c->sv, sv.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -706,6 +726,7 @@ msrs_status msrs_save(msrs_handle h, const char* path) {
         w.val<double>(c->ir_tol);
         w.val<double>(c->eps);
         w.val<double>(c->hg);
+        w.val<double>(c->rank_tol);
         w.val<uint32_t>(c->flags);
         w.val<int32_t>(c->last_ir_iters);
         w.val<int32_t>((int32_t)c->overlap.size());
@@ -718,6 +739,7 @@ msrs_status msrs_save(msrs_handle h, const char* path) {
         w.put(Q.data(), Q.size() * sizeof(double));
         w.put(sv.data(), sv.size() * sizeof(double));
         w.put(gp.data(), gp.size() * sizeof(double));
+        w.put(ranks.data(), ranks.size() * sizeof(int32_t));
         const uint64_t sum = w.h;
         if (!w.ok || fwrite(&sum, 1, sizeof(sum), g.f) != sizeof(sum) || fflush(g.f) != 0)
             return fail(c, MSRS_ERR_IO, std::string("write failed: ") + path);
@@ -754,6 +776,7 @@ msrs_status msrs_load(msrs_handle* out, const char* path, void* stream) {
     d.ir_tol = r.val<double>();
     d.eps = r.val<double>();
     d.hg_g = r.val<double>();
+    d.rank_tol = r.val<double>();
     d.flags = r.val<uint32_t>();
     const int32_t ir_iters = r.val<int32_t>();
     const int32_t nov = r.val<int32_t>();
@@ -777,16 +800,26 @@ msrs_status msrs_load(msrs_handle* out, const char* path, void* stream) {
     }
     try {
         std::vector<double> coef(ncoef), Q(nQ), sv(nsv), gp(ngp);
+        std::vector<int32_t> ranks(c->n_patches);
         r.get(coef.data(), coef.size() * sizeof(double));
         r.get(Q.data(), Q.size() * sizeof(double));
         r.get(sv.data(), sv.size() * sizeof(double));
         r.get(gp.data(), gp.size() * sizeof(double));
+        r.get(ranks.data(), ranks.size() * sizeof(int32_t));
         const uint64_t sum = r.h;
         uint64_t stored = 0;
         if (!r.ok || fread(&stored, 1, sizeof(stored), g.f) != sizeof(stored) || stored != sum) {
             msrs_destroy(h);
             return fail(nullptr, MSRS_ERR_IO, "truncated file or checksum mismatch" + where);
         }
+        for (int p = 0; p < c->n_patches; ++p) {
+            if (ranks[p] < 1 || ranks[p] > c->hp[p].kreq || (ranks[p] != c->hp[p].kreq && !(d.rank_tol > 0.0))) {
+                msrs_destroy(h);
+                return fail(nullptr, MSRS_ERR_IO, "patch ranks do not match the description" + where);
+            }
+            c->hp[p].ncols = ranks[p];
+        }
+        MSRS_HIP_CHECK(hipMemcpyAsync(c->dp, c->hp.data(), sizeof(PatchDesc) * c->n_patches, hipMemcpyHostToDevice, c->stream));
         MSRS_HIP_CHECK(hipMemcpyAsync(c->coef_copy, coef.data(), ncoef * sizeof(double), hipMemcpyHostToDevice, c->stream));
         MSRS_HIP_CHECK(hipMemcpyAsync(c->Q, Q.data(), nQ * sizeof(double), hipMemcpyHostToDevice, c->stream));
         MSRS_HIP_CHECK(hipMemcpyAsync(c->sv, sv.data(), nsv * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -829,37 +862,67 @@ msrs_status msrs_set_max_batch(msrs_handle h, int32_t max_batch) {
     return MSRS_OK;
 }
 
+// Coarse unknowns (patch columns in patch order), the half bandwidth of the
+// normal equations and the columns of the patches with Dirichlet / inflow
+// rows, at the ranks in hp (or every patch at its requested rank).
+static void coarse_layout(Ctx* c, bool requested, std::vector<int32_t>& bmap) {
+    c->hc.assign(c->n_patches, CoarseDesc{});
+    int off = 0;
+    for (int p = 0; p < c->n_patches; ++p) {
+        c->hc[p].col_off = off;
+        c->hc[p].ncols = requested ? c->hp[p].kreq : c->hp[p].ncols;
+        c->hc[p].b_off = -1;
+        off += c->hc[p].ncols;
+    }
+    c->Np = off;
+    // half bandwidth: last unknown of the farthest coupled patch
+    int bw = 0;
+    for (int p = 0; p < c->n_patches; ++p) {
+        int far = p;
+        if (c->kind == kElliptic) {
+            const int m1 = p % c->M, m2 = p / c->M;
+            if (m2 < c->M - 1) far = p + c->M + (m1 < c->M - 1 ? 1 : 0);
+            else if (m1 < c->M - 1) far = p + 1;
+        } else {
+            far = std::min(p + 1, c->n_patches - 1);
+        }
+        bw = std::max(bw, c->hc[far].col_off + c->hc[far].ncols - 1 - c->hc[p].col_off);
+    }
+    c->bw = std::min(bw, c->Np - 1);
+    c->bpatch.clear();
+    bmap.clear();
+    for (int p = 0; p < c->n_patches; ++p) {
+        bool bd;
+        if (c->kind == kElliptic) {
+            const int m1 = p % c->M, m2 = p / c->M;
+            bd = m1 == 0 || m2 == 0 || m1 == c->M - 1 || m2 == c->M - 1;
+        } else {
+            bd = p == 0 || p == c->n_patches - 1;
+        }
+        if (!bd) continue;
+        c->hc[p].b_off = (int32_t)bmap.size();
+        c->bpatch.push_back(p);
+        for (int a = 0; a < c->hc[p].ncols; ++a) bmap.push_back(c->hc[p].col_off + a);
+    }
+    c->nB = (int)bmap.size();
+}
+
 msrs_status msrs_assemble_coarse(msrs_handle h) {
     Ctx* c = h;
     if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
     if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
     if (!c->ranged) return fail(c, MSRS_ERR_STATE, "msrs_range_finder must come first");
     try {
-        if (!c->dc) {
-            c->hc.assign(c->n_patches, CoarseDesc{});
-            int off = 0;
-            for (int p = 0; p < c->n_patches; ++p) {
-                c->hc[p].col_off = off;
-                c->hc[p].ncols = c->hp[p].ncols;
-                c->hc[p].b_off = -1;
-                off += c->hp[p].ncols;
-            }
-            c->Np = off;
-            // half bandwidth: last unknown of the farthest coupled patch
-            int bw = 0;
-            for (int p = 0; p < c->n_patches; ++p) {
-                int far = p;
-                if (c->kind == kElliptic) {
-                    const int m1 = p % c->M, m2 = p / c->M;
-                    if (m2 < c->M - 1) far = p + c->M + (m1 < c->M - 1 ? 1 : 0);
-                    else if (m1 < c->M - 1) far = p + 1;
-                } else {
-                    far = std::min(p + 1, c->n_patches - 1);
-                }
-                bw = std::max(bw, c->hc[far].col_off + c->hc[far].ncols - 1 - c->hc[p].col_off);
-            }
-            c->bw = std::min(bw, c->Np - 1);
+        sync_ranks(c);
+        std::vector<int32_t> bmap;
+        const bool first = !c->dc;
+        if (first) {
+            // buffers for every patch at its requested rank: the ranks a
+            // tolerance chooses (never above it) fit without reallocation
+            coarse_layout(c, true, bmap);
             if (c->bw + 1 > 1024) return fail(c, MSRS_ERR_ARG, "coarse band wider than 1023");
+            c->Np_cap = c->Np;
+            c->nB_cap = c->nB;
             int kmax = 0;
             for (auto& d : c->hc) kmax = std::max(kmax, d.ncols);
             c->dc = dalloc<CoarseDesc>(*c, c->n_patches);
@@ -868,28 +931,8 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
                 c->tr = dalloc<double>(*c, (int64_t)c->n_patches * c->tr_stride);
             }
             c->band = dalloc<double>(*c, (int64_t)c->Np * (c->bw + 1));
-            // patches with Dirichlet (inflow) rows and their columns of G_B
-            c->bpatch.clear();
-            std::vector<int32_t> bmap;
-            for (int p = 0; p < c->n_patches; ++p) {
-                bool bd;
-                if (c->kind == kElliptic) {
-                    const int m1 = p % c->M, m2 = p / c->M;
-                    bd = m1 == 0 || m2 == 0 || m1 == c->M - 1 || m2 == c->M - 1;
-                } else {
-                    bd = p == 0 || p == c->n_patches - 1;
-                }
-                if (!bd) continue;
-                c->hc[p].b_off = (int32_t)bmap.size();
-                c->bpatch.push_back(p);
-                for (int a = 0; a < c->hc[p].ncols; ++a) bmap.push_back(c->hc[p].col_off + a);
-            }
-            c->nB = (int)bmap.size();
-            MSRS_HIP_CHECK(hipMemcpy(c->dc, c->hc.data(), sizeof(CoarseDesc) * c->n_patches, hipMemcpyHostToDevice));
             c->dbpatch = dalloc<int32_t>(*c, (int64_t)c->bpatch.size());
-            MSRS_HIP_CHECK(hipMemcpy(c->dbpatch, c->bpatch.data(), sizeof(int32_t) * c->bpatch.size(), hipMemcpyHostToDevice));
             c->bmap = dalloc<int32_t>(*c, c->nB);
-            MSRS_HIP_CHECK(hipMemcpy(c->bmap, bmap.data(), sizeof(int32_t) * bmap.size(), hipMemcpyHostToDevice));
             c->GB = dalloc<double>(*c, (int64_t)c->Np * c->nB);
             c->GT = dalloc<double>(*c, (int64_t)c->Np * c->nB);
             for (auto& w : c->ws) {
@@ -898,6 +941,12 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
                 MSRS_HIP_CHECK(hipEventCreateWithFlags(&w.done, hipEventDisableTiming));
             }
             if (c->budget && (size_t)c->bytes > c->budget) return fail(c, MSRS_ERR_OOM, "coarse factor exceeds the HBM budget");
+        }
+        if (first || c->rank_tol > 0.0) {
+            coarse_layout(c, false, bmap);
+            MSRS_HIP_CHECK(hipMemcpy(c->dc, c->hc.data(), sizeof(CoarseDesc) * c->n_patches, hipMemcpyHostToDevice));
+            MSRS_HIP_CHECK(hipMemcpy(c->dbpatch, c->bpatch.data(), sizeof(int32_t) * c->bpatch.size(), hipMemcpyHostToDevice));
+            if (c->nB) MSRS_HIP_CHECK(hipMemcpy(c->bmap, bmap.data(), sizeof(int32_t) * bmap.size(), hipMemcpyHostToDevice));
         }
         coarse_setup(*c);
         MSRS_HIP_CHECK(hipGetLastError());
@@ -1082,6 +1131,11 @@ msrs_status msrs_get_tuning(msrs_handle h, int32_t key, int32_t* value) {
 msrs_status msrs_query_layout(msrs_handle h, msrs_layout* out) {
     Ctx* c = h;
     if (!c || !out) return fail(c, MSRS_ERR_ARG, "NULL argument");
+    try {
+        sync_ranks(c);
+    } catch (const HipError& e) {
+        return hip_fail(c, e);
+    }
     out->n_patches = c->n_patches;
     out->n_samples = c->s;
     out->rank = c->k;
@@ -1102,6 +1156,11 @@ msrs_status msrs_query_patch(msrs_handle h, int32_t patch, msrs_patch_info* out)
     Ctx* c = h;
     if (!c || !out) return fail(c, MSRS_ERR_ARG, "NULL argument");
     if (patch < 0 || patch >= c->n_patches) return fail(c, MSRS_ERR_ARG, "patch out of range");
+    try {
+        sync_ranks(c);
+    } catch (const HipError& e) {
+        return hip_fail(c, e);
+    }
     const PatchDesc& P = c->hp[patch];
     out->x0 = P.x0; out->y0 = P.y0; out->cx = P.cx; out->cy = P.cy;
     out->kx0 = P.kx0; out->ky0 = P.ky0; out->nH = P.nH;

@@ -131,9 +131,9 @@ int eig_threads(int max_s) {
     return std::max(64, (np2 * p2 + 63) / 64 * 64);
 }
 
-__global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(const PatchDesc* pd, int p0, const double* __restrict__ part, int maxrc,
+__global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int p0, const double* __restrict__ part, int maxrc,
                                                              double* __restrict__ small, double* __restrict__ sv_all,
-                                                             double* __restrict__ gap, int32_t* flags) {
+                                                             double* __restrict__ gap, int32_t* flags, double rank_tol) {
     // G and V with an odd leading dimension: a wave's column accesses
     // (V[j][a] over rows j) fall on distinct LDS banks
     constexpr int LDG = kRfMax + 1;
@@ -145,7 +145,8 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(const PatchDesc* pd
     const int p = p0 + blockIdx.x;
     const PatchDesc P = pd[p];
     const int tid = threadIdx.x, nth = blockDim.x;
-    const int s = P.s, k = P.ncols;
+    const int s = P.s, kreq = P.kreq;
+    __shared__ int kshared;
     const int nch = (P.nrows + kRowChunk - 1) / kRowChunk;
     for (int o = tid; o < kRfMax * LDG; o += nth) {
         Gb[0][o] = 0.0;
@@ -256,11 +257,24 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(const PatchDesc* pd
     if (tid == 0) {
         double* svp = sv_all + P.sv_off;
         for (int i = 0; i < s; ++i) svp[i] = sqrt(fmax(lam[perm[i]], 0.0));
-        const double s1 = svp[0], sk = svp[k - 1];
+        const double s1 = svp[0];
+        // rank: the requested one, or the numerical rank at rank_tol (the count of
+        // singular values above rank_tol sigma_1), between 1 and the requested one;
+        // the later kernels of the range finder read it from the descriptor
+        int kk = kreq;
+        if (rank_tol > 0.0 && P.sampled) {
+            kk = 0;
+            while (kk < kreq && svp[kk] > rank_tol * s1) ++kk;
+            kk = max(kk, 1);
+        }
+        if (kk != P.ncols) pd[p].ncols = kk;
+        kshared = kk;
+        const double sk = svp[kk - 1];
         if (!(sk > 1e-13 * s1)) raise_flag(flags, 2);
-        gap[p] = (k < s) ? (sk - svp[k]) / s1 : 1.0;
+        gap[p] = (kk < s) ? (sk - svp[kk]) / s1 : 1.0;
     }
     __syncthreads();
+    const int k = kshared;
     double* B = small + (int64_t)p * kSmall;
     for (int o = tid; o < kSmall; o += nth) {
         const int i = o / kRfMax, j = o % kRfMax;
@@ -425,10 +439,11 @@ __global__ __launch_bounds__(kThreads) void sign_apply_kernel(const PatchDesc* p
     const int r0 = blockIdx.y * kRowChunk;
     if (r0 >= P.nrows) return;
     const int r1 = min(P.nrows, r0 + kRowChunk), nr = r1 - r0;
-    for (int o = threadIdx.x; o < nr * P.ncols; o += kThreads) {
+    // columns past a tolerance-chosen rank are zero
+    for (int o = threadIdx.x; o < nr * P.kreq; o += kThreads) {
         const int j = o / nr, r = r0 + (o - j * nr);
         const int64_t idx = P.Q_off + (int64_t)j * P.nrows + r;
-        Q[idx] = small[(int64_t)p * kSmall + j] * W[idx];
+        Q[idx] = j < P.ncols ? small[(int64_t)p * kSmall + j] * W[idx] : 0.0;
     }
 }
 
@@ -445,7 +460,7 @@ void launch_range(Ctx& c, int p0, int p1) {
     int maxs = 0;
     for (int p = p0; p < p1; ++p) maxs = std::max(maxs, c.hp[p].s);
     hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
-                       c.dflags);
+                       c.dflags, c.rank_tol);
     hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kY, (int)kW, c.Y, c.Q, c.rf_ws, c.rf_small);
     // two Cholesky-QR passes: W -> Q -> W
     for (int pass = 0; pass < 2; ++pass) {

@@ -49,6 +49,7 @@ struct PatchDesc {
     int32_t full;             // full (delta) basis: Omega = identity
     int32_t sampled;          // Omega drawn at random (0 for full-basis patches)
     int32_t hg;               // kinetic: anisotropic (Henyey-Greenstein) scattering, tables in vw
+    int32_t kreq;             // requested basis columns (ncols before a tolerance-chosen rank lowers it)
     int64_t a_off;            // aL (doubles)
     int64_t om_off;           // Omega, nb x s column-major
     int64_t x_off;            // line vectors, nl x bp x sp (samples fastest)
@@ -81,6 +82,7 @@ struct Ctx {
     double ir_tol = 1e-10;
     double eps = 1.0;
     double hg = 0.0;          // kinetic: Henyey-Greenstein anisotropy g (0: isotropic)
+    double rank_tol = 0.0;    // > 0: each sampled patch keeps its numerical rank at this tolerance (at most k)
     uint64_t seed = 0;
     uint32_t flags = 0;
     size_t budget = 0;
@@ -129,6 +131,7 @@ struct Ctx {
     // factor (the boundary draws and the lift) runs beside it; used inside a
     // graph capture only, where the capture spans both
     bool defer_factor_join = false;
+    bool ranks_stale = false;     // the device descriptors hold ranks the host copy has not seen
     int n_join = 0;
     int maxch = 1;                // line chunks per patch at most
 
@@ -145,6 +148,7 @@ struct Ctx {
     int recon_batch = 8;         // requests per reconstruction pass (1, 2, 4, 8, 16)
     int apply_batch = 8;         // requests per G_B workgroup (4, 8, 16)
     int Np = 0, bw = 0;
+    int Np_cap = 0, nB_cap = 0;   // sizes the coarse buffers were allocated for (every patch at its requested rank)
     std::vector<CoarseDesc> hc;
     CoarseDesc* dc = nullptr;
     double* tr = nullptr;         // traces (values, fluxes)

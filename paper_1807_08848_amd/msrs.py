@@ -41,7 +41,7 @@ class ProblemDesc(C.Structure):
                 ("rank", C.c_int32), ("precision", C.c_int32), ("ir_max_iters", C.c_int32), ("n_vel", C.c_int32),
                 ("seed", C.c_uint64), ("ir_tol", C.c_double), ("eps", C.c_double),
                 ("overlap", C.POINTER(C.c_int32)), ("flags", C.c_uint32), ("reserved", C.c_int32),
-                ("hg_g", C.c_double)]
+                ("hg_g", C.c_double), ("rank_tol", C.c_double)]
 
 
 class Layout(C.Structure):
@@ -165,11 +165,11 @@ def _stream(stream):
 
 
 def make_desc(kind, n_cells, M, overlap, n_samples, rank, precision=PREC_FP64, seed=2, ir_tol=1e-10,
-              ir_max_iters=30, n_vel=0, eps=1.0, flags=0, hg=0.0):
+              ir_max_iters=30, n_vel=0, eps=1.0, flags=0, hg=0.0, rank_tol=0.0):
     ov = (C.c_int32 * len(overlap))(*[int(x) for x in overlap])
     d = ProblemDesc(kind=kind, n_cells=n_cells, M=M, n_samples=n_samples, rank=rank, precision=precision,
                     ir_max_iters=ir_max_iters, n_vel=n_vel, seed=seed, ir_tol=ir_tol, eps=eps,
-                    overlap=C.cast(ov, C.POINTER(C.c_int32)), flags=flags, reserved=0, hg_g=hg)
+                    overlap=C.cast(ov, C.POINTER(C.c_int32)), flags=flags, reserved=0, hg_g=hg, rank_tol=rank_tol)
     d._keep = ov
     return d
 

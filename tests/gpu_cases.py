@@ -23,7 +23,7 @@ def run(cfg, precision, omegas=None, flags=0, phi=None, n_req=None, max_batch=No
     d = msrs.make_desc(msrs.KIND_KINETIC_DO if kin else msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"],
                        list(cfg["overlap"]), cfg["s"], cfg["k"], precision=precision, seed=cfg["seed"],
                        n_vel=cfg.get("n_vel", 0), eps=cfg.get("eps", 1.0), hg=cfg.get("hg", 0.0),
-                       flags=flags | (msrs.FLAG_FULL_BASIS_ENDS if kin else 0))
+                       rank_tol=cfg.get("rank_tol", 0.0), flags=flags | (msrs.FLAG_FULL_BASIS_ENDS if kin else 0))
     pr = msrs.Problem(d)
     try:
         L = pr.layout()
@@ -43,11 +43,13 @@ def run(cfg, precision, omegas=None, flags=0, phi=None, n_req=None, max_batch=No
         Q = torch.empty(L.Q_total, device=dev, dtype=torch.float64)
         sv = torch.empty(L.sv_total, device=dev, dtype=torch.float64)
         pr.range_finder(Q, sv)
+        infos = [pr.patch(p) for p in range(L.n_patches)]     # ranks chosen at a tolerance, if any
+        L = pr.layout()
         Om = torch.empty(L.omega_total, device=dev, dtype=torch.float64)
         pr.copy_omega(Om)
         st = pr.stats() if stats else None
         Yh, Qh, svh, Omh = (t.cpu().numpy() for t in (Y, Q, sv, Om))
-        out = dict(layout=L, infos=infos, stats=st,
+        out = dict(layout=L, infos=infos, stats=st, Q_flat=Qh,
                    Y=[_unpack(Yh, i.Y_off, i.n_rows, i.n_samples) for i in infos],
                    Q=[_unpack(Qh, i.Q_off, i.n_rows, i.n_cols) for i in infos],
                    sv=[svh[i.sv_off:i.sv_off + i.n_samples] for i in infos],
@@ -79,8 +81,8 @@ def resident(cfg, precision, max_batch=None):
     kin = cfg["kind"] == "kinetic"
     d = msrs.make_desc(msrs.KIND_KINETIC_DO if kin else msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"],
                        list(cfg["overlap"]), cfg["s"], cfg["k"], precision=precision, seed=cfg["seed"],
-                       n_vel=cfg.get("n_vel", 0), eps=cfg.get("eps", 1.0),
-                       flags=msrs.FLAG_FULL_BASIS_ENDS if kin else 0)
+                       n_vel=cfg.get("n_vel", 0), eps=cfg.get("eps", 1.0), hg=cfg.get("hg", 0.0),
+                       rank_tol=cfg.get("rank_tol", 0.0), flags=msrs.FLAG_FULL_BASIS_ENDS if kin else 0)
     pr = msrs.Problem(d)
     try:
         a = torch.tensor(np.asarray(cfg["coef"]), device="cuda:0", dtype=torch.float64)

@@ -1,0 +1,194 @@
+"""Adaptive rank: each sampled patch keeps the numerical tau-rank of its
+snapshots (Def. num_rank) at tau = rank_tol sigma_1(Y_m), at most k, instead
+of a fixed k.
+
+CPU: the numerical rank against closed forms and the Eckart-Young distances
+it stands on; the oracle's offline stage with a tolerance (every kept rank
+sits at the threshold, the reduced global solution stays close to the
+fixed-rank one); the ABI's validation.  GPU: the ranks the device chooses,
+its bases and its online solution against the oracle's, with the columns
+past the rank zero; a basis file keeps the ranks.
+"""
+import numpy as np
+import pytest
+
+from synth import configs
+from oracle import elliptic as E
+from oracle import kinetic as K
+from oracle.rangefinder import adaptive_rank, numerical_rank, range_finder, sin_max_angle
+
+
+def _orthogonal(n, rng):
+    q, r = np.linalg.qr(rng.standard_normal((n, n)))
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def test_numerical_rank_closed_forms():
+    sv = np.array([5.0, 3.0, 1.0, 0.5, 0.0])
+    assert numerical_rank(sv, 2.0) == 2
+    assert numerical_rank(sv, 0.5) == 3        # sigma_4 = tau: the rank-3 truncation is within tau
+    assert numerical_rank(sv, 0.0) == 4        # tau = 0: the exact rank
+    assert numerical_rank(sv, 5.0) == 0        # the zero matrix is within tau
+    assert adaptive_rank(sv, 3, 0.0) == 3      # no tolerance: the requested rank
+    assert adaptive_rank(sv, 3, 0.1) == 3      # clamped at k
+    assert adaptive_rank(sv, 4, 0.5) == 2      # tau = 2.5
+    assert adaptive_rank(sv, 4, 0.99) == 1     # at least one column
+
+
+def test_numerical_rank_is_the_smallest_rank_within_tau():
+    """A = U diag(sigma) V^T with a prescribed spectrum: the rank-k_tau
+    truncation is within tau, and no rank below k_tau is (every rank-r matrix
+    is at distance >= sigma_{r+1}; random rank-r candidates never beat it)."""
+    rng = np.random.default_rng(7)
+    sigma = np.array([4.0, 2.5, 1.2, 0.6, 0.3, 0.1])
+    A = _orthogonal(8, rng)[:, :6] @ np.diag(sigma) @ _orthogonal(6, rng).T
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert np.allclose(sv, sigma)
+    U, S, Vt = np.linalg.svd(A)
+    for tau in (3.0, 1.0, 0.45, 0.2, 0.05):
+        kt = numerical_rank(sv, tau)
+        assert kt == int((sigma > tau).sum())
+        Ak = (U[:, :kt] * S[:kt]) @ Vt[:kt]
+        assert np.linalg.norm(A - Ak, 2) <= tau + 1e-12
+        if kt > 0:
+            r = kt - 1
+            best = np.linalg.norm(A - (U[:, :r] * S[:r]) @ Vt[:r], 2)
+            assert best > tau
+            for _ in range(50):
+                B = rng.standard_normal((8, r)) @ rng.standard_normal((r, 6)) if r else np.zeros((8, 6))
+                assert np.linalg.norm(A - B, 2) >= best - 1e-12
+
+
+def test_oracle_elliptic_ranks_sit_at_the_threshold():
+    cfg = configs.elliptic_two_scale_100(20)
+    tol = 1e-3
+    fixed = E.offline(cfg["coef"], cfg["N"], cfg["M"], cfg["overlap"], cfg["s"], cfg["k"], seed=cfg["seed"])
+    adapt = E.offline(cfg["coef"], cfg["N"], cfg["M"], cfg["overlap"], cfg["s"], cfg["k"], seed=cfg["seed"],
+                      rank_tol=tol)
+    ks = []
+    for f, a in zip(fixed, adapt):
+        sv = f["sv"]
+        kt = a["Q"].shape[1]
+        ks.append(kt)
+        assert 1 <= kt <= cfg["k"]
+        if kt < cfg["k"]:
+            assert sv[kt] <= tol * sv[0] < sv[kt - 1]
+        else:
+            assert sv[-1] > tol * sv[0]
+        Q = a["Q"]
+        assert np.abs(Q.T @ Q - np.eye(kt)).max() < 1e-12
+        # the kept columns are the leading ones of the fixed-rank basis
+        assert sin_max_angle(f["Q"], Q) < 1e-10
+    assert min(ks) < cfg["k"] and max(ks) == cfg["k"]       # the interior patches drop columns
+    u_ref = E.global_solve(cfg["coef"], cfg["N"], cfg["phi"])
+    e_fixed = E.relative_l2(E.online(cfg["N"], cfg["M"], fixed, cfg["coef"], cfg["phi"]), u_ref)
+    e_adapt = E.relative_l2(E.online(cfg["N"], cfg["M"], adapt, cfg["coef"], cfg["phi"]), u_ref)
+    assert e_adapt < 2 * e_fixed + 1e-3
+
+
+def test_oracle_tolerance_zero_keeps_k():
+    cfg = configs.small_elliptic(N=32, M=2, delta=4, s=8, k=5)
+    a = E.offline(cfg["coef"], cfg["N"], cfg["M"], cfg["overlap"], cfg["s"], cfg["k"], seed=cfg["seed"], rank_tol=0.0)
+    assert all(p["Q"].shape[1] == cfg["k"] for p in a)
+
+
+def test_abi_rejects_bad_rank_tol():
+    from paper_1807_08848_amd import msrs
+    cfg = configs.small_elliptic()
+    for tol in (-0.1, 1.0, float("nan")):
+        d = msrs.make_desc(msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"], list(cfg["overlap"]), cfg["s"], cfg["k"],
+                           rank_tol=tol)
+        with pytest.raises(msrs.MsrsError) as e:
+            msrs.Problem(d)
+        assert e.value.status == msrs.ERR_ARG and "rank_tol" in str(e.value)
+
+
+def _margin_ok(sv, tol, k):
+    """True when no singular value of the first k+1 lies within 1e-6 (relative)
+    of the threshold, so that both sides must take the same rank."""
+    t = tol * sv[0]
+    return np.all(np.abs(sv[:k + 1] - t) > 1e-6 * t)
+
+
+FP32_IR = 1
+
+
+@pytest.mark.gpu
+def test_elliptic_adaptive_rank_parity(lib):
+    from gpu_cases import rel, run
+    cfg = configs.elliptic_two_scale_100(20)
+    cfg["rank_tol"] = 1e-3
+    out = run(cfg, FP32_IR, phi=cfg["phi"])
+    ref = E.offline(cfg["coef"], cfg["N"], cfg["M"], cfg["overlap"], cfg["s"], cfg["k"], seed=cfg["seed"],
+                    rank_tol=cfg["rank_tol"])
+    full = E.offline(cfg["coef"], cfg["N"], cfg["M"], cfg["overlap"], cfg["s"], cfg["k"], seed=cfg["seed"])
+    ks = [i.n_cols for i in out["infos"]]
+    assert out["layout"].coarse_dim == sum(ks)
+    assert min(ks) < cfg["k"]
+    for p, (r, f, inf) in enumerate(zip(ref, full, out["infos"])):
+        assert rel(out["Y"][p], r["Y"]) < 1e-8, p
+        if _margin_ok(f["sv"], cfg["rank_tol"], cfg["k"]):
+            assert inf.n_cols == r["Q"].shape[1], p
+        Qg = out["Q"][p]
+        assert np.abs(Qg.T @ Qg - np.eye(inf.n_cols)).max() < 1e-12, p
+        assert sin_max_angle(r["Q"], Qg) < 1e-6, p
+        tail = out["Q_flat"][inf.Q_off + inf.n_rows * inf.n_cols: inf.Q_off + inf.n_rows * cfg["k"]]
+        assert not tail.any(), p
+    u_or = E.online(cfg["N"], cfg["M"], ref, cfg["coef"], cfg["phi"])
+    assert E.relative_l2(out["u"][0], u_or) <= 1e-6
+
+
+@pytest.mark.gpu
+def test_kinetic_adaptive_rank_parity(lib):
+    from gpu_cases import run
+    cfg = configs.kinetic_hg_100(2.0 ** -6, 24, n_vel=32)
+    cfg["rank_tol"] = 1e-2
+    out = run(cfg, FP32_IR)
+    args = (cfg["coef"], cfg["eps"], cfg["N"], cfg["M"], cfg["overlap"], cfg["n_vel"], cfg["s"], cfg["k"])
+    ref = K.offline(*args, seed=cfg["seed"], hg=cfg["hg"], rank_tol=cfg["rank_tol"])
+    full = K.offline(*args, seed=cfg["seed"], hg=cfg["hg"])
+    ks = [i.n_cols for i, r in zip(out["infos"], ref) if not r["full"]]
+    assert min(ks) < cfg["k"]
+    for p, (r, f, inf) in enumerate(zip(ref, full, out["infos"])):
+        if r["full"]:
+            assert inf.n_cols == cfg["n_vel"]
+            continue
+        if _margin_ok(f["sv"], cfg["rank_tol"], cfg["k"]):
+            assert inf.n_cols == r["Q"].shape[1], p
+        assert sin_max_angle(r["Q"], out["Q"][p]) < 1e-6, p
+
+
+@pytest.mark.gpu
+def test_adaptive_ranks_survive_a_basis_file(lib, tmp_path):
+    import torch
+    from gpu_cases import bases, resident
+    cfg = configs.elliptic_two_scale_100(20)
+    cfg["rank_tol"] = 1e-3
+    pr = resident(cfg, FP32_IR)
+    try:
+        L = pr.layout()
+        ks = [pr.patch(p).n_cols for p in range(L.n_patches)]
+        f = torch.tensor(np.atleast_2d(cfg["phi"]), device="cuda:0")
+        u0 = torch.empty((1, L.n_nodes), device="cuda:0", dtype=torch.float64)
+        pr.solve_global(f, u0)
+        path = str(tmp_path / "adaptive.msrs")
+        pr.save(path)
+        ld = lib.Problem.load(path)
+        try:
+            assert [ld.patch(p).n_cols for p in range(L.n_patches)] == ks
+            assert ld.layout().coarse_dim == sum(ks)
+            ld.assemble_coarse()
+            u1 = torch.empty_like(u0)
+            ld.solve_global(f, u1)
+            torch.cuda.synchronize()
+            assert torch.equal(u0, u1)
+        finally:
+            ld.close()
+        # a second offline pass on the same handle chooses the same ranks
+        pr.sample_local_solutions()
+        pr.range_finder()
+        assert [pr.patch(p).n_cols for p in range(L.n_patches)] == ks
+        Q = bases(pr)
+        assert all(q.shape[1] == k for q, k in zip(Q, ks))
+    finally:
+        pr.close()

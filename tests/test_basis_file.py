@@ -17,10 +17,10 @@ MAGIC = b"MSRSBAS1"
 
 
 def _header(version=1, kind=0, n_cells=128, M=4, s=10, k=6, prec=1, ir_max=30, nv=0, seed=2, tol=1e-10, eps=1.0,
-            hg=0.0, flags=0, ir_iters=3, overlap=None, counts=(128 * 128, 0, 0, 0)):
+            hg=0.0, rank_tol=0.0, flags=0, ir_iters=3, overlap=None, counts=(128 * 128, 0, 0, 0)):
     ov = [8] * (M * M) if overlap is None else overlap
-    b = struct.pack("<I8iQdddIii", version, kind, n_cells, M, s, k, prec, ir_max, nv, seed, tol, eps, hg, flags,
-                    ir_iters, len(ov))
+    b = struct.pack("<I8iQddddIii", version, kind, n_cells, M, s, k, prec, ir_max, nv, seed, tol, eps, hg, rank_tol,
+                    flags, ir_iters, len(ov))
     b += struct.pack(f"<{len(ov)}i", *ov)
     b += struct.pack("<4q", *counts)
     return MAGIC + b
