@@ -1153,11 +1153,14 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const PatchDesc* pd,
     partial_column_sums(ssum, m, sp, red, part + ((int64_t)p * maxch + blockIdx.y) * kMaxSamples);
 }
 
-// Elliptic residual, sliding-window form: thread (line l0 + lo, sample c)
-// walks down its line with the 3 x 3 stencil window of x in registers (three
-// new loads per node instead of nine) and the coefficient cell rows of the
-// chunk staged in LDS (two new cells per node), so the loads scale with the
-// output instead of nine-fold.  Same arithmetic as the generic kernel.
+// Elliptic residual, sliding-window form: thread (segment g, line l0 + lo,
+// sample c) walks down its segment of the line with the 3 x 3 stencil window
+// of x in registers (three new loads per node instead of nine) and the
+// coefficient cell rows of the chunk staged in LDS (two new cells per node),
+// so the loads scale with the output instead of nine-fold.  A line splits
+// into as many segments as the workgroup has threads to spare for its sample
+// count (2 at 32 samples): shorter dependent walks, more loads in flight.
+// Same arithmetic per node as the generic kernel.
 constexpr int kResThreads = kChunkLines * kMaxSamples;   // 8 lines x up to 64 samples
 __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
                                                                    const double* __restrict__ om, const double* __restrict__ x64_all,
@@ -1181,8 +1184,11 @@ __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDe
     // cell rows l0 .. l1 (line l is bounded by cell rows l and l + 1)
     for (int o = tid; o < (l1 - l0 + 1) * L; o += kResThreads) cell[o] = aL[(int64_t)l0 * L + o];
     __syncthreads();
-    const int lo = tid / sp, c = tid - lo * sp;
-    const bool active = lo < l1 - l0;
+    const int nseg = max(1, kResThreads / (sp * kChunkLines));
+    const int c = tid % sp, lo = (tid / sp) % kChunkLines, g = tid / (sp * kChunkLines);
+    const bool active = lo < l1 - l0 && g < nseg;
+    // nodes pa .. pb of the line (1-based along it)
+    const int pa = 1 + (g * b) / nseg, pb = ((g + 1) * b) / nseg;
     double ssum = 0.0;
     if (active) {
         const int l = l0 + lo, q = l + 1;
@@ -1201,10 +1207,10 @@ __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDe
             const double* cN = cell + (l - l0 + 1) * L;    // cell row q
             // window columns p-1, p, p+1 of node rows q-1, q, q+1
             double wm[3], w0[3], wp[3];
-            wm[0] = u(q - 1, 0); w0[0] = u(q, 0); wp[0] = u(q + 1, 0);
-            wm[1] = u(q - 1, 1); w0[1] = u(q, 1); wp[1] = u(q + 1, 1);
-            double SW = cS[0], NW = cN[0];
-            for (int pp = 1; pp <= b; ++pp) {
+            wm[0] = u(q - 1, pa - 1); w0[0] = u(q, pa - 1); wp[0] = u(q + 1, pa - 1);
+            wm[1] = u(q - 1, pa); w0[1] = u(q, pa); wp[1] = u(q + 1, pa);
+            double SW = cS[pa - 1], NW = cN[pa - 1];
+            for (int pp = pa; pp <= pb; ++pp) {
                 wm[2] = u(q - 1, pp + 1);
                 w0[2] = u(q, pp + 1);
                 wp[2] = u(q + 1, pp + 1);
@@ -1229,18 +1235,19 @@ __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDe
                 wp[0] = wp[1]; wp[1] = wp[2];
                 SW = SE; NW = NE;
             }
-            if (R32)
+            if (R32 && g == nseg - 1)
                 for (int i = b; i < bp; ++i) R32[(int64_t)i * sp] = 0.0f;
-        } else if (R32) {
+        } else if (R32 && g == 0) {
             for (int i = 0; i < bp; ++i) R32[(int64_t)i * sp] = 0.0f;
         }
     }
-    // per-sample sums over the chunk's lines, fixed order
-    red[tid] = ssum;
+    // per-sample sums over the chunk's lines and segments, fixed order
+    red[tid] = active ? ssum : 0.0;
     __syncthreads();
     if (tid < sp) {
         double s = 0.0;
-        for (int r = 0; r < l1 - l0; ++r) s += red[r * sp + tid];
+        for (int gg = 0; gg < nseg; ++gg)
+            for (int r = 0; r < l1 - l0; ++r) s += red[(gg * kChunkLines + r) * sp + tid];
         part[((int64_t)p * maxch + blockIdx.y) * kMaxSamples + tid] = s;
     }
 }
@@ -1279,23 +1286,26 @@ __global__ __launch_bounds__(64) void norms_kernel(const PatchDesc* pd, int p0, 
 }
 
 // ------------------------------------------------------------ restriction (a7)
-// grid (patch, chunk of kRestrictChunk outputs); Y column-major.
-constexpr int kRestrictChunk = 4096;
+// grid (patch, tile of kRestrictRows rows of Y), every sample column of the
+// tile.  The iterate is sample-fastest and Y column-major (row-fastest), so
+// the tile passes through LDS: both the gather and the store are contiguous.
+constexpr int kRestrictRows = 64;
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void restrict_kernel(const PatchDesc* pd, int p0, const double* __restrict__ x64_all,
                                                             const double* __restrict__ om, const double* __restrict__ vw,
                                                             double* __restrict__ Y_all) {
+    constexpr int LDT = kMaxSamples + 1;
+    __shared__ double tile[kRestrictRows * LDT];
     const PatchDesc P = pd[p0 + blockIdx.x];
-    const int n = P.nrows * P.s;
-    const int o0 = blockIdx.y * kRestrictChunk;
-    if (o0 >= n) return;
-    const int o1 = min(n, o0 + kRestrictChunk);
+    const int r0 = blockIdx.y * kRestrictRows;
+    if (r0 >= P.nrows) return;
+    const int nr = min(kRestrictRows, P.nrows - r0), ns = P.s, n = nr * ns;
     const double* X = x64_all + P.x_off;
     const double* O = om + P.om_off;
     double* Y = Y_all + P.Y_off;
     const int64_t lstride = (int64_t)P.bp * P.sp;
-    for (int o = o0 + threadIdx.x; o < o1; o += kThreads) {
-        const int c = o / P.nrows, row = o - c * P.nrows;
+    for (int o = threadIdx.x; o < n; o += kThreads) {
+        const int rr = o / ns, c = o - rr * ns, row = r0 + rr;
         double v;
         if (KIND == kElliptic) {
             const int W = P.nH + 1;
@@ -1314,7 +1324,12 @@ __global__ __launch_bounds__(kThreads) void restrict_kernel(const PatchDesc* pd,
             else if (lc < 0) v = vw[j] > 0 ? O[(int64_t)c * P.nb + (j - h)] : 0.0;
             else v = vw[j] < 0 ? O[(int64_t)c * P.nb + h + j] : 0.0;
         }
-        Y[o] = v;
+        tile[rr * LDT + c] = v;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < n; o += kThreads) {
+        const int c = o / nr, rr = o - c * nr;
+        Y[(int64_t)c * P.nrows + r0 + rr] = tile[rr * LDT + c];
     }
 }
 
@@ -1505,9 +1520,9 @@ void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it) {
 
 void launch_restrict(Ctx& c, int p0, int p1) {
     StageTimer t(c, MSRS_K_RESTRICT);
-    int64_t maxn = 0;
-    for (int p = p0; p < p1; ++p) maxn = std::max<int64_t>(maxn, (int64_t)c.hp[p].nrows * c.hp[p].s);
-    const dim3 grid(p1 - p0, (int)((maxn + kRestrictChunk - 1) / kRestrictChunk));
+    int maxrows = 0;
+    for (int p = p0; p < p1; ++p) maxrows = std::max(maxrows, c.hp[p].nrows);
+    const dim3 grid(p1 - p0, (maxrows + kRestrictRows - 1) / kRestrictRows);
     if (c.kind == kElliptic)
         hipLaunchKernelGGL((restrict_kernel<kElliptic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.x64, c.om, c.vw, c.Y);
     else
