@@ -250,6 +250,53 @@ def build_model(cfg, precision=1):
     return pr, ts
 
 
+def run_constrained(reps=50):
+    """The two online formulations on the h=1/64 workload with full bases on
+    the boundary patches (4x4 patches, buffers of 8 cells, k=8 sampled on the
+    interior): plain least squares against the constrained variant (Dirichlet
+    rows exact).  Set-up time (msrs_assemble_coarse), device time of one
+    batched solve of 1 and of 32 requests (events on the handle's stream,
+    mean over reps), and the largest boundary mismatch |u - phi| on dOmega."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1807_08848_amd import msrs
+    N, M, k = 64, 4, 8
+    a = torch.tensor(synth.periodic_coefficient(N, 1.0 / 8.0), device="cuda:0")
+    phis = torch.tensor(synth.fourier_boundary(N, range(32)), device="cuda:0")
+    b = np.array([(i, 0) for i in range(N)] + [(N, j) for j in range(N)] + [(i, N) for i in range(N, 0, -1)]
+                 + [(0, j) for j in range(N, 0, -1)])
+    bidx = torch.tensor(b[:, 1] * (N + 1) + b[:, 0], device="cuda:0")
+    out = {"workload": f"elliptic_periodic_N{N}_M{M}_k{k}, full bases on the boundary patches"}
+    for name, extra in (("least_squares", 0), ("constrained", msrs.FLAG_CONSTRAINED_BC)):
+        d = msrs.make_desc(msrs.KIND_ELLIPTIC_Q1, N, M, [8] * (M * M), k, k, precision=msrs.PREC_FP32_IR, seed=2,
+                           flags=msrs.FLAG_FULL_BASIS_BOUNDARY | extra)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream), msrs.Problem(d, stream=stream) as pr:
+            pr.assemble_patch(a)
+            pr.sample_local_solutions()
+            pr.range_finder()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pr.assemble_coarse()
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t0
+            u = torch.empty((32, (N + 1) ** 2), device="cuda:0", dtype=torch.float64)
+            res = {"setup_ms": ts * 1e3}
+            for nb in (1, 32):
+                pr.solve_global(phis[:nb], u[:nb])
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    pr.solve_global(phis[:nb], u[:nb])
+                e1.record(stream)
+                e1.synchronize()
+                res[f"solve_ms_batch{nb}"] = e0.elapsed_time(e1) / reps
+            res["max_boundary_mismatch"] = float((u[:, bidx] - phis).abs().max())
+            out[name] = res
+    return out
+
+
 def run_serving(lams=(200, 500, 1000, 2000), seconds=2.0, seed_arrival=5):
     """Online stage over two resident models (h = 1/512 and h = 1/1024 domains).
 
@@ -429,6 +476,8 @@ def main():
     if not args.no_serve:
         print("[bench] online serving (two resident models)", file=sys.stderr, flush=True)
         out["online"] = run_serving()
+        print("[bench] online formulations: least squares vs constrained", file=sys.stderr, flush=True)
+        out["online_constrained"] = run_constrained()
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -95,6 +95,14 @@ typedef int32_t msrs_status;
  * full (delta) basis of its 4 N/M boundary nodes instead of random samples
  * (needs 4 N/M <= 64); interior patches are sampled as usual */
 #define MSRS_FLAG_FULL_BASIS_BOUNDARY 8u
+/* elliptic, with MSRS_FLAG_FULL_BASIS_BOUNDARY: the constrained alternative
+ * of the online least-squares problem (Sec. 5.2, after eq.
+ * elliptic_cond_reduced): the Dirichlet rows hold exactly and only the
+ * continuity rows are minimized.  The full bases on the boundary patches make
+ * the constraint satisfiable for any boundary data.  Needs at most 1024
+ * Dirichlet rows (one per boundary patch and node of it on the domain
+ * boundary); msrs_solve_global_banded does not support it. */
+#define MSRS_FLAG_CONSTRAINED_BC 16u
 
 typedef struct msrs_ctx* msrs_handle;
 
@@ -230,8 +238,12 @@ msrs_status msrs_range_finder(msrs_handle h, double* Q_out_dev, double* sv_out_d
  * Online set-up (eqs. elliptic_cond_tilde / gb3): boundary traces and
  * conormal fluxes of the bases, the normal-equations matrix of the
  * least-squares system and its FP64 Cholesky factor, kept resident.
- * Synchronises the stream.  Errors: STATE, OOM; NOT_SPD if P~ is rank
- * deficient.
+ * With MSRS_FLAG_CONSTRAINED_BC also the constrained solution operator
+ * G_C = K^{-1} B^T S^{-1} E (K = P~^T P~, B the Dirichlet rows,
+ * S = B K^{-1} B^T, E the gather of the boundary data at the rows' nodes):
+ * the stationarity condition of the Lagrangian with B^T B c = B^T phi added
+ * to both sides.  Synchronises the stream.  Errors: STATE, OOM; ARG (more
+ * than 1024 Dirichlet rows); NOT_SPD if P~ (or S) is rank deficient.
  */
 msrs_status msrs_assemble_coarse(msrs_handle h);
 
@@ -249,8 +261,9 @@ msrs_status msrs_assemble_coarse(msrs_handle h);
  * partition-of-unity average.  Calls on one stream reuse one internal
  * workspace in stream order; calls on up to four different streams may
  * overlap, each taking a workspace that is no longer in use on the device,
- * and a call that finds none fails with MSRS_ERR_BUSY.  Errors: ARG (n_req
- * outside [1, max_batch]), STATE, BUSY.
+ * and a call that finds none fails with MSRS_ERR_BUSY.  With
+ * MSRS_FLAG_CONSTRAINED_BC the coefficients are c = G_C f instead (the same
+ * cost).  Errors: ARG (n_req outside [1, max_batch]), STATE, BUSY.
  */
 msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev,
                               void* stream);
@@ -259,7 +272,8 @@ msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev,
  * The same solve by the plain direct method, one request after another:
  * d~ = P~^T d and two band triangular solves with the Cholesky factor of
  * P~^T P~ per request, then the reconstruction.  Same arguments, layouts
- * and errors as msrs_solve_global; results agree to rounding.
+ * and errors as msrs_solve_global; results agree to rounding.  STATE for a
+ * handle with MSRS_FLAG_CONSTRAINED_BC.
  */
 msrs_status msrs_solve_global_banded(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev,
                                      void* stream);

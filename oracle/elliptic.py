@@ -363,6 +363,39 @@ def online(N, M, patches, a_flat, phi):
     return reconstruct(N, M, patches, off, c)[:, 0] if np.ndim(phi) == 1 else reconstruct(N, M, patches, off, c)
 
 
+def coarse_solve_constrained(P, n_cont, drows, phi):
+    """The constrained least-squares alternative of Sec. 5.2 (after eq.
+    elliptic_cond_reduced): minimize the continuity rows ||A c||_2 (value and
+    flux mismatch) subject to the Dirichlet rows B c = phi holding exactly.
+
+    Null-space method: a particular solution c_0 of B c = phi (minimum norm),
+    an orthonormal basis Z of null(B), and c = c_0 + Z y with
+    y = argmin ||A (c_0 + Z y)||_2.  The constraint must be satisfiable for
+    every phi: B needs full row rank, which holds when the patches touching
+    the boundary keep their full bases; otherwise ValueError.
+    """
+    phi = np.asarray(phi, dtype=np.float64)
+    if phi.ndim == 1:
+        phi = phi[:, None]
+    A, B = P[:n_cont], P[n_cont:]
+    sv = np.linalg.svd(B, compute_uv=False)
+    if sv.size < B.shape[0] or sv[-1] <= 1e-10 * sv[0]:
+        raise ValueError("Dirichlet rows are rank deficient: the boundary condition cannot hold exactly")
+    rhs = phi[drows, :]
+    c0 = np.linalg.lstsq(B, rhs, rcond=None)[0]
+    Z = sla.null_space(B)
+    y = np.linalg.lstsq(A @ Z, -(A @ c0), rcond=None)[0]
+    return c0 + Z @ y
+
+
+def online_constrained(N, M, patches, a_flat, phi):
+    """Global solution from the constrained least-squares coefficients."""
+    P, n_cont, drows, off = coarse_rows(N, M, patches, a_flat)
+    c = coarse_solve_constrained(P, n_cont, drows, phi)
+    u = reconstruct(N, M, patches, off, c)
+    return u[:, 0] if np.ndim(phi) == 1 else u
+
+
 # ---------------------------------------------------------------- brute force
 def global_solve(a_flat, N, phi) -> np.ndarray:
     """Fine-grid FE solution on all (N+1)^2 nodes with Dirichlet phi (the reference solution)."""

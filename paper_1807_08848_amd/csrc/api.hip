@@ -188,9 +188,17 @@ msrs_status validate(const msrs_problem_desc* d, std::string& msg) {
             msg = "full basis on boundary patches needs 4 N/M <= 64 boundary nodes";
             return MSRS_ERR_ARG;
         }
+        if ((d->flags & MSRS_FLAG_CONSTRAINED_BC) && !(d->flags & MSRS_FLAG_FULL_BASIS_BOUNDARY)) {
+            msg = "the constrained least-squares variant needs MSRS_FLAG_FULL_BASIS_BOUNDARY";
+            return MSRS_ERR_ARG;
+        }
     } else {
         if (d->n_vel < 2 || d->n_vel > 64 || (d->n_vel & 1)) { msg = "n_vel must be even, 2..64"; return MSRS_ERR_ARG; }
         if (!(d->hg_g > -1.0 && d->hg_g < 1.0)) { msg = "hg_g must be in (-1, 1)"; return MSRS_ERR_ARG; }
+        if (d->flags & (MSRS_FLAG_CONSTRAINED_BC | MSRS_FLAG_FULL_BASIS_BOUNDARY)) {
+            msg = "MSRS_FLAG_FULL_BASIS_BOUNDARY and MSRS_FLAG_CONSTRAINED_BC are elliptic options";
+            return MSRS_ERR_ARG;
+        }
         if (!(d->eps > 0)) { msg = "eps must be positive"; return MSRS_ERR_ARG; }
         if (d->M < 2) { msg = "kinetic needs M >= 2"; return MSRS_ERR_ARG; }
         if (d->n_cells / d->M < 1) { msg = "patch too small"; return MSRS_ERR_ARG; }
@@ -441,6 +449,8 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->nv = desc->kind == MSRS_KIND_KINETIC_DO ? desc->n_vel : 0;
         c->seed = desc->seed;
         c->flags = desc->flags;
+        c->constrained = desc->kind == MSRS_KIND_ELLIPTIC_Q1 && (desc->flags & MSRS_FLAG_CONSTRAINED_BC);
+        c->nF = c->constrained ? 4 * desc->n_cells : 0;
         c->timing = (desc->flags & MSRS_FLAG_TIMING) != 0;
         c->budget = hbm_budget_bytes;
         const int np = c->kind == kElliptic ? c->M * c->M : c->M;
@@ -937,7 +947,7 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
             c->GT = dalloc<double>(*c, (int64_t)c->Np * c->nB);
             for (auto& w : c->ws) {
                 w.cbuf = dalloc<double>(*c, (int64_t)c->Np * kOutPerLaunch);
-                w.gbuf = dalloc<double>(*c, (int64_t)c->nB * kOutPerLaunch);
+                w.gbuf = dalloc<double>(*c, (int64_t)std::max(c->nB, c->nF) * kOutPerLaunch);
                 MSRS_HIP_CHECK(hipEventCreateWithFlags(&w.done, hipEventDisableTiming));
             }
             if (c->budget && (size_t)c->bytes > c->budget) return fail(c, MSRS_ERR_OOM, "coarse factor exceeds the HBM budget");
@@ -949,13 +959,38 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
             if (c->nB) MSRS_HIP_CHECK(hipMemcpy(c->bmap, bmap.data(), sizeof(int32_t) * bmap.size(), hipMemcpyHostToDevice));
         }
         coarse_setup(*c);
+        if (c->constrained) {
+            const std::vector<int32_t> rows = constrained_rows(*c);
+            const int nC = (int)rows.size() / 3;
+            if (nC < 1 || nC > 1024) return fail(c, MSRS_ERR_ARG, "the constrained variant needs 1..1024 Dirichlet rows");
+            if (!c->cons_rows) {
+                // the rows are fixed by the geometry; the boundary unknowns are at most nB_cap
+                const int64_t nBc = c->nB_cap, nF = c->nF;
+                c->cons_rows = dalloc<int32_t>(*c, 3LL * nC);
+                const int64_t sz[7] = {nC * nBc, nBc * nBc, nC * nBc, (int64_t)nC * nC, (int64_t)nC * nC, nC * nF, nBc * nF};
+                for (int64_t n : sz) c->cons_ws.push_back(dalloc<double>(*c, n));
+                c->GC = dalloc<double>(*c, (int64_t)c->Np_cap * nF);
+                c->GCT = dalloc<double>(*c, (int64_t)c->Np_cap * nF);
+                c->cons_cap_C = nC;
+                if (c->budget && (size_t)c->bytes > c->budget) return fail(c, MSRS_ERR_OOM, "constrained set-up exceeds the HBM budget");
+            }
+            if (nC != c->cons_cap_C) return fail(c, MSRS_ERR_STATE, "Dirichlet rows changed since the first set-up");
+            c->nC = nC;
+            MSRS_HIP_CHECK(hipMemcpy(c->cons_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice));
+            const auto& v = c->cons_ws;
+            coarse_constrained_setup(*c, ConsWs{c->cons_rows, v[0], v[1], v[2], v[3], v[4], v[5], v[6]});
+        }
         MSRS_HIP_CHECK(hipGetLastError());
         sync_flags(*c);
     } catch (const HipError& e) {
         return hip_fail(c, e);
     }
     msrs_status st = MSRS_OK;
-    if (c->hflags[0]) { st = MSRS_ERR_NOT_SPD; c->err = "normal equations not positive definite (P~ rank deficient)"; }
+    if (c->hflags[0]) {
+        st = MSRS_ERR_NOT_SPD;
+        c->err = c->constrained ? "normal equations or constraint system not positive definite (P~ or its Dirichlet rows rank deficient)"
+                                : "normal equations not positive definite (P~ rank deficient)";
+    }
     if (st == MSRS_OK) c->coarse_ready = true;
     return st;
 }
@@ -963,6 +998,8 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
 static msrs_status solve_common(Ctx* c, int32_t n_req, const double* f_dev, double* u_dev, void* stream, bool banded) {
     if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
     if (!c->coarse_ready) return fail(c, MSRS_ERR_STATE, "msrs_assemble_coarse must come first");
+    if (banded && c->constrained)
+        return fail(c, MSRS_ERR_STATE, "the banded path solves the plain least-squares system only");
     if (n_req < 1 || n_req > c->max_batch) return fail(c, MSRS_ERR_ARG, "n_req must be in [1, max_batch]");
     if (!f_dev || !u_dev) return fail(c, MSRS_ERR_ARG, "f_dev / u_dev is NULL");
     try {

@@ -24,14 +24,14 @@ namespace msrs {
 // element matrix of the bilinear element (times 6), local order SW SE NE NW
 __device__ __constant__ double kKref6[16] = {4, -1, -2, -1, -1, 4, -1, -2, -2, -1, 4, -1, -1, -2, -1, 4};
 
-__device__ __forceinline__ void kbnode(int t, int nH, int& ii, int& jj) {
+__host__ __device__ __forceinline__ void kbnode(int t, int nH, int& ii, int& jj) {
     if (t < nH) { ii = t; jj = 0; }
     else if (t < 2 * nH) { ii = nH; jj = t - nH; }
     else if (t < 3 * nH) { ii = 3 * nH - t; jj = nH; }
     else { ii = 0; jj = 4 * nH - t; }
 }
 
-__device__ __forceinline__ int kb_index(int ii, int jj, int nH) {
+__host__ __device__ __forceinline__ int kb_index(int ii, int jj, int nH) {
     if (jj == 0 && ii < nH) return ii;
     if (ii == nH && jj < nH) return nH + jj;
     if (jj == nH && ii > 0) return 2 * nH + (nH - ii);
@@ -39,7 +39,7 @@ __device__ __forceinline__ int kb_index(int ii, int jj, int nH) {
 }
 
 // global boundary index (counter-clockwise from (0,0)) of node (gx, gy) on dOmega
-__device__ __forceinline__ int gb_index(int gx, int gy, int N) { return kb_index(gx, gy, N); }
+__host__ __device__ __forceinline__ int gb_index(int gx, int gy, int N) { return kb_index(gx, gy, N); }
 
 // ------------------------------------------------------------ elliptic traces
 // tr layout per patch: [values 4nH x ncols][fluxes 4nH x ncols], row-major (t, col).
@@ -620,6 +620,125 @@ void coarse_setup(Ctx& c) {
     hipLaunchKernelGGL(transpose_kernel, dim3((c.Np + 63) / 64, (c.nB + 63) / 64), dim3(kThreads), 0, c.stream, c.GB, c.Np, c.nB, c.GT);
 }
 
+// ------------------------------------------------------------ constrained least squares (elliptic)
+// Dirichlet rows held exactly, continuity rows minimized (the constrained
+// alternative of Sec. 5.2, after eq. elliptic_cond_reduced).  With
+// K = P~^T P~ (factored above), A the continuity rows and B the Dirichlet
+// rows, the Lagrangian's stationarity A^T A c + B^T l = 0 plus
+// B^T B c = B^T phi on both sides gives K c = B^T (phi - l); the constraint
+// then fixes nu = phi - l by S nu = phi_B, S = B K^{-1} B^T (SPD when B has
+// full row rank).  So c = G_B B_B^T S^{-1} E f =: G_C f, with B_B the
+// Dirichlet rows on the boundary-patch unknowns and E the gather of the
+// boundary data at the rows' nodes: one dense pass per request, as in the
+// least-squares path.  The set-up products are small (at most 1024 rows) and
+// run once per model.
+
+// Dirichlet rows: (patch m, node t of dK_m in kbnode order, global boundary
+// index of the node) for every boundary patch and node of it on dOmega.
+std::vector<int32_t> constrained_rows(const Ctx& c) {
+    std::vector<int32_t> rows;
+    for (int m : c.bpatch) {
+        const int m1 = m % c.M, m2 = m / c.M, nH = c.hp[m].nH;
+        for (int t = 0; t < 4 * nH; ++t) {
+            int ii, jj;
+            kbnode(t, nH, ii, jj);
+            const int gx = m1 * nH + ii, gy = m2 * nH + jj;
+            if (gx == 0 || gx == c.N || gy == 0 || gy == c.N) {
+                rows.push_back(m);
+                rows.push_back(t);
+                rows.push_back(gb_index(gx, gy, c.N));
+            }
+        }
+    }
+    return rows;
+}
+
+// BB (nC x nB, column-major, zeroed): row rho holds the values at its node of
+// its patch's basis functions, in that patch's boundary columns.
+__global__ __launch_bounds__(kThreads) void cons_bb_kernel(const CoarseDesc* __restrict__ cd, const double* __restrict__ tr,
+                                                           int64_t tr_stride, const int32_t* __restrict__ rows, int nC,
+                                                           double* __restrict__ BB) {
+    const int rho = blockIdx.x;
+    const int m = rows[3 * rho], t = rows[3 * rho + 1];
+    const int km = cd[m].ncols, bo = cd[m].b_off;
+    const double* T = tr + (int64_t)m * tr_stride;
+    for (int a = threadIdx.x; a < km; a += kThreads) BB[(int64_t)(bo + a) * nC + rho] = T[(int64_t)t * km + a];
+}
+
+// H (nB x nB, column-major) = the rows bmap of G_B.
+__global__ __launch_bounds__(kThreads) void gather_rows_kernel(const double* __restrict__ GB, int Np, const int32_t* __restrict__ bmap,
+                                                               int nB, double* __restrict__ H) {
+    const int64_t n = (int64_t)nB * nB;
+    for (int64_t o = blockIdx.x * (int64_t)kThreads + threadIdx.x; o < n; o += (int64_t)gridDim.x * kThreads) {
+        const int i = (int)(o % nB), j = (int)(o / nB);
+        H[o] = GB[(int64_t)j * Np + bmap[i]];
+    }
+}
+
+// C (m x n, column-major) = op(A) op(B), op(X) = X (ta / tb = 0) or X^T;
+// A and B column-major with leading dimensions lda, ldb.  One thread per
+// output: set-up sized products only.
+__global__ __launch_bounds__(kThreads) void gemm_small_kernel(int m, int n, int k, const double* __restrict__ A, int lda, int ta,
+                                                              const double* __restrict__ B, int ldb, int tb, double* __restrict__ C) {
+    const int64_t tot = (int64_t)m * n;
+    for (int64_t o = blockIdx.x * (int64_t)kThreads + threadIdx.x; o < tot; o += (int64_t)gridDim.x * kThreads) {
+        const int i = (int)(o % m), j = (int)(o / m);
+        double s = 0.0;
+        for (int p = 0; p < k; ++p) {
+            const double a = ta ? A[(int64_t)i * lda + p] : A[(int64_t)p * lda + i];
+            const double b = tb ? B[(int64_t)p * ldb + j] : B[(int64_t)j * ldb + p];
+            s = fma(a, b, s);
+        }
+        C[o] = s;
+    }
+}
+
+// Lower band of the dense symmetric S (n x n, column-major) with bw = n - 1:
+// band[j n + d] = S[j + d, j].
+__global__ __launch_bounds__(kThreads) void dense_to_band_kernel(const double* __restrict__ S, int n, double* __restrict__ band) {
+    const int64_t tot = (int64_t)n * n;
+    for (int64_t o = blockIdx.x * (int64_t)kThreads + threadIdx.x; o < tot; o += (int64_t)gridDim.x * kThreads) {
+        const int j = (int)(o / n), d = (int)(o % n);
+        band[o] = j + d < n ? S[(int64_t)j * n + j + d] : 0.0;
+    }
+}
+
+// E (nC x nF, column-major, zeroed): E[rho, g(rho)] = 1.
+__global__ __launch_bounds__(kThreads) void cons_gather_kernel(const int32_t* __restrict__ rows, int nC, double* __restrict__ E) {
+    const int rho = blockIdx.x * kThreads + threadIdx.x;
+    if (rho < nC) E[(int64_t)rows[3 * rho + 2] * nC + rho] = 1.0;
+}
+
+// Copies each request's boundary data into g (r * nF + i).
+__global__ __launch_bounds__(kThreads) void copy_bdry_kernel(InPtrs in, int nF, double* __restrict__ g) {
+    const int r = blockIdx.y;
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < nF; i += gridDim.x * kThreads) g[(int64_t)r * nF + i] = in.f[r][i];
+}
+
+static dim3 grid_of(int64_t n) { return dim3((unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 4096)); }
+
+void coarse_constrained_setup(Ctx& c, const ConsWs& w) {
+    StageTimer t(c, MSRS_K_COARSE);
+    const int nC = c.nC, nB = c.nB, nF = c.nF, Np = c.Np;
+    hipStream_t st = c.stream;
+    auto gemm = [&](int m, int n, int k, const double* A, int lda, int ta, const double* B, int ldb, int tb, double* C) {
+        hipLaunchKernelGGL(gemm_small_kernel, grid_of((int64_t)m * n), dim3(kThreads), 0, st, m, n, k, A, lda, ta, B, ldb, tb, C);
+    };
+    hipLaunchKernelGGL(fill_kernel, grid_of((int64_t)nC * nB), dim3(kThreads), 0, st, w.BB, (int64_t)nC * nB, 0.0);
+    hipLaunchKernelGGL(cons_bb_kernel, dim3(nC), dim3(kThreads), 0, st, c.dc, c.tr, c.tr_stride, w.rows, nC, w.BB);
+    hipLaunchKernelGGL(gather_rows_kernel, grid_of((int64_t)nB * nB), dim3(kThreads), 0, st, c.GB, Np, c.bmap, nB, w.H);
+    gemm(nC, nB, nB, w.BB, nC, 0, w.H, nB, 0, w.X);             // X = B_B H
+    gemm(nC, nC, nB, w.X, nC, 0, w.BB, nC, 1, w.S);             // S = X B_B^T
+    hipLaunchKernelGGL(dense_to_band_kernel, grid_of((int64_t)nC * nC), dim3(kThreads), 0, st, w.S, nC, w.band);
+    hipLaunchKernelGGL(band_cholesky_kernel, dim3(1), dim3(1024), 0, st, w.band, nC, nC - 1, c.dflags);
+    hipLaunchKernelGGL(fill_kernel, grid_of((int64_t)nC * nF), dim3(kThreads), 0, st, w.W, (int64_t)nC * nF, 0.0);
+    hipLaunchKernelGGL(cons_gather_kernel, dim3((nC + kThreads - 1) / kThreads), dim3(kThreads), 0, st, w.rows, nC, w.W);
+    hipLaunchKernelGGL(band_solve_kernel, dim3((nF + 63) / 64), dim3(1024), 0, st, w.band, nC, nC - 1, w.W, nF);   // W = S^-1 E
+    gemm(nB, nF, nC, w.BB, nC, 1, w.W, nC, 0, w.V);             // V = B_B^T W
+    gemm(Np, nF, nB, c.GB, Np, 0, w.V, nB, 0, c.GC);            // G_C = G_B V
+    hipLaunchKernelGGL(transpose_kernel, dim3((Np + 63) / 64, (nF + 63) / 64), dim3(kThreads), 0, st, c.GC, Np, nF, c.GCT);
+}
+
 static void launch_recon(const Ctx& c, const double* cbuf, int n_req, const OutPtrs& out, hipStream_t st) {
     if (c.kind == kElliptic && c.N / c.M >= kTile) {
         const dim3 g((c.N + kTile) / kTile, (c.N + kTile) / kTile);
@@ -653,16 +772,20 @@ void coarse_apply(const Ctx& c, int n_req, const double* const* f, double* const
             out.u[r] = u[r0 + r];
         }
         const dim3 gb((unsigned)c.bpatch.size(), nr);
-        if (c.kind == kElliptic)
+        const int ng = c.g_len();
+        const double* GT = c.constrained ? c.GCT : c.GT;
+        if (c.constrained)
+            hipLaunchKernelGGL(copy_bdry_kernel, dim3((ng + kThreads - 1) / kThreads, nr), dim3(kThreads), 0, st, in, ng, gbuf);
+        else if (c.kind == kElliptic)
             hipLaunchKernelGGL(bdry_rhs_elliptic_kernel, gb, dim3(kThreads), 0, st, c.dp, c.dc, c.tr, c.tr_stride, c.dbpatch, c.M, c.N, in,
                                c.nB, gbuf);
         else
             hipLaunchKernelGGL(bdry_rhs_kinetic_kernel, gb, dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.vw, c.dbpatch, c.M, c.nv, in, c.nB, gbuf);
         const int rb = c.apply_batch;
         const dim3 ga((c.Np + kGRows - 1) / kGRows, (nr + rb - 1) / rb);
-        if (rb == 4) hipLaunchKernelGGL(apply_G_kernel<4>, ga, dim3(kThreads), 0, st, c.GT, c.Np, c.nB, gbuf, nr, cbuf);
-        else if (rb == 16) hipLaunchKernelGGL(apply_G_kernel<16>, ga, dim3(kThreads), 0, st, c.GT, c.Np, c.nB, gbuf, nr, cbuf);
-        else hipLaunchKernelGGL(apply_G_kernel<8>, ga, dim3(kThreads), 0, st, c.GT, c.Np, c.nB, gbuf, nr, cbuf);
+        if (rb == 4) hipLaunchKernelGGL(apply_G_kernel<4>, ga, dim3(kThreads), 0, st, GT, c.Np, ng, gbuf, nr, cbuf);
+        else if (rb == 16) hipLaunchKernelGGL(apply_G_kernel<16>, ga, dim3(kThreads), 0, st, GT, c.Np, ng, gbuf, nr, cbuf);
+        else hipLaunchKernelGGL(apply_G_kernel<8>, ga, dim3(kThreads), 0, st, GT, c.Np, ng, gbuf, nr, cbuf);
         launch_recon(c, cbuf, nr, out, st);
     }
 }

@@ -155,6 +155,16 @@ struct Ctx {
     double* band = nullptr;       // normal matrix, then its Cholesky factor (lower band)
     double* GB = nullptr;         // (P~^T P~)^{-1} restricted to the columns of boundary-patch unknowns, Np x nB
     double* GT = nullptr;         // the same, row-major (row j contiguous): the batched solve streams its rows
+    // constrained least squares (Dirichlet rows exact): G_C (Np x nF, nF = 4N)
+    // maps the global boundary data to c; GCT is it row-major
+    bool constrained = false;
+    int nC = 0, nF = 0;           // Dirichlet rows, boundary data length
+    double* GC = nullptr;
+    double* GCT = nullptr;
+    int g_len() const { return constrained ? nF : nB; }   // per-request length of the batched solve's input
+    std::vector<double*> cons_ws;  // constrained set-up workspaces (BB, H, X, S, band, W, V)
+    int32_t* cons_rows = nullptr;
+    int cons_cap_C = 0;            // rows the workspaces were sized for
     int nB = 0;                   // unknowns of the patches with Dirichlet / inflow rows
     std::vector<int32_t> bpatch;  // those patches (host), and on the device:
     int32_t* dbpatch = nullptr;
@@ -212,6 +222,21 @@ void coarse_setup(Ctx& c);     // traces, normal matrix, Cholesky (enqueued)
 // may run it at once.
 void coarse_apply(const Ctx& c, int n_req, const double* const* f, double* const* u, double* gbuf, double* cbuf,
                   hipStream_t st);
+// Constrained least squares: the Dirichlet rows (3 ints each: patch, node of
+// dK_m, global boundary index) and the set-up of G_C / GCT from G_B, with
+// workspaces sized for nC rows and nB boundary unknowns.
+struct ConsWs {
+    int32_t* rows;   // 3 nC
+    double* BB;      // nC x nB
+    double* H;       // nB x nB
+    double* X;       // nC x nB
+    double* S;       // nC x nC
+    double* band;    // nC x nC
+    double* W;       // nC x nF
+    double* V;       // nB x nF
+};
+std::vector<int32_t> constrained_rows(const Ctx& c);
+void coarse_constrained_setup(Ctx& c, const ConsWs& w);
 // Banded path: one request by P~^T d and two band triangular solves; cbuf Np.
 void coarse_banded(const Ctx& c, const double* f, double* u, double* cbuf, hipStream_t st);
 

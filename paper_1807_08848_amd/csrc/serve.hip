@@ -317,7 +317,7 @@ msrs_status msrs_server_create(msrs_server* out, const msrs_handle* models, int3
     int64_t np_max = 0, nB_max = 0;
     for (Ctx* c : s->models) {
         np_max = std::max<int64_t>(np_max, c->Np);
-        nB_max = std::max<int64_t>(nB_max, c->nB);
+        nB_max = std::max<int64_t>(nB_max, c->g_len());
     }
     if (chk(hipSetDevice(dev0), "hipSetDevice") && chk(hipMalloc((void**)&s->dslots, slot_bytes), "hipMalloc slots")) {
         s->dallocs.push_back(s->dslots);
