@@ -961,7 +961,10 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         lds_barrier();
         mfma();
         if (nst > 0) load_A(E + (int64_t)(m - dir) * BP * BP);        // the first back line, one step ahead
-        store_acc(half == 0 ? X + m * lstride : nullptr, acc64 ? X64 + m * lstride : nullptr, pre64);   // x_m (identical in both halves)
+        // x_m (identical in both halves).  With an FP64 iterate (refinement) the
+        // FP32 solution is not stored: the iterate takes it, and the line
+        // vectors are next overwritten by the residual.
+        store_acc(half == 0 && !X64 ? X + m * lstride : nullptr, acc64 ? X64 + m * lstride : nullptr, pre64);
         lds_barrier();
         for (int k = 0; k < nst; ++k) {
             launder();
@@ -992,7 +995,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
             lds_barrier();
             mfma();                                                                    // x_ln = E_ln z
             if (more) load_A(E + (int64_t)(ln - dir) * BP * BP);                     // E of the next line
-            store_acc(X + ln * lstride, X64 ? X64 + ln * lstride : nullptr, pre64);
+            store_acc(X64 ? nullptr : X + ln * lstride, X64 ? X64 + ln * lstride : nullptr, pre64);
 #pragma unroll
             for (int e = 0; e < RPT; ++e) rv[e] = rvn[e];
             crow = crown;
