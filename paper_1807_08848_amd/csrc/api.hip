@@ -482,6 +482,7 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->rf_small = dalloc<double>(*c, (int64_t)c->n_patches * 4096);
         c->rf_pval = dalloc<double>(*c, (int64_t)c->n_patches * c->rf_maxrc * 64);
         c->rf_pidx = dalloc<int32_t>(*c, (int64_t)c->n_patches * c->rf_maxrc * 64);
+        c->rf_skip = dalloc<int32_t>(*c, c->n_patches);
         c->sv = dalloc<double>(*c, c->sv_total);
         int64_t rn_total = 0;
         for (auto& P : c->hp) rn_total += 2 * P.sp;

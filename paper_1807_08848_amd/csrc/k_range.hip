@@ -4,7 +4,8 @@
 // Per patch: G = Y^T Y; cyclic Jacobi eigendecomposition G = V diag(lambda)
 // V^T, so sigma_j(Y) = sqrt(lambda_j) and Y V_j / sigma_j are the left
 // singular vectors; the k leading ones are formed and re-orthonormalised by
-// two Cholesky-QR passes (G' = W^T W = L L^T, Q = W L^{-T}, twice).  This
+// up to two Cholesky-QR passes (G' = W^T W = L L^T, Q = W L^{-T}; the second
+// only where the first one's G' was not already within 1e-4 of I).  This
 // handles rank-deficient sketches (more samples than boundary degrees of
 // freedom) with the same code path.  Each column's largest-magnitude entry is
 // made positive (first index on ties).
@@ -73,11 +74,13 @@ __device__ void gram_rows(const double* __restrict__ A, int nrows, int r0, int r
 }
 
 // grid (patch, row chunk): partial Gram of the chunk's rows -> part[(p * maxrc + chunk) * 4096]
+// (skip: patches whose flag is set have nothing to do)
 __global__ __launch_bounds__(kThreads) void gram_partial_kernel(const PatchDesc* pd, int p0, int which, const double* __restrict__ Y,
                                                                 const double* __restrict__ Q, const double* __restrict__ W,
-                                                                double* __restrict__ part, int maxrc) {
+                                                                double* __restrict__ part, int maxrc, const int32_t* __restrict__ skip) {
     __shared__ double stage[kRfStage * kRfMax];
     const int p = p0 + blockIdx.x;
+    if (skip && skip[p]) return;
     const PatchDesc P = pd[p];
     const int r0 = blockIdx.y * kRowChunk;
     if (r0 >= P.nrows) return;
@@ -290,16 +293,44 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
 // ---------------------------------------------------------------- Cholesky factor
 // One workgroup per patch: G' = sum of partials (k x k), G' = L L^T,
 // T = L^{-T} -> small[p].  A non-positive pivot latches ERR_RANK.
+// Pass 0 also decides whether pass 1 is needed: when the Gram matrix of its
+// input is within kCholQRSkip of the identity entrywise (so its condition
+// number is within 1 + 2 n kCholQRSkip of 1), one pass already leaves the
+// columns orthonormal to rounding, and pass 1 applies the identity (its Gram
+// matrix is not formed).
+constexpr double kCholQRSkip = 1e-4;
 __global__ __launch_bounds__(kThreads) void chol_kernel(const PatchDesc* pd, int p0, const double* __restrict__ part, int maxrc,
-                                                        double* __restrict__ small, int32_t* flags) {
+                                                        double* __restrict__ small, int32_t* flags, int32_t* __restrict__ skip,
+                                                        int pass) {
     __shared__ double G[kSmall];
+    __shared__ double dev[kThreads];
     __shared__ int bad;
     const int p = p0 + blockIdx.x;
     const PatchDesc P = pd[p];
     const int tid = threadIdx.x, n = P.ncols;
+    double* T = small + (int64_t)p * kSmall;
+    if (pass == 1 && skip[p]) {
+        for (int o = tid; o < kSmall; o += kThreads) T[o] = (o / kRfMax == o % kRfMax && o % kRfMax < n) ? 1.0 : 0.0;
+        return;
+    }
     const int nch = (P.nrows + kRowChunk - 1) / kRowChunk;
     if (tid == 0) bad = 0;
     sum_partials(part, p, maxrc, nch, n, G);
+    if (pass == 0) {
+        double d = 0.0;
+        for (int o = tid; o < n * n; o += kThreads) {
+            const int i = o / n, j = o % n;
+            d = fmax(d, fabs(G[i * kRfMax + j] - (i == j ? 1.0 : 0.0)));
+        }
+        dev[tid] = d;
+        __syncthreads();
+        if (tid == 0) {
+            double m = 0.0;
+            for (int t = 0; t < kThreads; ++t) m = fmax(m, dev[t]);
+            skip[p] = m <= kCholQRSkip ? 1 : 0;     // a NaN never skips
+        }
+        __syncthreads();
+    }
     for (int j = 0; j < n; ++j) {
         if (tid == 0) {
             const double d = G[j * kRfMax + j];
@@ -318,7 +349,6 @@ __global__ __launch_bounds__(kThreads) void chol_kernel(const PatchDesc* pd, int
         __syncthreads();
     }
     // column c of L^{-1} by forward substitution (thread c); T[i][c] ... stored as T[c][i] = L^{-1}[i][c]
-    double* T = small + (int64_t)p * kSmall;
     if (tid < kRfMax) {
         const int c = tid;
         for (int i = 0; i < kRfMax; ++i) {
@@ -456,7 +486,8 @@ void launch_range(Ctx& c, int p0, int p1) {
     const int mrc = c.rf_maxrc;
     hipStream_t st = c.stream;
     // snapshots: Gram, eigendecomposition, W = Y B
-    hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kY, c.Y, c.Q, c.rf_ws, c.rf_part, mrc);
+    hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kY, c.Y, c.Q, c.rf_ws, c.rf_part, mrc,
+                       (const int32_t*)nullptr);
     int maxs = 0;
     for (int p = p0; p < p1; ++p) maxs = std::max(maxs, c.hp[p].s);
     hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
@@ -465,8 +496,9 @@ void launch_range(Ctx& c, int p0, int p1) {
     // two Cholesky-QR passes: W -> Q -> W
     for (int pass = 0; pass < 2; ++pass) {
         const int src = pass == 0 ? kW : kQ, dst = pass == 0 ? kQ : kW;
-        hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, src, c.Y, c.Q, c.rf_ws, c.rf_part, mrc);
-        hipLaunchKernelGGL(chol_kernel, one, dim3(kThreads), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.dflags);
+        hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, src, c.Y, c.Q, c.rf_ws, c.rf_part, mrc,
+                           pass == 1 ? (const int32_t*)c.rf_skip : nullptr);
+        hipLaunchKernelGGL(chol_kernel, one, dim3(kThreads), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.dflags, c.rf_skip, pass);
         hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, src, dst, c.Y, c.Q, c.rf_ws, c.rf_small);
     }
     // sign fix: W -> Q

@@ -117,6 +117,7 @@ struct Ctx {
     double* rf_small = nullptr;   // per patch 64 x 64 factor (B, L^{-T}, signs)
     double* rf_pval = nullptr;    // per (patch, row chunk) column maxima
     int32_t* rf_pidx = nullptr;
+    int32_t* rf_skip = nullptr;   // per patch: the second Cholesky-QR pass is not needed
     int rf_maxrc = 1;             // row chunks per patch at most
     double* coef_copy = nullptr;  // device copy of the coefficient field (traces)
     int32_t* iters = nullptr;     // per patch refinement iterations at convergence
