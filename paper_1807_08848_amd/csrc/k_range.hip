@@ -367,11 +367,14 @@ __global__ __launch_bounds__(kThreads) void chol_kernel(const PatchDesc* pd, int
 // ---------------------------------------------------------------- tall products
 // grid (patch, row chunk): dst = src * small[p] (m x k), src / dst tall
 // matrices of the patch; a thread owns one row and 8 columns.
+// (skip: patches whose flag is set keep src as it is)
 __global__ __launch_bounds__(kThreads) void tall_gemm_kernel(const PatchDesc* pd, int p0, int src_which, int dst_which,
                                                              const double* __restrict__ Y, double* __restrict__ Q,
-                                                             double* __restrict__ W, const double* __restrict__ small) {
+                                                             double* __restrict__ W, const double* __restrict__ small,
+                                                             const int32_t* __restrict__ skip) {
     __shared__ double B[kSmall];
     const int p = p0 + blockIdx.x;
+    if (skip && skip[p]) return;
     const PatchDesc P = pd[p];
     const int r0 = blockIdx.y * kRowChunk;
     if (r0 >= P.nrows) return;
@@ -402,9 +405,12 @@ __global__ __launch_bounds__(kThreads) void tall_gemm_kernel(const PatchDesc* pd
 }
 
 // ---------------------------------------------------------------- sign fix
+// The orthonormal columns are in W after two Cholesky-QR passes, in Q where
+// the second pass was skipped (skip[p]).
 // grid (patch, row chunk): per column, the largest |W| of the chunk and its
 // first row -> parts (value, index).
 __global__ __launch_bounds__(kThreads) void sign_partial_kernel(const PatchDesc* pd, int p0, const double* __restrict__ W,
+                                                                const double* __restrict__ Qs, const int32_t* __restrict__ skip,
                                                                 double* __restrict__ pval, int32_t* __restrict__ pidx, int maxrc) {
     __shared__ double rv[kThreads];
     __shared__ int ri[kThreads];
@@ -413,7 +419,7 @@ __global__ __launch_bounds__(kThreads) void sign_partial_kernel(const PatchDesc*
     const int r0 = blockIdx.y * kRowChunk;
     if (r0 >= P.nrows) return;
     const int r1 = min(P.nrows, r0 + kRowChunk);
-    const double* A = W + P.Q_off;
+    const double* A = (skip[p] ? Qs : W) + P.Q_off;
     const int tid = threadIdx.x;
     for (int j = 0; j < P.ncols; ++j) {
         double bv = -1.0;
@@ -443,6 +449,7 @@ __global__ __launch_bounds__(kThreads) void sign_partial_kernel(const PatchDesc*
 
 // one workgroup per patch: combine the chunk maxima (first index on ties) -> sign per column in small[p][0..k)
 __global__ __launch_bounds__(kRfMax) void sign_final_kernel(const PatchDesc* pd, int p0, const double* __restrict__ W,
+                                                           const double* __restrict__ Qs, const int32_t* __restrict__ skip,
                                                            const double* __restrict__ pval, const int32_t* __restrict__ pidx,
                                                            int maxrc, double* __restrict__ small) {
     const int p = p0 + blockIdx.x;
@@ -458,22 +465,25 @@ __global__ __launch_bounds__(kRfMax) void sign_final_kernel(const PatchDesc* pd,
         if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
     }
     bi = min(max(bi, 0), P.nrows - 1);
-    small[(int64_t)p * kSmall + j] = W[P.Q_off + (int64_t)j * P.nrows + bi] < 0.0 ? -1.0 : 1.0;
+    const double* A = skip[p] ? Qs : W;
+    small[(int64_t)p * kSmall + j] = A[P.Q_off + (int64_t)j * P.nrows + bi] < 0.0 ? -1.0 : 1.0;
 }
 
-// grid (patch, row chunk): Q = W * sign(column)
-__global__ __launch_bounds__(kThreads) void sign_apply_kernel(const PatchDesc* pd, int p0, const double* __restrict__ W,
-                                                              double* __restrict__ Q, const double* __restrict__ small) {
+// grid (patch, row chunk): Q = W * sign(column), or Q *= sign(column) in place
+// (no restrict: source and destination are one array where skip[p])
+__global__ __launch_bounds__(kThreads) void sign_apply_kernel(const PatchDesc* pd, int p0, const double* W, double* Q,
+                                                              const int32_t* __restrict__ skip, const double* __restrict__ small) {
     const int p = p0 + blockIdx.x;
     const PatchDesc P = pd[p];
     const int r0 = blockIdx.y * kRowChunk;
     if (r0 >= P.nrows) return;
     const int r1 = min(P.nrows, r0 + kRowChunk), nr = r1 - r0;
+    const double* src = skip[p] ? Q : W;
     // columns past a tolerance-chosen rank are zero
     for (int o = threadIdx.x; o < nr * P.kreq; o += kThreads) {
         const int j = o / nr, r = r0 + (o - j * nr);
         const int64_t idx = P.Q_off + (int64_t)j * P.nrows + r;
-        Q[idx] = j < P.ncols ? small[(int64_t)p * kSmall + j] * W[idx] : 0.0;
+        Q[idx] = j < P.ncols ? small[(int64_t)p * kSmall + j] * src[idx] : 0.0;
     }
 }
 
@@ -492,19 +502,22 @@ void launch_range(Ctx& c, int p0, int p1) {
     for (int p = p0; p < p1; ++p) maxs = std::max(maxs, c.hp[p].s);
     hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
                        c.dflags, c.rank_tol);
-    hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kY, (int)kW, c.Y, c.Q, c.rf_ws, c.rf_small);
-    // two Cholesky-QR passes: W -> Q -> W
+    hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kY, (int)kW, c.Y, c.Q, c.rf_ws, c.rf_small,
+                       (const int32_t*)nullptr);
+    // Cholesky-QR passes: W -> Q (-> W where the second pass is needed)
     for (int pass = 0; pass < 2; ++pass) {
         const int src = pass == 0 ? kW : kQ, dst = pass == 0 ? kQ : kW;
         hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, src, c.Y, c.Q, c.rf_ws, c.rf_part, mrc,
                            pass == 1 ? (const int32_t*)c.rf_skip : nullptr);
         hipLaunchKernelGGL(chol_kernel, one, dim3(kThreads), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.dflags, c.rf_skip, pass);
-        hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, src, dst, c.Y, c.Q, c.rf_ws, c.rf_small);
+        hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, src, dst, c.Y, c.Q, c.rf_ws, c.rf_small,
+                           pass == 1 ? (const int32_t*)c.rf_skip : nullptr);
     }
     // sign fix: W -> Q
-    hipLaunchKernelGGL(sign_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, c.rf_ws, c.rf_pval, c.rf_pidx, mrc);
-    hipLaunchKernelGGL(sign_final_kernel, one, dim3(kRfMax), 0, st, c.dp, p0, c.rf_ws, c.rf_pval, c.rf_pidx, mrc, c.rf_small);
-    hipLaunchKernelGGL(sign_apply_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, c.rf_ws, c.Q, c.rf_small);
+    hipLaunchKernelGGL(sign_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, c.rf_ws, c.Q, c.rf_skip, c.rf_pval, c.rf_pidx, mrc);
+    hipLaunchKernelGGL(sign_final_kernel, one, dim3(kRfMax), 0, st, c.dp, p0, c.rf_ws, c.Q, c.rf_skip, c.rf_pval, c.rf_pidx, mrc,
+                       c.rf_small);
+    hipLaunchKernelGGL(sign_apply_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, c.rf_ws, c.Q, c.rf_skip, c.rf_small);
 }
 
 }  // namespace msrs
