@@ -304,13 +304,13 @@ void sample_enqueue(Ctx* c, const double* omega_dev, int fixed_iters) {
     for_patches(*c, [&](int p0, int p1) { launch_lift(*c, p0, p1); });
     join_factor(*c);   // the sweeps need the factor
     if (c->prec == MSRS_PREC_FP64) {
-        for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, false); });
+        for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, false, false); });
         for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, true, 0); });
         c->last_ir_iters = 0;
     } else if (fixed_iters >= 0) {
         launch_clear_conv(*c);
         for (int it = 0; it < fixed_iters; ++it) {
-            for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true); });
+            for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true, it == 0); });
             for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it); });
         }
         launch_check_conv(*c);
@@ -320,7 +320,7 @@ void sample_enqueue(Ctx* c, const double* omega_dev, int fixed_iters) {
         int it = 0;
         const int first = std::min(c->ir_max, c->ir_hint);
         for (; it < first; ++it) {
-            for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true); });
+            for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true, it == 0); });
             for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it); });
         }
         // continue until every patch has converged (one host check per extra iteration)
@@ -333,7 +333,7 @@ void sample_enqueue(Ctx* c, const double* omega_dev, int fixed_iters) {
                 if (!all) launch_check_conv(*c);
                 break;
             }
-            for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true); });
+            for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true, it == 0); });
             for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it); });
             ++it;
         }

@@ -123,13 +123,11 @@ __device__ __forceinline__ void partial_column_sums(double ssum, const LineMap& 
     }
 }
 
-// rhs = -A_IB omega into the line vectors X (FP64 or FP32), padding zeroed;
-// x64zero (if given) is zeroed.
+// rhs = -A_IB omega into the line vectors X (FP64 or FP32), padding zeroed.
 template <int KIND, typename TX>
 __global__ __launch_bounds__(kThreads) void lift_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
                                                         const double* __restrict__ om, const double* __restrict__ vw, double dx,
-                                                        TX* __restrict__ X, double* __restrict__ x64zero,
-                                                        double* __restrict__ part, int maxch) {
+                                                        TX* __restrict__ X, double* __restrict__ part, int maxch) {
     __shared__ double red[kThreads];
     const int p = p0 + blockIdx.x;
     const PatchDesc P = pd[p];
@@ -168,7 +166,6 @@ __global__ __launch_bounds__(kThreads) void lift_kernel(const PatchDesc* pd, int
             }
             const int64_t o = P.x_off + (int64_t)l * bp * sp + (int64_t)i * sp + c;
             X[o] = (TX)v;
-            if (x64zero) x64zero[o] = 0.0;
             ssum += v * v;
         }
     }
@@ -937,11 +934,14 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         // ln = m - dir (k + 1) from pv = ln + dir.  Its right-hand side y_ln, the
         // shared cell row and (FP32 refinement) the FP64 iterate of the line are
         // loaded one step ahead, E_ln during the step before.
+        // PHASE 2 is the first solve of a refinement: the FP64 iterate holds
+        // nothing yet and is written, not accumulated (pre64 stays zero).
         launder();
+        constexpr bool kAccum = PHASE == 1;
         double pre64[NCT][4] = {}, pre64n[NCT][4] = {};
         load_A(E + (int64_t)m * BP * BP);
         const bool acc64 = X64 && half == 0;   // line m's iterate is updated once, by the top half
-        if (acc64) load_64(X64 + m * lstride, pre64);
+        if (kAccum && acc64) load_64(X64 + m * lstride, pre64);
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
             const int i = li0 + e * DI;
@@ -956,7 +956,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
             const int l1 = m - dir;
             load_line(X + l1 * lstride, rv);
             if (KIND == kElliptic && tid <= b) crow = aL[(dir > 0 ? m : l1) * L + tid];
-            if (X64) load_64(X64 + l1 * lstride, pre64n);
+            if (kAccum && X64) load_64(X64 + l1 * lstride, pre64n);
         }
         lds_barrier();
         mfma();
@@ -980,7 +980,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
                 const int l2 = ln - dir;
                 load_line(X + l2 * lstride, rvn);                                     // y of the next step
                 if (KIND == kElliptic && tid <= b) crown = aL[(dir > 0 ? ln : l2) * L + tid];
-                if (X64) load_64(X64 + l2 * lstride, pre64n);
+                if (kAccum && X64) load_64(X64 + l2 * lstride, pre64n);
             }
             if (KIND == kElliptic && tid <= b) craw[tid] = crow * (-1.0 / 3.0);
             lds_barrier();
@@ -1371,11 +1371,11 @@ void launch_lift(Ctx& c, int p0, int p1) {
     const bool ir = c.prec == MSRS_PREC_FP32_IR;
     const dim3 grid(p1 - p0, max_chunks(c, p0, p1));
     if (c.kind == kElliptic) {
-        if (ir) hipLaunchKernelGGL((lift_kernel<kElliptic, float>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x32, c.x64, c.part, c.maxch);
-        else hipLaunchKernelGGL((lift_kernel<kElliptic, double>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, (double*)nullptr, c.part, c.maxch);
+        if (ir) hipLaunchKernelGGL((lift_kernel<kElliptic, float>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x32, c.part, c.maxch);
+        else hipLaunchKernelGGL((lift_kernel<kElliptic, double>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, c.part, c.maxch);
     } else {
-        if (ir) hipLaunchKernelGGL((lift_kernel<kKinetic, float>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x32, c.x64, c.part, c.maxch);
-        else hipLaunchKernelGGL((lift_kernel<kKinetic, double>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, (double*)nullptr, c.part, c.maxch);
+        if (ir) hipLaunchKernelGGL((lift_kernel<kKinetic, float>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x32, c.part, c.maxch);
+        else hipLaunchKernelGGL((lift_kernel<kKinetic, double>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, c.part, c.maxch);
     }
     hipLaunchKernelGGL(norms_kernel, dim3(p1 - p0), dim3(64), 0, c.stream, c.dp, p0, c.part, c.maxch, c.rn, 0, (int32_t*)nullptr,
                        (double*)nullptr, (int32_t*)nullptr, 0, 0.0);
@@ -1466,7 +1466,7 @@ static int sweep_chunk(const Ctx& c, int p0, int p1, bool fp32) {
     return 16;
 }
 
-void launch_sweep(Ctx& c, int p0, int p1, bool fp32) {
+void launch_sweep(Ctx& c, int p0, int p1, bool fp32, bool first) {
     StageTimer t(c, MSRS_K_SWEEP);
     int maxsp = 0;
     for (int p = p0; p < p1; ++p) maxsp = std::max(maxsp, c.hp[p].sp);
@@ -1483,8 +1483,20 @@ void launch_sweep(Ctx& c, int p0, int p1, bool fp32) {
         hipLaunchKernelGGL((sweep_kernel<TT, KK, NN, 1>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, \
                            x64acc, (TT*)c.tw, conv, c.dflags);                                                                 \
     } while (0)
+    // the first solve of a refinement writes the FP64 iterate instead of adding to it
+#define MSRS_SWEEP_FIRST(KK, NN)                                                                                               \
+    do {                                                                                                                      \
+        hipLaunchKernelGGL((sweep_kernel<float, KK, NN, 0>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const float*)c.E, \
+                           c.x32, (double*)nullptr, (float*)c.tw, conv, c.dflags);                                            \
+        hipLaunchKernelGGL((sweep_kernel<float, KK, NN, 2>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const float*)c.E, \
+                           c.x32, x64acc, (float*)c.tw, conv, c.dflags);                                                      \
+    } while (0)
     if (c.kind == kElliptic) {
-        if (fp32) {
+        if (fp32 && first) {
+            if (sc == 64) MSRS_SWEEP_FIRST(kElliptic, 4);
+            else if (sc == 32) MSRS_SWEEP_FIRST(kElliptic, 2);
+            else MSRS_SWEEP_FIRST(kElliptic, 1);
+        } else if (fp32) {
             if (sc == 64) MSRS_SWEEP(float, kElliptic, 4, c.x32);
             else if (sc == 32) MSRS_SWEEP(float, kElliptic, 2, c.x32);
             else MSRS_SWEEP(float, kElliptic, 1, c.x32);
@@ -1493,7 +1505,11 @@ void launch_sweep(Ctx& c, int p0, int p1, bool fp32) {
             else MSRS_SWEEP(double, kElliptic, 1, c.x64);
         }
     } else {
-        if (fp32) {
+        if (fp32 && first) {
+            if (sc == 64) MSRS_SWEEP_FIRST(kKinetic, 4);
+            else if (sc == 32) MSRS_SWEEP_FIRST(kKinetic, 2);
+            else MSRS_SWEEP_FIRST(kKinetic, 1);
+        } else if (fp32) {
             if (sc == 64) MSRS_SWEEP(float, kKinetic, 4, c.x32);
             else if (sc == 32) MSRS_SWEEP(float, kKinetic, 2, c.x32);
             else MSRS_SWEEP(float, kKinetic, 1, c.x32);
@@ -1503,6 +1519,7 @@ void launch_sweep(Ctx& c, int p0, int p1, bool fp32) {
         }
     }
 #undef MSRS_SWEEP
+#undef MSRS_SWEEP_FIRST
 }
 
 void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it) {

@@ -208,7 +208,7 @@ void launch_omega(Ctx& c, const double* user, int p0, int p1);
 void launch_lift(Ctx& c, int p0, int p1);
 void launch_factor(Ctx& c, int p0, int p1);
 void join_factor(Ctx& c);
-void launch_sweep(Ctx& c, int p0, int p1, bool fp32);
+void launch_sweep(Ctx& c, int p0, int p1, bool fp32, bool first);   // first: the first solve of a refinement
 void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it);
 void launch_restrict(Ctx& c, int p0, int p1);
 void launch_range(Ctx& c, int p0, int p1);
