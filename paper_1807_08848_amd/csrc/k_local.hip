@@ -141,9 +141,12 @@ __global__ __launch_bounds__(kThreads) void lift_kernel(const PatchDesc* pd, int
     const int c = m.col;
     double ssum = 0.0;
     for (int l = l0; l < l1; ++l) {
+        // only nodes next to the buffered patch's boundary (first / last line,
+        // first / last row) have boundary neighbours
+        const bool edge_line = l == 0 || l == nl - 1;
         for (int i = m.row0; m.active && i < bp; i += m.rows) {
             double v = 0.0;
-            if (i < b && c < P.s) {
+            if (i < b && c < P.s && (edge_line || i == 0 || i == b - 1)) {
                 if (KIND == kElliptic) {
                     const int pp = i + 1, q = l + 1;
 #pragma unroll
