@@ -1305,38 +1305,43 @@ __global__ __launch_bounds__(kThreads) void restrict_kernel(const PatchDesc* pd,
     const PatchDesc P = pd[p0 + blockIdx.x];
     const int r0 = blockIdx.y * kRestrictRows;
     if (r0 >= P.nrows) return;
-    const int nr = min(kRestrictRows, P.nrows - r0), ns = P.s, n = nr * ns;
+    const int nr = min(kRestrictRows, P.nrows - r0), ns = P.s;
     const double* X = x64_all + P.x_off;
     const double* O = om + P.om_off;
     double* Y = Y_all + P.Y_off;
     const int64_t lstride = (int64_t)P.bp * P.sp;
-    for (int o = threadIdx.x; o < n; o += kThreads) {
-        const int rr = o / ns, c = o - rr * ns, row = r0 + rr;
-        double v;
+    // gather: 32 lanes along the samples, 8 rows at a time; the row's
+    // position is resolved once per row, not per value
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int rr = ty; rr < nr; rr += kThreads / 32) {
+        const int row = r0 + rr;
         if (KIND == kElliptic) {
             const int W = P.nH + 1;
             const int jj = row / W, ii = row - jj * W;
             const int ip = P.kx0 - P.x0 + ii, jp = P.ky0 - P.y0 + jj;
             const int pl = P.trans ? jp : ip, ql = P.trans ? ip : jp;
-            if (pl >= 1 && pl <= P.L - 1 && ql >= 1 && ql <= P.Qn - 1)
-                v = X[(int64_t)(ql - 1) * lstride + (int64_t)(pl - 1) * P.sp + c];
-            else
-                v = O[(int64_t)c * P.nb + bidx_ccw(ip, jp, P.cx, P.cy)];
+            const bool inner = pl >= 1 && pl <= P.L - 1 && ql >= 1 && ql <= P.Qn - 1;
+            const double* src = inner ? X + (int64_t)(ql - 1) * lstride + (int64_t)(pl - 1) * P.sp : nullptr;
+            const int bi = inner ? 0 : bidx_ccw(ip, jp, P.cx, P.cy);
+            for (int c = tx; c < ns; c += 32) tile[rr * LDT + c] = inner ? src[c] : O[(int64_t)c * P.nb + bi];
         } else {
             const int nv = P.b, h = nv / 2;
             const int cell = row / nv, j = row - cell * nv;
             const int lc = P.kx0 - 1 + cell - P.x0;
-            if (lc >= 0 && lc < P.cx) v = X[(int64_t)lc * lstride + (int64_t)j * P.sp + c];
-            else if (lc < 0) v = vw[j] > 0 ? O[(int64_t)c * P.nb + (j - h)] : 0.0;
-            else v = vw[j] < 0 ? O[(int64_t)c * P.nb + h + j] : 0.0;
+            for (int c = tx; c < ns; c += 32) {
+                double v;
+                if (lc >= 0 && lc < P.cx) v = X[(int64_t)lc * lstride + (int64_t)j * P.sp + c];
+                else if (lc < 0) v = vw[j] > 0 ? O[(int64_t)c * P.nb + (j - h)] : 0.0;
+                else v = vw[j] < 0 ? O[(int64_t)c * P.nb + h + j] : 0.0;
+                tile[rr * LDT + c] = v;
+            }
         }
-        tile[rr * LDT + c] = v;
     }
     __syncthreads();
-    for (int o = threadIdx.x; o < n; o += kThreads) {
-        const int c = o / nr, rr = o - c * nr;
-        Y[(int64_t)c * P.nrows + r0 + rr] = tile[rr * LDT + c];
-    }
+    // store: 64 lanes along the rows of one column, 4 columns at a time
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    if (lx < nr)
+        for (int c = ly; c < ns; c += kThreads / 64) Y[(int64_t)c * P.nrows + r0 + lx] = tile[lx * LDT + c];
 }
 
 __global__ void clear_kernel(int32_t* a, int n) {
