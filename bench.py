@@ -19,6 +19,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# The throughput form replays several handles' graphs on streams of their own:
+# give them hardware queues of their own (HIP's default is 4 per process; set
+# before the runtime starts).  MSRS_BENCH_HW_QUEUES overrides the count.
+os.environ["GPU_MAX_HW_QUEUES"] = os.environ.get("MSRS_BENCH_HW_QUEUES", "16")
+
 METRIC = "patch×sample local solves/s; online solve p50/p99 ms at rel err ≤1e-6"
 PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "fp32_valu": 157.3e12, "fp64_valu": 78.6e12, "hbm": 8.0e12}
 K_FACTOR, K_SWEEP, K_RESIDUAL, K_RANGE = 3, 4, 5, 7

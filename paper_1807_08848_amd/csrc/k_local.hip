@@ -695,15 +695,20 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
 // plist lists the patches of this R (workgroup x -> patch plist[x]).  The
 // halves kernel has grid (patches, 2): y = 0 top, y = 1 bottom; the middle
 // kernel one workgroup per patch, after it.
+// LDS of the factor for R line tiles: E (BP x (BP+1)) and, aliased, the
+// panel buffers (2 BP x 17 + 4 x 16 (BP+1) + 2 x 16 x 17)
+template <int R>
+constexpr int factor_lds_elems() {
+    constexpr int BPR = 16 * R;
+    constexpr int PANEL = 2 * BPR * 17 + 4 * 16 * (BPR + 1) + 2 * 16 * 17;
+    return BPR * (BPR + 1) > PANEL ? BPR * (BPR + 1) : PANEL;
+}
+
 template <typename T, int KIND, int R, bool MID>
 __global__ __launch_bounds__(kFactorThreads) void factor_kernel(const PatchDesc* pd, const int32_t* __restrict__ plist,
                                                                 const double* __restrict__ aL_all, const double* __restrict__ vw,
                                                                 double dx, double inv_eps, T* __restrict__ E_all, int32_t* flags) {
-    // E (BP x (BP+1)) and, aliased, the panel buffers (2 BP x 17 + 4 x 16 (BP+1) + 2 x 16 x 17)
-    constexpr int BPR = 16 * R;
-    constexpr int PANEL = 2 * BPR * 17 + 4 * 16 * (BPR + 1) + 2 * 16 * 17;
-    constexpr int LDS_ELEMS = BPR * (BPR + 1) > PANEL ? BPR * (BPR + 1) : PANEL;
-    __shared__ T lds[LDS_ELEMS];
+    __shared__ T lds[factor_lds_elems<R>()];
     __shared__ double cf[2 * kMaxLine];
     __shared__ double crow[2 * (kMaxLine + 1)];
     const PatchDesc P = pd[plist[blockIdx.x]];
@@ -713,6 +718,30 @@ __global__ __launch_bounds__(kFactorThreads) void factor_kernel(const PatchDesc*
     }
     const int dir = MID ? 0 : (blockIdx.y == 0 ? 1 : -1);
     factor_mfma_body<T, KIND, R, MID>(P, aL_all + P.a_off, vw, dx, inv_eps, E_all + P.E_off, lds, cf, crow, dir, flags);
+}
+
+// Two line-tile counts in one launch, so that a batch with two adjacent
+// counts needs no second stream: workgroups x < nA factor the patches of
+// plistA (RA tiles), the others those of plistB (RB tiles), each with its own
+// body; LDS and registers are those of the larger.
+template <typename T, int KIND, int RA, int RB, bool MID>
+__global__ __launch_bounds__(kFactorThreads) void factor2_kernel(const PatchDesc* pd, const int32_t* __restrict__ plistA, int nA,
+                                                                 const int32_t* __restrict__ plistB, const double* __restrict__ aL_all,
+                                                                 const double* __restrict__ vw, double dx, double inv_eps,
+                                                                 T* __restrict__ E_all, int32_t* flags) {
+    constexpr int LA = factor_lds_elems<RA>(), LB = factor_lds_elems<RB>();
+    __shared__ T lds[LA > LB ? LA : LB];
+    __shared__ double cf[2 * kMaxLine];
+    __shared__ double crow[2 * (kMaxLine + 1)];
+    const bool a = (int)blockIdx.x < nA;
+    const PatchDesc P = pd[a ? plistA[blockIdx.x] : plistB[blockIdx.x - nA]];
+    if (P.bp != 16 * (a ? RA : RB)) {
+        if (threadIdx.x == 0) raise_flag(flags, 3);
+        return;
+    }
+    const int dir = MID ? 0 : (blockIdx.y == 0 ? 1 : -1);
+    if (a) factor_mfma_body<T, KIND, RA, MID>(P, aL_all + P.a_off, vw, dx, inv_eps, E_all + P.E_off, lds, cf, crow, dir, flags);
+    else factor_mfma_body<T, KIND, RB, MID>(P, aL_all + P.a_off, vw, dx, inv_eps, E_all + P.E_off, lds, cf, crow, dir, flags);
 }
 
 // ------------------------------------------------------------ sweeps (a5)
@@ -1426,17 +1455,63 @@ static void launch_factor_group(Ctx& c, int R, hipStream_t st, const int32_t* pl
     }
 }
 
+// FP32 batch with two adjacent line-tile counts ra = rb + 1: one launch for
+// the halves and one for the middle lines, on the handle's stream.
+template <int KIND>
+static bool launch_factor_pair(Ctx& c, int ra, int rb) {
+    if (c.prec != MSRS_PREC_FP32_IR || ra != rb + 1) return false;
+    const int nA = c.rgroup_n[ra], nB = c.rgroup_n[rb];
+    const double inv_eps = 1.0 / c.eps;
+    float* E = (float*)c.E;
+#define MSRS_FACTOR2(RA, RB)                                                                                                     \
+    do {                                                                                                                        \
+        hipLaunchKernelGGL((factor2_kernel<float, KIND, RA, RB, false>), dim3(nA + nB, 2), dim3(kFactorThreads), 0, c.stream, c.dp, \
+                           c.rgroup[RA], nA, c.rgroup[RB], c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags);                         \
+        hipLaunchKernelGGL((factor2_kernel<float, KIND, RA, RB, true>), dim3(nA + nB), dim3(kFactorThreads), 0, c.stream, c.dp,     \
+                           c.rgroup[RA], nA, c.rgroup[RB], c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags);                         \
+    } while (0)
+    if constexpr (KIND == kElliptic) {
+        switch (ra) {
+            case 2: MSRS_FACTOR2(2, 1); return true;
+            case 3: MSRS_FACTOR2(3, 2); return true;
+            case 4: MSRS_FACTOR2(4, 3); return true;
+            case 5: MSRS_FACTOR2(5, 4); return true;
+            case 6: MSRS_FACTOR2(6, 5); return true;
+            case 7: MSRS_FACTOR2(7, 6); return true;
+            case 8: MSRS_FACTOR2(8, 7); return true;
+            default: return false;
+        }
+    } else {
+        switch (ra) {
+            case 2: MSRS_FACTOR2(2, 1); return true;
+            case 3: MSRS_FACTOR2(3, 2); return true;
+            case 4: MSRS_FACTOR2(4, 3); return true;
+            default: return false;
+        }
+    }
+#undef MSRS_FACTOR2
+}
+
 // Patches are grouped by line-tile count R; each group runs its own kernel.
-// A single patch (reference mode) launches on the handle's stream; a batch
-// forks one stream per group from the handle's stream and joins back.
+// A single patch (reference mode) launches on the handle's stream.  A batch
+// with one count, or (FP32) two adjacent ones, launches on the handle's
+// stream; otherwise it forks one stream per group from the handle's stream
+// and joins back.
 void launch_factor(Ctx& c, int p0, int p1) {
     StageTimer t(c, MSRS_K_FACTOR);
     if (p1 - p0 == 1) {
         launch_factor_group(c, c.hp[p0].bp / 16, c.stream, c.pid + p0, 1);
         return;
     }
-    int ng = 0;
-    for (int g = 0; g < 9; ++g) ng += c.rgroup_n[g] > 0;
+    int ng = 0, rmax = 0, rmin = 9;
+    for (int g = 0; g < 9; ++g)
+        if (c.rgroup_n[g] > 0) {
+            ++ng;
+            rmax = std::max(rmax, g);
+            rmin = std::min(rmin, g);
+        }
+    if (ng == 2 && (c.kind == kElliptic ? launch_factor_pair<kElliptic>(c, rmax, rmin) : launch_factor_pair<kKinetic>(c, rmax, rmin)))
+        return;
     if (ng <= 1) {
         for (int g = 0; g < 9; ++g)
             if (c.rgroup_n[g]) launch_factor_group(c, g, c.stream, c.rgroup[g], c.rgroup_n[g]);
