@@ -293,3 +293,25 @@ def test_elliptic_full_basis_on_boundary_patches(gpu, k):
     assert E.relative_l2(out["u"][0], u_or) <= 1e-6
     err = E.relative_l2(out["u"][0], E.global_solve(cfg["coef"], N, cfg["phi"]))
     assert err < (0.15 if k == 8 else 1e-2)
+
+
+@pytest.mark.parametrize("ov,counts", [
+    # line-tile counts {2, 3}: one factor launch for both
+    ([6, 12, 12, 6, 12, 6, 12, 12, 6, 12, 6, 12, 12, 12, 6, 6], {2, 3}),
+    # {1, 2, 3}: one factor kernel per count on forked streams
+    ([0, 6, 12, 0, 12, 0, 12, 6, 6, 12, 0, 12, 0, 6, 12, 0], {1, 2, 3}),
+])
+def test_elliptic_mixed_line_tile_counts_fp32(gpu, ov, counts):
+    """Patches of different line lengths in one FP32-IR batch: parity of the
+    snapshots, bases and global solution with the oracle for both ways the
+    factor stage launches them."""
+    N, M = 64, 4
+    cfg = dict(name="mixed", kind="elliptic", N=N, M=M, overlap=np.asarray(ov, dtype=np.int32), s=10, k=6,
+               coef=synth.lognormal_coefficient(N, 0.05, 7), phi=synth.dirichlet_sin_cos(N), seed=13)
+    out = run(cfg, FP32_IR, phi=cfg["phi"])
+    assert {inf.line_len // 16 + (inf.line_len % 16 > 0) for inf in out["infos"]} == counts
+    ref = _oracle_elliptic(cfg)
+    _check_bases(out, ref, 1e-8)
+    assert out["stats"].max_rel_residual <= 1e-10
+    u_or = E.online(N, M, ref, cfg["coef"], cfg["phi"])
+    assert E.relative_l2(out["u"][0], u_or) <= 1e-6
