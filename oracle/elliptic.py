@@ -22,7 +22,7 @@ step by step from the paper:
   nodal partition-of-unity weights at shared nodes;
 * brute force: the global fine-grid FE solve.
 
-Readings where the paper is silent are listed in DESIGN.md ("Readings").
+Where the paper is silent, each function's docstring states the reading it takes.
 """
 from __future__ import annotations
 
