@@ -192,3 +192,54 @@ def test_adaptive_ranks_survive_a_basis_file(lib, tmp_path):
         assert all(q.shape[1] == k for q, k in zip(Q, ks))
     finally:
         pr.close()
+
+
+@pytest.mark.gpu
+def test_adaptive_ranks_under_graph_replay(lib):
+    """The captured offline step chooses its ranks on the device at every
+    replay: a replay on a new medium gives the ranks and bases the eager path
+    gives on that medium, and the coarse system follows them."""
+    import torch
+    import synth
+    from gpu_cases import _unpack
+    cfg = configs.elliptic_two_scale_100(20)
+    tol = 1e-3
+    dev = torch.device("cuda:0")
+    st = torch.cuda.Stream()
+    d = lib.make_desc(lib.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"], list(cfg["overlap"]), cfg["s"], cfg["k"],
+                      precision=FP32_IR, seed=cfg["seed"], rank_tol=tol)
+    a0 = torch.tensor(cfg["coef"], device=dev)
+    a1 = torch.tensor(synth.high_contrast_coefficient(cfg["N"], 10.0), device=dev)
+    with lib.Problem(d, stream=st) as pr, lib.Problem(d, stream=st) as eager:
+        L = pr.layout()
+        pr.assemble_patch(a0)
+        pr.sample_local_solutions()
+        pr.range_finder()
+        pr.offline_graph_capture(a0)
+        pr.offline_graph_launch()              # medium a0, captured pointer: replay reads a0
+        torch.cuda.synchronize()
+        k0 = [pr.patch(p).n_cols for p in range(L.n_patches)]
+        a0.copy_(a1)                           # the graph reads the coefficient where it was captured
+        torch.cuda.synchronize()
+        pr.offline_graph_launch()
+        torch.cuda.synchronize()
+        k1 = [pr.patch(p).n_cols for p in range(L.n_patches)]
+        eager.assemble_patch(a1)
+        eager.sample_local_solutions()
+        eager.range_finder()
+        torch.cuda.synchronize()
+        ke = [eager.patch(p).n_cols for p in range(L.n_patches)]
+        assert k1 == ke and k1 != k0
+        Qg = torch.empty(L.Q_total, device=dev, dtype=torch.float64)
+        Qe = torch.empty_like(Qg)
+        pr.copy_results(None, Qg, None)
+        eager.copy_results(None, Qe, None)
+        torch.cuda.synchronize()
+        Qg, Qe = Qg.cpu().numpy(), Qe.cpu().numpy()
+        for p in range(L.n_patches):
+            inf = pr.patch(p)
+            A = _unpack(Qg, inf.Q_off, inf.n_rows, inf.n_cols)
+            B = _unpack(Qe, inf.Q_off, inf.n_rows, inf.n_cols)
+            assert sin_max_angle(A, B) < 1e-6, p
+        pr.assemble_coarse()
+        assert pr.layout().coarse_dim == sum(k1)
