@@ -183,6 +183,7 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
             double* Gn = Gb[cur ^ 1];
             int a = 0, b = 0, a2 = 0, b2 = 0;
             double c2 = 1.0, s2 = 0.0, t2 = 0.0;   // rotation of pair i2
+            bool big = false;
             double g00 = 0.0, g01 = 0.0, g10 = 0.0, g11 = 0.0, va0 = 0.0, vb0 = 0.0, va1 = 0.0, vb1 = 0.0;
             if (act) {
                 rr_pair(i, st, nm1, a, b);
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
                 vb1 = V[(i2 + np2) * LDG + b];
                 if (b2 < s && apq != 0.0) {
                     // |g_pq| > 1e-13 sqrt|g_pp g_qq| compared in squares
-                    if (apq * apq > 1e-26 * fabs(app * aqq) && fabs(apq) > floor_abs) rot = 1;
+                    big = apq * apq > 1e-26 * fabs(app * aqq) && fabs(apq) > floor_abs;
                     // the smaller root of t^2 + 2 tau t - 1 = 0, tau = d / (2 g_pq),
                     // d = g_qq - g_pp, with numerator and denominator scaled by 2|g_pq|
                     const double d = aqq - app;
@@ -207,6 +208,8 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
                     s2 = t2 * c2;
                 }
             }
+            // one store of the flag per wave
+            if (__any(big) && (tid & 63) == 0) rot = 1;
             const double c = __shfl(c2, src, 64), sv = __shfl(s2, src, 64), t = __shfl(t2, src, 64);
             if (act) {
                 if (i == i2) {
