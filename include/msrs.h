@@ -98,11 +98,18 @@ typedef int32_t msrs_status;
 /* elliptic, with MSRS_FLAG_FULL_BASIS_BOUNDARY: the constrained alternative
  * of the online least-squares problem (Sec. 5.2, after eq.
  * elliptic_cond_reduced): the Dirichlet rows hold exactly and only the
- * continuity rows are minimized.  The full bases on the boundary patches make
+ * continuity rows are minimized.  The full bases on the boundary patches (this
+ * flag or MSRS_FLAG_FULL_BASIS) make
  * the constraint satisfiable for any boundary data.  Needs at most 1024
  * Dirichlet rows (one per boundary patch and node of it on the domain
  * boundary); msrs_solve_global_banded does not support it. */
 #define MSRS_FLAG_CONSTRAINED_BC 16u
+/* every patch: no buffer and the full (delta) basis of its boundary data,
+ * DetLocalSolu of Alg. alg:summary (elliptic: 4 N/M <= 64 boundary nodes;
+ * kinetic: the n_vel inflow ordinates).  The bases then span the fine
+ * solution's restrictions, and the online solve reproduces the fine
+ * discrete solution. */
+#define MSRS_FLAG_FULL_BASIS 32u
 
 typedef struct msrs_ctx* msrs_handle;
 

@@ -78,12 +78,12 @@ void for_patches(Ctx& c, F&& f) {
 
 void build_elliptic(Ctx& c) {
     const int N = c.N, M = c.M, nH = N / M;
-    const bool fbb = (c.flags & MSRS_FLAG_FULL_BASIS_BOUNDARY) != 0;
+    const bool fbb = (c.flags & MSRS_FLAG_FULL_BASIS_BOUNDARY) != 0, fball = (c.flags & MSRS_FLAG_FULL_BASIS) != 0;
     int64_t a_off = 0, om_off = 0, x_off = 0, E_off = 0, Y_off = 0, Q_off = 0, sv_off = 0, rn_off = 0, tw_off = 0;
     for (int m2 = 0; m2 < M; ++m2)
         for (int m1 = 0; m1 < M; ++m1) {
             const int p = m2 * M + m1;
-            const bool full = fbb && (m1 == 0 || m1 == M - 1 || m2 == 0 || m2 == M - 1);
+            const bool full = fball || (fbb && (m1 == 0 || m1 == M - 1 || m2 == 0 || m2 == M - 1));
             const int d = full ? 0 : c.overlap[p];
             PatchDesc P{};
             const int x0 = std::max(0, m1 * nH - d), x1 = std::min(N, (m1 + 1) * nH + d);
@@ -123,10 +123,10 @@ void build_elliptic(Ctx& c) {
 
 void build_kinetic(Ctx& c) {
     const int Nx = c.N, M = c.M, nH = Nx / M, nv = c.nv;
-    const bool ends = (c.flags & MSRS_FLAG_FULL_BASIS_ENDS) != 0;
+    const bool ends = (c.flags & MSRS_FLAG_FULL_BASIS_ENDS) != 0, fball = (c.flags & MSRS_FLAG_FULL_BASIS) != 0;
     int64_t a_off = 0, om_off = 0, x_off = 0, E_off = 0, Y_off = 0, Q_off = 0, sv_off = 0, rn_off = 0, tw_off = 0;
     for (int m = 0; m < M; ++m) {
-        const bool full = ends && (m == 0 || m == M - 1);
+        const bool full = fball || (ends && (m == 0 || m == M - 1));
         const int d = full ? 0 : c.overlap[m];
         PatchDesc P{};
         const int x0 = std::max(0, m * nH - d), x1 = std::min(Nx, (m + 1) * nH + d);
@@ -184,11 +184,11 @@ msrs_status validate(const msrs_problem_desc* d, std::string& msg) {
                 if (std::min(cx, cy) - 1 > kMaxLine) { msg = "buffered patch too large: min side must be <= 129 cells"; return MSRS_ERR_ARG; }
             }
         if (d->M < 2) { msg = "elliptic needs M >= 2"; return MSRS_ERR_ARG; }
-        if ((d->flags & MSRS_FLAG_FULL_BASIS_BOUNDARY) && 4 * nH > kMaxSamples) {
-            msg = "full basis on boundary patches needs 4 N/M <= 64 boundary nodes";
+        if ((d->flags & (MSRS_FLAG_FULL_BASIS_BOUNDARY | MSRS_FLAG_FULL_BASIS)) && 4 * nH > kMaxSamples) {
+            msg = "full bases need at most 64 boundary nodes per patch (4 N/M <= 64)";
             return MSRS_ERR_ARG;
         }
-        if ((d->flags & MSRS_FLAG_CONSTRAINED_BC) && !(d->flags & MSRS_FLAG_FULL_BASIS_BOUNDARY)) {
+        if ((d->flags & MSRS_FLAG_CONSTRAINED_BC) && !(d->flags & (MSRS_FLAG_FULL_BASIS_BOUNDARY | MSRS_FLAG_FULL_BASIS))) {
             msg = "the constrained least-squares variant needs MSRS_FLAG_FULL_BASIS_BOUNDARY";
             return MSRS_ERR_ARG;
         }

@@ -30,6 +30,7 @@ KIND_ELLIPTIC_Q1, KIND_KINETIC_DO = 0, 1
 PREC_FP64, PREC_FP32_IR = 0, 1
 FLAG_FULL_BASIS_ENDS, FLAG_PER_PATCH_LAUNCH, FLAG_TIMING, FLAG_FULL_BASIS_BOUNDARY = 1, 2, 4, 8
 FLAG_CONSTRAINED_BC = 16
+FLAG_FULL_BASIS = 32
 TUNE_SWEEP_COLS, TUNE_RECON_BATCH, TUNE_APPLY_BATCH = 0, 1, 2
 TUNE_STAGE_OFFLINE, TUNE_STAGE_ONLINE = 0, 1
 TUNE_NAMES = {TUNE_SWEEP_COLS: "sweep_cols", TUNE_RECON_BATCH: "recon_batch", TUNE_APPLY_BATCH: "apply_batch"}

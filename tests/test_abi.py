@@ -51,6 +51,9 @@ def test_full_basis_boundary_needs_small_patches():
     with pytest.raises(msrs.MsrsError) as e:
         msrs.Problem(msrs.make_desc(0, 128, 4, [8] * 16, 10, 6, flags=msrs.FLAG_FULL_BASIS_BOUNDARY))
     assert e.value.status == msrs.ERR_ARG and "4 N/M <= 64" in str(e.value)
+    with pytest.raises(msrs.MsrsError) as e:
+        msrs.Problem(msrs.make_desc(0, 128, 4, [8] * 16, 10, 6, flags=msrs.FLAG_FULL_BASIS))
+    assert e.value.status == msrs.ERR_ARG and "4 N/M <= 64" in str(e.value)
 
 
 def test_null_handle_calls_fail_cleanly():

@@ -315,3 +315,25 @@ def test_elliptic_mixed_line_tile_counts_fp32(gpu, ov, counts):
     assert out["stats"].max_rel_residual <= 1e-10
     u_or = E.online(N, M, ref, cfg["coef"], cfg["phi"])
     assert E.relative_l2(out["u"][0], u_or) <= 1e-6
+
+
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-9), (FP32_IR, 1e-6)])
+def test_full_basis_everywhere_reproduces_the_fine_solution(gpu, prec, tol):
+    """MSRS_FLAG_FULL_BASIS: DetLocalSolu on every patch (no buffer, Kronecker-
+    delta boundary data).  The bases then span every restriction of a fine
+    solution, and the online solve returns the fine discrete solution, for the
+    elliptic and the kinetic problem (brute force: the oracle's global solve)."""
+    N, M = 64, 4
+    cfg = dict(name="full", kind="elliptic", N=N, M=M, overlap=np.full(M * M, 8, dtype=np.int32), s=8, k=8,
+               coef=synth.lognormal_coefficient(N, 0.05, 7), phi=synth.dirichlet_sin_cos(N), seed=2)
+    out = run(cfg, prec, phi=cfg["phi"], flags=gpu.FLAG_FULL_BASIS)
+    assert all(inf.full_basis == 1 and inf.n_cols == 4 * (N // M) for inf in out["infos"])
+    u_ref = E.global_solve(cfg["coef"], N, cfg["phi"])
+    assert E.relative_l2(out["u"][0], u_ref) <= tol
+    kcfg = configs.kinetic_hg_100(1.0, 10, n_vel=16)
+    v, _ = K.ordinates(16)
+    phi = np.concatenate([3 + np.sin(2 * np.pi * v[v > 0]), 2 + np.sin(2 * np.pi * v[v < 0])])
+    kout = run(kcfg, prec, phi=phi, flags=gpu.FLAG_FULL_BASIS)
+    assert all(inf.full_basis == 1 for inf in kout["infos"])
+    f_ref = K.global_solve(kcfg["coef"], kcfg["eps"], 16, phi, hg=kcfg["hg"])
+    assert np.linalg.norm(kout["u"][0] - f_ref) / np.linalg.norm(f_ref) <= tol
