@@ -126,3 +126,49 @@ def test_constrained_parity(lib, prec, tol):
         assert np.array_equal(u.cpu().numpy()[0], out["u"][0])
     finally:
         pr.close()
+
+
+@pytest.mark.gpu
+def test_constrained_model_under_the_server(lib):
+    """A constrained model served beside a plain least-squares one: every result
+    equals the same request solved alone, and the constrained results take the
+    boundary data exactly."""
+    import torch
+    a, phi, ov, _ = _setup()
+    dev = torch.device("cuda:0")
+    prs = []
+    try:
+        for extra in (0, lib.FLAG_CONSTRAINED_BC):
+            d = lib.make_desc(lib.KIND_ELLIPTIC_Q1, N, M, list(ov), 8, 8, precision=1, seed=2,
+                              flags=lib.FLAG_FULL_BASIS_BOUNDARY | extra)
+            pr = lib.Problem(d)
+            prs.append(pr)
+            pr.assemble_patch(torch.tensor(a, device=dev))
+            pr.sample_local_solutions()
+            pr.range_finder()
+            pr.assemble_coarse()
+        torch.cuda.synchronize()
+        reqs = synth.fourier_boundary(N, range(40))
+        mdl = [i % 2 for i in range(40)]
+        with lib.Server(prs, n_streams=2, max_batch=8) as srv:
+            tickets = []
+            while len(tickets) < len(mdl):     # as far as staging allows at a time
+                tickets += srv.submit_many(mdl[len(tickets):], reqs[len(tickets):])
+            outs = []
+            for t in tickets:
+                u = np.empty((N + 1) ** 2)
+                assert srv.fetch(t, u).status == 0
+                outs.append(u)
+        bn = _boundary_nodes(N)
+        for i in range(40):
+            pr = prs[mdl[i]]
+            f = torch.tensor(reqs[i][None, :], device=dev)
+            u = torch.empty((1, (N + 1) ** 2), device=dev, dtype=torch.float64)
+            pr.solve_global(f, u)
+            torch.cuda.synchronize()
+            assert np.array_equal(outs[i], u.cpu().numpy()[0]), i
+            if mdl[i] == 1:
+                assert np.abs(outs[i][bn] - reqs[i]).max() <= 1e-9 * np.abs(reqs[i]).max(), i
+    finally:
+        for pr in prs:
+            pr.close()
