@@ -337,3 +337,55 @@ def test_full_basis_everywhere_reproduces_the_fine_solution(gpu, prec, tol):
     assert all(inf.full_basis == 1 for inf in kout["infos"])
     f_ref = K.global_solve(kcfg["coef"], kcfg["eps"], 16, phi, hg=kcfg["hg"])
     assert np.linalg.norm(kout["u"][0] - f_ref) / np.linalg.norm(f_ref) <= tol
+
+
+def test_elliptic_lognormal_512_benchmarked_form(gpu):
+    """The benchmarked workload (h=1/512, 8x8 patches of two line lengths,
+    32 samples, rank 12) in the form the benchmark times: the captured step
+    replayed on its own stream.  The oracle checks the snapshots, singular
+    values and bases of patches of both line lengths one by one."""
+    import torch
+    from gpu_cases import _unpack
+    from oracle.rangefinder import range_finder
+    cfg = configs.elliptic_lognormal_512()
+    st = torch.cuda.Stream()
+    d = gpu.make_desc(gpu.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"], list(cfg["overlap"]), cfg["s"], cfg["k"],
+                      precision=FP32_IR, seed=cfg["seed"])
+    a = torch.tensor(cfg["coef"], device="cuda:0")
+    with gpu.Problem(d, stream=st) as pr:
+        pr.assemble_patch(a)
+        pr.sample_local_solutions()
+        pr.range_finder()
+        pr.offline_graph_capture(a)
+        for _ in range(3):
+            pr.offline_graph_launch()
+        L = pr.layout()
+        Y = torch.empty(L.Y_total, device="cuda:0", dtype=torch.float64)
+        Q = torch.empty(L.Q_total, device="cuda:0", dtype=torch.float64)
+        sv = torch.empty(L.sv_total, device="cuda:0", dtype=torch.float64)
+        pr.copy_results(Y, Q, sv)
+        torch.cuda.synchronize()
+        stats = pr.stats()
+        infos = [pr.patch(p) for p in range(L.n_patches)]
+    assert stats.error_latched == 0 and stats.max_rel_residual <= 1e-10
+    Yh, Qh, svh = Y.cpu().numpy(), Q.cpu().numpy(), sv.cpu().numpy()
+    geo = E.patch_geometry(cfg["N"], cfg["M"], cfg["overlap"])
+    lens = {}
+    for p, inf in enumerate(infos):
+        lens.setdefault(inf.line_len, p)
+    picks = sorted(set(lens.values()) | {0, 27, 63})
+    assert len(lens) >= 2
+    for p in picks:
+        inf, g = infos[p], geo[p]
+        Yo = E.sample_patch(cfg["coef"], cfg["N"], g, E.patch_omega(cfg["seed"], g, cfg["s"]))
+        Qo, svo = range_finder(Yo, cfg["k"])
+        Yg = _unpack(Yh, inf.Y_off, inf.n_rows, inf.n_samples)
+        assert rel(Yg, Yo) < 1e-8, p
+        # Weyl: the singular values move by at most ||Y_g - Y_o||_2 (refined FP32
+        # snapshots differ from the FP64 ones by about 1e-9 here)
+        bound = np.linalg.norm(Yg - Yo, 2) + 1e-12 * svo[0]
+        assert np.abs(svh[inf.sv_off:inf.sv_off + inf.n_samples] - svo).max() <= bound, p
+        Qg = _unpack(Qh, inf.Q_off, inf.n_rows, inf.n_cols)
+        assert np.abs(Qg.T @ Qg - np.eye(cfg["k"])).max() < 1e-12, p
+        if (svo[cfg["k"] - 1] - svo[cfg["k"]]) / svo[0] >= 1e-3:
+            assert sin_max_angle(Qo, Qg) <= 1e-6, p
