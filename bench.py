@@ -125,16 +125,20 @@ def _desc(cfg, precision, flags, seed):
                           flags=flags | (msrs.FLAG_FULL_BASIS_ENDS if kin else 0))
 
 
-def run_pipelined(cfg, precision, pr, a, steps, warmup, max_handles, tune):
+def run_pipelined(cfg, precision, pr, a, steps, warmup, max_handles, tune, factor_share=2):
     """Throughput form of the offline stage: several handles, each an independent
     sampling pass over the same medium (its own Omega seed), replay their captured
     steps on their own streams, round-robin, so that one pass's latency-bound
     phases (the factor's chain of lines, the per-patch eigensolver) overlap
     another's wide ones.  The handle count is chosen by timing 1..max_handles;
-    pr (seed cfg["seed"], graph captured) is the first handle."""
+    pr (seed cfg["seed"]) is the first handle.  Every handle's factor is
+    compiled for factor_share resident workgroups per compute unit (its graph
+    captured again with that shape)."""
     import torch
     from paper_1807_08848_amd import msrs, tuning
     hs = [pr]
+    pr.set_tuning(msrs.TUNE_FACTOR_SHARE, factor_share)
+    pr.offline_graph_capture(a)
     try:
         for h in range(1, max_handles):
             sh = torch.cuda.Stream()
@@ -143,6 +147,7 @@ def run_pipelined(cfg, precision, pr, a, steps, warmup, max_handles, tune):
                 hs.append(ph)
                 if tune:
                     tuning.tune(ph, msrs.TUNE_STAGE_OFFLINE)
+                ph.set_tuning(msrs.TUNE_FACTOR_SHARE, factor_share)
                 ph.assemble_patch(a)
                 ph.sample_local_solutions(None, None)
                 ph.range_finder(None, None)
@@ -168,7 +173,7 @@ def run_pipelined(cfg, precision, pr, a, steps, warmup, max_handles, tune):
         stats = [ph.stats() for ph in hs[:best]]
         ok = all(st.error_latched == 0 and st.max_rel_residual <= 1e-10 for st in stats)
         return dict(T=T, handles=best, ok=ok, max_rel_residual=max(st.max_rel_residual for st in stats),
-                    trials_ms={P: t * 1e3 for P, t in trials.items()})
+                    trials_ms={P: t * 1e3 for P, t in trials.items()}, factor_share=factor_share)
     finally:
         for ph in hs[1:]:
             ph.close()
@@ -470,7 +475,7 @@ def main():
     }
     if pipe:
         out["pipeline"] = {"handles": pipe["handles"], "ms_per_step_by_handles": pipe["trials_ms"],
-                           "max_rel_residual": pipe["max_rel_residual"]}
+                           "max_rel_residual": pipe["max_rel_residual"], "factor_share": pipe["factor_share"]}
     if kinetic:
         out["roofline"] = None     # no banded-direct count is defined for the transport operator here
     if not args.no_plain:

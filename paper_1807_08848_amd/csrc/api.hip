@@ -1060,6 +1060,10 @@ msrs_status msrs_set_tuning(msrs_handle h, int32_t key, int32_t value) {
             if (!in({4, 8, 16})) return fail(c, MSRS_ERR_ARG, "apply batch must be 4, 8 or 16");
             c->apply_batch = value;
             return MSRS_OK;
+        case MSRS_TUNE_FACTOR_SHARE:
+            if (!in({1, 2})) return fail(c, MSRS_ERR_ARG, "factor share must be 1 or 2");
+            c->factor_share = value;
+            return MSRS_OK;
         default:
             return fail(c, MSRS_ERR_ARG, "unknown tuning key");
     }
@@ -1162,6 +1166,7 @@ msrs_status msrs_get_tuning(msrs_handle h, int32_t key, int32_t* value) {
         case MSRS_TUNE_SWEEP_COLS: *value = c->sweep_cols32; return MSRS_OK;
         case MSRS_TUNE_RECON_BATCH: *value = c->recon_batch; return MSRS_OK;
         case MSRS_TUNE_APPLY_BATCH: *value = c->apply_batch; return MSRS_OK;
+        case MSRS_TUNE_FACTOR_SHARE: *value = c->factor_share; return MSRS_OK;
         default: return fail(c, MSRS_ERR_ARG, "unknown tuning key");
     }
 }

@@ -723,9 +723,11 @@ __global__ __launch_bounds__(kFactorThreads) void factor_kernel(const PatchDesc*
 // Two line-tile counts in one launch, so that a batch with two adjacent
 // counts needs no second stream: workgroups x < nA factor the patches of
 // plistA (RA tiles), the others those of plistB (RB tiles), each with its own
-// body; LDS and registers are those of the larger.
-template <typename T, int KIND, int RA, int RB, bool MID>
-__global__ __launch_bounds__(kFactorThreads) void factor2_kernel(const PatchDesc* pd, const int32_t* __restrict__ plistA, int nA,
+// body; LDS and registers are those of the larger.  SHARE = 2 compiles for
+// two resident workgroups per compute unit (8 waves per SIMD: a 64-register
+// budget, at the price of a few spills).
+template <typename T, int KIND, int RA, int RB, bool MID, int SHARE>
+__global__ __launch_bounds__(kFactorThreads, SHARE == 2 ? 8 : 1) void factor2_kernel(const PatchDesc* pd, const int32_t* __restrict__ plistA, int nA,
                                                                  const int32_t* __restrict__ plistB, const double* __restrict__ aL_all,
                                                                  const double* __restrict__ vw, double dx, double inv_eps,
                                                                  T* __restrict__ E_all, int32_t* flags) {
@@ -1463,12 +1465,17 @@ static bool launch_factor_pair(Ctx& c, int ra, int rb) {
     const int nA = c.rgroup_n[ra], nB = c.rgroup_n[rb];
     const double inv_eps = 1.0 / c.eps;
     float* E = (float*)c.E;
-#define MSRS_FACTOR2(RA, RB)                                                                                                     \
+#define MSRS_FACTOR2_SH(RA, RB, SH)                                                                                               \
     do {                                                                                                                        \
-        hipLaunchKernelGGL((factor2_kernel<float, KIND, RA, RB, false>), dim3(nA + nB, 2), dim3(kFactorThreads), 0, c.stream, c.dp, \
-                           c.rgroup[RA], nA, c.rgroup[RB], c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags);                         \
-        hipLaunchKernelGGL((factor2_kernel<float, KIND, RA, RB, true>), dim3(nA + nB), dim3(kFactorThreads), 0, c.stream, c.dp,     \
-                           c.rgroup[RA], nA, c.rgroup[RB], c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags);                         \
+        hipLaunchKernelGGL((factor2_kernel<float, KIND, RA, RB, false, SH>), dim3(nA + nB, 2), dim3(kFactorThreads), 0, c.stream,    \
+                           c.dp, c.rgroup[RA], nA, c.rgroup[RB], c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags);                   \
+        hipLaunchKernelGGL((factor2_kernel<float, KIND, RA, RB, true, SH>), dim3(nA + nB), dim3(kFactorThreads), 0, c.stream,        \
+                           c.dp, c.rgroup[RA], nA, c.rgroup[RB], c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags);                   \
+    } while (0)
+#define MSRS_FACTOR2(RA, RB)                                 \
+    do {                                                     \
+        if (c.factor_share == 2) MSRS_FACTOR2_SH(RA, RB, 2); \
+        else MSRS_FACTOR2_SH(RA, RB, 1);                     \
     } while (0)
     if constexpr (KIND == kElliptic) {
         switch (ra) {
@@ -1490,6 +1497,7 @@ static bool launch_factor_pair(Ctx& c, int ra, int rb) {
         }
     }
 #undef MSRS_FACTOR2
+#undef MSRS_FACTOR2_SH
 }
 
 // Patches are grouped by line-tile count R; each group runs its own kernel.

@@ -145,6 +145,7 @@ struct Ctx {
     // online
     int max_batch = 64;
     int sweep_cols32 = 64;       // samples per sweep workgroup (FP32), 16 | value
+    int factor_share = 1;        // factor workgroups per compute unit the kernel's registers allow (1 or 2)
     int sweep_cols64 = 32;       // samples per sweep workgroup (FP64)
     int recon_batch = 8;         // requests per reconstruction pass (1, 2, 4, 8, 16)
     int apply_batch = 8;         // requests per G_B workgroup (4, 8, 16)

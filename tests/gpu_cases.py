@@ -9,7 +9,7 @@ def _unpack(flat, off, rows, cols):
     return flat[off:off + rows * cols].reshape(cols, rows).T
 
 
-def run(cfg, precision, omegas=None, flags=0, phi=None, n_req=None, max_batch=None, stats=True):
+def run(cfg, precision, omegas=None, flags=0, phi=None, n_req=None, max_batch=None, stats=True, tuning=None):
     """Run assemble -> sample -> range finder (-> coarse + solve) on cuda:0.
 
     cfg: a workload dict of synth.configs; omegas: optional list of per-patch
@@ -26,6 +26,8 @@ def run(cfg, precision, omegas=None, flags=0, phi=None, n_req=None, max_batch=No
                        rank_tol=cfg.get("rank_tol", 0.0), flags=flags | (msrs.FLAG_FULL_BASIS_ENDS if kin else 0))
     pr = msrs.Problem(d)
     try:
+        for key, value in (tuning or {}).items():
+            pr.set_tuning(key, value)
         L = pr.layout()
         infos = [pr.patch(p) for p in range(L.n_patches)]
         dev = torch.device("cuda:0")

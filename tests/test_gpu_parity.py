@@ -389,3 +389,20 @@ def test_elliptic_lognormal_512_benchmarked_form(gpu):
         assert np.abs(Qg.T @ Qg - np.eye(cfg["k"])).max() < 1e-12, p
         if (svo[cfg["k"] - 1] - svo[cfg["k"]]) / svo[0] >= 1e-3:
             assert sin_max_angle(Qo, Qg) <= 1e-6, p
+
+
+def test_factor_share_keeps_results(gpu):
+    """MSRS_TUNE_FACTOR_SHARE = 2 compiles the two-length factor for two
+    resident workgroups per compute unit: a register budget, not arithmetic.
+    Snapshots, bases and the global solution are those of the default."""
+    N, M = 64, 4
+    ov = np.asarray([6, 12, 12, 6, 12, 6, 12, 12, 6, 12, 6, 12, 12, 12, 6, 6], dtype=np.int32)
+    cfg = dict(name="share", kind="elliptic", N=N, M=M, overlap=ov, s=10, k=6,
+               coef=synth.lognormal_coefficient(N, 0.05, 7), phi=synth.dirichlet_sin_cos(N), seed=13)
+    outs = []
+    for share in (1, 2):
+        outs.append(run(cfg, FP32_IR, phi=cfg["phi"], tuning={gpu.TUNE_FACTOR_SHARE: share}))
+    a, b = outs
+    for p in range(M * M):
+        assert np.array_equal(a["Y"][p], b["Y"][p]) and np.array_equal(a["Q"][p], b["Q"][p]), p
+    assert np.array_equal(a["u"], b["u"])
