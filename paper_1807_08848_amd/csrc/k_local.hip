@@ -704,8 +704,8 @@ constexpr int factor_lds_elems() {
     return BPR * (BPR + 1) > PANEL ? BPR * (BPR + 1) : PANEL;
 }
 
-template <typename T, int KIND, int R, bool MID>
-__global__ __launch_bounds__(kFactorThreads) void factor_kernel(const PatchDesc* pd, const int32_t* __restrict__ plist,
+template <typename T, int KIND, int R, bool MID, int SHARE = 1>
+__global__ __launch_bounds__(kFactorThreads, SHARE == 2 ? 8 : 1) void factor_kernel(const PatchDesc* pd, const int32_t* __restrict__ plist,
                                                                 const double* __restrict__ aL_all, const double* __restrict__ vw,
                                                                 double dx, double inv_eps, T* __restrict__ E_all, int32_t* flags) {
     __shared__ T lds[factor_lds_elems<R>()];
@@ -1425,12 +1425,22 @@ static void launch_factor_r(Ctx& c, int R, hipStream_t st, const int32_t* plist,
     const double inv_eps = 1.0 / c.eps;
     T* E = (T*)c.E;
     // both halves at once, then the middle lines
-#define MSRS_FACTOR(RR)                                                                                                          \
+#define MSRS_FACTOR_SH(RR, SH)                                                                                                    \
     do {                                                                                                                        \
-        hipLaunchKernelGGL((factor_kernel<T, KIND, RR, false>), dim3(n, 2), dim3(kFactorThreads), 0, st, c.dp, plist, c.aL, c.vw, \
+        hipLaunchKernelGGL((factor_kernel<T, KIND, RR, false, SH>), dim3(n, 2), dim3(kFactorThreads), 0, st, c.dp, plist, c.aL,    \
+                           c.vw, dx_of(c), inv_eps, E, c.dflags);                                                               \
+        hipLaunchKernelGGL((factor_kernel<T, KIND, RR, true, SH>), dim3(n), dim3(kFactorThreads), 0, st, c.dp, plist, c.aL, c.vw, \
                            dx_of(c), inv_eps, E, c.dflags);                                                                     \
-        hipLaunchKernelGGL((factor_kernel<T, KIND, RR, true>), dim3(n), dim3(kFactorThreads), 0, st, c.dp, plist, c.aL, c.vw,     \
-                           dx_of(c), inv_eps, E, c.dflags);                                                                     \
+    } while (0)
+    // the factor share applies to the FP32 kernels
+#define MSRS_FACTOR(RR)                                                           \
+    do {                                                                          \
+        if constexpr (sizeof(T) == 4) {                                           \
+            if (c.factor_share == 2) MSRS_FACTOR_SH(RR, 2);                       \
+            else MSRS_FACTOR_SH(RR, 1);                                           \
+        } else {                                                                  \
+            MSRS_FACTOR_SH(RR, 1);                                                \
+        }                                                                         \
     } while (0)
     switch (R) {
         case 1: MSRS_FACTOR(1); break;
@@ -1444,6 +1454,7 @@ static void launch_factor_r(Ctx& c, int R, hipStream_t st, const int32_t* plist,
         default: break;
     }
 #undef MSRS_FACTOR
+#undef MSRS_FACTOR_SH
 }
 
 static void launch_factor_group(Ctx& c, int R, hipStream_t st, const int32_t* plist, int n) {

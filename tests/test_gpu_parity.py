@@ -391,12 +391,17 @@ def test_elliptic_lognormal_512_benchmarked_form(gpu):
             assert sin_max_angle(Qo, Qg) <= 1e-6, p
 
 
-def test_factor_share_keeps_results(gpu):
-    """MSRS_TUNE_FACTOR_SHARE = 2 compiles the two-length factor for two
-    resident workgroups per compute unit: a register budget, not arithmetic.
+@pytest.mark.parametrize("ov", [
+    [6, 12, 12, 6, 12, 6, 12, 12, 6, 12, 6, 12, 12, 12, 6, 6],     # two lengths, one launch
+    [8] * 16,                                                      # one length
+    [0, 6, 12, 0, 12, 0, 12, 6, 6, 12, 0, 12, 0, 6, 12, 0],        # three lengths, forked streams
+])
+def test_factor_share_keeps_results(gpu, ov):
+    """MSRS_TUNE_FACTOR_SHARE = 2 compiles the FP32 factor for two resident
+    workgroups per compute unit: a register budget, not arithmetic.
     Snapshots, bases and the global solution are those of the default."""
     N, M = 64, 4
-    ov = np.asarray([6, 12, 12, 6, 12, 6, 12, 12, 6, 12, 6, 12, 12, 12, 6, 6], dtype=np.int32)
+    ov = np.asarray(ov, dtype=np.int32)
     cfg = dict(name="share", kind="elliptic", N=N, M=M, overlap=ov, s=10, k=6,
                coef=synth.lognormal_coefficient(N, 0.05, 7), phi=synth.dirichlet_sin_cos(N), seed=13)
     outs = []
