@@ -172,3 +172,32 @@ def test_constrained_model_under_the_server(lib):
     finally:
         for pr in prs:
             pr.close()
+
+
+@pytest.mark.gpu
+def test_constrained_model_from_a_basis_file(lib, tmp_path):
+    """A basis file keeps the constrained flag: the loaded handle forms G_C at
+    msrs_assemble_coarse and solves like the original, bit for bit."""
+    import torch
+    a, phi, ov, _ = _setup()
+    dev = torch.device("cuda:0")
+    d = lib.make_desc(lib.KIND_ELLIPTIC_Q1, N, M, list(ov), 8, 8, precision=1, seed=2,
+                      flags=lib.FLAG_FULL_BASIS_BOUNDARY | lib.FLAG_CONSTRAINED_BC)
+    with lib.Problem(d) as pr:
+        pr.assemble_patch(torch.tensor(a, device=dev))
+        pr.sample_local_solutions()
+        pr.range_finder()
+        pr.assemble_coarse()
+        f = torch.tensor(synth.fourier_boundary(N, range(4)), device=dev)
+        u0 = torch.empty((4, (N + 1) ** 2), device=dev, dtype=torch.float64)
+        pr.solve_global(f, u0)
+        path = str(tmp_path / "constrained.msrs")
+        pr.save(path)
+        with lib.Problem.load(path) as ld:
+            ld.assemble_coarse()
+            u1 = torch.empty_like(u0)
+            ld.solve_global(f, u1)
+            torch.cuda.synchronize()
+            assert torch.equal(u0, u1)
+            bn = torch.tensor(_boundary_nodes(N), device=dev)
+            assert float((u1[:, bn] - f).abs().max()) <= 1e-9 * float(f.abs().max())
