@@ -1,0 +1,415 @@
+// Multi-RHS block sweeps of the local solves (stage a5): forward and back
+// substitution through the explicit inverses E_l, products on MFMA.  The
+// operator's block structure is described in k_local.hip.
+#include "local_common.h"
+
+namespace msrs {
+
+// ------------------------------------------------------------ sweeps (a5)
+// Twisted block sweeps, matching the twisted elimination (m = nl/2; E_l is
+// the inverse of the top recursion for l < m, of the bottom recursion for
+// l > m, of the two-sided Schur complement at m):
+//   forward halves (one kernel, grid (patch, chunk, half)):
+//     top     y_0 = r_0,        y_{l+1} = r_{l+1} - Low_{l+1} E_l y_l,  l < m-1;
+//             t_top = r_m - Low_m E_{m-1} y_{m-1}
+//     bottom  y_{nl-1} = r_{nl-1}, y_{l-1} = r_{l-1} - Up_{l-1} E_l y_l, l > m+1;
+//             t_bot = Up_m E_{m+1} y_{m+1}
+//   middle and back halves (second kernel, same grid):
+//     x_m = E_m (t_top - t_bot) (both halves form it; the top stores it, and
+//     nothing of the second kernel reads line m of X)
+//     top     x_l = E_l (y_l - Up_l x_{l+1}),   l = m-1 .. 0
+//     bottom  x_l = E_l (y_l - Low_l x_{l-1}),  l = m+1 .. nl-1
+// The y_l overwrite the right-hand sides in place and the x_l the y_l; t_top
+// and t_bot go through a small per-patch buffer, so no workgroup ever waits
+// for another.  In FP32 refinement the solution x_l is the correction, and the
+// back halves also add it to the FP64 iterate (X64, prefetched one stage
+// ahead), which saves a separate accumulation pass.  The products E_l y run
+// on MFMA 16x16x4 (8 waves: wave w owns row tile w of E_l and all column
+// tiles of the chunk).
+//
+// Software pipeline: the A operands of the next E_l are loaded into registers
+// while line l is processed, and the right-hand side and coupling loads of a
+// line are issued before them, so that the in-order load counter never makes
+// the stencil wait for the prefetch.
+constexpr int kSweepThreads = 512;   // 8 waves: wave w owns row tile w of E_l
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+
+// One patch x column chunk x half, with compile-time line tiles R (bp = 16 R)
+// and column tiles NCT (16 NCT samples), so the MFMA loop is straight-line
+// code.  TW: this chunk's [2][bp x sp] middle-line couplings (row stride sp).
+template <typename T, int KIND, int R, int NCT, int PHASE>
+__device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw, double dx,
+                           const T* __restrict__ E, T* __restrict__ X, double* __restrict__ X64, T* __restrict__ TW, int half,
+                           T* ybuf, T* wbuf, double* craw, double* cvp, double* cvm) {
+    typedef typename Vec16<T>::type V;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int BP = 16 * R, NKS = 4 * R, NSC = 16 * NCT;
+    constexpr int DI = kSweepThreads / NSC;          // rows between a thread's elements
+    constexpr int RPT = (BP + DI - 1) / DI;          // elements per thread
+    const int tid = threadIdx.x, lane = tid & 63, rt = tid >> 6;
+    const bool mf = rt < R;                          // this wave owns a row tile
+    const int b = P.b, nl = P.nl, sp = P.sp, L = P.L;
+    const int lstride = BP * sp;
+    const int m = nl / 2;
+    const int dir = half == 0 ? 1 : -1;
+    typename Mfma<T>::acc acc[NCT];
+    T aC[NKS];
+    T rv[RPT];
+    double crow = 0.0;
+    const int i0 = tid / NSC, jj = tid % NSC;
+    T* TWh = TW + (int64_t)half * lstride;
+
+    if (KIND == kKinetic) {
+        for (int a = tid; a < b; a += kSweepThreads) {
+            const double v = vw[a];
+            cvp[a] = v > 0 ? v / dx : 0.0;
+            cvm[a] = v < 0 ? -v / dx : 0.0;
+        }
+    }
+    // Per-line copies of the thread's base indices: the empty asm hides their
+    // loop invariance so that per-element offsets are recomputed each line
+    // instead of being hoisted and kept live.
+    int li0 = i0, ljj = jj, llane = lane;
+    auto launder = [&]() {
+        li0 = i0; ljj = jj; llane = lane;
+        asm volatile("" : "+v"(li0), "+v"(ljj), "+v"(llane));
+    };
+    auto load_line = [&](const T* Xl, T (&dst)[RPT]) {
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) {
+            const int i = li0 + e * DI;
+            if (BP % DI == 0 || i < BP) dst[e] = Xl[(uint32_t)(i * sp + ljj)];
+        }
+    };
+    // every wave loads (the ones past the row tiles a copy of the last tile):
+    // loads outside branches keep the compiler's wait counts exact
+    auto load_A = [&](const T* El) {
+        const int rtc = rt < R ? rt : R - 1;
+        const V* A = reinterpret_cast<const V*>(El + (uint32_t)((rtc * 64 + llane) * NKS));
+#pragma unroll
+        for (int q = 0; q < NKS / VN; ++q) {
+            const V v = A[q];
+#pragma unroll
+            for (int u = 0; u < VN; ++u) aC[q * VN + u] = v[u];
+        }
+    };
+    auto mfma = [&]() {
+        const int lli = llane & 15, llk = llane >> 4;
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) acc[c] = Mfma<T>::zero();
+        if (mf) {
+#pragma unroll
+            for (int kk = 0; kk < NKS; ++kk) {
+                const T* yb = ybuf + (4 * kk + llk) * NSC + lli;
+#pragma unroll
+                for (int c = 0; c < NCT; ++c) acc[c] = Mfma<T>::step(aC[kk], yb[16 * c], acc[c]);
+            }
+        }
+    };
+    // accumulators -> wbuf, and for a solution line (gdst) to global; with
+    // g64 the FP64 iterate of that line (prefetched into pre64) gets += v
+    auto load_64 = [&](const double* g64, double (&dst)[NCT][4]) {
+        const int lli = llane & 15, rtc = rt < R ? rt : R - 1;
+#pragma unroll
+        for (int c = 0; c < NCT; ++c)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = 16 * rtc + Mfma<T>::row(llane, t), j = 16 * c + lli;
+                dst[c][t] = g64[(uint32_t)(i * sp + j)];
+            }
+    };
+    auto store_acc = [&](T* gdst, double* g64, const double (&pre64)[NCT][4]) {
+        const int lli = llane & 15;
+        if (mf) {
+#pragma unroll
+            for (int c = 0; c < NCT; ++c)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int i = 16 * rt + Mfma<T>::row(llane, t), j = 16 * c + lli;
+                    const T v = acc[c][t];
+                    wbuf[i * NSC + j] = v;
+                    if (gdst) gdst[(uint32_t)(i * sp + j)] = v;
+                    if (g64) g64[(uint32_t)(i * sp + j)] = pre64[c][t] + (double)v;
+                }
+        }
+    };
+    // coupling block between two adjacent lines applied to column j of src,
+    // row i: Low (A_{l+1,l}) if low, else Up (A_{l,l+1}).  Elliptic: the
+    // symmetric tridiagonal block of their shared cell row c: diagonal
+    // -(c_i + c_{i+1})/6, off-diagonal (i, i+1) -c_{i+1}/3; craw holds the
+    // row already scaled by -1/3
+    auto couple = [&](const T* src, int i, int j, bool low) -> double {
+        if (KIND == kElliptic) {
+            const int im = i > 0 ? i - 1 : 0, ip = i + 1 < BP ? i + 1 : BP - 1;
+            const double cm = i > 0 ? craw[i] : 0.0;
+            const double cp = i < b - 1 ? craw[i + 1] : 0.0;
+            return 0.5 * (craw[i] + craw[i + 1]) * (double)src[i * NSC + j] + cm * (double)src[im * NSC + j] +
+                   cp * (double)src[ip * NSC + j];
+        } else {
+            return -(low ? cvp[i] : cvm[i]) * (double)src[i * NSC + j];
+        }
+    };
+
+    // Register sets of prefetched loads alternate between consecutive steps
+    // (the step body is instantiated twice per loop trip), so that no copy of
+    // a register with a load in flight makes the wave wait for it early.
+    double nopre[NCT][4] = {};
+    if constexpr (PHASE == 0) {
+        // ---- forward half: lines ln0, ln0 + dir, ...; the last one couples into m
+        const int nst = half == 0 ? m : nl - 1 - m;
+        const int ln0 = half == 0 ? 0 : nl - 1;
+        const bool low = half == 0;   // top: Low_{l+1} (line below from above); bottom: Up_{l-1}
+        T rvA[RPT], rvB[RPT];
+        launder();
+        if (nst <= 0) {
+            // no line in this half: t_top = r_m, t_bot = 0
+            if (half == 0) load_line(X + m * lstride, rvA);
+#pragma unroll
+            for (int e = 0; e < RPT; ++e) {
+                const int i = li0 + e * DI;
+                if (BP % DI == 0 || i < BP) TWh[(uint32_t)(i * sp + ljj)] = (half == 0 && i < b) ? rvA[e] : T(0);
+            }
+            return;
+        }
+        // step k works on line ln = ln0 + dir k and its successor nx = ln + dir
+        // (m after the last step); the successor's right-hand side r_nx and the
+        // shared cell row are loaded during the step before, after its products
+        // (so that the products' operand waits never cover them), E_nx likewise
+        auto sub_of = [&](int k) { return k + 1 < nst || half == 0; };   // the top's last step carries r_m
+        load_line(X + ln0 * lstride, rvA);                 // y_{ln0} = r_{ln0}
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) {
+            const int i = li0 + e * DI;
+            if (BP % DI == 0 || i < BP) ybuf[i * NSC + ljj] = rvA[e];
+        }
+        load_A(E + (int64_t)ln0 * BP * BP);
+        double crA = 0.0, crB = 0.0;
+        if (sub_of(0)) load_line(X + (ln0 + dir) * lstride, rvA);
+        if (KIND == kElliptic) crA = aL[(dir > 0 ? ln0 + 1 : ln0) * L + min(tid, b)];
+        lds_barrier();
+        auto step = [&](int k, T (&rc)[RPT], T (&rn)[RPT], double& cc, double& cn) {
+            launder();
+            const int ln = ln0 + dir * k, nx = ln + dir;
+            const bool more = k + 1 < nst;
+            const bool sub = sub_of(k);
+            mfma();                                                                   // w = E_ln y_ln
+            // r of the next step, its cell row and E (unconditional, clamped to
+            // lines that exist when there is no next step)
+            load_line(X + ((more && sub_of(k + 1)) ? nx + dir : nx) * lstride, rn);
+            if (KIND == kElliptic) cn = aL[(more ? (dir > 0 ? nx + 1 : nx) : (dir > 0 ? ln + 1 : ln)) * L + min(tid, b)];
+            load_A(E + (int64_t)(more ? nx : ln) * BP * BP);
+            store_acc(nullptr, nullptr, nopre);
+            if (KIND == kElliptic && tid <= b) craw[tid] = cc * (-1.0 / 3.0);
+            lds_barrier();
+            T* dst = more ? X + nx * lstride : TWh;
+#pragma unroll
+            for (int e = 0; e < RPT; ++e) {
+                const int i = li0 + e * DI;
+                if (BP % DI == 0 || i < BP) {
+                    const double cw = couple(wbuf, i, ljj, low);
+                    const double v = sub ? (double)rc[e] - cw : cw;
+                    const T y = i < b ? (T)v : T(0);
+                    dst[(uint32_t)(i * sp + ljj)] = y;
+                    if (more) ybuf[i * NSC + ljj] = y;
+                }
+            }
+            lds_barrier();
+        };
+        for (int k = 0; k < nst; k += 2) {
+            step(k, rvA, rvB, crA, crB);
+            if (k + 1 < nst) step(k + 1, rvB, rvA, crB, crA);
+        }
+    } else {
+        // ---- middle line, then the back half; step k solves line
+        // ln = m - dir (k + 1) from pv = ln + dir.  Its right-hand side y_ln, the
+        // shared cell row and (FP32 refinement) the FP64 iterate of the line are
+        // loaded one step ahead, E_ln during the step before.
+        // PHASE 2 is the first solve of a refinement: the FP64 iterate holds
+        // nothing yet and is written, not accumulated (pre64 stays zero).
+        launder();
+        constexpr bool kAccum = PHASE == 1;
+        double pre64[NCT][4] = {}, pre64n[NCT][4] = {};
+        load_A(E + (int64_t)m * BP * BP);
+        const bool acc64 = X64 && half == 0;   // line m's iterate is updated once, by the top half
+        if (kAccum && acc64) load_64(X64 + m * lstride, pre64);
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) {
+            const int i = li0 + e * DI;
+            if (BP % DI == 0 || i < BP) {
+                const double v = (double)TW[(uint32_t)(i * sp + ljj)] - (double)TW[lstride + (uint32_t)(i * sp + ljj)];
+                ybuf[i * NSC + ljj] = i < b ? (T)v : T(0);
+            }
+        }
+        const int nst = half == 0 ? m : nl - 1 - m;
+        const bool low = half != 0;   // top: Up_l x_{l+1}; bottom: Low_l x_{l-1}
+        if (nst > 0) {
+            const int l1 = m - dir;
+            load_line(X + l1 * lstride, rv);
+            if (KIND == kElliptic && tid <= b) crow = aL[(dir > 0 ? m : l1) * L + tid];
+            if (kAccum && X64) load_64(X64 + l1 * lstride, pre64n);
+        }
+        lds_barrier();
+        mfma();
+        if (nst > 0) load_A(E + (int64_t)(m - dir) * BP * BP);        // the first back line, one step ahead
+        // x_m (identical in both halves).  With an FP64 iterate (refinement) the
+        // FP32 solution is not stored: the iterate takes it, and the line
+        // vectors are next overwritten by the residual.
+        store_acc(half == 0 && !X64 ? X + m * lstride : nullptr, acc64 ? X64 + m * lstride : nullptr, pre64);
+        lds_barrier();
+        for (int k = 0; k < nst; ++k) {
+            launder();
+            const int ln = m - dir * (k + 1);
+            const bool more = k + 1 < nst;
+#pragma unroll
+            for (int c = 0; c < NCT; ++c)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) pre64[c][t] = pre64n[c][t];
+            T rvn[RPT];
+            double crown = 0.0;
+            if (more) {
+                const int l2 = ln - dir;
+                load_line(X + l2 * lstride, rvn);                                     // y of the next step
+                if (KIND == kElliptic && tid <= b) crown = aL[(dir > 0 ? ln : l2) * L + tid];
+                if (kAccum && X64) load_64(X64 + l2 * lstride, pre64n);
+            }
+            if (KIND == kElliptic && tid <= b) craw[tid] = crow * (-1.0 / 3.0);
+            lds_barrier();
+#pragma unroll
+            for (int e = 0; e < RPT; ++e) {
+                const int i = li0 + e * DI;
+                if (BP % DI == 0 || i < BP) {
+                    const double v = (double)rv[e] - couple(wbuf, i, ljj, low);
+                    ybuf[i * NSC + ljj] = i < b ? (T)v : T(0);
+                }
+            }
+            lds_barrier();
+            mfma();                                                                    // x_ln = E_ln z
+            if (more) load_A(E + (int64_t)(ln - dir) * BP * BP);                     // E of the next line
+            store_acc(X64 ? nullptr : X + ln * lstride, X64 ? X64 + ln * lstride : nullptr, pre64);
+#pragma unroll
+            for (int e = 0; e < RPT; ++e) rv[e] = rvn[e];
+            crow = crown;
+            lds_barrier();
+        }
+    }
+}
+
+// grid (patch, column chunk of 16*NCT samples, half); sp of every patch is a
+// multiple of the chunk.
+template <typename T, int KIND, int NCT, int PHASE>
+__global__ __launch_bounds__(kSweepThreads) void sweep_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
+                                                              const double* __restrict__ vw, double dx, const T* __restrict__ E_all,
+                                                              T* __restrict__ X_all, double* __restrict__ X64_all, T* __restrict__ TW_all,
+                                                              const int32_t* __restrict__ conv, int32_t* flags) {
+    __shared__ T ybuf[kMaxLine * 16 * NCT];
+    __shared__ T wbuf[kMaxLine * 16 * NCT];
+    __shared__ double craw[kMaxLine + 1];
+    __shared__ double cvp[kMaxLine], cvm[kMaxLine];
+    const int p = p0 + blockIdx.x;
+    if (conv && conv[p]) return;
+    const PatchDesc P = pd[p];
+    const int s0 = blockIdx.y * 16 * NCT;
+    if (s0 >= P.sp) return;
+    const int half = blockIdx.z;
+    const double* aL = aL_all + P.a_off;
+    const T* E = E_all + P.E_off;
+    T* X = X_all + P.x_off + s0;
+    T* TW = TW_all + P.tw_off + s0;
+    double* X64 = X64_all ? X64_all + P.x_off + s0 : nullptr;
+#define MSRS_SWB(RR) sweep_body<T, KIND, RR, NCT, PHASE>(P, aL, vw, dx, E, X, X64, TW, half, ybuf, wbuf, craw, cvp, cvm)
+    if (KIND == kKinetic) {
+        switch (P.bp >> 4) {
+            case 1: MSRS_SWB(1); break;
+            case 2: MSRS_SWB(2); break;
+            case 3: MSRS_SWB(3); break;
+            case 4: MSRS_SWB(4); break;
+            default: if (threadIdx.x == 0) raise_flag(flags, 3); break;
+        }
+        return;
+    }
+    switch (P.bp >> 4) {
+        case 1: MSRS_SWB(1); break;
+        case 2: MSRS_SWB(2); break;
+        case 3: MSRS_SWB(3); break;
+        case 4: MSRS_SWB(4); break;
+        case 5: MSRS_SWB(5); break;
+        case 6: MSRS_SWB(6); break;
+        case 7: MSRS_SWB(7); break;
+        case 8: MSRS_SWB(8); break;
+        default: if (threadIdx.x == 0) raise_flag(flags, 3); break;
+    }
+#undef MSRS_SWB
+}
+
+// a register budget) not above the requested width that divides every sp
+static int sweep_chunk(const Ctx& c, int p0, int p1, bool fp32) {
+    int want = fp32 ? c.sweep_cols32 : std::min(c.sweep_cols64, 32);
+    for (int sc : {64, 32, 16}) {
+        if (sc > want) continue;
+        bool ok = true;
+        for (int p = p0; p < p1; ++p) ok = ok && (c.hp[p].sp % sc == 0);
+        if (ok) return sc;
+    }
+    return 16;
+}
+
+void launch_sweep(Ctx& c, int p0, int p1, bool fp32, bool first) {
+    StageTimer t(c, MSRS_K_SWEEP);
+    int maxsp = 0;
+    for (int p = p0; p < p1; ++p) maxsp = std::max(maxsp, c.hp[p].sp);
+    const int sc = sweep_chunk(c, p0, p1, fp32);
+    const dim3 grid(p1 - p0, maxsp / sc, 2), blk(kSweepThreads);
+    const int32_t* conv = fp32 ? c.conv : nullptr;
+    const double dx = dx_of(c);
+    // FP32 refinement: the back halves add the correction to the FP64 iterate
+    double* x64acc = fp32 ? c.x64 : nullptr;
+#define MSRS_SWEEP(TT, KK, NN, XX)                                                                                             \
+    do {                                                                                                                      \
+        hipLaunchKernelGGL((sweep_kernel<TT, KK, NN, 0>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, \
+                           (double*)nullptr, (TT*)c.tw, conv, c.dflags);                                                      \
+        hipLaunchKernelGGL((sweep_kernel<TT, KK, NN, 1>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, \
+                           x64acc, (TT*)c.tw, conv, c.dflags);                                                                 \
+    } while (0)
+    // the first solve of a refinement writes the FP64 iterate instead of adding to it
+#define MSRS_SWEEP_FIRST(KK, NN)                                                                                               \
+    do {                                                                                                                      \
+        hipLaunchKernelGGL((sweep_kernel<float, KK, NN, 0>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const float*)c.E, \
+                           c.x32, (double*)nullptr, (float*)c.tw, conv, c.dflags);                                            \
+        hipLaunchKernelGGL((sweep_kernel<float, KK, NN, 2>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const float*)c.E, \
+                           c.x32, x64acc, (float*)c.tw, conv, c.dflags);                                                      \
+    } while (0)
+    if (c.kind == kElliptic) {
+        if (fp32 && first) {
+            if (sc == 64) MSRS_SWEEP_FIRST(kElliptic, 4);
+            else if (sc == 32) MSRS_SWEEP_FIRST(kElliptic, 2);
+            else MSRS_SWEEP_FIRST(kElliptic, 1);
+        } else if (fp32) {
+            if (sc == 64) MSRS_SWEEP(float, kElliptic, 4, c.x32);
+            else if (sc == 32) MSRS_SWEEP(float, kElliptic, 2, c.x32);
+            else MSRS_SWEEP(float, kElliptic, 1, c.x32);
+        } else {
+            if (sc == 32) MSRS_SWEEP(double, kElliptic, 2, c.x64);
+            else MSRS_SWEEP(double, kElliptic, 1, c.x64);
+        }
+    } else {
+        if (fp32 && first) {
+            if (sc == 64) MSRS_SWEEP_FIRST(kKinetic, 4);
+            else if (sc == 32) MSRS_SWEEP_FIRST(kKinetic, 2);
+            else MSRS_SWEEP_FIRST(kKinetic, 1);
+        } else if (fp32) {
+            if (sc == 64) MSRS_SWEEP(float, kKinetic, 4, c.x32);
+            else if (sc == 32) MSRS_SWEEP(float, kKinetic, 2, c.x32);
+            else MSRS_SWEEP(float, kKinetic, 1, c.x32);
+        } else {
+            if (sc == 32) MSRS_SWEEP(double, kKinetic, 2, c.x64);
+            else MSRS_SWEEP(double, kKinetic, 1, c.x64);
+        }
+    }
+#undef MSRS_SWEEP
+#undef MSRS_SWEEP_FIRST
+}
+
+}  // namespace msrs
