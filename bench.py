@@ -75,12 +75,34 @@ def measured_traffic(kernel_class):
     return None
 
 
+def host_info():
+    """CPU model, the threads the process may use, and numpy's LAPACK."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        import numpy as np
+        lp = np.__config__.CONFIG["Build Dependencies"]["lapack"]
+        lapack = f"{lp.get('name')} {lp.get('version')}"
+    except Exception:
+        lapack = "unknown"
+    return dict(cpu_model=model, cores=len(os.sched_getaffinity(0)), lapack=lapack)
+
+
 def cpu_baseline(cfg, max_seconds=20.0):
-    """The oracle's offline stage on the host cores, over a bounded sample of patches."""
+    """The oracle's offline stage on every host core the process may use, over
+    a bounded sample of patches (one process per core, one BLAS thread each)."""
     from concurrent.futures import ProcessPoolExecutor
-    workers = max(1, min(16, len(os.sched_getaffinity(0))))
     import numpy as np
     from oracle import elliptic as E
+    info = host_info()
+    workers = info["cores"]
     geo = E.patch_geometry(cfg["N"], cfg["M"], cfg["overlap"])
     # probe one interior patch to size the sample
     t0 = time.perf_counter()
@@ -96,7 +118,44 @@ def cpu_baseline(cfg, max_seconds=20.0):
     return {"value": n * cfg["s"] / T, "unit": "patch×sample local solves/s", "cores": workers, "kind": "oracle",
             "sample": f"{n} of {len(geo)} patches of {cfg['name']} (offline stage: banded Cholesky, "
                       f"{cfg['s']} solves, restriction, QR+SVD), {workers} worker processes x 1 BLAS thread, "
-                      f"{T:.1f} s"}
+                      f"{T:.1f} s", "cpu_model": info["cpu_model"], "lapack": info["lapack"]}
+
+
+def cpu_online(names=("elliptic_lognormal_512", "elliptic_lognormal_1024"), n_req=100):
+    """The oracle's online stage per request: the least-squares coefficients
+    from the precomputed Householder QR of P~ (Q^T d, a triangular solve) and
+    the partition-of-unity reconstruction; median of n_req requests per domain.
+    The offline bases and the QR are computed first, untimed (the offline
+    patches over every host core)."""
+    from concurrent.futures import ProcessPoolExecutor
+    import numpy as np
+    import synth
+    from synth import configs
+    from oracle import elliptic as E
+    workers = len(os.sched_getaffinity(0))
+    out = {}
+    for name in names:
+        cfg = configs.WORKLOADS[name]()
+        geo = E.patch_geometry(cfg["N"], cfg["M"], cfg["overlap"])
+        t0 = time.perf_counter()
+        with ProcessPoolExecutor(max_workers=workers, initializer=_one_thread) as ex:
+            ref = list(ex.map(_oracle_patch_basis, [(cfg, g) for g in geo]))
+        P, n_cont, drows, off = E.coarse_rows(cfg["N"], cfg["M"], ref, cfg["coef"])
+        Qf, Rf = E.coarse_factor(P)
+        t_setup = time.perf_counter() - t0
+        reqs = synth.fourier_boundary(cfg["N"], range(n_req))
+        ts = []
+        for r in range(n_req):
+            t0 = time.perf_counter()
+            c = E.coarse_solve(Qf, Rf, n_cont, drows, reqs[r])
+            E.reconstruct(cfg["N"], cfg["M"], ref, off, c)
+            ts.append(time.perf_counter() - t0)
+        out[cfg["name"]] = {"p50_ms": float(np.median(ts) * 1e3), "p99_ms": float(np.percentile(ts, 99) * 1e3),
+                            "requests": n_req, "setup_s": t_setup, "ls_rows": int(P.shape[0]),
+                            "coarse_dim": int(P.shape[1])}
+        print(f"[bench] cpu online {cfg['name']}: p50 {out[cfg['name']]['p50_ms']:.1f} ms "
+              f"(set-up {t_setup:.0f} s)", file=sys.stderr, flush=True)
+    return out
 
 
 def _one_thread():
@@ -114,6 +173,15 @@ def _oracle_patch(args):
     Y = E.sample_patch(cfg["coef"], cfg["N"], g, E.patch_omega(cfg["seed"], g, cfg["s"]))
     range_finder(Y, cfg["k"])
     return 0
+
+
+def _oracle_patch_basis(args):
+    cfg, g = args
+    from oracle import elliptic as E
+    from oracle.rangefinder import range_finder
+    Y = E.sample_patch(cfg["coef"], cfg["N"], g, E.patch_omega(cfg["seed"], g, cfg["s"]))
+    Q, sv = range_finder(Y, cfg["k"])
+    return dict(geo=g, Q=Q, sv=sv)
 
 
 def _desc(cfg, precision, flags, seed):
@@ -179,19 +247,20 @@ def run_pipelined(cfg, precision, pr, a, steps, warmup, max_handles, tune, facto
             ph.close()
 
 
-def run_gpu(cfg, precision, steps, warmup, flags=0, tune=False, graph=False, pipeline=0):
+def run_gpu(cfg, precision, steps, warmup, flags=0, tune=False, graph=False, pipeline=0, timing=True):
     """Time `steps` offline steps (assemble + sample + range finder) after `warmup`.
 
     Eager: the three calls per step, with per-kernel-class HIP event timing.
     graph=True additionally times replays of the captured step (the
     production form: no host synchronisation between refinement iterations);
     pipeline=P > 0 then times the throughput form with up to P handles.
+    timing=False leaves out the per-kernel-class events (wall clock only).
     """
     import torch
     from paper_1807_08848_amd import msrs, tuning
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream()
-    d = _desc(cfg, precision, flags | msrs.FLAG_TIMING, cfg["seed"])
+    d = _desc(cfg, precision, flags | (msrs.FLAG_TIMING if timing else 0), cfg["seed"])
     with torch.cuda.stream(stream):
         pr = msrs.Problem(d, stream=stream)
         a = torch.tensor(cfg["coef"], device=dev)
@@ -307,6 +376,42 @@ def run_constrained(reps=50):
     return out
 
 
+def _fixtures():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("online_fixtures",
+                                                  os.path.join(ROOT, "tests", "golden", "make_online_fixtures.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def served_accuracy(srv, cfgs, pool):
+    """Relative L2 error of served solutions against the oracle's (its own
+    bases, Householder-QR least squares and reconstruction), stored at every
+    32nd node in each direction for serving requests 0..3 of both domains;
+    submitted as one interleaved mix through the server."""
+    import numpy as np
+    fx = _fixtures()
+    ref = [fx.load(_fixture_name(c)) for c in cfgs]
+    tickets = []
+    for r in range(fx.N_REQUESTS):
+        for m in range(len(cfgs)):
+            tickets.append((m, r, srv.submit(m, pool[m][r])))
+    worst = {}
+    for m, r, t in tickets:
+        nodes, U, _ = ref[m]
+        u = np.empty(srv.problems[m].layout().n_nodes)
+        srv.fetch(t, u)
+        e = float(np.linalg.norm(u[nodes] - U[:, 1 + r]) / np.linalg.norm(U[:, 1 + r]))
+        worst[cfgs[m]["name"]] = max(worst.get(cfgs[m]["name"], 0.0), e)
+    return worst
+
+
+def _fixture_name(cfg):
+    return {"elliptic_lognormal_N512_M8_s32_k12": "elliptic_lognormal_512",
+            "elliptic_lognormal_N1024_M16_s64_k16": "elliptic_lognormal_1024"}[cfg["name"]]
+
+
 def run_serving(lams=(200, 500, 1000, 2000), seconds=2.0, seed_arrival=5):
     """Online stage over two resident models (h = 1/512 and h = 1/1024 domains).
 
@@ -373,6 +478,7 @@ def run_serving(lams=(200, 500, 1000, 2000), seconds=2.0, seed_arrival=5):
     rng = np.random.default_rng(seed_arrival)
     res = {}
     with msrs.Server(models, n_streams=4, max_batch=32, slot_bytes=2 << 30) as srv:
+        accuracy = served_accuracy(srv, cfgs, pool)
         mdl = rng.integers(0, 2, 200)
         srv.replay(mdl, [pool[m][i % 64] for i, m in enumerate(mdl)])          # warm-up
         for lam in lams:
@@ -397,7 +503,7 @@ def run_serving(lams=(200, 500, 1000, 2000), seconds=2.0, seed_arrival=5):
         "workload": "serving over elliptic_lognormal_512 + elliptic_lognormal_1024 (50/50, Poisson arrivals)",
         "n_nodes": nn, "coarse_dim": [int(m.layout().coarse_dim) for m in models], "setup_s": setup,
         "autotune": [m.tuned for m in models],
-        "rel_err_batched_vs_banded": acc, "open_loop": res,
+        "rel_err_batched_vs_banded": acc, "rel_err_vs_oracle": accuracy, "open_loop": res,
         "saturation_solves_per_s": sat, "saturation_mean_batch": sat_batch, "saturation": sat_s,
         "plain_fp64_ms_per_request": plain,
         "plain_fp64_solves_per_s": plain_rate, "speedup_vs_plain": sat / plain_rate,
@@ -414,10 +520,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="elliptic_lognormal_512")
+    ap.add_argument("--workload", default="elliptic_lognormal_1024")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cpu-online", action="store_true")
     ap.add_argument("--handles", type=int, default=8,
                     help="largest number of concurrent handles tried for the throughput form (1: one handle)")
     args = ap.parse_args()
@@ -479,10 +586,23 @@ def main():
     if kinetic:
         out["roofline"] = None     # no banded-direct count is defined for the transport operator here
     if not args.no_plain:
+        # the plain FP64 method: FP64 factor and sweeps, no refinement, one
+        # launch per patch per stage, eager, no events
         print("[bench] plain FP64 reference (one launch per patch per stage)", file=sys.stderr, flush=True)
-        rp = run_gpu(cfg, msrs.PREC_FP64, max(1, min(3, args.steps)), 1, flags=msrs.FLAG_PER_PATCH_LAUNCH)
-        vp = rp["n_solves"] * max(1, min(3, args.steps)) / rp["T"]
-        out["plain_fp64"] = {"value": vp, "speedup": value / vp}
+        n_plain = max(1, min(3, args.steps))
+        rp = run_gpu(cfg, msrs.PREC_FP64, n_plain, 1, flags=msrs.FLAG_PER_PATCH_LAUNCH, timing=False)
+        vp = rp["n_solves"] * n_plain / rp["T"]
+        out["plain_fp64"] = {"value": vp, "speedup": value / vp,
+                             "form": "eager, one launch per patch per stage, FP64 factor and sweeps"}
+        # the same FP64 method in the timed form (batched launches, graph
+        # replay, concurrent handles): the precision pattern's own gain
+        print("[bench] batched FP64 in the timed form", file=sys.stderr, flush=True)
+        rb = run_gpu(cfg, msrs.PREC_FP64, args.steps, args.warmup, graph=True, pipeline=args.handles, timing=False)
+        Tb = rb["pipe"]["T"] if rb.get("pipe") else rb["T_graph"]
+        vb = rb["n_solves"] * args.steps / Tb
+        out["batched_fp64"] = {"value": vb, "speedup": value / vb,
+                               "handles": rb["pipe"]["handles"] if rb.get("pipe") else 1,
+                               "form": "batched launches, graph replay by concurrent handles, FP64 factor and sweeps"}
     if not args.no_serve:
         print("[bench] online serving (two resident models)", file=sys.stderr, flush=True)
         out["online"] = run_serving()
@@ -491,6 +611,8 @@ def main():
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)
+        if not args.no_cpu_online:
+            out["cpu_baseline"]["online"] = cpu_online()
     print(json.dumps(out), flush=True)
 
 

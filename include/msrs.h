@@ -80,6 +80,7 @@ typedef int32_t msrs_status;
 #define MSRS_ERR_RANK       8   /* sketch rank below the requested rank k */
 #define MSRS_ERR_BUSY       9   /* no free online slot */
 #define MSRS_ERR_IO        10   /* a basis file could not be written or read, or is not one */
+#define MSRS_ERR_NONFINITE 11   /* non-finite values in the boundary samples, local solutions or residuals */
 
 #define MSRS_KIND_ELLIPTIC_Q1 0
 #define MSRS_KIND_KINETIC_DO  1
@@ -124,7 +125,8 @@ typedef struct msrs_problem_desc {
     int32_t ir_max_iters;    /* FP32_IR: refinement iterations at most (0 -> 30) */
     int32_t n_vel;           /* kinetic: Gauss-Legendre ordinates (even, 2..64) */
     uint64_t seed;           /* Philox key of the device-drawn boundary samples */
-    double ir_tol;           /* FP32_IR: stop when every ||r_j||/||rhs_j|| <= ir_tol (0 -> 1e-10) */
+    double ir_tol;           /* FP32_IR: every column must reach ||r_j||/||rhs_j|| <= ir_tol (0 -> 1e-10), else
+                                MSRS_ERR_NOCONV after ir_max_iters refinement iterations */
     double eps;              /* kinetic: eps of the collision term */
     const int32_t* overlap;  /* host: buffer width in cells per patch (M*M elliptic, M kinetic) */
     uint32_t flags;          /* MSRS_FLAG_* */
@@ -136,7 +138,12 @@ typedef struct msrs_problem_desc {
     double rank_tol;         /* 0: every sampled patch keeps rank k.  In (0, 1): each keeps its numerical rank at
                                 this relative tolerance (Def. num_rank with tau = rank_tol sigma_1(Y_m): the number of
                                 singular values of Y_m above it), at least 1 and at most k; msrs_query_patch reports
-                                it as n_cols once the range finder has run, and the columns of Q past it are zero. */
+                                it as n_cols once the range finder has run, and the columns of Q past it are zero.
+                                Values below the range finder's resolution 2 sqrt(s u) (u = 2^-53) are refused. */
+    double ir_stop;          /* FP32_IR: refinement runs to stagnation.  A patch stops once the largest
+                                ||r_j||/||rhs_j|| of its columns is <= ir_stop, or is <= ir_tol and the last
+                                iteration did not halve it (0 -> 1e-13, the level of the FP64 residual's own
+                                rounding; ir_stop = ir_tol stops at ir_tol). */
 } msrs_problem_desc;
 
 typedef struct msrs_layout {
@@ -225,8 +232,10 @@ msrs_status msrs_assemble_patch(msrs_handle h, const double* coef_dev);
  * the device with Philox4x32-10 (key = seed, counter = (node, sample,
  * patch, 0), Box-Muller on two 53-bit uniforms).  Y_out_dev: device,
  * optional copy of the concatenated Y (NULL: kept resident only).
- * FP32_IR refines each column until ||r||/||rhs|| <= ir_tol.
- * Errors: ARG, STATE; latched NOT_SPD / NOCONV.
+ * FP32_IR refines each patch to stagnation (desc.ir_stop) and requires
+ * ||r||/||rhs|| <= ir_tol of every column.
+ * Errors: ARG, STATE; latched NOT_SPD / NOCONV / NONFINITE (a non-finite
+ * boundary value, right-hand side or residual norm).
  */
 msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, double* Y_out_dev);
 
@@ -237,7 +246,11 @@ msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, 
  * entry made positive.  Full-basis patches keep all columns.
  * Q_out_dev: device, optional copy of the concatenated Q.  sv_out_dev:
  * device, optional s singular values of each Y_m (descending).
- * Errors: STATE; latched RANK if sigma_k(Y_m) <= 1e-13 sigma_1(Y_m).
+ * The singular values come from the Gram matrix Y_m^T Y_m, which resolves
+ * them down to about sqrt(s u) sigma_1 (u = 2^-53).
+ * Errors: STATE; latched RANK if sigma_k(Y_m) <= 2 sqrt(s u) sigma_1(Y_m)
+ * (the k-th direction is not resolved) or the orthonormalisation breaks down;
+ * latched NONFINITE for non-finite snapshots.
  */
 msrs_status msrs_range_finder(msrs_handle h, double* Q_out_dev, double* sv_out_dev);
 
@@ -293,9 +306,9 @@ msrs_status msrs_solve_global_banded(msrs_handle h, int32_t n_req, const double*
  * is baked into the graph: it must stay valid, and a replay reads its
  * current contents.  FP32_IR: the graph runs a fixed number of refinement
  * iterations, one more than the most any patch needed in the preceding
- * eager sampling call (required first); converged patches skip their work,
- * so the results equal the eager ones, and a patch still above ir_tol after
- * the last iteration latches MSRS_ERR_NOCONV.  A new capture replaces the
+ * eager sampling call (required first); patches that have stopped skip their
+ * work, so the results equal the eager ones, and a patch still above ir_tol
+ * after the last iteration latches MSRS_ERR_NOCONV.  A new capture replaces the
  * previous graph.  Synchronises.  Errors: ARG, STATE, HIP.
  */
 msrs_status msrs_offline_graph_capture(msrs_handle h, const double* coef_dev);
@@ -317,6 +330,19 @@ msrs_status msrs_copy_results(msrs_handle h, double* Y_out_dev, double* Q_out_de
  * Full-basis patches hold the identity.  Errors: ARG, STATE.
  */
 msrs_status msrs_copy_omega(msrs_handle h, double* omega_out_dev);
+
+/*
+ * The device generator of the random boundary data (Sec. 3, RanLocalSolu:
+ * i.i.d. N(0,1) values at the boundary nodes), without a handle: for nodes
+ * 0..n_node-1 and samples 0..n_sample-1 of patch `patch` under key `seed`,
+ * the four Philox4x32-10 output words of counter (node, sample, patch, 0) go
+ * to words_dev[4 (sample n_node + node) + t], t = 0..3 (device, nullable),
+ * and the normal msrs_sample_local_solutions draws for that node and sample
+ * to normals_dev[sample n_node + node] (device, nullable).  Enqueued on
+ * stream (NULL: the default stream).  Errors: ARG (negative sizes), HIP.
+ */
+msrs_status msrs_draw_boundary_samples(uint64_t seed, int32_t patch, int32_t n_node, int32_t n_sample, uint32_t* words_dev,
+                                       double* normals_dev, void* stream);
 
 /*
  * Keep the product of the offline stage (the call summary of the method,

@@ -18,6 +18,11 @@ thread_local std::string g_create_err;
 
 int round16(int v) { return ((v + 15) / 16) * 16; }
 
+// Smallest sigma_j / sigma_1 the Gram-matrix range finder resolves for s
+// samples: the eigenvalues of the rounded Y^T Y carry absolute errors of about
+// s u sigma_1^2 (u = 2^-53).
+double gram_resolution(int s) { return 2.0 * std::sqrt((double)s * 0x1p-53); }
+
 // Gauss-Legendre nodes (ascending) and weights on [-1, 1], Newton iteration
 // on the three-term recurrence of the Legendre polynomials.
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
@@ -170,6 +175,11 @@ msrs_status validate(const msrs_problem_desc* d, std::string& msg) {
     if (d->precision != MSRS_PREC_FP64 && d->precision != MSRS_PREC_FP32_IR) { msg = "unknown precision"; return MSRS_ERR_ARG; }
     if (!d->overlap) { msg = "overlap is NULL"; return MSRS_ERR_ARG; }
     if (!(d->rank_tol >= 0.0 && d->rank_tol < 1.0)) { msg = "rank_tol must be in [0, 1)"; return MSRS_ERR_ARG; }
+    if (d->rank_tol > 0.0 && d->rank_tol < gram_resolution(d->n_samples)) {
+        msg = "rank_tol below the range finder's resolution 2 sqrt(s u)";
+        return MSRS_ERR_ARG;
+    }
+    if (!(d->ir_tol >= 0.0) || !(d->ir_stop >= 0.0)) { msg = "ir_tol and ir_stop must be >= 0"; return MSRS_ERR_ARG; }
     const int np = d->kind == MSRS_KIND_ELLIPTIC_Q1 ? d->M * d->M : d->M;
     for (int p = 0; p < np; ++p)
         if (d->overlap[p] < 0) { msg = "negative overlap"; return MSRS_ERR_ARG; }
@@ -209,13 +219,14 @@ msrs_status validate(const msrs_problem_desc* d, std::string& msg) {
 void latch_from_host(Ctx& c, msrs_status& st) {
     // flags copied to pinned memory by the last synchronising call
     if (c.hflags[0]) { st = MSRS_ERR_NOT_SPD; c.err = "non-positive coefficient or pivot"; }
+    else if (c.hflags[4]) { st = MSRS_ERR_NONFINITE; c.err = "non-finite boundary data, local solution or residual"; }
     else if (c.hflags[1]) { st = MSRS_ERR_NOCONV; c.err = "iterative refinement did not reach ir_tol"; }
     else if (c.hflags[2]) { st = MSRS_ERR_RANK; c.err = "sketch rank below the requested rank"; }
     else if (c.hflags[3]) { st = MSRS_ERR_ARG; c.err = "unsupported patch shape on the device"; }
 }
 
 void sync_flags(Ctx& c) {
-    MSRS_HIP_CHECK(hipMemcpyAsync(c.hflags, c.dflags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+    MSRS_HIP_CHECK(hipMemcpyAsync(c.hflags, c.dflags, kFlags * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
     MSRS_HIP_CHECK(hipStreamSynchronize(c.stream));
 }
 
@@ -369,7 +380,7 @@ void drop_graph(Ctx* c) {
 // ---- basis files
 namespace {
 constexpr char kBasisMagic[8] = {'M', 'S', 'R', 'S', 'B', 'A', 'S', '1'};
-constexpr uint32_t kBasisVersion = 1;
+constexpr uint32_t kBasisVersion = 2;   // 2: adds ir_stop after rank_tol
 
 // FNV-1a (64-bit) over a byte range, continuing from h
 uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
@@ -443,6 +454,7 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->prec = desc->precision;
         c->ir_max = desc->ir_max_iters > 0 ? desc->ir_max_iters : 30;
         c->ir_tol = desc->ir_tol > 0 ? desc->ir_tol : 1e-10;
+        c->ir_stop = std::min(c->ir_tol, desc->ir_stop > 0 ? desc->ir_stop : 1e-13);
         c->eps = desc->kind == MSRS_KIND_KINETIC_DO ? desc->eps : 1.0;
         c->hg = desc->kind == MSRS_KIND_KINETIC_DO ? desc->hg_g : 0.0;
         c->rank_tol = desc->rank_tol;
@@ -515,14 +527,14 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
                 }
             }
         }
-        c->dflags = dalloc<int32_t>(*c, 4);
+        c->dflags = dalloc<int32_t>(*c, kFlags);
         c->coef_copy = dalloc<double>(*c, c->kind == kElliptic ? (int64_t)c->N * c->N : c->N);
-        MSRS_HIP_CHECK(hipMemset(c->dflags, 0, 4 * sizeof(int32_t)));
+        MSRS_HIP_CHECK(hipMemset(c->dflags, 0, kFlags * sizeof(int32_t)));
         MSRS_HIP_CHECK(hipMemset(c->gap, 0, 2 * c->n_patches * sizeof(double)));
         MSRS_HIP_CHECK(hipMemset(c->iters, 0, c->n_patches * sizeof(int32_t)));
         MSRS_HIP_CHECK(hipMemset(c->x64, 0, c->x_total * sizeof(double)));
-        MSRS_HIP_CHECK(hipHostMalloc((void**)&c->hflags, 4 * sizeof(int32_t), hipHostMallocDefault));
-        std::memset(c->hflags, 0, 4 * sizeof(int32_t));
+        MSRS_HIP_CHECK(hipHostMalloc((void**)&c->hflags, kFlags * sizeof(int32_t), hipHostMallocDefault));
+        std::memset(c->hflags, 0, kFlags * sizeof(int32_t));
         // kinetic ordinate tables: [v (nv) | w (nv) | lambda (nv) | K (nv x nv)], with
         // K_ij = k(v_i, v_j) w_j the quadrature of the gain and lambda_i =
         // sum_j k(v_j, v_i) w_j that of the loss (isotropic: K_ij = w_j / 2, lambda = 1)
@@ -738,6 +750,7 @@ msrs_status msrs_save(msrs_handle h, const char* path) {
         w.val<double>(c->eps);
         w.val<double>(c->hg);
         w.val<double>(c->rank_tol);
+        w.val<double>(c->ir_stop);
         w.val<uint32_t>(c->flags);
         w.val<int32_t>(c->last_ir_iters);
         w.val<int32_t>((int32_t)c->overlap.size());
@@ -773,7 +786,8 @@ msrs_status msrs_load(msrs_handle* out, const char* path, void* stream) {
     if (fread(magic, 1, sizeof(magic), g.f) != sizeof(magic) || std::memcmp(magic, kBasisMagic, sizeof(magic)))
         return fail(nullptr, MSRS_ERR_IO, "not a basis file" + where);
     BasisReader r{g.f};
-    if (r.val<uint32_t>() != kBasisVersion || !r.ok) return fail(nullptr, MSRS_ERR_IO, "unsupported basis file version" + where);
+    const uint32_t version = r.val<uint32_t>();
+    if ((version != 1 && version != kBasisVersion) || !r.ok) return fail(nullptr, MSRS_ERR_IO, "unsupported basis file version" + where);
     msrs_problem_desc d{};
     d.kind = r.val<int32_t>();
     d.n_cells = r.val<int32_t>();
@@ -788,6 +802,7 @@ msrs_status msrs_load(msrs_handle* out, const char* path, void* stream) {
     d.eps = r.val<double>();
     d.hg_g = r.val<double>();
     d.rank_tol = r.val<double>();
+    d.ir_stop = version >= 2 ? r.val<double>() : 0.0;
     d.flags = r.val<uint32_t>();
     const int32_t ir_iters = r.val<int32_t>();
     const int32_t nov = r.val<int32_t>();
@@ -848,6 +863,19 @@ msrs_status msrs_load(msrs_handle* out, const char* path, void* stream) {
     c->ranged = true;
     c->coarse_ready = false;
     *out = h;
+    return MSRS_OK;
+}
+
+msrs_status msrs_draw_boundary_samples(uint64_t seed, int32_t patch, int32_t n_node, int32_t n_sample, uint32_t* words_dev,
+                                       double* normals_dev, void* stream) {
+    if (patch < 0 || n_node < 0 || n_sample < 0) return fail(nullptr, MSRS_ERR_ARG, "negative patch, node or sample count");
+    if ((int64_t)n_node * n_sample == 0) return MSRS_OK;
+    try {
+        launch_philox_draw(seed, patch, n_node, n_sample, words_dev, normals_dev, (hipStream_t)stream);
+        MSRS_HIP_CHECK(hipGetLastError());
+    } catch (const HipError& e) {
+        return hip_fail(nullptr, e);
+    }
     return MSRS_OK;
 }
 

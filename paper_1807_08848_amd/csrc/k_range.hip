@@ -275,8 +275,11 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
         }
         if (kk != P.ncols) pd[p].ncols = kk;
         kshared = kk;
+        // the k-th direction must lie above the Gram matrix's resolution: its
+        // eigenvalues carry absolute errors of about s u sigma_1^2 (u = 2^-53)
         const double sk = svp[kk - 1];
-        if (!(sk > 1e-13 * s1)) raise_flag(flags, 2);
+        if (!(sk > 2.0 * sqrt((double)s * 0x1p-53) * s1)) raise_flag(flags, 2);
+        if (!isfinite(s1)) raise_flag(flags, 4);
         gap[p] = (kk < s) ? (sk - svp[kk]) / s1 : 1.0;
     }
     __syncthreads();

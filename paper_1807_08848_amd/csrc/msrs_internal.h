@@ -19,6 +19,7 @@ constexpr int kThreads = 256;      // threads of every per-patch workgroup
 constexpr int kChunkLines = 8;     // block rows per workgroup of the lifting and residual kernels
 constexpr int kOutPerLaunch = 32;  // requests per reconstruction launch
 constexpr int kOnlineWs = 4;       // concurrent msrs_solve_global calls per handle
+constexpr int kFlags = 8;          // device error flags (see Ctx::dflags)
 
 // Input and output pointers of the requests of one launch, passed by value in
 // the kernel arguments (no device pointer array to stage).  Inputs may be
@@ -80,6 +81,7 @@ struct Ctx {
     int N = 0, M = 0, s = 0, k = 0, prec = 0, nv = 0;
     int ir_max = 30;
     double ir_tol = 1e-10;
+    double ir_stop = 1e-13;   // a patch stops refining at this relative residual (or at stagnation below ir_tol)
     double eps = 1.0;
     double hg = 0.0;          // kinetic: Henyey-Greenstein anisotropy g (0: isotropic)
     double rank_tol = 0.0;    // > 0: each sampled patch keeps its numerical rank at this tolerance (at most k)
@@ -109,7 +111,8 @@ struct Ctx {
     double* rn = nullptr;         // norms
     double* gap = nullptr;        // per patch relative gap
     int32_t* conv = nullptr;      // per patch converged flag
-    int32_t* dflags = nullptr;    // device error flags [0]=NOT_SPD [1]=NOCONV [2]=RANK [3]=nonfinite
+    // device error flags: [0] NOT_SPD, [1] NOCONV, [2] RANK, [3] unsupported patch shape, [4] non-finite values
+    int32_t* dflags = nullptr;
     int32_t* hflags = nullptr;    // pinned host mirror
     double* vw = nullptr;         // kinetic ordinates and weights (2 nv)
     double* rf_ws = nullptr;      // range finder workspace (shape of Q)
@@ -206,6 +209,7 @@ struct Ctx {
 void launch_gather_elliptic(Ctx& c, const double* a, int p0, int p1);
 void launch_gather_kinetic(Ctx& c, const double* sigma, int p0, int p1);
 void launch_omega(Ctx& c, const double* user, int p0, int p1);
+void launch_philox_draw(uint64_t seed, int patch, int n_node, int n_sample, uint32_t* words, double* normals, hipStream_t st);
 void launch_lift(Ctx& c, int p0, int p1);
 void launch_factor(Ctx& c, int p0, int p1);
 void join_factor(Ctx& c);

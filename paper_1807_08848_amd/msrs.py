@@ -23,9 +23,10 @@ import torch  # noqa: E402,F401
 
 _lib = C.CDLL(LIB_PATH)
 
-OK, ERR_ARG, ERR_STATE, ERR_OOM, ERR_HIP, ERR_NO_DEVICE, ERR_NOT_SPD, ERR_NOCONV, ERR_RANK, ERR_BUSY, ERR_IO = range(11)
+(OK, ERR_ARG, ERR_STATE, ERR_OOM, ERR_HIP, ERR_NO_DEVICE, ERR_NOT_SPD, ERR_NOCONV, ERR_RANK, ERR_BUSY, ERR_IO,
+ ERR_NONFINITE) = range(12)
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_STATE", 3: "ERR_OOM", 4: "ERR_HIP", 5: "ERR_NO_DEVICE",
-                6: "ERR_NOT_SPD", 7: "ERR_NOCONV", 8: "ERR_RANK", 9: "ERR_BUSY", 10: "ERR_IO"}
+                6: "ERR_NOT_SPD", 7: "ERR_NOCONV", 8: "ERR_RANK", 9: "ERR_BUSY", 10: "ERR_IO", 11: "ERR_NONFINITE"}
 KIND_ELLIPTIC_Q1, KIND_KINETIC_DO = 0, 1
 PREC_FP64, PREC_FP32_IR = 0, 1
 FLAG_FULL_BASIS_ENDS, FLAG_PER_PATCH_LAUNCH, FLAG_TIMING, FLAG_FULL_BASIS_BOUNDARY = 1, 2, 4, 8
@@ -44,7 +45,7 @@ class ProblemDesc(C.Structure):
                 ("rank", C.c_int32), ("precision", C.c_int32), ("ir_max_iters", C.c_int32), ("n_vel", C.c_int32),
                 ("seed", C.c_uint64), ("ir_tol", C.c_double), ("eps", C.c_double),
                 ("overlap", C.POINTER(C.c_int32)), ("flags", C.c_uint32), ("reserved", C.c_int32),
-                ("hg_g", C.c_double), ("rank_tol", C.c_double)]
+                ("hg_g", C.c_double), ("rank_tol", C.c_double), ("ir_stop", C.c_double)]
 
 
 class Layout(C.Structure):
@@ -110,6 +111,7 @@ _sig = {
     "msrs_server_destroy": (None, [_H]),
     "msrs_set_max_batch": (C.c_int32, [_H, C.c_int32]),
     "msrs_copy_omega": (C.c_int32, [_H, _P]),
+    "msrs_draw_boundary_samples": (C.c_int32, [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P]),
     "msrs_save": (C.c_int32, [_H, C.c_char_p]),
     "msrs_load": (C.c_int32, [C.POINTER(_H), C.c_char_p, _P]),
     "msrs_copy_results": (C.c_int32, [_H, _P, _P, _P]),
@@ -168,11 +170,12 @@ def _stream(stream):
 
 
 def make_desc(kind, n_cells, M, overlap, n_samples, rank, precision=PREC_FP64, seed=2, ir_tol=1e-10,
-              ir_max_iters=30, n_vel=0, eps=1.0, flags=0, hg=0.0, rank_tol=0.0):
+              ir_max_iters=30, n_vel=0, eps=1.0, flags=0, hg=0.0, rank_tol=0.0, ir_stop=0.0):
     ov = (C.c_int32 * len(overlap))(*[int(x) for x in overlap])
     d = ProblemDesc(kind=kind, n_cells=n_cells, M=M, n_samples=n_samples, rank=rank, precision=precision,
                     ir_max_iters=ir_max_iters, n_vel=n_vel, seed=seed, ir_tol=ir_tol, eps=eps,
-                    overlap=C.cast(ov, C.POINTER(C.c_int32)), flags=flags, reserved=0, hg_g=hg, rank_tol=rank_tol)
+                    overlap=C.cast(ov, C.POINTER(C.c_int32)), flags=flags, reserved=0, hg_g=hg, rank_tol=rank_tol,
+                    ir_stop=ir_stop)
     d._keep = ov
     return d
 
@@ -295,6 +298,24 @@ class Problem:
 
     def __exit__(self, *a):
         self.close()
+
+
+def draw_boundary_samples(seed: int, patch: int, n_node: int, n_sample: int, words=None, normals=None, stream=None):
+    """The device generator of the boundary samples (msrs_draw_boundary_samples):
+    words (int32 CUDA tensor of 4 n_node n_sample, the Philox output words as
+    stored bits) and normals (float64 CUDA tensor of n_node n_sample), each
+    optional, in Omega's column-major order."""
+    def p(t, dtype):
+        if t is None:
+            return None
+        if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+            raise ValueError(f"expected a contiguous {dtype} CUDA tensor")
+        return C.c_void_p(t.data_ptr())
+    import torch
+    st = _lib.msrs_draw_boundary_samples(C.c_uint64(seed), int(patch), int(n_node), int(n_sample),
+                                         p(words, torch.int32), p(normals, torch.float64), _stream(stream))
+    if st != OK:
+        raise MsrsError(st, _lib.msrs_last_error(None).decode())
 
 
 def server_clock() -> float:

@@ -46,6 +46,19 @@ def test_create_validates_arguments(args, msg):
     assert e.value.status == msrs.ERR_ARG and msg in str(e.value)
 
 
+def test_rank_tol_below_the_range_finders_resolution_is_refused():
+    """The Gram-matrix range finder resolves sigma_j / sigma_1 down to about
+    sqrt(s u): a tolerance below 2 sqrt(s u) would choose directions it cannot
+    resolve."""
+    from paper_1807_08848_amd import msrs
+    with pytest.raises(msrs.MsrsError) as e:
+        msrs.Problem(msrs.make_desc(0, 128, 4, [8] * 16, 32, 6, rank_tol=1e-9))
+    assert e.value.status == msrs.ERR_ARG and "resolution" in str(e.value)
+    with pytest.raises(msrs.MsrsError) as e:
+        msrs.Problem(msrs.make_desc(0, 128, 4, [8] * 16, 32, 6, ir_stop=-1.0))
+    assert e.value.status == msrs.ERR_ARG and "ir_stop" in str(e.value)
+
+
 def test_full_basis_boundary_needs_small_patches():
     from paper_1807_08848_amd import msrs
     with pytest.raises(msrs.MsrsError) as e:

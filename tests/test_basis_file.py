@@ -30,7 +30,7 @@ def _header(version=1, kind=0, n_cells=128, M=4, s=10, k=6, prec=1, ir_max=30, n
     (None, "cannot open"),
     (b"NOTABASI" + bytes(64), "not a basis file"),
     (MAGIC[:5], "not a basis file"),
-    (lambda: _header(version=2), "unsupported basis file version"),
+    (lambda: _header(version=3), "unsupported basis file version"),
     (lambda: _header()[:30], "truncated or corrupt header"),
     (lambda: _header(overlap=[8] * 9), "sizes do not match"),
     (lambda: _header(counts=(64 * 64, 0, 0, 0)), "sizes do not match"),

@@ -178,10 +178,14 @@ def test_global_solve_reproduces_linear_function():
 def test_partition_of_unity():
     for N, M in [(16, 2), (32, 4), (64, 8)]:
         w = E.pou_weights(N, M)
-        # the weights of all patches containing a node sum to one
-        cnt = 1.0 / w
-        assert np.allclose(w * cnt, 1.0)
+        # the weights of all patches containing a node sum to one: add each
+        # patch's weights over its own closed node block
         nH = N // M
+        total = np.zeros((N + 1, N + 1))
+        for g in E.patch_geometry(N, M, 0):
+            total[g["ky0"]:g["ky0"] + nH + 1, g["kx0"]:g["kx0"] + nH + 1] += w[g["ky0"]:g["ky0"] + nH + 1,
+                                                                             g["kx0"]:g["kx0"] + nH + 1]
+        assert np.abs(total - 1.0).max() < 1e-15
         assert w[nH, nH] == 0.25 and w[0, nH] == 0.5 and w[1, 1] == 1.0
 
 

@@ -88,3 +88,21 @@ def test_snapshots_have_rank_of_inflow_dimension():
     Y = K.sample_patch(sig, 2.0 ** -6, 512, 32, g, K.patch_omega(2, g, 32, 48))
     s = np.linalg.svd(Y, compute_uv=False)
     assert s[1] / s[0] > 1e-3 and s[32] / s[0] < 1e-13
+
+
+@pytest.mark.parametrize("Nx,M,delta,seed", [(512, 8, 32, 2), (256, 4, 20, 5)])
+def test_sampled_buffered_patches_at_full_inflow_rank_glue_exactly(Nx, M, delta, seed):
+    """Buffered patches sampled with as many random inflow columns as the
+    inflow space has dimensions (s = k = 32): each basis spans every solution
+    of its patch, so the least-squares gluing must return the fine solve.  This
+    pins the restriction of a buffered patch (the cells of K_m and one ghost
+    each side, offset by the buffer): a one-cell shift breaks the interface
+    rows."""
+    sig = synth.kinetic_sigma(Nx, 0.05)
+    v, _ = K.ordinates(32)
+    phi = np.concatenate([3 + np.sin(2 * np.pi * v[v > 0]), 2 + np.sin(2 * np.pi * v[v < 0])])
+    pts = K.offline(sig, 2.0 ** -6, Nx, M, delta, 32, 32, 32, seed=seed)
+    assert any(not p["full"] and p["geo"]["x0"] < p["geo"]["k0"] for p in pts)
+    f = K.online(M, 32, pts, phi)
+    ref = K.global_solve(sig, 2.0 ** -6, 32, phi)
+    assert np.linalg.norm(f - ref) / np.linalg.norm(ref) < 1e-11

@@ -23,8 +23,31 @@ def test_sign_fix_makes_largest_entry_positive():
     assert np.all(Q[idx, np.arange(4)] > 0)
 
 
+def test_sin_max_angle_of_subspaces_at_known_angles():
+    """Two k-dimensional subspaces whose principal angles are set by
+    construction: span{u_i} and span{cos t_i u_i + sin t_i u_{k+i}} with
+    orthonormal u_1..u_2k.  The largest principal angle is max t_i, whatever
+    orthonormal bases represent the two spans, in either argument order."""
+    rng = np.random.default_rng(5)
+    n, k = 80, 5
+    U, _ = np.linalg.qr(rng.standard_normal((n, 2 * k)))
+    for t in ([0.3, 0.1, 0.2, 0.05, 0.0], [1e-7, 2e-7, 0.0, 0.0, 5e-8], [1.2, 0.4, 0.0, 0.9, 0.1]):
+        t = np.asarray(t)
+        Qa = U[:, :k]
+        Qb = U[:, :k] * np.cos(t) + U[:, k:] * np.sin(t)
+        Ra, _ = np.linalg.qr(rng.standard_normal((k, k)))
+        Rb, _ = np.linalg.qr(rng.standard_normal((k, k)))
+        for a, b in ((Qa @ Ra, Qb @ Rb), (Qb @ Rb, Qa @ Ra)):
+            assert abs(sin_max_angle(a, b) - np.sin(t.max())) <= 1e-14 + 1e-12 * np.sin(t.max())
+    # a subspace against one of its own supersets' k-dimensional parts
+    assert sin_max_angle(U[:, :k], U[:, :k] @ Ra) < 1e-14
+    assert abs(sin_max_angle(U[:, :k], U[:, k:2 * k]) - 1.0) < 1e-14
+
+
 def test_hmt_average_spectral_error_bound():
-    """Theorem average_spectral (a): mean over draws of ||A - P_Y A|| below the stated bound."""
+    """Theorem average_spectral (a): mean over draws of ||A - P_Y A|| below the
+    stated bound, with the oracle's range finder forming the basis of the
+    sketch (k + p columns kept)."""
     rng = np.random.default_rng(2)
     m, n, k, p = 200, 120, 6, 4
     sig = np.concatenate([np.ones(k), 0.05 * 0.8 ** np.arange(n - k)])
@@ -34,8 +57,8 @@ def test_hmt_average_spectral_error_bound():
     errs = []
     for t in range(100):
         Om = rng.standard_normal((n, k + p))
-        Q, _ = np.linalg.qr(A @ Om)
-        errs.append(np.linalg.norm(A - Q @ (Q.T @ A), 2))
+        Q, _ = range_finder(A @ Om, k + p)
+        errs.append(projection_error(A, Q) * np.linalg.norm(A, 2))
     bound = (1 + k / (p - 1)) * sig[k] + np.e * np.sqrt(k + p) / p * np.sqrt(np.sum(sig[k:] ** 2))
     assert np.mean(errs) <= bound
     assert min(errs) >= sig[k + p] * (1 - 1e-9)  # never better than the optimal rank-(k+p) error

@@ -64,15 +64,16 @@ def test_high_contrast_random_sampling_captures_leading_modes():
 
 
 # (workload, precision, snapshot bar).  The FP32 path refines each local
-# solve to a relative residual of 1e-10, which bounds its forward error by
-# kappa * 1e-10 only: ~1e-6 for the two-scale medium (contrast ~20, kappa
-# ~1e4), ~1e-4 at contrast 1000 (kappa ~7e5), where the element-wise
-# comparison is made tight in FP64 instead (both sides direct: kappa * 1e-16).
+# solve to stagnation of its FP64 residual (relative residual ~1e-13 or no
+# further halving), which bounds its forward error by about kappa * 1e-13: ~1e-9
+# for the two-scale medium (contrast ~20, kappa ~1e4), ~7e-8 at contrast 1000
+# (kappa ~7e5).  Bases and global solutions are held to the 1e-6 bars in every
+# case.
 CASES = {
     "two_scale_k10": (lambda: configs.elliptic_two_scale_100(10), FP32_IR, 1e-8),
     "two_scale_k20": (lambda: configs.elliptic_two_scale_100(20), FP32_IR, 1e-8),
     "high_contrast_k6_fp64": (lambda: configs.elliptic_high_contrast_100(6), FP64, 1e-9),
-    "high_contrast_k6_fp32ir": (lambda: configs.elliptic_high_contrast_100(6), FP32_IR, 1e-4),
+    "high_contrast_k6_fp32ir": (lambda: configs.elliptic_high_contrast_100(6), FP32_IR, 1e-7),
 }
 
 
@@ -83,6 +84,8 @@ def test_paper_media_parity(lib, which):
     make, prec, tol_y = CASES[which]
     cfg = make()
     out = run(cfg, prec, phi=cfg["phi"])
+    if prec == FP32_IR:
+        assert out["stats"].max_rel_residual <= 1e-10
     ref = _offline(cfg)
     for p, r in enumerate(ref):
         assert rel(out["Y"][p], r["Y"]) < tol_y, p
@@ -91,9 +94,9 @@ def test_paper_media_parity(lib, which):
         assert np.abs(out["sv"][p] - r["sv"]).max() <= tol_sv, p
         Qg = out["Q"][p]
         assert np.abs(Qg.T @ Qg - np.eye(Qg.shape[1])).max() < 1e-12, p
-        assert sin_max_angle(r["Q"], Qg) <= max(1e-6, 100 * tol_y), p     # s = k: the bases span all of Y
+        assert sin_max_angle(r["Q"], Qg) <= 1e-6, p     # s = k: the bases span all of Y
     u_or = E.online(cfg["N"], cfg["M"], ref, cfg["coef"], cfg["phi"])
-    assert E.relative_l2(out["u"][0], u_or) <= max(1e-6, 100 * tol_y)
+    assert E.relative_l2(out["u"][0], u_or) <= 1e-6
 
 
 @pytest.mark.gpu
