@@ -299,6 +299,24 @@ msrs_status msrs_solve_global_banded(msrs_handle h, int32_t n_req, const double*
                                      void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of msrs_solve_global with the same arguments, layouts and results (the
+ * same kernels), but its per-launch workspace (the boundary right-hand sides
+ * and least-squares coefficients of up to 32 requests) lives in a fixed
+ * 2 MiB device array of the library, one per GPU, held until the process
+ * ends, instead of the handle's online workspaces.  The call allocates no
+ * device memory; the array's address on each device is looked up on that
+ * device's first call.  Every call on a GPU shares its array, so calls that
+ * overlap on one GPU (other streams, other handles, other threads) race:
+ * order them on one stream or synchronise between them.  Errors: ARG
+ * (n_req outside [1, max_batch], NULL pointers, or
+ * (boundary unknowns + coarse unknowns) x min(n_req, 32) doubles above the
+ * array), STATE (no msrs_assemble_coarse yet), HIP.
+ */
+msrs_status msrs_solve_global_noalloc(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev, void* stream);
+
+/*
  * Capture one offline step -- msrs_assemble_patch(coef_dev),
  * msrs_sample_local_solutions with device-drawn samples, msrs_range_finder
  * -- as a HIP graph of the handle's stream (which must not be the default

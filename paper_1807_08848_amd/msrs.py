@@ -99,6 +99,8 @@ _sig = {
     "msrs_assemble_coarse": (C.c_int32, [_H]),
     "msrs_solve_global": (C.c_int32, [_H, C.c_int32, _P, _P, _P]),
     "msrs_solve_global_banded": (C.c_int32, [_H, C.c_int32, _P, _P, _P]),
+    "msrs_coarse_condition": (C.c_int32, [_H, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "msrs_solve_global_noalloc": (C.c_int32, [_H, C.c_int32, _P, _P, _P]),
     "msrs_server_clock": (C.c_double, []),
     "msrs_server_last_error": (C.c_char_p, []),
     "msrs_server_create": (C.c_int32, [C.POINTER(_H), C.POINTER(_H), C.c_int32, C.POINTER(ServerConfig)]),
@@ -242,6 +244,12 @@ class Problem:
         n_req = f.shape[0] if f.dim() == 2 else 1
         s = None if stream is None else _stream(stream)
         self._check(_lib.msrs_solve_global(self.h, int(n_req), _ptr(f), _ptr(u), s))
+
+    def solve_global_noalloc(self, f, u, stream=None):
+        """msrs_solve_global with the workspace in the library's fixed device array (no allocation)."""
+        n_req = f.shape[0] if f.dim() == 2 else 1
+        s = None if stream is None else _stream(stream)
+        self._check(_lib.msrs_solve_global_noalloc(self.h, int(n_req), _ptr(f), _ptr(u), s))
 
     def solve_global_banded(self, f, u, stream=None):
         n_req = f.shape[0] if f.dim() == 2 else 1
