@@ -57,16 +57,17 @@ def algorithmic(cfg):
             K_RANGE: sum(6 * nk * s * s for b, nl, n, nk, s in ps)}
 
 
-def measured_traffic(kernel_class):
-    """HBM bytes per launch of a kernel class from the committed counter summary
-    (profiles/traffic_*.json), or None when the kernel source has changed since
-    the counters were taken (the record carries the source's SHA-1)."""
+def measured_traffic(kernel_class, workload):
+    """HBM bytes per launch of a kernel class on a workload from the committed
+    counter summary (profiles/traffic_*.json), or None when there is none or the
+    kernel source has changed since the counters were taken (the record carries
+    the source's SHA-1)."""
     import glob
     import hashlib
     for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
         with open(path) as f:
             rec = json.load(f)
-        if rec.get("kernel_class") != kernel_class:
+        if rec.get("kernel_class") != kernel_class or rec.get("workload") != workload:
             continue
         with open(os.path.join(ROOT, rec["source"]), "rb") as f:
             if hashlib.sha1(f.read()).hexdigest() != rec["source_sha1"]:
@@ -569,7 +570,7 @@ def main():
                    "precision": "fp32 factor+sweeps, fp64 refinement/range finder"},
         "roofline": {"bound": kind[0], "kernel": kind[2], "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic({K_FACTOR: "factor", K_SWEEP: "sweep", K_RANGE: "range"}[dom]),
+                     "traffic": measured_traffic({K_FACTOR: "factor", K_SWEEP: "sweep", K_RANGE: "range"}[dom], cfg["name"]),
                      "avg_launch_ms": avg_ms, "launches": n[dom]},
         "kernel_ms_per_step": {msrs.K_CLASSES[k]: ms[k] / args.steps for k in range(11) if n[k]},
         "ir_iters": st.ir_iters, "max_rel_residual": st.max_rel_residual, "autotune": r["tuned"],

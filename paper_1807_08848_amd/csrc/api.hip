@@ -313,7 +313,6 @@ namespace {
 void sample_enqueue(Ctx* c, const double* omega_dev, int fixed_iters) {
     for_patches(*c, [&](int p0, int p1) { launch_omega(*c, omega_dev, p0, p1); });
     for_patches(*c, [&](int p0, int p1) { launch_lift(*c, p0, p1); });
-    join_factor(*c);   // the sweeps need the factor
     if (c->prec == MSRS_PREC_FP64) {
         for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, false, false); });
         for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, true, 0); });
@@ -511,21 +510,23 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
             MSRS_HIP_CHECK(hipMemcpy(c->pid, ids.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice));
             std::vector<std::vector<int32_t>> grp(9);
             for (int p = 0; p < c->n_patches; ++p) grp[std::min(8, c->hp[p].bp / 16)].push_back(p);
-            int ngroups = 0;
             for (int g = 0; g < 9; ++g) {
                 c->rgroup_n[g] = (int)grp[g].size();
                 if (grp[g].empty()) continue;
                 c->rgroup[g] = dalloc<int32_t>(*c, (int64_t)grp[g].size());
                 MSRS_HIP_CHECK(hipMemcpy(c->rgroup[g], grp[g].data(), grp[g].size() * sizeof(int32_t), hipMemcpyHostToDevice));
-                ++ngroups;
             }
-            if (ngroups > 1) {
-                MSRS_HIP_CHECK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-                for (int k = 0; k < ngroups; ++k) {
-                    MSRS_HIP_CHECK(hipStreamCreateWithFlags(&c->aux[k], hipStreamNonBlocking));
-                    MSRS_HIP_CHECK(hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming));
-                }
-            }
+            // longest-processing-time order of the patches: cost of the banded
+            // factor plus the s solve pairs, N (b+1)^2 + 4 N (b+1) s (ties by index)
+            std::vector<int32_t> order(ids);
+            auto cost = [&](int p) {
+                const PatchDesc& P = c->hp[p];
+                const double n = (double)P.b * P.nl, w = P.b + 1.0;
+                return n * w * w + 4.0 * n * w * P.s;
+            };
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+            c->lpt = dalloc<int32_t>(*c, c->n_patches);
+            MSRS_HIP_CHECK(hipMemcpy(c->lpt, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         }
         c->dflags = dalloc<int32_t>(*c, kFlags);
         c->coef_copy = dalloc<double>(*c, c->kind == kElliptic ? (int64_t)c->N * c->N : c->N);
@@ -652,17 +653,10 @@ msrs_status msrs_offline_graph_capture(msrs_handle h, const double* coef_dev) {
         c->timing = false;   // no event nodes inside the graph
         MSRS_HIP_CHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         try {
-            // the factor's streams join the capture stream only before the first
-            // sweep: the boundary draws and the lift run beside the factor
-            c->defer_factor_join = true;
-            c->n_join = 0;
             assemble_enqueue(c, coef_dev);
-            c->defer_factor_join = false;
             sample_enqueue(c, nullptr, iters);
             for_patches(*c, [&](int p0, int p1) { launch_range(*c, p0, p1); });
         } catch (const HipError&) {
-            c->defer_factor_join = false;
-            c->n_join = 0;
             hipGraph_t g = nullptr;
             (void)hipStreamEndCapture(c->stream, &g);
             if (g) (void)hipGraphDestroy(g);
@@ -1299,11 +1293,6 @@ void msrs_destroy(msrs_handle h) {
         if (w.used) (void)hipEventSynchronize(w.done);
     for (auto& pe : c->pending) { (void)hipEventDestroy(pe.a); (void)hipEventDestroy(pe.b); }
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
-    for (int k = 0; k < 8; ++k) {
-        if (c->aux[k]) (void)hipStreamDestroy(c->aux[k]);
-        if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
-    }
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     for (auto& w : c->ws)
         if (w.done) (void)hipEventDestroy(w.done);
     drop_graph(c);

@@ -577,6 +577,44 @@ __global__ __launch_bounds__(kFactorThreads, SHARE == 2 ? 8 : 1) void factor2_ke
     else factor_mfma_body<T, KIND, RB, MID>(P, aL_all + P.a_off, vw, dx, inv_eps, E_all + P.E_off, lds, cf, crow, dir, flags);
 }
 
+// Any mix of line-tile counts 1..RMAX in one launch: workgroup x factors
+// patch plist[x] with the body compiled for its count; LDS and registers are
+// those of the largest body.  plist is in longest-processing-time order (the
+// costliest patches first), so the long chains start first and the short ones
+// fill in behind them; a batch of several line lengths is then one launch on
+// the handle's stream, a single chain in a captured graph.
+template <typename T, int KIND, int RMAX, bool MID, int SHARE>
+__global__ __launch_bounds__(kFactorThreads, SHARE == 2 ? 8 : 1) void factor_any_kernel(const PatchDesc* pd, const int32_t* __restrict__ plist,
+                                                                    const double* __restrict__ aL_all, const double* __restrict__ vw,
+                                                                    double dx, double inv_eps, T* __restrict__ E_all, int32_t* flags) {
+    __shared__ T lds[factor_lds_elems<RMAX>()];
+    __shared__ double cf[2 * kMaxLine];
+    __shared__ double crow[2 * (kMaxLine + 1)];
+    const PatchDesc P = pd[plist[blockIdx.x]];
+    const int dir = MID ? 0 : (blockIdx.y == 0 ? 1 : -1);
+    const double* aL = aL_all + P.a_off;
+    T* E = E_all + P.E_off;
+#define MSRS_FB(RR) factor_mfma_body<T, KIND, RR, MID>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, dir, flags)
+    const int R = P.bp >> 4;
+    if (R == 1) MSRS_FB(1);
+    else if (R == 2) MSRS_FB(2);
+    else if (R == 3) MSRS_FB(3);
+    else if (R == 4) MSRS_FB(4);
+    else {
+        bool done = false;
+        if constexpr (RMAX >= 8) {
+            done = true;
+            if (R == 5) MSRS_FB(5);
+            else if (R == 6) MSRS_FB(6);
+            else if (R == 7) MSRS_FB(7);
+            else if (R == 8) MSRS_FB(8);
+            else done = false;
+        }
+        if (!done && threadIdx.x == 0) raise_flag(flags, 3);
+    }
+#undef MSRS_FB
+}
+
 template <typename T, int KIND>
 static void launch_factor_r(Ctx& c, int R, hipStream_t st, const int32_t* plist, int n) {
     const double inv_eps = 1.0 / c.eps;
@@ -668,11 +706,34 @@ static bool launch_factor_pair(Ctx& c, int ra, int rb) {
 #undef MSRS_FACTOR2_SH
 }
 
-// Patches are grouped by line-tile count R; each group runs its own kernel.
-// A single patch (reference mode) launches on the handle's stream.  A batch
-// with one count, or (FP32) two adjacent ones, launches on the handle's
-// stream; otherwise it forks one stream per group from the handle's stream
-// and joins back.
+// One launch for the halves and one for the middle lines over every patch
+// of plist (any mix of line-tile counts).
+template <typename T, int KIND>
+static void launch_factor_any(Ctx& c, const int32_t* plist, int n) {
+    constexpr int RMAX = KIND == kElliptic ? 8 : 4;
+    const double inv_eps = 1.0 / c.eps;
+    T* E = (T*)c.E;
+#define MSRS_FANY(SH)                                                                                                        \
+    do {                                                                                                                     \
+        hipLaunchKernelGGL((factor_any_kernel<T, KIND, RMAX, false, SH>), dim3(n, 2), dim3(kFactorThreads), 0, c.stream, c.dp, \
+                           plist, c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags);                                                \
+        hipLaunchKernelGGL((factor_any_kernel<T, KIND, RMAX, true, SH>), dim3(n), dim3(kFactorThreads), 0, c.stream, c.dp,     \
+                           plist, c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags);                                                \
+    } while (0)
+    if constexpr (sizeof(T) == 4) {
+        if (c.factor_share == 2) MSRS_FANY(2);
+        else MSRS_FANY(1);
+    } else {
+        MSRS_FANY(1);
+    }
+#undef MSRS_FANY
+}
+
+// Patches are grouped by line-tile count R.  A single patch (reference mode)
+// or a batch of one count runs the kernel compiled for exactly that count; a
+// FP32 batch of two adjacent counts the two-count kernel; any other mix one
+// launch of the any-count kernel over the patches in longest-processing-time
+// order.  Everything goes to the handle's stream.
 void launch_factor(Ctx& c, int p0, int p1) {
     StageTimer t(c, MSRS_K_FACTOR);
     if (p1 - p0 == 1) {
@@ -686,31 +747,21 @@ void launch_factor(Ctx& c, int p0, int p1) {
             rmax = std::max(rmax, g);
             rmin = std::min(rmin, g);
         }
-    if (ng == 2 && (c.kind == kElliptic ? launch_factor_pair<kElliptic>(c, rmax, rmin) : launch_factor_pair<kKinetic>(c, rmax, rmin)))
-        return;
     if (ng <= 1) {
         for (int g = 0; g < 9; ++g)
             if (c.rgroup_n[g]) launch_factor_group(c, g, c.stream, c.rgroup[g], c.rgroup_n[g]);
         return;
     }
-    MSRS_HIP_CHECK(hipEventRecord(c.ev_fork, c.stream));
-    int k = 0;
-    for (int g = 0; g < 9; ++g) {
-        if (!c.rgroup_n[g]) continue;
-        hipStream_t st = c.aux[k];
-        MSRS_HIP_CHECK(hipStreamWaitEvent(st, c.ev_fork, 0));
-        launch_factor_group(c, g, st, c.rgroup[g], c.rgroup_n[g]);
-        MSRS_HIP_CHECK(hipEventRecord(c.ev_join[k], st));
-        if (!c.defer_factor_join) MSRS_HIP_CHECK(hipStreamWaitEvent(c.stream, c.ev_join[k], 0));
-        ++k;
+    if (ng == 2 && (c.kind == kElliptic ? launch_factor_pair<kElliptic>(c, rmax, rmin) : launch_factor_pair<kKinetic>(c, rmax, rmin)))
+        return;
+    const bool ir = c.prec == MSRS_PREC_FP32_IR;
+    if (c.kind == kElliptic) {
+        if (ir) launch_factor_any<float, kElliptic>(c, c.lpt, c.n_patches);
+        else launch_factor_any<double, kElliptic>(c, c.lpt, c.n_patches);
+    } else {
+        if (ir) launch_factor_any<float, kKinetic>(c, c.lpt, c.n_patches);
+        else launch_factor_any<double, kKinetic>(c, c.lpt, c.n_patches);
     }
-    if (c.defer_factor_join) c.n_join = k;
 }
 
-void join_factor(Ctx& c) {
-    for (int k = 0; k < c.n_join; ++k) MSRS_HIP_CHECK(hipStreamWaitEvent(c.stream, c.ev_join[k], 0));
-    c.n_join = 0;
-}
-
-// samples per sweep workgroup: the largest of {64, 32, 16} (FP64 at most 32,
 }  // namespace msrs

@@ -12,8 +12,8 @@
 //
 // Tall work (Gram matrices, products with the small s x k / k x k factors,
 // the column argmax) runs over (patch, chunk of kRowChunk rows) workgroups with
-// per-chunk partials reduced per patch in a fixed order; the small dense
-// work (Jacobi, Cholesky) runs one workgroup per patch.
+// per-chunk partials reduced per patch in a fixed order, on FP64 MFMA; the
+// small dense work (Jacobi, Cholesky) runs one workgroup per patch.
 #include "device_common.h"
 
 namespace msrs {
@@ -36,41 +36,61 @@ __device__ __forceinline__ Tall tall_of(const PatchDesc& P, int which, const dou
 }
 
 // ---------------------------------------------------------------- Gram partials
-template <int TS>
-__device__ void gram_rows(const double* __restrict__ A, int nrows, int r0, int r1, int ncols, double* stage, double* out) {
-    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-    double acc[TS][TS];
+// FP64 MFMA (16x16x4): the chunk's rows pass through LDS in blocks of
+// kRfStage rows (coalesced along the column-major tall matrix), and the
+// upper-triangle 16x16 tiles of A^T A (ti <= tj) go round-robin over the
+// waves; each tile's k-steps read A^T[ti][4 rows] and A[4 rows][tj] from the
+// staged block, lanes along the columns.  A tile's transpose is written with
+// it, so out holds the full symmetric matrix.
+constexpr int kStageLd = kRfMax + 1;   // odd leading dimension of the staged block
+
+template <int NT>
+__device__ void gram_rows_mfma(const double* __restrict__ A, int nrows, int r0, int r1, int ncols, double* stage, double* out) {
+    typedef Mfma<double>::acc Acc;
+    constexpr int NTILE = NT * (NT + 1) / 2;
+    constexpr int NWAVE = kThreads / 64;
+    constexpr int PER = (NTILE + NWAVE - 1) / NWAVE;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+    int tiA[PER], tiB[PER];
 #pragma unroll
-    for (int r = 0; r < TS; ++r)
+    for (int q = 0; q < PER; ++q) {
+        int t = q * NWAVE + w, a = 0;
+        if (t >= NTILE) { tiA[q] = -1; tiB[q] = -1; continue; }
+        while (t >= NT - a) { t -= NT - a; ++a; }
+        tiA[q] = a;
+        tiB[q] = a + t;
+    }
+    Acc acc[PER];
 #pragma unroll
-        for (int c = 0; c < TS; ++c) acc[r][c] = 0.0;
+    for (int q = 0; q < PER; ++q) acc[q] = Mfma<double>::zero();
     for (int q0 = r0; q0 < r1; q0 += kRfStage) {
         const int nr = min(kRfStage, r1 - q0);
         __syncthreads();
-        for (int o = tid; o < kRfStage * ncols; o += kThreads) {
+        for (int o = tid; o < kRfStage * 16 * NT; o += kThreads) {
             const int col = o / kRfStage, row = o - col * kRfStage;
-            stage[row * kRfMax + col] = row < nr ? A[(int64_t)col * nrows + q0 + row] : 0.0;
+            stage[row * kStageLd + col] = (row < nr && col < ncols) ? A[(int64_t)col * nrows + q0 + row] : 0.0;
         }
         __syncthreads();
-        for (int row = 0; row < nr; ++row) {
-            double a[TS], b[TS];
+#pragma unroll 4
+        for (int kk = 0; kk < kRfStage / 4; ++kk) {
+            const double* srow = stage + (4 * kk + lk) * kStageLd + li;
 #pragma unroll
-            for (int r = 0; r < TS; ++r) a[r] = stage[row * kRfMax + ty + 16 * r];
-#pragma unroll
-            for (int c = 0; c < TS; ++c) b[c] = stage[row * kRfMax + tx + 16 * c];
-#pragma unroll
-            for (int r = 0; r < TS; ++r)
-#pragma unroll
-                for (int c = 0; c < TS; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+            for (int q = 0; q < PER; ++q)
+                if (tiA[q] >= 0) acc[q] = Mfma<double>::step(srow[16 * tiA[q]], srow[16 * tiB[q]], acc[q]);
         }
     }
 #pragma unroll
-    for (int r = 0; r < TS; ++r)
+    for (int q = 0; q < PER; ++q) {
+        if (tiA[q] < 0) continue;
 #pragma unroll
-        for (int c = 0; c < TS; ++c) {
-            const int i = ty + 16 * r, j = tx + 16 * c;
-            if (i < ncols && j < ncols) out[i * kRfMax + j] = acc[r][c];
+        for (int t = 0; t < 4; ++t) {
+            const int i = 16 * tiA[q] + Mfma<double>::row(lane, t), j = 16 * tiB[q] + li;
+            if (i < ncols && j < ncols) {
+                out[i * kRfMax + j] = acc[q][t];
+                if (tiA[q] != tiB[q]) out[j * kRfMax + i] = acc[q][t];   // a diagonal tile holds both halves
+            }
         }
+    }
 }
 
 // grid (patch, row chunk): partial Gram of the chunk's rows -> part[(p * maxrc + chunk) * 4096]
@@ -78,7 +98,7 @@ __device__ void gram_rows(const double* __restrict__ A, int nrows, int r0, int r
 __global__ __launch_bounds__(kThreads) void gram_partial_kernel(const PatchDesc* pd, int p0, int which, const double* __restrict__ Y,
                                                                 const double* __restrict__ Q, const double* __restrict__ W,
                                                                 double* __restrict__ part, int maxrc, const int32_t* __restrict__ skip) {
-    __shared__ double stage[kRfStage * kRfMax];
+    __shared__ double stage[kRfStage * kStageLd];
     const int p = p0 + blockIdx.x;
     if (skip && skip[p]) return;
     const PatchDesc P = pd[p];
@@ -87,10 +107,10 @@ __global__ __launch_bounds__(kThreads) void gram_partial_kernel(const PatchDesc*
     const int r1 = min(P.nrows, r0 + kRowChunk);
     const Tall T = tall_of(P, which, Y, Q, W);
     double* out = part + ((int64_t)p * maxrc + blockIdx.y) * kSmall;
-    if (T.ncols <= 16) gram_rows<1>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
-    else if (T.ncols <= 32) gram_rows<2>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
-    else if (T.ncols <= 48) gram_rows<3>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
-    else gram_rows<4>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
+    if (T.ncols <= 16) gram_rows_mfma<1>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
+    else if (T.ncols <= 32) gram_rows_mfma<2>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
+    else if (T.ncols <= 48) gram_rows_mfma<3>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
+    else gram_rows_mfma<4>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
 }
 
 // sum of the chunk partials of patch p into G (LDS, leading dimension ld), fixed order
@@ -119,12 +139,13 @@ __device__ __forceinline__ void rr_pair(int i, int st, int nm1, int& a, int& b) 
 // One workgroup per patch: G = sum of partials, cyclic Jacobi (round-robin
 // pairs, two-sided updates on 2x2 blocks), eigenvalues sorted descending,
 // singular values, relative gap, and B = V[:, :k] / sigma -> small[p] (s x k).
-// In a round, thread (i, i2) (pairs i, i2 < n/2, i2 padded to a power of two
-// P2 <= 32, so that the threads of one i lie in one wave) owns the 2x2 block
-// (pair i, pair i2) of G and rows i2 and i2 + n/2 of V in the two columns of
-// pair i.  It forms the rotation of pair i2 itself and takes that of pair i
-// from the lane of its group with i2 = i.  G is double-buffered (a round reads
-// one copy and writes the other), so one barrier per round suffices.
+// A round has two phases.  First the threads of pair ip (ip < n/2, one wave)
+// form that pair's rotation from its 2x2 diagonal block and publish it.  Then
+// thread (i, i2) (pairs i, i2 < n/2, i2 padded to a power of two P2 <= 32)
+// applies the rotations of pairs i (rows) and i2 (columns) to the 2x2 block
+// (pair i, pair i2) of G and pair i's rotation to rows i2 and i2 + n/2 of V in
+// the columns of pair i.  Every entry of G and V belongs to exactly one
+// thread's block in a round, so both are updated in place.
 constexpr int kEigMaxThreads = (kRfMax / 2) * 32;
 
 int eig_threads(int max_s) {
@@ -140,8 +161,9 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
     // G and V with an odd leading dimension: a wave's column accesses
     // (V[j][a] over rows j) fall on distinct LDS banks
     constexpr int LDG = kRfMax + 1;
-    __shared__ double Gb[2][kRfMax * LDG];
+    __shared__ double G[kRfMax * LDG];
     __shared__ double V[kRfMax * LDG];
+    __shared__ double rc[kRfMax / 2], rs[kRfMax / 2], rt[kRfMax / 2];   // rotation of each pair this round
     __shared__ int perm[kRfMax];
     __shared__ double lam[kRfMax];
     __shared__ int rot;
@@ -152,18 +174,16 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
     __shared__ int kshared;
     const int nch = (P.nrows + kRowChunk - 1) / kRowChunk;
     for (int o = tid; o < kRfMax * LDG; o += nth) {
-        Gb[0][o] = 0.0;
-        Gb[1][o] = 0.0;
+        G[o] = 0.0;
         V[o] = (o / LDG == o % LDG) ? 1.0 : 0.0;
     }
     __syncthreads();
-    sum_partials(part, p, maxrc, nch, s, Gb[0], LDG);
+    sum_partials(part, p, maxrc, nch, s, G, LDG);
     const int n = s + (s & 1), np2 = n / 2, nm1 = n - 1;
     int sh = 0;
     while ((1 << sh) < np2) ++sh;
     const int i = tid >> sh, i2 = tid & ((1 << sh) - 1);
     const bool act = i < np2 && i2 < np2;
-    const int src = (tid & ~((1 << sh) - 1)) + (i & ((1 << sh) - 1));   // lane (i, i2 = i)
     // Sweeps until every rotation of a sweep finds |g_pq| <= 1e-13 sqrt(g_pp g_qq)
     // (relative off-diagonal criterion; the rotation it leaves is below 1e-13
     // over the relative gap, and the convergence is quadratic by then) or
@@ -172,68 +192,66 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
     // met between widely separated eigenvalues), at most 30.  The trace is
     // invariant under the rotations.
     double gtr = 0.0;
-    for (int x = 0; x < s; ++x) gtr += Gb[0][x * LDG + x];
+    for (int x = 0; x < s; ++x) gtr += G[x * LDG + x];
     const double floor_abs = 1e-16 * gtr;
     if (tid == 0) rot = 0;
     __syncthreads();
-    int cur = 0;
     for (int sweep = 0; sweep < 30; ++sweep) {
         for (int st = 0; st < nm1; ++st) {
-            const double* Gc = Gb[cur];
-            double* Gn = Gb[cur ^ 1];
-            int a = 0, b = 0, a2 = 0, b2 = 0;
-            double c2 = 1.0, s2 = 0.0, t2 = 0.0;   // rotation of pair i2
-            bool big = false;
-            double g00 = 0.0, g01 = 0.0, g10 = 0.0, g11 = 0.0, va0 = 0.0, vb0 = 0.0, va1 = 0.0, vb1 = 0.0;
-            if (act) {
-                rr_pair(i, st, nm1, a, b);
-                rr_pair(i2, st, nm1, a2, b2);
-                const double apq = Gc[a2 * LDG + b2], app = Gc[a2 * LDG + a2], aqq = Gc[b2 * LDG + b2];
-                g00 = Gc[a * LDG + a2];
-                g01 = Gc[a * LDG + b2];
-                g10 = Gc[b * LDG + a2];
-                g11 = Gc[b * LDG + b2];
-                va0 = V[i2 * LDG + a];
-                vb0 = V[i2 * LDG + b];
-                va1 = V[(i2 + np2) * LDG + a];
-                vb1 = V[(i2 + np2) * LDG + b];
-                if (b2 < s && apq != 0.0) {
+            // phase 1: the rotation of pair tid (tid < n/2)
+            if (tid < np2) {
+                int a, b;
+                rr_pair(tid, st, nm1, a, b);
+                const double apq = G[a * LDG + b], app = G[a * LDG + a], aqq = G[b * LDG + b];
+                double c = 1.0, sn = 0.0, t = 0.0;
+                bool big = false;
+                if (b < s && apq != 0.0) {
                     // |g_pq| > 1e-13 sqrt|g_pp g_qq| compared in squares
                     big = apq * apq > 1e-26 * fabs(app * aqq) && fabs(apq) > floor_abs;
                     // the smaller root of t^2 + 2 tau t - 1 = 0, tau = d / (2 g_pq),
                     // d = g_qq - g_pp, with numerator and denominator scaled by 2|g_pq|
                     const double d = aqq - app;
-                    t2 = (d < 0 ? -2.0 * apq : 2.0 * apq) / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
-                    c2 = rsqrt(1.0 + t2 * t2);
-                    s2 = t2 * c2;
+                    t = (d < 0 ? -2.0 * apq : 2.0 * apq) / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
+                    c = rsqrt(1.0 + t * t);
+                    sn = t * c;
                 }
+                rc[tid] = c;
+                rs[tid] = sn;
+                rt[tid] = t;
+                if (big) rot = 1;
             }
-            // one store of the flag per wave
-            if (__any(big) && (tid & 63) == 0) rot = 1;
-            const double c = __shfl(c2, src, 64), sv = __shfl(s2, src, 64), t = __shfl(t2, src, 64);
+            __syncthreads();
+            // phase 2: the 2x2 block (pair i, pair i2) of G and pair i's columns of V
             if (act) {
+                int a, b, a2, b2;
+                rr_pair(i, st, nm1, a, b);
+                rr_pair(i2, st, nm1, a2, b2);
+                const double c = rc[i], sv = rs[i], t = rt[i], c2 = rc[i2], s2 = rs[i2];
+                const double g00 = G[a * LDG + a2], g01 = G[a * LDG + b2];
+                const double g10 = G[b * LDG + a2], g11 = G[b * LDG + b2];
+                const double va0 = V[i2 * LDG + a], vb0 = V[i2 * LDG + b];
+                const double va1 = V[(i2 + np2) * LDG + a], vb1 = V[(i2 + np2) * LDG + b];
                 if (i == i2) {
                     // the rotated pair's own block: diagonal by the tangent update,
                     // the annihilated entry exactly zero (no rounding residue left
                     // to stall the relative test on widely separated eigenvalues)
-                    Gn[a * LDG + a] = g00 - t * g01;
-                    Gn[b * LDG + b] = g11 + t * g01;
-                    Gn[a * LDG + b] = 0.0;
-                    Gn[b * LDG + a] = 0.0;
+                    G[a * LDG + a] = g00 - t * g01;
+                    G[b * LDG + b] = g11 + t * g01;
+                    G[a * LDG + b] = 0.0;
+                    G[b * LDG + a] = 0.0;
                 } else {
                     const double r00 = c * g00 - sv * g10, r01 = c * g01 - sv * g11;
                     const double r10 = sv * g00 + c * g10, r11 = sv * g01 + c * g11;
-                    Gn[a * LDG + a2] = c2 * r00 - s2 * r01;
-                    Gn[a * LDG + b2] = s2 * r00 + c2 * r01;
-                    Gn[b * LDG + a2] = c2 * r10 - s2 * r11;
-                    Gn[b * LDG + b2] = s2 * r10 + c2 * r11;
+                    G[a * LDG + a2] = c2 * r00 - s2 * r01;
+                    G[a * LDG + b2] = s2 * r00 + c2 * r01;
+                    G[b * LDG + a2] = c2 * r10 - s2 * r11;
+                    G[b * LDG + b2] = s2 * r10 + c2 * r11;
                 }
                 V[i2 * LDG + a] = c * va0 - sv * vb0;
                 V[i2 * LDG + b] = sv * va0 + c * vb0;
                 V[(i2 + np2) * LDG + a] = c * va1 - sv * vb1;
                 V[(i2 + np2) * LDG + b] = sv * va1 + c * vb1;
             }
-            cur ^= 1;
             __syncthreads();
         }
         // uniform decision: every thread reads the flag before it is reset
@@ -243,7 +261,6 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
         __syncthreads();
         if (!r) break;
     }
-    const double* G = Gb[cur];
     // descending order by rank: eigenvalue i goes to the number of eigenvalues
     // above it, ties by index (a NaN ranks as -inf, so the ranks stay a
     // permutation)
@@ -372,8 +389,42 @@ __global__ __launch_bounds__(kThreads) void chol_kernel(const PatchDesc* pd, int
 
 // ---------------------------------------------------------------- tall products
 // grid (patch, row chunk): dst = src * small[p] (m x k), src / dst tall
-// matrices of the patch; a thread owns one row and 8 columns.
-// (skip: patches whose flag is set keep src as it is)
+// matrices of the patch (skip: patches whose flag is set keep src as it is).
+// FP64 MFMA on the transposed product dst^T = small^T src^T, so that a tile's
+// accumulator holds 16 consecutive rows of one dst column per lane group
+// (coalesced column-major stores) and the src operand is 16 consecutive rows
+// of one src column (coalesced loads); small sits in LDS.  Each wave walks
+// the chunk's 16-row tiles with every column tile of dst.
+template <int NTJ>
+__device__ void tall_rows_mfma(const double* __restrict__ S, int nrows, int m, int k, int r0, int r1, const double* B,
+                               double* __restrict__ D) {
+    typedef Mfma<double>::acc Acc;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int nks = (m + 3) / 4;
+    for (int rt = r0 + 16 * w; rt < r1; rt += 16 * (kThreads / 64)) {
+        const int row = rt + li;
+        const bool rin = row < r1;
+        Acc acc[NTJ];
+#pragma unroll
+        for (int c = 0; c < NTJ; ++c) acc[c] = Mfma<double>::zero();
+#pragma unroll 4
+        for (int kk = 0; kk < nks; ++kk) {
+            const int mi = 4 * kk + lk;
+            const double sv = (rin && mi < m) ? S[(int64_t)mi * nrows + row] : 0.0;
+            const double* brow = B + (4 * kk + lk) * kRfMax + li;
+#pragma unroll
+            for (int c = 0; c < NTJ; ++c) acc[c] = Mfma<double>::step(brow[16 * c], sv, acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < NTJ; ++c)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int j = 16 * c + Mfma<double>::row(lane, t);
+                if (j < k && rin) D[(int64_t)j * nrows + row] = acc[c][t];
+            }
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void tall_gemm_kernel(const PatchDesc* pd, int p0, int src_which, int dst_which,
                                                              const double* __restrict__ Y, double* __restrict__ Q,
                                                              double* __restrict__ W, const double* __restrict__ small,
@@ -388,26 +439,16 @@ __global__ __launch_bounds__(kThreads) void tall_gemm_kernel(const PatchDesc* pd
     const Tall S = tall_of(P, src_which, Y, Q, W);
     double* D = (dst_which == kQ ? Q : W) + P.Q_off;
     const int m = S.ncols, k = P.ncols, nrows = P.nrows;
-    for (int o = threadIdx.x; o < kSmall; o += kThreads) B[o] = small[(int64_t)p * kSmall + o];
-    __syncthreads();
-    constexpr int CB = 8;
-    const int nblk = (k + CB - 1) / CB, nr = r1 - r0;
-    for (int o = threadIdx.x; o < nr * nblk; o += kThreads) {
-        const int jb = o / nr, r = r0 + (o - jb * nr);
-        const int j0 = jb * CB;
-        double acc[CB];
-#pragma unroll
-        for (int c = 0; c < CB; ++c) acc[c] = 0.0;
-#pragma unroll 8
-        for (int i = 0; i < m; ++i) {
-            const double a = S.base[(int64_t)i * nrows + r];
-#pragma unroll
-            for (int c = 0; c < CB; ++c) acc[c] = fma(a, B[i * kRfMax + min(j0 + c, kRfMax - 1)], acc[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < CB; ++c)
-            if (j0 + c < k) D[(int64_t)(j0 + c) * nrows + r] = acc[c];
+    // rows of small past m and columns past k are zero in the operand
+    for (int o = threadIdx.x; o < kSmall; o += kThreads) {
+        const int i = o / kRfMax, j = o % kRfMax;
+        B[o] = (i < m && j < k) ? small[(int64_t)p * kSmall + o] : 0.0;
     }
+    __syncthreads();
+    if (k <= 16) tall_rows_mfma<1>(S.base, nrows, m, k, r0, r1, B, D);
+    else if (k <= 32) tall_rows_mfma<2>(S.base, nrows, m, k, r0, r1, B, D);
+    else if (k <= 48) tall_rows_mfma<3>(S.base, nrows, m, k, r0, r1, B, D);
+    else tall_rows_mfma<4>(S.base, nrows, m, k, r0, r1, B, D);
 }
 
 // ---------------------------------------------------------------- sign fix

@@ -128,15 +128,8 @@ struct Ctx {
     int32_t* pid = nullptr;       // 0..n_patches-1 (single-patch launches)
     int32_t* rgroup[9] = {};      // patches with line-tile count R (device lists)
     int rgroup_n[9] = {};
-    hipStream_t aux[8] = {};      // fork streams of the per-R factor kernels
-    hipEvent_t ev_fork = nullptr, ev_join[8] = {};
-    // while set, launch_factor leaves its forked streams unjoined (n_join of
-    // them) and join_factor joins them later, so that work independent of the
-    // factor (the boundary draws and the lift) runs beside it; used inside a
-    // graph capture only, where the capture spans both
-    bool defer_factor_join = false;
+    int32_t* lpt = nullptr;       // every patch, costliest first (factor launches over mixed line lengths)
     bool ranks_stale = false;     // the device descriptors hold ranks the host copy has not seen
-    int n_join = 0;
     int maxch = 1;                // line chunks per patch at most
 
     int64_t omega_total = 0, Y_total = 0, Q_total = 0, sv_total = 0;
@@ -212,7 +205,6 @@ void launch_omega(Ctx& c, const double* user, int p0, int p1);
 void launch_philox_draw(uint64_t seed, int patch, int n_node, int n_sample, uint32_t* words, double* normals, hipStream_t st);
 void launch_lift(Ctx& c, int p0, int p1);
 void launch_factor(Ctx& c, int p0, int p1);
-void join_factor(Ctx& c);
 void launch_sweep(Ctx& c, int p0, int p1, bool fp32, bool first);   // first: the first solve of a refinement
 void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it);
 void launch_restrict(Ctx& c, int p0, int p1);
