@@ -327,6 +327,7 @@ def build_model(cfg, precision=1):
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
     pr.tuned = tuning.tune(pr, msrs.TUNE_STAGE_ONLINE)
+    pr.cond = pr.coarse_condition()
     return pr, ts
 
 
@@ -504,7 +505,9 @@ def run_serving(lams=(200, 500, 1000, 2000), seconds=2.0, seed_arrival=5):
         "workload": "serving over elliptic_lognormal_512 + elliptic_lognormal_1024 (50/50, Poisson arrivals)",
         "n_nodes": nn, "coarse_dim": [int(m.layout().coarse_dim) for m in models], "setup_s": setup,
         "autotune": [m.tuned for m in models],
-        "rel_err_batched_vs_banded": acc, "rel_err_vs_oracle": accuracy, "open_loop": res,
+        "rel_err_batched_vs_banded": acc, "rel_err_vs_oracle": accuracy,
+        "coarse_condition": [{"kappa1_normal_equations": m.cond[0], "kappa_least_squares": m.cond[1]} for m in models],
+        "open_loop": res,
         "saturation_solves_per_s": sat, "saturation_mean_batch": sat_batch, "saturation": sat_s,
         "plain_fp64_ms_per_request": plain,
         "plain_fp64_solves_per_s": plain_rate, "speedup_vs_plain": sat / plain_rate,

@@ -139,7 +139,7 @@ typedef struct msrs_problem_desc {
                                 this relative tolerance (Def. num_rank with tau = rank_tol sigma_1(Y_m): the number of
                                 singular values of Y_m above it), at least 1 and at most k; msrs_query_patch reports
                                 it as n_cols once the range finder has run, and the columns of Q past it are zero.
-                                Values below the range finder's resolution 2 sqrt(s u) (u = 2^-53) are refused. */
+                                Values below 1e-12 (the range finder's resolution) are refused. */
     double ir_stop;          /* FP32_IR: refinement runs to stagnation.  A patch stops once the largest
                                 ||r_j||/||rhs_j|| of its columns is <= ir_stop, or is <= ir_tol and the last
                                 iteration did not halve it (0 -> 1e-13, the level of the FP64 residual's own
@@ -246,10 +246,12 @@ msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, 
  * entry made positive.  Full-basis patches keep all columns.
  * Q_out_dev: device, optional copy of the concatenated Q.  sv_out_dev:
  * device, optional s singular values of each Y_m (descending).
- * The singular values come from the Gram matrix Y_m^T Y_m, which resolves
- * them down to about sqrt(s u) sigma_1 (u = 2^-53).
- * Errors: STATE; latched RANK if sigma_k(Y_m) <= 2 sqrt(s u) sigma_1(Y_m)
- * (the k-th direction is not resolved) or the orthonormalisation breaks down;
+ * The singular values come from the Gram matrix Y_m^T Y_m (resolved down to
+ * about sqrt(s u) sigma_1, u = 2^-53); a patch whose sigma_{k+1} lies below
+ * 1e-4 sigma_1 takes a second pass on the rotated snapshots Y_m V, whose
+ * graded Gram matrix resolves them down to about u sigma_1.
+ * Errors: STATE; latched RANK if sigma_k(Y_m) <= 1e-13 sigma_1(Y_m) (the
+ * snapshots have lower rank than k) or the orthonormalisation breaks down;
  * latched NONFINITE for non-finite snapshots.
  */
 msrs_status msrs_range_finder(msrs_handle h, double* Q_out_dev, double* sv_out_dev);
@@ -287,6 +289,19 @@ msrs_status msrs_assemble_coarse(msrs_handle h);
  */
 msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev,
                               void* stream);
+
+/*
+ * Conditioning of the least-squares system of eq. elliptic_cond_reduced /
+ * rte_cond_reduced, which the online stage solves through its normal
+ * equations: *kappa_normal (nullable) receives the 1-norm condition estimate
+ * of P~^T P~ made at msrs_assemble_coarse (||K||_1 times Hager and Higham's
+ * estimate of ||K^{-1}||_1 from the resident band Cholesky factor, as
+ * LAPACK's banded condition estimators do; a lower bound, in practice within
+ * a small factor), *kappa_ls (nullable) its square root, the matching
+ * estimate of kappa(P~).  The normal equations lose about
+ * log10(kappa_normal) digits of the coefficients.  Errors: ARG, STATE.
+ */
+msrs_status msrs_coarse_condition(msrs_handle h, double* kappa_normal, double* kappa_ls);
 
 /*
  * The same solve by the plain direct method, one request after another:

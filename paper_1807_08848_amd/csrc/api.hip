@@ -18,10 +18,10 @@ thread_local std::string g_create_err;
 
 int round16(int v) { return ((v + 15) / 16) * 16; }
 
-// Smallest sigma_j / sigma_1 the Gram-matrix range finder resolves for s
-// samples: the eigenvalues of the rounded Y^T Y carry absolute errors of about
-// s u sigma_1^2 (u = 2^-53).
-double gram_resolution(int s) { return 2.0 * std::sqrt((double)s * 0x1p-53); }
+// Smallest relative tolerance of an adaptive rank: the range finder resolves
+// sigma_j down to about u sigma_1 (its second pass on the rotated snapshots),
+// and a tolerance needs a margin above the rounding of the snapshots.
+constexpr double kMinRankTol = 1e-12;
 
 // Gauss-Legendre nodes (ascending) and weights on [-1, 1], Newton iteration
 // on the three-term recurrence of the Legendre polynomials.
@@ -175,8 +175,8 @@ msrs_status validate(const msrs_problem_desc* d, std::string& msg) {
     if (d->precision != MSRS_PREC_FP64 && d->precision != MSRS_PREC_FP32_IR) { msg = "unknown precision"; return MSRS_ERR_ARG; }
     if (!d->overlap) { msg = "overlap is NULL"; return MSRS_ERR_ARG; }
     if (!(d->rank_tol >= 0.0 && d->rank_tol < 1.0)) { msg = "rank_tol must be in [0, 1)"; return MSRS_ERR_ARG; }
-    if (d->rank_tol > 0.0 && d->rank_tol < gram_resolution(d->n_samples)) {
-        msg = "rank_tol below the range finder's resolution 2 sqrt(s u)";
+    if (d->rank_tol > 0.0 && d->rank_tol < kMinRankTol) {
+        msg = "rank_tol below the range finder's resolution (1e-12)";
         return MSRS_ERR_ARG;
     }
     if (!(d->ir_tol >= 0.0) || !(d->ir_stop >= 0.0)) { msg = "ir_tol and ir_stop must be >= 0"; return MSRS_ERR_ARG; }
@@ -494,6 +494,9 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->rf_pval = dalloc<double>(*c, (int64_t)c->n_patches * c->rf_maxrc * 64);
         c->rf_pidx = dalloc<int32_t>(*c, (int64_t)c->n_patches * c->rf_maxrc * 64);
         c->rf_skip = dalloc<int32_t>(*c, c->n_patches);
+        c->rf_second = dalloc<int32_t>(*c, c->n_patches);
+        c->rf_small2 = dalloc<double>(*c, (int64_t)c->n_patches * 4096);
+        c->rf_Z = dalloc<double>(*c, c->Y_total);
         c->sv = dalloc<double>(*c, c->sv_total);
         int64_t rn_total = 0;
         for (auto& P : c->hp) rn_total += 2 * P.sp;
@@ -975,6 +978,9 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
             }
             if (c->budget && (size_t)c->bytes > c->budget) return fail(c, MSRS_ERR_OOM, "coarse factor exceeds the HBM budget");
         }
+        // the set-up rewrites the factor and G_B that online calls read
+        for (auto& w : c->ws)
+            if (w.used) MSRS_HIP_CHECK(hipEventSynchronize(w.done));
         if (first || c->rank_tol > 0.0) {
             coarse_layout(c, false, bmap);
             MSRS_HIP_CHECK(hipMemcpy(c->dc, c->hc.data(), sizeof(CoarseDesc) * c->n_patches, hipMemcpyHostToDevice));
@@ -1005,6 +1011,7 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
         }
         MSRS_HIP_CHECK(hipGetLastError());
         sync_flags(*c);
+        c->cond_normal = c->hflags[0] ? INFINITY : coarse_condition(*c, c->ws[0].cbuf);
     } catch (const HipError& e) {
         return hip_fail(c, e);
     }
@@ -1049,6 +1056,15 @@ static msrs_status solve_common(Ctx* c, int32_t n_req, const double* f_dev, doub
     } catch (const HipError& e) {
         return hip_fail(c, e);
     }
+    return MSRS_OK;
+}
+
+msrs_status msrs_coarse_condition(msrs_handle h, double* kappa_normal, double* kappa_ls) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (!c->coarse_ready) return fail(c, MSRS_ERR_STATE, "msrs_assemble_coarse must come first");
+    if (kappa_normal) *kappa_normal = c->cond_normal;
+    if (kappa_ls) *kappa_ls = std::sqrt(c->cond_normal);
     return MSRS_OK;
 }
 

@@ -10,6 +10,15 @@
 // freedom) with the same code path.  Each column's largest-magnitude entry is
 // made positive (first index on ties).
 //
+// The eigenvalues of the rounded Y^T Y carry absolute errors of about
+// s u sigma_1^2, so this resolves sigma_j only down to about sqrt(s u) sigma_1.
+// A patch whose sigma_{k+1} (sigma_k when k = s) lies below kResolve sigma_1
+// takes a second pass on the rotated snapshots Z = Y V: Z^T Z is graded and
+// nearly diagonal (its entries carry errors of u |z_i| |z_j|, relative to its
+// own scale), so a Jacobi sweep with a purely relative stopping test resolves
+// its eigenvalues to high relative accuracy, and Z V2 / sigma are the left
+// singular vectors with column errors of order u, down to sigma_j ~ u sigma_1.
+//
 // Tall work (Gram matrices, products with the small s x k / k x k factors,
 // the column argmax) runs over (patch, chunk of kRowChunk rows) workgroups with
 // per-chunk partials reduced per patch in a fixed order, on FP64 MFMA; the
@@ -22,16 +31,21 @@ constexpr int kRfMax = 64;          // max columns
 constexpr int kRfStage = 32;        // rows staged in LDS per Gram step
 constexpr int kRowChunk = 512;      // rows per workgroup of the tall kernels
 constexpr int kSmall = kRfMax * kRfMax;
+constexpr double kResolve = 1e-4;   // below this sigma_{k+1} / sigma_1 a patch takes the second pass
 
 // columns and base of the tall matrix a kernel works on
 struct Tall {
     const double* base;
     int ncols;
 };
-enum Which { kY = 0, kQ = 1, kW = 2 };
+// kZ: the rotated snapshots Z = Y V1 (shape of Y); kYZ: Z for the patches
+// that took the second pass, Y for the others
+enum Which { kY = 0, kQ = 1, kW = 2, kZ = 3, kYZ = 4 };
 
-__device__ __forceinline__ Tall tall_of(const PatchDesc& P, int which, const double* Y, const double* Q, const double* W) {
-    if (which == kY) return Tall{Y + P.Y_off, P.s};
+__device__ __forceinline__ Tall tall_of(const PatchDesc& P, int which, const double* Y, const double* Q, const double* W,
+                                        const double* Z = nullptr, bool second = false) {
+    if (which == kY || (which == kYZ && !second)) return Tall{Y + P.Y_off, P.s};
+    if (which == kZ || which == kYZ) return Tall{Z + P.Y_off, P.s};
     return Tall{(which == kQ ? Q : W) + P.Q_off, P.ncols};
 }
 
@@ -95,17 +109,20 @@ __device__ void gram_rows_mfma(const double* __restrict__ A, int nrows, int r0, 
 
 // grid (patch, row chunk): partial Gram of the chunk's rows -> part[(p * maxrc + chunk) * 4096]
 // (skip: patches whose flag is set have nothing to do)
+// (only: patches whose entry is zero have nothing to do)
 __global__ __launch_bounds__(kThreads) void gram_partial_kernel(const PatchDesc* pd, int p0, int which, const double* __restrict__ Y,
                                                                 const double* __restrict__ Q, const double* __restrict__ W,
-                                                                double* __restrict__ part, int maxrc, const int32_t* __restrict__ skip) {
+                                                                double* __restrict__ part, int maxrc, const int32_t* __restrict__ skip,
+                                                                const double* __restrict__ Z = nullptr,
+                                                                const int32_t* __restrict__ only = nullptr) {
     __shared__ double stage[kRfStage * kStageLd];
     const int p = p0 + blockIdx.x;
-    if (skip && skip[p]) return;
+    if ((skip && skip[p]) || (only && !only[p])) return;
     const PatchDesc P = pd[p];
     const int r0 = blockIdx.y * kRowChunk;
     if (r0 >= P.nrows) return;
     const int r1 = min(P.nrows, r0 + kRowChunk);
-    const Tall T = tall_of(P, which, Y, Q, W);
+    const Tall T = tall_of(P, which, Y, Q, W, Z, only && only[p]);
     double* out = part + ((int64_t)p * maxrc + blockIdx.y) * kSmall;
     if (T.ncols <= 16) gram_rows_mfma<1>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
     else if (T.ncols <= 32) gram_rows_mfma<2>(T.base, P.nrows, r0, r1, T.ncols, stage, out);
@@ -155,9 +172,16 @@ int eig_threads(int max_s) {
     return std::max(64, (np2 * p2 + 63) / 64 * 64);
 }
 
+// pass 0: Y^T Y.  Patches whose sigma_{k+1} (sigma_k when k = s) falls below
+// kResolve sigma_1, or whose rank is chosen at a tolerance below it, are
+// marked in second[p] and leave V (all s columns, in descending order) in
+// small2[p] for Z = Y V; the others finish here.  pass 1 (marked patches
+// only): Z^T Z, with the relative stopping test alone; its singular values,
+// gap, rank and B replace pass 0's.
 __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int p0, const double* __restrict__ part, int maxrc,
                                                              double* __restrict__ small, double* __restrict__ sv_all,
-                                                             double* __restrict__ gap, int32_t* flags, double rank_tol) {
+                                                             double* __restrict__ gap, int32_t* flags, double rank_tol, int pass,
+                                                             double* __restrict__ small2, int32_t* __restrict__ second) {
     // G and V with an odd leading dimension: a wave's column accesses
     // (V[j][a] over rows j) fall on distinct LDS banks
     constexpr int LDG = kRfMax + 1;
@@ -168,10 +192,11 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
     __shared__ double lam[kRfMax];
     __shared__ int rot;
     const int p = p0 + blockIdx.x;
+    if (pass == 1 && !second[p]) return;
     const PatchDesc P = pd[p];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int s = P.s, kreq = P.kreq;
-    __shared__ int kshared;
+    __shared__ int kshared, second_s;
     const int nch = (P.nrows + kRowChunk - 1) / kRowChunk;
     for (int o = tid; o < kRfMax * LDG; o += nth) {
         G[o] = 0.0;
@@ -191,9 +216,10 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
     // the rounding in forming G = Y^T Y, below which the relative test cannot be
     // met between widely separated eigenvalues), at most 30.  The trace is
     // invariant under the rotations.
+    // (pass 1: Z^T Z is graded; the relative test alone)
     double gtr = 0.0;
     for (int x = 0; x < s; ++x) gtr += G[x * LDG + x];
-    const double floor_abs = 1e-16 * gtr;
+    const double floor_abs = pass == 0 ? 1e-16 * gtr : 0.0;
     if (tid == 0) rot = 0;
     __syncthreads();
     for (int sweep = 0; sweep < 30; ++sweep) {
@@ -292,15 +318,29 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
         }
         if (kk != P.ncols) pd[p].ncols = kk;
         kshared = kk;
-        // the k-th direction must lie above the Gram matrix's resolution: its
-        // eigenvalues carry absolute errors of about s u sigma_1^2 (u = 2^-53)
         const double sk = svp[kk - 1];
-        if (!(sk > 2.0 * sqrt((double)s * 0x1p-53) * s1)) raise_flag(flags, 2);
+        const double next = svp[min(kk, s - 1)];
+        const bool again = pass == 0 && P.sampled && isfinite(s1) && s1 > 0.0 &&
+                           (!(next >= kResolve * s1) || (rank_tol > 0.0 && rank_tol < kResolve));
+        second_s = again ? 1 : 0;
+        if (pass == 0) second[p] = again ? 1 : 0;
+        // the k-th direction must be resolved: a rank deficiency of the
+        // snapshots themselves (sigma_k at rounding level) after the second pass
+        if (!again && !(sk > 1e-13 * s1)) raise_flag(flags, 2);
         if (!isfinite(s1)) raise_flag(flags, 4);
         gap[p] = (kk < s) ? (sk - svp[kk]) / s1 : 1.0;
     }
     __syncthreads();
     const int k = kshared;
+    if (second_s) {
+        // V in descending order for Z = Y V (all s columns)
+        double* V1 = small2 + (int64_t)p * kSmall;
+        for (int o = tid; o < kSmall; o += nth) {
+            const int i = o / kRfMax, j = o % kRfMax;
+            V1[o] = (i < s && j < s) ? V[i * LDG + perm[j]] : 0.0;
+        }
+        return;
+    }
     double* B = small + (int64_t)p * kSmall;
     for (int o = tid; o < kSmall; o += nth) {
         const int i = o / kRfMax, j = o % kRfMax;
@@ -425,20 +465,24 @@ __device__ void tall_rows_mfma(const double* __restrict__ S, int nrows, int m, i
     }
 }
 
+// (only: patches whose entry is zero have nothing to do; dst_which = kZ
+// writes Z = src small with all s columns)
 __global__ __launch_bounds__(kThreads) void tall_gemm_kernel(const PatchDesc* pd, int p0, int src_which, int dst_which,
                                                              const double* __restrict__ Y, double* __restrict__ Q,
                                                              double* __restrict__ W, const double* __restrict__ small,
-                                                             const int32_t* __restrict__ skip) {
+                                                             const int32_t* __restrict__ skip, double* __restrict__ Z = nullptr,
+                                                             const int32_t* __restrict__ only = nullptr,
+                                                             const int32_t* __restrict__ second = nullptr) {
     __shared__ double B[kSmall];
     const int p = p0 + blockIdx.x;
-    if (skip && skip[p]) return;
+    if ((skip && skip[p]) || (only && !only[p])) return;
     const PatchDesc P = pd[p];
     const int r0 = blockIdx.y * kRowChunk;
     if (r0 >= P.nrows) return;
     const int r1 = min(P.nrows, r0 + kRowChunk);
-    const Tall S = tall_of(P, src_which, Y, Q, W);
-    double* D = (dst_which == kQ ? Q : W) + P.Q_off;
-    const int m = S.ncols, k = P.ncols, nrows = P.nrows;
+    const Tall S = tall_of(P, src_which, Y, Q, W, Z, second && second[p]);
+    double* D = dst_which == kZ ? Z + P.Y_off : (dst_which == kQ ? Q : W) + P.Q_off;
+    const int m = S.ncols, k = dst_which == kZ ? P.s : P.ncols, nrows = P.nrows;
     // rows of small past m and columns past k are zero in the operand
     for (int o = threadIdx.x; o < kSmall; o += kThreads) {
         const int i = o / kRfMax, j = o % kRfMax;
@@ -548,9 +592,17 @@ void launch_range(Ctx& c, int p0, int p1) {
     int maxs = 0;
     for (int p = p0; p < p1; ++p) maxs = std::max(maxs, c.hp[p].s);
     hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
-                       c.dflags, c.rank_tol);
-    hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kY, (int)kW, c.Y, c.Q, c.rf_ws, c.rf_small,
-                       (const int32_t*)nullptr);
+                       c.dflags, c.rank_tol, 0, c.rf_small2, c.rf_second);
+    // second pass where Y^T Y does not resolve sigma_{k+1}: Z = Y V, Z^T Z, Jacobi
+    hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kY, (int)kZ, c.Y, c.Q, c.rf_ws, c.rf_small2,
+                       (const int32_t*)nullptr, c.rf_Z, (const int32_t*)c.rf_second, (const int32_t*)nullptr);
+    hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kZ, c.Y, c.Q, c.rf_ws, c.rf_part, mrc,
+                       (const int32_t*)nullptr, (const double*)c.rf_Z, (const int32_t*)c.rf_second);
+    hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
+                       c.dflags, c.rank_tol, 1, c.rf_small2, c.rf_second);
+    // W = Y B (first pass) or Z B (second pass)
+    hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kYZ, (int)kW, c.Y, c.Q, c.rf_ws, c.rf_small,
+                       (const int32_t*)nullptr, c.rf_Z, (const int32_t*)nullptr, (const int32_t*)c.rf_second);
     // Cholesky-QR passes: W -> Q (-> W where the second pass is needed)
     for (int pass = 0; pass < 2; ++pass) {
         const int src = pass == 0 ? kW : kQ, dst = pass == 0 ? kQ : kW;

@@ -121,6 +121,9 @@ struct Ctx {
     double* rf_pval = nullptr;    // per (patch, row chunk) column maxima
     int32_t* rf_pidx = nullptr;
     int32_t* rf_skip = nullptr;   // per patch: the second Cholesky-QR pass is not needed
+    int32_t* rf_second = nullptr; // per patch: the range finder's second (rotated) pass is needed
+    double* rf_small2 = nullptr;  // per patch 64 x 64: the first pass's eigenvectors (second pass only)
+    double* rf_Z = nullptr;       // rotated snapshots Z = Y V (shape of Y; second pass only)
     int rf_maxrc = 1;             // row chunks per patch at most
     double* coef_copy = nullptr;  // device copy of the coefficient field (traces)
     int32_t* iters = nullptr;     // per patch refinement iterations at convergence
@@ -146,6 +149,8 @@ struct Ctx {
     int recon_batch = 8;         // requests per reconstruction pass (1, 2, 4, 8, 16)
     int apply_batch = 8;         // requests per G_B workgroup (4, 8, 16)
     int Np = 0, bw = 0;
+    double norm1_normal = 0.0;    // ||P~^T P~||_1 of the last coarse assembly
+    double cond_normal = 0.0;     // 1-norm condition estimate of P~^T P~ (0 before msrs_assemble_coarse)
     int Np_cap = 0, nB_cap = 0;   // sizes the coarse buffers were allocated for (every patch at its requested rank)
     std::vector<CoarseDesc> hc;
     CoarseDesc* dc = nullptr;
@@ -214,6 +219,9 @@ void launch_check_conv(Ctx& c);
 
 // coarse (k_coarse.hip)
 void coarse_setup(Ctx& c);     // traces, normal matrix, Cholesky (enqueued)
+// 1-norm condition estimate of the factored normal matrix (host-driven band
+// solves on the handle's stream; work: Np device doubles)
+double coarse_condition(Ctx& c, double* work);
 // Batched path: n_req requests, boundary data f[r] (device or mapped pinned
 // host memory), outputs u[r] (device), workspaces gbuf (nB x kOutPerLaunch)
 // and cbuf (Np x kOutPerLaunch).  Reads the handle only, so several streams

@@ -237,6 +237,12 @@ class Problem:
     def assemble_coarse(self):
         self._check(_lib.msrs_assemble_coarse(self.h))
 
+    def coarse_condition(self):
+        """(1-norm condition estimate of P~^T P~, its square root) from msrs_assemble_coarse."""
+        kn, kl = C.c_double(), C.c_double()
+        self._check(_lib.msrs_coarse_condition(self.h, C.byref(kn), C.byref(kl)))
+        return kn.value, kl.value
+
     def set_max_batch(self, n):
         self._check(_lib.msrs_set_max_batch(self.h, int(n)))
 

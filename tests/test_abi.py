@@ -47,12 +47,12 @@ def test_create_validates_arguments(args, msg):
 
 
 def test_rank_tol_below_the_range_finders_resolution_is_refused():
-    """The Gram-matrix range finder resolves sigma_j / sigma_1 down to about
-    sqrt(s u): a tolerance below 2 sqrt(s u) would choose directions it cannot
-    resolve."""
+    """The range finder resolves sigma_j / sigma_1 down to about u (its second
+    pass): a tolerance below 1e-12 would choose directions inside the
+    snapshots' own rounding."""
     from paper_1807_08848_amd import msrs
     with pytest.raises(msrs.MsrsError) as e:
-        msrs.Problem(msrs.make_desc(0, 128, 4, [8] * 16, 32, 6, rank_tol=1e-9))
+        msrs.Problem(msrs.make_desc(0, 128, 4, [8] * 16, 32, 6, rank_tol=1e-13))
     assert e.value.status == msrs.ERR_ARG and "resolution" in str(e.value)
     with pytest.raises(msrs.MsrsError) as e:
         msrs.Problem(msrs.make_desc(0, 128, 4, [8] * 16, 32, 6, ir_stop=-1.0))

@@ -553,3 +553,28 @@ def test_factor_share_keeps_results(gpu, ov):
     for p in range(M * M):
         assert np.array_equal(a["Y"][p], b["Y"][p]) and np.array_equal(a["Q"][p], b["Q"][p]), p
     assert np.array_equal(a["u"], b["u"])
+
+
+@pytest.mark.parametrize("make", [configs.elliptic_periodic_128, configs.elliptic_lognormal_512])
+def test_coarse_condition_estimate(gpu, make):
+    """msrs_coarse_condition: the 1-norm condition estimate of the normal
+    equations P~^T P~ (Hager-Higham on the resident band factor) against the
+    exact kappa_1 of the oracle's own P~^T P~ (a lower bound, within a small
+    factor), and the estimate of kappa(P~) against the 2-norm condition of the
+    oracle's P~ (within the factor sqrt(Np) that separates the norms)."""
+    from gpu_cases import resident
+    cfg = make()
+    pr = resident(cfg, FP64)
+    try:
+        kn, kl = pr.coarse_condition()
+        Np = pr.layout().coarse_dim
+    finally:
+        pr.close()
+    ref = _oracle_elliptic(cfg)
+    P, _, _, _ = E.coarse_rows(cfg["N"], cfg["M"], ref, cfg["coef"])
+    K = P.T @ P
+    exact = np.linalg.cond(K, 1)
+    assert exact / 10 <= kn <= exact * (1 + 1e-6), (kn, exact)
+    k2 = np.linalg.cond(P)
+    assert k2 / np.sqrt(Np) <= kl <= k2 * np.sqrt(Np), (kl, k2)
+    assert abs(kl - np.sqrt(kn)) <= 1e-12 * kl
