@@ -72,3 +72,96 @@ def test_hg_parity(lib, eps):
             assert sin_max_angle(r["Q"], out["Q"][p]) <= 1e-6, p       # s = k: the span of Y
     f_or = K.online(cfg["M"], nv, ref, phi)
     assert np.linalg.norm(out["u"][0] - f_or) / np.linalg.norm(f_or) <= 1e-6
+
+
+# ------------------------------------------------------------------ local test
+# The paper's local transport test (Sec. 4.3): the second patch K_2 of the
+# M = 10 decomposition, its buffered patch twice as large, g = 1/2, and the
+# Green's matrices G_2 (unbuffered) and G~_2 (buffered) from the patch's
+# inflow data to its cells and ghost cells.  No printed values: the trends of
+# its three local figures.
+EPS_LOCAL = (1.0, 2.0 ** -2, 2.0 ** -4, 2.0 ** -6)
+
+
+def _local_setup(eps, nv=64):
+    cfg = configs.kinetic_hg_100(eps, 10, n_vel=nv)
+    g = K.patch_geometry(cfg["N"], cfg["M"], cfg["overlap"])[1]
+    g0 = K.patch_geometry(cfg["N"], cfg["M"], 0)[1]
+    green = lambda gg: K.sample_patch(cfg["coef"], eps, cfg["N"], nv, gg, np.eye(nv), hg=cfg["hg"])
+    return cfg, g, green(g0), green(g)
+
+
+def test_rte_local_buffer_speeds_up_singular_value_decay():
+    """Fig. rte_local: the normalized singular values of G~_2 fall faster than
+    those of G_2 (at every eps; by a factor of about 9 at sigma_11 for
+    eps = 2^-6)."""
+    for eps in EPS_LOCAL:
+        _, _, G0, Gt = _local_setup(eps)
+        s0 = np.linalg.svd(G0, compute_uv=False)
+        st = np.linalg.svd(Gt, compute_uv=False)
+        assert st[10] / st[0] < s0[10] / s0[0], eps
+        if eps == 2.0 ** -6:
+            assert st[10] / st[0] < 0.2 * s0[10] / s0[0]
+
+
+def test_rte_local_sampling_error_trends():
+    """Fig. RTE_LocalError: ||G~_2 - Q Q^T G~_2||_2 / ||G~_2||_2 with Q from a QR
+    of k_m random solutions (nested: the first k_m columns of one draw) falls
+    as k_m grows, and at every k_m is smaller for smaller eps."""
+    from oracle.rangefinder import projection_error, range_finder
+    ks = (5, 10, 20, 40, 60)
+    errs = {}
+    for eps in EPS_LOCAL:
+        cfg, g, _, Gt = _local_setup(eps)
+        om = K.patch_omega(cfg["seed"], g, 64, max(ks))
+        for k in ks:
+            Y = K.sample_patch(cfg["coef"], eps, cfg["N"], 64, g, om[:, :k], hg=cfg["hg"])
+            errs[eps, k] = projection_error(Gt, range_finder(Y, k)[0])
+    for eps in EPS_LOCAL:
+        assert all(errs[eps, a] >= errs[eps, b] for a, b in zip(ks, ks[1:])), eps
+    for k in ks:
+        assert all(errs[a, k] > errs[b, k] for a, b in zip(EPS_LOCAL, EPS_LOCAL[1:])), k
+    assert errs[2.0 ** -6, 20] < 0.1 and errs[1.0, 20] > 0.9
+
+
+def test_rte_local_leading_modes_captured():
+    """Fig. rte_local_mode: at eps = 2^-6 the span of k_2 = 50 random
+    solutions captures the first three left singular vectors of G_2 on the
+    cells of K_2 (projection residuals below 0.1), and at eps = 1 it does not
+    (above 0.3).  The ghost rows are left out: for the unbuffered patch they
+    hold the inflow data itself, which no buffered solution reproduces."""
+    from oracle.rangefinder import range_finder
+    res = {}
+    for eps in (1.0, 2.0 ** -6):
+        cfg, g, G0, _ = _local_setup(eps)
+        Y = K.sample_patch(cfg["coef"], eps, cfg["N"], 64, g, K.patch_omega(cfg["seed"], g, 64, 50), hg=cfg["hg"])
+        U = np.linalg.svd(G0[64:-64])[0][:, :3]
+        Q, _ = range_finder(Y[64:-64], 50)
+        res[eps] = np.linalg.norm(U - Q @ (Q.T @ U), axis=0)
+    assert res[2.0 ** -6].max() < 0.1 and res[1.0].min() > 0.3
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("eps", EPS_LOCAL)
+def test_rte_local_parity(lib, eps):
+    """The local test on the device at every eps: the buffered Green's matrix
+    G~_2 (DetLocalSolu as 64 Kronecker-delta inflow columns through the
+    explicit-Omega entry, FP64) and its singular values against the oracle's,
+    and the sampling error of the device's bases from k_m = 10, 20, 40 device
+    Philox samples against the oracle's on the same draws."""
+    from gpu_cases import run
+    from oracle.rangefinder import projection_error, range_finder
+    cfg, g, _, Gt = _local_setup(eps)
+    nv = 64
+    full = dict(cfg, s=nv, k=nv)
+    out = run(full, 0, omegas=[np.eye(nv)] * cfg["M"])
+    Gd = out["Y"][1]
+    assert np.abs(Gd - Gt).max() <= 1e-10 * np.abs(Gt).max()
+    st = np.linalg.svd(Gt, compute_uv=False)
+    assert np.abs(out["sv"][1] - st).max() <= 1e-10 * st[0]
+    for k in (10, 20, 40):
+        o = run(dict(cfg, s=k, k=k), FP32_IR)
+        Y = K.sample_patch(cfg["coef"], eps, cfg["N"], nv, g, K.patch_omega(cfg["seed"], g, nv, k), hg=cfg["hg"])
+        e_or = projection_error(Gt, range_finder(Y, k)[0])
+        e_dev = projection_error(Gt, o["Q"][1])
+        assert abs(e_dev - e_or) <= 1e-6 * max(1.0, e_or), (k, e_dev, e_or)
