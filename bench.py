@@ -479,7 +479,9 @@ def run_serving(lams=(200, 500, 1000, 2000), seconds=2.0, seed_arrival=5):
 
     rng = np.random.default_rng(seed_arrival)
     res = {}
-    with msrs.Server(models, n_streams=4, max_batch=32, slot_bytes=2 << 30) as srv:
+    # the worker polls through idle gaps of up to 0.2 s (a host core for arrival latency: at 200 req/s one
+    # gap in 7 exceeds the default 10 ms, after which a wake-up would add the scheduler's latency)
+    with msrs.Server(models, n_streams=4, max_batch=32, slot_bytes=2 << 30, idle_spin_us=200000) as srv:
         accuracy = served_accuracy(srv, cfgs, pool)
         mdl = rng.integers(0, 2, 200)
         srv.replay(mdl, [pool[m][i % 64] for i, m in enumerate(mdl)])          # warm-up
@@ -511,7 +513,7 @@ def run_serving(lams=(200, 500, 1000, 2000), seconds=2.0, seed_arrival=5):
         "saturation_solves_per_s": sat, "saturation_mean_batch": sat_batch, "saturation": sat_s,
         "plain_fp64_ms_per_request": plain,
         "plain_fp64_solves_per_s": plain_rate, "speedup_vs_plain": sat / plain_rate,
-        "server": {"streams": 4, "max_batch": 32, "mean_batch": st.mean_batch, "max_in_flight": st.max_in_flight,
+        "server": {"streams": 4, "max_batch": 32, "idle_spin_us": 200000, "mean_batch": st.mean_batch, "max_in_flight": st.max_in_flight,
                    "admission_waits": st.admission_waits, "peak_slot_bytes": st.peak_slot_bytes},
     }
     for m in models:
