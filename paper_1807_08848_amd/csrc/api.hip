@@ -530,6 +530,22 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
             std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
             c->lpt = dalloc<int32_t>(*c, c->n_patches);
             MSRS_HIP_CHECK(hipMemcpy(c->lpt, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+            // sweep workgroups (patch, half), a chain of the half's lines each:
+            // sorted by cost (lines x bp^2), the costliest half first, and the
+            // second half of the list reversed, so that with two resident
+            // workgroups per compute unit the i-th costliest shares its unit
+            // with the i-th cheapest rather than with a chain of the same length
+            std::vector<int32_t> items;
+            for (int p = 0; p < c->n_patches; ++p) items.push_back(p << 1), items.push_back(p << 1 | 1);
+            auto scost = [&](int32_t v) {
+                const PatchDesc& P = c->hp[v >> 1];
+                const int m = P.nl / 2, nlines = (v & 1) ? P.nl - 1 - m : m + 1;
+                return (double)nlines * P.bp * P.bp;
+            };
+            std::stable_sort(items.begin(), items.end(), [&](int32_t a, int32_t b) { return scost(a) > scost(b); });
+            std::reverse(items.begin() + c->n_patches, items.end());
+            c->sweep_items = dalloc<int32_t>(*c, (int64_t)items.size());
+            MSRS_HIP_CHECK(hipMemcpy(c->sweep_items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         }
         c->dflags = dalloc<int32_t>(*c, kFlags);
         c->coef_copy = dalloc<double>(*c, c->kind == kElliptic ? (int64_t)c->N * c->N : c->N);

@@ -41,7 +41,7 @@ template <> struct Vec16<double> { typedef double2 type; static constexpr int n 
 // and column tiles NCT (16 NCT samples), so the MFMA loop is straight-line
 // code.  TW: this chunk's [2][bp x sp] middle-line couplings (row stride sp).
 template <typename T, int KIND, int R, int NCT, int PHASE>
-__device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw, double dx,
+__device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw, double dx,
                            const T* __restrict__ E, T* __restrict__ X, double* __restrict__ X64, T* __restrict__ TW, int half,
                            T* ybuf, T* wbuf, double* craw, double* cvp, double* cvm) {
     typedef typename Vec16<T>::type V;
@@ -231,7 +231,7 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
         // nothing yet and is written, not accumulated (pre64 stays zero).
         launder();
         constexpr bool kAccum = PHASE == 1;
-        double pre64[NCT][4] = {}, pre64n[NCT][4] = {};
+        double pre64[NCT][4] = {};
         load_A(E + (int64_t)m * BP * BP);
         const bool acc64 = X64 && half == 0;   // line m's iterate is updated once, by the top half
         if (kAccum && acc64) load_64(X64 + m * lstride, pre64);
@@ -249,7 +249,6 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
             const int l1 = m - dir;
             load_line(X + l1 * lstride, rv);
             if (KIND == kElliptic && tid <= b) crow = aL[(dir > 0 ? m : l1) * L + tid];
-            if (kAccum && X64) load_64(X64 + l1 * lstride, pre64n);
         }
         lds_barrier();
         mfma();
@@ -263,17 +262,15 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
             launder();
             const int ln = m - dir * (k + 1);
             const bool more = k + 1 < nst;
-#pragma unroll
-            for (int c = 0; c < NCT; ++c)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) pre64[c][t] = pre64n[c][t];
+            // this line's FP64 iterate: consumed at the end of the step, so the
+            // coupling, the barriers and the products hide the load
+            if (kAccum && X64) load_64(X64 + ln * lstride, pre64);
             T rvn[RPT];
             double crown = 0.0;
             if (more) {
                 const int l2 = ln - dir;
                 load_line(X + l2 * lstride, rvn);                                     // y of the next step
                 if (KIND == kElliptic && tid <= b) crown = aL[(dir > 0 ? ln : l2) * L + tid];
-                if (kAccum && X64) load_64(X64 + l2 * lstride, pre64n);
             }
             if (KIND == kElliptic && tid <= b) craw[tid] = crow * (-1.0 / 3.0);
             lds_barrier();
@@ -300,20 +297,24 @@ __device__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, co
 // grid (patch, column chunk of 16*NCT samples, half); sp of every patch is a
 // multiple of the chunk.
 template <typename T, int KIND, int NCT, int PHASE>
-__global__ __launch_bounds__(kSweepThreads) void sweep_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
+__global__ __launch_bounds__(kSweepThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void sweep_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
                                                               const double* __restrict__ vw, double dx, const T* __restrict__ E_all,
                                                               T* __restrict__ X_all, double* __restrict__ X64_all, T* __restrict__ TW_all,
-                                                              const int32_t* __restrict__ conv, int32_t* flags) {
+                                                              const int32_t* __restrict__ conv, const int32_t* __restrict__ items,
+                                                              int32_t* flags) {
     __shared__ T ybuf[kMaxLine * 16 * NCT];
     __shared__ T wbuf[kMaxLine * 16 * NCT];
     __shared__ double craw[kMaxLine + 1];
     __shared__ double cvp[kMaxLine], cvm[kMaxLine];
-    const int p = p0 + blockIdx.x;
+    // items: workgroup x runs (patch, half) = (items[x] >> 1, items[x] & 1);
+    // without it, patch p0 + x and half z
+    const int it = items ? items[blockIdx.x] : 0;
+    const int p = items ? it >> 1 : p0 + (int)blockIdx.x;
+    const int half = items ? it & 1 : (int)blockIdx.z;
     if (conv && conv[p]) return;
     const PatchDesc P = pd[p];
     const int s0 = blockIdx.y * 16 * NCT;
     if (s0 >= P.sp) return;
-    const int half = blockIdx.z;
     const double* aL = aL_all + P.a_off;
     const T* E = E_all + P.E_off;
     T* X = X_all + P.x_off + s0;
@@ -361,7 +362,10 @@ void launch_sweep(Ctx& c, int p0, int p1, bool fp32, bool first) {
     int maxsp = 0;
     for (int p = p0; p < p1; ++p) maxsp = std::max(maxsp, c.hp[p].sp);
     const int sc = sweep_chunk(c, p0, p1, fp32);
-    const dim3 grid(p1 - p0, maxsp / sc, 2), blk(kSweepThreads);
+    // the whole batch runs in the paired cost order; a single patch as (patch, half)
+    const bool all = p0 == 0 && p1 == c.n_patches && c.sweep_items;
+    const int32_t* items = all ? c.sweep_items : nullptr;
+    const dim3 grid(all ? 2 * c.n_patches : p1 - p0, maxsp / sc, all ? 1 : 2), blk(kSweepThreads);
     const int32_t* conv = fp32 ? c.conv : nullptr;
     const double dx = dx_of(c);
     // FP32 refinement: the back halves add the correction to the FP64 iterate
@@ -369,17 +373,17 @@ void launch_sweep(Ctx& c, int p0, int p1, bool fp32, bool first) {
 #define MSRS_SWEEP(TT, KK, NN, XX)                                                                                             \
     do {                                                                                                                      \
         hipLaunchKernelGGL((sweep_kernel<TT, KK, NN, 0>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, \
-                           (double*)nullptr, (TT*)c.tw, conv, c.dflags);                                                      \
+                           (double*)nullptr, (TT*)c.tw, conv, items, c.dflags);                                                      \
         hipLaunchKernelGGL((sweep_kernel<TT, KK, NN, 1>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, \
-                           x64acc, (TT*)c.tw, conv, c.dflags);                                                                 \
+                           x64acc, (TT*)c.tw, conv, items, c.dflags);                                                                 \
     } while (0)
     // the first solve of a refinement writes the FP64 iterate instead of adding to it
 #define MSRS_SWEEP_FIRST(KK, NN)                                                                                               \
     do {                                                                                                                      \
         hipLaunchKernelGGL((sweep_kernel<float, KK, NN, 0>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const float*)c.E, \
-                           c.x32, (double*)nullptr, (float*)c.tw, conv, c.dflags);                                            \
+                           c.x32, (double*)nullptr, (float*)c.tw, conv, items, c.dflags);                                            \
         hipLaunchKernelGGL((sweep_kernel<float, KK, NN, 2>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const float*)c.E, \
-                           c.x32, x64acc, (float*)c.tw, conv, c.dflags);                                                      \
+                           c.x32, x64acc, (float*)c.tw, conv, items, c.dflags);                                                      \
     } while (0)
     if (c.kind == kElliptic) {
         if (fp32 && first) {

@@ -132,6 +132,7 @@ struct Ctx {
     int32_t* rgroup[9] = {};      // patches with line-tile count R (device lists)
     int rgroup_n[9] = {};
     int32_t* lpt = nullptr;       // every patch, costliest first (factor launches over mixed line lengths)
+    int32_t* sweep_items = nullptr;   // 2 n_patches (patch << 1 | half): sweep workgroup order, costliest paired with cheapest
     bool ranks_stale = false;     // the device descriptors hold ranks the host copy has not seen
     int maxch = 1;                // line chunks per patch at most
 
