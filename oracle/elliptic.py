@@ -31,7 +31,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from . import philox
-from .rangefinder import adaptive_rank, range_finder
+from .rangefinder import adaptive_rank, range_finder, sign_fix
 
 # Bilinear element stiffness of the unit square for -div(grad u), local node
 # order SW, SE, NE, NW (counter-clockwise).  Scale-free in 2D: the element
@@ -177,8 +177,73 @@ def full_basis_patch(a_flat, N, g) -> np.ndarray:
     return sample_patch(a_flat, N, g, np.eye(nb))
 
 
+def adjoint_patch(a_flat, N, g, q) -> np.ndarray:
+    """Transpose of the reduced Green's matrix of a buffered patch applied to q (n_K x r).
+
+    The forward map (RanLocalSolu on one patch) is G omega = R_K u with u_B =
+    omega and A_II u_I = -A_IB omega.  Written out, its transpose is
+    G^T q = f_B - A_BI A_II^{-1} f_I, where f = R_K^T q is q placed at the nodes
+    of K_m and zero elsewhere; A_II is symmetric, so the interior solve is the
+    forward one with the source f_I in place of -A_IB omega.  Returns the
+    n_b x r boundary values in counter-clockwise order.
+    """
+    a_patch = patch_coefficient(a_flat, N, g)
+    cy, cx = a_patch.shape
+    q = np.asarray(q, dtype=np.float64)
+    if q.ndim == 1:
+        q = q[:, None]
+    A = assemble_stiffness(a_patch)
+    W = cx + 1
+    bn = boundary_nodes_ccw(cx, cy)
+    bidx = bn[:, 1] * W + bn[:, 0]
+    if cx <= cy:
+        jj, ii = np.meshgrid(np.arange(1, cy), np.arange(1, cx), indexing="ij")
+        band = cx
+    else:
+        ii, jj = np.meshgrid(np.arange(1, cx), np.arange(1, cy), indexing="ij")
+        band = cy
+    iidx = (jj * W + ii).ravel()
+    # f = R_K^T q: the rows of q are the nodes of K_m, row-major (as restrict_to_patch)
+    nH = g["nH"]
+    i0, j0 = g["kx0"] - g["x0"], g["ky0"] - g["y0"]
+    kj, ki = np.meshgrid(np.arange(nH + 1), np.arange(nH + 1), indexing="ij")
+    knodes = ((j0 + kj) * W + (i0 + ki)).ravel()
+    assert q.shape[0] == knodes.size
+    f = np.zeros(((cx + 1) * (cy + 1), q.shape[1]))
+    f[knodes, :] = q
+    out = f[bidx, :].copy()
+    if iidx.size:
+        A_II = A[iidx][:, iidx]
+        A_BI = A[bidx][:, iidx]
+        cb = sla.cholesky_banded(to_banded_upper(A_II, band), lower=False)
+        z = sla.cho_solve_banded((cb, False), f[iidx, :])
+        out -= A_BI @ z
+    return out
+
+
+def two_pass_basis(a_flat, N, g, Y, k, rank_rtol=1e-12):
+    """Two-pass randomized SVD of a patch's reduced Green's matrix from its snapshots.
+
+    The randomized SVD recalled in Section 2.3 (Theorem average_spectral,
+    after Halko, Martinsson and Tropp) projects G onto span(Y), Y = G Omega;
+    its direct-SVD form reads G a second time through its transpose: Q = an
+    orthonormal basis of span(Y) (Householder QR and the SVD of R, kept at the
+    numerical rank sigma_j(Y) > rank_rtol sigma_1(Y)), B = Q^T G = (G^T Q)^T
+    by adjoint local solves, B = U_B S V^T, and the basis Q U_B[:, :k] (the k
+    leading left singular vectors of Q Q^T G, sign-fixed).  Returns (basis,
+    singular values of B).
+    """
+    Qh, R = np.linalg.qr(Y, mode="reduced")
+    U, S, _ = np.linalg.svd(R)
+    r = int(np.count_nonzero(S > rank_rtol * S[0]))
+    Q = Qh @ U[:, :r]
+    C = adjoint_patch(a_flat, N, g, Q)
+    UB, SB, _ = np.linalg.svd(C.T, full_matrices=False)
+    return sign_fix(Q @ UB[:, :k]), SB
+
+
 def offline(a_flat, N, M, overlap, s, k, seed=2, omegas=None, full_basis=False, full_basis_boundary=False,
-            rank_tol=0.0):
+            rank_tol=0.0, two_pass=False):
     """Offline stage over all patches: snapshots Y_m, rank-k bases Q_m and singular values.
 
     omegas: optional list of explicit boundary sample matrices (one per patch);
@@ -189,7 +254,9 @@ def offline(a_flat, N, M, overlap, s, k, seed=2, omegas=None, full_basis=False, 
     nodes), with the basis orthonormalized by the range finder at full rank;
     the interior patches are sampled as usual.  rank_tol > 0 keeps, per
     sampled patch, the numerical rank of Y_m at tau = rank_tol sigma_1(Y_m)
-    (Def. num_rank), at most k, instead of k.
+    (Def. num_rank), at most k, instead of k.  two_pass=True builds each
+    sampled patch's basis by the two-pass randomized SVD (two_pass_basis; sv
+    are then the singular values of Q^T G, and rank_tol applies to them).
     """
     geo = patch_geometry(N, M, 0 if full_basis else overlap)
     geo0 = patch_geometry(N, M, 0) if full_basis_boundary else None
@@ -206,10 +273,11 @@ def offline(a_flat, N, M, overlap, s, k, seed=2, omegas=None, full_basis=False, 
         else:
             om = omegas[g["p"]] if omegas is not None else patch_omega(seed, g, s)
             Y = sample_patch(a_flat, N, g, om)
-            Q, sv = range_finder(Y, k)
+            basis = (lambda kk: two_pass_basis(a_flat, N, g, Y, kk)) if two_pass else (lambda kk: range_finder(Y, kk))
+            Q, sv = basis(k)
             kt = adaptive_rank(sv, k, rank_tol)
             if kt < k:
-                Q, sv = range_finder(Y, kt)
+                Q, sv = basis(kt)
         out.append(dict(geo=g, Y=Y, Q=Q, sv=sv))
     return out
 
