@@ -111,6 +111,14 @@ typedef int32_t msrs_status;
  * solution's restrictions, and the online solve reproduces the fine
  * discrete solution. */
 #define MSRS_FLAG_FULL_BASIS 32u
+/* elliptic, sampled patches (no full-basis flag): msrs_range_finder builds
+ * each basis by the two-pass randomized SVD -- the direct SVD of Q^T G_m, Q an
+ * orthonormal basis of span(Y_m) (the randomized SVD of Section 2.3 with
+ * G_m read a second time through its transpose): adjoint local solves
+ * G_m^T Q, which use the same factor (A_II is symmetric), the same sweeps
+ * and refinement.  Extra device memory: two arrays of Y's size and one of
+ * Omega's. */
+#define MSRS_FLAG_TWO_PASS 64u
 
 typedef struct msrs_ctx* msrs_handle;
 
@@ -250,9 +258,17 @@ msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, 
  * about sqrt(s u) sigma_1, u = 2^-53); a patch whose sigma_{k+1} lies below
  * 1e-4 sigma_1 takes a second pass on the rotated snapshots Y_m V, whose
  * graded Gram matrix resolves them down to about u sigma_1.
+ * With MSRS_FLAG_TWO_PASS: Q = the orthonormal basis of span(Y_m) at its
+ * numerical rank (sigma_j(Y_m) > max(rank_tol, 1e-12) sigma_1(Y_m), by the
+ * passes above), C = G_m^T Q by adjoint local solves (refined like the
+ * forward solves; msrs_get_stats then reports them), the eigenvectors V of
+ * C^T C, and the basis = Q V[:, :k], re-orthonormalised and sign-fixed; the
+ * singular values are those of Q^T G_m (zero past the rank), and k and
+ * rank_tol apply to them.
  * Errors: STATE; latched RANK if sigma_k(Y_m) <= 1e-13 sigma_1(Y_m) (the
- * snapshots have lower rank than k) or the orthonormalisation breaks down;
- * latched NONFINITE for non-finite snapshots.
+ * snapshots have lower rank than k; with MSRS_FLAG_TWO_PASS sigma_k(Q^T G_m))
+ * or the orthonormalisation breaks down; latched NONFINITE for non-finite
+ * snapshots; NOCONV from the adjoint refinement.
  */
 msrs_status msrs_range_finder(msrs_handle h, double* Q_out_dev, double* sv_out_dev);
 

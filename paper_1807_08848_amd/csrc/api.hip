@@ -202,11 +202,15 @@ msrs_status validate(const msrs_problem_desc* d, std::string& msg) {
             msg = "the constrained least-squares variant needs MSRS_FLAG_FULL_BASIS_BOUNDARY";
             return MSRS_ERR_ARG;
         }
+        if ((d->flags & MSRS_FLAG_TWO_PASS) && (d->flags & (MSRS_FLAG_FULL_BASIS_BOUNDARY | MSRS_FLAG_FULL_BASIS))) {
+            msg = "the two-pass range finder applies to sampled patches (no full-basis flags)";
+            return MSRS_ERR_ARG;
+        }
     } else {
         if (d->n_vel < 2 || d->n_vel > 64 || (d->n_vel & 1)) { msg = "n_vel must be even, 2..64"; return MSRS_ERR_ARG; }
         if (!(d->hg_g > -1.0 && d->hg_g < 1.0)) { msg = "hg_g must be in (-1, 1)"; return MSRS_ERR_ARG; }
-        if (d->flags & (MSRS_FLAG_CONSTRAINED_BC | MSRS_FLAG_FULL_BASIS_BOUNDARY)) {
-            msg = "MSRS_FLAG_FULL_BASIS_BOUNDARY and MSRS_FLAG_CONSTRAINED_BC are elliptic options";
+        if (d->flags & (MSRS_FLAG_CONSTRAINED_BC | MSRS_FLAG_FULL_BASIS_BOUNDARY | MSRS_FLAG_TWO_PASS)) {
+            msg = "MSRS_FLAG_FULL_BASIS_BOUNDARY, MSRS_FLAG_CONSTRAINED_BC and MSRS_FLAG_TWO_PASS are elliptic options";
             return MSRS_ERR_ARG;
         }
         if (!(d->eps > 0)) { msg = "eps must be positive"; return MSRS_ERR_ARG; }
@@ -310,28 +314,32 @@ namespace {
 // has converged (host checks between iterations); fixed_iters >= 0: exactly
 // that many iterations with no host synchronisation (converged patches skip
 // their work) and a device-side NOCONV check, the form a graph can capture.
-void sample_enqueue(Ctx* c, const double* omega_dev, int fixed_iters) {
-    for_patches(*c, [&](int p0, int p1) { launch_omega(*c, omega_dev, p0, p1); });
-    for_patches(*c, [&](int p0, int p1) { launch_lift(*c, p0, p1); });
+// adjQ != nullptr: the adjoint solves of the two-pass range finder instead
+// (source R_K^T q for the columns q of adjQ, zero boundary values; the
+// boundary values G^T q go to adjC in place of the restriction).
+void sample_enqueue(Ctx* c, const double* omega_dev, int fixed_iters, const double* adjQ = nullptr, double* adjC = nullptr) {
+    if (!adjQ) for_patches(*c, [&](int p0, int p1) { launch_omega(*c, omega_dev, p0, p1); });
+    for_patches(*c, [&](int p0, int p1) { launch_lift(*c, p0, p1, adjQ); });
     if (c->prec == MSRS_PREC_FP64) {
         for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, false, false); });
-        for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, true, 0); });
+        for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, true, 0, adjQ); });
         c->last_ir_iters = 0;
     } else if (fixed_iters >= 0) {
         launch_clear_conv(*c);
         for (int it = 0; it < fixed_iters; ++it) {
             for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true, it == 0); });
-            for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it); });
+            for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it, adjQ); });
         }
         launch_check_conv(*c);
         c->last_ir_iters = fixed_iters;
     } else {
         launch_clear_conv(*c);
         int it = 0;
-        const int first = std::min(c->ir_max, c->ir_hint);
+        int& hint = adjQ ? c->ir_hint_adj : c->ir_hint;
+        const int first = std::min(c->ir_max, hint);
         for (; it < first; ++it) {
             for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true, it == 0); });
-            for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it); });
+            for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it, adjQ); });
         }
         // continue until every patch has converged (one host check per extra iteration)
         std::vector<int32_t> conv(c->n_patches);
@@ -344,7 +352,7 @@ void sample_enqueue(Ctx* c, const double* omega_dev, int fixed_iters) {
                 break;
             }
             for_patches(*c, [&](int p0, int p1) { launch_sweep(*c, p0, p1, true, it == 0); });
-            for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it); });
+            for_patches(*c, [&](int p0, int p1) { launch_residual(*c, p0, p1, false, it, adjQ); });
             ++it;
         }
         std::vector<int32_t> iters(c->n_patches);
@@ -353,9 +361,23 @@ void sample_enqueue(Ctx* c, const double* omega_dev, int fixed_iters) {
         int mx = 0;
         for (int v : iters) mx = std::max(mx, v);
         c->last_ir_iters = it;
-        c->ir_hint = std::max(1, mx);
+        hint = std::max(1, mx);
     }
-    for_patches(*c, [&](int p0, int p1) { launch_restrict(*c, p0, p1); });
+    if (adjQ) for_patches(*c, [&](int p0, int p1) { launch_adj_flux(*c, p0, p1, adjQ, adjC); });
+    else for_patches(*c, [&](int p0, int p1) { launch_restrict(*c, p0, p1); });
+}
+
+// Stage a8: the range finder; with MSRS_FLAG_TWO_PASS the wide pass, the
+// adjoint solves (refinement as the forward's: fixed_iters as in
+// sample_enqueue) and the basis from Q^T G.
+void range_enqueue(Ctx* c, int fixed_iters) {
+    if (!c->two_pass) {
+        for_patches(*c, [&](int p0, int p1) { launch_range(*c, p0, p1); });
+        return;
+    }
+    for_patches(*c, [&](int p0, int p1) { launch_range_wide(*c, p0, p1); });
+    sample_enqueue(c, nullptr, fixed_iters, c->tp_Q, c->tp_C);
+    for_patches(*c, [&](int p0, int p1) { launch_range_two_pass(*c, p0, p1); });
 }
 
 void assemble_enqueue(Ctx* c, const double* coef_dev) {
@@ -470,8 +492,10 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->n_patches = (int)c->hp.size();
         // footprint
         const bool ir = c->prec == MSRS_PREC_FP32_IR;
+        c->two_pass = (desc->flags & MSRS_FLAG_TWO_PASS) != 0;
         int64_t need = c->aL_total * 8 + c->omega_total * 8 + c->x_total * 8 + (ir ? c->x_total * 4 : 0) +
                        c->E_total * (ir ? 4 : 8) + c->Y_total * 8 + c->Q_total * 8 + c->sv_total * 8;
+        if (c->two_pass) need += 2 * c->Y_total * 8 + c->omega_total * 8;
         need += (c->kind == kElliptic ? (int64_t)c->N * c->N : c->N) * 8;
         if (c->budget && (size_t)need > c->budget) {
             delete c;
@@ -497,6 +521,19 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->rf_second = dalloc<int32_t>(*c, c->n_patches);
         c->rf_small2 = dalloc<double>(*c, (int64_t)c->n_patches * 4096);
         c->rf_Z = dalloc<double>(*c, c->Y_total);
+        if (c->two_pass) {
+            // the wide pass: s basis columns at Y's offsets
+            std::vector<PatchDesc> w(c->hp);
+            for (auto& P : w) {
+                P.Q_off = P.Y_off;
+                P.ncols = P.kreq = P.s;
+            }
+            c->dp_wide = dalloc<PatchDesc>(*c, c->n_patches);
+            MSRS_HIP_CHECK(hipMemcpy(c->dp_wide, w.data(), sizeof(PatchDesc) * c->n_patches, hipMemcpyHostToDevice));
+            c->tp_Q = dalloc<double>(*c, c->Y_total);
+            c->tp_W = dalloc<double>(*c, c->Y_total);
+            c->tp_C = dalloc<double>(*c, c->omega_total);
+        }
         c->sv = dalloc<double>(*c, c->sv_total);
         int64_t rn_total = 0;
         for (auto& P : c->hp) rn_total += 2 * P.sp;
@@ -642,7 +679,7 @@ msrs_status msrs_range_finder(msrs_handle h, double* Q_out_dev, double* sv_out_d
     if (c->served) return fail(c, MSRS_ERR_STATE, "the handle is held by a server (destroy the server first)");
     if (!c->sampled) return fail(c, MSRS_ERR_STATE, "msrs_sample_local_solutions must come first");
     try {
-        for_patches(*c, [&](int p0, int p1) { launch_range(*c, p0, p1); });
+        range_enqueue(c, -1);
         if (Q_out_dev)
             MSRS_HIP_CHECK(hipMemcpyAsync(Q_out_dev, c->Q, c->Q_total * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         if (sv_out_dev)
@@ -669,12 +706,13 @@ msrs_status msrs_offline_graph_capture(msrs_handle h, const double* coef_dev) {
         drop_graph(c);
         MSRS_HIP_CHECK(hipStreamSynchronize(c->stream));
         const int iters = c->prec == MSRS_PREC_FP32_IR ? std::min(c->ir_max, c->ir_hint + 1) : 0;
+        const int iters_adj = c->prec == MSRS_PREC_FP32_IR ? std::min(c->ir_max, c->ir_hint_adj + 1) : 0;
         c->timing = false;   // no event nodes inside the graph
         MSRS_HIP_CHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         try {
             assemble_enqueue(c, coef_dev);
             sample_enqueue(c, nullptr, iters);
-            for_patches(*c, [&](int p0, int p1) { launch_range(*c, p0, p1); });
+            range_enqueue(c, iters_adj);
         } catch (const HipError&) {
             hipGraph_t g = nullptr;
             (void)hipStreamEndCapture(c->stream, &g);
@@ -683,7 +721,7 @@ msrs_status msrs_offline_graph_capture(msrs_handle h, const double* coef_dev) {
         }
         MSRS_HIP_CHECK(hipStreamEndCapture(c->stream, &c->graph));
         MSRS_HIP_CHECK(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
-        c->graph_iters = iters;
+        c->graph_iters = c->two_pass ? iters_adj : iters;   // the last solve of the step
     } catch (const HipError& e) {
         c->timing = timing;
         drop_graph(c);

@@ -164,6 +164,69 @@ __global__ __launch_bounds__(kThreads) void lift_kernel(const PatchDesc* pd, int
     partial_column_sums(ssum, m, sp, red, part + ((int64_t)p * maxch + blockIdx.y) * kMaxSamples);
 }
 
+// Adjoint source (two-pass range finder): f_I = R_K^T q at the interior nodes
+// of K_m (zero elsewhere and in the padding), q the columns of Qs (Y's
+// layout), into the line vectors X; per-sample sums of squares as lift_kernel.
+template <typename TX>
+__global__ __launch_bounds__(kThreads) void adj_lift_kernel(const PatchDesc* pd, int p0, const double* __restrict__ Qs,
+                                                            TX* __restrict__ X, double* __restrict__ part, int maxch) {
+    __shared__ double red[kThreads];
+    const int p = p0 + blockIdx.x;
+    const PatchDesc P = pd[p];
+    const int l0 = blockIdx.y * kChunkLines;
+    if (l0 >= P.nl) return;
+    const int l1 = min(P.nl, l0 + kChunkLines);
+    const int sp = P.sp, bp = P.bp, b = P.b;
+    const LineMap m(sp);
+    const int c = m.col;
+    const double* Qc = Qs + P.Y_off + (int64_t)c * P.nrows;
+    double ssum = 0.0;
+    for (int l = l0; l < l1; ++l) {
+        for (int i = m.row0; m.active && i < bp; i += m.rows) {
+            double v = 0.0;
+            if (i < b && c < P.s) {
+                const int row = k_row_of(P, i + 1, l + 1);
+                if (row >= 0) v = Qc[row];
+            }
+            X[P.x_off + (int64_t)l * bp * sp + (int64_t)i * sp + c] = (TX)v;
+            ssum += v * v;
+        }
+    }
+    partial_column_sums(ssum, m, sp, red, part + ((int64_t)p * maxch + blockIdx.y) * kMaxSamples);
+}
+
+// Boundary values of the adjoint (two-pass range finder): for boundary node
+// t of the buffered patch and sample column c, C = f_B - A_BI z, with z the
+// interior solution (x64) of A_II z = f_I and f = R_K^T q (q in Qs, Y's
+// layout); C in Omega's layout.  A_BI from the stencil of each interior
+// neighbour (A symmetric).  grid (patch, chunk of kThreads outputs).
+__global__ __launch_bounds__(kThreads) void adj_flux_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
+                                                            const double* __restrict__ x64_all, const double* __restrict__ Qs,
+                                                            double* __restrict__ C_all) {
+    const int p = p0 + blockIdx.x;
+    const PatchDesc P = pd[p];
+    const int o = blockIdx.y * kThreads + threadIdx.x;
+    if (o >= P.nb * P.s) return;
+    const int c = o / P.nb, t = o - c * P.nb;
+    int i, j;
+    phys_of_bidx(t, P.cx, P.cy, i, j);
+    const int pp = P.trans ? j : i, q = P.trans ? i : j;
+    const int row = k_row_of(P, pp, q);
+    double v = row >= 0 ? Qs[P.Y_off + (int64_t)c * P.nrows + row] : 0.0;
+    const double* aL = aL_all + P.a_off;
+    const double* X = x64_all + P.x_off;
+    const int64_t lstride = (int64_t)P.bp * P.sp;
+#pragma unroll
+    for (int dq = -1; dq <= 1; ++dq)
+#pragma unroll
+        for (int dp = -1; dp <= 1; ++dp) {
+            const int p2 = pp + dp, q2 = q + dq;
+            if (p2 < 1 || p2 > P.L - 1 || q2 < 1 || q2 > P.Qn - 1) continue;   // not an interior node
+            v -= q1_coef(aL, P.L, p2, q2, -dp, -dq) * X[(int64_t)(q2 - 1) * lstride + (int64_t)(p2 - 1) * P.sp + c];
+        }
+    C_all[P.om_off + (int64_t)c * P.nb + t] = v;
+}
+
 // ------------------------------------------------------------ FP64 residual (a6)
 // r = rhs - A x64 per interior unknown, grid (patch, chunk of lines); r is
 // written to x32 (the next correction's right-hand side) unless x32 is null.
@@ -277,11 +340,14 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const PatchDesc* pd,
 // into as many segments as the workgroup has threads to spare for its sample
 // count (2 at 32 samples): shorter dependent walks, more loads in flight.
 // Same arithmetic per node as the generic kernel.
+// ADJ (two-pass range finder): the adjoint system A_II z = f_I, f = R_K^T q
+// with q the columns of Qs: zero boundary values and the source f added.
 constexpr int kResThreads = kChunkLines * kMaxSamples;   // 8 lines x up to 64 samples
+template <bool ADJ>
 __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
                                                                    const double* __restrict__ om, const double* __restrict__ x64_all,
                                                                    float* __restrict__ x32_all, const int32_t* __restrict__ conv,
-                                                                   double* __restrict__ part, int maxch) {
+                                                                   double* __restrict__ part, int maxch, const double* __restrict__ Qs) {
     __shared__ double cell[(kChunkLines + 1) * (kMaxLine + 1)];
     __shared__ double red[kResThreads];
     const int p = p0 + blockIdx.x;
@@ -313,6 +379,7 @@ __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDe
             // u(q2, p2): interior nodes from x, nodes on the buffered patch's boundary from Omega
             auto u = [&](int q2, int p2) -> double {
                 if (p2 == 0 || p2 == L || q2 == 0 || q2 == Qn) {
+                    if constexpr (ADJ) return 0.0;
                     int ii, jj;
                     line_to_phys(P, p2, q2, ii, jj);
                     return O[(int64_t)c * P.nb + bidx_ccw(ii, jj, P.cx, P.cy)];
@@ -344,6 +411,10 @@ __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDe
                 r += (NW * k3) * wp[0];
                 r += ((NE + NW) * k6) * wp[1];
                 r += (NE * k3) * wp[2];
+                if constexpr (ADJ) {
+                    const int row = k_row_of(P, pp, q);
+                    if (row >= 0) r += Qs[P.Y_off + (int64_t)c * P.nrows + row];
+                }
                 if (R32) R32[(int64_t)(pp - 1) * sp] = (float)r;
                 ssum += r * r;
                 wm[0] = wm[1]; wm[1] = wm[2];
@@ -510,11 +581,14 @@ static int max_chunks(const Ctx& c, int p0, int p1) {
     return m;
 }
 
-void launch_lift(Ctx& c, int p0, int p1) {
+void launch_lift(Ctx& c, int p0, int p1, const double* adjQ) {
     StageTimer t(c, MSRS_K_LIFT);
     const bool ir = c.prec == MSRS_PREC_FP32_IR;
     const dim3 grid(p1 - p0, max_chunks(c, p0, p1));
-    if (c.kind == kElliptic) {
+    if (adjQ) {
+        if (ir) hipLaunchKernelGGL(adj_lift_kernel<float>, grid, dim3(kThreads), 0, c.stream, c.dp, p0, adjQ, c.x32, c.part, c.maxch);
+        else hipLaunchKernelGGL(adj_lift_kernel<double>, grid, dim3(kThreads), 0, c.stream, c.dp, p0, adjQ, c.x64, c.part, c.maxch);
+    } else if (c.kind == kElliptic) {
         if (ir) hipLaunchKernelGGL((lift_kernel<kElliptic, float>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x32, c.part, c.maxch);
         else hipLaunchKernelGGL((lift_kernel<kElliptic, double>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, c.part, c.maxch);
     } else {
@@ -525,15 +599,18 @@ void launch_lift(Ctx& c, int p0, int p1) {
                        (double*)nullptr, (int32_t*)nullptr, 0, 0.0, 0.0, c.dflags);
 }
 
-void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it) {
+void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it, const double* adjQ) {
     StageTimer t(c, MSRS_K_RESIDUAL);
     const double inv_eps = 1.0 / c.eps;
     int32_t* conv = stats_only ? nullptr : c.conv;
     float* x32 = stats_only ? nullptr : c.x32;
     const dim3 grid(p1 - p0, max_chunks(c, p0, p1));
-    if (c.kind == kElliptic)
-        hipLaunchKernelGGL(residual_ell_kernel, grid, dim3(kResThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.x64, x32, conv, c.part,
-                           c.maxch);
+    if (c.kind == kElliptic && adjQ)
+        hipLaunchKernelGGL(residual_ell_kernel<true>, grid, dim3(kResThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.x64, x32, conv,
+                           c.part, c.maxch, adjQ);
+    else if (c.kind == kElliptic)
+        hipLaunchKernelGGL(residual_ell_kernel<false>, grid, dim3(kResThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.x64, x32, conv,
+                           c.part, c.maxch, (const double*)nullptr);
     else
         hipLaunchKernelGGL((residual_kernel<kKinetic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), inv_eps,
                            c.x64, x32, conv, c.part, c.maxch);
@@ -550,6 +627,14 @@ void launch_restrict(Ctx& c, int p0, int p1) {
         hipLaunchKernelGGL((restrict_kernel<kElliptic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.x64, c.om, c.vw, c.Y);
     else
         hipLaunchKernelGGL((restrict_kernel<kKinetic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.x64, c.om, c.vw, c.Y);
+}
+
+void launch_adj_flux(Ctx& c, int p0, int p1, const double* Qs, double* C) {
+    StageTimer t(c, MSRS_K_RESTRICT);
+    int maxn = 0;
+    for (int p = p0; p < p1; ++p) maxn = std::max(maxn, c.hp[p].nb * c.hp[p].s);
+    const dim3 grid(p1 - p0, (maxn + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(adj_flux_kernel, grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.x64, Qs, C);
 }
 
 void launch_clear_conv(Ctx& c) {

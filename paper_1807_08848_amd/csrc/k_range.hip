@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
     // (pass 1: Z^T Z is graded; the relative test alone)
     double gtr = 0.0;
     for (int x = 0; x < s; ++x) gtr += G[x * LDG + x];
-    const double floor_abs = pass == 0 ? 1e-16 * gtr : 0.0;
+    const double floor_abs = pass != 1 ? 1e-16 * gtr : 0.0;
     if (tid == 0) rot = 0;
     __syncthreads();
     for (int sweep = 0; sweep < 30; ++sweep) {
@@ -341,16 +341,40 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
         }
         return;
     }
+    // pass 2 (two-pass range finder, G = (G^T Q)^T (G^T Q)): the eigenvectors
+    // themselves, the basis being Q V[:, :k]
     double* B = small + (int64_t)p * kSmall;
     for (int o = tid; o < kSmall; o += nth) {
         const int i = o / kRfMax, j = o % kRfMax;
         double v = 0.0;
         if (i < s && j < k) {
-            const double sg = sqrt(fmax(lam[perm[j]], 0.0));
+            const double sg = pass == 2 ? 1.0 : sqrt(fmax(lam[perm[j]], 0.0));
             v = sg > 0 ? V[i * LDG + perm[j]] / sg : 0.0;
         }
         B[o] = v;
     }
+}
+
+// Two-pass range finder: H = C^T C for C = G^T Q (nb x s per patch, Omega's
+// layout), one workgroup per patch, into the partials of row chunk 0 (the
+// other chunks of the patch zeroed), where the eigensolver sums them.
+__global__ __launch_bounds__(kThreads) void adj_gram_kernel(const PatchDesc* pd, int p0, const double* __restrict__ C_all,
+                                                            double* __restrict__ part, int maxrc) {
+    const int p = p0 + blockIdx.x;
+    const PatchDesc P = pd[p];
+    const int s = P.s, nb = P.nb, nch = (P.nrows + kRowChunk - 1) / kRowChunk;
+    const double* C = C_all + P.om_off;
+    double* out = part + (int64_t)p * maxrc * kSmall;
+    for (int o = threadIdx.x; o < s * s; o += kThreads) {
+        const int a = o / s, b = o - a * s;
+        if (b < a) continue;
+        double h = 0.0;
+        for (int t = 0; t < nb; ++t) h += C[(int64_t)a * nb + t] * C[(int64_t)b * nb + t];
+        out[a * kRfMax + b] = h;
+        out[b * kRfMax + a] = h;
+    }
+    for (int ch = 1; ch < nch; ++ch)
+        for (int o = threadIdx.x; o < s * s; o += kThreads) out[(int64_t)ch * kSmall + (o / s) * kRfMax + o % s] = 0.0;
 }
 
 // ---------------------------------------------------------------- Cholesky factor
@@ -578,8 +602,33 @@ __global__ __launch_bounds__(kThreads) void sign_apply_kernel(const PatchDesc* p
     }
 }
 
-void launch_range(Ctx& c, int p0, int p1) {
-    StageTimer t(c, MSRS_K_RANGE);
+// Cholesky-QR passes on W (-> Q, -> W where the second pass is needed) and
+// the sign fix into Q, over descriptors pd and buffers Q, W.
+static void range_tail(Ctx& c, int p0, int p1, PatchDesc* pd, double* Q, double* W) {
+    int maxrows = 0;
+    for (int p = p0; p < p1; ++p) maxrows = std::max(maxrows, c.hp[p].nrows);
+    const int np = p1 - p0;
+    const dim3 tall(np, (maxrows + kRowChunk - 1) / kRowChunk), one(np);
+    const int mrc = c.rf_maxrc;
+    hipStream_t st = c.stream;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int src = pass == 0 ? kW : kQ, dst = pass == 0 ? kQ : kW;
+        hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, pd, p0, src, c.Y, Q, W, c.rf_part, mrc,
+                           pass == 1 ? (const int32_t*)c.rf_skip : nullptr);
+        hipLaunchKernelGGL(chol_kernel, one, dim3(kThreads), 0, st, pd, p0, c.rf_part, mrc, c.rf_small, c.dflags, c.rf_skip, pass);
+        hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, pd, p0, src, dst, c.Y, Q, W, c.rf_small,
+                           pass == 1 ? (const int32_t*)c.rf_skip : nullptr);
+    }
+    // sign fix: W -> Q
+    hipLaunchKernelGGL(sign_partial_kernel, tall, dim3(kThreads), 0, st, pd, p0, W, Q, c.rf_skip, c.rf_pval, c.rf_pidx, mrc);
+    hipLaunchKernelGGL(sign_final_kernel, one, dim3(kRfMax), 0, st, pd, p0, W, Q, c.rf_skip, c.rf_pval, c.rf_pidx, mrc,
+                       c.rf_small);
+    hipLaunchKernelGGL(sign_apply_kernel, tall, dim3(kThreads), 0, st, pd, p0, W, Q, c.rf_skip, c.rf_small);
+}
+
+// The range finder over descriptors pd, into basis Q with workspace W, at
+// rank tolerance rank_tol.
+static void range_core(Ctx& c, int p0, int p1, PatchDesc* pd, double* Q, double* W, double rank_tol) {
     int maxrows = 0;
     for (int p = p0; p < p1; ++p) maxrows = std::max(maxrows, c.hp[p].nrows);
     const int np = p1 - p0;
@@ -587,36 +636,55 @@ void launch_range(Ctx& c, int p0, int p1) {
     const int mrc = c.rf_maxrc;
     hipStream_t st = c.stream;
     // snapshots: Gram, eigendecomposition, W = Y B
-    hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kY, c.Y, c.Q, c.rf_ws, c.rf_part, mrc,
+    hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, pd, p0, (int)kY, c.Y, Q, W, c.rf_part, mrc,
                        (const int32_t*)nullptr);
     int maxs = 0;
     for (int p = p0; p < p1; ++p) maxs = std::max(maxs, c.hp[p].s);
-    hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
-                       c.dflags, c.rank_tol, 0, c.rf_small2, c.rf_second);
+    hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, pd, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
+                       c.dflags, rank_tol, 0, c.rf_small2, c.rf_second);
     // second pass where Y^T Y does not resolve sigma_{k+1}: Z = Y V, Z^T Z, Jacobi
-    hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kY, (int)kZ, c.Y, c.Q, c.rf_ws, c.rf_small2,
+    hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, pd, p0, (int)kY, (int)kZ, c.Y, Q, W, c.rf_small2,
                        (const int32_t*)nullptr, c.rf_Z, (const int32_t*)c.rf_second, (const int32_t*)nullptr);
-    hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kZ, c.Y, c.Q, c.rf_ws, c.rf_part, mrc,
+    hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, pd, p0, (int)kZ, c.Y, Q, W, c.rf_part, mrc,
                        (const int32_t*)nullptr, (const double*)c.rf_Z, (const int32_t*)c.rf_second);
-    hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
-                       c.dflags, c.rank_tol, 1, c.rf_small2, c.rf_second);
+    hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, pd, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
+                       c.dflags, rank_tol, 1, c.rf_small2, c.rf_second);
     // W = Y B (first pass) or Z B (second pass)
-    hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kYZ, (int)kW, c.Y, c.Q, c.rf_ws, c.rf_small,
+    hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, pd, p0, (int)kYZ, (int)kW, c.Y, Q, W, c.rf_small,
                        (const int32_t*)nullptr, c.rf_Z, (const int32_t*)nullptr, (const int32_t*)c.rf_second);
-    // Cholesky-QR passes: W -> Q (-> W where the second pass is needed)
-    for (int pass = 0; pass < 2; ++pass) {
-        const int src = pass == 0 ? kW : kQ, dst = pass == 0 ? kQ : kW;
-        hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, src, c.Y, c.Q, c.rf_ws, c.rf_part, mrc,
-                           pass == 1 ? (const int32_t*)c.rf_skip : nullptr);
-        hipLaunchKernelGGL(chol_kernel, one, dim3(kThreads), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.dflags, c.rf_skip, pass);
-        hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, src, dst, c.Y, c.Q, c.rf_ws, c.rf_small,
-                           pass == 1 ? (const int32_t*)c.rf_skip : nullptr);
-    }
-    // sign fix: W -> Q
-    hipLaunchKernelGGL(sign_partial_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, c.rf_ws, c.Q, c.rf_skip, c.rf_pval, c.rf_pidx, mrc);
-    hipLaunchKernelGGL(sign_final_kernel, one, dim3(kRfMax), 0, st, c.dp, p0, c.rf_ws, c.Q, c.rf_skip, c.rf_pval, c.rf_pidx, mrc,
-                       c.rf_small);
-    hipLaunchKernelGGL(sign_apply_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, c.rf_ws, c.Q, c.rf_skip, c.rf_small);
+    range_tail(c, p0, p1, pd, Q, W);
+}
+
+void launch_range(Ctx& c, int p0, int p1) {
+    StageTimer t(c, MSRS_K_RANGE);
+    range_core(c, p0, p1, c.dp, c.Q, c.rf_ws, c.rank_tol);
+}
+
+// Wide pass: every patch at s columns (the wide descriptors place the basis
+// at Y's offsets), at the numerical rank sigma_j(Y) > 1e-12 sigma_1(Y) (or the
+// handle's tolerance if larger); the columns past the rank are zero.
+void launch_range_wide(Ctx& c, int p0, int p1) {
+    StageTimer t(c, MSRS_K_RANGE);
+    range_core(c, p0, p1, c.dp_wide, c.tp_Q, c.tp_W, std::max(c.rank_tol, 1e-12));
+}
+
+// H = (G^T Q)^T (G^T Q), its eigenvectors V (Jacobi, descending), the basis
+// Q V[:, :k] -> W, then Cholesky-QR and the sign fix into the handle's basis;
+// the singular values are those of Q^T G.
+void launch_range_two_pass(Ctx& c, int p0, int p1) {
+    StageTimer t(c, MSRS_K_RANGE);
+    int maxrows = 0, maxs = 0;
+    for (int p = p0; p < p1; ++p) maxrows = std::max(maxrows, c.hp[p].nrows), maxs = std::max(maxs, c.hp[p].s);
+    const int np = p1 - p0;
+    const dim3 tall(np, (maxrows + kRowChunk - 1) / kRowChunk), one(np);
+    const int mrc = c.rf_maxrc;
+    hipStream_t st = c.stream;
+    hipLaunchKernelGGL(adj_gram_kernel, one, dim3(kThreads), 0, st, c.dp, p0, c.tp_C, c.rf_part, mrc);
+    hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
+                       c.dflags, c.rank_tol, 2, c.rf_small2, c.rf_second);
+    hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kZ, (int)kW, c.Y, c.Q, c.rf_ws, c.rf_small,
+                       (const int32_t*)nullptr, c.tp_Q, (const int32_t*)nullptr, (const int32_t*)nullptr);
+    range_tail(c, p0, p1, c.dp, c.Q, c.rf_ws);
 }
 
 }  // namespace msrs

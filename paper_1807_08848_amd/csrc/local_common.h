@@ -17,9 +17,27 @@ __device__ __forceinline__ int bidx_ccw(int i, int j, int cx, int cy) {
     return 2 * cx + cy + (cy - j);
 }
 
+// Local physical node (i, j) of counter-clockwise boundary index t (the
+// inverse of bidx_ccw).
+__device__ __forceinline__ void phys_of_bidx(int t, int cx, int cy, int& i, int& j) {
+    if (t < cx) { i = t; j = 0; }
+    else if (t < cx + cy) { i = cx; j = t - cx; }
+    else if (t < 2 * cx + cy) { i = cx - (t - cx - cy); j = cy; }
+    else { i = 0; j = cy - (t - 2 * cx - cy); }
+}
+
 // physical local node of line coordinates (p, q)
 __device__ __forceinline__ void line_to_phys(const PatchDesc& P, int p, int q, int& i, int& j) {
     if (P.trans) { i = q; j = p; } else { i = p; j = q; }
+}
+
+// Row of the node at line coordinates (p, q) among the nodes of K_m
+// (row-major, (nH + 1)^2 rows: the rows of Y and Q), or -1 outside K_m.
+__device__ __forceinline__ int k_row_of(const PatchDesc& P, int p, int q) {
+    int i, j;
+    line_to_phys(P, p, q, i, j);
+    const int ii = i - (P.kx0 - P.x0), jj = j - (P.ky0 - P.y0);
+    return (ii >= 0 && ii <= P.nH && jj >= 0 && jj <= P.nH) ? jj * (P.nH + 1) + ii : -1;
 }
 
 __device__ __forceinline__ double a_cell(const double* aL, int L, int cr, int cp) { return aL[cr * L + cp]; }

@@ -90,6 +90,7 @@ struct Ctx {
     size_t budget = 0;
     int n_patches = 0;
     int ir_hint = 3;
+    int ir_hint_adj = 3;          // the same for the adjoint solves of the two-pass range finder
     int last_ir_iters = 0;
     std::string err;
 
@@ -125,6 +126,14 @@ struct Ctx {
     double* rf_small2 = nullptr;  // per patch 64 x 64: the first pass's eigenvectors (second pass only)
     double* rf_Z = nullptr;       // rotated snapshots Z = Y V (shape of Y; second pass only)
     int rf_maxrc = 1;             // row chunks per patch at most
+    // two-pass range finder (MSRS_FLAG_TWO_PASS): the wide pass's descriptors
+    // (basis at Y's offsets with s columns), its basis and workspace (shape of
+    // Y), and the adjoint boundary values G^T Q (shape of Omega)
+    bool two_pass = false;
+    PatchDesc* dp_wide = nullptr;
+    double* tp_Q = nullptr;
+    double* tp_W = nullptr;
+    double* tp_C = nullptr;
     double* coef_copy = nullptr;  // device copy of the coefficient field (traces)
     int32_t* iters = nullptr;     // per patch refinement iterations at convergence
     double* part = nullptr;       // per (patch, line chunk) partial column sums, 64 each
@@ -209,12 +218,19 @@ void launch_gather_elliptic(Ctx& c, const double* a, int p0, int p1);
 void launch_gather_kinetic(Ctx& c, const double* sigma, int p0, int p1);
 void launch_omega(Ctx& c, const double* user, int p0, int p1);
 void launch_philox_draw(uint64_t seed, int patch, int n_node, int n_sample, uint32_t* words, double* normals, hipStream_t st);
-void launch_lift(Ctx& c, int p0, int p1);
+// adjQ: the adjoint source f_I = R_K^T q, q the columns of adjQ (Y's layout)
+void launch_lift(Ctx& c, int p0, int p1, const double* adjQ = nullptr);
 void launch_factor(Ctx& c, int p0, int p1);
 void launch_sweep(Ctx& c, int p0, int p1, bool fp32, bool first);   // first: the first solve of a refinement
-void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it);
+void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it, const double* adjQ = nullptr);
 void launch_restrict(Ctx& c, int p0, int p1);
+void launch_adj_flux(Ctx& c, int p0, int p1, const double* Qs, double* C);   // C = f_B - A_BI z (Omega's layout)
 void launch_range(Ctx& c, int p0, int p1);
+// two-pass range finder: the wide pass (orthonormal basis of span(Y) at its
+// numerical rank into tp_Q), then, after the adjoint solves have written
+// G^T tp_Q into tp_C, the basis from the SVD of (G^T tp_Q)^T
+void launch_range_wide(Ctx& c, int p0, int p1);
+void launch_range_two_pass(Ctx& c, int p0, int p1);
 void launch_clear_conv(Ctx& c);
 void launch_check_conv(Ctx& c);
 

@@ -32,6 +32,7 @@ PREC_FP64, PREC_FP32_IR = 0, 1
 FLAG_FULL_BASIS_ENDS, FLAG_PER_PATCH_LAUNCH, FLAG_TIMING, FLAG_FULL_BASIS_BOUNDARY = 1, 2, 4, 8
 FLAG_CONSTRAINED_BC = 16
 FLAG_FULL_BASIS = 32
+FLAG_TWO_PASS = 64
 TUNE_SWEEP_COLS, TUNE_RECON_BATCH, TUNE_APPLY_BATCH, TUNE_FACTOR_SHARE = 0, 1, 2, 3
 TUNE_STAGE_OFFLINE, TUNE_STAGE_ONLINE = 0, 1
 TUNE_NAMES = {TUNE_SWEEP_COLS: "sweep_cols", TUNE_RECON_BATCH: "recon_batch", TUNE_APPLY_BATCH: "apply_batch",
