@@ -77,6 +77,20 @@ constexpr int factor_slots() {
     }
 }
 
+// Symmetric storage (elliptic FP32): the Schur blocks D_l are symmetric and
+// only the R (R + 1) / 2 upper tiles (ti <= tj) are held, round-robin over
+// the waves (slot q of wave w: upper tile q * 16 + w in row-major order).
+template <int R>
+constexpr int factor_sym_slots() { return (R * (R + 1) / 2 + kFactorWaves - 1) / kFactorWaves; }
+template <int R>
+__device__ __forceinline__ int factor_sym_tile(int q, int w) {
+    int rem = q * kFactorWaves + w, ti = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (ti == r && rem >= R - r) { rem -= R - r; ++ti; }
+    return ti < R ? ti * R + ti + rem : -1;
+}
+
 // Inverse of a 16 x 16 block (row-major in LDS, leading dimension LDA; the
 // inverse with LDD) by one wave: lane l
 // holds row l%16, columns 4(l/16)..4(l/16)+3; Gauss-Jordan without pivoting.
@@ -184,10 +198,15 @@ template <typename T, int KIND, int R, bool MID>
 __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw,
                                               double dx, double inv_eps, T* __restrict__ E, T* lds, double* cf,
                                               double* crow, int dir, int32_t* flags) {
-    constexpr int BP = 16 * R, LDE = BP + 1, NSLOT = factor_slots<R>();
+    // SYM: elliptic FP32, upper tiles only (the blocks are symmetric, and
+    // Gauss-Jordan keeps every block symmetric except those between pivoted
+    // and unpivoted indices, which are antisymmetric: A_ji = -A_ij^T)
+    constexpr bool SYM = KIND == kElliptic && sizeof(T) == 4;
+    constexpr int BP = 16 * R, LDE = BP + 1, NSLOT = SYM ? factor_sym_slots<R>() : factor_slots<R>();
     constexpr int NKS = BP / 4;
     typedef typename Mfma<T>::acc Acc;
-    const int tid0 = threadIdx.x, w = tid0 >> 6;
+    const int tid0 = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid0 >> 6);
+    auto tile_of = [&](int q) -> int { return SYM ? factor_sym_tile<R>(q, w) : factor_tile<R>(q, w); };
     // Lane-dependent indices are re-derived per block row and per panel from a
     // laundered thread id, so their address arithmetic is not hoisted and kept
     // live across the loops (register pressure).
@@ -288,7 +307,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
         auto schur = [&](bool init, bool term, bool kin_rev) {
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
-                const int idx = factor_tile<R>(q, w);
+                const int idx = tile_of(q);
                 if (idx < 0) continue;
                 const int ti = idx / R, tj = idx - ti * R;
                 const int j = 16 * tj + li;
@@ -378,7 +397,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
         auto publish = [&](int p, T* pc, T* pr) {
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
-                const int idx = factor_tile<R>(q, w);
+                const int idx = tile_of(q);
                 if (idx < 0) continue;
                 const int ti = idx / R, tj = idx - ti * R;
                 if (tj != p && ti != p) continue;
@@ -395,7 +414,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
             if constexpr (sizeof(T) == 4) {
 #pragma unroll
                 for (int q = 0; q < NSLOT; ++q) {
-                    if (factor_tile<R>(q, w) != p * (R + 1)) continue;
+                    if (tile_of(q) != p * (R + 1)) continue;
                     float a4[4];
 #pragma unroll
                     for (int t = 0; t < 4; ++t) a4[t] = tile[q][t];
@@ -411,7 +430,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
         auto row_panel = [&](int pn, const T* pr, T* xs, const T* dv) {
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
-                const int idx = factor_tile<R>(q, w);
+                const int idx = tile_of(q);
                 if (idx < 0) continue;
                 const int ti = idx / R, tj = idx - ti * R;
                 if (ti != pn || tj == pn) continue;
@@ -429,7 +448,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
         auto update = [&](int pn, const T* pc, const T* xs, const T* dv, bool set_diag) {
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
-                const int idx = factor_tile<R>(q, w);
+                const int idx = tile_of(q);
                 if (idx < 0) continue;
                 const int ti = idx / R, tj = idx - ti * R;
                 if (ti == pn) {
@@ -458,7 +477,97 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
                 }
             }
         };
-        if constexpr (sizeof(T) == 4) {
+        // SYM: the pivot step pn on upper tiles.  Publish: a tile of column pn
+        // (ti <= pn) gives Pc block ti and, transposed and negated, Pr block ti
+        // (A_{pn,ti} = -A_{ti,pn}^T: ti pivoted, pn not); a tile of row pn
+        // (tj > pn) gives Pr block tj and, transposed, Pc block tj (both
+        // unpivoted).  Row panel: X_j = Dinv A_{pn,j} for every j != pn, by the
+        // owner of the row tile (pn, j), j > pn (which becomes X_j), or of the
+        // column tile (j, pn), j < pn.  Update: column tiles -A_{i,pn} Dinv, the
+        // others A_ij -= A_{i,pn} X_j.
+        auto publish_sym = [&](int p, T* pc, T* pr) {
+#pragma unroll
+            for (int q = 0; q < NSLOT; ++q) {
+                const int idx = tile_of(q);
+                if (idx < 0) continue;
+                const int ti = idx / R, tj = idx - ti * R;
+                if (tj != p && ti != p) continue;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int r = Mfma<T>::row(lane, t);
+                    const T v = tile[q][t];
+                    if (tj == p) {
+                        pc[(16 * ti + r) * PCL + li] = v;
+                        if (ti < p) pr[li * PRL + 16 * ti + r] = -v;
+                    } else {
+                        pr[r * PRL + 16 * tj + li] = v;
+                        pc[(16 * tj + li) * PCL + r] = v;
+                    }
+                }
+            }
+        };
+        auto row_panel_sym = [&](int pn, const T* pr, T* xs, const T* dv) {
+#pragma unroll
+            for (int q = 0; q < NSLOT; ++q) {
+                const int idx = tile_of(q);
+                if (idx < 0) continue;
+                const int ti = idx / R, tj = idx - ti * R;
+                const int j = ti == pn ? tj : (tj == pn ? ti : -1);
+                if (j < 0 || j == pn) continue;
+                Acc x = Mfma<T>::zero();
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const int k = 4 * st + lk;
+                    x = Mfma<T>::step(dv[li * DVL + k], pr[k * PRL + 16 * j + li], x);
+                }
+                if (ti == pn) tile[q] = x;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) xs[Mfma<T>::row(lane, t) * PRL + 16 * j + li] = x[t];
+            }
+        };
+        auto update_sym = [&](int pn, const T* pc, const T* xs, const T* dv) {
+#pragma unroll
+            for (int q = 0; q < NSLOT; ++q) {
+                const int idx = tile_of(q);
+                if (idx < 0) continue;
+                const int ti = idx / R, tj = idx - ti * R;
+                if (ti == pn) continue;   // the new row (X) or the diagonal (Dinv)
+                if (tj == pn) {
+                    Acc x = Mfma<T>::zero();
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) {
+                        const int k = 4 * st + lk;
+                        x = Mfma<T>::step(-pc[(16 * ti + li) * PCL + k], dv[k * DVL + li], x);
+                    }
+                    tile[q] = x;
+                } else {
+                    Acc x = tile[q];
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) {
+                        const int k = 4 * st + lk;
+                        x = Mfma<T>::step(-pc[(16 * ti + li) * PCL + k], xs[k * PRL + 16 * tj + li], x);
+                    }
+                    tile[q] = x;
+                }
+            }
+        };
+        if constexpr (SYM) {
+            publish_sym(0, Pc, Pr);
+            invert_diag(0, Dv);
+            __syncthreads();
+            for (int pn = 0; pn < npan; ++pn) {
+                launder();
+                const int buf = pn & 1, nb = buf ^ 1;
+                row_panel_sym(pn, Pr + buf * 16 * PRL, Xs + buf * 16 * PRL, Dv + buf * 16 * DVL);
+                __syncthreads();
+                update_sym(pn, Pc + buf * BP * PCL, Xs + buf * 16 * PRL, Dv + buf * 16 * DVL);
+                if (pn + 1 < npan) {
+                    publish_sym(pn + 1, Pc + nb * BP * PCL, Pr + nb * 16 * PRL);
+                    invert_diag(pn + 1, Dv + nb * 16 * DVL);
+                }
+                __syncthreads();
+            }
+        } else if constexpr (sizeof(T) == 4) {
             publish(0, Pc, Pr);
             invert_diag(0, Dv);
             __syncthreads();
@@ -497,11 +606,14 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
         // the sweep's MFMA operand order
 #pragma unroll
         for (int q = 0; q < NSLOT; ++q) {
-            const int idx = factor_tile<R>(q, w);
+            const int idx = tile_of(q);
             if (idx < 0) continue;
             const int ti = idx / R, tj = idx - ti * R;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) Es[(16 * ti + Mfma<T>::row(lane, t)) * LDE + 16 * tj + li] = tile[q][t];
+            for (int t = 0; t < 4; ++t) {
+                Es[(16 * ti + Mfma<T>::row(lane, t)) * LDE + 16 * tj + li] = tile[q][t];
+                if (SYM && ti != tj) Es[(16 * tj + li) * LDE + 16 * ti + Mfma<T>::row(lane, t)] = tile[q][t];
+            }
         }
         __syncthreads();
         T* El = E + (int64_t)ln * BP * BP;
