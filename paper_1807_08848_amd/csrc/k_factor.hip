@@ -198,10 +198,10 @@ template <typename T, int KIND, int R, bool MID>
 __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw,
                                               double dx, double inv_eps, T* __restrict__ E, T* lds, double* cf,
                                               double* crow, int dir, int32_t* flags) {
-    // SYM: elliptic FP32, upper tiles only (the blocks are symmetric, and
+    // SYM: elliptic, upper tiles only (the blocks are symmetric, and
     // Gauss-Jordan keeps every block symmetric except those between pivoted
     // and unpivoted indices, which are antisymmetric: A_ji = -A_ij^T)
-    constexpr bool SYM = KIND == kElliptic && sizeof(T) == 4;
+    constexpr bool SYM = KIND == kElliptic;
     constexpr int BP = 16 * R, LDE = BP + 1, NSLOT = SYM ? factor_sym_slots<R>() : factor_slots<R>();
     constexpr int NKS = BP / 4;
     typedef typename Mfma<T>::acc Acc;
@@ -525,13 +525,21 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
                 for (int t = 0; t < 4; ++t) xs[Mfma<T>::row(lane, t) * PRL + 16 * j + li] = x[t];
             }
         };
-        auto update_sym = [&](int pn, const T* pc, const T* xs, const T* dv) {
+        // set_diag: the owner writes Dinv into the diagonal tile (FP64, whose
+        // inverse is formed in LDS; the FP32 owner inverted it in place)
+        auto update_sym = [&](int pn, const T* pc, const T* xs, const T* dv, bool set_diag) {
 #pragma unroll
             for (int q = 0; q < NSLOT; ++q) {
                 const int idx = tile_of(q);
                 if (idx < 0) continue;
                 const int ti = idx / R, tj = idx - ti * R;
-                if (ti == pn) continue;   // the new row (X) or the diagonal (Dinv)
+                if (ti == pn) {   // the new row (X) or the diagonal (Dinv)
+                    if (tj == pn && set_diag) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) tile[q][t] = dv[Mfma<T>::row(lane, t) * DVL + li];
+                    }
+                    continue;
+                }
                 if (tj == pn) {
                     Acc x = Mfma<T>::zero();
 #pragma unroll
@@ -551,7 +559,23 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
                 }
             }
         };
-        if constexpr (SYM) {
+        if constexpr (SYM && sizeof(T) == 8) {
+            for (int pn = 0; pn < npan; ++pn) {
+                launder();
+                const int buf = pn & 1;
+                T* pc = Pc + buf * BP * PCL;
+                T* pr = Pr + buf * 16 * PRL;
+                T* xs = Xs + buf * 16 * PRL;
+                T* dv = Dv + buf * 16 * DVL;
+                publish_sym(pn, pc, pr);
+                __syncthreads();
+                if (w == 0) inv16_wave<T, PCL, DVL>(pc + 16 * pn * PCL, dv, bad);
+                __syncthreads();
+                row_panel_sym(pn, pr, xs, dv);
+                __syncthreads();
+                update_sym(pn, pc, xs, dv, true);
+            }
+        } else if constexpr (SYM) {
             publish_sym(0, Pc, Pr);
             invert_diag(0, Dv);
             __syncthreads();
@@ -560,7 +584,7 @@ __device__ __forceinline__ void factor_mfma_body(const PatchDesc& P, const doubl
                 const int buf = pn & 1, nb = buf ^ 1;
                 row_panel_sym(pn, Pr + buf * 16 * PRL, Xs + buf * 16 * PRL, Dv + buf * 16 * DVL);
                 __syncthreads();
-                update_sym(pn, Pc + buf * BP * PCL, Xs + buf * 16 * PRL, Dv + buf * 16 * DVL);
+                update_sym(pn, Pc + buf * BP * PCL, Xs + buf * 16 * PRL, Dv + buf * 16 * DVL, false);
                 if (pn + 1 < npan) {
                     publish_sym(pn + 1, Pc + nb * BP * PCL, Pr + nb * 16 * PRL);
                     invert_diag(pn + 1, Dv + nb * 16 * DVL);
