@@ -430,10 +430,11 @@ msrs_status msrs_set_max_batch(msrs_handle h, int32_t max_batch);
 #define MSRS_TUNE_SWEEP_COLS   0   /* samples per sweep workgroup: 16, 32, 64 (FP64 path: at most 32) */
 #define MSRS_TUNE_RECON_BATCH  1   /* requests per reconstruction pass: 1, 2, 4, 8, 16 */
 #define MSRS_TUNE_APPLY_BATCH  2   /* requests per workgroup of the G_B product: 4, 8, 16 */
-/* factor workgroups a compute unit can hold (FP32 path): 1 (default,
- * registers for the shortest chain) or 2 (the
- * register budget of two resident workgroups: a slightly longer chain, half
- * the footprint, for several handles running at once) */
+/* factor workgroups a compute unit can hold (FP32 path): 2 (default: the
+ * register budget of two resident workgroups, so every chain of lines of a
+ * batch runs at once) or 1 (registers and scalar registers unconstrained: a
+ * unit holds one workgroup, and a batch of more chains than units runs in
+ * rounds) */
 #define MSRS_TUNE_FACTOR_SHARE 3
 msrs_status msrs_set_tuning(msrs_handle h, int32_t key, int32_t value);
 msrs_status msrs_get_tuning(msrs_handle h, int32_t key, int32_t* value);

@@ -583,6 +583,17 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
             std::reverse(items.begin() + c->n_patches, items.end());
             c->sweep_items = dalloc<int32_t>(*c, (int64_t)items.size());
             MSRS_HIP_CHECK(hipMemcpy(c->sweep_items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+            // the factor's chains (a half's lines of b x b inverses, b^3 each) in
+            // the same paired order
+            auto fcost = [&](int32_t v) {
+                const PatchDesc& P = c->hp[v >> 1];
+                const int m = P.nl / 2, nlines = (v & 1) ? P.nl - 1 - m : m;
+                return (double)nlines * P.bp * P.bp * P.bp;
+            };
+            std::stable_sort(items.begin(), items.end(), [&](int32_t a, int32_t b) { return fcost(a) > fcost(b); });
+            std::reverse(items.begin() + c->n_patches, items.end());
+            c->factor_items = dalloc<int32_t>(*c, (int64_t)items.size());
+            MSRS_HIP_CHECK(hipMemcpy(c->factor_items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         }
         c->dflags = dalloc<int32_t>(*c, kFlags);
         c->coef_copy = dalloc<double>(*c, c->kind == kElliptic ? (int64_t)c->N * c->N : c->N);

@@ -719,15 +719,22 @@ __global__ __launch_bounds__(kFactorThreads, SHARE == 2 ? 8 : 1) void factor2_ke
 // costliest patches first), so the long chains start first and the short ones
 // fill in behind them; a batch of several line lengths is then one launch on
 // the handle's stream, a single chain in a captured graph.
+// items (halves launch, optional): workgroup x runs the chain items[x] =
+// (patch << 1 | half), half 1 the bottom one, in place of (plist[x],
+// blockIdx.y); the list is sorted by cost with its second half reversed, so
+// that with two resident workgroups per compute unit a long chain shares its
+// unit with a short one.
 template <typename T, int KIND, int RMAX, bool MID, int SHARE>
 __global__ __launch_bounds__(kFactorThreads, SHARE == 2 ? 8 : 1) void factor_any_kernel(const PatchDesc* pd, const int32_t* __restrict__ plist,
                                                                     const double* __restrict__ aL_all, const double* __restrict__ vw,
-                                                                    double dx, double inv_eps, T* __restrict__ E_all, int32_t* flags) {
+                                                                    double dx, double inv_eps, T* __restrict__ E_all, int32_t* flags,
+                                                                    const int32_t* __restrict__ items) {
     __shared__ T lds[factor_lds_elems<RMAX>()];
     __shared__ double cf[2 * kMaxLine];
     __shared__ double crow[2 * (kMaxLine + 1)];
-    const PatchDesc P = pd[plist[blockIdx.x]];
-    const int dir = MID ? 0 : (blockIdx.y == 0 ? 1 : -1);
+    const int item = (!MID && items) ? items[blockIdx.x] : 0;
+    const PatchDesc P = pd[(!MID && items) ? item >> 1 : plist[blockIdx.x]];
+    const int dir = MID ? 0 : ((items ? (item & 1) : (int)blockIdx.y) == 0 ? 1 : -1);
     const double* aL = aL_all + P.a_off;
     T* E = E_all + P.E_off;
 #define MSRS_FB(RR) factor_mfma_body<T, KIND, RR, MID>(P, aL, vw, dx, inv_eps, E, lds, cf, crow, dir, flags)
@@ -845,16 +852,17 @@ static bool launch_factor_pair(Ctx& c, int ra, int rb) {
 // One launch for the halves and one for the middle lines over every patch
 // of plist (any mix of line-tile counts).
 template <typename T, int KIND>
-static void launch_factor_any(Ctx& c, const int32_t* plist, int n) {
+static void launch_factor_any(Ctx& c, const int32_t* plist, int n, const int32_t* items) {
     constexpr int RMAX = KIND == kElliptic ? 8 : 4;
     const double inv_eps = 1.0 / c.eps;
     T* E = (T*)c.E;
+    const dim3 halves = items ? dim3(2 * n) : dim3(n, 2);
 #define MSRS_FANY(SH)                                                                                                        \
     do {                                                                                                                     \
-        hipLaunchKernelGGL((factor_any_kernel<T, KIND, RMAX, false, SH>), dim3(n, 2), dim3(kFactorThreads), 0, c.stream, c.dp, \
-                           plist, c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags);                                                \
+        hipLaunchKernelGGL((factor_any_kernel<T, KIND, RMAX, false, SH>), halves, dim3(kFactorThreads), 0, c.stream, c.dp,    \
+                           plist, c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags, items);                                         \
         hipLaunchKernelGGL((factor_any_kernel<T, KIND, RMAX, true, SH>), dim3(n), dim3(kFactorThreads), 0, c.stream, c.dp,     \
-                           plist, c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags);                                                \
+                           plist, c.aL, c.vw, dx_of(c), inv_eps, E, c.dflags, (const int32_t*)nullptr);                       \
     } while (0)
     if constexpr (sizeof(T) == 4) {
         if (c.factor_share == 2) MSRS_FANY(2);
@@ -892,11 +900,11 @@ void launch_factor(Ctx& c, int p0, int p1) {
         return;
     const bool ir = c.prec == MSRS_PREC_FP32_IR;
     if (c.kind == kElliptic) {
-        if (ir) launch_factor_any<float, kElliptic>(c, c.lpt, c.n_patches);
-        else launch_factor_any<double, kElliptic>(c, c.lpt, c.n_patches);
+        if (ir) launch_factor_any<float, kElliptic>(c, c.lpt, c.n_patches, c.factor_items);
+        else launch_factor_any<double, kElliptic>(c, c.lpt, c.n_patches, c.factor_items);
     } else {
-        if (ir) launch_factor_any<float, kKinetic>(c, c.lpt, c.n_patches);
-        else launch_factor_any<double, kKinetic>(c, c.lpt, c.n_patches);
+        if (ir) launch_factor_any<float, kKinetic>(c, c.lpt, c.n_patches, c.factor_items);
+        else launch_factor_any<double, kKinetic>(c, c.lpt, c.n_patches, c.factor_items);
     }
 }
 

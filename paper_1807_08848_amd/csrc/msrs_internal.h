@@ -142,6 +142,7 @@ struct Ctx {
     int rgroup_n[9] = {};
     int32_t* lpt = nullptr;       // every patch, costliest first (factor launches over mixed line lengths)
     int32_t* sweep_items = nullptr;   // 2 n_patches (patch << 1 | half): sweep workgroup order, costliest paired with cheapest
+    int32_t* factor_items = nullptr;  // 2 n_patches (patch << 1 | half): factor chains in the same paired order, by factor cost
     bool ranks_stale = false;     // the device descriptors hold ranks the host copy has not seen
     int maxch = 1;                // line chunks per patch at most
 
@@ -154,7 +155,7 @@ struct Ctx {
     // online
     int max_batch = 64;
     int sweep_cols32 = 64;       // samples per sweep workgroup (FP32), 16 | value
-    int factor_share = 1;        // factor workgroups per compute unit the kernel's registers allow (1 or 2)
+    int factor_share = 2;        // factor workgroups per compute unit the kernel's registers allow (1 or 2)
     int sweep_cols64 = 32;       // samples per sweep workgroup (FP64)
     int recon_batch = 8;         // requests per reconstruction pass (1, 2, 4, 8, 16)
     int apply_batch = 8;         // requests per G_B workgroup (4, 8, 16)
