@@ -231,7 +231,10 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
         // nothing yet and is written, not accumulated (pre64 stays zero).
         launder();
         constexpr bool kAccum = PHASE == 1;
-        double pre64[NCT][4] = {};
+        // the FP64 iterate of a back line: loaded one step ahead where the
+        // registers allow it (up to 32 samples), else at the top of its own step
+        constexpr bool kAhead = NCT <= 2;
+        double pre64[NCT][4] = {}, pre64n[kAhead ? NCT : 1][4] = {};
         load_A(E + (int64_t)m * BP * BP);
         const bool acc64 = X64 && half == 0;   // line m's iterate is updated once, by the top half
         if (kAccum && acc64) load_64(X64 + m * lstride, pre64);
@@ -249,6 +252,9 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
             const int l1 = m - dir;
             load_line(X + l1 * lstride, rv);
             if (KIND == kElliptic && tid <= b) crow = aL[(dir > 0 ? m : l1) * L + tid];
+            if constexpr (kAhead) {
+                if (kAccum && X64) load_64(X64 + l1 * lstride, pre64n);
+            }
         }
         lds_barrier();
         mfma();
@@ -262,15 +268,26 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
             launder();
             const int ln = m - dir * (k + 1);
             const bool more = k + 1 < nst;
-            // this line's FP64 iterate: consumed at the end of the step, so the
-            // coupling, the barriers and the products hide the load
-            if (kAccum && X64) load_64(X64 + ln * lstride, pre64);
+            // this line's FP64 iterate: loaded a step ahead (kAhead), or now and
+            // consumed at the end of the step, the coupling, the barriers and
+            // the products hiding the load
+            if constexpr (kAhead) {
+#pragma unroll
+                for (int c = 0; c < NCT; ++c)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) pre64[c][t] = pre64n[c][t];
+            } else {
+                if (kAccum && X64) load_64(X64 + ln * lstride, pre64);
+            }
             T rvn[RPT];
             double crown = 0.0;
             if (more) {
                 const int l2 = ln - dir;
                 load_line(X + l2 * lstride, rvn);                                     // y of the next step
                 if (KIND == kElliptic && tid <= b) crown = aL[(dir > 0 ? ln : l2) * L + tid];
+                if constexpr (kAhead) {
+                    if (kAccum && X64) load_64(X64 + l2 * lstride, pre64n);
+                }
             }
             if (KIND == kElliptic && tid <= b) craw[tid] = crow * (-1.0 / 3.0);
             lds_barrier();
