@@ -259,7 +259,7 @@ msrs_status msrs_sample_local_solutions(msrs_handle h, const double* omega_dev, 
  * 1e-4 sigma_1 takes a second pass on the rotated snapshots Y_m V, whose
  * graded Gram matrix resolves them down to about u sigma_1.
  * With MSRS_FLAG_TWO_PASS: Q = the orthonormal basis of span(Y_m) at its
- * numerical rank (sigma_j(Y_m) > max(rank_tol, 1e-12) sigma_1(Y_m), by the
+ * numerical rank (sigma_j(Y_m) > 1e-12 sigma_1(Y_m), by the
  * passes above), C = G_m^T Q by adjoint local solves (refined like the
  * forward solves; msrs_get_stats then reports them), the eigenvectors V of
  * C^T C, and the basis = Q V[:, :k], re-orthonormalised and sign-fixed; the

@@ -661,11 +661,12 @@ void launch_range(Ctx& c, int p0, int p1) {
 }
 
 // Wide pass: every patch at s columns (the wide descriptors place the basis
-// at Y's offsets), at the numerical rank sigma_j(Y) > 1e-12 sigma_1(Y) (or the
-// handle's tolerance if larger); the columns past the rank are zero.
+// at Y's offsets), at the numerical rank sigma_j(Y) > 1e-12 sigma_1(Y) (the
+// handle's rank tolerance applies to the two-pass singular values instead);
+// the columns past the rank are zero.
 void launch_range_wide(Ctx& c, int p0, int p1) {
     StageTimer t(c, MSRS_K_RANGE);
-    range_core(c, p0, p1, c.dp_wide, c.tp_Q, c.tp_W, std::max(c.rank_tol, 1e-12));
+    range_core(c, p0, p1, c.dp_wide, c.tp_Q, c.tp_W, 1e-12);
 }
 
 // H = (G^T Q)^T (G^T Q), its eigenvectors V (Jacobi, descending), the basis

@@ -27,7 +27,8 @@ FLAG_TWO_PASS = 64
 
 
 def _check(cfg, out, tol_y):
-    ref = E.offline(cfg["coef"], cfg["N"], cfg["M"], cfg["overlap"], cfg["s"], cfg["k"], seed=cfg["seed"], two_pass=True)
+    ref = E.offline(cfg["coef"], cfg["N"], cfg["M"], cfg["overlap"], cfg["s"], cfg["k"], seed=cfg["seed"], two_pass=True,
+                    rank_tol=cfg.get("rank_tol", 0.0))
     for p, r in enumerate(ref):
         assert rel(out["Y"][p], r["Y"]) < tol_y, p
         k = r["Q"].shape[1]
@@ -67,6 +68,20 @@ def test_two_pass_periodic_128_and_projection_error(gpu, prec):
         e2 = np.linalg.norm(G - out["Q"][p] @ (out["Q"][p].T @ G))
         e1 = np.linalg.norm(G - one["Q"][p] @ (one["Q"][p].T @ G))
         assert e2 <= e1 * (1 + 1e-8), (p, e2, e1)
+
+
+def test_two_pass_with_a_rank_tolerance(gpu):
+    """rank_tol applies to the two-pass singular values (those of Q^T G): each
+    patch keeps the numerical rank of Q^T G at rank_tol sigma_1, at most k."""
+    # the singular values of Q^T G of these patches fall slowly (0.33-0.40 sigma_1
+    # at j = 10); 0.45 keeps 3 to 6 columns, the nearest one 2e-3 sigma_1 away
+    cfg = dict(configs.small_elliptic(N=64, M=2, delta=8, s=12, k=10, coef="lognormal"), rank_tol=0.45)
+    print("[two-pass] rank_tol 0.45", flush=True)
+    out = run(cfg, FP64, flags=FLAG_TWO_PASS)
+    ref = _check(cfg, out, 1e-11)
+    ranks = [r["Q"].shape[1] for r in ref]
+    assert ranks == [inf.n_cols for inf in out["infos"]]
+    assert min(ranks) < cfg["k"]
 
 
 def test_two_pass_flag_is_refused_where_it_does_not_apply(gpu):
