@@ -1,6 +1,7 @@
 // Multi-RHS block sweeps of the local solves (stage a5): forward and back
 // substitution through the explicit inverses E_l, products on MFMA.  The
 // operator's block structure is described in k_local.hip.
+#include <type_traits>
 #include "local_common.h"
 
 namespace msrs {
@@ -47,6 +48,9 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
     typedef typename Vec16<T>::type V;
     constexpr int VN = Vec16<T>::n;
     constexpr int BP = 16 * R, NKS = 4 * R, NSC = 16 * NCT;
+    struct alignas(sizeof(T) * NCT) YRow { T v[NCT]; };
+    // ybuf element (row i, column j of the chunk): column tiles innermost
+    auto yix = [](int i, int j) { return i * NSC + (j & 15) * NCT + (j >> 4); };
     constexpr int DI = kSweepThreads / NSC;          // rows between a thread's elements
     constexpr int RPT = (BP + DI - 1) / DI;          // elements per thread
     const int tid = threadIdx.x, lane = tid & 63, rt = tid >> 6;
@@ -96,16 +100,21 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
             for (int u = 0; u < VN; ++u) aC[q * VN + u] = v[u];
         }
     };
+    // B operands: the NCT column tiles of a lane's k row are adjacent in ybuf
+    // (yix), one vector read per k step, issued a step ahead of its products
     auto mfma = [&]() {
         const int lli = llane & 15, llk = llane >> 4;
 #pragma unroll
         for (int c = 0; c < NCT; ++c) acc[c] = Mfma<T>::zero();
         if (mf) {
+            const T* yb = ybuf + llk * NSC + lli * NCT;     // k row 4 kk + llk at yb + 4 kk NSC
+            YRow bc = *reinterpret_cast<const YRow*>(yb), bn;
 #pragma unroll
             for (int kk = 0; kk < NKS; ++kk) {
-                const T* yb = ybuf + (4 * kk + llk) * NSC + lli;
+                if (kk + 1 < NKS) bn = *reinterpret_cast<const YRow*>(yb + 4 * (kk + 1) * NSC);
 #pragma unroll
-                for (int c = 0; c < NCT; ++c) acc[c] = Mfma<T>::step(aC[kk], yb[16 * c], acc[c]);
+                for (int c = 0; c < NCT; ++c) acc[c] = Mfma<T>::step(aC[kk], bc.v[c], acc[c]);
+                bc = bn;
             }
         }
     };
@@ -121,7 +130,7 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
                 dst[c][t] = g64[(uint32_t)(i * sp + j)];
             }
     };
-    auto store_acc = [&](T* gdst, double* g64, const double (&pre64)[NCT][4]) {
+    auto store_acc = [&](T* gdst, double* g64, const double (&pre64)[NCT][4], bool to_wbuf) {
         const int lli = llane & 15;
         if (mf) {
 #pragma unroll
@@ -130,7 +139,7 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
                 for (int t = 0; t < 4; ++t) {
                     const int i = 16 * rt + Mfma<T>::row(llane, t), j = 16 * c + lli;
                     const T v = acc[c][t];
-                    wbuf[i * NSC + j] = v;
+                    if (to_wbuf) wbuf[i * NSC + j] = v;
                     if (gdst) gdst[(uint32_t)(i * sp + j)] = v;
                     if (g64) g64[(uint32_t)(i * sp + j)] = pre64[c][t] + (double)v;
                 }
@@ -150,6 +159,71 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
                    cp * (double)src[ip * NSC + j];
         } else {
             return -(low ? cvp[i] : cvm[i]) * (double)src[i * NSC + j];
+        }
+    };
+
+    // Register-resident coupling (FP32 elliptic).  A line vector of a step
+    // lives in the MFMA accumulator layout: element (c, t) of a lane is row
+    // 16 rt + 4 (lane / 16) + t, column 16 c + lane % 16 of the chunk.  The
+    // coupling of row i takes rows i - 1, i, i + 1 of the product: rows inside
+    // the lane's four come from its registers, the rows just above and below
+    // them from the edge rows (= 0 and 3 mod 4) that every lane puts into wbuf
+    // (column tiles innermost, as in ybuf).
+    constexpr bool RC = sizeof(T) == 4 && KIND == kElliptic;
+    // (the back half with an FP64 iterate to accumulate keeps the LDS form:
+    // the iterate's registers do not fit beside the accumulators)
+    constexpr bool RC_BACK = PHASE != 1;
+    const int rtc = rt < R ? rt : R - 1;
+    // (the lane's row and column offsets come from the laundered lane index,
+    // so that they are recomputed per line rather than held in registers)
+    // a line in the accumulator layout (waves past the row tiles: a copy of the last tile)
+    auto ld_acc_line = [&](const T* Xl, T (&dst)[NCT][4]) {
+        const int q4 = 4 * (llane >> 4), lq = llane & 15;
+#pragma unroll
+        for (int c = 0; c < NCT; ++c)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) dst[c][t] = Xl[(uint32_t)((16 * rtc + q4 + t) * sp + 16 * c + lq)];
+    };
+    auto put_halo = [&]() {
+        const int q4 = 4 * (llane >> 4), lq = llane & 15;
+        if (mf) {
+            YRow a, z;
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) { a.v[c] = acc[c][0]; z.v[c] = acc[c][3]; }
+            *reinterpret_cast<YRow*>(wbuf + yix(16 * rt + q4, lq)) = a;
+            *reinterpret_cast<YRow*>(wbuf + yix(16 * rt + q4 + 3, lq)) = z;
+        }
+    };
+    // y over the lane's elements: r - C w with sub, else C w, C the coupling
+    // block of the cell row in craw (the same expression and order as
+    // couple()); rows at or past b zero.  y goes to ybuf
+    // (toy: the next product's B operand) and, with glob, to gdst.
+    auto couple_rc = [&](const T (&r)[NCT][4], bool sub, T* gdst, bool toy, auto glob) {
+        if (!mf) return;
+        const int q4 = 4 * (llane >> 4), lq = llane & 15;
+        const int i0r = 16 * rt + q4;
+        const YRow hm = *reinterpret_cast<const YRow*>(wbuf + yix(i0r > 0 ? i0r - 1 : 0, lq));
+        const YRow hp = *reinterpret_cast<const YRow*>(wbuf + yix(i0r + 4 < BP ? i0r + 4 : BP - 1, lq));
+        double cr[5];
+#pragma unroll
+        for (int u = 0; u < 5; ++u) cr[u] = craw[i0r + u];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int i = i0r + t;
+            const double cm = i > 0 ? cr[t] : 0.0;
+            const double cp = i < b - 1 ? cr[t + 1] : 0.0;
+            YRow yr;
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) {
+                const double wm = (double)(t > 0 ? acc[c][t > 0 ? t - 1 : 0] : hm.v[c]);
+                const double wp = (double)(t < 3 ? acc[c][t < 3 ? t + 1 : 3] : hp.v[c]);
+                const double cw = 0.5 * (cr[t] + cr[t + 1]) * (double)acc[c][t] + cm * wm + cp * wp;
+                const double v = sub ? (double)r[c][t] - cw : cw;
+                const T y = i < b ? (T)v : T(0);
+                yr.v[c] = y;
+                if constexpr (decltype(glob)::value) gdst[(uint32_t)(i * sp + 16 * c + lq)] = y;
+            }
+            if (toy) *reinterpret_cast<YRow*>(ybuf + yix(i, lq)) = yr;
         }
     };
 
@@ -179,48 +253,87 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
         // shared cell row are loaded during the step before, after its products
         // (so that the products' operand waits never cover them), E_nx likewise
         auto sub_of = [&](int k) { return k + 1 < nst || half == 0; };   // the top's last step carries r_m
-        load_line(X + ln0 * lstride, rvA);                 // y_{ln0} = r_{ln0}
+        if constexpr (RC) {
+            {
+                T r0[RPT];
+                load_line(X + ln0 * lstride, r0);                 // y_{ln0} = r_{ln0}
 #pragma unroll
-        for (int e = 0; e < RPT; ++e) {
-            const int i = li0 + e * DI;
-            if (BP % DI == 0 || i < BP) ybuf[i * NSC + ljj] = rvA[e];
-        }
-        load_A(E + (int64_t)ln0 * BP * BP);
-        double crA = 0.0, crB = 0.0;
-        if (sub_of(0)) load_line(X + (ln0 + dir) * lstride, rvA);
-        if (KIND == kElliptic) crA = aL[(dir > 0 ? ln0 + 1 : ln0) * L + min(tid, b)];
-        lds_barrier();
-        auto step = [&](int k, T (&rc)[RPT], T (&rn)[RPT], double& cc, double& cn) {
-            launder();
-            const int ln = ln0 + dir * k, nx = ln + dir;
-            const bool more = k + 1 < nst;
-            const bool sub = sub_of(k);
-            mfma();                                                                   // w = E_ln y_ln
-            // r of the next step, its cell row and E (unconditional, clamped to
-            // lines that exist when there is no next step)
-            load_line(X + ((more && sub_of(k + 1)) ? nx + dir : nx) * lstride, rn);
-            if (KIND == kElliptic) cn = aL[(more ? (dir > 0 ? nx + 1 : nx) : (dir > 0 ? ln + 1 : ln)) * L + min(tid, b)];
-            load_A(E + (int64_t)(more ? nx : ln) * BP * BP);
-            store_acc(nullptr, nullptr, nopre);
-            if (KIND == kElliptic && tid <= b) craw[tid] = cc * (-1.0 / 3.0);
+                for (int e = 0; e < RPT; ++e) {
+                    const int i = li0 + e * DI;
+                    if (BP % DI == 0 || i < BP) ybuf[yix(i, ljj)] = r0[e];
+                }
+            }
+            T rcA[NCT][4] = {}, rcB[NCT][4] = {};
+            load_A(E + (int64_t)ln0 * BP * BP);
+            double crA = 0.0, crB = 0.0;
+            if (sub_of(0)) ld_acc_line(X + (ln0 + dir) * lstride, rcA);
+            crA = aL[(dir > 0 ? ln0 + 1 : ln0) * L + min(tid, b)];
             lds_barrier();
-            T* dst = more ? X + nx * lstride : TWh;
+            auto step = [&](int k, T (&rc)[NCT][4], T (&rn)[NCT][4], double& cc, double& cn) {
+                launder();
+                const int ln = ln0 + dir * k, nx = ln + dir;
+                const bool more = k + 1 < nst;
+                const bool sub = sub_of(k);
+                mfma();                                                               // w = E_ln y_ln
+                cn = aL[(more ? (dir > 0 ? nx + 1 : nx) : (dir > 0 ? ln + 1 : ln)) * L + min(tid, b)];
+                load_A(E + (int64_t)(more ? nx : ln) * BP * BP);                     // E of the next step
+                put_halo();
+                if (tid <= b) craw[tid] = cc * (-1.0 / 3.0);
+                lds_barrier();
+                couple_rc(rc, sub, more ? X + nx * lstride : TWh, more, std::true_type{});
+                // r of the next step, after the coupling (its registers are free
+                // then), consumed after the next products
+                ld_acc_line(X + ((more && sub_of(k + 1)) ? nx + dir : nx) * lstride, rn);
+                lds_barrier();
+            };
+            for (int k = 0; k < nst; k += 2) {
+                step(k, rcA, rcB, crA, crB);
+                if (k + 1 < nst) step(k + 1, rcB, rcA, crB, crA);
+            }
+        } else {
+            load_line(X + ln0 * lstride, rvA);                 // y_{ln0} = r_{ln0}
 #pragma unroll
             for (int e = 0; e < RPT; ++e) {
                 const int i = li0 + e * DI;
-                if (BP % DI == 0 || i < BP) {
-                    const double cw = couple(wbuf, i, ljj, low);
-                    const double v = sub ? (double)rc[e] - cw : cw;
-                    const T y = i < b ? (T)v : T(0);
-                    dst[(uint32_t)(i * sp + ljj)] = y;
-                    if (more) ybuf[i * NSC + ljj] = y;
-                }
+                if (BP % DI == 0 || i < BP) ybuf[yix(i, ljj)] = rvA[e];
             }
+            load_A(E + (int64_t)ln0 * BP * BP);
+            double crA = 0.0, crB = 0.0;
+            if (sub_of(0)) load_line(X + (ln0 + dir) * lstride, rvA);
+            if (KIND == kElliptic) crA = aL[(dir > 0 ? ln0 + 1 : ln0) * L + min(tid, b)];
             lds_barrier();
-        };
-        for (int k = 0; k < nst; k += 2) {
-            step(k, rvA, rvB, crA, crB);
-            if (k + 1 < nst) step(k + 1, rvB, rvA, crB, crA);
+            auto step = [&](int k, T (&rc)[RPT], T (&rn)[RPT], double& cc, double& cn) {
+                launder();
+                const int ln = ln0 + dir * k, nx = ln + dir;
+                const bool more = k + 1 < nst;
+                const bool sub = sub_of(k);
+                mfma();                                                                   // w = E_ln y_ln
+                // r of the next step, its cell row and E (unconditional, clamped to
+                // lines that exist when there is no next step)
+                load_line(X + ((more && sub_of(k + 1)) ? nx + dir : nx) * lstride, rn);
+                if (KIND == kElliptic) cn = aL[(more ? (dir > 0 ? nx + 1 : nx) : (dir > 0 ? ln + 1 : ln)) * L + min(tid, b)];
+                load_A(E + (int64_t)(more ? nx : ln) * BP * BP);
+                store_acc(nullptr, nullptr, nopre, true);
+                if (KIND == kElliptic && tid <= b) craw[tid] = cc * (-1.0 / 3.0);
+                lds_barrier();
+                T* dst = more ? X + nx * lstride : TWh;
+#pragma unroll
+                for (int e = 0; e < RPT; ++e) {
+                    const int i = li0 + e * DI;
+                    if (BP % DI == 0 || i < BP) {
+                        const double cw = couple(wbuf, i, ljj, low);
+                        const double v = sub ? (double)rc[e] - cw : cw;
+                        const T y = i < b ? (T)v : T(0);
+                        dst[(uint32_t)(i * sp + ljj)] = y;
+                        if (more) ybuf[yix(i, ljj)] = y;
+                    }
+                }
+                lds_barrier();
+            };
+            for (int k = 0; k < nst; k += 2) {
+                step(k, rvA, rvB, crA, crB);
+                if (k + 1 < nst) step(k + 1, rvB, rvA, crB, crA);
+            }
         }
     } else {
         // ---- middle line, then the back half; step k solves line
@@ -229,84 +342,157 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
         // loaded one step ahead, E_ln during the step before.
         // PHASE 2 is the first solve of a refinement: the FP64 iterate holds
         // nothing yet and is written, not accumulated (pre64 stays zero).
-        launder();
-        constexpr bool kAccum = PHASE == 1;
-        // the FP64 iterate of a back line: loaded one step ahead where the
-        // registers allow it (up to 32 samples), else at the top of its own step
-        constexpr bool kAhead = NCT <= 2;
-        double pre64[NCT][4] = {}, pre64n[kAhead ? NCT : 1][4] = {};
-        load_A(E + (int64_t)m * BP * BP);
-        const bool acc64 = X64 && half == 0;   // line m's iterate is updated once, by the top half
-        if (kAccum && acc64) load_64(X64 + m * lstride, pre64);
-#pragma unroll
-        for (int e = 0; e < RPT; ++e) {
-            const int i = li0 + e * DI;
-            if (BP % DI == 0 || i < BP) {
-                const double v = (double)TW[(uint32_t)(i * sp + ljj)] - (double)TW[lstride + (uint32_t)(i * sp + ljj)];
-                ybuf[i * NSC + ljj] = i < b ? (T)v : T(0);
-            }
-        }
-        const int nst = half == 0 ? m : nl - 1 - m;
-        const bool low = half != 0;   // top: Up_l x_{l+1}; bottom: Low_l x_{l-1}
-        if (nst > 0) {
-            const int l1 = m - dir;
-            load_line(X + l1 * lstride, rv);
-            if (KIND == kElliptic && tid <= b) crow = aL[(dir > 0 ? m : l1) * L + tid];
-            if constexpr (kAhead) {
-                if (kAccum && X64) load_64(X64 + l1 * lstride, pre64n);
-            }
-        }
-        lds_barrier();
-        mfma();
-        if (nst > 0) load_A(E + (int64_t)(m - dir) * BP * BP);        // the first back line, one step ahead
-        // x_m (identical in both halves).  With an FP64 iterate (refinement) the
-        // FP32 solution is not stored: the iterate takes it, and the line
-        // vectors are next overwritten by the residual.
-        store_acc(half == 0 && !X64 ? X + m * lstride : nullptr, acc64 ? X64 + m * lstride : nullptr, pre64);
-        lds_barrier();
-        for (int k = 0; k < nst; ++k) {
+        if constexpr (RC && RC_BACK) {
             launder();
-            const int ln = m - dir * (k + 1);
-            const bool more = k + 1 < nst;
-            // this line's FP64 iterate: loaded a step ahead (kAhead), or now and
-            // consumed at the end of the step, the coupling, the barriers and
-            // the products hiding the load
-            if constexpr (kAhead) {
-#pragma unroll
-                for (int c = 0; c < NCT; ++c)
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) pre64[c][t] = pre64n[c][t];
-            } else {
-                if (kAccum && X64) load_64(X64 + ln * lstride, pre64);
-            }
-            T rvn[RPT];
-            double crown = 0.0;
-            if (more) {
-                const int l2 = ln - dir;
-                load_line(X + l2 * lstride, rvn);                                     // y of the next step
-                if (KIND == kElliptic && tid <= b) crown = aL[(dir > 0 ? ln : l2) * L + tid];
-                if constexpr (kAhead) {
-                    if (kAccum && X64) load_64(X64 + l2 * lstride, pre64n);
-                }
-            }
-            if (KIND == kElliptic && tid <= b) craw[tid] = crow * (-1.0 / 3.0);
-            lds_barrier();
+            constexpr bool kAccum = PHASE == 1;
+            constexpr bool kAhead = NCT <= 2;
+            double pre64[NCT][4] = {}, pre64n[kAhead ? NCT : 1][4] = {};
+            load_A(E + (int64_t)m * BP * BP);
+            const bool acc64 = X64 && half == 0;   // line m's iterate is updated once, by the top half
+            if (kAccum && acc64) load_64(X64 + m * lstride, pre64);
 #pragma unroll
             for (int e = 0; e < RPT; ++e) {
                 const int i = li0 + e * DI;
                 if (BP % DI == 0 || i < BP) {
-                    const double v = (double)rv[e] - couple(wbuf, i, ljj, low);
-                    ybuf[i * NSC + ljj] = i < b ? (T)v : T(0);
+                    const double v = (double)TW[(uint32_t)(i * sp + ljj)] - (double)TW[lstride + (uint32_t)(i * sp + ljj)];
+                    ybuf[yix(i, ljj)] = i < b ? (T)v : T(0);
+                }
+            }
+            const int nst = half == 0 ? m : nl - 1 - m;
+            T rv2[NCT][4] = {};
+            double crow2 = 0.0;
+            if (nst > 0) {
+                const int l1 = m - dir;
+                ld_acc_line(X + l1 * lstride, rv2);
+                if (tid <= b) crow2 = aL[(dir > 0 ? m : l1) * L + tid];
+                if constexpr (kAhead) {
+                    if (kAccum && X64) load_64(X64 + l1 * lstride, pre64n);
                 }
             }
             lds_barrier();
-            mfma();                                                                    // x_ln = E_ln z
-            if (more) load_A(E + (int64_t)(ln - dir) * BP * BP);                     // E of the next line
-            store_acc(X64 ? nullptr : X + ln * lstride, X64 ? X64 + ln * lstride : nullptr, pre64);
-#pragma unroll
-            for (int e = 0; e < RPT; ++e) rv[e] = rvn[e];
-            crow = crown;
+            mfma();
+            if (nst > 0) load_A(E + (int64_t)(m - dir) * BP * BP);        // the first back line, one step ahead
+            store_acc(half == 0 && !X64 ? X + m * lstride : nullptr, acc64 ? X64 + m * lstride : nullptr, pre64, false);
+            put_halo();
+            // the cell row of the first back step's coupling: every read of craw
+            // comes after the barrier that follows its write
+            if (tid <= b) craw[tid] = crow2 * (-1.0 / 3.0);
             lds_barrier();
+            for (int k = 0; k < nst; ++k) {
+                launder();
+                const int ln = m - dir * (k + 1);
+                const bool more = k + 1 < nst;
+                couple_rc(rv2, true, nullptr, true, std::false_type{});              // z = y_ln - C x_{ln + dir}
+                // after the coupling (its registers are free then): the next
+                // step's y and cell row; this line's FP64 iterate (consumed after
+                // the products) a step ahead where the registers allow it
+                if constexpr (kAhead) {
+#pragma unroll
+                    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) pre64[c][t] = pre64n[c][t];
+                }
+                double crown = 0.0;
+                if (more) {
+                    const int l2 = ln - dir;
+                    ld_acc_line(X + l2 * lstride, rv2);                               // y of the next step
+                    if (tid <= b) crown = aL[(dir > 0 ? ln : l2) * L + tid];
+                    if constexpr (kAhead) {
+                        if (kAccum && X64) load_64(X64 + l2 * lstride, pre64n);
+                    }
+                }
+                lds_barrier();
+                if constexpr (!kAhead) {
+                    if (kAccum && X64) load_64(X64 + ln * lstride, pre64);
+                }
+                mfma();                                                                // x_ln = E_ln z
+                if (more) load_A(E + (int64_t)(ln - dir) * BP * BP);                 // E of the next line
+                store_acc(X64 ? nullptr : X + ln * lstride, X64 ? X64 + ln * lstride : nullptr, pre64, false);
+                put_halo();
+                // the couplings of this step were read before the barrier above
+                if (more && tid <= b) craw[tid] = crown * (-1.0 / 3.0);
+                lds_barrier();
+            }
+        } else {
+            launder();
+            constexpr bool kAccum = PHASE == 1;
+            // the FP64 iterate of a back line: loaded one step ahead where the
+            // registers allow it (up to 32 samples), else at the top of its own step
+            constexpr bool kAhead = NCT <= 2;
+            double pre64[NCT][4] = {}, pre64n[kAhead ? NCT : 1][4] = {};
+            load_A(E + (int64_t)m * BP * BP);
+            const bool acc64 = X64 && half == 0;   // line m's iterate is updated once, by the top half
+            if (kAccum && acc64) load_64(X64 + m * lstride, pre64);
+#pragma unroll
+            for (int e = 0; e < RPT; ++e) {
+                const int i = li0 + e * DI;
+                if (BP % DI == 0 || i < BP) {
+                    const double v = (double)TW[(uint32_t)(i * sp + ljj)] - (double)TW[lstride + (uint32_t)(i * sp + ljj)];
+                    ybuf[yix(i, ljj)] = i < b ? (T)v : T(0);
+                }
+            }
+            const int nst = half == 0 ? m : nl - 1 - m;
+            const bool low = half != 0;   // top: Up_l x_{l+1}; bottom: Low_l x_{l-1}
+            if (nst > 0) {
+                const int l1 = m - dir;
+                load_line(X + l1 * lstride, rv);
+                if (KIND == kElliptic && tid <= b) crow = aL[(dir > 0 ? m : l1) * L + tid];
+                if constexpr (kAhead) {
+                    if (kAccum && X64) load_64(X64 + l1 * lstride, pre64n);
+                }
+            }
+            lds_barrier();
+            mfma();
+            if (nst > 0) load_A(E + (int64_t)(m - dir) * BP * BP);        // the first back line, one step ahead
+            // x_m (identical in both halves).  With an FP64 iterate (refinement) the
+            // FP32 solution is not stored: the iterate takes it, and the line
+            // vectors are next overwritten by the residual.
+            store_acc(half == 0 && !X64 ? X + m * lstride : nullptr, acc64 ? X64 + m * lstride : nullptr, pre64, true);
+            lds_barrier();
+            for (int k = 0; k < nst; ++k) {
+                launder();
+                const int ln = m - dir * (k + 1);
+                const bool more = k + 1 < nst;
+                // this line's FP64 iterate: loaded a step ahead (kAhead), or now and
+                // consumed at the end of the step, the coupling, the barriers and
+                // the products hiding the load
+                if constexpr (kAhead) {
+#pragma unroll
+                    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) pre64[c][t] = pre64n[c][t];
+                } else {
+                    if (kAccum && X64) load_64(X64 + ln * lstride, pre64);
+                }
+                T rvn[RPT];
+                double crown = 0.0;
+                if (more) {
+                    const int l2 = ln - dir;
+                    load_line(X + l2 * lstride, rvn);                                     // y of the next step
+                    if (KIND == kElliptic && tid <= b) crown = aL[(dir > 0 ? ln : l2) * L + tid];
+                    if constexpr (kAhead) {
+                        if (kAccum && X64) load_64(X64 + l2 * lstride, pre64n);
+                    }
+                }
+                if (KIND == kElliptic && tid <= b) craw[tid] = crow * (-1.0 / 3.0);
+                lds_barrier();
+#pragma unroll
+                for (int e = 0; e < RPT; ++e) {
+                    const int i = li0 + e * DI;
+                    if (BP % DI == 0 || i < BP) {
+                        const double v = (double)rv[e] - couple(wbuf, i, ljj, low);
+                        ybuf[yix(i, ljj)] = i < b ? (T)v : T(0);
+                    }
+                }
+                lds_barrier();
+                mfma();                                                                    // x_ln = E_ln z
+                if (more) load_A(E + (int64_t)(ln - dir) * BP * BP);                     // E of the next line
+                store_acc(X64 ? nullptr : X + ln * lstride, X64 ? X64 + ln * lstride : nullptr, pre64, true);
+#pragma unroll
+                for (int e = 0; e < RPT; ++e) rv[e] = rvn[e];
+                crow = crown;
+                lds_barrier();
+            }
         }
     }
 }
@@ -319,7 +505,7 @@ __global__ __launch_bounds__(kSweepThreads) __attribute__((amdgpu_waves_per_eu(s
                                                               T* __restrict__ X_all, double* __restrict__ X64_all, T* __restrict__ TW_all,
                                                               const int32_t* __restrict__ conv, const int32_t* __restrict__ items,
                                                               int32_t* flags) {
-    __shared__ T ybuf[kMaxLine * 16 * NCT];
+    __shared__ __align__(16) T ybuf[kMaxLine * 16 * NCT];
     __shared__ T wbuf[kMaxLine * 16 * NCT];
     __shared__ double craw[kMaxLine + 1];
     __shared__ double cvp[kMaxLine], cvm[kMaxLine];
