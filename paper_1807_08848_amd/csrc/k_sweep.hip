@@ -130,19 +130,29 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
                 dst[c][t] = g64[(uint32_t)(i * sp + j)];
             }
     };
+    // (each destination's test taken once, outside the element loops: tests per
+    // element left the memory-counter waits at their merge points conservative)
     auto store_acc = [&](T* gdst, double* g64, const double (&pre64)[NCT][4], bool to_wbuf) {
         const int lli = llane & 15;
-        if (mf) {
+        if (!mf) return;
+        if (to_wbuf) {
 #pragma unroll
             for (int c = 0; c < NCT; ++c)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int i = 16 * rt + Mfma<T>::row(llane, t), j = 16 * c + lli;
-                    const T v = acc[c][t];
-                    if (to_wbuf) wbuf[i * NSC + j] = v;
-                    if (gdst) gdst[(uint32_t)(i * sp + j)] = v;
-                    if (g64) g64[(uint32_t)(i * sp + j)] = pre64[c][t] + (double)v;
-                }
+                for (int t = 0; t < 4; ++t) wbuf[(16 * rt + Mfma<T>::row(llane, t)) * NSC + 16 * c + lli] = acc[c][t];
+        }
+        if (gdst) {
+#pragma unroll
+            for (int c = 0; c < NCT; ++c)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) gdst[(uint32_t)((16 * rt + Mfma<T>::row(llane, t)) * sp + 16 * c + lli)] = acc[c][t];
+        }
+        if (g64) {
+#pragma unroll
+            for (int c = 0; c < NCT; ++c)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    g64[(uint32_t)((16 * rt + Mfma<T>::row(llane, t)) * sp + 16 * c + lli)] = pre64[c][t] + (double)acc[c][t];
         }
     };
     // coupling block between two adjacent lines applied to column j of src,
@@ -453,15 +463,27 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
                 launder();
                 const int ln = m - dir * (k + 1);
                 const bool more = k + 1 < nst;
-                // this line's FP64 iterate: loaded a step ahead (kAhead), or now and
-                // consumed at the end of the step, the coupling, the barriers and
-                // the products hiding the load
                 if constexpr (kAhead) {
 #pragma unroll
                     for (int c = 0; c < NCT; ++c)
 #pragma unroll
                         for (int t = 0; t < 4; ++t) pre64[c][t] = pre64n[c][t];
-                } else {
+                }
+                if (KIND == kElliptic && tid <= b) craw[tid] = crow * (-1.0 / 3.0);
+                lds_barrier();
+#pragma unroll
+                for (int e = 0; e < RPT; ++e) {
+                    const int i = li0 + e * DI;
+                    if (BP % DI == 0 || i < BP) {
+                        const double v = (double)rv[e] - couple(wbuf, i, ljj, low);
+                        ybuf[yix(i, ljj)] = i < b ? (T)v : T(0);
+                    }
+                }
+                // after the coupling (fewer registers live than during it): this
+                // line's FP64 iterate where it is not loaded a step ahead (the
+                // products hide it; it is consumed after them), and the next step's
+                // y and cell row
+                if constexpr (!kAhead) {
                     if (kAccum && X64) load_64(X64 + ln * lstride, pre64);
                 }
                 T rvn[RPT];
@@ -472,16 +494,6 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
                     if (KIND == kElliptic && tid <= b) crown = aL[(dir > 0 ? ln : l2) * L + tid];
                     if constexpr (kAhead) {
                         if (kAccum && X64) load_64(X64 + l2 * lstride, pre64n);
-                    }
-                }
-                if (KIND == kElliptic && tid <= b) craw[tid] = crow * (-1.0 / 3.0);
-                lds_barrier();
-#pragma unroll
-                for (int e = 0; e < RPT; ++e) {
-                    const int i = li0 + e * DI;
-                    if (BP % DI == 0 || i < BP) {
-                        const double v = (double)rv[e] - couple(wbuf, i, ljj, low);
-                        ybuf[yix(i, ljj)] = i < b ? (T)v : T(0);
                     }
                 }
                 lds_barrier();
