@@ -342,6 +342,34 @@ def test_sweep_width_and_offline_autotune_keep_results(gpu):
         pr.range_finder()        # the tuner left the handle sampled
 
 
+def test_seven_tile_lines_at_every_sweep_width(gpu):
+    """Line-tile count 7 (the 112 x 112 centre patch of a 3 x 3 layout with
+    24-cell buffers; the others have 6) at 64 samples, through each sweep width
+    (16, 32 and 64 samples per workgroup, the last one the register-coupled
+    FP32 sweeps): snapshots, singular values and bases against the oracle, and
+    the global solution at the widest."""
+    from paper_1807_08848_amd import msrs
+    cfg = configs.small_elliptic(N=192, M=3, delta=24, s=64, k=8, coef="lognormal")
+    ref = _oracle_elliptic(cfg)
+    u_or = E.online(cfg["N"], cfg["M"], ref, cfg["coef"], cfg["phi"])
+    k = cfg["k"]
+    for sc in (16, 32, 64):
+        out = run(cfg, FP32_IR, phi=cfg["phi"] if sc == 64 else None, tuning={msrs.TUNE_SWEEP_COLS: sc})
+        assert max(-(-inf.line_len // 16) for inf in out["infos"]) == 7
+        assert out["stats"].max_rel_residual <= 1e-10
+        for p, r in enumerate(ref):
+            # 64 samples reach sigma_64 ~ 1e-9 sigma_1 here: the singular values
+            # within Weyl's bound plus the Gram resolution (gram_sv_bar)
+            assert rel(out["Y"][p], r["Y"]) < 1e-8, (sc, p)
+            assert np.all(np.abs(out["sv"][p] - r["sv"]) <= gram_sv_bar(out["Y"][p], r["Y"], r["sv"])), (sc, p)
+            Qg = out["Q"][p]
+            assert np.abs(Qg.T @ Qg - np.eye(k)).max() < 1e-12, (sc, p)
+            if (r["sv"][k - 1] - r["sv"][k]) / r["sv"][0] >= 1e-3:
+                assert sin_max_angle(r["Q"], Qg) <= 1e-6, (sc, p)
+        if sc == 64:
+            assert E.relative_l2(out["u"][0], u_or) <= 1e-6
+
+
 def test_offline_graph_replays_match_eager(gpu):
     """The captured offline step replays to the eager results (every replay, with
     eager torch work and synchronisations between replays) and reads the current
