@@ -1,8 +1,8 @@
 // Range finder of the snapshots (stage a8): the QR at the end of
 // RanLocalSolu and the randomized range finder of Section 2.3, in FP64.
 //
-// Per patch: G = Y^T Y; cyclic Jacobi eigendecomposition G = V diag(lambda)
-// V^T, so sigma_j(Y) = sqrt(lambda_j) and Y V_j / sigma_j are the left
+// Per patch: G = Y^T Y; eigendecomposition G = V diag(lambda) V^T (Householder
+// tridiagonalisation and implicit QL), so sigma_j(Y) = sqrt(lambda_j) and Y V_j / sigma_j are the left
 // singular vectors; the k leading ones are formed and re-orthonormalised by
 // up to two Cholesky-QR passes (G' = W^T W = L L^T, Q = W L^{-T}; the second
 // only where the first one's G' was not already within 1e-4 of I).  This
@@ -22,7 +22,7 @@
 // Tall work (Gram matrices, products with the small s x k / k x k factors,
 // the column argmax) runs over (patch, chunk of kRowChunk rows) workgroups with
 // per-chunk partials reduced per patch in a fixed order, on FP64 MFMA; the
-// small dense work (Jacobi, Cholesky) runs one workgroup per patch.
+// small dense work (eigensolvers, Cholesky) runs one workgroup per patch.
 #include "device_common.h"
 
 namespace msrs {
@@ -153,9 +153,91 @@ __device__ __forceinline__ void rr_pair(int i, int st, int nm1, int& a, int& b) 
     b = max(u, v);
 }
 
-// One workgroup per patch: G = sum of partials, cyclic Jacobi (round-robin
-// pairs, two-sided updates on 2x2 blocks), eigenvalues sorted descending,
-// singular values, relative gap, and B = V[:, :k] / sigma -> small[p] (s x k).
+// The tail of both eigensolvers, from the eigenvalues on G's diagonal and the
+// eigenvectors in V's columns (leading dimension ldg): descending order,
+// singular values, rank, the second-pass decision, relative gap, and B -> small
+// (pass 0: V[:, :k] / sigma; pass 2: V[:, :k]) or V -> small2 (all s columns,
+// for Z = Y V).  Every thread of the workgroup calls it.
+__device__ void eig_finish(PatchDesc* pd, int p, const PatchDesc& P, const double* G, const double* V, int LDG, int* perm,
+                           double* lam, int* kshared_p, int* second_sp, double* __restrict__ small, double* __restrict__ sv_all,
+                           double* __restrict__ gap, int32_t* flags, double rank_tol, int pass, double* __restrict__ small2,
+                           int32_t* __restrict__ second) {
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int s = P.s, kreq = P.kreq;
+    int& kshared = *kshared_p;
+    int& second_s = *second_sp;
+    // descending order by rank: eigenvalue i goes to the number of eigenvalues
+    // above it, ties by index (a NaN ranks as -inf, so the ranks stay a
+    // permutation)
+    if (tid < s) {
+        const double gi = G[tid * LDG + tid];
+        const double li = (gi == gi) ? gi : -INFINITY;
+        int r = 0;
+        for (int j = 0; j < s; ++j) {
+            const double gj = G[j * LDG + j];
+            const double lj = (gj == gj) ? gj : -INFINITY;
+            r += (lj > li) || (lj == li && j < tid);
+        }
+        perm[r] = tid;
+        lam[tid] = gi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double* svp = sv_all + P.sv_off;
+        for (int i = 0; i < s; ++i) svp[i] = sqrt(fmax(lam[perm[i]], 0.0));
+        const double s1 = svp[0];
+        // rank: the requested one, or the numerical rank at rank_tol (the count of
+        // singular values above rank_tol sigma_1), between 1 and the requested one;
+        // the later kernels of the range finder read it from the descriptor
+        int kk = kreq;
+        if (rank_tol > 0.0 && P.sampled) {
+            kk = 0;
+            while (kk < kreq && svp[kk] > rank_tol * s1) ++kk;
+            kk = max(kk, 1);
+        }
+        if (kk != P.ncols) pd[p].ncols = kk;
+        kshared = kk;
+        const double sk = svp[kk - 1];
+        const double next = svp[min(kk, s - 1)];
+        const bool again = pass == 0 && P.sampled && isfinite(s1) && s1 > 0.0 &&
+                           (!(next >= kResolve * s1) || (rank_tol > 0.0 && rank_tol < kResolve));
+        second_s = again ? 1 : 0;
+        if (pass == 0) second[p] = again ? 1 : 0;
+        // the k-th direction must be resolved: a rank deficiency of the
+        // snapshots themselves (sigma_k at rounding level) after the second pass
+        if (!again && !(sk > 1e-13 * s1)) raise_flag(flags, 2);
+        if (!isfinite(s1)) raise_flag(flags, 4);
+        gap[p] = (kk < s) ? (sk - svp[kk]) / s1 : 1.0;
+    }
+    __syncthreads();
+    const int k = kshared;
+    if (second_s) {
+        // V in descending order for Z = Y V (all s columns)
+        double* V1 = small2 + (int64_t)p * kSmall;
+        for (int o = tid; o < kSmall; o += nth) {
+            const int i = o / kRfMax, j = o % kRfMax;
+            V1[o] = (i < s && j < s) ? V[i * LDG + perm[j]] : 0.0;
+        }
+        return;
+    }
+    // pass 2 (two-pass range finder, G = (G^T Q)^T (G^T Q)): the eigenvectors
+    // themselves, the basis being Q V[:, :k]
+    double* B = small + (int64_t)p * kSmall;
+    for (int o = tid; o < kSmall; o += nth) {
+        const int i = o / kRfMax, j = o % kRfMax;
+        double v = 0.0;
+        if (i < s && j < k) {
+            const double sg = pass == 2 ? 1.0 : sqrt(fmax(lam[perm[j]], 0.0));
+            v = sg > 0 ? V[i * LDG + perm[j]] / sg : 0.0;
+        }
+        B[o] = v;
+    }
+}
+
+// The second pass's eigensolver (Z^T Z is graded: Jacobi keeps its small
+// eigenvalues to high relative accuracy).  One workgroup per patch: G = sum of
+// partials, cyclic Jacobi (round-robin pairs, two-sided updates on 2x2
+// blocks), then the shared tail (eig_finish).
 // A round has two phases.  First the threads of pair ip (ip < n/2, one wave)
 // form that pair's rotation from its 2x2 diagonal block and publish it.  Then
 // thread (i, i2) (pairs i, i2 < n/2, i2 padded to a power of two P2 <= 32)
@@ -195,7 +277,7 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
     if (pass == 1 && !second[p]) return;
     const PatchDesc P = pd[p];
     const int tid = threadIdx.x, nth = blockDim.x;
-    const int s = P.s, kreq = P.kreq;
+    const int s = P.s;
     __shared__ int kshared, second_s;
     const int nch = (P.nrows + kRowChunk - 1) / kRowChunk;
     for (int o = tid; o < kRfMax * LDG; o += nth) {
@@ -287,72 +369,212 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
         __syncthreads();
         if (!r) break;
     }
-    // descending order by rank: eigenvalue i goes to the number of eigenvalues
-    // above it, ties by index (a NaN ranks as -inf, so the ranks stay a
-    // permutation)
-    if (tid < s) {
-        const double gi = G[tid * LDG + tid];
-        const double li = (gi == gi) ? gi : -INFINITY;
-        int r = 0;
-        for (int j = 0; j < s; ++j) {
-            const double gj = G[j * LDG + j];
-            const double lj = (gj == gj) ? gj : -INFINITY;
-            r += (lj > li) || (lj == li && j < tid);
-        }
-        perm[r] = tid;
-        lam[tid] = gi;
+    eig_finish(pd, p, P, G, V, LDG, perm, lam, &kshared, &second_s, small, sv_all, gap, flags, rank_tol, pass, small2,
+               second);
+}
+
+// ---------------------------------------------------------------- tridiagonal eigensolver
+// One wave per patch (the range finder's first pass and the two-pass basis):
+// Householder reduction G = Q T Q^T, then the implicit QL iteration with
+// shifts on T (the tql2 procedure of Bowdler, Martin, Reinsch and Wilkinson,
+// restated), its rotations accumulated into Q, which ends as the eigenvectors.
+// Fixed cost (no sweep count): the Householder steps are wave-parallel over a
+// row each, the QL recurrence runs on wave-uniform values (the diagonal and
+// off-diagonal of T held one entry per lane, read with readlane) while every
+// lane rotates its row of the eigenvector matrix.  Its eigenvalues carry
+// absolute errors of a small multiple of u ||G||, as the Gram matrix's own.
+__device__ __forceinline__ double lane_value(double x, int i) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), i);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), i);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// LDS visibility between the lanes of the one wave (in-order LDS, and no
+// compiler reordering across it)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+__global__ __launch_bounds__(64) void eig_ql_kernel(PatchDesc* pd, int p0, const double* __restrict__ part, int maxrc,
+                                                    double* __restrict__ small, double* __restrict__ sv_all,
+                                                    double* __restrict__ gap, int32_t* flags, double rank_tol, int pass,
+                                                    double* __restrict__ small2, int32_t* __restrict__ second) {
+    constexpr int LDG = kRfMax + 1;
+    __shared__ double G[kRfMax * LDG];   // the matrix, reduced in place; T's diagonals at the end
+    __shared__ double V[kRfMax * LDG];   // Q, then the eigenvectors (columns)
+    __shared__ double hv[kRfMax], hq[kRfMax];
+    __shared__ double rot_c[kRfMax], rot_s[kRfMax];   // a QL chase's rotations
+    __shared__ int perm[kRfMax];
+    __shared__ double lam[kRfMax];
+    __shared__ int kshared, second_s;
+    const int p = p0 + blockIdx.x;
+    const PatchDesc P = pd[p];
+    const int lane = threadIdx.x;
+    const int n = P.s;
+    const int nch = (P.nrows + kRowChunk - 1) / kRowChunk;
+    for (int o = lane; o < kRfMax * LDG; o += 64) {
+        G[o] = 0.0;
+        V[o] = (o / LDG == o % LDG) ? 1.0 : 0.0;
     }
     __syncthreads();
-    if (tid == 0) {
-        double* svp = sv_all + P.sv_off;
-        for (int i = 0; i < s; ++i) svp[i] = sqrt(fmax(lam[perm[i]], 0.0));
-        const double s1 = svp[0];
-        // rank: the requested one, or the numerical rank at rank_tol (the count of
-        // singular values above rank_tol sigma_1), between 1 and the requested one;
-        // the later kernels of the range finder read it from the descriptor
-        int kk = kreq;
-        if (rank_tol > 0.0 && P.sampled) {
-            kk = 0;
-            while (kk < kreq && svp[kk] > rank_tol * s1) ++kk;
-            kk = max(kk, 1);
+    sum_partials(part, p, maxrc, nch, n, G, LDG);
+    // Householder step k: x = G[k+1.., k] -> (alpha, 0, .., 0) by H = I - tau v v^T
+    // on indices k+1 .. n-1: A <- H A H = A - v q^T - q v^T with p = tau A v,
+    // q = p - (tau / 2) (v^T p) v; Q <- Q H.  Lane j holds entry j of the
+    // vectors and works on row k+1+j of A (row j of Q).
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1, o = k + 1;
+        const double x = lane < m ? G[(o + lane) * LDG + k] : 0.0;
+        const double x0 = lane_value(x, 0);
+        const double tail = wave_sum64(lane >= 1 ? x * x : 0.0);
+        if (!(tail > 0.0)) continue;   // already reduced (or not finite: left to the checks downstream)
+        const double alpha = x0 > 0.0 ? -sqrt(x0 * x0 + tail) : sqrt(x0 * x0 + tail);
+        const double v0 = x0 - alpha;
+        const double v = lane == 0 ? v0 : x;
+        const double tau = 2.0 / (v0 * v0 + tail);
+        hv[lane] = v;
+        wave_lds_sync();
+        double pj = 0.0;
+        if (lane < m) {
+            const double* row = G + (o + lane) * LDG + o;
+            for (int i = 0; i < m; ++i) pj += row[i] * hv[i];
+            pj *= tau;
         }
-        if (kk != P.ncols) pd[p].ncols = kk;
-        kshared = kk;
-        const double sk = svp[kk - 1];
-        const double next = svp[min(kk, s - 1)];
-        const bool again = pass == 0 && P.sampled && isfinite(s1) && s1 > 0.0 &&
-                           (!(next >= kResolve * s1) || (rank_tol > 0.0 && rank_tol < kResolve));
-        second_s = again ? 1 : 0;
-        if (pass == 0) second[p] = again ? 1 : 0;
-        // the k-th direction must be resolved: a rank deficiency of the
-        // snapshots themselves (sigma_k at rounding level) after the second pass
-        if (!again && !(sk > 1e-13 * s1)) raise_flag(flags, 2);
-        if (!isfinite(s1)) raise_flag(flags, 4);
-        gap[p] = (kk < s) ? (sk - svp[kk]) / s1 : 1.0;
+        const double K = 0.5 * tau * wave_sum64(lane < m ? v * pj : 0.0);
+        const double q = pj - K * v;
+        hq[lane] = q;
+        wave_lds_sync();
+        if (lane < m) {
+            double* row = G + (o + lane) * LDG + o;
+            for (int i = 0; i < m; ++i) row[i] -= v * hq[i] + q * hv[i];
+            const double xr = lane == 0 ? alpha : 0.0;
+            G[(o + lane) * LDG + k] = xr;
+            G[k * LDG + o + lane] = xr;
+        }
+        if (lane < n) {
+            double* row = V + lane * LDG + o;
+            double t = 0.0;
+            for (int i = 0; i < m; ++i) t += row[i] * hv[i];
+            t *= tau;
+            for (int i = 0; i < m; ++i) row[i] -= t * hv[i];
+        }
+        wave_lds_sync();
     }
+    // T in reversed order, so that QL (which deflates from the top) meets the
+    // small end of the graded T first (the reduction leaves the large entries
+    // at the top; reversed, the chases on these Gram matrices take 1.1-3x fewer
+    // rotations): diagonal d_j = T[n-1-j][n-1-j] on lane j, off-diagonal
+    // e_j = T[n-1-j][n-2-j] (e_{n-1} = 0), and the columns of Q reversed with it
+    const int jr = n - 1 - lane;
+    double d = lane < n ? G[jr * LDG + jr] : 0.0;
+    double e = lane + 1 < n ? G[jr * LDG + jr - 1] : 0.0;
+    if (lane < n) {
+        double* row = V + lane * LDG;
+        for (int j = 0; j < n / 2; ++j) {
+            const double a = row[j], b = row[n - 1 - j];
+            row[j] = b;
+            row[n - 1 - j] = a;
+        }
+    }
+    wave_lds_sync();
+    // implicit QL: for each l, chase the shifted rotation from the first
+    // negligible off-diagonal below l up to l until e_l is negligible, here
+    // against the norm of T (|e_j| <= u max_i (|d_i| + |e_i|)): absolute
+    // accuracy, which is what the Gram matrix's own rounding leaves
+    constexpr double kEps = 2.220446049250313e-16;
+    double tn = fabs(d) + fabs(e);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o, 64));
+    const double tol = kEps * tn;
+    bool stalled = false;
+    for (int l = 0; l < n; ++l) {
+        for (int iter = 0;; ++iter) {
+            // first mm >= l with a negligible e_mm, else n - 1
+            const bool neg = lane >= l && lane < n - 1 && fabs(e) <= tol;
+            const uint64_t bal = __ballot(neg);
+            const int mm = bal ? (int)__builtin_ctzll(bal) : n - 1;
+            if (mm == l) break;
+            if (iter == 60) { stalled = true; break; }
+            const double dl = lane_value(d, l), el = lane_value(e, l);
+            double g = (lane_value(d, l + 1) - dl) / (2.0 * el);
+            double r = hypot(g, 1.0);
+            g = lane_value(d, mm) - dl + el / (g + (g >= 0.0 ? r : -r));
+            double sn = 1.0, c = 1.0, pp = 0.0;
+            bool zero = false;
+            int lo = l;   // the last rotation applied (a split stops the chase early)
+            for (int i = mm - 1; i >= l; --i) {
+                const double ei = lane_value(e, i);
+                const double f = sn * ei, bb = c * ei;
+                // |f|, |g| stay far from the overflow and underflow thresholds
+                // here (entries of a Gram matrix of unit-variance samples), so
+                // r = sqrt(f^2 + g^2) and the ratios come from one reciprocal root
+                const double r2 = f * f + g * g;
+                if (r2 == 0.0) {
+                    // split: d_{i+1} takes the accumulated shift, e_{i+1} = 0, e_mm = 0
+                    if (lane == i + 1) {
+                        d -= pp;
+                        e = 0.0;
+                    }
+                    if (lane == mm) e = 0.0;
+                    zero = true;
+                    lo = i + 1;
+                    break;
+                }
+                const double rinv = rsqrt(r2);
+                r = r2 * rinv;
+                if (lane == i + 1) e = r;
+                sn = f * rinv;
+                c = g * rinv;
+                const double gi = lane_value(d, i + 1) - pp;
+                r = (lane_value(d, i) - gi) * sn + 2.0 * c * bb;
+                pp = sn * r;
+                if (lane == i + 1) d = gi + pp;
+                g = c * r - bb;
+                if (lane == 0) {
+                    rot_c[i] = c;
+                    rot_s[i] = sn;
+                }
+            }
+            // the chase's rotations on every row of the eigenvector matrix
+            // (lane = row): rotation i mixes columns i and i + 1, and after it
+            // column i + 1 is final for this chase, so a row is one pass down
+            // from column mm with the running column in a register
+            wave_lds_sync();
+            if (lane < n && lo < mm) {
+                double* row = V + lane * LDG;
+                double carry = row[mm];
+                for (int i = mm - 1; i >= lo; --i) {
+                    const double zi = row[i], ci = rot_c[i], si = rot_s[i];
+                    row[i + 1] = si * zi + ci * carry;
+                    carry = ci * zi - si * carry;
+                }
+                row[lo] = carry;
+            }
+            wave_lds_sync();
+            if (zero) continue;
+            if (lane == l) {
+                d -= pp;
+                e = g;
+            }
+            if (lane == mm) e = 0.0;
+        }
+        if (stalled) break;
+    }
+    if (stalled && lane == 0) raise_flag(flags, 4);
+    wave_lds_sync();
+    // eigenvalues on G's diagonal for the shared tail
+    if (lane < n) G[lane * LDG + lane] = d;
     __syncthreads();
-    const int k = kshared;
-    if (second_s) {
-        // V in descending order for Z = Y V (all s columns)
-        double* V1 = small2 + (int64_t)p * kSmall;
-        for (int o = tid; o < kSmall; o += nth) {
-            const int i = o / kRfMax, j = o % kRfMax;
-            V1[o] = (i < s && j < s) ? V[i * LDG + perm[j]] : 0.0;
-        }
-        return;
-    }
-    // pass 2 (two-pass range finder, G = (G^T Q)^T (G^T Q)): the eigenvectors
-    // themselves, the basis being Q V[:, :k]
-    double* B = small + (int64_t)p * kSmall;
-    for (int o = tid; o < kSmall; o += nth) {
-        const int i = o / kRfMax, j = o % kRfMax;
-        double v = 0.0;
-        if (i < s && j < k) {
-            const double sg = pass == 2 ? 1.0 : sqrt(fmax(lam[perm[j]], 0.0));
-            v = sg > 0 ? V[i * LDG + perm[j]] / sg : 0.0;
-        }
-        B[o] = v;
-    }
+    eig_finish(pd, p, P, G, V, LDG, perm, lam, &kshared, &second_s, small, sv_all, gap, flags, rank_tol, pass, small2,
+               second);
 }
 
 // Two-pass range finder: H = C^T C for C = G^T Q (nb x s per patch, Omega's
@@ -640,8 +862,8 @@ static void range_core(Ctx& c, int p0, int p1, PatchDesc* pd, double* Q, double*
                        (const int32_t*)nullptr);
     int maxs = 0;
     for (int p = p0; p < p1; ++p) maxs = std::max(maxs, c.hp[p].s);
-    hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, pd, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
-                       c.dflags, rank_tol, 0, c.rf_small2, c.rf_second);
+    hipLaunchKernelGGL(eig_ql_kernel, one, dim3(64), 0, st, pd, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap, c.dflags,
+                       rank_tol, 0, c.rf_small2, c.rf_second);
     // second pass where Y^T Y does not resolve sigma_{k+1}: Z = Y V, Z^T Z, Jacobi
     hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, pd, p0, (int)kY, (int)kZ, c.Y, Q, W, c.rf_small2,
                        (const int32_t*)nullptr, c.rf_Z, (const int32_t*)c.rf_second, (const int32_t*)nullptr);
@@ -669,7 +891,7 @@ void launch_range_wide(Ctx& c, int p0, int p1) {
     range_core(c, p0, p1, c.dp_wide, c.tp_Q, c.tp_W, 1e-12);
 }
 
-// H = (G^T Q)^T (G^T Q), its eigenvectors V (Jacobi, descending), the basis
+// H = (G^T Q)^T (G^T Q), its eigenvectors V (descending), the basis
 // Q V[:, :k] -> W, then Cholesky-QR and the sign fix into the handle's basis;
 // the singular values are those of Q^T G.
 void launch_range_two_pass(Ctx& c, int p0, int p1) {
@@ -681,8 +903,8 @@ void launch_range_two_pass(Ctx& c, int p0, int p1) {
     const int mrc = c.rf_maxrc;
     hipStream_t st = c.stream;
     hipLaunchKernelGGL(adj_gram_kernel, one, dim3(kThreads), 0, st, c.dp, p0, c.tp_C, c.rf_part, mrc);
-    hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
-                       c.dflags, c.rank_tol, 2, c.rf_small2, c.rf_second);
+    hipLaunchKernelGGL(eig_ql_kernel, one, dim3(64), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap, c.dflags,
+                       c.rank_tol, 2, c.rf_small2, c.rf_second);
     hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kZ, (int)kW, c.Y, c.Q, c.rf_ws, c.rf_small,
                        (const int32_t*)nullptr, c.tp_Q, (const int32_t*)nullptr, (const int32_t*)nullptr);
     range_tail(c, p0, p1, c.dp, c.Q, c.rf_ws);
