@@ -347,13 +347,21 @@ template <bool ADJ>
 __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
                                                                    const double* __restrict__ om, const double* __restrict__ x64_all,
                                                                    float* __restrict__ x32_all, const int32_t* __restrict__ conv,
-                                                                   double* __restrict__ part, int maxch, const double* __restrict__ Qs) {
+                                                                   double* __restrict__ part, int maxch, const double* __restrict__ Qs,
+                                                                   int np, int nch) {
     __shared__ double cell[(kChunkLines + 1) * (kMaxLine + 1)];
     __shared__ double red[kResThreads];
-    const int p = p0 + blockIdx.x;
+    // workgroup -> (patch, chunk) so that a patch's chunks are dispatched one
+    // after another on one XCD (workgroups go round-robin over the 8 XCDs):
+    // the rows two neighbouring chunks share are still in that XCD's L2 when
+    // the second one reads them
+    const int grp = blockIdx.x / (8 * nch), rem = blockIdx.x - grp * 8 * nch;
+    const int chunk = rem >> 3, pl = grp * 8 + (rem & 7);
+    if (pl >= np) return;
+    const int p = p0 + pl;
     if (conv && conv[p]) return;
     const PatchDesc P = pd[p];
-    const int l0 = blockIdx.y * kChunkLines;
+    const int l0 = chunk * kChunkLines;
     if (l0 >= P.nl) return;
     const int l1 = min(P.nl, l0 + kChunkLines);
     const double* aL = aL_all + P.a_off;
@@ -435,7 +443,7 @@ __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDe
         double s = 0.0;
         for (int gg = 0; gg < nseg; ++gg)
             for (int r = 0; r < l1 - l0; ++r) s += red[(gg * kChunkLines + r) * sp + tid];
-        part[((int64_t)p * maxch + blockIdx.y) * kMaxSamples + tid] = s;
+        part[((int64_t)p * maxch + chunk) * kMaxSamples + tid] = s;
     }
 }
 
@@ -605,12 +613,14 @@ void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it, const doub
     int32_t* conv = stats_only ? nullptr : c.conv;
     float* x32 = stats_only ? nullptr : c.x32;
     const dim3 grid(p1 - p0, max_chunks(c, p0, p1));
+    const int np = p1 - p0, nch = max_chunks(c, p0, p1);
+    const dim3 grid_ell((np + 7) / 8 * 8 * nch);   // (patch, chunk) in the XCD-aware order of the kernel
     if (c.kind == kElliptic && adjQ)
-        hipLaunchKernelGGL(residual_ell_kernel<true>, grid, dim3(kResThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.x64, x32, conv,
-                           c.part, c.maxch, adjQ);
+        hipLaunchKernelGGL(residual_ell_kernel<true>, grid_ell, dim3(kResThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.x64, x32,
+                           conv, c.part, c.maxch, adjQ, np, nch);
     else if (c.kind == kElliptic)
-        hipLaunchKernelGGL(residual_ell_kernel<false>, grid, dim3(kResThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.x64, x32, conv,
-                           c.part, c.maxch, (const double*)nullptr);
+        hipLaunchKernelGGL(residual_ell_kernel<false>, grid_ell, dim3(kResThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.x64, x32,
+                           conv, c.part, c.maxch, (const double*)nullptr, np, nch);
     else
         hipLaunchKernelGGL((residual_kernel<kKinetic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), inv_eps,
                            c.x64, x32, conv, c.part, c.maxch);
