@@ -263,7 +263,8 @@ int eig_threads(int max_s) {
 __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int p0, const double* __restrict__ part, int maxrc,
                                                              double* __restrict__ small, double* __restrict__ sv_all,
                                                              double* __restrict__ gap, int32_t* flags, double rank_tol, int pass,
-                                                             double* __restrict__ small2, int32_t* __restrict__ second) {
+                                                             double* __restrict__ small2, int32_t* __restrict__ second,
+                                                             int only_full) {
     // G and V with an odd leading dimension: a wave's column accesses
     // (V[j][a] over rows j) fall on distinct LDS banks
     constexpr int LDG = kRfMax + 1;
@@ -276,6 +277,7 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
     const int p = p0 + blockIdx.x;
     if (pass == 1 && !second[p]) return;
     const PatchDesc P = pd[p];
+    if (only_full && P.sampled) return;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int s = P.s;
     __shared__ int kshared, second_s;
@@ -417,6 +419,7 @@ __global__ __launch_bounds__(64) void eig_ql_kernel(PatchDesc* pd, int p0, const
     __shared__ int kshared, second_s;
     const int p = p0 + blockIdx.x;
     const PatchDesc P = pd[p];
+    if (!P.sampled) return;   // full-basis patches: Jacobi (their Gram matrices are not graded)
     const int lane = threadIdx.x;
     const int n = P.s;
     const int nch = (P.nrows + kRowChunk - 1) / kRowChunk;
@@ -864,13 +867,17 @@ static void range_core(Ctx& c, int p0, int p1, PatchDesc* pd, double* Q, double*
     for (int p = p0; p < p1; ++p) maxs = std::max(maxs, c.hp[p].s);
     hipLaunchKernelGGL(eig_ql_kernel, one, dim3(64), 0, st, pd, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap, c.dflags,
                        rank_tol, 0, c.rf_small2, c.rf_second);
+    // full-basis patches (their Gram matrices are not graded, and Jacobi needs few sweeps on them where the QL
+    // chases run the full length): the Jacobi solver, which returns at once for the sampled patches
+    hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, pd, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
+                       c.dflags, rank_tol, 0, c.rf_small2, c.rf_second, 1);
     // second pass where Y^T Y does not resolve sigma_{k+1}: Z = Y V, Z^T Z, Jacobi
     hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, pd, p0, (int)kY, (int)kZ, c.Y, Q, W, c.rf_small2,
                        (const int32_t*)nullptr, c.rf_Z, (const int32_t*)c.rf_second, (const int32_t*)nullptr);
     hipLaunchKernelGGL(gram_partial_kernel, tall, dim3(kThreads), 0, st, pd, p0, (int)kZ, c.Y, Q, W, c.rf_part, mrc,
                        (const int32_t*)nullptr, (const double*)c.rf_Z, (const int32_t*)c.rf_second);
     hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, pd, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
-                       c.dflags, rank_tol, 1, c.rf_small2, c.rf_second);
+                       c.dflags, rank_tol, 1, c.rf_small2, c.rf_second, 0);
     // W = Y B (first pass) or Z B (second pass)
     hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, pd, p0, (int)kYZ, (int)kW, c.Y, Q, W, c.rf_small,
                        (const int32_t*)nullptr, c.rf_Z, (const int32_t*)nullptr, (const int32_t*)c.rf_second);
