@@ -153,6 +153,16 @@ __device__ __forceinline__ void rr_pair(int i, int st, int nm1, int& a, int& b) 
     b = max(u, v);
 }
 
+// Which patches take the tridiagonal eigensolver (eig_ql_kernel; Jacobi, eig_kernel, the others): sampled ones
+// with at least kQlMinCols samples.
+// Full-basis patches have Gram matrices that are not graded, on which Jacobi
+// needs few sweeps while the QL chases run their full length (the kinetic
+// test workload's full-basis end patches: 1.05 ms in QL, 0.30 in Jacobi); and
+// at 32 samples the Jacobi rounds are cheap (h=1/512: 0.34 against 0.42 ms),
+// while from 48 on QL wins (h=1/1024, 64 samples: 1.39 against 1.90 ms).
+constexpr int kQlMinCols = 40;
+__device__ __forceinline__ bool ql_patch(const PatchDesc& P) { return P.sampled && P.s >= kQlMinCols; }
+
 // The tail of both eigensolvers, from the eigenvalues on G's diagonal and the
 // eigenvectors in V's columns (leading dimension ldg): descending order,
 // singular values, rank, the second-pass decision, relative gap, and B -> small
@@ -264,7 +274,7 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
                                                              double* __restrict__ small, double* __restrict__ sv_all,
                                                              double* __restrict__ gap, int32_t* flags, double rank_tol, int pass,
                                                              double* __restrict__ small2, int32_t* __restrict__ second,
-                                                             int only_full) {
+                                                             int only_rest) {
     // G and V with an odd leading dimension: a wave's column accesses
     // (V[j][a] over rows j) fall on distinct LDS banks
     constexpr int LDG = kRfMax + 1;
@@ -277,7 +287,7 @@ __global__ __launch_bounds__(kEigMaxThreads) void eig_kernel(PatchDesc* pd, int 
     const int p = p0 + blockIdx.x;
     if (pass == 1 && !second[p]) return;
     const PatchDesc P = pd[p];
-    if (only_full && P.sampled) return;
+    if (only_rest && ql_patch(P)) return;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int s = P.s;
     __shared__ int kshared, second_s;
@@ -419,7 +429,7 @@ __global__ __launch_bounds__(64) void eig_ql_kernel(PatchDesc* pd, int p0, const
     __shared__ int kshared, second_s;
     const int p = p0 + blockIdx.x;
     const PatchDesc P = pd[p];
-    if (!P.sampled) return;   // full-basis patches: Jacobi (their Gram matrices are not graded)
+    if (!ql_patch(P)) return;
     const int lane = threadIdx.x;
     const int n = P.s;
     const int nch = (P.nrows + kRowChunk - 1) / kRowChunk;
@@ -867,8 +877,8 @@ static void range_core(Ctx& c, int p0, int p1, PatchDesc* pd, double* Q, double*
     for (int p = p0; p < p1; ++p) maxs = std::max(maxs, c.hp[p].s);
     hipLaunchKernelGGL(eig_ql_kernel, one, dim3(64), 0, st, pd, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap, c.dflags,
                        rank_tol, 0, c.rf_small2, c.rf_second);
-    // full-basis patches (their Gram matrices are not graded, and Jacobi needs few sweeps on them where the QL
-    // chases run the full length): the Jacobi solver, which returns at once for the sampled patches
+    // the other patches (full-basis ones, and those with fewer than kQlMinCols samples): the Jacobi solver,
+    // which returns at once for the patches of the tridiagonal one
     hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, pd, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
                        c.dflags, rank_tol, 0, c.rf_small2, c.rf_second, 1);
     // second pass where Y^T Y does not resolve sigma_{k+1}: Z = Y V, Z^T Z, Jacobi
@@ -912,6 +922,8 @@ void launch_range_two_pass(Ctx& c, int p0, int p1) {
     hipLaunchKernelGGL(adj_gram_kernel, one, dim3(kThreads), 0, st, c.dp, p0, c.tp_C, c.rf_part, mrc);
     hipLaunchKernelGGL(eig_ql_kernel, one, dim3(64), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap, c.dflags,
                        c.rank_tol, 2, c.rf_small2, c.rf_second);
+    hipLaunchKernelGGL(eig_kernel, one, dim3(eig_threads(maxs)), 0, st, c.dp, p0, c.rf_part, mrc, c.rf_small, c.sv, c.gap,
+                       c.dflags, c.rank_tol, 2, c.rf_small2, c.rf_second, 1);
     hipLaunchKernelGGL(tall_gemm_kernel, tall, dim3(kThreads), 0, st, c.dp, p0, (int)kZ, (int)kW, c.Y, c.Q, c.rf_ws, c.rf_small,
                        (const int32_t*)nullptr, c.tp_Q, (const int32_t*)nullptr, (const int32_t*)nullptr);
     range_tail(c, p0, p1, c.dp, c.Q, c.rf_ws);
