@@ -523,8 +523,13 @@ __global__ __launch_bounds__(64) void eig_ql_kernel(PatchDesc* pd, int p0, const
             double sn = 1.0, c = 1.0, pp = 0.0;
             bool zero = false;
             int lo = l;   // the last rotation applied (a split stops the chase early)
+            // rotation i reads d_i, d_{i+1} and e_i; rotation j writes only d_{j+1}
+            // and e_{j+1}, after its own reads, so no rotation before i (j > i)
+            // has written them: read them from copies taken at the chase's start,
+            // so that the reads do not wait on the writes of the rotations before
+            const double dch = d, ech = e;
             for (int i = mm - 1; i >= l; --i) {
-                const double ei = lane_value(e, i);
+                const double ei = lane_value(ech, i);
                 const double f = sn * ei, bb = c * ei;
                 // |f|, |g| stay far from the overflow and underflow thresholds
                 // here (entries of a Gram matrix of unit-variance samples), so
@@ -546,8 +551,8 @@ __global__ __launch_bounds__(64) void eig_ql_kernel(PatchDesc* pd, int p0, const
                 if (lane == i + 1) e = r;
                 sn = f * rinv;
                 c = g * rinv;
-                const double gi = lane_value(d, i + 1) - pp;
-                r = (lane_value(d, i) - gi) * sn + 2.0 * c * bb;
+                const double gi = lane_value(dch, i + 1) - pp;
+                r = (lane_value(dch, i) - gi) * sn + 2.0 * c * bb;
                 pp = sn * r;
                 if (lane == i + 1) d = gi + pp;
                 g = c * r - bb;
