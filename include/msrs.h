@@ -119,6 +119,19 @@ typedef int32_t msrs_status;
  * and refinement.  Extra device memory: two arrays of Y's size and one of
  * Omega's. */
 #define MSRS_FLAG_TWO_PASS 64u
+/* The online least-squares solver (eqs. elliptic_cond_reduced,
+ * rte_cond_reduced through their normal equations).  By default every solve
+ * takes one step of the corrected semi-normal equations (Bjorck's method:
+ * r = d - P~ c with P~ itself, P~^T P~ dc = P~^T r with the resident
+ * Cholesky factor, c += dc) when the condition estimate of P~^T P~ made at
+ * msrs_assemble_coarse exceeds 1e12, where the normal equations alone keep
+ * fewer than about four correct digits; the step brings the coefficients'
+ * error from about kappa(P~)^2 u to about kappa(P~) u.  LS_NORMAL never takes
+ * the step, LS_CORRECTED always does (not with MSRS_FLAG_CONSTRAINED_BC).
+ * The step costs, per launch of up to 32 requests, the rows of P~ rebuilt
+ * from the traces and two band triangular sweeps. */
+#define MSRS_FLAG_LS_NORMAL    128u
+#define MSRS_FLAG_LS_CORRECTED 256u
 
 typedef struct msrs_ctx* msrs_handle;
 
@@ -301,7 +314,9 @@ msrs_status msrs_assemble_coarse(msrs_handle h);
  * overlap, each taking a workspace that is no longer in use on the device,
  * and a call that finds none fails with MSRS_ERR_BUSY.  With
  * MSRS_FLAG_CONSTRAINED_BC the coefficients are c = G_C f instead (the same
- * cost).  Errors: ARG (n_req outside [1, max_batch]), STATE, BUSY.
+ * cost).  Where the handle's solves take the corrected semi-normal step
+ * (MSRS_FLAG_LS_CORRECTED, msrs_coarse_corrected) it follows c = K f.
+ * Errors: ARG (n_req outside [1, max_batch]), STATE, BUSY.
  */
 msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev,
                               void* stream);
@@ -318,6 +333,15 @@ msrs_status msrs_solve_global(msrs_handle h, int32_t n_req, const double* f_dev,
  * log10(kappa_normal) digits of the coefficients.  Errors: ARG, STATE.
  */
 msrs_status msrs_coarse_condition(msrs_handle h, double* kappa_normal, double* kappa_ls);
+
+/*
+ * *corrected = 1 if the online solves of this handle take the corrected
+ * semi-normal step (MSRS_FLAG_LS_CORRECTED, or a condition estimate of
+ * P~^T P~ above 1e12 without MSRS_FLAG_LS_NORMAL), else 0; decided at
+ * msrs_assemble_coarse, which fails with ARG where the step would need more
+ * than 64 KiB of LDS (elliptic N/M > 680).  Errors: ARG (NULL), STATE.
+ */
+msrs_status msrs_coarse_corrected(msrs_handle h, int32_t* corrected);
 
 /*
  * The same solve by the plain direct method, one request after another:
@@ -343,7 +367,8 @@ msrs_status msrs_solve_global_banded(msrs_handle h, int32_t n_req, const double*
  * order them on one stream or synchronise between them.  Errors: ARG
  * (n_req outside [1, max_batch], NULL pointers, or
  * (boundary unknowns + coarse unknowns) x min(n_req, 32) doubles above the
- * array), STATE (no msrs_assemble_coarse yet), HIP.
+ * array, the coarse unknowns counted twice where the solves take the
+ * corrected semi-normal step), STATE (no msrs_assemble_coarse yet), HIP.
  */
 msrs_status msrs_solve_global_noalloc(msrs_handle h, int32_t n_req, const double* f_dev, double* u_dev, void* stream);
 

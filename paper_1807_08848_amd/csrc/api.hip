@@ -180,6 +180,14 @@ msrs_status validate(const msrs_problem_desc* d, std::string& msg) {
         return MSRS_ERR_ARG;
     }
     if (!(d->ir_tol >= 0.0) || !(d->ir_stop >= 0.0)) { msg = "ir_tol and ir_stop must be >= 0"; return MSRS_ERR_ARG; }
+    if ((d->flags & MSRS_FLAG_LS_NORMAL) && (d->flags & MSRS_FLAG_LS_CORRECTED)) {
+        msg = "MSRS_FLAG_LS_NORMAL and MSRS_FLAG_LS_CORRECTED exclude each other";
+        return MSRS_ERR_ARG;
+    }
+    if ((d->flags & MSRS_FLAG_LS_CORRECTED) && (d->flags & MSRS_FLAG_CONSTRAINED_BC)) {
+        msg = "the corrected semi-normal step applies to the least-squares system, not the constrained variant";
+        return MSRS_ERR_ARG;
+    }
     const int np = d->kind == MSRS_KIND_ELLIPTIC_Q1 ? d->M * d->M : d->M;
     for (int p = 0; p < np; ++p)
         if (d->overlap[p] < 0) { msg = "negative overlap"; return MSRS_ERR_ARG; }
@@ -1039,6 +1047,7 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
             for (auto& w : c->ws) {
                 w.cbuf = dalloc<double>(*c, (int64_t)c->Np * kOutPerLaunch);
                 w.gbuf = dalloc<double>(*c, (int64_t)std::max(c->nB, c->nF) * kOutPerLaunch);
+                w.zbuf = dalloc<double>(*c, (int64_t)c->Np * kOutPerLaunch);
                 MSRS_HIP_CHECK(hipEventCreateWithFlags(&w.done, hipEventDisableTiming));
             }
             if (c->budget && (size_t)c->bytes > c->budget) return fail(c, MSRS_ERR_OOM, "coarse factor exceeds the HBM budget");
@@ -1077,6 +1086,12 @@ msrs_status msrs_assemble_coarse(msrs_handle h) {
         MSRS_HIP_CHECK(hipGetLastError());
         sync_flags(*c);
         c->cond_normal = c->hflags[0] ? INFINITY : coarse_condition(*c, c->ws[0].cbuf);
+        // kappa(P~)^2 above 1e12 leaves the normal equations fewer than about
+        // four correct digits: the solves then take the corrected step
+        c->lsq_correct = !c->constrained && !(c->flags & MSRS_FLAG_LS_NORMAL) &&
+                         ((c->flags & MSRS_FLAG_LS_CORRECTED) || c->cond_normal > kLsqCorrectKappa);
+        if (c->lsq_correct && lsq_correct_lds(*c) > 65536)
+            return fail(c, MSRS_ERR_ARG, "the corrected semi-normal step needs N/M <= 680 (its rows of one patch in 64 KiB of LDS)");
     } catch (const HipError& e) {
         return hip_fail(c, e);
     }
@@ -1103,7 +1118,8 @@ static msrs_status solve_common(Ctx* c, int32_t n_req, const double* f_dev, doub
         if (!w) return fail(c, MSRS_ERR_BUSY, "every online workspace is in use by unfinished calls");
         if (banded) {
             StageTimer t(*c, MSRS_K_CSOLVE, st);
-            for (int r = 0; r < n_req; ++r) coarse_banded(*c, f_dev + (int64_t)r * c->n_bdry, u_dev + r * c->n_nodes, w->cbuf, st);
+            for (int r = 0; r < n_req; ++r)
+                coarse_banded(*c, f_dev + (int64_t)r * c->n_bdry, u_dev + r * c->n_nodes, w->cbuf, w->zbuf, st);
         } else {
             std::vector<double*> u(n_req);
             std::vector<const double*> f(n_req);
@@ -1112,7 +1128,7 @@ static msrs_status solve_common(Ctx* c, int32_t n_req, const double* f_dev, doub
                 f[r] = f_dev + (int64_t)r * c->n_bdry;
             }
             StageTimer t(*c, MSRS_K_CSOLVE, st);
-            coarse_apply(*c, n_req, f.data(), u.data(), w->gbuf, w->cbuf, st);
+            coarse_apply(*c, n_req, f.data(), u.data(), w->gbuf, w->cbuf, w->zbuf, st);
         }
         MSRS_HIP_CHECK(hipGetLastError());
         MSRS_HIP_CHECK(hipEventRecord(w->done, st));
@@ -1130,6 +1146,15 @@ msrs_status msrs_coarse_condition(msrs_handle h, double* kappa_normal, double* k
     if (!c->coarse_ready) return fail(c, MSRS_ERR_STATE, "msrs_assemble_coarse must come first");
     if (kappa_normal) *kappa_normal = c->cond_normal;
     if (kappa_ls) *kappa_ls = std::sqrt(c->cond_normal);
+    return MSRS_OK;
+}
+
+msrs_status msrs_coarse_corrected(msrs_handle h, int32_t* corrected) {
+    Ctx* c = h;
+    if (!c) return fail(nullptr, MSRS_ERR_ARG, "handle is NULL");
+    if (!corrected) return fail(c, MSRS_ERR_ARG, "corrected is NULL");
+    if (!c->coarse_ready) return fail(c, MSRS_ERR_STATE, "msrs_assemble_coarse must come first");
+    *corrected = c->lsq_correct ? 1 : 0;
     return MSRS_OK;
 }
 
@@ -1235,7 +1260,7 @@ msrs_status msrs_autotune(msrs_handle h, int32_t stage, int32_t reps, msrs_tune_
                 for (int ab : {4, 8, 16}) {
                     c->recon_batch = rb;
                     c->apply_batch = ab;
-                    const double ms = time_calls(*c, reps, [&] { coarse_apply(*c, nr, fp.data(), up.data(), w->gbuf, w->cbuf, c->stream); });
+                    const double ms = time_calls(*c, reps, [&] { coarse_apply(*c, nr, fp.data(), up.data(), w->gbuf, w->cbuf, w->zbuf, c->stream); });
                     record(MSRS_TUNE_RECON_BATCH * 100 + MSRS_TUNE_APPLY_BATCH, rb * 100 + ab, ms);
                     if (ms < best) { best = ms; ra = rb; aa = ab; }
                 }

@@ -808,6 +808,192 @@ void coarse_constrained_setup(Ctx& c, const ConsWs& w) {
     hipLaunchKernelGGL(transpose_kernel, dim3((Np + 63) / 64, (nF + 63) / 64), dim3(kThreads), 0, st, c.GC, Np, nF, c.GCT);
 }
 
+// ------------------------------------------------------------ corrected semi-normal equations
+// The normal equations lose about log10 kappa(P~)^2 digits of c.  Where that
+// is too many, every solve takes one step of the corrected semi-normal
+// equations (Bjorck, 1987): the residual r = d - P~ c with P~ itself (rebuilt
+// row by row from the traces, never stored), then P~^T P~ dc = P~^T r with the
+// resident Cholesky factor, and c += dc.  The step takes the forward error
+// from about kappa(P~)^2 u to about kappa(P~) u, the accuracy of a QR solve.
+//
+// z = P~^T (d - P~ c) on the unknowns of patch m, per request (grid: patch x
+// request).  The workgroup forms the residual of every row that touches m
+// (a row shared with a neighbour is formed by both patches), stages them in
+// LDS, and each thread sums its column's share.  LDS, for W = nH + 1:
+//   [e W + t]            value row of edge e (0 right, 1 left, 2 top, 3 bottom) at node t
+//   [4 W + e W + t]      flux row of edge e at inner node t (1 <= t < nH)
+//   [8 W + v]            vertex row at corner v (0 SW, 1 SE, 2 NE, 3 NW)
+//   [8 W + 4 + t]        Dirichlet row at node t of dK_m (kbnode order)
+// Rows that do not exist (no neighbour, a vertex on dOmega, a node off
+// dOmega) hold 0.
+__device__ __forceinline__ double trace_dot(const ElTr& T, bool flux, int ii, int jj, const double* __restrict__ cm, int k) {
+    double s = 0.0;
+    for (int b = 0; b < k; ++b) s += (flux ? T.flx(ii, jj, b) : T.val(ii, jj, b)) * cm[b];
+    return s;
+}
+
+// node (ii, jj) of patch m at position t of edge e, the neighbour across e
+// (-1 on dOmega) and the neighbour's node facing it
+__device__ __forceinline__ int edge_nodes(int e, int t, int nH, int m, int m1, int m2, int M, int& ii, int& jj, int& ni, int& nj) {
+    switch (e) {
+        case 0: ii = nH; jj = t; ni = 0; nj = t; return m1 < M - 1 ? m + 1 : -1;
+        case 1: ii = 0; jj = t; ni = nH; nj = t; return m1 > 0 ? m - 1 : -1;
+        case 2: ii = t; jj = nH; ni = t; nj = 0; return m2 < M - 1 ? m + M : -1;
+        default: ii = t; jj = 0; ni = t; nj = nH; return m2 > 0 ? m - M : -1;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void lsq_correct_elliptic_kernel(const PatchDesc* pd, const CoarseDesc* cd,
+                                                                        const double* __restrict__ tr, int64_t tr_stride, int M,
+                                                                        int N, int Np, InPtrs in, const double* __restrict__ cbuf,
+                                                                        double* __restrict__ zbuf) {
+    extern __shared__ double rs[];
+    const int m = blockIdx.x, r = blockIdx.y;
+    const int m1 = m % M, m2 = m / M;
+    const int nH = pd[m].nH, W = nH + 1;
+    const double* c = cbuf + (int64_t)r * Np;
+    const double* f = in.f[r];
+    auto TR = [&](int p) { return ElTr{tr + (int64_t)p * tr_stride, nH, cd[p].ncols}; };
+    const ElTr Tm = TR(m);
+    const int km = cd[m].ncols;
+    const double* cm = c + cd[m].col_off;
+    const int nrow = 8 * W + 4 + 4 * nH;
+    for (int i = threadIdx.x; i < nrow; i += kThreads) {
+        double res = 0.0;
+        if (i < 8 * W) {
+            const bool flux = i >= 4 * W;
+            const int e = (i - (flux ? 4 * W : 0)) / W, t = i % W;
+            int ii, jj, ni, nj;
+            const int n = edge_nodes(e, t, nH, m, m1, m2, M, ii, jj, ni, nj);
+            if (n >= 0 && (!flux || (t > 0 && t < nH))) {
+                const double sm = trace_dot(Tm, flux, ii, jj, cm, km);
+                const double sn = trace_dot(TR(n), flux, ni, nj, c + cd[n].col_off, cd[n].ncols);
+                // d = 0; a value row is (left or bottom patch) - (right or top
+                // patch), a flux row the sum of both
+                res = flux ? -(sm + sn) : ((e == 0 || e == 2) ? sn - sm : sm - sn);
+            }
+        } else if (i < 8 * W + 4) {
+            const int v = i - 8 * W;
+            const int vx = m1 + (v == 1 || v == 2), vy = m2 + (v >= 2);
+            if (vx > 0 && vx < M && vy > 0 && vy < M) {
+                // the patches (vx - 1 + dx, vy - 1 + dy) around the vertex, each at its corner facing it
+                double s = 0.0;
+                for (int q = 0; q < 4; ++q) {
+                    const int dx = q & 1, dy = q >> 1;
+                    const int p = (vy - 1 + dy) * M + (vx - 1 + dx);
+                    s += trace_dot(TR(p), true, dx ? 0 : nH, dy ? 0 : nH, c + cd[p].col_off, cd[p].ncols);
+                }
+                res = -s;
+            }
+        } else {
+            const int t = i - 8 * W - 4;
+            int ii, jj;
+            kbnode(t, nH, ii, jj);
+            const int gx = m1 * nH + ii, gy = m2 * nH + jj;
+            if (gx == 0 || gx == N || gy == 0 || gy == N) res = f[gb_index(gx, gy, N)] - trace_dot(Tm, false, ii, jj, cm, km);
+        }
+        rs[i] = res;
+    }
+    __syncthreads();
+    for (int a = threadIdx.x; a < km; a += kThreads) {
+        double z = 0.0;
+        for (int e = 0; e < 4; ++e) {
+            int ii, jj, ni, nj;
+            if (edge_nodes(e, 0, nH, m, m1, m2, M, ii, jj, ni, nj) < 0) continue;
+            const double sg = (e == 0 || e == 2) ? 1.0 : -1.0;   // c_m's sign in the edge's value rows
+            for (int t = 0; t <= nH; ++t) {
+                edge_nodes(e, t, nH, m, m1, m2, M, ii, jj, ni, nj);
+                z += sg * Tm.val(ii, jj, a) * rs[e * W + t];
+                if (t > 0 && t < nH) z += Tm.flx(ii, jj, a) * rs[4 * W + e * W + t];
+            }
+        }
+        for (int v = 0; v < 4; ++v) {
+            const int cx = (v == 1 || v == 2) ? nH : 0, cy = v >= 2 ? nH : 0;
+            z += Tm.flx(cx, cy, a) * rs[8 * W + v];
+        }
+        for (int t = 0; t < 4 * nH; ++t) {
+            int ii, jj;
+            kbnode(t, nH, ii, jj);
+            z += Tm.val(ii, jj, a) * rs[8 * W + 4 + t];
+        }
+        zbuf[(int64_t)r * Np + cd[m].col_off + a] = z;
+    }
+}
+
+// Kinetic rows (grid: patch x request).  LDS: [j] the rows of the interface
+// with patch m - 1, [nv + j] those with m + 1, [2 nv + j] the inflow rows of
+// an end patch, ordinate j.
+__global__ __launch_bounds__(kThreads) void lsq_correct_kinetic_kernel(const PatchDesc* pd, const CoarseDesc* cd,
+                                                                       const double* __restrict__ Q_all, const double* __restrict__ vw,
+                                                                       int M, int nv, int Np, InPtrs in, const double* __restrict__ cbuf,
+                                                                       double* __restrict__ zbuf) {
+    extern __shared__ double rs[];
+    const int m = blockIdx.x, r = blockIdx.y, h = nv / 2;
+    const double* c = cbuf + (int64_t)r * Np;
+    const double* f = in.f[r];
+    // row of basis values at (cell, ordinate j) of patch p times c_p
+    auto qdot = [&](int p, int cell, int j) {
+        const PatchDesc& P = pd[p];
+        const double* Q = Q_all + P.Q_off;
+        const double* cp = c + cd[p].col_off;
+        double s = 0.0;
+        for (int b = 0; b < cd[p].ncols; ++b) s += Q[(int64_t)b * P.nrows + cell * nv + j] * cp[b];
+        return s;
+    };
+    for (int i = threadIdx.x; i < 3 * nv; i += kThreads) {
+        const int side = i / nv, j = i % nv;
+        const bool pos = vw[j] > 0;
+        double res = 0.0;
+        // an interface row is (upwind patch's outgoing value) - (downwind patch's ghost value); d = 0
+        if (side == 0 && m > 0)
+            res = qdot(m, pos ? 0 : 1, j) - qdot(m - 1, pos ? pd[m - 1].nH : pd[m - 1].nH + 1, j);
+        else if (side == 1 && m < M - 1)
+            res = qdot(m + 1, pos ? 0 : 1, j) - qdot(m, pos ? pd[m].nH : pd[m].nH + 1, j);
+        else if (side == 2 && m == 0 && pos)
+            res = f[j - h] - qdot(m, 0, j);
+        else if (side == 2 && m == M - 1 && !pos)
+            res = f[h + j] - qdot(m, pd[m].nH + 1, j);
+        rs[i] = res;
+    }
+    __syncthreads();
+    const PatchDesc P = pd[m];
+    const double* Q = Q_all + P.Q_off;
+    for (int a = threadIdx.x; a < cd[m].ncols; a += kThreads) {
+        const double* qa = Q + (int64_t)a * P.nrows;
+        double z = 0.0;
+        for (int j = 0; j < nv; ++j) {
+            const bool pos = vw[j] > 0;
+            if (m > 0) z -= qa[(pos ? 0 : 1) * nv + j] * rs[j];
+            if (m < M - 1) z += qa[(pos ? P.nH : P.nH + 1) * nv + j] * rs[nv + j];
+            if ((m == 0 && pos) || (m == M - 1 && !pos)) z += qa[(pos ? 0 : P.nH + 1) * nv + j] * rs[2 * nv + j];
+        }
+        zbuf[(int64_t)r * Np + cd[m].col_off + a] = z;
+    }
+}
+
+__global__ void add_kernel(double* __restrict__ x, const double* __restrict__ y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] += y[i];
+}
+
+size_t lsq_correct_lds(const Ctx& c) {
+    if (c.kind != kElliptic) return sizeof(double) * 3 * (size_t)c.nv;
+    const int nH = c.N / c.M;
+    return sizeof(double) * (size_t)(12 * nH + 12);
+}
+
+static void lsq_correct(const Ctx& c, int nr, const InPtrs& in, double* cbuf, double* zbuf, hipStream_t st) {
+    const dim3 g(c.n_patches, nr);
+    const size_t lds = lsq_correct_lds(c);
+    if (c.kind == kElliptic)
+        hipLaunchKernelGGL(lsq_correct_elliptic_kernel, g, dim3(kThreads), lds, st, c.dp, c.dc, c.tr, c.tr_stride, c.M, c.N, c.Np, in,
+                           cbuf, zbuf);
+    else
+        hipLaunchKernelGGL(lsq_correct_kinetic_kernel, g, dim3(kThreads), lds, st, c.dp, c.dc, c.Q, c.vw, c.M, c.nv, c.Np, in, cbuf,
+                           zbuf);
+    hipLaunchKernelGGL(band_solve_kernel, dim3((nr + 63) / 64), dim3(1024), 0, st, c.band, c.Np, c.bw, zbuf, nr);
+    hipLaunchKernelGGL(add_kernel, grid_of((int64_t)c.Np * nr), dim3(kThreads), 0, st, cbuf, zbuf, (int64_t)c.Np * nr);
+}
+
 static void launch_recon(const Ctx& c, const double* cbuf, int n_req, const OutPtrs& out, hipStream_t st) {
     if (c.kind == kElliptic && c.N / c.M >= kTile) {
         const dim3 g((c.N + kTile) / kTile, (c.N + kTile) / kTile);
@@ -831,7 +1017,7 @@ static void launch_recon(const Ctx& c, const double* cbuf, int n_req, const OutP
 }
 
 void coarse_apply(const Ctx& c, int n_req, const double* const* f, double* const* u, double* gbuf, double* cbuf,
-                  hipStream_t st) {
+                  double* zbuf, hipStream_t st) {
     for (int r0 = 0; r0 < n_req; r0 += kOutPerLaunch) {
         const int nr = std::min(kOutPerLaunch, n_req - r0);
         InPtrs in{};
@@ -855,16 +1041,22 @@ void coarse_apply(const Ctx& c, int n_req, const double* const* f, double* const
         if (rb == 4) hipLaunchKernelGGL(apply_G_kernel<4>, ga, dim3(kThreads), 0, st, GT, c.Np, ng, gbuf, nr, cbuf);
         else if (rb == 16) hipLaunchKernelGGL(apply_G_kernel<16>, ga, dim3(kThreads), 0, st, GT, c.Np, ng, gbuf, nr, cbuf);
         else hipLaunchKernelGGL(apply_G_kernel<8>, ga, dim3(kThreads), 0, st, GT, c.Np, ng, gbuf, nr, cbuf);
+        if (c.lsq_correct) lsq_correct(c, nr, in, cbuf, zbuf, st);
         launch_recon(c, cbuf, nr, out, st);
     }
 }
 
-void coarse_banded(const Ctx& c, const double* f, double* u, double* cbuf, hipStream_t st) {
+void coarse_banded(const Ctx& c, const double* f, double* u, double* cbuf, double* zbuf, hipStream_t st) {
     if (c.kind == kElliptic)
         hipLaunchKernelGGL(rhs_elliptic_kernel, dim3(c.n_patches), dim3(kThreads), 0, st, c.dp, c.dc, c.tr, c.tr_stride, c.M, c.N, f, cbuf);
     else
         hipLaunchKernelGGL(rhs_kinetic_kernel, dim3(c.n_patches), dim3(kThreads), 0, st, c.dp, c.dc, c.Q, c.vw, c.M, c.nv, f, cbuf);
     hipLaunchKernelGGL(band_solve_kernel, dim3(1), dim3(1024), 0, st, c.band, c.Np, c.bw, cbuf, 1);
+    if (c.lsq_correct) {
+        InPtrs in{};
+        in.f[0] = f;
+        lsq_correct(c, 1, in, cbuf, zbuf, st);
+    }
     OutPtrs out{};
     out.u[0] = u;
     launch_recon(c, cbuf, 1, out, st);

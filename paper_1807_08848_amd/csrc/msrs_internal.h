@@ -18,6 +18,7 @@ constexpr int kMaxHgVel = 64;      // ordinates of an anisotropic-scattering (ki
 constexpr int kThreads = 256;      // threads of every per-patch workgroup
 constexpr int kChunkLines = 8;     // block rows per workgroup of the lifting and residual kernels
 constexpr int kOutPerLaunch = 32;  // requests per reconstruction launch
+constexpr double kLsqCorrectKappa = 1e12;  // condition of P~^T P~ above which solves take the corrected step
 constexpr int kOnlineWs = 4;       // concurrent msrs_solve_global calls per handle
 constexpr int kFlags = 8;          // device error flags (see Ctx::dflags)
 
@@ -162,6 +163,7 @@ struct Ctx {
     int Np = 0, bw = 0;
     double norm1_normal = 0.0;    // ||P~^T P~||_1 of the last coarse assembly
     double cond_normal = 0.0;     // 1-norm condition estimate of P~^T P~ (0 before msrs_assemble_coarse)
+    bool lsq_correct = false;     // online solves take a corrected semi-normal step
     int Np_cap = 0, nB_cap = 0;   // sizes the coarse buffers were allocated for (every patch at its requested rank)
     std::vector<CoarseDesc> hc;
     CoarseDesc* dc = nullptr;
@@ -189,6 +191,7 @@ struct Ctx {
     struct OnlineWs {
         double* cbuf = nullptr;
         double* gbuf = nullptr;
+        double* zbuf = nullptr;      // Np x kOutPerLaunch, the corrected semi-normal step's workspace
         hipEvent_t done = nullptr;   // recorded after the last use
         hipStream_t last = nullptr;  // stream of the last use (stream order makes reuse there safe)
         bool used = false;
@@ -245,7 +248,11 @@ double coarse_condition(Ctx& c, double* work);
 // and cbuf (Np x kOutPerLaunch).  Reads the handle only, so several streams
 // may run it at once.
 void coarse_apply(const Ctx& c, int n_req, const double* const* f, double* const* u, double* gbuf, double* cbuf,
-                  hipStream_t st);
+                  double* zbuf, hipStream_t st);
+// With lsq_correct set: one corrected semi-normal step per solve, zbuf
+// (Np x kOutPerLaunch) its workspace (unused, may be null, otherwise).  LDS
+// bytes per workgroup of its row kernel (at most 64 KiB must hold).
+size_t lsq_correct_lds(const Ctx& c);
 // Constrained least squares: the Dirichlet rows (3 ints each: patch, node of
 // dK_m, global boundary index) and the set-up of G_C / GCT from G_B, with
 // workspaces sized for nC rows and nB boundary unknowns.
@@ -262,7 +269,7 @@ struct ConsWs {
 std::vector<int32_t> constrained_rows(const Ctx& c);
 void coarse_constrained_setup(Ctx& c, const ConsWs& w);
 // Banded path: one request by P~^T d and two band triangular solves; cbuf Np.
-void coarse_banded(const Ctx& c, const double* f, double* u, double* cbuf, hipStream_t st);
+void coarse_banded(const Ctx& c, const double* f, double* u, double* cbuf, double* zbuf, hipStream_t st);
 
 // timing helpers (api.hip)
 struct StageTimer {

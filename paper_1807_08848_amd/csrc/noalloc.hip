@@ -19,7 +19,9 @@ namespace {
 
 // The workspace of one launch of up to kOutPerLaunch requests: the boundary
 // right-hand sides (g_len doubles per request), then the least-squares
-// coefficients (Np doubles per request).
+// coefficients (Np doubles per request), then, for a handle whose solves take
+// the corrected semi-normal step, that step's right-hand sides (Np doubles
+// per request).
 constexpr int64_t kScratchDoubles = int64_t(1) << 18;   // 2 MiB
 
 static __device__ __align__(256) double scratch[kScratchDoubles];
@@ -64,15 +66,18 @@ extern "C" msrs_status msrs_solve_global_noalloc(msrs_handle h, int32_t n_req, c
     if (!f_dev || !u_dev) return set_err(h, MSRS_ERR_ARG, "f_dev / u_dev is NULL");
     const int nr = std::min<int>(n_req, kOutPerLaunch);
     const int64_t ng = c->g_len();
-    if ((ng + c->Np) * nr > kScratchDoubles)
+    const int64_t per_req = ng + c->Np * (c->lsq_correct ? 2 : 1);
+    if (per_req * nr > kScratchDoubles)
         return set_err(h, MSRS_ERR_ARG,
-                       "the fixed workspace (2 MiB) is too small: (boundary unknowns + coarse unknowns) x "
-                       "min(n_req, 32) doubles must fit; use fewer requests per call or msrs_solve_global");
+                       "the fixed workspace (2 MiB) is too small: (boundary unknowns + coarse unknowns, twice the "
+                       "latter with the corrected semi-normal step) x min(n_req, 32) doubles must fit; use fewer "
+                       "requests per call or msrs_solve_global");
     double* ws = nullptr;
     const hipError_t e = device_scratch(c->device, &ws);
     if (e != hipSuccess) return set_err(h, MSRS_ERR_HIP, "hipGetSymbolAddress of the fixed workspace failed");
     double* gbuf = ws;
     double* cbuf = ws + ng * nr;
+    double* zbuf = c->lsq_correct ? cbuf + c->Np * nr : nullptr;
     const hipStream_t st = stream ? (hipStream_t)stream : c->stream;
     try {
         const double* fp[kOutPerLaunch];
@@ -83,7 +88,7 @@ extern "C" msrs_status msrs_solve_global_noalloc(msrs_handle h, int32_t n_req, c
                 fp[r] = f_dev + (int64_t)(r0 + r) * c->n_bdry;
                 up[r] = u_dev + (int64_t)(r0 + r) * c->n_nodes;
             }
-            coarse_apply(*c, m, fp, up, gbuf, cbuf, st);
+            coarse_apply(*c, m, fp, up, gbuf, cbuf, zbuf, st);
         }
         MSRS_HIP_CHECK(hipGetLastError());
     } catch (const HipError&) {

@@ -55,6 +55,7 @@ struct Lane {
     hipEvent_t ev = nullptr;
     double* cbuf = nullptr;   // max Np x kOutPerLaunch
     double* gbuf = nullptr;   // max nB x kOutPerLaunch
+    double* zbuf = nullptr;   // max Np x kOutPerLaunch (corrected semi-normal step)
     std::vector<int64_t> ids;
     bool busy = false;
 };
@@ -158,7 +159,7 @@ void launch_batch(msrs_server_s* s, int k, const std::vector<serve::Scheduler::I
         q.stream = k;
         L.ids.push_back(b[r].id);
     }
-    coarse_apply(c, n, f.data(), u.data(), L.gbuf, L.cbuf, L.st);
+    coarse_apply(c, n, f.data(), u.data(), L.gbuf, L.cbuf, L.zbuf, L.st);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(L.ev, L.st);
     if (e != hipSuccess) throw HipError(e, "batch launch", __FILE__, __LINE__);
@@ -334,6 +335,7 @@ msrs_status msrs_server_create(msrs_server* out, const msrs_handle* models, int3
         chk(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming), "hipEventCreate");
         if (chk(hipMalloc((void**)&L.cbuf, sizeof(double) * (size_t)np_max * kOutPerLaunch), "hipMalloc cbuf")) s->dallocs.push_back(L.cbuf);
         if (chk(hipMalloc((void**)&L.gbuf, sizeof(double) * (size_t)nB_max * kOutPerLaunch), "hipMalloc gbuf")) s->dallocs.push_back(L.gbuf);
+        if (chk(hipMalloc((void**)&L.zbuf, sizeof(double) * (size_t)np_max * kOutPerLaunch), "hipMalloc zbuf")) s->dallocs.push_back(L.zbuf);
     }
     if (e != hipSuccess) {
         st = e == hipErrorOutOfMemory ? MSRS_ERR_OOM : MSRS_ERR_HIP;

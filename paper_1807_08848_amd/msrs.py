@@ -33,6 +33,7 @@ FLAG_FULL_BASIS_ENDS, FLAG_PER_PATCH_LAUNCH, FLAG_TIMING, FLAG_FULL_BASIS_BOUNDA
 FLAG_CONSTRAINED_BC = 16
 FLAG_FULL_BASIS = 32
 FLAG_TWO_PASS = 64
+FLAG_LS_NORMAL, FLAG_LS_CORRECTED = 128, 256
 TUNE_SWEEP_COLS, TUNE_RECON_BATCH, TUNE_APPLY_BATCH, TUNE_FACTOR_SHARE = 0, 1, 2, 3
 TUNE_STAGE_OFFLINE, TUNE_STAGE_ONLINE = 0, 1
 TUNE_NAMES = {TUNE_SWEEP_COLS: "sweep_cols", TUNE_RECON_BATCH: "recon_batch", TUNE_APPLY_BATCH: "apply_batch",
@@ -101,6 +102,7 @@ _sig = {
     "msrs_solve_global": (C.c_int32, [_H, C.c_int32, _P, _P, _P]),
     "msrs_solve_global_banded": (C.c_int32, [_H, C.c_int32, _P, _P, _P]),
     "msrs_coarse_condition": (C.c_int32, [_H, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "msrs_coarse_corrected": (C.c_int32, [_H, C.POINTER(C.c_int32)]),
     "msrs_solve_global_noalloc": (C.c_int32, [_H, C.c_int32, _P, _P, _P]),
     "msrs_server_clock": (C.c_double, []),
     "msrs_server_last_error": (C.c_char_p, []),
@@ -243,6 +245,12 @@ class Problem:
         kn, kl = C.c_double(), C.c_double()
         self._check(_lib.msrs_coarse_condition(self.h, C.byref(kn), C.byref(kl)))
         return kn.value, kl.value
+
+    def coarse_corrected(self):
+        """True if the online solves take the corrected semi-normal step."""
+        v = C.c_int32()
+        self._check(_lib.msrs_coarse_corrected(self.h, C.byref(v)))
+        return bool(v.value)
 
     def set_max_batch(self, n):
         self._check(_lib.msrs_set_max_batch(self.h, int(n)))

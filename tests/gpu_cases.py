@@ -75,7 +75,7 @@ def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-def resident(cfg, precision, max_batch=None):
+def resident(cfg, precision, max_batch=None, flags=0):
     """A handle with bases and coarse factor resident (caller closes it)."""
     import torch
     from paper_1807_08848_amd import msrs
@@ -84,7 +84,7 @@ def resident(cfg, precision, max_batch=None):
     d = msrs.make_desc(msrs.KIND_KINETIC_DO if kin else msrs.KIND_ELLIPTIC_Q1, cfg["N"], cfg["M"],
                        list(cfg["overlap"]), cfg["s"], cfg["k"], precision=precision, seed=cfg["seed"],
                        n_vel=cfg.get("n_vel", 0), eps=cfg.get("eps", 1.0), hg=cfg.get("hg", 0.0),
-                       rank_tol=cfg.get("rank_tol", 0.0), flags=msrs.FLAG_FULL_BASIS_ENDS if kin else 0)
+                       rank_tol=cfg.get("rank_tol", 0.0), flags=flags | (msrs.FLAG_FULL_BASIS_ENDS if kin else 0))
     pr = msrs.Problem(d)
     try:
         a = torch.tensor(np.asarray(cfg["coef"]), device="cuda:0", dtype=torch.float64)
