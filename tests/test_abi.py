@@ -69,6 +69,19 @@ def test_full_basis_boundary_needs_small_patches():
     assert e.value.status == msrs.ERR_ARG and "4 N/M <= 64" in str(e.value)
 
 
+def test_least_squares_solver_flags_are_validated():
+    """MSRS_FLAG_LS_NORMAL and MSRS_FLAG_LS_CORRECTED exclude each other, and
+    the corrected semi-normal step does not apply to the constrained variant."""
+    from paper_1807_08848_amd import msrs
+    with pytest.raises(msrs.MsrsError) as e:
+        msrs.Problem(msrs.make_desc(0, 128, 4, [8] * 16, 10, 6, flags=msrs.FLAG_LS_NORMAL | msrs.FLAG_LS_CORRECTED))
+    assert e.value.status == msrs.ERR_ARG and "exclude each other" in str(e.value)
+    with pytest.raises(msrs.MsrsError) as e:
+        msrs.Problem(msrs.make_desc(0, 64, 4, [8] * 16, 10, 6,
+                                    flags=msrs.FLAG_LS_CORRECTED | msrs.FLAG_CONSTRAINED_BC | msrs.FLAG_FULL_BASIS_BOUNDARY))
+    assert e.value.status == msrs.ERR_ARG and "constrained" in str(e.value)
+
+
 def test_null_handle_calls_fail_cleanly():
     from paper_1807_08848_amd import msrs
     L = msrs.lib
@@ -77,6 +90,7 @@ def test_null_handle_calls_fail_cleanly():
     assert L.msrs_range_finder(None, None, None) == msrs.ERR_ARG
     assert L.msrs_assemble_coarse(None) == msrs.ERR_ARG
     assert L.msrs_solve_global(None, 1, None, None, None) == msrs.ERR_ARG
+    assert L.msrs_coarse_corrected(None, None) == msrs.ERR_ARG
     L.msrs_destroy(None)
 
 
