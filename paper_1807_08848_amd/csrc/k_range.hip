@@ -569,6 +569,7 @@ __global__ __launch_bounds__(64) void eig_ql_kernel(PatchDesc* pd, int p0, const
             if (lane < n && lo < mm) {
                 double* row = V + lane * LDG;
                 double carry = row[mm];
+#pragma unroll 4
                 for (int i = mm - 1; i >= lo; --i) {
                     const double zi = row[i], ci = rot_c[i], si = rot_s[i];
                     row[i + 1] = si * zi + ci * carry;
