@@ -424,6 +424,7 @@ __global__ __launch_bounds__(64) void eig_ql_kernel(PatchDesc* pd, int p0, const
     __shared__ double V[kRfMax * LDG];   // Q, then the eigenvectors (columns)
     __shared__ double hv[kRfMax], hq[kRfMax];
     __shared__ double rot_c[kRfMax], rot_s[kRfMax];   // a QL chase's rotations
+    __shared__ double new_e[kRfMax], new_d[kRfMax];   // and the entries of T it rewrites
     __shared__ int perm[kRfMax];
     __shared__ double lam[kRfMax];
     __shared__ int kshared, second_s;
@@ -528,7 +529,49 @@ __global__ __launch_bounds__(64) void eig_ql_kernel(PatchDesc* pd, int p0, const
             // has written them: read them from copies taken at the chase's start,
             // so that the reads do not wait on the writes of the rotations before
             const double dch = d, ech = e;
-            for (int i = mm - 1; i >= l; --i) {
+            // The chase as straight-line code: no test inside (a rotation with
+            // f = g = 0, the split case, is detected afterwards and the chase
+            // redone below with the test), the rewritten d_{i+1}, e_{i+1} and
+            // the rotation go to LDS from lane 0 (every lane holds the same
+            // values), and d_{i+1} of rotation i is d_i of rotation i + 1.
+            bool redo;
+            {
+                bool hit = false;
+                double sf = 1.0, cf = 1.0, pf = 0.0, gf = g, di1 = lane_value(dch, mm);
+                for (int i = mm - 1; i >= l; --i) {
+                    const double ei = lane_value(ech, i), di = lane_value(dch, i);
+                    const double f = sf * ei, bb = cf * ei;
+                    const double r2 = f * f + gf * gf;
+                    hit |= r2 == 0.0;
+                    const double rinv = rsqrt(r2);
+                    sf = f * rinv;
+                    cf = gf * rinv;
+                    const double gi = di1 - pf;
+                    const double rr = (di - gi) * sf + 2.0 * cf * bb;
+                    pf = sf * rr;
+                    gf = cf * rr - bb;
+                    if (lane == 0) {
+                        rot_c[i] = cf;
+                        rot_s[i] = sf;
+                        new_e[i + 1] = r2 * rinv;
+                        new_d[i + 1] = gi + pf;
+                    }
+                    di1 = di;
+                }
+                if (!hit) {
+                    wave_lds_sync();
+                    if (lane > l && lane <= mm) {
+                        e = new_e[lane];
+                        d = new_d[lane];
+                    }
+                    sn = sf;
+                    c = cf;
+                    pp = pf;
+                    g = gf;
+                }
+                redo = hit;   // d, e and g untouched: the chase again, with the test
+            }
+            for (int i = mm - 1; redo && i >= l; --i) {
                 const double ei = lane_value(ech, i);
                 const double f = sn * ei, bb = c * ei;
                 // |f|, |g| stay far from the overflow and underflow thresholds
