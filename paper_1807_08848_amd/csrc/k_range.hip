@@ -401,6 +401,16 @@ __device__ __forceinline__ double lane_value(double x, int i) {
     return __hiloint2double(hi, lo);
 }
 
+// 1/sqrt(x) for finite x > 0: the hardware estimate y, then one step of the
+// series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ... with e = 1 - x y^2, which
+// multiplies the estimate's number of correct bits by three (no special-value
+// handling, which rsqrt() adds for 0, infinities and NaN)
+__device__ __forceinline__ double rsqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 __device__ __forceinline__ double wave_sum64(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -543,7 +553,7 @@ __global__ __launch_bounds__(64) void eig_ql_kernel(PatchDesc* pd, int p0, const
                     const double f = sf * ei, bb = cf * ei;
                     const double r2 = f * f + gf * gf;
                     hit |= r2 == 0.0;
-                    const double rinv = rsqrt(r2);
+                    const double rinv = rsqrt_pos(r2);   // r2 = 0 gives non-finite values, and the redo
                     sf = f * rinv;
                     cf = gf * rinv;
                     const double gi = di1 - pf;
