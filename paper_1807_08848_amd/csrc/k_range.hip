@@ -433,8 +433,10 @@ __global__ __launch_bounds__(64) void eig_ql_kernel(PatchDesc* pd, int p0, const
     __shared__ double G[kRfMax * LDG];   // the matrix, reduced in place; T's diagonals at the end
     __shared__ double V[kRfMax * LDG];   // Q, then the eigenvectors (columns)
     __shared__ double hv[kRfMax], hq[kRfMax];
-    __shared__ double rot_c[kRfMax], rot_s[kRfMax];   // a QL chase's rotations
-    __shared__ double new_e[kRfMax], new_d[kRfMax];   // and the entries of T it rewrites
+    // a QL chase's rotations and the entries of T it rewrites (lane 0's
+    // values; the other lanes store theirs past the end, see the chase)
+    __shared__ double rot_c[kRfMax + 64], rot_s[kRfMax + 64];
+    __shared__ double new_e[kRfMax + 65], new_d[kRfMax + 65];
     __shared__ int perm[kRfMax];
     __shared__ double lam[kRfMax];
     __shared__ int kshared, second_s;
@@ -560,12 +562,13 @@ __global__ __launch_bounds__(64) void eig_ql_kernel(PatchDesc* pd, int p0, const
                     const double rr = (di - gi) * sf + 2.0 * cf * bb;
                     pf = sf * rr;
                     gf = cf * rr - bb;
-                    if (lane == 0) {
-                        rot_c[i] = cf;
-                        rot_s[i] = sf;
-                        new_e[i + 1] = r2 * rinv;
-                        new_d[i + 1] = gi + pf;
-                    }
+                    // every lane stores (the same values; lanes 1..63 to slots
+                    // past the end): no exec-mask branch in the loop
+                    const int slot = lane == 0 ? i : kRfMax + lane;
+                    rot_c[slot] = cf;
+                    rot_s[slot] = sf;
+                    new_e[slot + 1] = r2 * rinv;
+                    new_d[slot + 1] = gi + pf;
                     di1 = di;
                 }
                 if (!hit) {
