@@ -501,7 +501,7 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         // footprint
         const bool ir = c->prec == MSRS_PREC_FP32_IR;
         c->two_pass = (desc->flags & MSRS_FLAG_TWO_PASS) != 0;
-        int64_t need = c->aL_total * 8 + c->omega_total * 8 + c->x_total * 8 + (ir ? c->x_total * 4 : 0) +
+        int64_t need = c->aL_total * 8 + c->omega_total * 8 + c->x_total * 8 + (ir ? c->x_total * 8 : 0) +
                        c->E_total * (ir ? 4 : 8) + c->Y_total * 8 + c->Q_total * 8 + c->sv_total * 8;
         if (c->two_pass) need += 2 * c->Y_total * 8 + c->omega_total * 8;
         need += (c->kind == kElliptic ? (int64_t)c->N * c->N : c->N) * 8;
@@ -514,7 +514,12 @@ msrs_status msrs_create(msrs_handle* out, const msrs_problem_desc* desc, void* s
         c->aL = dalloc<double>(*c, c->aL_total);
         c->om = dalloc<double>(*c, c->omega_total);
         c->x64 = dalloc<double>(*c, c->x_total);
-        if (ir) c->x32 = dalloc<float>(*c, c->x_total);
+        if (ir) {
+            c->x32 = dalloc<float>(*c, c->x_total);
+            // zero once: the lift writes only the entries next to each patch's boundary
+            c->xlift = dalloc<float>(*c, c->x_total);
+            MSRS_HIP_CHECK(hipMemset(c->xlift, 0, sizeof(float) * (size_t)c->x_total));
+        }
         c->E = ir ? (void*)dalloc<float>(*c, c->E_total) : (void*)dalloc<double>(*c, c->E_total);
         c->tw = dalloc<double>(*c, c->tw_total);
         c->Y = dalloc<double>(*c, c->Y_total);

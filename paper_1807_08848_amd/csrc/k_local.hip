@@ -113,7 +113,38 @@ __device__ __forceinline__ void partial_column_sums(double ssum, const LineMap& 
 }
 
 // rhs = -A_IB omega into the line vectors X (FP64 or FP32), padding zeroed.
-template <int KIND, typename TX>
+// SPARSE: only the entries that can be non-zero are written (the nodes next to
+// the buffered patch's boundary: the first and last line whole, rows 0 and
+// b - 1 of the others; kinetic: the first and last line), into a buffer that
+// holds zeros everywhere else from its allocation on.  The threads of a
+// sample take the chunk's list of such entries in turn.
+template <int KIND>
+__device__ __forceinline__ double lift_value(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ O,
+                                             const double* __restrict__ vw, double dx, int l, int i, int c) {
+    double v = 0.0;
+    if (KIND == kElliptic) {
+        const int pp = i + 1, q = l + 1;
+#pragma unroll
+        for (int dq = -1; dq <= 1; ++dq)
+#pragma unroll
+            for (int dp = -1; dp <= 1; ++dp) {
+                const int p2 = pp + dp, q2 = q + dq;
+                if (p2 == 0 || p2 == P.L || q2 == 0 || q2 == P.Qn) {
+                    int ii, jj;
+                    line_to_phys(P, p2, q2, ii, jj);
+                    v -= q1_coef(aL, P.L, pp, q, dp, dq) * O[(int64_t)c * P.nb + bidx_ccw(ii, jj, P.cx, P.cy)];
+                }
+            }
+    } else {
+        const int h = P.b / 2;
+        const double vi = vw[i];
+        if (l == 0 && vi > 0) v += vi / dx * O[(int64_t)c * P.nb + (i - h)];
+        if (l == P.nl - 1 && vi < 0) v += -vi / dx * O[(int64_t)c * P.nb + h + i];
+    }
+    return v;
+}
+
+template <int KIND, typename TX, bool SPARSE>
 __global__ __launch_bounds__(kThreads) void lift_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
                                                         const double* __restrict__ om, const double* __restrict__ vw, double dx,
                                                         TX* __restrict__ X, double* __restrict__ part, int maxch) {
@@ -129,36 +160,38 @@ __global__ __launch_bounds__(kThreads) void lift_kernel(const PatchDesc* pd, int
     const LineMap m(sp);
     const int c = m.col;
     double ssum = 0.0;
-    for (int l = l0; l < l1; ++l) {
-        // only nodes next to the buffered patch's boundary (first / last line,
-        // first / last row) have boundary neighbours
-        const bool edge_line = l == 0 || l == nl - 1;
-        for (int i = m.row0; m.active && i < bp; i += m.rows) {
-            double v = 0.0;
-            if (i < b && c < P.s && (edge_line || i == 0 || i == b - 1)) {
-                if (KIND == kElliptic) {
-                    const int pp = i + 1, q = l + 1;
-#pragma unroll
-                    for (int dq = -1; dq <= 1; ++dq)
-#pragma unroll
-                        for (int dp = -1; dp <= 1; ++dp) {
-                            const int p2 = pp + dp, q2 = q + dq;
-                            if (p2 == 0 || p2 == P.L || q2 == 0 || q2 == P.Qn) {
-                                int ii, jj;
-                                line_to_phys(P, p2, q2, ii, jj);
-                                v -= q1_coef(aL, P.L, pp, q, dp, dq) * O[(int64_t)c * P.nb + bidx_ccw(ii, jj, P.cx, P.cy)];
-                            }
-                        }
-                } else {
-                    const int h = b / 2;
-                    const double vi = vw[i];
-                    if (l == 0 && vi > 0) v += vi / dx * O[(int64_t)c * P.nb + (i - h)];
-                    if (l == nl - 1 && vi < 0) v += -vi / dx * O[(int64_t)c * P.nb + h + i];
-                }
+    if constexpr (SPARSE) {
+        if (m.active && c < P.s) {
+            auto put = [&](int l, int i) {
+                const double v = lift_value<KIND>(P, aL, O, vw, dx, l, i, c);
+                X[P.x_off + (int64_t)l * bp * sp + (int64_t)i * sp + c] = (TX)v;
+                ssum += v * v;
+            };
+            // the chunk's lines next to the boundary, whole (independent
+            // entries: unrolled so that their loads overlap)
+            for (int e = 0; e < 2; ++e) {
+                const int l = e == 0 ? 0 : nl - 1;
+                if (l < l0 || l >= l1 || (e == 1 && nl == 1)) continue;
+#pragma unroll 4
+                for (int i = m.row0; i < b; i += m.rows) put(l, i);
             }
-            const int64_t o = P.x_off + (int64_t)l * bp * sp + (int64_t)i * sp + c;
-            X[o] = (TX)v;
-            ssum += v * v;
+            // elliptic: rows 0 and b - 1 of the chunk's other lines
+            if (KIND == kElliptic) {
+                const int la = max(l0, 1), lb = min(l1, nl - 1), nper = b > 1 ? 2 : 1;
+#pragma unroll 4
+                for (int t = m.row0; t < nper * (lb - la); t += m.rows) put(la + t / nper, (t % nper) ? b - 1 : 0);
+            }
+        }
+    } else {
+        for (int l = l0; l < l1; ++l) {
+            const bool edge_line = l == 0 || l == nl - 1;
+            for (int i = m.row0; m.active && i < bp; i += m.rows) {
+                // only nodes next to the buffered patch's boundary (first / last
+                // line, first / last row) have boundary neighbours
+                const double v = (i < b && c < P.s && (edge_line || i == 0 || i == b - 1)) ? lift_value<KIND>(P, aL, O, vw, dx, l, i, c) : 0.0;
+                X[P.x_off + (int64_t)l * bp * sp + (int64_t)i * sp + c] = (TX)v;
+                ssum += v * v;
+            }
         }
     }
     partial_column_sums(ssum, m, sp, red, part + ((int64_t)p * maxch + blockIdx.y) * kMaxSamples);
@@ -597,12 +630,15 @@ void launch_lift(Ctx& c, int p0, int p1, const double* adjQ) {
         if (ir) hipLaunchKernelGGL(adj_lift_kernel<float>, grid, dim3(kThreads), 0, c.stream, c.dp, p0, adjQ, c.x32, c.part, c.maxch);
         else hipLaunchKernelGGL(adj_lift_kernel<double>, grid, dim3(kThreads), 0, c.stream, c.dp, p0, adjQ, c.x64, c.part, c.maxch);
     } else if (c.kind == kElliptic) {
-        if (ir) hipLaunchKernelGGL((lift_kernel<kElliptic, float>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x32, c.part, c.maxch);
-        else hipLaunchKernelGGL((lift_kernel<kElliptic, double>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, c.part, c.maxch);
+        if (ir) hipLaunchKernelGGL((lift_kernel<kElliptic, float, true>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.xlift, c.part, c.maxch);
+        else hipLaunchKernelGGL((lift_kernel<kElliptic, double, false>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, c.part, c.maxch);
     } else {
-        if (ir) hipLaunchKernelGGL((lift_kernel<kKinetic, float>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x32, c.part, c.maxch);
-        else hipLaunchKernelGGL((lift_kernel<kKinetic, double>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, c.part, c.maxch);
+        if (ir) hipLaunchKernelGGL((lift_kernel<kKinetic, float, true>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.xlift, c.part, c.maxch);
+        else hipLaunchKernelGGL((lift_kernel<kKinetic, double, false>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), c.x64, c.part, c.maxch);
     }
+    // FP32 refinement: the first solve reads the lifted data from xlift, the
+    // adjoint source (dense) from x32
+    c.rhs_in_xlift = ir && !adjQ;
     hipLaunchKernelGGL(norms_kernel, dim3(p1 - p0), dim3(64), 0, c.stream, c.dp, p0, c.part, c.maxch, c.rn, 0, (int32_t*)nullptr,
                        (double*)nullptr, (int32_t*)nullptr, 0, 0.0, 0.0, c.dflags);
 }

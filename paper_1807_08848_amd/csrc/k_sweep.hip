@@ -43,8 +43,8 @@ template <> struct Vec16<double> { typedef double2 type; static constexpr int n 
 // code.  TW: this chunk's [2][bp x sp] middle-line couplings (row stride sp).
 template <typename T, int KIND, int R, int NCT, int PHASE>
 __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __restrict__ aL, const double* __restrict__ vw, double dx,
-                           const T* __restrict__ E, T* __restrict__ X, double* __restrict__ X64, T* __restrict__ TW, int half,
-                           T* ybuf, T* wbuf, double* craw, double* cvp, double* cvm) {
+                           const T* __restrict__ E, T* __restrict__ X, const T* __restrict__ XR, double* __restrict__ X64,
+                           T* __restrict__ TW, int half, T* ybuf, T* wbuf, double* craw, double* cvp, double* cvm) {
     typedef typename Vec16<T>::type V;
     constexpr int VN = Vec16<T>::n;
     constexpr int BP = 16 * R, NKS = 4 * R, NSC = 16 * NCT;
@@ -243,6 +243,8 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
     double nopre[NCT][4] = {};
     if constexpr (PHASE == 0) {
         // ---- forward half: lines ln0, ln0 + dir, ...; the last one couples into m
+        // (right-hand sides read from XR, results written to X: no line read here
+        // is written here)
         const int nst = half == 0 ? m : nl - 1 - m;
         const int ln0 = half == 0 ? 0 : nl - 1;
         const bool low = half == 0;   // top: Low_{l+1} (line below from above); bottom: Up_{l-1}
@@ -250,7 +252,7 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
         launder();
         if (nst <= 0) {
             // no line in this half: t_top = r_m, t_bot = 0
-            if (half == 0) load_line(X + m * lstride, rvA);
+            if (half == 0) load_line(XR + m * lstride, rvA);
 #pragma unroll
             for (int e = 0; e < RPT; ++e) {
                 const int i = li0 + e * DI;
@@ -266,17 +268,21 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
         if constexpr (RC) {
             {
                 T r0[RPT];
-                load_line(X + ln0 * lstride, r0);                 // y_{ln0} = r_{ln0}
+                load_line(XR + ln0 * lstride, r0);                 // y_{ln0} = r_{ln0}
+                const bool copy = XR != X;                         // the back half reads y_{ln0} from X
 #pragma unroll
                 for (int e = 0; e < RPT; ++e) {
                     const int i = li0 + e * DI;
-                    if (BP % DI == 0 || i < BP) ybuf[yix(i, ljj)] = r0[e];
+                    if (BP % DI == 0 || i < BP) {
+                        ybuf[yix(i, ljj)] = r0[e];
+                        if (copy) X[ln0 * lstride + (uint32_t)(i * sp + ljj)] = r0[e];
+                    }
                 }
             }
             T rcA[NCT][4] = {}, rcB[NCT][4] = {};
             load_A(E + (int64_t)ln0 * BP * BP);
             double crA = 0.0, crB = 0.0;
-            if (sub_of(0)) ld_acc_line(X + (ln0 + dir) * lstride, rcA);
+            if (sub_of(0)) ld_acc_line(XR + (ln0 + dir) * lstride, rcA);
             crA = aL[(dir > 0 ? ln0 + 1 : ln0) * L + min(tid, b)];
             lds_barrier();
             auto step = [&](int k, T (&rc)[NCT][4], T (&rn)[NCT][4], double& cc, double& cn) {
@@ -293,7 +299,7 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
                 couple_rc(rc, sub, more ? X + nx * lstride : TWh, more, std::true_type{});
                 // r of the next step, after the coupling (its registers are free
                 // then), consumed after the next products
-                ld_acc_line(X + ((more && sub_of(k + 1)) ? nx + dir : nx) * lstride, rn);
+                ld_acc_line(XR + ((more && sub_of(k + 1)) ? nx + dir : nx) * lstride, rn);
                 lds_barrier();
             };
             for (int k = 0; k < nst; k += 2) {
@@ -301,15 +307,19 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
                 if (k + 1 < nst) step(k + 1, rcB, rcA, crB, crA);
             }
         } else {
-            load_line(X + ln0 * lstride, rvA);                 // y_{ln0} = r_{ln0}
+            load_line(XR + ln0 * lstride, rvA);                 // y_{ln0} = r_{ln0}
+            const bool copy = XR != X;                          // the back half reads y_{ln0} from X
 #pragma unroll
             for (int e = 0; e < RPT; ++e) {
                 const int i = li0 + e * DI;
-                if (BP % DI == 0 || i < BP) ybuf[yix(i, ljj)] = rvA[e];
+                if (BP % DI == 0 || i < BP) {
+                    ybuf[yix(i, ljj)] = rvA[e];
+                    if (copy) X[ln0 * lstride + (uint32_t)(i * sp + ljj)] = rvA[e];
+                }
             }
             load_A(E + (int64_t)ln0 * BP * BP);
             double crA = 0.0, crB = 0.0;
-            if (sub_of(0)) load_line(X + (ln0 + dir) * lstride, rvA);
+            if (sub_of(0)) load_line(XR + (ln0 + dir) * lstride, rvA);
             if (KIND == kElliptic) crA = aL[(dir > 0 ? ln0 + 1 : ln0) * L + min(tid, b)];
             lds_barrier();
             auto step = [&](int k, T (&rc)[RPT], T (&rn)[RPT], double& cc, double& cn) {
@@ -320,7 +330,7 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
                 mfma();                                                                   // w = E_ln y_ln
                 // r of the next step, its cell row and E (unconditional, clamped to
                 // lines that exist when there is no next step)
-                load_line(X + ((more && sub_of(k + 1)) ? nx + dir : nx) * lstride, rn);
+                load_line(XR + ((more && sub_of(k + 1)) ? nx + dir : nx) * lstride, rn);
                 if (KIND == kElliptic) cn = aL[(more ? (dir > 0 ? nx + 1 : nx) : (dir > 0 ? ln + 1 : ln)) * L + min(tid, b)];
                 load_A(E + (int64_t)(more ? nx : ln) * BP * BP);
                 store_acc(nullptr, nullptr, nopre, true);
@@ -514,7 +524,8 @@ __device__ __forceinline__ void sweep_body(const PatchDesc& P, const double* __r
 template <typename T, int KIND, int NCT, int PHASE>
 __global__ __launch_bounds__(kSweepThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void sweep_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
                                                               const double* __restrict__ vw, double dx, const T* __restrict__ E_all,
-                                                              T* __restrict__ X_all, double* __restrict__ X64_all, T* __restrict__ TW_all,
+                                                              T* __restrict__ X_all, const T* __restrict__ XR_all,
+                                                              double* __restrict__ X64_all, T* __restrict__ TW_all,
                                                               const int32_t* __restrict__ conv, const int32_t* __restrict__ items,
                                                               int32_t* flags) {
     __shared__ __align__(16) T ybuf[kMaxLine * 16 * NCT];
@@ -533,9 +544,12 @@ __global__ __launch_bounds__(kSweepThreads) __attribute__((amdgpu_waves_per_eu(s
     const double* aL = aL_all + P.a_off;
     const T* E = E_all + P.E_off;
     T* X = X_all + P.x_off + s0;
+    // the forward half's right-hand sides: XR_all where given (FP32 refinement's
+    // first solve: the lifted boundary data), else X itself
+    const T* XR = XR_all ? XR_all + P.x_off + s0 : X;
     T* TW = TW_all + P.tw_off + s0;
     double* X64 = X64_all ? X64_all + P.x_off + s0 : nullptr;
-#define MSRS_SWB(RR) sweep_body<T, KIND, RR, NCT, PHASE>(P, aL, vw, dx, E, X, X64, TW, half, ybuf, wbuf, craw, cvp, cvm)
+#define MSRS_SWB(RR) sweep_body<T, KIND, RR, NCT, PHASE>(P, aL, vw, dx, E, X, XR, X64, TW, half, ybuf, wbuf, craw, cvp, cvm)
     if (KIND == kKinetic) {
         switch (P.bp >> 4) {
             case 1: MSRS_SWB(1); break;
@@ -588,17 +602,18 @@ void launch_sweep(Ctx& c, int p0, int p1, bool fp32, bool first) {
 #define MSRS_SWEEP(TT, KK, NN, XX)                                                                                             \
     do {                                                                                                                      \
         hipLaunchKernelGGL((sweep_kernel<TT, KK, NN, 0>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, \
-                           (double*)nullptr, (TT*)c.tw, conv, items, c.dflags);                                                      \
+                           (const TT*)nullptr, (double*)nullptr, (TT*)c.tw, conv, items, c.dflags);                                  \
         hipLaunchKernelGGL((sweep_kernel<TT, KK, NN, 1>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const TT*)c.E, XX, \
-                           x64acc, (TT*)c.tw, conv, items, c.dflags);                                                                 \
+                           (const TT*)nullptr, x64acc, (TT*)c.tw, conv, items, c.dflags);                                             \
     } while (0)
     // the first solve of a refinement writes the FP64 iterate instead of adding to it
 #define MSRS_SWEEP_FIRST(KK, NN)                                                                                               \
     do {                                                                                                                      \
         hipLaunchKernelGGL((sweep_kernel<float, KK, NN, 0>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const float*)c.E, \
-                           c.x32, (double*)nullptr, (float*)c.tw, conv, items, c.dflags);                                            \
+                           c.x32, (const float*)(c.rhs_in_xlift ? c.xlift : nullptr), (double*)nullptr, (float*)c.tw, conv,      \
+                           items, c.dflags);                                                                                         \
         hipLaunchKernelGGL((sweep_kernel<float, KK, NN, 2>), grid, blk, 0, c.stream, c.dp, p0, c.aL, c.vw, dx, (const float*)c.E, \
-                           c.x32, x64acc, (float*)c.tw, conv, items, c.dflags);                                                      \
+                           c.x32, (const float*)nullptr, x64acc, (float*)c.tw, conv, items, c.dflags);                              \
     } while (0)
     if (c.kind == kElliptic) {
         if (fp32 && first) {

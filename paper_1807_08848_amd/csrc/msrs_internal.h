@@ -104,6 +104,8 @@ struct Ctx {
     double* om = nullptr;         // Omega
     double* x64 = nullptr;        // FP64 line vectors (solution)
     float* x32 = nullptr;         // FP32 line vectors (FP32_IR: residual / correction)
+    float* xlift = nullptr;       // FP32_IR: the lifted boundary data, zero except next to each patch's boundary
+    bool rhs_in_xlift = false;    // the next first solve reads xlift (else x32: the adjoint source)
     void* E = nullptr;            // inverse blocks (float or double)
     void* tw = nullptr;           // middle-line couplings of the twisted sweeps (float or double)
     int64_t tw_total = 0;
