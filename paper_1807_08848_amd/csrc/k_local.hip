@@ -552,11 +552,17 @@ __global__ __launch_bounds__(kThreads) void restrict_kernel(const PatchDesc* pd,
     const double* O = om + P.om_off;
     double* Y = Y_all + P.Y_off;
     const int64_t lstride = (int64_t)P.bp * P.sp;
-    // gather: 32 lanes along the samples, 8 rows at a time; the row's
-    // position is resolved once per row, not per value
+    // gather: 32 lanes along the samples (two samples each, s <= 64), 8 rows at
+    // a time; all of a thread's loads are issued before the tile is written,
+    // so they are in flight together.  A row's position is resolved once.
+    constexpr int RPTH = kRestrictRows / (kThreads / 32);   // rows per thread
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    for (int rr = ty; rr < nr; rr += kThreads / 32) {
-        const int row = r0 + rr;
+    double v[RPTH][2];
+#pragma unroll
+    for (int k = 0; k < RPTH; ++k) {
+        const int rr = ty + k * (kThreads / 32), row = r0 + rr;
+        v[k][0] = v[k][1] = 0.0;
+        if (rr >= nr) continue;
         if (KIND == kElliptic) {
             const int W = P.nH + 1;
             const int jj = row / W, ii = row - jj * W;
@@ -565,19 +571,32 @@ __global__ __launch_bounds__(kThreads) void restrict_kernel(const PatchDesc* pd,
             const bool inner = pl >= 1 && pl <= P.L - 1 && ql >= 1 && ql <= P.Qn - 1;
             const double* src = inner ? X + (int64_t)(ql - 1) * lstride + (int64_t)(pl - 1) * P.sp : nullptr;
             const int bi = inner ? 0 : bidx_ccw(ip, jp, P.cx, P.cy);
-            for (int c = tx; c < ns; c += 32) tile[rr * LDT + c] = inner ? src[c] : O[(int64_t)c * P.nb + bi];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int c = tx + 32 * h;
+                if (c < ns) v[k][h] = inner ? src[c] : O[(int64_t)c * P.nb + bi];
+            }
         } else {
-            const int nv = P.b, h = nv / 2;
+            const int nv = P.b, hv = nv / 2;
             const int cell = row / nv, j = row - cell * nv;
             const int lc = P.kx0 - 1 + cell - P.x0;
-            for (int c = tx; c < ns; c += 32) {
-                double v;
-                if (lc >= 0 && lc < P.cx) v = X[(int64_t)lc * lstride + (int64_t)j * P.sp + c];
-                else if (lc < 0) v = vw[j] > 0 ? O[(int64_t)c * P.nb + (j - h)] : 0.0;
-                else v = vw[j] < 0 ? O[(int64_t)c * P.nb + h + j] : 0.0;
-                tile[rr * LDT + c] = v;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int c = tx + 32 * h;
+                if (c >= ns) continue;
+                if (lc >= 0 && lc < P.cx) v[k][h] = X[(int64_t)lc * lstride + (int64_t)j * P.sp + c];
+                else if (lc < 0) v[k][h] = vw[j] > 0 ? O[(int64_t)c * P.nb + (j - hv)] : 0.0;
+                else v[k][h] = vw[j] < 0 ? O[(int64_t)c * P.nb + hv + j] : 0.0;
             }
         }
+    }
+#pragma unroll
+    for (int k = 0; k < RPTH; ++k) {
+        const int rr = ty + k * (kThreads / 32);
+        if (rr >= nr) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (tx + 32 * h < ns) tile[rr * LDT + tx + 32 * h] = v[k][h];
     }
     __syncthreads();
     // store: 64 lanes along the rows of one column, 4 columns at a time
