@@ -157,10 +157,11 @@ __device__ __forceinline__ void rr_pair(int i, int st, int nm1, int& a, int& b) 
 // with at least kQlMinCols samples.
 // Full-basis patches have Gram matrices that are not graded, on which Jacobi
 // needs few sweeps while the QL chases run their full length (the kinetic
-// test workload's full-basis end patches: 1.05 ms in QL, 0.30 in Jacobi); and
-// at 32 samples the Jacobi rounds are cheap (h=1/512: 0.34 against 0.42 ms),
-// while from 48 on QL wins (h=1/1024, 64 samples: 1.39 against 1.90 ms).
-constexpr int kQlMinCols = 40;
+// test workload's full-basis end patches: 1.05 ms in QL, 0.30 in Jacobi).
+// On sampled patches QL wins from 32 samples on (h=1/512, 32 samples: 0.31
+// against 0.34 ms; h=1/1024, 64 samples: 1.00 against 1.90 ms); below, both
+// take a few microseconds and Jacobi's fixed cost is the smaller.
+constexpr int kQlMinCols = 32;
 __device__ __forceinline__ bool ql_patch(const PatchDesc& P) { return P.sampled && P.s >= kQlMinCols; }
 
 // The tail of both eigensolvers, from the eigenvalues on G's diagonal and the
