@@ -159,8 +159,8 @@ __device__ __forceinline__ void rr_pair(int i, int st, int nm1, int& a, int& b) 
 // needs few sweeps while the QL chases run their full length (the kinetic
 // test workload's full-basis end patches: 1.05 ms in QL, 0.30 in Jacobi).
 // On sampled patches QL wins from 32 samples on (h=1/512, 32 samples: 0.31
-// against 0.34 ms; h=1/1024, 64 samples: 1.00 against 1.90 ms); below, both
-// take a few microseconds and Jacobi's fixed cost is the smaller.
+// against 0.34 ms; h=1/1024, 64 samples: 1.00 against 1.90 ms); the small
+// sampled patches below 32 samples keep Jacobi (not timed against QL there).
 constexpr int kQlMinCols = 32;
 __device__ __forceinline__ bool ql_patch(const PatchDesc& P) { return P.sampled && P.s >= kQlMinCols; }
 
