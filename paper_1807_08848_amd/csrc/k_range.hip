@@ -545,8 +545,9 @@ __global__ __launch_bounds__(64) void eig_ql_kernel(PatchDesc* pd, int p0, const
             // The chase as straight-line code: no test inside (a rotation with
             // f = g = 0, the split case, is detected afterwards and the chase
             // redone below with the test), the rewritten d_{i+1}, e_{i+1} and
-            // the rotation go to LDS from lane 0 (every lane holds the same
-            // values), and d_{i+1} of rotation i is d_i of rotation i + 1.
+            // the rotation go to LDS (every lane holds the same values; lane 0's
+            // copies are the ones read), and d_{i+1} of rotation i is d_i of
+            // rotation i + 1.
             bool redo;
             {
                 bool hit = false;
