@@ -365,24 +365,28 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const PatchDesc* pd,
     partial_column_sums(ssum, m, sp, red, part + ((int64_t)p * maxch + blockIdx.y) * kMaxSamples);
 }
 
-// Elliptic residual, sliding-window form: thread (segment g, line l0 + lo,
-// sample c) walks down its segment of the line with the 3 x 3 stencil window
-// of x in registers (three new loads per node instead of nine) and the
-// coefficient cell rows of the chunk staged in LDS (two new cells per node),
-// so the loads scale with the output instead of nine-fold.  A line splits
-// into as many segments as the workgroup has threads to spare for its sample
-// count (2 at 32 samples): shorter dependent walks, more loads in flight.
-// Same arithmetic per node as the generic kernel.
+// Elliptic residual, sliding-window form: a workgroup takes 16 lines of a
+// patch, thread (segment g, line pair lo, sample c) walks down its segment of
+// lines l0 + 2 lo and l0 + 2 lo + 1 together, with the 4 x 3 window of x
+// spanning both lines' stencils in registers (four new loads per node for two
+// outputs) and the coefficient cell rows of the chunk staged in LDS.  Chunks
+// of 16 lines read 18 rows of x per 16 (the halo rows two chunks share)
+// instead of 10 per 8.  A line splits into as many segments as the workgroup
+// has threads to spare for its sample count (2 at 32 samples): shorter
+// dependent walks, more loads in flight.  Same arithmetic per node as the
+// generic kernel.  The per-sample sums of a chunk go to the first of its two
+// 8-line partial slots, zero to the second.
 // ADJ (two-pass range finder): the adjoint system A_II z = f_I, f = R_K^T q
 // with q the columns of Qs: zero boundary values and the source f added.
-constexpr int kResThreads = kChunkLines * kMaxSamples;   // 8 lines x up to 64 samples
+constexpr int kResThreads = kChunkLines * kMaxSamples;   // 8 line pairs x up to 64 samples
+constexpr int kResLines = 2 * kChunkLines;                // lines per workgroup
 template <bool ADJ>
 __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDesc* pd, int p0, const double* __restrict__ aL_all,
                                                                    const double* __restrict__ om, const double* __restrict__ x64_all,
                                                                    float* __restrict__ x32_all, const int32_t* __restrict__ conv,
                                                                    double* __restrict__ part, int maxch, const double* __restrict__ Qs,
                                                                    int np, int nch) {
-    __shared__ double cell[(kChunkLines + 1) * (kMaxLine + 1)];
+    __shared__ double cell[(kResLines + 1) * (kMaxLine + 1)];
     __shared__ double red[kResThreads];
     // workgroup -> (patch, chunk) so that a patch's chunks are dispatched one
     // after another on one XCD (workgroups go round-robin over the 8 XCDs):
@@ -394,9 +398,9 @@ __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDe
     const int p = p0 + pl;
     if (conv && conv[p]) return;
     const PatchDesc P = pd[p];
-    const int l0 = chunk * kChunkLines;
+    const int l0 = chunk * kResLines;
     if (l0 >= P.nl) return;
-    const int l1 = min(P.nl, l0 + kChunkLines);
+    const int l1 = min(P.nl, l0 + kResLines);
     const double* aL = aL_all + P.a_off;
     const double* O = om + P.om_off;
     const int sp = P.sp, bp = P.bp, b = P.b, L = P.L, Qn = P.Qn;
@@ -409,13 +413,16 @@ __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDe
     __syncthreads();
     const int nseg = max(1, kResThreads / (sp * kChunkLines));
     const int c = tid % sp, lo = (tid / sp) % kChunkLines, g = tid / (sp * kChunkLines);
-    const bool active = lo < l1 - l0 && g < nseg;
-    // nodes pa .. pb of the line (1-based along it)
+    const int la = l0 + 2 * lo;                 // the pair's first line
+    const bool active = la < l1 && g < nseg;
+    const bool two = la + 1 < l1;               // the pair's second line exists
+    // nodes pa .. pb of the lines (1-based along them)
     const int pa = 1 + (g * b) / nseg, pb = ((g + 1) * b) / nseg;
     double ssum = 0.0;
     if (active) {
-        const int l = l0 + lo, q = l + 1;
-        float* R32 = X32 ? X32 + (int64_t)l * lstride + c : nullptr;
+        const int q = la + 1;                   // node row of line la
+        float* Ra = X32 ? X32 + (int64_t)la * lstride + c : nullptr;
+        float* Rb = X32 && two ? X32 + (int64_t)(la + 1) * lstride + c : nullptr;
         if (c < P.s) {
             // u(q2, p2): interior nodes from x, nodes on the buffered patch's boundary from Omega
             auto u = [&](int q2, int p2) -> double {
@@ -427,20 +434,10 @@ __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDe
                 }
                 return X[(int64_t)(q2 - 1) * lstride + (int64_t)(p2 - 1) * sp + c];
             };
-            const double* cS = cell + (l - l0) * L;        // cell row q - 1
-            const double* cN = cell + (l - l0 + 1) * L;    // cell row q
-            // window columns p-1, p, p+1 of node rows q-1, q, q+1
-            double wm[3], w0[3], wp[3];
-            wm[0] = u(q - 1, pa - 1); w0[0] = u(q, pa - 1); wp[0] = u(q + 1, pa - 1);
-            wm[1] = u(q - 1, pa); w0[1] = u(q, pa); wp[1] = u(q + 1, pa);
-            double SW = cS[pa - 1], NW = cN[pa - 1];
-            for (int pp = pa; pp <= pb; ++pp) {
-                wm[2] = u(q - 1, pp + 1);
-                w0[2] = u(q, pp + 1);
-                wp[2] = u(q + 1, pp + 1);
-                const double SE = cS[pp], NE = cN[pp];
-                // the terms of q1_coef over dq, dp = -1, 0, 1, in that order; the
-                // divisions by 3 and 6 as products with the rounded reciprocals
+            // the terms of q1_coef over dq, dp = -1, 0, 1, in that order; the
+            // divisions by 3 and 6 as products with the rounded reciprocals
+            auto stencil = [](const double (&wm)[3], const double (&w0)[3], const double (&wp)[3], double SW, double SE,
+                              double NW, double NE) {
                 constexpr double k3 = 1.0 / 3.0, k6 = 1.0 / 6.0;
                 double r = 0.0;
                 r += (SW * k3) * wm[0];
@@ -452,31 +449,65 @@ __global__ __launch_bounds__(kResThreads) void residual_ell_kernel(const PatchDe
                 r += (NW * k3) * wp[0];
                 r += ((NE + NW) * k6) * wp[1];
                 r += (NE * k3) * wp[2];
+                return r;
+            };
+            const double* cS = cell + (la - l0) * L;   // cell row q - 1
+            const double* cM = cell + (la - l0 + 1) * L;   // cell row q
+            const double* cN = cell + (la - l0 + (two ? 2 : 1)) * L;   // cell row q + 1 (second line only)
+            // window columns p-1, p, p+1 of node rows q-1 .. q+2 (q+2: second line only)
+            double w[4][3];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                w[r][0] = (r < 3 || two) ? u(q - 1 + r, pa - 1) : 0.0;
+                w[r][1] = (r < 3 || two) ? u(q - 1 + r, pa) : 0.0;
+            }
+            double SW = cS[pa - 1], MW = cM[pa - 1], NW = cN[pa - 1];
+            for (int pp = pa; pp <= pb; ++pp) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) w[r][2] = (r < 3 || two) ? u(q - 1 + r, pp + 1) : 0.0;
+                const double SE = cS[pp], ME = cM[pp], NE = cN[pp];
+                double ra = stencil(w[0], w[1], w[2], SW, SE, MW, ME);
+                double rb = stencil(w[1], w[2], w[3], MW, ME, NW, NE);
                 if constexpr (ADJ) {
                     const int row = k_row_of(P, pp, q);
-                    if (row >= 0) r += Qs[P.Y_off + (int64_t)c * P.nrows + row];
+                    if (row >= 0) ra += Qs[P.Y_off + (int64_t)c * P.nrows + row];
+                    const int row2 = two ? k_row_of(P, pp, q + 1) : -1;
+                    if (row2 >= 0) rb += Qs[P.Y_off + (int64_t)c * P.nrows + row2];
                 }
-                if (R32) R32[(int64_t)(pp - 1) * sp] = (float)r;
-                ssum += r * r;
-                wm[0] = wm[1]; wm[1] = wm[2];
-                w0[0] = w0[1]; w0[1] = w0[2];
-                wp[0] = wp[1]; wp[1] = wp[2];
-                SW = SE; NW = NE;
+                if (Ra) Ra[(int64_t)(pp - 1) * sp] = (float)ra;
+                if (Rb) Rb[(int64_t)(pp - 1) * sp] = (float)rb;
+                ssum += ra * ra;
+                if (two) ssum += rb * rb;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    w[r][0] = w[r][1];
+                    w[r][1] = w[r][2];
+                }
+                SW = SE; MW = ME; NW = NE;
             }
-            if (R32 && g == nseg - 1)
-                for (int i = b; i < bp; ++i) R32[(int64_t)i * sp] = 0.0f;
-        } else if (R32 && g == 0) {
-            for (int i = 0; i < bp; ++i) R32[(int64_t)i * sp] = 0.0f;
+            if (g == nseg - 1)
+                for (int i = b; i < bp; ++i) {
+                    if (Ra) Ra[(int64_t)i * sp] = 0.0f;
+                    if (Rb) Rb[(int64_t)i * sp] = 0.0f;
+                }
+        } else if (g == 0) {
+            for (int i = 0; i < bp; ++i) {
+                if (Ra) Ra[(int64_t)i * sp] = 0.0f;
+                if (Rb) Rb[(int64_t)i * sp] = 0.0f;
+            }
         }
     }
-    // per-sample sums over the chunk's lines and segments, fixed order
+    // per-sample sums over the chunk's line pairs and segments, fixed order
     red[tid] = active ? ssum : 0.0;
     __syncthreads();
     if (tid < sp) {
         double s = 0.0;
+        const int npair = (l1 - l0 + 1) / 2;
         for (int gg = 0; gg < nseg; ++gg)
-            for (int r = 0; r < l1 - l0; ++r) s += red[(gg * kChunkLines + r) * sp + tid];
-        part[((int64_t)p * maxch + chunk) * kMaxSamples + tid] = s;
+            for (int r = 0; r < npair; ++r) s += red[(gg * kChunkLines + r) * sp + tid];
+        const int64_t slot = (int64_t)p * maxch + 2 * chunk;
+        part[slot * kMaxSamples + tid] = s;
+        if (l1 - l0 > kChunkLines) part[(slot + 1) * kMaxSamples + tid] = 0.0;
     }
 }
 
@@ -669,13 +700,14 @@ void launch_residual(Ctx& c, int p0, int p1, bool stats_only, int it, const doub
     float* x32 = stats_only ? nullptr : c.x32;
     const dim3 grid(p1 - p0, max_chunks(c, p0, p1));
     const int np = p1 - p0, nch = max_chunks(c, p0, p1);
-    const dim3 grid_ell((np + 7) / 8 * 8 * nch);   // (patch, chunk) in the XCD-aware order of the kernel
+    const int nch16 = (nch + 1) / 2;                 // the elliptic kernel's chunks of 16 lines
+    const dim3 grid_ell((np + 7) / 8 * 8 * nch16);   // (patch, chunk) in the XCD-aware order of the kernel
     if (c.kind == kElliptic && adjQ)
         hipLaunchKernelGGL(residual_ell_kernel<true>, grid_ell, dim3(kResThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.x64, x32,
-                           conv, c.part, c.maxch, adjQ, np, nch);
+                           conv, c.part, c.maxch, adjQ, np, nch16);
     else if (c.kind == kElliptic)
         hipLaunchKernelGGL(residual_ell_kernel<false>, grid_ell, dim3(kResThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.x64, x32,
-                           conv, c.part, c.maxch, (const double*)nullptr, np, nch);
+                           conv, c.part, c.maxch, (const double*)nullptr, np, nch16);
     else
         hipLaunchKernelGGL((residual_kernel<kKinetic>), grid, dim3(kThreads), 0, c.stream, c.dp, p0, c.aL, c.om, c.vw, dx_of(c), inv_eps,
                            c.x64, x32, conv, c.part, c.maxch);
